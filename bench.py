@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the sparse-Radon split-Bregman hot path on one MI355X.
+
+Workload: the 512 x 512 FP32 random-ellipse phantom (10 ellipses), 360 angles
+on [0, pi) of which every second one is measured (180), 725 bins, 2% noise,
+split Bregman with alpha = 10, lambda = 1, 50 outer x 20 CG iterations.
+
+One step = one full split-Bregman reconstruction (every stage of the path:
+the forward product, the adjoint product with the fused normal-operator
+epilogue, the CG updates and the Bregman shrink/update steps).  It performs
+exactly 50 x 20 = 1000 normal-operator applies, so
+
+  value      = normal-operator applies per second inside the solver
+               (1000 * steps / timed seconds, the whole job),
+  recon_per_s = reconstructions per second.
+
+The JSON line also carries the standalone back-to-back normal_apply rate,
+the roofline of the dominant kernel (algorithmic CSR bytes per launch over
+its HIP-event-timed average duration, against the 8 TB/s HBM peak) and the
+FP64 CPU oracle timed on the host cores as a reported baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "normal-operator applies/s + HBM GB/s (% peak); split-Bregman recon/s at 1e-5 rel"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "gpu_512_f32"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed split-Bregman reconstructions")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--applies", type=int, default=200, help="timed standalone kernel calls")
+    ap.add_argument("--no-verify", action="store_true", help="skip the oracle accuracy check")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-applies", type=int, default=0,
+                    help="oracle normal applies to time (0: sized to ~15 s)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (got --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_1705_07497_amd as sct
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    w = W.WORKLOADS[WORKLOAD]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    print(f"# built operator: nnz={op.info.nnz} rows={op.rows} in {build_s:.2f} s", file=sys.stderr,
+          flush=True)
+
+    mu_np, eps_np = W.phantom_and_noise(w.n, w.n_ellipses, op.rows, seed=0)
+    mu = torch.as_tensor(mu_np, dtype=torch.float32, device=dev).reshape(1, -1)
+    y_clean = op.fwd(mu)
+    sigma = w.noise * torch.sqrt(torch.mean(y_clean.double() ** 2)).item()
+    f = (y_clean + sigma * torch.as_tensor(eps_np, dtype=torch.float32, device=dev)).contiguous()
+
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    # warmup
+    x = torch.randn((1, op.nn), dtype=torch.float32, device=dev)
+    out = torch.empty_like(x)
+    ysb = torch.empty((1, op.rows), dtype=torch.float32, device=dev)
+    for _ in range(10):
+        op.normal(x, w.alpha, w.lam, out=out)
+    for _ in range(args.warmup):
+        op.sb(f, w.alpha, w.lam, w.n_outer, w.n_cg)
+    torch.cuda.synchronize()
+
+    # standalone kernels
+    t_normal = timed(lambda: op.normal(x, w.alpha, w.lam, out=out), args.applies)
+    t_fwd = timed(lambda: op.fwd(x, out=ysb), args.applies)
+    t_adj = timed(lambda: op.adj(ysb, out=out), args.applies)
+    print(f"# normal {t_normal / args.applies * 1e6:.1f} us, fwd {t_fwd / args.applies * 1e6:.1f} us, "
+          f"adj {t_adj / args.applies * 1e6:.1f} us", file=sys.stderr, flush=True)
+
+    # timed split-Bregman reconstructions (the step)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        u, info = op.sb(f, w.alpha, w.lam, w.n_outer, w.n_cg)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_sb = e0.elapsed_time(e1) / 1e3
+    applies_per_recon = w.n_outer * w.n_cg
+    recon_per_s = args.steps / t_sb
+    value = applies_per_recon * recon_per_s
+
+    # roofline of the dominant kernel (algorithmic CSR bytes: 4 B value + 4 B index
+    # per nonzero, row pointers, vectors read and written once)
+    nnz, rows, nn = op.info.nnz, op.rows, op.nn
+    bytes_fwd = 8 * nnz + 4 * (rows + 1) + 4 * nn + 4 * rows
+    bytes_adj = 8 * nnz + 4 * (nn + 1) + 4 * rows + 4 * nn
+    avg_fwd, avg_adj = t_fwd / args.applies, t_adj / args.applies
+    if avg_adj >= avg_fwd:
+        kname, kbytes, kavg = "k_adj", bytes_adj, avg_adj
+    else:
+        kname, kbytes, kavg = "k_fwd (+k_transpose)", bytes_fwd, avg_fwd
+    achieved = kbytes / kavg / 1e9
+    normal_bytes = bytes_fwd + bytes_adj
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+                "avg_us": round(kavg * 1e6, 2), "algorithmic_bytes": kbytes}
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "normal applies/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_sb / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "split-Bregman TV, 512x512 FP32 ellipse phantom, 180 of 360 angles, "
+                               "725 bins, 50 outer x 20 CG", "n": w.n, "angles": w.n_angles,
+                   "measured_angles": w.n_meas, "bins": w.n_bins, "n_outer": w.n_outer,
+                   "n_cg": w.n_cg, "nnz": nnz, "batch": 1},
+        "recon_per_s": round(recon_per_s, 3),
+        "normal_apply_per_s": round(args.applies / t_normal, 1),
+        "normal_apply_gbs": round(normal_bytes / (t_normal / args.applies) / 1e9, 1),
+        "fwd_us": round(avg_fwd * 1e6, 2), "adj_us": round(avg_adj * 1e6, 2),
+        "build_s": round(build_s, 3),
+        "roofline": roofline,
+    }
+
+    if not args.no_verify or not args.no_cpu:
+        import oracle
+        fr = f.double().cpu().numpy().reshape(-1)
+        t0 = time.perf_counter()
+        ref = oracle.OracleOp(w.n, w.n_angles, w.n_bins, w.mask)
+        oracle_build_s = time.perf_counter() - t0
+        if not args.no_cpu:
+            xr = x.double().cpu().numpy().reshape(-1)
+            ref.normal(xr, w.alpha, w.lam)
+            t0 = time.perf_counter()
+            ref.normal(xr, w.alpha, w.lam)
+            one = time.perf_counter() - t0
+            reps = args.cpu_applies or max(3, min(400, int(15.0 / max(one, 1e-4))))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ref.normal(xr, w.alpha, w.lam)
+            tc = time.perf_counter() - t0
+            cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+            result["cpu_baseline"] = {
+                "value": round(reps / tc, 2), "unit": "normal applies/s", "cores": cores,
+                "kind": "oracle",
+                "sample": f"{reps} FP64 normal applies of the same 512x512 / 180-angle operator "
+                          f"({tc:.1f} s); oracle CSR build {oracle_build_s:.1f} s not included",
+            }
+            print(f"# cpu oracle: {reps / tc:.2f} applies/s on {cores} threads", file=sys.stderr,
+                  flush=True)
+        if not args.no_verify:
+            t0 = time.perf_counter()
+            uo = ref.sb(fr, w.alpha, w.lam, w.n_outer, w.n_cg)[0]
+            ug = u.double().cpu().numpy().reshape(-1)
+            err = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+            result["sb_rel_l2_vs_oracle"] = err
+            result["oracle_sb_s"] = round(time.perf_counter() - t0, 2)
+            print(f"# reconstruction rel L2 vs FP64 oracle: {err:.3e}", file=sys.stderr, flush=True)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

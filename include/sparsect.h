@@ -1,0 +1,253 @@
+/*
+ * sparsect -- precomputed sparse Radon operators for TV-regularised
+ * parallel-beam CT on AMD Instinct MI355X (gfx950).
+ *
+ * The library applies the parallel-beam Radon transform R restricted to the
+ * measured angles (the "row selector" M of eq:objmin, Section 1 of Barnard &
+ * Archibald, "Accelerating optimization-based computed tomography via sparse
+ * matrix approximations") and its adjoint as precomputed sparse matrices, the
+ * principle of Section 3 (the geometry is fixed, so the operator is built
+ * once, offline, and every evaluation inside the solver becomes a sparse
+ * product).  On top of that it provides the normal operator of eq:KKT,
+ * eq:PD_resolve and eq:SB_solve (Section 2), conjugate gradients for those
+ * systems, and anisotropic-TV split Bregman (Section 4).
+ *
+ * Geometry (the paper leaves it open; this is the library's convention):
+ *   image of n x n unit pixels on [-n/2, n/2]^2, pixel (iy, ix) covers
+ *   [ix - n/2, ix - n/2 + 1) x [iy - n/2, iy - n/2 + 1), flat index iy*n + ix;
+ *   angles theta_k = pi*k/n_angles, k = 0..n_angles-1; bins
+ *   s_b = b - (n_bins - 1)/2; ray (k, b) is the line p.(cos, sin) = s_b.
+ *   Entry (ray, pixel) is the length of the ray inside the pixel (Siddon).
+ *   A ray exactly on a pixel edge gives half of each length to the two pixels
+ *   sharing the edge; lengths <= 1e-12 are dropped.
+ *
+ * Conventions for every call:
+ *   - Device pointers are HIP device memory owned by the caller (the Python
+ *     binding passes torch tensors).  The operator's own matrix storage is
+ *     allocated by build_radon_csr and released by radon_op_destroy.
+ *   - Compute calls enqueue on `stream` (a hipStream_t; NULL = default
+ *     stream) and return without synchronising.  build_radon_csr and the
+ *     export calls synchronise.
+ *   - Images are laid out [batch][n*n]; measured sinograms [batch][n_meas][n_bins]
+ *     with the measured angles in ascending order.  The element type is the
+ *     operator's dtype (float for SPARSECT_F32, double for SPARSECT_F64).
+ *   - Every call returns RADON_OK (0) or a negative status; radon_last_error()
+ *     returns a message for the calling thread's most recent failure.
+ *   - Argument checks happen before anything is enqueued.
+ *   - Results are deterministic: no atomics on any apply path and all
+ *     reductions in a fixed order.
+ */
+#ifndef SPARSECT_H
+#define SPARSECT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPARSECT_F32 0
+#define SPARSECT_F64 1
+
+#define RADON_OK            0
+#define RADON_EINVAL       -1   /* bad argument */
+#define RADON_EOVERFLOW    -2   /* a size does not fit the index types */
+#define RADON_EHIP         -3   /* a HIP runtime call failed (message has the HIP error) */
+#define RADON_EWORKSPACE   -4   /* workspace pointer NULL or too small */
+#define RADON_ESTATE       -5   /* operator handle unusable */
+#define RADON_EUNSUPPORTED -6   /* valid request the library does not implement */
+
+typedef struct radon_op radon_op;   /* opaque operator handle */
+
+typedef struct {
+    int32_t n;                  /* image side, 1 <= n <= 32767 */
+    int32_t n_angles;           /* angles theta_k = pi*k/n_angles, >= 1 */
+    int32_t n_bins;             /* detector bins, 1 <= n_bins <= 65535 */
+    int32_t dtype;              /* SPARSECT_F32 or SPARSECT_F64 */
+    const uint8_t *measured;    /* host array of n_angles flags (nonzero = measured),
+                                   NULL = every angle measured; at least one set */
+} radon_geom;
+
+typedef struct {
+    int64_t n_pixels;           /* n*n */
+    int64_t n_meas_angles;      /* measured angles */
+    int64_t n_meas_rays;        /* n_meas_angles * n_bins = length of a measured sinogram */
+    int64_t nnz;                /* nonzeros of MR (equal to those of (MR)^T) */
+    int64_t fwd_slots;          /* slots of the ray-bundle layout (see below) */
+    int64_t adj_slots;          /* slots of the pixel-group layout */
+    int64_t device_bytes;       /* device memory held by the operator */
+    int32_t dtype;
+    int32_t n, n_angles, n_bins;
+} radon_info;
+
+/*
+ * build_radon_csr -- precompute MR and (MR)^T for one geometry (Section 3:
+ * the matrices depend only on the detector, the angle set and the image
+ * size, so they are built once, offline).
+ *
+ * On the GPU it traces every measured ray through the pixel grid (Siddon;
+ * FP64 geometry, entries rounded once to the operator dtype) and stores:
+ *   - the CSR of MR: row = measured ray (angle-major, bins ascending), entries
+ *     in the order the ray visits the pixels (int64 row pointers, int32 pixel
+ *     indices);
+ *   - a ray-bundle layout of MR for the forward product: groups of 16
+ *     adjacent bins of one angle, one slot per (ray, image line along the
+ *     ray's major axis) holding the first pixel's offset along that line
+ *     (uint16) and the lengths in that pixel and the next one (a ray meets at
+ *     most two adjacent pixels of any line along its major axis);
+ *   - a pixel-group layout of (MR)^T for the adjoint: groups of 64 pixels,
+ *     one slot per (pixel, measured angle) holding the first bin crossing
+ *     the pixel (uint16) and the lengths for that bin and the next one (a
+ *     pixel meets at most two adjacent bins of any angle).
+ * Both layouts hold exactly the CSR's values.
+ *
+ *   g       geometry (host struct); `measured` is read during the call only.
+ *   stream  stream for the build kernels; the call synchronises it.
+ *   out     receives the handle (host object owning its device storage).
+ * Errors: RADON_EINVAL (geometry out of range), RADON_EOVERFLOW (nnz or a
+ * layout needs >= 2^31 entries per index type it uses), RADON_EHIP.
+ */
+int build_radon_csr(const radon_geom *g, void *stream, radon_op **out);
+
+/* Sizes of a built operator (host call, no device work). */
+int radon_op_info(const radon_op *op, radon_info *out);
+
+/* Release the operator's device storage and the handle.  NULL is a no-op.
+ * The caller must ensure no enqueued work still uses the operator. */
+void radon_op_destroy(radon_op *op);
+
+/* Message for the calling thread's most recent failed call ("" if none). */
+const char *radon_last_error(void);
+
+/* Workspace kinds for radon_workspace_bytes. */
+#define RADON_WS_FWD      0
+#define RADON_WS_NORMAL   1
+#define RADON_WS_CG       2
+#define RADON_WS_SB       3
+
+/* Bytes of device workspace a call of the given kind needs for `batch`
+ * right-hand sides (>= 0; negative = error status). */
+int64_t radon_workspace_bytes(const radon_op *op, int32_t which, int32_t batch);
+
+/*
+ * radon_fwd -- y = M R x for `batch` images (the data term of eq:objmin).
+ *   x   device, [batch][n*n], operator dtype, read only.
+ *   y   device, [batch][n_meas_rays], written.
+ *   ws  device workspace of radon_workspace_bytes(op, RADON_WS_FWD, batch)
+ *       bytes (holds the transposed image the ray-bundle layout gathers from
+ *       for rays closer to horizontal than vertical).
+ */
+int radon_fwd(const radon_op *op, const void *x, void *y, int32_t batch,
+              void *ws, int64_t ws_bytes, void *stream);
+
+/*
+ * radon_adj -- x = R^T M^T y (the adjoint in eq:KKT, eq:PD_resolve,
+ * eq:SB_solve), through the stored transpose: each output pixel is one
+ * sequential sum, no atomics.  y [batch][n_meas_rays] -> x [batch][n*n].
+ */
+int radon_adj(const radon_op *op, const void *y, void *x, int32_t batch, void *stream);
+
+/*
+ * normal_apply -- out = alpha R^T M^T M R x + lambda K^T K x + sigma x.
+ * With sigma = 0 this is the operator of eq:KKT and eq:SB_solve; with
+ * alpha <- tau*alpha, lambda = 0, sigma = 1 that of eq:PD_resolve (Section 2).
+ * K is the forward-difference gradient with a zero last difference
+ * (Neumann), so K^T K is the 5-point grid Laplacian with Neumann boundary.
+ *   x, out   device [batch][n*n]; out must not alias x.
+ *   dot_out  optional device double[batch]: <x, out> per image (FP64 sum of
+ *            exact FP64 products, fixed order); NULL to skip.
+ *   ws       radon_workspace_bytes(op, RADON_WS_NORMAL, batch) bytes.
+ */
+int normal_apply(const radon_op *op, double alpha, double lambda, double sigma,
+                 const void *x, void *out, double *dot_out, int32_t batch,
+                 void *ws, int64_t ws_bytes, void *stream);
+
+typedef struct {
+    int32_t iterations;   /* iterations that changed x */
+    int32_t breakdown;    /* 0, or k+1 if iteration k met <p, Ap> <= 0 or non-finite */
+    double rho0;          /* ||r_0||^2 */
+    double rho;           /* ||r||^2 after the last iteration */
+} radon_cg_info;
+
+/*
+ * cg_solve -- conjugate gradients (Hestenes-Stiefel) on
+ * A = alpha R^T M^T M R + lambda K^T K + sigma I, one independent solve per
+ * image (Section 2: the systems have no closed form and are solved
+ * iteratively).  Vectors in the operator dtype, the scalars rho, gamma,
+ * alpha_k and beta_k in FP64 on the device.
+ *   rhs      device [batch][n*n].
+ *   x        device [batch][n*n]: initial guess if x0_given, else zeroed;
+ *            receives the iterate.  r_0 = rhs - A x_0.
+ *   n_iter   iteration cap; rtol > 0 also stops once ||r|| <= rtol ||r_0||;
+ *            a zero residual stops; <p, Ap> <= 0 or non-finite stops and is
+ *            reported as a breakdown.
+ *   info     optional device radon_cg_info[batch].
+ *   ws       radon_workspace_bytes(op, RADON_WS_CG, batch) bytes.
+ */
+int cg_solve(const radon_op *op, double alpha, double lambda, double sigma,
+             const void *rhs, void *x, int32_t x0_given, int32_t batch,
+             int32_t n_iter, double rtol, void *ws, int64_t ws_bytes,
+             radon_cg_info *info, void *stream);
+
+#define RADON_SB_WARM   1   /* mu holds the starting image */
+#define RADON_SB_RESUME 2   /* continue from the state held in ws by a previous call */
+
+typedef struct {
+    double alpha;         /* data weight (eq:objmin) */
+    double lambda;        /* splitting weight; shrink threshold is 1/lambda */
+    double tol;           /* > 0: stop once the Bregman update's L1 norm falls
+                             below tol times the first update's */
+    int32_t n_outer;      /* Bregman iterations */
+    int32_t n_cg;         /* CG iterations per Bregman iteration (inexact solve) */
+    int32_t flags;        /* RADON_SB_WARM | RADON_SB_RESUME */
+    int32_t reserved;
+} radon_sb_params;
+
+typedef struct {
+    int32_t outer;        /* Bregman iterations run (this call) */
+    int32_t breakdowns;   /* inner CG solves that reported a breakdown */
+    double upd_b_first;   /* ||b^1 - b^0||_1 of the first update of the run */
+    double upd_b;         /* ||b^{k+1} - b^k||_1 of the last iteration */
+    double upd_u;         /* ||u^{k+1} - u^k||_1 of the last iteration */
+} radon_sb_info;
+
+/*
+ * split_bregman_tv -- anisotropic-TV split Bregman (Goldstein-Osher, the
+ * method of Section 4) for min_u alpha/2 ||M R u - f||^2 + ||K u||_1:
+ *   per Bregman iteration, n_cg CG steps on
+ *     (alpha R^T M^T M R + lambda K^T K) u = alpha R^T M^T f + lambda K^T (d - b)
+ *   (eq:SB_solve, read with K^* as the transpose and a plus sign), warm
+ *   started from the previous u with the residual carried across iterations,
+ *   then d = shrink(K u + b, 1/lambda), b <- b + K u - d.
+ *   f     device [batch][n_meas_rays].
+ *   mu    device [batch][n*n]; the start if RADON_SB_WARM, receives u.
+ *   ws    radon_workspace_bytes(op, RADON_WS_SB, batch) bytes; holds d, b and
+ *         the residual, so a later call with RADON_SB_RESUME continues.
+ *   info  optional device radon_sb_info[batch].
+ */
+int split_bregman_tv(const radon_op *op, const radon_sb_params *params, const void *f,
+                     void *mu, int32_t batch, void *ws, int64_t ws_bytes,
+                     radon_sb_info *info, void *stream);
+
+/*
+ * radon_export_csr -- copy the CSR of MR to host memory (synchronous; for
+ * checks and external tools).  row_ptr int64[n_meas_rays+1], col int32[nnz],
+ * val double[nnz] (entries widened from the operator dtype), each NULL to
+ * skip.  Entries are in the order the ray visits the pixels.
+ */
+int radon_export_csr(const radon_op *op, int64_t *row_ptr, int32_t *col, double *val);
+
+/*
+ * radon_export_adj -- copy the pixel-group layout of (MR)^T to host memory as
+ * per-(pixel, measured angle) records: bin int32[n*n*n_meas_angles] (first
+ * bin, or -1 if no ray of that angle crosses the pixel), v0 and v1
+ * double[n*n*n_meas_angles] (lengths for that bin and the next one).  Record
+ * (j, a) is at j*n_meas_angles + a.  Synchronous.
+ */
+int radon_export_adj(const radon_op *op, int32_t *bin, double *v0, double *v1);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPARSECT_H */

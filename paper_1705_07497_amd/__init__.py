@@ -1,0 +1,320 @@
+"""Python binding of libsparsect: sparse Radon operators, normal operator, CG and
+split Bregman on AMD MI355X (gfx950).
+
+Every call marshals arguments into the C ABI declared in include/sparsect.h;
+all arithmetic runs in the library's HIP kernels.  PyTorch supplies device
+memory (tensors) and the current stream.  There is no CPU fallback: without
+the built library or a GPU the calls raise.
+
+Method: Barnard & Archibald, "Accelerating optimization-based computed
+tomography via sparse matrix approximations" -- the Radon transform is
+precomputed as a sparse matrix for a fixed geometry (Section 3) and applied
+inside CG solves of eq:KKT / eq:PD_resolve / eq:SB_solve (Section 2) and
+anisotropic-TV split Bregman (Section 4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsparsect.so")
+
+F32, F64 = 0, 1
+WS_FWD, WS_NORMAL, WS_CG, WS_SB = 0, 1, 2, 3
+SB_WARM, SB_RESUME = 1, 2
+
+_vp = ctypes.c_void_p
+
+
+class SparsectError(RuntimeError):
+    """A libsparsect call returned a negative status."""
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("measured", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_pixels", ctypes.c_int64), ("n_meas_angles", ctypes.c_int64),
+                ("n_meas_rays", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("fwd_slots", ctypes.c_int64), ("adj_slots", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32)]
+
+
+class CgInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("breakdown", ctypes.c_int32),
+                ("rho0", ctypes.c_double), ("rho", ctypes.c_double)]
+
+
+class SbParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("lambda_", ctypes.c_double), ("tol", ctypes.c_double),
+                ("n_outer", ctypes.c_int32), ("n_cg", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class SbInfo(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int32), ("breakdowns", ctypes.c_int32),
+                ("upd_b_first", ctypes.c_double), ("upd_b", ctypes.c_double),
+                ("upd_u", ctypes.c_double)]
+
+
+# exported symbols and their signatures (kept in step with include/sparsect.h)
+SIGNATURES = {
+    "build_radon_csr": (ctypes.c_int, [ctypes.POINTER(_Geom), _vp, ctypes.POINTER(_vp)]),
+    "radon_op_info": (ctypes.c_int, [_vp, ctypes.POINTER(_Info)]),
+    "radon_op_destroy": (None, [_vp]),
+    "radon_last_error": (ctypes.c_char_p, []),
+    "radon_workspace_bytes": (ctypes.c_int64, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "radon_fwd": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
+    "radon_adj": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
+    "normal_apply": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
+                                    _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
+    "cg_solve": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _vp,
+                                ctypes.c_int64, _vp, _vp]),
+    "split_bregman_tv": (ctypes.c_int, [_vp, ctypes.POINTER(SbParams), _vp, _vp, ctypes.c_int32, _vp,
+                                        ctypes.c_int64, _vp, _vp]),
+    "radon_export_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "radon_export_adj": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsparsect.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SparsectError(f"{LIB_PATH} is missing: run paper_1705_07497_amd.build_lib.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        msg = lib().radon_last_error()
+        raise SparsectError(f"status {rc}: {msg.decode() if msg else ''}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class OpInfo:
+    n_pixels: int
+    n_meas_angles: int
+    n_meas_rays: int
+    nnz: int
+    fwd_slots: int
+    adj_slots: int
+    device_bytes: int
+
+
+class RadonOp:
+    """MR and (MR)^T for one geometry, built on the GPU (see build_radon_csr)."""
+
+    def __init__(self, n: int, n_angles: int, n_bins: int, measured=None, dtype=None, device=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise SparsectError("no GPU visible: libsparsect runs on AMD Instinct GPUs only")
+        dtype = torch.float32 if dtype is None else dtype
+        if dtype not in (torch.float32, torch.float64):
+            raise SparsectError("dtype must be torch.float32 or torch.float64")
+        self.device = torch.device("cuda" if device is None else device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.dtype = dtype
+        self.n, self.n_angles, self.n_bins = int(n), int(n_angles), int(n_bins)
+        if measured is None:
+            self.measured = np.ones(self.n_angles, dtype=np.uint8)
+        else:
+            self.measured = np.ascontiguousarray(np.asarray(measured, dtype=np.uint8))
+            if self.measured.shape != (self.n_angles,):
+                raise SparsectError("measured must have one flag per angle")
+        self.n_meas = int(np.count_nonzero(self.measured))
+        g = _Geom(self.n, self.n_angles, self.n_bins, F32 if dtype == torch.float32 else F64,
+                  self.measured.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib().build_radon_csr(ctypes.byref(g), self._stream(), ctypes.byref(h)))
+        self._h = h
+        inf = _Info()
+        _check(lib().radon_op_info(self._h, ctypes.byref(inf)))
+        self.info = OpInfo(inf.n_pixels, inf.n_meas_angles, inf.n_meas_rays, inf.nnz, inf.fwd_slots,
+                           inf.adj_slots, inf.device_bytes)
+        self.rows = inf.n_meas_rays
+        self.nn = inf.n_pixels
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _torch().cuda.synchronize(self.device)
+            except Exception:
+                pass
+            _lib.radon_op_destroy(h)
+            self._h = None
+
+    # -- helpers --------------------------------------------------------------
+    def _stream(self):
+        torch = _torch()
+        return _vp(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def workspace(self, which: int, batch: int, key=None):
+        """Cached device workspace of the size the library asks for."""
+        torch = _torch()
+        nbytes = lib().radon_workspace_bytes(self._h, which, batch)
+        if nbytes < 0:
+            _check(int(nbytes))
+        k = (which, batch) if key is None else key
+        buf = self._ws.get(k)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+            self._ws[k] = buf
+        return buf, int(nbytes)
+
+    def _img(self, x, name="x"):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or x.device != self.device or x.dtype != self.dtype:
+            raise SparsectError(f"{name} must be a {self.dtype} tensor on {self.device}")
+        if not x.is_contiguous():
+            raise SparsectError(f"{name} must be contiguous")
+        if x.numel() % self.nn:
+            raise SparsectError(f"{name} has {x.numel()} elements, not a multiple of n*n = {self.nn}")
+        return x.numel() // self.nn
+
+    def _sino(self, y, name="y"):
+        torch = _torch()
+        if not isinstance(y, torch.Tensor) or y.device != self.device or y.dtype != self.dtype:
+            raise SparsectError(f"{name} must be a {self.dtype} tensor on {self.device}")
+        if not y.is_contiguous():
+            raise SparsectError(f"{name} must be contiguous")
+        if y.numel() % self.rows:
+            raise SparsectError(f"{name} has {y.numel()} elements, not a multiple of {self.rows}")
+        return y.numel() // self.rows
+
+    @staticmethod
+    def _p(t):
+        return _vp(t.data_ptr()) if t is not None else None
+
+    # -- products -------------------------------------------------------------
+    def fwd(self, x, out=None):
+        """y = M R x; x [..., n*n] (or [..., n, n]) -> y [batch, rows]."""
+        torch = _torch()
+        b = self._img(x)
+        y = torch.empty((b, self.rows), dtype=self.dtype, device=self.device) if out is None else out
+        self._sino(y, "out")
+        ws, nb = self.workspace(WS_FWD, b)
+        _check(lib().radon_fwd(self._h, self._p(x), self._p(y), b, self._p(ws), nb, self._stream()))
+        return y
+
+    def adj(self, y, out=None):
+        """x = R^T M^T y; y [..., rows] -> x [batch, n*n]."""
+        torch = _torch()
+        b = self._sino(y)
+        x = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self._img(x, "out")
+        _check(lib().radon_adj(self._h, self._p(y), self._p(x), b, self._stream()))
+        return x
+
+    def normal(self, x, alpha: float, lam: float, sigma: float = 0.0, out=None, dot: bool = False):
+        """alpha R^T M^T M R x + lam K^T K x + sigma x (and <x, out> per image if dot)."""
+        torch = _torch()
+        b = self._img(x)
+        o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self._img(o, "out")
+        d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
+        ws, nb = self.workspace(WS_NORMAL, b)
+        _check(lib().normal_apply(self._h, float(alpha), float(lam), float(sigma), self._p(x),
+                                  self._p(o), self._p(d), b, self._p(ws), nb, self._stream()))
+        return (o, d) if dot else o
+
+    def cg(self, rhs, alpha: float, lam: float, sigma: float = 0.0, x0=None, n_iter: int = 10,
+           rtol: float = 0.0, out=None):
+        """CG on A(alpha, lam, sigma) x = rhs; returns (x, info tensor of CgInfo bytes)."""
+        torch = _torch()
+        b = self._img(rhs, "rhs")
+        if x0 is not None:
+            self._img(x0, "x0")
+            x = x0.clone() if out is None else out.copy_(x0)
+        else:
+            x = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        info = torch.zeros(b * ctypes.sizeof(CgInfo), dtype=torch.uint8, device=self.device)
+        ws, nb = self.workspace(WS_CG, b)
+        _check(lib().cg_solve(self._h, float(alpha), float(lam), float(sigma), self._p(rhs),
+                              self._p(x), int(x0 is not None), b, int(n_iter), float(rtol),
+                              self._p(ws), nb, self._p(info), self._stream()))
+        return x, info
+
+    def sb(self, f, alpha: float, lam: float, n_outer: int, n_cg: int, tol: float = 0.0,
+           mu0=None, resume: bool = False, out=None, ws_key="sb"):
+        """Split Bregman TV; returns (mu, info tensor of SbInfo bytes).  The state
+        (d, b, carried residual) stays in a cached workspace so resume=True continues."""
+        torch = _torch()
+        b = self._sino(f, "f")
+        flags = 0
+        if resume:
+            flags |= SB_RESUME
+            if out is None:
+                raise SparsectError("resume needs out= (the image of the previous call)")
+            mu = out
+        elif mu0 is not None:
+            flags |= SB_WARM
+            mu = mu0.clone() if out is None else out.copy_(mu0)
+        else:
+            mu = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self._img(mu, "mu")
+        P = SbParams(float(alpha), float(lam), float(tol), int(n_outer), int(n_cg), flags, 0)
+        info = torch.zeros(b * ctypes.sizeof(SbInfo), dtype=torch.uint8, device=self.device)
+        ws, nb = self.workspace(WS_SB, b, key=(ws_key, b))
+        _check(lib().split_bregman_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b,
+                                      self._p(ws), nb, self._p(info), self._stream()))
+        return mu, info
+
+    # -- host copies ------------------------------------------------------------
+    def export_csr(self):
+        rp = np.empty(self.rows + 1, dtype=np.int64)
+        col = np.empty(self.info.nnz, dtype=np.int32)
+        val = np.empty(self.info.nnz, dtype=np.float64)
+        _check(lib().radon_export_csr(self._h, rp.ctypes.data_as(_vp), col.ctypes.data_as(_vp),
+                                      val.ctypes.data_as(_vp)))
+        return rp, col, val
+
+    def export_adj(self):
+        m = self.nn * self.n_meas
+        b = np.empty(m, dtype=np.int32)
+        v0 = np.empty(m, dtype=np.float64)
+        v1 = np.empty(m, dtype=np.float64)
+        _check(lib().radon_export_adj(self._h, b.ctypes.data_as(_vp), v0.ctypes.data_as(_vp),
+                                      v1.ctypes.data_as(_vp)))
+        return b, v0, v1
+
+
+def decode_cg_info(info) -> list[dict]:
+    raw = info.cpu().numpy().tobytes()
+    n = len(raw) // ctypes.sizeof(CgInfo)
+    arr = (CgInfo * n).from_buffer_copy(raw)
+    return [dict(iterations=a.iterations, breakdown=a.breakdown, rho0=a.rho0, rho=a.rho) for a in arr]
+
+
+def decode_sb_info(info) -> list[dict]:
+    raw = info.cpu().numpy().tobytes()
+    n = len(raw) // ctypes.sizeof(SbInfo)
+    arr = (SbInfo * n).from_buffer_copy(raw)
+    return [dict(outer=a.outer, breakdowns=a.breakdowns, upd_b_first=a.upd_b_first, upd_b=a.upd_b,
+                 upd_u=a.upd_u) for a in arr]

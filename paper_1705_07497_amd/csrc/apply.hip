@@ -1,0 +1,347 @@
+// Sparse products with the precomputed operator: y = MR x through the
+// ray-bundle layout, x = (MR)^T y through the pixel-group layout, and the
+// normal operator alpha R^T M^T M R + lambda K^T K + sigma I of eq:KKT,
+// eq:PD_resolve and eq:SB_solve (Section 2) with the K^T K and sigma terms and
+// the FP64 <x, Ax> partial sums fused into the adjoint's epilogue.
+//
+// Both products are bound by HBM bandwidth (2 flops per 5 bytes of stored
+// matrix): no MFMA; the work is laid out so that the value/index streams are
+// read with fully coalesced 64-lane loads and the gathers of the vector being
+// multiplied touch a few cache lines per wave load.
+#include "internal.hpp"
+
+namespace sct {
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// xT[b][ix][iy] = x[b][iy][ix] through a padded 32x32 LDS tile.
+template <class T>
+__global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ x, T *__restrict__ xT,
+                                                   int n, int64_t nn)
+{
+    __shared__ T tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int64_t boff = int64_t(blockIdx.z) * nn;
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int iy = by + i, ix = bx + threadIdx.x;
+        if (iy < n && ix < n) tile[i][threadIdx.x] = x[boff + int64_t(iy) * n + ix];
+    }
+    __syncthreads();
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int ix = bx + i, iy = by + threadIdx.x;
+        if (ix < n && iy < n) xT[boff + int64_t(ix) * n + iy] = tile[threadIdx.x][i];
+    }
+}
+
+// One wave per ray bundle: lane = (line offset q in 0..3, ray r in 0..15);
+// the wave walks the bundle's major lines four at a time, so every load of
+// the value/index streams is 64 consecutive slots and every gather hits four
+// image lines near the same place.
+template <class T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_fwd(const FwdBundle *__restrict__ fb, int64_t n_fb,
+                                                  const uint16_t *__restrict__ idx,
+                                                  const T *__restrict__ v0, const T *__restrict__ v1,
+                                                  const T *__restrict__ x, const T *__restrict__ xT,
+                                                  T *__restrict__ y, int n, int64_t nn, int64_t rows)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t B = int64_t(blockIdx.x) * WPB + wave;
+    if (B >= n_fb) return;
+    const int64_t bat = blockIdx.y;
+    const FwdBundle d = fb[B];
+    const T *__restrict__ img = (d.horiz ? xT : x) + bat * nn;
+    const int r = lane & 15, q = lane >> 4;
+    T acc = T(0);
+    int64_t s = d.off + int64_t(q) * kFwdLanes + r;
+#pragma unroll 4
+    for (int t = q; t < d.nrows; t += 4, s += 4 * kFwdLanes) {
+        const int m = min(d.m0 + t, n - 1);
+        const int i0 = idx[s];
+        const int i1 = i0 + 1 < n ? i0 + 1 : i0;
+        const T *__restrict__ line = img + int64_t(m) * n;
+        acc = fma(v0[s], line[i0], acc);
+        acc = fma(v1[s], line[i1], acc);
+    }
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    if (q == 0 && r < d.nrays) y[bat * rows + d.ray0 + r] = acc;
+}
+
+template <class T>
+__device__ inline T ktk_at(const T *__restrict__ xb, int64_t j, int n, T xj)
+{
+    const int iy = int(j / n), ix = int(j % n);
+    T k = T(0);
+    if (ix > 0) k += xj - xb[j - 1];
+    if (ix < n - 1) k += xj - xb[j + 1];
+    if (iy > 0) k += xj - xb[j - n];
+    if (iy < n - 1) k += xj - xb[j + n];
+    return k;
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One workgroup of W waves per 64-pixel group: wave w sums its share of the
+// measured angles for the 64 pixels (one sequential sum per pixel and wave),
+// the shares are added in wave order, and wave 0 applies the epilogue
+// out = alpha*acc + lambda*(K^T K x) + sigma*x and the FP64 partial <x, out>.
+template <class T, int W>
+__global__ __launch_bounds__(64 * W) void k_adj(const uint16_t *__restrict__ bin,
+                                                const T *__restrict__ v0, const T *__restrict__ v1,
+                                                int64_t n_ag, int n_meas, int nb,
+                                                const T *__restrict__ y, const T *__restrict__ x,
+                                                T *__restrict__ out, T alpha, T lambda, T sigma,
+                                                double *__restrict__ part, int n, int64_t nn,
+                                                int64_t rows)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t g = blockIdx.x;
+    const int64_t bat = blockIdx.y;
+    const T *__restrict__ yb = y + bat * rows;
+    const int a0 = (n_meas * wave) / W, a1 = (n_meas * (wave + 1)) / W;
+    T acc = T(0);
+    int64_t s = (g * n_meas + a0) * kAdjLanes + lane;
+#pragma unroll 4
+    for (int a = a0; a < a1; ++a, s += kAdjLanes) {
+        const int b0 = bin[s];
+        const int b1 = b0 + 1 < nb ? b0 + 1 : b0;
+        const T *__restrict__ yr = yb + int64_t(a) * nb;
+        acc = fma(v0[s], yr[b0], acc);
+        acc = fma(v1[s], yr[b1], acc);
+    }
+    if constexpr (W > 1) {
+        __shared__ T red[W][64];
+        red[wave][lane] = acc;
+        __syncthreads();
+        if (wave != 0) return;
+        acc = red[0][lane];
+#pragma unroll
+        for (int w = 1; w < W; ++w) acc += red[w][lane];
+    }
+    const int64_t j = g * kAdjLanes + lane;
+    double dp = 0.0;
+    if (j < nn) {
+        T o = alpha * acc;
+        if (x) {
+            const T *__restrict__ xb = x + bat * nn;
+            const T xj = xb[j];
+            if (lambda != T(0)) o += lambda * ktk_at(xb, j, n, xj);
+            if (sigma != T(0)) o += sigma * xj;
+            dp = double(xj) * double(o);
+        }
+        out[bat * nn + j] = o;
+    }
+    if (part) {
+        dp = wave_sum(dp);
+        if (lane == 0) part[bat * n_ag + g] = dp;
+    }
+}
+
+// dst[b] = sum_i part[b][i], in a fixed order (one block per b).
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part,
+                                                      int64_t count, double *__restrict__ dst)
+{
+    __shared__ double red[256];
+    const int64_t b = blockIdx.x;
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) v += part[b * count + i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dst[b] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static int check_grid_y(int batch)
+{
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    return RADON_OK;
+}
+
+template <class T>
+int launch_transpose(const Op &op, const T *x, T *xT, int batch, hipStream_t s)
+{
+    SCT_TRY(check_grid_y(batch));
+    const unsigned t = unsigned((op.n + 31) / 32);
+    k_transpose<T><<<dim3(t, t, unsigned(batch)), dim3(32, 8), 0, s>>>(x, xT, op.n, op.nn);
+    return check_launch("k_transpose");
+}
+
+template <class T>
+int launch_fwd(const Op &op, const T *x, const T *xT, T *y, int batch, hipStream_t s)
+{
+    SCT_TRY(check_grid_y(batch));
+    constexpr int WPB = 4;
+    const int64_t blocks = (op.n_fb + WPB - 1) / WPB;
+    k_fwd<T, WPB><<<dim3(unsigned(blocks), unsigned(batch)), 64 * WPB, 0, s>>>(
+        op.fb, op.n_fb, op.f_idx, static_cast<const T *>(op.f_v0), static_cast<const T *>(op.f_v1),
+        x, xT ? xT : x, y, op.n, op.nn, op.rows);
+    return check_launch("k_fwd");
+}
+
+template <class T>
+int launch_adj(const Op &op, const T *y, const T *x, T *out, double alpha, double lambda,
+               double sigma, double *part, int batch, hipStream_t s)
+{
+    SCT_TRY(check_grid_y(batch));
+    if (op.n_ag > int64_t(INT_MAX)) return set_error(RADON_EOVERFLOW, "too many pixel groups");
+    const dim3 grid(unsigned(op.n_ag), unsigned(batch));
+    const auto *bin = op.a_bin;
+    const T *a0 = static_cast<const T *>(op.a_v0), *a1 = static_cast<const T *>(op.a_v1);
+    const T al = T(alpha), la = T(lambda), si = T(sigma);
+    if (op.n_meas >= 128)
+        k_adj<T, 4><<<grid, 256, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out, al, la,
+                                         si, part, op.n, op.nn, op.rows);
+    else if (op.n_meas >= 48)
+        k_adj<T, 2><<<grid, 128, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out, al, la,
+                                         si, part, op.n, op.nn, op.rows);
+    else
+        k_adj<T, 1><<<grid, 64, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out, al, la,
+                                        si, part, op.n, op.nn, op.rows);
+    return check_launch("k_adj");
+}
+
+int launch_sum_partials(const double *part, int64_t count, double *dst, int batch, hipStream_t s)
+{
+    k_sum_partials<<<unsigned(batch), 256, 0, s>>>(part, count, dst);
+    return check_launch("k_sum_partials");
+}
+
+template int launch_transpose<float>(const Op &, const float *, float *, int, hipStream_t);
+template int launch_transpose<double>(const Op &, const double *, double *, int, hipStream_t);
+template int launch_fwd<float>(const Op &, const float *, const float *, float *, int, hipStream_t);
+template int launch_fwd<double>(const Op &, const double *, const double *, double *, int, hipStream_t);
+template int launch_adj<float>(const Op &, const float *, const float *, float *, double, double,
+                               double, double *, int, hipStream_t);
+template int launch_adj<double>(const Op &, const double *, const double *, double *, double, double,
+                                double, double *, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// workspace sizes
+// ---------------------------------------------------------------------------
+
+static int64_t fwd_ws_bytes(const Op &op, int batch)
+{
+    Carver c(nullptr);
+    if (op.need_T) c.take<char>(int64_t(op.esize) * op.nn * batch);
+    return c.used;
+}
+
+static int64_t normal_ws_bytes(const Op &op, int batch)
+{
+    Carver c(nullptr);
+    if (op.need_T) c.take<char>(int64_t(op.esize) * op.nn * batch);
+    c.take<char>(int64_t(op.esize) * op.rows * batch);
+    c.take<double>(op.n_ag * batch);
+    return c.used;
+}
+
+int64_t cg_ws_bytes(const Op &op, int batch);   // solve.hip
+int64_t sb_ws_bytes(const Op &op, int batch);   // solve.hip
+
+}  // namespace sct
+
+using namespace sct;
+
+extern "C" int64_t radon_workspace_bytes(const radon_op *p, int32_t which, int32_t batch)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    const Op &op = *as_op(p);
+    switch (which) {
+    case RADON_WS_FWD: return fwd_ws_bytes(op, batch);
+    case RADON_WS_NORMAL: return normal_ws_bytes(op, batch);
+    case RADON_WS_CG: return cg_ws_bytes(op, batch);
+    case RADON_WS_SB: return sb_ws_bytes(op, batch);
+    default: return set_error(RADON_EINVAL, "unknown workspace kind %d", which);
+    }
+}
+
+template <class T>
+static int fwd_typed(const Op &op, const void *x, void *y, int batch, void *ws, hipStream_t s)
+{
+    Carver c(ws);
+    T *xT = nullptr;
+    if (op.need_T) {
+        xT = c.take<T>(op.nn * batch);
+        SCT_TRY(launch_transpose<T>(op, static_cast<const T *>(x), xT, batch, s));
+    }
+    return launch_fwd<T>(op, static_cast<const T *>(x), xT, static_cast<T *>(y), batch, s);
+}
+
+extern "C" int radon_fwd(const radon_op *p, const void *x, void *y, int32_t batch, void *ws,
+                         int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!x || !y) return set_error(RADON_EINVAL, "x and y must be non-NULL");
+    const Op &op = *as_op(p);
+    SCT_TRY(check_ws(ws, ws_bytes, fwd_ws_bytes(op, batch), "radon_fwd"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return op.dtype == SPARSECT_F32 ? fwd_typed<float>(op, x, y, batch, ws, s)
+                                    : fwd_typed<double>(op, x, y, batch, ws, s);
+}
+
+extern "C" int radon_adj(const radon_op *p, const void *y, void *x, int32_t batch, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!x || !y) return set_error(RADON_EINVAL, "x and y must be non-NULL");
+    const Op &op = *as_op(p);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (op.dtype == SPARSECT_F32)
+        return launch_adj<float>(op, static_cast<const float *>(y), nullptr, static_cast<float *>(x),
+                                 1.0, 0.0, 0.0, nullptr, batch, s);
+    return launch_adj<double>(op, static_cast<const double *>(y), nullptr, static_cast<double *>(x),
+                              1.0, 0.0, 0.0, nullptr, batch, s);
+}
+
+template <class T>
+static int normal_typed(const Op &op, double alpha, double lambda, double sigma, const void *x,
+                        void *out, double *dot_out, int batch, void *ws, hipStream_t s)
+{
+    Carver c(ws);
+    T *xT = op.need_T ? c.take<T>(op.nn * batch) : nullptr;
+    T *y = c.take<T>(op.rows * batch);
+    double *part = c.take<double>(op.n_ag * batch);
+    const T *xx = static_cast<const T *>(x);
+    if (xT) SCT_TRY(launch_transpose<T>(op, xx, xT, batch, s));
+    SCT_TRY(launch_fwd<T>(op, xx, xT, y, batch, s));
+    SCT_TRY(launch_adj<T>(op, y, xx, static_cast<T *>(out), alpha, lambda, sigma,
+                          dot_out ? part : nullptr, batch, s));
+    if (dot_out) SCT_TRY(launch_sum_partials(part, op.n_ag, dot_out, batch, s));
+    return RADON_OK;
+}
+
+extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, double sigma,
+                            const void *x, void *out, double *dot_out, int32_t batch, void *ws,
+                            int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!x || !out) return set_error(RADON_EINVAL, "x and out must be non-NULL");
+    if (x == out) return set_error(RADON_EINVAL, "out must not alias x");
+    const Op &op = *as_op(p);
+    SCT_TRY(check_ws(ws, ws_bytes, normal_ws_bytes(op, batch), "normal_apply"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return op.dtype == SPARSECT_F32
+               ? normal_typed<float>(op, alpha, lambda, sigma, x, out, dot_out, batch, ws, s)
+               : normal_typed<double>(op, alpha, lambda, sigma, x, out, dot_out, batch, ws, s);
+}

@@ -1,0 +1,131 @@
+// Internal declarations of the sparsect library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sparsect.h"
+
+namespace sct {
+
+// Forward product layout: one bundle = up to 16 adjacent bins of one measured
+// angle.  Slot (t, r) of a bundle sits at off + t*16 + r and covers ray r of
+// the bundle on image line m0 + t along the rays' major axis (rows for rays
+// closer to vertical, columns for rays closer to horizontal).
+constexpr int kFwdLanes = 16;
+// Adjoint layout: one group = 64 consecutive pixels (row-major); slot (a, l)
+// of group g sits at (g*n_meas + a)*64 + l and covers pixel g*64 + l at
+// measured angle a.
+constexpr int kAdjLanes = 64;
+
+struct FwdBundle {
+    int64_t off;    // first slot
+    int32_t m0;     // first major line
+    int32_t nrows;  // major lines covered (multiple of 4, may be 0)
+    int32_t ray0;   // first measured ray of the bundle
+    int32_t nrays;  // rays in the bundle (<= 16)
+    int32_t horiz;  // 1: major axis is x (gather from the transposed image)
+    int32_t pad;
+};
+static_assert(sizeof(FwdBundle) == 32, "FwdBundle layout");
+
+struct Op {
+    int32_t n = 0, n_angles = 0, n_bins = 0, dtype = 0;
+    int32_t n_meas = 0;              // measured angles
+    int64_t nn = 0;                  // pixels
+    int64_t rows = 0;                // measured rays
+    int64_t nnz = 0;
+    bool need_T = false;             // some measured angle uses the transposed image
+    std::vector<int32_t> meas;       // measured angle indices (host)
+    int32_t esize = 4;               // bytes per value
+
+    // CSR of MR (device)
+    int64_t *rp = nullptr;
+    int32_t *col = nullptr;
+    void *val = nullptr;
+
+    // forward ray-bundle layout (device)
+    int64_t n_fb = 0, f_slots = 0;
+    FwdBundle *fb = nullptr;
+    uint16_t *f_idx = nullptr;
+    void *f_v0 = nullptr, *f_v1 = nullptr;
+
+    // adjoint pixel-group layout (device)
+    int64_t n_ag = 0, a_slots = 0;
+    uint16_t *a_bin = nullptr;
+    void *a_v0 = nullptr, *a_v1 = nullptr;
+
+    int64_t device_bytes = 0;
+    std::vector<void *> owned;       // every hipMalloc of the handle
+};
+
+// thread-local error state
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+
+#define SCT_HIP(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::sct::set_error(RADON_EHIP, "%s failed: %s", #expr,              \
+                                    hipGetErrorString(e_));                           \
+    } while (0)
+
+#define SCT_TRY(expr)                                                                 \
+    do {                                                                              \
+        int s_ = (expr);                                                              \
+        if (s_ != RADON_OK) return s_;                                                \
+    } while (0)
+
+inline int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(RADON_EHIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return RADON_OK;
+}
+
+inline const Op *as_op(const radon_op *p) { return reinterpret_cast<const Op *>(p); }
+inline Op *as_op(radon_op *p) { return reinterpret_cast<Op *>(p); }
+
+int check_op(const radon_op *p);
+int check_batch(int32_t batch);
+int check_ws(const void *ws, int64_t ws_bytes, int64_t need, const char *what);
+
+// Workspace carving: 256-byte aligned sub-buffers.
+struct Carver {
+    char *base;
+    int64_t used = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(int64_t count)
+    {
+        used = (used + 255) & ~int64_t(255);
+        T *p = reinterpret_cast<T *>(base ? base + used : nullptr);
+        used += count * int64_t(sizeof(T));
+        return p;
+    }
+};
+
+// --- apply-level launchers (apply.hip) ----------------------------------------
+// Transposed copy of `batch` n x n images.
+template <class T>
+int launch_transpose(const Op &op, const T *x, T *xT, int batch, hipStream_t s);
+// y = MR x, gathering from x and (for horizontal bundles) xT.
+template <class T>
+int launch_fwd(const Op &op, const T *x, const T *xT, T *y, int batch, hipStream_t s);
+// out = alpha (MR)^T y + lambda K^T K x + sigma x; partial <x, out> per group
+// into part[batch][n_ag] when part != nullptr.  x may be nullptr when
+// lambda == sigma == 0 and part == nullptr.
+template <class T>
+int launch_adj(const Op &op, const T *y, const T *x, T *out, double alpha, double lambda,
+               double sigma, double *part, int batch, hipStream_t s);
+// sum part[batch][count] -> dst[batch] (fixed order)
+int launch_sum_partials(const double *part, int64_t count, double *dst, int batch, hipStream_t s);
+
+// Sizes of the apply temporaries.
+int64_t normal_ws_elems(const Op &op, int batch);   // in units of the op dtype + partials
+
+}  // namespace sct

@@ -1,0 +1,640 @@
+// Conjugate gradients on the normal operator (Section 2: eq:KKT, eq:PD_resolve
+// and eq:SB_solve have no closed-form solution and are solved iteratively)
+// and anisotropic-TV split Bregman (Goldstein-Osher, the solver of Section 4,
+// with inexact inner solves as in Section 3.2).
+//
+// Vectors stay in the operator dtype; the CG scalars rho, gamma, alpha_k and
+// beta_k live in FP64 on the device and are updated by single-block kernels,
+// so nothing is read back to the host inside a solve.  Every reduction sums
+// FP64 partials in a fixed order, which makes runs bitwise reproducible.
+#include "internal.hpp"
+
+#include <cmath>
+
+namespace sct {
+
+struct CgScal {
+    double rho, rho0, a, beta, gamma;
+    int32_t stopped, iters, breakdown, pad;
+};
+
+struct SbScal {
+    double first, upd_b, upd_u;
+    int32_t outer, stop, breakdowns, pad;
+};
+
+constexpr int kVecThreads = 256;
+
+static int vec_blocks(int64_t nn)
+{
+    const int64_t b = (nn + 4 * kVecThreads - 1) / (4 * kVecThreads);
+    return int(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+static int tiles_of(int n) { return (n + 31) / 32; }
+
+__device__ inline double block_sum(double v, double *red)
+{
+    // fixed-order tree over the block (blockDim.x * blockDim.y threads, a power of two)
+    const int nt = blockDim.x * blockDim.y;
+    const int t = threadIdx.y * blockDim.x + threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int o = nt / 2; o >= 1; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels
+// ---------------------------------------------------------------------------
+
+// p = r (and its transposed copy pT when requested), uprev = u when requested,
+// partial <r, r> per 32x32 tile.
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_start(const T *__restrict__ r, T *__restrict__ p,
+                                                  T *__restrict__ pT, const T *__restrict__ u,
+                                                  T *__restrict__ uprev, double *__restrict__ part,
+                                                  int n, int64_t nn)
+{
+    __shared__ T tile[32][33];
+    __shared__ double red[256];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int64_t off = int64_t(blockIdx.z) * nn;
+    double acc = 0.0;
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int iy = by + i, ix = bx + threadIdx.x;
+        if (iy < n && ix < n) {
+            const int64_t j = off + int64_t(iy) * n + ix;
+            const T v = r[j];
+            p[j] = v;
+            tile[i][threadIdx.x] = v;
+            acc += double(v) * double(v);
+            if (uprev) uprev[j] = u[j];
+        }
+    }
+    const double tot = block_sum(acc, red);
+    if (pT) {
+        for (int i = threadIdx.y; i < 32; i += 8) {
+            const int ix = bx + i, iy = by + threadIdx.x;
+            if (ix < n && iy < n) pT[off + int64_t(ix) * n + iy] = tile[threadIdx.x][i];
+        }
+    }
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        part[int64_t(blockIdx.z) * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = tot;
+}
+
+__device__ inline double sum_part_block(const double *__restrict__ part, int64_t count, double *red)
+{
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) v += part[i];
+    return block_sum(v, red);
+}
+
+// rho_0 = sum of partials; resets the per-solve state.  A set SB stop flag
+// starts the solve stopped (the outer loop has finished).
+__global__ __launch_bounds__(256) void k_cg_begin(const double *__restrict__ part, int64_t count,
+                                                  CgScal *__restrict__ sc,
+                                                  const SbScal *__restrict__ sbs)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    const double rho = sum_part_block(part + int64_t(b) * count, count, red);
+    if (threadIdx.x == 0) {
+        CgScal c;
+        c.rho = rho;
+        c.rho0 = rho;
+        c.a = 0.0;
+        c.beta = 0.0;
+        c.gamma = 0.0;
+        c.stopped = (sbs && sbs[b].stop) ? 1 : 0;
+        c.iters = 0;
+        c.breakdown = 0;
+        c.pad = 0;
+        sc[b] = c;
+    }
+}
+
+// gamma = <p, Ap>; stop on rho == 0, on the relative tolerance, or on a
+// breakdown (gamma <= 0 or non-finite); a = rho / gamma otherwise.
+__global__ __launch_bounds__(256) void k_cg_alpha(const double *__restrict__ part, int64_t count,
+                                                  CgScal *__restrict__ sc, double rtol, int it)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    const double gamma = sum_part_block(part + int64_t(b) * count, count, red);
+    if (threadIdx.x == 0) {
+        CgScal c = sc[b];
+        c.gamma = gamma;
+        c.a = 0.0;
+        if (!c.stopped) {
+            if (c.rho == 0.0 || (rtol > 0.0 && sqrt(c.rho) <= rtol * sqrt(c.rho0))) {
+                c.stopped = 1;
+            } else if (!(gamma > 0.0) || !isfinite(gamma)) {
+                c.stopped = 1;
+                c.breakdown = it + 1;
+            } else {
+                c.a = c.rho / gamma;
+            }
+        }
+        sc[b] = c;
+    }
+}
+
+// x += a p ; r -= a q ; partial <r, r>
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_cg_xr(T *__restrict__ x, T *__restrict__ r,
+                                                        const T *__restrict__ p,
+                                                        const T *__restrict__ q,
+                                                        const CgScal *__restrict__ sc,
+                                                        double *__restrict__ part, int64_t nn)
+{
+    __shared__ double red[kVecThreads];
+    const int64_t b = blockIdx.y;
+    if (sc[b].stopped) return;   // uniform per block; the partials are then unused
+    const T a = T(sc[b].a);
+    const int64_t off = b * nn;
+    double acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
+         i += int64_t(gridDim.x) * kVecThreads) {
+        const int64_t j = off + i;
+        x[j] = fma(a, p[j], x[j]);
+        const T rn = fma(-a, q[j], r[j]);
+        r[j] = rn;
+        acc += double(rn) * double(rn);
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_cg_beta(const double *__restrict__ part, int64_t count,
+                                                 CgScal *__restrict__ sc)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    const double rn = sum_part_block(part + int64_t(b) * count, count, red);
+    if (threadIdx.x == 0) {
+        CgScal c = sc[b];
+        if (!c.stopped) {
+            c.beta = rn / c.rho;
+            c.rho = rn;
+            c.iters += 1;
+        } else {
+            c.beta = 0.0;
+        }
+        sc[b] = c;
+    }
+}
+
+// p = r + beta p, with the transposed copy.
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_p(const T *__restrict__ r, T *__restrict__ p,
+                                              T *__restrict__ pT, const CgScal *__restrict__ sc,
+                                              int n, int64_t nn)
+{
+    __shared__ T tile[32][33];
+    const int64_t b = blockIdx.z;
+    if (sc[b].stopped) return;
+    const T beta = T(sc[b].beta);
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int64_t off = b * nn;
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int iy = by + i, ix = bx + threadIdx.x;
+        if (iy < n && ix < n) {
+            const int64_t j = off + int64_t(iy) * n + ix;
+            const T v = fma(beta, p[j], r[j]);
+            p[j] = v;
+            tile[i][threadIdx.x] = v;
+        }
+    }
+    if (!pT) return;
+    __syncthreads();
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int ix = bx + i, iy = by + threadIdx.x;
+        if (ix < n && iy < n) pT[off + int64_t(ix) * n + iy] = tile[threadIdx.x][i];
+    }
+}
+
+__global__ void k_cg_info(const CgScal *__restrict__ sc, radon_cg_info *__restrict__ info, int batch)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    radon_cg_info o;
+    o.iterations = sc[b].iters;
+    o.breakdown = sc[b].breakdown;
+    o.rho0 = sc[b].rho0;
+    o.rho = sc[b].rho;
+    info[b] = o;
+}
+
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_fill(T *__restrict__ x, T v, int64_t count)
+{
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < count;
+         i += int64_t(gridDim.x) * kVecThreads)
+        x[i] = v;
+}
+
+// r = a - b (a may alias r)
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_sub(const T *a, const T *__restrict__ b, T *r,
+                                                      int64_t count)
+{
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < count;
+         i += int64_t(gridDim.x) * kVecThreads)
+        r[i] = a[i] - b[i];
+}
+
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_copy(const T *__restrict__ a, T *__restrict__ r,
+                                                       int64_t count)
+{
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < count;
+         i += int64_t(gridDim.x) * kVecThreads)
+        r[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------
+// split Bregman kernels
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ inline T shrink(T z, T g)
+{
+    const T a = fabs(z) - g;
+    if (a <= T(0)) return T(0);
+    return z > T(0) ? a : -a;
+}
+
+// g = K u; d = shrink(g + b, 1/lambda); b += g - d; dw = (d - b) - (d_old - b_old);
+// partials of ||b_new - b_old||_1 and ||u - u_prev||_1.
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_sb_shrink(
+    const T *__restrict__ u, const T *__restrict__ uprev, T *__restrict__ dx, T *__restrict__ dy,
+    T *__restrict__ bx, T *__restrict__ by, T *__restrict__ dwx, T *__restrict__ dwy, T thresh,
+    const SbScal *__restrict__ sbs, double *__restrict__ part, int n, int64_t nn)
+{
+    __shared__ double red[kVecThreads];
+    const int64_t b = blockIdx.y;
+    if (sbs[b].stop) return;
+    const int64_t off = b * nn;
+    double sb_acc = 0.0, su_acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
+         i += int64_t(gridDim.x) * kVecThreads) {
+        const int iy = int(i / n), ix = int(i % n);
+        const int64_t j = off + i;
+        const T uj = u[j];
+        const T gx = ix < n - 1 ? u[j + 1] - uj : T(0);
+        const T gy = iy < n - 1 ? u[j + n] - uj : T(0);
+        const T obx = bx[j], oby = by[j], odx = dx[j], ody = dy[j];
+        const T ndx = shrink(gx + obx, thresh);
+        const T ndy = shrink(gy + oby, thresh);
+        const T nbx = obx + gx - ndx;
+        const T nby = oby + gy - ndy;
+        sb_acc += double(fabs(nbx - obx)) + double(fabs(nby - oby));
+        su_acc += double(fabs(uj - uprev[j]));
+        dwx[j] = (ndx - nbx) - (odx - obx);
+        dwy[j] = (ndy - nby) - (ody - oby);
+        dx[j] = ndx;
+        dy[j] = ndy;
+        bx[j] = nbx;
+        by[j] = nby;
+    }
+    const double t1 = block_sum(sb_acc, red);
+    const double t2 = block_sum(su_acc, red);
+    if (threadIdx.x == 0) {
+        part[(b * gridDim.x + blockIdx.x) * 2 + 0] = t1;
+        part[(b * gridDim.x + blockIdx.x) * 2 + 1] = t2;
+    }
+}
+
+// r += lambda K^T dw  (the right-hand side of the next solve grows by
+// lambda K^T (w_new - w_old), w = d - b)
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_sb_carry(T *__restrict__ r,
+                                                           const T *__restrict__ dwx,
+                                                           const T *__restrict__ dwy, T lambda,
+                                                           const SbScal *__restrict__ sbs, int n,
+                                                           int64_t nn)
+{
+    const int64_t b = blockIdx.y;
+    if (sbs[b].stop) return;
+    const int64_t off = b * nn;
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
+         i += int64_t(gridDim.x) * kVecThreads) {
+        const int iy = int(i / n), ix = int(i % n);
+        const int64_t j = off + i;
+        T kt = T(0);
+        if (ix >= 1) kt += dwx[j - 1];
+        if (ix <= n - 2) kt -= dwx[j];
+        if (iy >= 1) kt += dwy[j - n];
+        if (iy <= n - 2) kt -= dwy[j];
+        r[j] += lambda * kt;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sb_update(const double *__restrict__ part, int64_t count,
+                                                   SbScal *__restrict__ sbs,
+                                                   const CgScal *__restrict__ sc, double tol)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    double v1 = 0.0, v2 = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) {
+        v1 += part[(int64_t(b) * count + i) * 2 + 0];
+        v2 += part[(int64_t(b) * count + i) * 2 + 1];
+    }
+    const double ub = block_sum(v1, red);
+    const double uu = block_sum(v2, red);
+    if (threadIdx.x == 0) {
+        SbScal s = sbs[b];
+        if (!s.stop) {
+            s.outer += 1;
+            if (sc[b].breakdown) s.breakdowns += 1;
+            if (s.outer == 1) s.first = ub;
+            s.upd_b = ub;
+            s.upd_u = uu;
+            if (tol > 0.0 && s.outer > 1 && ub < tol * s.first) s.stop = 1;
+        }
+        sbs[b] = s;
+    }
+}
+
+__global__ void k_sb_reset(SbScal *__restrict__ sbs, int batch)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    SbScal s;
+    s.first = 0.0;
+    s.upd_b = 0.0;
+    s.upd_u = 0.0;
+    s.outer = 0;
+    s.stop = 0;
+    s.breakdowns = 0;
+    s.pad = 0;
+    sbs[b] = s;
+}
+
+__global__ void k_sb_info(const SbScal *__restrict__ sbs, radon_sb_info *__restrict__ info, int batch)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    radon_sb_info o;
+    o.outer = sbs[b].outer;
+    o.breakdowns = sbs[b].breakdowns;
+    o.upd_b_first = sbs[b].first;
+    o.upd_b = sbs[b].upd_b;
+    o.upd_u = sbs[b].upd_u;
+    info[b] = o;
+}
+
+// ---------------------------------------------------------------------------
+// host drivers
+// ---------------------------------------------------------------------------
+
+template <class T>
+struct CgBufs {
+    T *r = nullptr, *p = nullptr, *pT = nullptr, *q = nullptr, *y = nullptr;
+    double *part_adj = nullptr, *part_vec = nullptr;
+    CgScal *sc = nullptr;
+};
+
+template <class T>
+static void carve_cg(const Op &op, int batch, Carver &c, CgBufs<T> &w)
+{
+    const int64_t nb = op.nn * batch;
+    w.r = c.take<T>(nb);
+    w.p = c.take<T>(nb);
+    w.pT = op.need_T ? c.take<T>(nb) : nullptr;
+    w.q = c.take<T>(nb);
+    w.y = c.take<T>(op.rows * batch);
+    w.part_adj = c.take<double>(op.n_ag * batch);
+    const int64_t tl = int64_t(tiles_of(op.n)) * tiles_of(op.n);
+    const int64_t pv = tl > 2 * vec_blocks(op.nn) ? tl : 2 * vec_blocks(op.nn);
+    w.part_vec = c.take<double>(pv * batch);
+    w.sc = c.take<CgScal>(batch);
+}
+
+int64_t cg_ws_bytes(const Op &op, int batch)
+{
+    Carver c(nullptr);
+    if (op.dtype == SPARSECT_F32) {
+        CgBufs<float> w;
+        carve_cg(op, batch, c, w);
+    } else {
+        CgBufs<double> w;
+        carve_cg(op, batch, c, w);
+    }
+    return c.used;
+}
+
+template <class T>
+struct SbBufs {
+    T *dx, *dy, *bx, *by, *dwx, *dwy, *uprev;
+    SbScal *sbs;
+    double *part;
+    CgBufs<T> cg;
+};
+
+template <class T>
+static void carve_sb(const Op &op, int batch, Carver &c, SbBufs<T> &w)
+{
+    const int64_t nb = op.nn * batch;
+    // persistent state first so that a resumed call finds it at the same place
+    w.dx = c.take<T>(nb);
+    w.dy = c.take<T>(nb);
+    w.bx = c.take<T>(nb);
+    w.by = c.take<T>(nb);
+    carve_cg(op, batch, c, w.cg);   // cg.r is the carried residual
+    w.dwx = c.take<T>(nb);
+    w.dwy = c.take<T>(nb);
+    w.uprev = c.take<T>(nb);
+    w.sbs = c.take<SbScal>(batch);
+    w.part = c.take<double>(int64_t(2) * vec_blocks(op.nn) * batch);
+}
+
+int64_t sb_ws_bytes(const Op &op, int batch)
+{
+    Carver c(nullptr);
+    if (op.dtype == SPARSECT_F32) {
+        SbBufs<float> w;
+        carve_sb(op, batch, c, w);
+    } else {
+        SbBufs<double> w;
+        carve_sb(op, batch, c, w);
+    }
+    return c.used;
+}
+
+// One CG solve on A(alpha, lambda, sigma) from x with the residual already in w.r.
+template <class T>
+static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x, int batch,
+                  int n_iter, double rtol, CgBufs<T> &w, T *u_for_prev, T *uprev,
+                  const SbScal *sbs, hipStream_t s)
+{
+    const unsigned t = unsigned(tiles_of(op.n));
+    const dim3 tg{t, t, unsigned(batch)}, tb{32, 8, 1};
+    const int64_t ntiles = int64_t(t) * t;
+    k_cg_start<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, u_for_prev, uprev, w.part_vec, op.n, op.nn);
+    SCT_TRY(check_launch("k_cg_start"));
+    k_cg_begin<<<unsigned(batch), 256, 0, s>>>(w.part_vec, ntiles, w.sc, sbs);
+    SCT_TRY(check_launch("k_cg_begin"));
+    const int vb = vec_blocks(op.nn);
+    for (int it = 0; it < n_iter; ++it) {
+        SCT_TRY(launch_fwd<T>(op, w.p, w.pT, w.y, batch, s));
+        SCT_TRY(launch_adj<T>(op, w.y, w.p, w.q, alpha, lambda, sigma, w.part_adj, batch, s));
+        k_cg_alpha<<<unsigned(batch), 256, 0, s>>>(w.part_adj, op.n_ag, w.sc, rtol, it);
+        SCT_TRY(check_launch("k_cg_alpha"));
+        k_cg_xr<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(x, w.r, w.p, w.q, w.sc,
+                                                                               w.part_vec, op.nn);
+        SCT_TRY(check_launch("k_cg_xr"));
+        k_cg_beta<<<unsigned(batch), 256, 0, s>>>(w.part_vec, vb, w.sc);
+        SCT_TRY(check_launch("k_cg_beta"));
+        k_cg_p<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, w.sc, op.n, op.nn);
+        SCT_TRY(check_launch("k_cg_p"));
+    }
+    return RADON_OK;
+}
+
+// w.q = A x (uses w.pT and w.y as temporaries)
+template <class T>
+static int apply_A_into_q(const Op &op, double alpha, double lambda, double sigma, const T *x,
+                          int batch, CgBufs<T> &w, hipStream_t s)
+{
+    if (w.pT) SCT_TRY(launch_transpose<T>(op, x, w.pT, batch, s));
+    SCT_TRY(launch_fwd<T>(op, x, w.pT, w.y, batch, s));
+    return launch_adj<T>(op, w.y, x, w.q, alpha, lambda, sigma, nullptr, batch, s);
+}
+
+template <class T>
+static int cg_typed(const Op &op, double alpha, double lambda, double sigma, const void *rhs_v,
+                    void *x_v, int x0_given, int batch, int n_iter, double rtol, void *ws,
+                    radon_cg_info *info, hipStream_t s)
+{
+    Carver c(ws);
+    CgBufs<T> w;
+    carve_cg(op, batch, c, w);
+    const T *rhs = static_cast<const T *>(rhs_v);
+    T *x = static_cast<T *>(x_v);
+    const int64_t cnt = op.nn * batch;
+    const int vb = vec_blocks(cnt);
+    if (x0_given) {
+        SCT_TRY(apply_A_into_q<T>(op, alpha, lambda, sigma, x, batch, w, s));
+        k_sub<T><<<vb, kVecThreads, 0, s>>>(rhs, w.q, w.r, cnt);
+        SCT_TRY(check_launch("k_sub"));
+    } else {
+        k_fill<T><<<vb, kVecThreads, 0, s>>>(x, T(0), cnt);
+        SCT_TRY(check_launch("k_fill"));
+        k_copy<T><<<vb, kVecThreads, 0, s>>>(rhs, w.r, cnt);
+        SCT_TRY(check_launch("k_copy"));
+    }
+    SCT_TRY(cg_run<T>(op, alpha, lambda, sigma, x, batch, n_iter, rtol, w, nullptr, nullptr, nullptr, s));
+    if (info) {
+        k_cg_info<<<unsigned((batch + 63) / 64), 64, 0, s>>>(w.sc, info, batch);
+        SCT_TRY(check_launch("k_cg_info"));
+    }
+    return RADON_OK;
+}
+
+template <class T>
+static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, void *mu_v, int batch,
+                    void *ws, radon_sb_info *info, hipStream_t s)
+{
+    Carver c(ws);
+    SbBufs<T> w;
+    carve_sb(op, batch, c, w);
+    const T *f = static_cast<const T *>(f_v);
+    T *u = static_cast<T *>(mu_v);
+    const int64_t cnt = op.nn * batch;
+    const int vbc = vec_blocks(cnt);
+    const int vb = vec_blocks(op.nn);
+    const double alpha = P.alpha, lambda = P.lambda;
+    if (!(P.flags & RADON_SB_RESUME)) {
+        for (T *z : {w.dx, w.dy, w.bx, w.by}) {
+            k_fill<T><<<vbc, kVecThreads, 0, s>>>(z, T(0), cnt);
+            SCT_TRY(check_launch("k_fill"));
+        }
+        // r = alpha (MR)^T f - A u
+        SCT_TRY(launch_adj<T>(op, f, nullptr, w.cg.r, alpha, 0.0, 0.0, nullptr, batch, s));
+        if (P.flags & RADON_SB_WARM) {
+            SCT_TRY(apply_A_into_q<T>(op, alpha, lambda, 0.0, u, batch, w.cg, s));
+            k_sub<T><<<vbc, kVecThreads, 0, s>>>(w.cg.r, w.cg.q, w.cg.r, cnt);
+            SCT_TRY(check_launch("k_sub"));
+        } else {
+            k_fill<T><<<vbc, kVecThreads, 0, s>>>(u, T(0), cnt);
+            SCT_TRY(check_launch("k_fill"));
+        }
+    }
+    k_sb_reset<<<unsigned((batch + 63) / 64), 64, 0, s>>>(w.sbs, batch);
+    SCT_TRY(check_launch("k_sb_reset"));
+    const T thresh = T(1.0 / lambda);
+    for (int k = 0; k < P.n_outer; ++k) {
+        SCT_TRY(cg_run<T>(op, alpha, lambda, 0.0, u, batch, P.n_cg, 0.0, w.cg, u, w.uprev, w.sbs, s));
+        k_sb_shrink<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
+            u, w.uprev, w.dx, w.dy, w.bx, w.by, w.dwx, w.dwy, thresh, w.sbs, w.part, op.n, op.nn);
+        SCT_TRY(check_launch("k_sb_shrink"));
+        k_sb_carry<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
+            w.cg.r, w.dwx, w.dwy, T(lambda), w.sbs, op.n, op.nn);
+        SCT_TRY(check_launch("k_sb_carry"));
+        k_sb_update<<<unsigned(batch), 256, 0, s>>>(w.part, vb, w.sbs, w.cg.sc, P.tol);
+        SCT_TRY(check_launch("k_sb_update"));
+    }
+    if (info) {
+        k_sb_info<<<unsigned((batch + 63) / 64), 64, 0, s>>>(w.sbs, info, batch);
+        SCT_TRY(check_launch("k_sb_info"));
+    }
+    return RADON_OK;
+}
+
+}  // namespace sct
+
+using namespace sct;
+
+extern "C" int cg_solve(const radon_op *p, double alpha, double lambda, double sigma,
+                        const void *rhs, void *x, int32_t x0_given, int32_t batch, int32_t n_iter,
+                        double rtol, void *ws, int64_t ws_bytes, radon_cg_info *info, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!rhs || !x) return set_error(RADON_EINVAL, "rhs and x must be non-NULL");
+    if (rhs == x) return set_error(RADON_EINVAL, "x must not alias rhs");
+    if (n_iter < 0) return set_error(RADON_EINVAL, "n_iter must be >= 0 (got %d)", n_iter);
+    if (!(rtol >= 0.0)) return set_error(RADON_EINVAL, "rtol must be >= 0");
+    const Op &op = *as_op(p);
+    SCT_TRY(check_ws(ws, ws_bytes, cg_ws_bytes(op, batch), "cg_solve"));
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return op.dtype == SPARSECT_F32
+               ? cg_typed<float>(op, alpha, lambda, sigma, rhs, x, x0_given, batch, n_iter, rtol, ws,
+                                 info, s)
+               : cg_typed<double>(op, alpha, lambda, sigma, rhs, x, x0_given, batch, n_iter, rtol, ws,
+                                  info, s);
+}
+
+extern "C" int split_bregman_tv(const radon_op *p, const radon_sb_params *params, const void *f,
+                                void *mu, int32_t batch, void *ws, int64_t ws_bytes,
+                                radon_sb_info *info, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!params) return set_error(RADON_EINVAL, "params is NULL");
+    if (!f || !mu) return set_error(RADON_EINVAL, "f and mu must be non-NULL");
+    if (!(params->lambda > 0.0)) return set_error(RADON_EINVAL, "lambda must be > 0");
+    if (params->n_outer < 0 || params->n_cg < 0)
+        return set_error(RADON_EINVAL, "n_outer and n_cg must be >= 0");
+    if (!(params->tol >= 0.0)) return set_error(RADON_EINVAL, "tol must be >= 0");
+    if (params->flags & ~(RADON_SB_WARM | RADON_SB_RESUME))
+        return set_error(RADON_EINVAL, "unknown flags 0x%x", params->flags);
+    const Op &op = *as_op(p);
+    SCT_TRY(check_ws(ws, ws_bytes, sb_ws_bytes(op, batch), "split_bregman_tv"));
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return op.dtype == SPARSECT_F32 ? sb_typed<float>(op, *params, f, mu, batch, ws, info, s)
+                                    : sb_typed<double>(op, *params, f, mu, batch, ws, info, s);
+}

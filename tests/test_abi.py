@@ -1,0 +1,106 @@
+"""C-ABI contract checks that need no GPU.
+
+* libsparsect.so loads and exports every function include/sparsect.h declares;
+* the binding's signature table covers exactly those functions;
+* argument validation happens before any HIP call and returns the documented
+  status with a message.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1705_07497_amd as sct
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sparsect.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 12, names
+    L = sct.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(sct.SIGNATURES) == names
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define\s+(\w+)\s+(-?\d+)", text))
+    assert int(consts["SPARSECT_F32"]) == sct.F32 and int(consts["SPARSECT_F64"]) == sct.F64
+    assert int(consts["RADON_WS_SB"]) == sct.WS_SB and int(consts["RADON_SB_RESUME"]) == sct.SB_RESUME
+    # struct sizes the binding assumes
+    assert ctypes.sizeof(sct.CgInfo) == 24
+    assert ctypes.sizeof(sct.SbParams) == 40
+    assert ctypes.sizeof(sct.SbInfo) == 32
+
+
+def _build(n, na, nb, dtype=0, measured=None):
+    L = sct.lib()
+    m = None
+    if measured is not None:
+        arr = (ctypes.c_uint8 * len(measured))(*measured)
+        m = ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint8))
+    g = sct._Geom(n, na, nb, dtype, m)
+    h = ctypes.c_void_p()
+    rc = L.build_radon_csr(ctypes.byref(g), None, ctypes.byref(h))
+    return rc, L.radon_last_error().decode()
+
+
+@pytest.mark.parametrize("args,code,frag", [
+    ((0, 4, 5), -1, "n must be"),
+    ((40000, 4, 5), -1, "n must be"),
+    ((8, 0, 5), -1, "n_angles"),
+    ((8, 4, 0), -1, "n_bins"),
+    ((8, 4, 70000), -1, "n_bins"),
+    ((8, 4, 13, 7), -1, "dtype"),
+])
+def test_build_rejects_bad_geometry(args, code, frag):
+    rc, msg = _build(*args)
+    assert rc == code and frag in msg
+
+
+def test_build_rejects_no_measured_angle():
+    rc, msg = _build(8, 4, 13, 0, [0, 0, 0, 0])
+    assert rc == -1 and "no measured angle" in msg
+
+
+def test_build_rejects_overflowing_geometry():
+    # 32767^2 pixels x 40000 measured angles overflows the adjoint layout
+    rc, msg = _build(32767, 40000, 46341)
+    assert rc == -2, msg
+
+
+def test_null_handles_are_rejected():
+    L = sct.lib()
+    assert L.build_radon_csr(None, None, None) == -1
+    h = ctypes.c_void_p()
+    assert L.build_radon_csr(None, None, ctypes.byref(h)) == -1
+    assert L.radon_fwd(None, None, None, 1, None, 0, None) == -1
+    assert "NULL" in L.radon_last_error().decode()
+    assert L.radon_adj(None, None, None, 1, None) == -1
+    assert L.normal_apply(None, 1.0, 1.0, 0.0, None, None, None, 1, None, 0, None) == -1
+    assert L.cg_solve(None, 1.0, 1.0, 0.0, None, None, 0, 1, 5, 0.0, None, 0, None, None) == -1
+    assert L.split_bregman_tv(None, None, None, None, 1, None, 0, None, None) == -1
+    assert L.radon_workspace_bytes(None, 0, 1) == -1
+    info = sct._Info()
+    assert L.radon_op_info(None, ctypes.byref(info)) == -1
+    assert L.radon_export_csr(None, None, None, None) == -1
+    L.radon_op_destroy(None)   # no-op
+
+
+def test_binding_refuses_without_gpu():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(sct.SparsectError):
+        sct.RadonOp(8, 4, 13)
