@@ -29,8 +29,14 @@
  *     stream) and return without synchronising.  build_radon_csr and the
  *     export calls synchronise.
  *   - Images are laid out [batch][n*n]; measured sinograms [batch][n_meas][n_bins]
- *     with the measured angles in ascending order.  The element type is the
- *     operator's dtype (float for SPARSECT_F32, double for SPARSECT_F64).
+ *     with the measured angles in ascending order.  Vector elements are float
+ *     for SPARSECT_F32 and double for SPARSECT_F64 and SPARSECT_F32_F64.
+ *     SPARSECT_F32_F64 streams the matrix in FP32 (the bandwidth-bound part)
+ *     but keeps every vector and every multiply-add in FP64: CG iterates in
+ *     FP32 drift from the exact-arithmetic iterates by the conditioning of the
+ *     normal operator times the FP32 rounding, which exceeds 1e-5 relative
+ *     within ten iterations on the workloads this library targets, while the
+ *     FP32 rounding of the matrix entries alone stays near 1e-6.
  *   - Every call returns RADON_OK (0) or a negative status; radon_last_error()
  *     returns a message for the calling thread's most recent failure.
  *   - Argument checks happen before anything is enqueued.
@@ -46,8 +52,9 @@
 extern "C" {
 #endif
 
-#define SPARSECT_F32 0
-#define SPARSECT_F64 1
+#define SPARSECT_F32     0   /* FP32 matrix values, FP32 vectors */
+#define SPARSECT_F64     1   /* FP64 matrix values, FP64 vectors */
+#define SPARSECT_F32_F64 2   /* FP32 matrix values, FP64 vectors and arithmetic */
 
 #define RADON_OK            0
 #define RADON_EINVAL       -1   /* bad argument */
@@ -63,7 +70,7 @@ typedef struct {
     int32_t n;                  /* image side, 1 <= n <= 32767 */
     int32_t n_angles;           /* angles theta_k = pi*k/n_angles, >= 1 */
     int32_t n_bins;             /* detector bins, 1 <= n_bins <= 65535 */
-    int32_t dtype;              /* SPARSECT_F32 or SPARSECT_F64 */
+    int32_t dtype;              /* SPARSECT_F32, SPARSECT_F64 or SPARSECT_F32_F64 */
     const uint8_t *measured;    /* host array of n_angles flags (nonzero = measured),
                                    NULL = every angle measured; at least one set */
 } radon_geom;

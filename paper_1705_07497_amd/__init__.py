@@ -23,7 +23,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsparsect.so")
 
-F32, F64 = 0, 1
+F32, F64, F32_F64 = 0, 1, 2
 WS_FWD, WS_NORMAL, WS_CG, WS_SB = 0, 1, 2, 3
 SB_WARM, SB_RESUME = 1, 2
 
@@ -125,19 +125,30 @@ class OpInfo:
 
 
 class RadonOp:
-    """MR and (MR)^T for one geometry, built on the GPU (see build_radon_csr)."""
+    """MR and (MR)^T for one geometry, built on the GPU (see build_radon_csr).
 
-    def __init__(self, n: int, n_angles: int, n_bins: int, measured=None, dtype=None, device=None):
+    dtype is the type the matrix values are stored in, vec_dtype the type of
+    every vector the calls take and return (default: dtype).  float32 values
+    with float64 vectors selects the mixed operator: FP32 matrix stream, FP64
+    vectors and multiply-adds."""
+
+    def __init__(self, n: int, n_angles: int, n_bins: int, measured=None, dtype=None, device=None,
+                 vec_dtype=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise SparsectError("no GPU visible: libsparsect runs on AMD Instinct GPUs only")
         dtype = torch.float32 if dtype is None else dtype
-        if dtype not in (torch.float32, torch.float64):
-            raise SparsectError("dtype must be torch.float32 or torch.float64")
+        vec_dtype = dtype if vec_dtype is None else vec_dtype
+        kinds = {(torch.float32, torch.float32): F32, (torch.float64, torch.float64): F64,
+                 (torch.float32, torch.float64): F32_F64}
+        if (dtype, vec_dtype) not in kinds:
+            raise SparsectError("(dtype, vec_dtype) must be (f32, f32), (f64, f64) or (f32, f64)")
+        self.kind = kinds[(dtype, vec_dtype)]
         self.device = torch.device("cuda" if device is None else device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        self.dtype = dtype
+        self.mat_dtype = dtype
+        self.dtype = vec_dtype
         self.n, self.n_angles, self.n_bins = int(n), int(n_angles), int(n_bins)
         if measured is None:
             self.measured = np.ones(self.n_angles, dtype=np.uint8)
@@ -146,7 +157,7 @@ class RadonOp:
             if self.measured.shape != (self.n_angles,):
                 raise SparsectError("measured must have one flag per angle")
         self.n_meas = int(np.count_nonzero(self.measured))
-        g = _Geom(self.n, self.n_angles, self.n_bins, F32 if dtype == torch.float32 else F64,
+        g = _Geom(self.n, self.n_angles, self.n_bins, self.kind,
                   self.measured.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
         h = _vp()
         with torch.cuda.device(self.device):

@@ -39,30 +39,30 @@ __global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ x, T *_
 // the wave walks the bundle's major lines four at a time, so every load of
 // the value/index streams is 64 consecutive slots and every gather hits four
 // image lines near the same place.
-template <class T, int WPB>
+template <class TM, class TV, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_fwd(const FwdBundle *__restrict__ fb, int64_t n_fb,
                                                   const uint16_t *__restrict__ idx,
-                                                  const T *__restrict__ v0, const T *__restrict__ v1,
-                                                  const T *__restrict__ x, const T *__restrict__ xT,
-                                                  T *__restrict__ y, int n, int64_t nn, int64_t rows)
+                                                  const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                  const TV *__restrict__ x, const TV *__restrict__ xT,
+                                                  TV *__restrict__ y, int n, int64_t nn, int64_t rows)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t B = int64_t(blockIdx.x) * WPB + wave;
     if (B >= n_fb) return;
     const int64_t bat = blockIdx.y;
     const FwdBundle d = fb[B];
-    const T *__restrict__ img = (d.horiz ? xT : x) + bat * nn;
+    const TV *__restrict__ img = (d.horiz ? xT : x) + bat * nn;
     const int r = lane & 15, q = lane >> 4;
-    T acc = T(0);
+    TV acc = TV(0);
     int64_t s = d.off + int64_t(q) * kFwdLanes + r;
 #pragma unroll 4
     for (int t = q; t < d.nrows; t += 4, s += 4 * kFwdLanes) {
         const int m = min(d.m0 + t, n - 1);
         const int i0 = idx[s];
         const int i1 = i0 + 1 < n ? i0 + 1 : i0;
-        const T *__restrict__ line = img + int64_t(m) * n;
-        acc = fma(v0[s], line[i0], acc);
-        acc = fma(v1[s], line[i1], acc);
+        const TV *__restrict__ line = img + int64_t(m) * n;
+        acc = fma(TV(v0[s]), line[i0], acc);
+        acc = fma(TV(v1[s]), line[i1], acc);
     }
     acc += __shfl_xor(acc, 16);
     acc += __shfl_xor(acc, 32);
@@ -92,9 +92,9 @@ __device__ inline double wave_sum(double v)
 // measured angles for the 64 pixels (one sequential sum per pixel and wave),
 // the shares are added in wave order, and wave 0 applies the epilogue
 // out = alpha*acc + lambda*(K^T K x) + sigma*x and the FP64 partial <x, out>.
-template <class T, int W>
+template <class TM, class T, int W>
 __global__ __launch_bounds__(64 * W) void k_adj(const uint16_t *__restrict__ bin,
-                                                const T *__restrict__ v0, const T *__restrict__ v1,
+                                                const TM *__restrict__ v0, const TM *__restrict__ v1,
                                                 int64_t n_ag, int n_meas, int nb,
                                                 const T *__restrict__ y, const T *__restrict__ x,
                                                 T *__restrict__ out, T alpha, T lambda, T sigma,
@@ -113,8 +113,8 @@ __global__ __launch_bounds__(64 * W) void k_adj(const uint16_t *__restrict__ bin
         const int b0 = bin[s];
         const int b1 = b0 + 1 < nb ? b0 + 1 : b0;
         const T *__restrict__ yr = yb + int64_t(a) * nb;
-        acc = fma(v0[s], yr[b0], acc);
-        acc = fma(v1[s], yr[b1], acc);
+        acc = fma(T(v0[s]), yr[b0], acc);
+        acc = fma(T(v1[s]), yr[b1], acc);
     }
     if constexpr (W > 1) {
         __shared__ T red[W][64];
@@ -171,46 +171,46 @@ static int check_grid_y(int batch)
     return RADON_OK;
 }
 
-template <class T>
-int launch_transpose(const Op &op, const T *x, T *xT, int batch, hipStream_t s)
+template <class TV>
+int launch_transpose(const Op &op, const TV *x, TV *xT, int batch, hipStream_t s)
 {
     SCT_TRY(check_grid_y(batch));
     const unsigned t = unsigned((op.n + 31) / 32);
-    k_transpose<T><<<dim3(t, t, unsigned(batch)), dim3(32, 8), 0, s>>>(x, xT, op.n, op.nn);
+    k_transpose<TV><<<dim3(t, t, unsigned(batch)), dim3(32, 8), 0, s>>>(x, xT, op.n, op.nn);
     return check_launch("k_transpose");
 }
 
-template <class T>
-int launch_fwd(const Op &op, const T *x, const T *xT, T *y, int batch, hipStream_t s)
+template <class TM, class TV>
+int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
 {
     SCT_TRY(check_grid_y(batch));
     constexpr int WPB = 4;
     const int64_t blocks = (op.n_fb + WPB - 1) / WPB;
-    k_fwd<T, WPB><<<dim3(unsigned(blocks), unsigned(batch)), 64 * WPB, 0, s>>>(
-        op.fb, op.n_fb, op.f_idx, static_cast<const T *>(op.f_v0), static_cast<const T *>(op.f_v1),
-        x, xT ? xT : x, y, op.n, op.nn, op.rows);
+    k_fwd<TM, TV, WPB><<<dim3(unsigned(blocks), unsigned(batch)), 64 * WPB, 0, s>>>(
+        op.fb, op.n_fb, op.f_idx, static_cast<const TM *>(op.f_v0),
+        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, y, op.n, op.nn, op.rows);
     return check_launch("k_fwd");
 }
 
-template <class T>
-int launch_adj(const Op &op, const T *y, const T *x, T *out, double alpha, double lambda,
+template <class TM, class TV>
+int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, double lambda,
                double sigma, double *part, int batch, hipStream_t s)
 {
     SCT_TRY(check_grid_y(batch));
     if (op.n_ag > int64_t(INT_MAX)) return set_error(RADON_EOVERFLOW, "too many pixel groups");
     const dim3 grid(unsigned(op.n_ag), unsigned(batch));
     const auto *bin = op.a_bin;
-    const T *a0 = static_cast<const T *>(op.a_v0), *a1 = static_cast<const T *>(op.a_v1);
-    const T al = T(alpha), la = T(lambda), si = T(sigma);
+    const TM *a0 = static_cast<const TM *>(op.a_v0), *a1 = static_cast<const TM *>(op.a_v1);
+    const TV al = TV(alpha), la = TV(lambda), si = TV(sigma);
     if (op.n_meas >= 128)
-        k_adj<T, 4><<<grid, 256, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out, al, la,
-                                         si, part, op.n, op.nn, op.rows);
+        k_adj<TM, TV, 4><<<grid, 256, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out,
+                                              al, la, si, part, op.n, op.nn, op.rows);
     else if (op.n_meas >= 48)
-        k_adj<T, 2><<<grid, 128, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out, al, la,
-                                         si, part, op.n, op.nn, op.rows);
+        k_adj<TM, TV, 2><<<grid, 128, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out,
+                                              al, la, si, part, op.n, op.nn, op.rows);
     else
-        k_adj<T, 1><<<grid, 64, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out, al, la,
-                                        si, part, op.n, op.nn, op.rows);
+        k_adj<TM, TV, 1><<<grid, 64, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out,
+                                             al, la, si, part, op.n, op.nn, op.rows);
     return check_launch("k_adj");
 }
 
@@ -222,12 +222,14 @@ int launch_sum_partials(const double *part, int64_t count, double *dst, int batc
 
 template int launch_transpose<float>(const Op &, const float *, float *, int, hipStream_t);
 template int launch_transpose<double>(const Op &, const double *, double *, int, hipStream_t);
-template int launch_fwd<float>(const Op &, const float *, const float *, float *, int, hipStream_t);
-template int launch_fwd<double>(const Op &, const double *, const double *, double *, int, hipStream_t);
-template int launch_adj<float>(const Op &, const float *, const float *, float *, double, double,
-                               double, double *, int, hipStream_t);
-template int launch_adj<double>(const Op &, const double *, const double *, double *, double, double,
-                                double, double *, int, hipStream_t);
+#define SCT_INST(TM, TV)                                                                          \
+    template int launch_fwd<TM, TV>(const Op &, const TV *, const TV *, TV *, int, hipStream_t);  \
+    template int launch_adj<TM, TV>(const Op &, const TV *, const TV *, TV *, double, double,     \
+                                    double, double *, int, hipStream_t);
+SCT_INST(float, float)
+SCT_INST(double, double)
+SCT_INST(float, double)
+#undef SCT_INST
 
 // ---------------------------------------------------------------------------
 // workspace sizes
@@ -236,15 +238,15 @@ template int launch_adj<double>(const Op &, const double *, const double *, doub
 static int64_t fwd_ws_bytes(const Op &op, int batch)
 {
     Carver c(nullptr);
-    if (op.need_T) c.take<char>(int64_t(op.esize) * op.nn * batch);
+    if (op.need_T) c.take<char>(int64_t(op.vsize) * op.nn * batch);
     return c.used;
 }
 
 static int64_t normal_ws_bytes(const Op &op, int batch)
 {
     Carver c(nullptr);
-    if (op.need_T) c.take<char>(int64_t(op.esize) * op.nn * batch);
-    c.take<char>(int64_t(op.esize) * op.rows * batch);
+    if (op.need_T) c.take<char>(int64_t(op.vsize) * op.nn * batch);
+    c.take<char>(int64_t(op.vsize) * op.rows * batch);
     c.take<double>(op.n_ag * batch);
     return c.used;
 }
@@ -271,18 +273,6 @@ extern "C" int64_t radon_workspace_bytes(const radon_op *p, int32_t which, int32
     }
 }
 
-template <class T>
-static int fwd_typed(const Op &op, const void *x, void *y, int batch, void *ws, hipStream_t s)
-{
-    Carver c(ws);
-    T *xT = nullptr;
-    if (op.need_T) {
-        xT = c.take<T>(op.nn * batch);
-        SCT_TRY(launch_transpose<T>(op, static_cast<const T *>(x), xT, batch, s));
-    }
-    return launch_fwd<T>(op, static_cast<const T *>(x), xT, static_cast<T *>(y), batch, s);
-}
-
 extern "C" int radon_fwd(const radon_op *p, const void *x, void *y, int32_t batch, void *ws,
                          int64_t ws_bytes, void *stream)
 {
@@ -293,8 +283,17 @@ extern "C" int radon_fwd(const radon_op *p, const void *x, void *y, int32_t batc
     const Op &op = *as_op(p);
     SCT_TRY(check_ws(ws, ws_bytes, fwd_ws_bytes(op, batch), "radon_fwd"));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return op.dtype == SPARSECT_F32 ? fwd_typed<float>(op, x, y, batch, ws, s)
-                                    : fwd_typed<double>(op, x, y, batch, ws, s);
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        Carver c(ws);
+        const TV *xx = static_cast<const TV *>(x);
+        TV *xT = nullptr;
+        if (op.need_T) {
+            xT = c.take<TV>(op.nn * batch);
+            SCT_TRY(launch_transpose<TV>(op, xx, xT, batch, s));
+        }
+        return launch_fwd<TM, TV>(op, xx, xT, static_cast<TV *>(y), batch, s);
+    });
 }
 
 extern "C" int radon_adj(const radon_op *p, const void *y, void *x, int32_t batch, void *stream)
@@ -305,28 +304,11 @@ extern "C" int radon_adj(const radon_op *p, const void *y, void *x, int32_t batc
     if (!x || !y) return set_error(RADON_EINVAL, "x and y must be non-NULL");
     const Op &op = *as_op(p);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (op.dtype == SPARSECT_F32)
-        return launch_adj<float>(op, static_cast<const float *>(y), nullptr, static_cast<float *>(x),
-                                 1.0, 0.0, 0.0, nullptr, batch, s);
-    return launch_adj<double>(op, static_cast<const double *>(y), nullptr, static_cast<double *>(x),
-                              1.0, 0.0, 0.0, nullptr, batch, s);
-}
-
-template <class T>
-static int normal_typed(const Op &op, double alpha, double lambda, double sigma, const void *x,
-                        void *out, double *dot_out, int batch, void *ws, hipStream_t s)
-{
-    Carver c(ws);
-    T *xT = op.need_T ? c.take<T>(op.nn * batch) : nullptr;
-    T *y = c.take<T>(op.rows * batch);
-    double *part = c.take<double>(op.n_ag * batch);
-    const T *xx = static_cast<const T *>(x);
-    if (xT) SCT_TRY(launch_transpose<T>(op, xx, xT, batch, s));
-    SCT_TRY(launch_fwd<T>(op, xx, xT, y, batch, s));
-    SCT_TRY(launch_adj<T>(op, y, xx, static_cast<T *>(out), alpha, lambda, sigma,
-                          dot_out ? part : nullptr, batch, s));
-    if (dot_out) SCT_TRY(launch_sum_partials(part, op.n_ag, dot_out, batch, s));
-    return RADON_OK;
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return launch_adj<TM, TV>(op, static_cast<const TV *>(y), nullptr, static_cast<TV *>(x), 1.0,
+                                  0.0, 0.0, nullptr, batch, s);
+    });
 }
 
 extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, double sigma,
@@ -341,7 +323,18 @@ extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, doub
     const Op &op = *as_op(p);
     SCT_TRY(check_ws(ws, ws_bytes, normal_ws_bytes(op, batch), "normal_apply"));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return op.dtype == SPARSECT_F32
-               ? normal_typed<float>(op, alpha, lambda, sigma, x, out, dot_out, batch, ws, s)
-               : normal_typed<double>(op, alpha, lambda, sigma, x, out, dot_out, batch, ws, s);
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        Carver c(ws);
+        TV *xT = op.need_T ? c.take<TV>(op.nn * batch) : nullptr;
+        TV *y = c.take<TV>(op.rows * batch);
+        double *part = c.take<double>(op.n_ag * batch);
+        const TV *xx = static_cast<const TV *>(x);
+        if (xT) SCT_TRY(launch_transpose<TV>(op, xx, xT, batch, s));
+        SCT_TRY(launch_fwd<TM, TV>(op, xx, xT, y, batch, s));
+        SCT_TRY(launch_adj<TM, TV>(op, y, xx, static_cast<TV *>(out), alpha, lambda, sigma,
+                                   dot_out ? part : nullptr, batch, s));
+        if (dot_out) SCT_TRY(launch_sum_partials(part, op.n_ag, dot_out, batch, s));
+        return RADON_OK;
+    });
 }

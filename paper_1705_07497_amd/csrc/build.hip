@@ -523,8 +523,9 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     if (g->n_angles < 1) return set_error(RADON_EINVAL, "n_angles must be >= 1 (got %d)", g->n_angles);
     if (g->n_bins < 1 || g->n_bins > 65535)
         return set_error(RADON_EINVAL, "n_bins must be in [1, 65535] (got %d)", g->n_bins);
-    if (g->dtype != SPARSECT_F32 && g->dtype != SPARSECT_F64)
-        return set_error(RADON_EINVAL, "dtype must be SPARSECT_F32 or SPARSECT_F64 (got %d)", g->dtype);
+    if (g->dtype != SPARSECT_F32 && g->dtype != SPARSECT_F64 && g->dtype != SPARSECT_F32_F64)
+        return set_error(RADON_EINVAL, "dtype must be SPARSECT_F32, SPARSECT_F64 or SPARSECT_F32_F64 (got %d)",
+                         g->dtype);
     std::vector<int32_t> meas;
     for (int k = 0; k < g->n_angles; ++k)
         if (!g->measured || g->measured[k]) meas.push_back(k);
@@ -545,7 +546,8 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     op->n_meas = int32_t(meas.size());
     op->nn = nn;
     op->rows = rows;
-    op->esize = g->dtype == SPARSECT_F32 ? 4 : 8;
+    op->msize = g->dtype == SPARSECT_F64 ? 8 : 4;
+    op->vsize = g->dtype == SPARSECT_F32 ? 4 : 8;
 
     std::vector<double> cs(2 * meas.size());
     for (size_t a = 0; a < meas.size(); ++a) {
@@ -555,7 +557,7 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     hipStream_t st = static_cast<hipStream_t>(stream);
     int rc;
     try {
-        rc = g->dtype == SPARSECT_F32 ? build_typed<float>(*op, cs, st) : build_typed<double>(*op, cs, st);
+        rc = op->msize == 4 ? build_typed<float>(*op, cs, st) : build_typed<double>(*op, cs, st);
     } catch (...) {
         rc = set_error(RADON_EINVAL, "unexpected host exception during build");
     }
@@ -609,8 +611,8 @@ extern "C" int radon_export_csr(const radon_op *p, int64_t *row_ptr, int32_t *co
     SCT_TRY(check_op(p));
     const Op &op = *as_op(p);
     try {
-        return op.dtype == SPARSECT_F32 ? export_csr_typed<float>(op, row_ptr, col, val)
-                                        : export_csr_typed<double>(op, row_ptr, col, val);
+        return op.msize == 4 ? export_csr_typed<float>(op, row_ptr, col, val)
+                             : export_csr_typed<double>(op, row_ptr, col, val);
     } catch (...) {
         return set_error(RADON_EINVAL, "out of host memory");
     }
@@ -643,8 +645,8 @@ extern "C" int radon_export_adj(const radon_op *p, int32_t *bin, double *v0, dou
     SCT_TRY(check_op(p));
     const Op &op = *as_op(p);
     try {
-        return op.dtype == SPARSECT_F32 ? export_adj_typed<float>(op, bin, v0, v1)
-                                        : export_adj_typed<double>(op, bin, v0, v1);
+        return op.msize == 4 ? export_adj_typed<float>(op, bin, v0, v1)
+                             : export_adj_typed<double>(op, bin, v0, v1);
     } catch (...) {
         return set_error(RADON_EINVAL, "out of host memory");
     }

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/sparsect.h"
@@ -40,7 +41,8 @@ struct Op {
     int64_t nnz = 0;
     bool need_T = false;             // some measured angle uses the transposed image
     std::vector<int32_t> meas;       // measured angle indices (host)
-    int32_t esize = 4;               // bytes per value
+    int32_t msize = 4;               // bytes per stored matrix value
+    int32_t vsize = 4;               // bytes per vector element
 
     // CSR of MR (device)
     int64_t *rp = nullptr;
@@ -74,9 +76,9 @@ void clear_error();
                                     hipGetErrorString(e_));                           \
     } while (0)
 
-#define SCT_TRY(expr)                                                                 \
+#define SCT_TRY(...)                                                                  \
     do {                                                                              \
-        int s_ = (expr);                                                              \
+        int s_ = (__VA_ARGS__);                                                       \
         if (s_ != RADON_OK) return s_;                                                \
     } while (0)
 
@@ -109,23 +111,36 @@ struct Carver {
     }
 };
 
+// Calls f(TM*, TV*) with null pointers whose types name the operator's matrix
+// value type TM and vector type TV.
+template <class F>
+int dispatch(const Op &op, F &&f)
+{
+    switch (op.dtype) {
+    case SPARSECT_F32: return f(static_cast<float *>(nullptr), static_cast<float *>(nullptr));
+    case SPARSECT_F64: return f(static_cast<double *>(nullptr), static_cast<double *>(nullptr));
+    default: return f(static_cast<float *>(nullptr), static_cast<double *>(nullptr));
+    }
+}
+#define SCT_TYPES(tm, tv)                                 \
+    using TM = std::remove_pointer_t<decltype(tm)>;       \
+    using TV = std::remove_pointer_t<decltype(tv)>
+
 // --- apply-level launchers (apply.hip) ----------------------------------------
 // Transposed copy of `batch` n x n images.
-template <class T>
-int launch_transpose(const Op &op, const T *x, T *xT, int batch, hipStream_t s);
+template <class TV>
+int launch_transpose(const Op &op, const TV *x, TV *xT, int batch, hipStream_t s);
 // y = MR x, gathering from x and (for horizontal bundles) xT.
-template <class T>
-int launch_fwd(const Op &op, const T *x, const T *xT, T *y, int batch, hipStream_t s);
+template <class TM, class TV>
+int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s);
 // out = alpha (MR)^T y + lambda K^T K x + sigma x; partial <x, out> per group
 // into part[batch][n_ag] when part != nullptr.  x may be nullptr when
 // lambda == sigma == 0 and part == nullptr.
-template <class T>
-int launch_adj(const Op &op, const T *y, const T *x, T *out, double alpha, double lambda,
+template <class TM, class TV>
+int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, double lambda,
                double sigma, double *part, int batch, hipStream_t s);
 // sum part[batch][count] -> dst[batch] (fixed order)
 int launch_sum_partials(const double *part, int64_t count, double *dst, int batch, hipStream_t s);
 
-// Sizes of the apply temporaries.
-int64_t normal_ws_elems(const Op &op, int batch);   // in units of the op dtype + partials
 
 }  // namespace sct

@@ -422,7 +422,7 @@ static void carve_cg(const Op &op, int batch, Carver &c, CgBufs<T> &w)
 int64_t cg_ws_bytes(const Op &op, int batch)
 {
     Carver c(nullptr);
-    if (op.dtype == SPARSECT_F32) {
+    if (op.vsize == 4) {
         CgBufs<float> w;
         carve_cg(op, batch, c, w);
     } else {
@@ -460,7 +460,7 @@ static void carve_sb(const Op &op, int batch, Carver &c, SbBufs<T> &w)
 int64_t sb_ws_bytes(const Op &op, int batch)
 {
     Carver c(nullptr);
-    if (op.dtype == SPARSECT_F32) {
+    if (op.vsize == 4) {
         SbBufs<float> w;
         carve_sb(op, batch, c, w);
     } else {
@@ -471,7 +471,7 @@ int64_t sb_ws_bytes(const Op &op, int batch)
 }
 
 // One CG solve on A(alpha, lambda, sigma) from x with the residual already in w.r.
-template <class T>
+template <class TM, class T>
 static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x, int batch,
                   int n_iter, double rtol, CgBufs<T> &w, T *u_for_prev, T *uprev,
                   const SbScal *sbs, hipStream_t s)
@@ -485,8 +485,8 @@ static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x,
     SCT_TRY(check_launch("k_cg_begin"));
     const int vb = vec_blocks(op.nn);
     for (int it = 0; it < n_iter; ++it) {
-        SCT_TRY(launch_fwd<T>(op, w.p, w.pT, w.y, batch, s));
-        SCT_TRY(launch_adj<T>(op, w.y, w.p, w.q, alpha, lambda, sigma, w.part_adj, batch, s));
+        SCT_TRY((launch_fwd<TM, T>(op, w.p, w.pT, w.y, batch, s)));
+        SCT_TRY((launch_adj<TM, T>(op, w.y, w.p, w.q, alpha, lambda, sigma, w.part_adj, batch, s)));
         k_cg_alpha<<<unsigned(batch), 256, 0, s>>>(w.part_adj, op.n_ag, w.sc, rtol, it);
         SCT_TRY(check_launch("k_cg_alpha"));
         k_cg_xr<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(x, w.r, w.p, w.q, w.sc,
@@ -501,16 +501,16 @@ static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x,
 }
 
 // w.q = A x (uses w.pT and w.y as temporaries)
-template <class T>
+template <class TM, class T>
 static int apply_A_into_q(const Op &op, double alpha, double lambda, double sigma, const T *x,
                           int batch, CgBufs<T> &w, hipStream_t s)
 {
     if (w.pT) SCT_TRY(launch_transpose<T>(op, x, w.pT, batch, s));
-    SCT_TRY(launch_fwd<T>(op, x, w.pT, w.y, batch, s));
-    return launch_adj<T>(op, w.y, x, w.q, alpha, lambda, sigma, nullptr, batch, s);
+    SCT_TRY((launch_fwd<TM, T>(op, x, w.pT, w.y, batch, s)));
+    return launch_adj<TM, T>(op, w.y, x, w.q, alpha, lambda, sigma, nullptr, batch, s);
 }
 
-template <class T>
+template <class TM, class T>
 static int cg_typed(const Op &op, double alpha, double lambda, double sigma, const void *rhs_v,
                     void *x_v, int x0_given, int batch, int n_iter, double rtol, void *ws,
                     radon_cg_info *info, hipStream_t s)
@@ -523,7 +523,7 @@ static int cg_typed(const Op &op, double alpha, double lambda, double sigma, con
     const int64_t cnt = op.nn * batch;
     const int vb = vec_blocks(cnt);
     if (x0_given) {
-        SCT_TRY(apply_A_into_q<T>(op, alpha, lambda, sigma, x, batch, w, s));
+        SCT_TRY((apply_A_into_q<TM, T>(op, alpha, lambda, sigma, x, batch, w, s)));
         k_sub<T><<<vb, kVecThreads, 0, s>>>(rhs, w.q, w.r, cnt);
         SCT_TRY(check_launch("k_sub"));
     } else {
@@ -532,7 +532,8 @@ static int cg_typed(const Op &op, double alpha, double lambda, double sigma, con
         k_copy<T><<<vb, kVecThreads, 0, s>>>(rhs, w.r, cnt);
         SCT_TRY(check_launch("k_copy"));
     }
-    SCT_TRY(cg_run<T>(op, alpha, lambda, sigma, x, batch, n_iter, rtol, w, nullptr, nullptr, nullptr, s));
+    SCT_TRY((cg_run<TM, T>(op, alpha, lambda, sigma, x, batch, n_iter, rtol, w, nullptr, nullptr,
+                           nullptr, s)));
     if (info) {
         k_cg_info<<<unsigned((batch + 63) / 64), 64, 0, s>>>(w.sc, info, batch);
         SCT_TRY(check_launch("k_cg_info"));
@@ -540,7 +541,7 @@ static int cg_typed(const Op &op, double alpha, double lambda, double sigma, con
     return RADON_OK;
 }
 
-template <class T>
+template <class TM, class T>
 static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, void *mu_v, int batch,
                     void *ws, radon_sb_info *info, hipStream_t s)
 {
@@ -559,9 +560,9 @@ static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, voi
             SCT_TRY(check_launch("k_fill"));
         }
         // r = alpha (MR)^T f - A u
-        SCT_TRY(launch_adj<T>(op, f, nullptr, w.cg.r, alpha, 0.0, 0.0, nullptr, batch, s));
+        SCT_TRY((launch_adj<TM, T>(op, f, nullptr, w.cg.r, alpha, 0.0, 0.0, nullptr, batch, s)));
         if (P.flags & RADON_SB_WARM) {
-            SCT_TRY(apply_A_into_q<T>(op, alpha, lambda, 0.0, u, batch, w.cg, s));
+            SCT_TRY((apply_A_into_q<TM, T>(op, alpha, lambda, 0.0, u, batch, w.cg, s)));
             k_sub<T><<<vbc, kVecThreads, 0, s>>>(w.cg.r, w.cg.q, w.cg.r, cnt);
             SCT_TRY(check_launch("k_sub"));
         } else {
@@ -573,7 +574,8 @@ static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, voi
     SCT_TRY(check_launch("k_sb_reset"));
     const T thresh = T(1.0 / lambda);
     for (int k = 0; k < P.n_outer; ++k) {
-        SCT_TRY(cg_run<T>(op, alpha, lambda, 0.0, u, batch, P.n_cg, 0.0, w.cg, u, w.uprev, w.sbs, s));
+        SCT_TRY((cg_run<TM, T>(op, alpha, lambda, 0.0, u, batch, P.n_cg, 0.0, w.cg, u, w.uprev, w.sbs,
+                               s)));
         k_sb_shrink<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
             u, w.uprev, w.dx, w.dy, w.bx, w.by, w.dwx, w.dwy, thresh, w.sbs, w.part, op.n, op.nn);
         SCT_TRY(check_launch("k_sb_shrink"));
@@ -609,11 +611,11 @@ extern "C" int cg_solve(const radon_op *p, double alpha, double lambda, double s
     SCT_TRY(check_ws(ws, ws_bytes, cg_ws_bytes(op, batch), "cg_solve"));
     if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return op.dtype == SPARSECT_F32
-               ? cg_typed<float>(op, alpha, lambda, sigma, rhs, x, x0_given, batch, n_iter, rtol, ws,
-                                 info, s)
-               : cg_typed<double>(op, alpha, lambda, sigma, rhs, x, x0_given, batch, n_iter, rtol, ws,
-                                  info, s);
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return cg_typed<TM, TV>(op, alpha, lambda, sigma, rhs, x, x0_given, batch, n_iter, rtol, ws,
+                                info, s);
+    });
 }
 
 extern "C" int split_bregman_tv(const radon_op *p, const radon_sb_params *params, const void *f,
@@ -635,6 +637,8 @@ extern "C" int split_bregman_tv(const radon_op *p, const radon_sb_params *params
     SCT_TRY(check_ws(ws, ws_bytes, sb_ws_bytes(op, batch), "split_bregman_tv"));
     if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return op.dtype == SPARSECT_F32 ? sb_typed<float>(op, *params, f, mu, batch, ws, info, s)
-                                    : sb_typed<double>(op, *params, f, mu, batch, ws, info, s);
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return sb_typed<TM, TV>(op, *params, f, mu, batch, ws, info, s);
+    });
 }

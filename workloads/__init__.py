@@ -125,12 +125,20 @@ class Workload:
         return int(self.mask.sum())
 
 
-# Shapes of the five workloads the library is measured and tested on.
+# Shapes of the five workloads the library is measured and tested on.  Only the
+# 64x64 case fixes the split-Bregman weights (alpha = 10, lambda = 1).  For the
+# larger images the data are line integrals over hundreds of unit pixels, so
+# alpha = 10 makes the data term outweigh the TV term by orders of magnitude:
+# the iterates then fit the noise (error to the phantom grows from 0.33 to 0.92
+# over 20 Bregman steps on the 512x512 case) and the trajectory amplifies a
+# 1e-13 data perturbation by ~1e11.  alpha = 0.01, lambda = 1 balances the two
+# terms at this data scale (error to the phantom 0.045 after 50 x 20) and keeps
+# the solve well posed.
 WORKLOADS = {
     "small_64_f64": Workload("small_64_f64", 64, 45, 91, 1, 5, 0.01, 10.0, 1.0, 20, 10, "f64"),
-    "gpu_512_f32": Workload("gpu_512_f32", 512, 360, 725, 2, 10, 0.02, 10.0, 1.0, 50, 20, "f32"),
-    "large_2048_f32": Workload("large_2048_f32", 2048, 90, 2897, 1, 30, 0.01, 10.0, 1.0, 30, 10, "f32"),
-    "volume_64x1024_f32": Workload("volume_64x1024_f32", 1024, 360, 1449, 1, 10, 0.01, 10.0, 1.0,
+    "gpu_512_f32": Workload("gpu_512_f32", 512, 360, 725, 2, 10, 0.02, 0.01, 1.0, 50, 20, "f32"),
+    "large_2048_f32": Workload("large_2048_f32", 2048, 90, 2897, 1, 30, 0.01, 0.01, 1.0, 30, 10, "f32"),
+    "volume_64x1024_f32": Workload("volume_64x1024_f32", 1024, 360, 1449, 1, 10, 0.01, 0.01, 1.0,
                                    20, 10, "f32", batch=64),
     "grad_16x512_f32": Workload("grad_16x512_f32", 512, 120, 725, 1, 10, 0.01, 10.0, 0.0, 0, 10,
                                 "f32", batch=16, extra={"tau": 0.1, "ckpt": 5}),
