@@ -35,37 +35,79 @@ __global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ x, T *_
     }
 }
 
-// One wave per ray bundle: lane = (line offset q in 0..3, ray r in 0..15);
-// the wave walks the bundle's major lines four at a time, so every load of
-// the value/index streams is 64 consecutive slots and every gather hits four
-// image lines near the same place.
-template <class TM, class TV, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_fwd(const FwdBundle *__restrict__ fb, int64_t n_fb,
-                                                  const uint16_t *__restrict__ idx,
-                                                  const TM *__restrict__ v0, const TM *__restrict__ v1,
-                                                  const TV *__restrict__ x, const TV *__restrict__ xT,
-                                                  TV *__restrict__ y, int n, int64_t nn, int64_t rows)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+template <class T> struct Quad;
+template <> struct Quad<float> { using type = f32x4; };
+template <> struct Quad<double> { using type = f64x4; };
+
+// The matrix streams are read exactly once per product: non-temporal loads
+// keep them from evicting the gathered vector from the caches.
+template <class V>
+__device__ inline V stream_load(const V *p)
 {
+    return __builtin_nontemporal_load(p);
+}
+
+// One workgroup of W waves per ray bundle (block -> bundle through `order`,
+// which places bundles of rays closer to vertical and closer to horizontal on
+// different XCDs, so each XCD's L2 caches only x or only its transpose).
+// Lane = (quad offset q in 0..3, ray r in 0..15): a lane reads a quad (4
+// consecutive major lines of its ray) with 16-byte loads, the 64 lanes of a
+// wave read 64 consecutive quads, and the 16 lanes of one q gather from the
+// same image line at neighbouring positions.  Wave w covers its share of the
+// bundle's quads; partial sums are combined over q with shuffles and over the
+// waves in LDS, in a fixed order.
+template <class TM, class TV, int W>
+__global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb,
+                                                const int32_t *__restrict__ order,
+                                                const uint16_t *__restrict__ idx,
+                                                const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                const TV *__restrict__ x, const TV *__restrict__ xT,
+                                                TV *__restrict__ y, int n, int64_t nn, int64_t rows)
+{
+    using Q = typename Quad<TM>::type;
+    const int B = order[blockIdx.x];
+    if (B < 0) return;                 // padding block (uniform)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t B = int64_t(blockIdx.x) * WPB + wave;
-    if (B >= n_fb) return;
     const int64_t bat = blockIdx.y;
     const FwdBundle d = fb[B];
     const TV *__restrict__ img = (d.horiz ? xT : x) + bat * nn;
     const int r = lane & 15, q = lane >> 4;
+    const int nq = d.nrows >> 2;
+    const int s0 = (nq * wave) / W, s1 = (nq * (wave + 1)) / W;
+    const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
+    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
+    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
     TV acc = TV(0);
-    int64_t s = d.off + int64_t(q) * kFwdLanes + r;
-#pragma unroll 4
-    for (int t = q; t < d.nrows; t += 4, s += 4 * kFwdLanes) {
-        const int m = min(d.m0 + t, n - 1);
-        const int i0 = idx[s];
-        const int i1 = i0 + 1 < n ? i0 + 1 : i0;
-        const TV *__restrict__ line = img + int64_t(m) * n;
-        acc = fma(TV(v0[s]), line[i0], acc);
-        acc = fma(TV(v1[s]), line[i1], acc);
+#pragma unroll 2
+    for (int tq = s0 + q; tq < s1; tq += 4) {
+        const int e = tq * kFwdLanes + r;
+        const u16x4 i4 = stream_load(I + e);
+        const Q a4 = stream_load(A + e);
+        const Q b4 = stream_load(Bv + e);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int m = min(d.m0 + 4 * tq + k, n - 1);
+            const TV *__restrict__ line = img + int64_t(m) * n;
+            const int i0 = i4[k];
+            const int i1 = i0 + 1 < n ? i0 + 1 : i0;
+            acc = fma(TV(a4[k]), line[i0], acc);
+            acc = fma(TV(b4[k]), line[i1], acc);
+        }
     }
     acc += __shfl_xor(acc, 16);
     acc += __shfl_xor(acc, 32);
+    if constexpr (W > 1) {
+        __shared__ TV red[W][kFwdLanes];
+        if (q == 0) red[wave][r] = acc;
+        __syncthreads();
+        if (wave != 0) return;
+        acc = red[0][r];
+#pragma unroll
+        for (int w = 1; w < W; ++w) acc += red[w][r];
+    }
     if (q == 0 && r < d.nrays) y[bat * rows + d.ray0 + r] = acc;
 }
 
@@ -89,32 +131,44 @@ __device__ inline double wave_sum(double v)
 }
 
 // One workgroup of W waves per 64-pixel group: wave w sums its share of the
-// measured angles for the 64 pixels (one sequential sum per pixel and wave),
-// the shares are added in wave order, and wave 0 applies the epilogue
+// measured-angle quads for the 64 pixels (one sequential sum per pixel and
+// wave, 16-byte loads of 4 angles per lane), the shares are added in wave
+// order, and wave 0 applies the epilogue
 // out = alpha*acc + lambda*(K^T K x) + sigma*x and the FP64 partial <x, out>.
 template <class TM, class T, int W>
 __global__ __launch_bounds__(64 * W) void k_adj(const uint16_t *__restrict__ bin,
                                                 const TM *__restrict__ v0, const TM *__restrict__ v1,
-                                                int64_t n_ag, int n_meas, int nb,
+                                                int64_t n_ag, int n_meas, int n_aq, int nb,
                                                 const T *__restrict__ y, const T *__restrict__ x,
                                                 T *__restrict__ out, T alpha, T lambda, T sigma,
                                                 double *__restrict__ part, int n, int64_t nn,
                                                 int64_t rows)
 {
+    using Q = typename Quad<TM>::type;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t g = blockIdx.x;
     const int64_t bat = blockIdx.y;
     const T *__restrict__ yb = y + bat * rows;
-    const int a0 = (n_meas * wave) / W, a1 = (n_meas * (wave + 1)) / W;
+    const int q0 = (n_aq * wave) / W, q1 = (n_aq * (wave + 1)) / W;
+    const u16x4 *__restrict__ Bn = reinterpret_cast<const u16x4 *>(bin);
+    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0);
+    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1);
     T acc = T(0);
-    int64_t s = (g * n_meas + a0) * kAdjLanes + lane;
-#pragma unroll 4
-    for (int a = a0; a < a1; ++a, s += kAdjLanes) {
-        const int b0 = bin[s];
-        const int b1 = b0 + 1 < nb ? b0 + 1 : b0;
-        const T *__restrict__ yr = yb + int64_t(a) * nb;
-        acc = fma(T(v0[s]), yr[b0], acc);
-        acc = fma(T(v1[s]), yr[b1], acc);
+#pragma unroll 2
+    for (int aq = q0; aq < q1; ++aq) {
+        const int64_t e = (g * n_aq + aq) * kAdjLanes + lane;
+        const u16x4 b4 = stream_load(Bn + e);
+        const Q a4 = stream_load(A + e);
+        const Q c4 = stream_load(Bv + e);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int a = min(4 * aq + k, n_meas - 1);   // zero slots past the last angle
+            const T *__restrict__ yr = yb + int64_t(a) * nb;
+            const int b0 = b4[k];
+            const int b1 = b0 + 1 < nb ? b0 + 1 : b0;
+            acc = fma(T(a4[k]), yr[b0], acc);
+            acc = fma(T(c4[k]), yr[b1], acc);
+        }
     }
     if constexpr (W > 1) {
         __shared__ T red[W][64];
@@ -184,10 +238,9 @@ template <class TM, class TV>
 int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
 {
     SCT_TRY(check_grid_y(batch));
-    constexpr int WPB = 4;
-    const int64_t blocks = (op.n_fb + WPB - 1) / WPB;
-    k_fwd<TM, TV, WPB><<<dim3(unsigned(blocks), unsigned(batch)), 64 * WPB, 0, s>>>(
-        op.fb, op.n_fb, op.f_idx, static_cast<const TM *>(op.f_v0),
+    constexpr int W = 4;
+    k_fwd<TM, TV, W><<<dim3(unsigned(op.n_order), unsigned(batch)), 64 * W, 0, s>>>(
+        op.fb, op.fb_order, op.f_idx, static_cast<const TM *>(op.f_v0),
         static_cast<const TM *>(op.f_v1), x, xT ? xT : x, y, op.n, op.nn, op.rows);
     return check_launch("k_fwd");
 }
@@ -203,13 +256,13 @@ int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, do
     const TM *a0 = static_cast<const TM *>(op.a_v0), *a1 = static_cast<const TM *>(op.a_v1);
     const TV al = TV(alpha), la = TV(lambda), si = TV(sigma);
     if (op.n_meas >= 128)
-        k_adj<TM, TV, 4><<<grid, 256, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out,
+        k_adj<TM, TV, 4><<<grid, 256, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y, x, out,
                                               al, la, si, part, op.n, op.nn, op.rows);
     else if (op.n_meas >= 48)
-        k_adj<TM, TV, 2><<<grid, 128, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out,
+        k_adj<TM, TV, 2><<<grid, 128, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y, x, out,
                                               al, la, si, part, op.n, op.nn, op.rows);
     else
-        k_adj<TM, TV, 1><<<grid, 64, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_bins, y, x, out,
+        k_adj<TM, TV, 1><<<grid, 64, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y, x, out,
                                              al, la, si, part, op.n, op.nn, op.rows);
     return check_launch("k_adj");
 }

@@ -262,7 +262,7 @@ __global__ void k_bundle_off(FwdBundle *__restrict__ fb, const int64_t *__restri
 // bin of every (pixel, angle) pair the ray touches.
 template <class T>
 __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nbpa, int64_t rows,
-                           int n_meas, const int64_t *__restrict__ rp, int32_t *__restrict__ col,
+                           int n_aq, const int64_t *__restrict__ rp, int32_t *__restrict__ col,
                            T *__restrict__ val, const FwdBundle *__restrict__ fb,
                            uint16_t *__restrict__ f_idx, T *__restrict__ f_v0,
                            T *__restrict__ f_v1, int32_t *__restrict__ bin_tmp,
@@ -286,7 +286,7 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nb
             atomicOr(bad, 16);
             return;
         }
-        const int64_t slot = d.off + int64_t(cur - d.m0) * kFwdLanes + r;
+        const int64_t slot = fwd_slot(d.off, cur - d.m0, r);
         if (nline == 1) {
             f_idx[slot] = uint16_t(q0);
             f_v0[slot] = w0;
@@ -322,8 +322,7 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nb
             q1 = q;
             w1 = v;
         }
-        const int64_t as = (int64_t(j >> 6) * n_meas + a) * kAdjLanes + (j & 63);
-        atomicMin(&bin_tmp[as], b);
+        atomicMin(&bin_tmp[adj_slot(j, a, n_aq)], b);
     });
     flush();
     if (o != oend) atomicOr(bad, 4);
@@ -331,7 +330,7 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nb
 
 // Pass 3: place each entry in its (pixel, angle) slot as the first or second bin.
 template <class T>
-__global__ void k_adj_fill(int nb, int64_t rows, int n_meas, const int64_t *__restrict__ rp,
+__global__ void k_adj_fill(int nb, int64_t rows, int n_aq, const int64_t *__restrict__ rp,
                            const int32_t *__restrict__ col, const T *__restrict__ val,
                            const int32_t *__restrict__ bin_tmp, T *__restrict__ a_v0,
                            T *__restrict__ a_v1, int32_t *__restrict__ bad)
@@ -341,7 +340,7 @@ __global__ void k_adj_fill(int nb, int64_t rows, int n_meas, const int64_t *__re
     const int a = int(ray / nb), b = int(ray % nb);
     for (int64_t e = rp[ray]; e < rp[ray + 1]; ++e) {
         const int j = col[e];
-        const int64_t as = (int64_t(j >> 6) * n_meas + a) * kAdjLanes + (j & 63);
+        const int64_t as = adj_slot(j, a, n_aq);
         const int first = bin_tmp[as];
         if (b == first) a_v0[as] = val[e];
         else if (b == first + 1) a_v1[as] = val[e];
@@ -473,7 +472,8 @@ static int build_typed(Op &op, const std::vector<double> &cs_host, hipStream_t s
     SCT_HIP(hipMemsetAsync(op.f_v1, 0, size_t(es * fslots), st));
 
     op.n_ag = (op.nn + kAdjLanes - 1) / kAdjLanes;
-    op.a_slots = op.n_ag * kAdjLanes * op.n_meas;
+    op.n_aq = (op.n_meas + 3) / 4;
+    op.a_slots = op.n_ag * kAdjLanes * 4 * op.n_aq;
     SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.a_bin), 2 * op.a_slots));
     SCT_TRY(op_alloc(op, &op.a_v0, es * op.a_slots));
     SCT_TRY(op_alloc(op, &op.a_v1, es * op.a_slots));
@@ -484,18 +484,57 @@ static int build_typed(Op &op, const std::vector<double> &cs_host, hipStream_t s
     SCT_HIP(hipMemsetAsync(bin_tmp, 0x7f, size_t(4 * op.a_slots), st));   // 0x7f7f7f7f > any bin
 
     SCT_TRY(grid_for(rows, blk, &g));
-    k_ray_fill<T><<<g, blk, 0, st>>>(cs, n, nb, nbpa, rows, op.n_meas, op.rp, op.col,
+    k_ray_fill<T><<<g, blk, 0, st>>>(cs, n, nb, nbpa, rows, op.n_aq, op.rp, op.col,
                                      static_cast<T *>(op.val), op.fb, op.f_idx,
                                      static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), bin_tmp,
                                      bad);
     SCT_TRY(check_launch("k_ray_fill"));
-    k_adj_fill<T><<<g, blk, 0, st>>>(nb, rows, op.n_meas, op.rp, op.col,
+    k_adj_fill<T><<<g, blk, 0, st>>>(nb, rows, op.n_aq, op.rp, op.col,
                                      static_cast<const T *>(op.val), bin_tmp,
                                      static_cast<T *>(op.a_v0), static_cast<T *>(op.a_v1), bad);
     SCT_TRY(check_launch("k_adj_fill"));
     SCT_TRY(grid_for(op.a_slots, 256, &g));
     k_adj_finish<<<g, 256, 0, st>>>(bin_tmp, op.a_bin, op.a_slots);
     SCT_TRY(check_launch("k_adj_finish"));
+
+    // Block order for the forward product.  Workgroups are dispatched to the 8
+    // XCDs round-robin by block index; bundles of vertical-class rays (gathering
+    // from x) go to one set of XCDs and horizontal-class ones (gathering from
+    // the transposed image) to the other, in proportion to their counts.
+    {
+        std::vector<FwdBundle> hb(size_t(op.n_fb));
+        SCT_HIP(hipMemcpyAsync(hb.data(), op.fb, sizeof(FwdBundle) * op.n_fb, hipMemcpyDeviceToHost, st));
+        SCT_HIP(hipStreamSynchronize(st));
+        std::vector<int32_t> V, H;
+        for (int64_t b = 0; b < op.n_fb; ++b)   // empty bundles too: they write zeros
+            (hb[size_t(b)].horiz ? H : V).push_back(int32_t(b));
+        const int nx = 8;
+        int kv = nx;
+        if (!V.empty() && !H.empty()) {
+            kv = int(std::lround(double(nx) * V.size() / double(V.size() + H.size())));
+            kv = kv < 1 ? 1 : (kv > nx - 1 ? nx - 1 : kv);
+        } else if (V.empty()) {
+            kv = 0;
+        }
+        const int64_t rv = kv ? (int64_t(V.size()) + kv - 1) / kv : 0;
+        const int64_t rh = kv < nx ? (int64_t(H.size()) + (nx - kv) - 1) / (nx - kv) : 0;
+        const int64_t rounds = rv > rh ? rv : rh;
+        std::vector<int32_t> order(size_t(rounds * nx > 0 ? rounds * nx : 1), -1);
+        for (int64_t i = 0; i < rounds * nx; ++i) {
+            const int xcd = int(i % nx);
+            const int64_t j = i / nx;
+            if (xcd < kv) {
+                const int64_t k = j * kv + xcd;
+                if (k < int64_t(V.size())) order[size_t(i)] = V[size_t(k)];
+            } else {
+                const int64_t k = j * (nx - kv) + (xcd - kv);
+                if (k < int64_t(H.size())) order[size_t(i)] = H[size_t(k)];
+            }
+        }
+        op.n_order = int64_t(order.size());
+        SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.fb_order), 4 * op.n_order));
+        SCT_HIP(hipMemcpyAsync(op.fb_order, order.data(), 4 * order.size(), hipMemcpyHostToDevice, st));
+    }
 
     int32_t bad_h = 0;
     SCT_HIP(hipMemcpyAsync(&bad_h, bad, 4, hipMemcpyDeviceToHost, st));
@@ -533,7 +572,7 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     const int64_t rows = int64_t(meas.size()) * g->n_bins;
     if (rows >= INT_MAX) return set_error(RADON_EOVERFLOW, "measured rays %lld exceed int32", (long long)rows);
     const int64_t nn = int64_t(g->n) * g->n;
-    const int64_t aslots = ((nn + 63) / 64) * 64 * int64_t(meas.size());
+    const int64_t aslots = ((nn + 63) / 64) * 64 * 4 * ((int64_t(meas.size()) + 3) / 4);
     if (aslots >= (int64_t(1) << 40)) return set_error(RADON_EOVERFLOW, "adjoint layout too large");
 
     Op *op = new (std::nothrow) Op();
@@ -629,7 +668,7 @@ static int export_adj_typed(const Op &op, int32_t *bin, double *v0, double *v1)
     SCT_HIP(hipMemcpy(a1.data(), op.a_v1, sizeof(T) * ns, hipMemcpyDeviceToHost));
     for (int64_t j = 0; j < op.nn; ++j)
         for (int a = 0; a < op.n_meas; ++a) {
-            const size_t s = size_t(((j >> 6) * op.n_meas + a) * kAdjLanes + (j & 63));
+            const size_t s = size_t(adj_slot(j, a, op.n_aq));
             const size_t o = size_t(j * op.n_meas + a);
             const bool empty = a0[s] == T(0) && a1[s] == T(0);
             if (bin) bin[o] = empty ? -1 : int32_t(b[s]);

@@ -13,14 +13,28 @@
 namespace sct {
 
 // Forward product layout: one bundle = up to 16 adjacent bins of one measured
-// angle.  Slot (t, r) of a bundle sits at off + t*16 + r and covers ray r of
-// the bundle on image line m0 + t along the rays' major axis (rows for rays
-// closer to vertical, columns for rays closer to horizontal).
+// angle.  Slot (t, r) covers ray r of the bundle on image line m0 + t along the
+// rays' major axis (rows for rays closer to vertical, columns for rays closer
+// to horizontal).  Slots are grouped in quads of 4 consecutive lines of one
+// ray so that a lane reads 4 slots with one 16-byte load:
+//   slot(t, r) = off + ((t/4)*16 + r)*4 + t%4.
 constexpr int kFwdLanes = 16;
-// Adjoint layout: one group = 64 consecutive pixels (row-major); slot (a, l)
-// of group g sits at (g*n_meas + a)*64 + l and covers pixel g*64 + l at
-// measured angle a.
+// Adjoint layout: one group = 64 consecutive pixels (row-major).  Slot (a, l)
+// covers pixel g*64 + l at measured angle a; quads of 4 consecutive angles of
+// one pixel are contiguous:
+//   slot(j, a) = ((g*nq + a/4)*64 + l)*4 + a%4,  g = j/64, l = j%64,
+// with nq = ceil(n_meas/4) (angles past n_meas in the last quad are zero).
 constexpr int kAdjLanes = 64;
+
+__host__ __device__ inline int64_t fwd_slot(int64_t off, int t, int r)
+{
+    return off + ((int64_t(t >> 2) * kFwdLanes + r) << 2) + (t & 3);
+}
+
+__host__ __device__ inline int64_t adj_slot(int64_t j, int a, int nq)
+{
+    return ((((j >> 6) * nq + (a >> 2)) * kAdjLanes + (j & 63)) << 2) + (a & 3);
+}
 
 struct FwdBundle {
     int64_t off;    // first slot
@@ -52,11 +66,14 @@ struct Op {
     // forward ray-bundle layout (device)
     int64_t n_fb = 0, f_slots = 0;
     FwdBundle *fb = nullptr;
+    int32_t *fb_order = nullptr;     // block -> bundle (-1: idle), XCD-aware
+    int64_t n_order = 0;
     uint16_t *f_idx = nullptr;
     void *f_v0 = nullptr, *f_v1 = nullptr;
 
     // adjoint pixel-group layout (device)
     int64_t n_ag = 0, a_slots = 0;
+    int32_t n_aq = 0;                // angle quads per pixel: ceil(n_meas / 4)
     uint16_t *a_bin = nullptr;
     void *a_v0 = nullptr, *a_v1 = nullptr;
 
