@@ -42,6 +42,13 @@ template <class T> struct Quad;
 template <> struct Quad<float> { using type = f32x4; };
 template <> struct Quad<double> { using type = f64x4; };
 
+// Two adjacent vector elements fetched with one 16-byte load (8-byte aligned).
+typedef double f64x2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f32x2u __attribute__((ext_vector_type(2), aligned(4)));
+template <class T> struct PairU;
+template <> struct PairU<float> { using type = f32x2u; };
+template <> struct PairU<double> { using type = f64x2u; };
+
 // The matrix streams are read exactly once per product: non-temporal loads
 // keep them from evicting the gathered vector from the caches.
 template <class V>
@@ -61,54 +68,68 @@ __device__ inline V stream_load(const V *p)
 // waves in LDS, in a fixed order.
 template <class TM, class TV, int W>
 __global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb,
-                                                const int32_t *__restrict__ order,
+                                                const int32_t *__restrict__ order, int64_t n_order,
                                                 const uint16_t *__restrict__ idx,
                                                 const TM *__restrict__ v0, const TM *__restrict__ v1,
                                                 const TV *__restrict__ x, const TV *__restrict__ xT,
                                                 TV *__restrict__ y, int n, int64_t nn, int64_t rows)
 {
     using Q = typename Quad<TM>::type;
-    const int B = order[blockIdx.x];
-    if (B < 0) return;                 // padding block (uniform)
+    using P = typename PairU<TV>::type;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t bat = blockIdx.y;
-    const FwdBundle d = fb[B];
-    const TV *__restrict__ img = (d.horiz ? xT : x) + bat * nn;
     const int r = lane & 15, q = lane >> 4;
-    const int nq = d.nrows >> 2;
-    const int s0 = (nq * wave) / W, s1 = (nq * (wave + 1)) / W;
-    const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
-    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
-    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
-    TV acc = TV(0);
+    // persistent: the grid is a multiple of 8 blocks, so block i stays on XCD
+    // i % 8 and order[] keeps one gather class per XCD
+    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+        const int B = order[o];
+        if (B < 0) continue;           // padding entry (uniform per block)
+        const FwdBundle d = fb[B];
+        const TV *__restrict__ img = (d.horiz ? xT : x) + bat * nn;
+        const int nq = d.nrows >> 2;
+        const int s0 = (nq * wave) / W, s1 = (nq * (wave + 1)) / W;
+        const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
+        const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
+        const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
+        TV acc = TV(0);
 #pragma unroll 2
-    for (int tq = s0 + q; tq < s1; tq += 4) {
-        const int e = tq * kFwdLanes + r;
-        const u16x4 i4 = stream_load(I + e);
-        const Q a4 = stream_load(A + e);
-        const Q b4 = stream_load(Bv + e);
+        for (int tq = s0 + q; tq < s1; tq += 4) {
+            const int e = tq * kFwdLanes + r;
+            const u16x4 i4 = stream_load(I + e);
+            const Q a4 = stream_load(A + e);
+            const Q b4 = stream_load(Bv + e);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int m = min(d.m0 + 4 * tq + k, n - 1);
-            const TV *__restrict__ line = img + int64_t(m) * n;
-            const int i0 = i4[k];
-            const int i1 = i0 + 1 < n ? i0 + 1 : i0;
-            acc = fma(TV(a4[k]), line[i0], acc);
-            acc = fma(TV(b4[k]), line[i1], acc);
+            for (int k = 0; k < 4; ++k) {
+                const int m = min(d.m0 + 4 * tq + k, n - 1);
+                const TV *__restrict__ line = img + int64_t(m) * n;
+                const int i0 = i4[k];
+                if (n >= 2) {
+                    // one load for both pixels; a slot at the last column has no
+                    // second pixel (weight 0), so the pair starts at n-2 there
+                    const int ic = i0 < n - 1 ? i0 : n - 2;
+                    const P pr = *reinterpret_cast<const P *>(line + ic);
+                    acc = fma(TV(a4[k]), i0 == ic ? pr.x : pr.y, acc);
+                    acc = fma(TV(b4[k]), pr.y, acc);
+                } else {
+                    acc = fma(TV(a4[k]), line[0], acc);
+                }
+            }
         }
-    }
-    acc += __shfl_xor(acc, 16);
-    acc += __shfl_xor(acc, 32);
-    if constexpr (W > 1) {
-        __shared__ TV red[W][kFwdLanes];
-        if (q == 0) red[wave][r] = acc;
-        __syncthreads();
-        if (wave != 0) return;
-        acc = red[0][r];
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        if constexpr (W > 1) {
+            __shared__ TV red[W][kFwdLanes];
+            if (q == 0) red[wave][r] = acc;
+            __syncthreads();
+            if (wave == 0) {
+                acc = red[0][r];
 #pragma unroll
-        for (int w = 1; w < W; ++w) acc += red[w][r];
+                for (int w = 1; w < W; ++w) acc += red[w][r];
+            }
+            __syncthreads();   // red is reused by the next bundle
+        }
+        if (wave == 0 && q == 0 && r < d.nrays) y[bat * rows + d.ray0 + r] = acc;
     }
-    if (q == 0 && r < d.nrays) y[bat * rows + d.ray0 + r] = acc;
 }
 
 template <class T>
@@ -130,71 +151,88 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// One workgroup of W waves per 64-pixel group: wave w sums its share of the
-// measured-angle quads for the 64 pixels (one sequential sum per pixel and
-// wave, 16-byte loads of 4 angles per lane), the shares are added in wave
-// order, and wave 0 applies the epilogue
+// Adjoint: one workgroup of W waves per 8x8 pixel tile (persistent loop over
+// tiles).  Wave w sums its share of the measured-angle quads for the tile's
+// 64 pixels.  Per quad it stages the tile's sinogram band (16 bins from the
+// tile's base bin, for each of the 4 angles: exactly one 64-lane load) in LDS
+// and reads the pixel's two bins from there, so the vector-memory pipeline
+// only carries the three matrix streams and the band.  The wave shares are
+// added in wave order, and wave 0 applies the epilogue
 // out = alpha*acc + lambda*(K^T K x) + sigma*x and the FP64 partial <x, out>.
 template <class TM, class T, int W>
-__global__ __launch_bounds__(64 * W) void k_adj(const uint16_t *__restrict__ bin,
+__global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
+                                                const uint16_t *__restrict__ base,
                                                 const TM *__restrict__ v0, const TM *__restrict__ v1,
                                                 int64_t n_ag, int n_meas, int n_aq, int nb,
                                                 const T *__restrict__ y, const T *__restrict__ x,
                                                 T *__restrict__ out, T alpha, T lambda, T sigma,
-                                                double *__restrict__ part, int n, int64_t nn,
-                                                int64_t rows)
+                                                double *__restrict__ part, int n, int tiles,
+                                                int64_t nn, int64_t rows)
 {
     using Q = typename Quad<TM>::type;
+    __shared__ T band[W][4][kAdjBand];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t g = blockIdx.x;
     const int64_t bat = blockIdx.y;
     const T *__restrict__ yb = y + bat * rows;
     const int q0 = (n_aq * wave) / W, q1 = (n_aq * (wave + 1)) / W;
-    const u16x4 *__restrict__ Bn = reinterpret_cast<const u16x4 *>(bin);
+    const uint32_t *__restrict__ Rl = reinterpret_cast<const uint32_t *>(rel);
     const Q *__restrict__ A = reinterpret_cast<const Q *>(v0);
     const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1);
-    T acc = T(0);
+    const int kk = lane >> 4, ee = lane & 15;   // this lane's band element
+    T *__restrict__ my = &band[wave][0][0];
+    double dsum = 0.0;   // this block's share of <x, out>, tiles in a fixed order
+    for (int64_t g = blockIdx.x; g < n_ag; g += gridDim.x) {
+        T acc = T(0);
 #pragma unroll 2
-    for (int aq = q0; aq < q1; ++aq) {
-        const int64_t e = (g * n_aq + aq) * kAdjLanes + lane;
-        const u16x4 b4 = stream_load(Bn + e);
-        const Q a4 = stream_load(A + e);
-        const Q c4 = stream_load(Bv + e);
+        for (int aq = q0; aq < q1; ++aq) {
+            const int64_t gq = g * n_aq + aq;
+            const int a_band = min(4 * aq + kk, n_meas - 1);
+            const int b_band = min(int(base[gq * 4 + kk]) + ee, nb - 1);
+            const T yv = yb[int64_t(a_band) * nb + b_band];
+            const int64_t e = gq * kAdjLanes + lane;
+            const uint32_t r4 = stream_load(Rl + e);
+            const Q a4 = stream_load(A + e);
+            const Q c4 = stream_load(Bv + e);
+            my[lane] = yv;
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int a = min(4 * aq + k, n_meas - 1);   // zero slots past the last angle
-            const T *__restrict__ yr = yb + int64_t(a) * nb;
-            const int b0 = b4[k];
-            const int b1 = b0 + 1 < nb ? b0 + 1 : b0;
-            acc = fma(T(a4[k]), yr[b0], acc);
-            acc = fma(T(c4[k]), yr[b1], acc);
+            for (int k = 0; k < 4; ++k) {
+                const int rb = int((r4 >> (8 * k)) & 0xffu);
+                acc = fma(T(a4[k]), my[k * kAdjBand + rb], acc);
+                acc = fma(T(c4[k]), my[k * kAdjBand + rb + 1], acc);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if constexpr (W > 1) {
+            __shared__ T red[W][64];
+            red[wave][lane] = acc;
+            __syncthreads();
+            if (wave == 0) {
+                acc = red[0][lane];
+#pragma unroll
+                for (int w = 1; w < W; ++w) acc += red[w][lane];
+            }
+            __syncthreads();   // red is reused by the next tile
+        }
+        if (wave == 0) {
+            const int iy = int(g / tiles) * 8 + (lane >> 3), ix = int(g % tiles) * 8 + (lane & 7);
+            const int64_t j = int64_t(iy) * n + ix;
+            if (iy < n && ix < n) {
+                T o = alpha * acc;
+                if (x) {
+                    const T *__restrict__ xb = x + bat * nn;
+                    const T xj = xb[j];
+                    if (lambda != T(0)) o += lambda * ktk_at(xb, j, n, xj);
+                    if (sigma != T(0)) o += sigma * xj;
+                    dsum += double(xj) * double(o);
+                }
+                out[bat * nn + j] = o;
+            }
         }
     }
-    if constexpr (W > 1) {
-        __shared__ T red[W][64];
-        red[wave][lane] = acc;
-        __syncthreads();
-        if (wave != 0) return;
-        acc = red[0][lane];
-#pragma unroll
-        for (int w = 1; w < W; ++w) acc += red[w][lane];
-    }
-    const int64_t j = g * kAdjLanes + lane;
-    double dp = 0.0;
-    if (j < nn) {
-        T o = alpha * acc;
-        if (x) {
-            const T *__restrict__ xb = x + bat * nn;
-            const T xj = xb[j];
-            if (lambda != T(0)) o += lambda * ktk_at(xb, j, n, xj);
-            if (sigma != T(0)) o += sigma * xj;
-            dp = double(xj) * double(o);
-        }
-        out[bat * nn + j] = o;
-    }
-    if (part) {
-        dp = wave_sum(dp);
-        if (lane == 0) part[bat * n_ag + g] = dp;
+    if (part && wave == 0) {
+        dsum = wave_sum(dsum);
+        if (lane == 0) part[bat * gridDim.x + blockIdx.x] = dsum;
     }
 }
 
@@ -239,31 +277,34 @@ int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStr
 {
     SCT_TRY(check_grid_y(batch));
     constexpr int W = 4;
-    k_fwd<TM, TV, W><<<dim3(unsigned(op.n_order), unsigned(batch)), 64 * W, 0, s>>>(
-        op.fb, op.fb_order, op.f_idx, static_cast<const TM *>(op.f_v0),
+    const int64_t g = op.n_order < kPersistentBlocks ? op.n_order : kPersistentBlocks;
+    k_fwd<TM, TV, W><<<dim3(unsigned(g), unsigned(batch)), 64 * W, 0, s>>>(
+        op.fb, op.fb_order, op.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
         static_cast<const TM *>(op.f_v1), x, xT ? xT : x, y, op.n, op.nn, op.rows);
     return check_launch("k_fwd");
 }
+
+int adj_blocks(const Op &op) { return int(op.n_ag < kPersistentBlocks ? op.n_ag : kPersistentBlocks); }
 
 template <class TM, class TV>
 int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, double lambda,
                double sigma, double *part, int batch, hipStream_t s)
 {
     SCT_TRY(check_grid_y(batch));
-    if (op.n_ag > int64_t(INT_MAX)) return set_error(RADON_EOVERFLOW, "too many pixel groups");
-    const dim3 grid(unsigned(op.n_ag), unsigned(batch));
-    const auto *bin = op.a_bin;
+    const dim3 grid(unsigned(adj_blocks(op)), unsigned(batch));
+    const uint8_t *rel = op.a_rel;
+    const uint16_t *bs = op.a_base;
     const TM *a0 = static_cast<const TM *>(op.a_v0), *a1 = static_cast<const TM *>(op.a_v1);
     const TV al = TV(alpha), la = TV(lambda), si = TV(sigma);
     if (op.n_meas >= 128)
-        k_adj<TM, TV, 4><<<grid, 256, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y, x, out,
-                                              al, la, si, part, op.n, op.nn, op.rows);
+        k_adj<TM, TV, 4><<<grid, 256, 0, s>>>(rel, bs, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y,
+                                              x, out, al, la, si, part, op.n, op.tiles, op.nn, op.rows);
     else if (op.n_meas >= 48)
-        k_adj<TM, TV, 2><<<grid, 128, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y, x, out,
-                                              al, la, si, part, op.n, op.nn, op.rows);
+        k_adj<TM, TV, 2><<<grid, 128, 0, s>>>(rel, bs, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y,
+                                              x, out, al, la, si, part, op.n, op.tiles, op.nn, op.rows);
     else
-        k_adj<TM, TV, 1><<<grid, 64, 0, s>>>(bin, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y, x, out,
-                                             al, la, si, part, op.n, op.nn, op.rows);
+        k_adj<TM, TV, 1><<<grid, 64, 0, s>>>(rel, bs, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y,
+                                             x, out, al, la, si, part, op.n, op.tiles, op.nn, op.rows);
     return check_launch("k_adj");
 }
 
@@ -387,7 +428,7 @@ extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, doub
         SCT_TRY(launch_fwd<TM, TV>(op, xx, xT, y, batch, s));
         SCT_TRY(launch_adj<TM, TV>(op, y, xx, static_cast<TV *>(out), alpha, lambda, sigma,
                                    dot_out ? part : nullptr, batch, s));
-        if (dot_out) SCT_TRY(launch_sum_partials(part, op.n_ag, dot_out, batch, s));
+        if (dot_out) SCT_TRY(launch_sum_partials(part, adj_blocks(op), dot_out, batch, s));
         return RADON_OK;
     });
 }

@@ -38,7 +38,7 @@ int check_op(const radon_op *p)
 {
     if (!p) return set_error(RADON_EINVAL, "operator handle is NULL");
     const Op *op = as_op(p);
-    if (op->n <= 0 || !op->fb || !op->a_v0) return set_error(RADON_ESTATE, "operator handle is not built");
+    if (op->n <= 0 || !op->fb || !op->a_v0 || !op->a_rel) return set_error(RADON_ESTATE, "operator handle is not built");
     return RADON_OK;
 }
 
@@ -262,7 +262,7 @@ __global__ void k_bundle_off(FwdBundle *__restrict__ fb, const int64_t *__restri
 // bin of every (pixel, angle) pair the ray touches.
 template <class T>
 __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nbpa, int64_t rows,
-                           int n_aq, const int64_t *__restrict__ rp, int32_t *__restrict__ col,
+                           int n_aq, int tiles, const int64_t *__restrict__ rp, int32_t *__restrict__ col,
                            T *__restrict__ val, const FwdBundle *__restrict__ fb,
                            uint16_t *__restrict__ f_idx, T *__restrict__ f_v0,
                            T *__restrict__ f_v1, int32_t *__restrict__ bin_tmp,
@@ -322,7 +322,7 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nb
             q1 = q;
             w1 = v;
         }
-        atomicMin(&bin_tmp[adj_slot(j, a, n_aq)], b);
+        atomicMin(&bin_tmp[adj_slot(j / n, j % n, a, n_aq, tiles)], b);
     });
     flush();
     if (o != oend) atomicOr(bad, 4);
@@ -330,7 +330,7 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nb
 
 // Pass 3: place each entry in its (pixel, angle) slot as the first or second bin.
 template <class T>
-__global__ void k_adj_fill(int nb, int64_t rows, int n_aq, const int64_t *__restrict__ rp,
+__global__ void k_adj_fill(int n, int nb, int64_t rows, int n_aq, int tiles, const int64_t *__restrict__ rp,
                            const int32_t *__restrict__ col, const T *__restrict__ val,
                            const int32_t *__restrict__ bin_tmp, T *__restrict__ a_v0,
                            T *__restrict__ a_v1, int32_t *__restrict__ bad)
@@ -340,7 +340,7 @@ __global__ void k_adj_fill(int nb, int64_t rows, int n_aq, const int64_t *__rest
     const int a = int(ray / nb), b = int(ray % nb);
     for (int64_t e = rp[ray]; e < rp[ray + 1]; ++e) {
         const int j = col[e];
-        const int64_t as = adj_slot(j, a, n_aq);
+        const int64_t as = adj_slot(j / n, j % n, a, n_aq, tiles);
         const int first = bin_tmp[as];
         if (b == first) a_v0[as] = val[e];
         else if (b == first + 1) a_v1[as] = val[e];
@@ -348,13 +348,37 @@ __global__ void k_adj_fill(int nb, int64_t rows, int n_aq, const int64_t *__rest
     }
 }
 
-__global__ void k_adj_finish(const int32_t *__restrict__ bin_tmp, uint16_t *__restrict__ a_bin,
-                             int64_t a_slots)
+// Per (tile, angle): the lowest first-bin over the tile's pixels.
+__global__ void k_adj_base(const int32_t *__restrict__ bin_tmp, uint16_t *__restrict__ a_base,
+                           int64_t n_ag, int n_aq)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;   // (tile, angle)
+    if (i >= n_ag * n_aq * 4) return;
+    const int64_t g = i / (int64_t(n_aq) * 4);
+    const int a = int(i % (int64_t(n_aq) * 4));
+    int lo = 65536;
+    for (int l = 0; l < kAdjLanes; ++l) {
+        const int t = bin_tmp[(((g * n_aq + (a >> 2)) * kAdjLanes + l) << 2) + (a & 3)];
+        lo = t < lo ? t : lo;
+    }
+    a_base[i] = lo >= 65536 ? uint16_t(0) : uint16_t(lo);
+}
+
+__global__ void k_adj_finish(const int32_t *__restrict__ bin_tmp, const uint16_t *__restrict__ a_base,
+                             uint8_t *__restrict__ a_rel, int64_t a_slots, int32_t *__restrict__ bad)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a_slots) return;
+    // slot i = ((g*nq + aq)*64 + l)*4 + k  ->  base index (g*nq + aq)*4 + k
+    const int64_t bi = ((i >> 2) / kAdjLanes) * 4 + (i & 3);
     const int t = bin_tmp[i];
-    a_bin[i] = t >= 65536 ? uint16_t(0) : uint16_t(t);
+    if (t >= 65536) {
+        a_rel[i] = 0;
+        return;
+    }
+    const int rel = t - int(a_base[bi]);
+    if (rel < 0 || rel + 1 >= kAdjBand) atomicOr(bad, 32);
+    a_rel[i] = uint8_t(rel < 0 ? 0 : (rel > kAdjBand - 2 ? kAdjBand - 2 : rel));
 }
 
 // ---------------------------------------------------------------------------
@@ -471,10 +495,12 @@ static int build_typed(Op &op, const std::vector<double> &cs_host, hipStream_t s
     SCT_HIP(hipMemsetAsync(op.f_v0, 0, size_t(es * fslots), st));
     SCT_HIP(hipMemsetAsync(op.f_v1, 0, size_t(es * fslots), st));
 
-    op.n_ag = (op.nn + kAdjLanes - 1) / kAdjLanes;
+    op.tiles = (op.n + 7) / 8;
+    op.n_ag = int64_t(op.tiles) * op.tiles;
     op.n_aq = (op.n_meas + 3) / 4;
     op.a_slots = op.n_ag * kAdjLanes * 4 * op.n_aq;
-    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.a_bin), 2 * op.a_slots));
+    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.a_rel), op.a_slots));
+    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.a_base), 2 * op.n_ag * op.n_aq * 4));
     SCT_TRY(op_alloc(op, &op.a_v0, es * op.a_slots));
     SCT_TRY(op_alloc(op, &op.a_v1, es * op.a_slots));
     SCT_HIP(hipMemsetAsync(op.a_v0, 0, size_t(es * op.a_slots), st));
@@ -484,17 +510,21 @@ static int build_typed(Op &op, const std::vector<double> &cs_host, hipStream_t s
     SCT_HIP(hipMemsetAsync(bin_tmp, 0x7f, size_t(4 * op.a_slots), st));   // 0x7f7f7f7f > any bin
 
     SCT_TRY(grid_for(rows, blk, &g));
-    k_ray_fill<T><<<g, blk, 0, st>>>(cs, n, nb, nbpa, rows, op.n_aq, op.rp, op.col,
+    k_ray_fill<T><<<g, blk, 0, st>>>(cs, n, nb, nbpa, rows, op.n_aq, op.tiles, op.rp, op.col,
                                      static_cast<T *>(op.val), op.fb, op.f_idx,
                                      static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), bin_tmp,
                                      bad);
     SCT_TRY(check_launch("k_ray_fill"));
-    k_adj_fill<T><<<g, blk, 0, st>>>(nb, rows, op.n_aq, op.rp, op.col,
+    k_adj_fill<T><<<g, blk, 0, st>>>(n, nb, rows, op.n_aq, op.tiles, op.rp, op.col,
                                      static_cast<const T *>(op.val), bin_tmp,
                                      static_cast<T *>(op.a_v0), static_cast<T *>(op.a_v1), bad);
     SCT_TRY(check_launch("k_adj_fill"));
     SCT_TRY(grid_for(op.a_slots, 256, &g));
-    k_adj_finish<<<g, 256, 0, st>>>(bin_tmp, op.a_bin, op.a_slots);
+    SCT_TRY(grid_for(op.n_ag * op.n_aq * 4, 256, &g));
+    k_adj_base<<<g, 256, 0, st>>>(bin_tmp, op.a_base, op.n_ag, op.n_aq);
+    SCT_TRY(check_launch("k_adj_base"));
+    SCT_TRY(grid_for(op.a_slots, 256, &g));
+    k_adj_finish<<<g, 256, 0, st>>>(bin_tmp, op.a_base, op.a_rel, op.a_slots, bad);
     SCT_TRY(check_launch("k_adj_finish"));
 
     // Block order for the forward product.  Workgroups are dispatched to the 8
@@ -572,7 +602,8 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     const int64_t rows = int64_t(meas.size()) * g->n_bins;
     if (rows >= INT_MAX) return set_error(RADON_EOVERFLOW, "measured rays %lld exceed int32", (long long)rows);
     const int64_t nn = int64_t(g->n) * g->n;
-    const int64_t aslots = ((nn + 63) / 64) * 64 * 4 * ((int64_t(meas.size()) + 3) / 4);
+    const int64_t aslots = int64_t((g->n + 7) / 8) * ((g->n + 7) / 8) * 64 * 4 *
+                           ((int64_t(meas.size()) + 3) / 4);
     if (aslots >= (int64_t(1) << 40)) return set_error(RADON_EOVERFLOW, "adjoint layout too large");
 
     Op *op = new (std::nothrow) Op();
@@ -661,17 +692,20 @@ template <class T>
 static int export_adj_typed(const Op &op, int32_t *bin, double *v0, double *v1)
 {
     const size_t ns = size_t(op.a_slots);
-    std::vector<uint16_t> b(ns);
+    std::vector<uint8_t> rel(ns);
+    std::vector<uint16_t> base(size_t(op.n_ag * op.n_aq * 4));
     std::vector<T> a0(ns), a1(ns);
-    SCT_HIP(hipMemcpy(b.data(), op.a_bin, 2 * ns, hipMemcpyDeviceToHost));
+    SCT_HIP(hipMemcpy(rel.data(), op.a_rel, ns, hipMemcpyDeviceToHost));
+    SCT_HIP(hipMemcpy(base.data(), op.a_base, 2 * base.size(), hipMemcpyDeviceToHost));
     SCT_HIP(hipMemcpy(a0.data(), op.a_v0, sizeof(T) * ns, hipMemcpyDeviceToHost));
     SCT_HIP(hipMemcpy(a1.data(), op.a_v1, sizeof(T) * ns, hipMemcpyDeviceToHost));
     for (int64_t j = 0; j < op.nn; ++j)
         for (int a = 0; a < op.n_meas; ++a) {
-            const size_t s = size_t(adj_slot(j, a, op.n_aq));
+            const size_t s = size_t(adj_slot(int(j / op.n), int(j % op.n), a, op.n_aq, op.tiles));
+            const size_t bi = ((s >> 2) / kAdjLanes) * 4 + (s & 3);
             const size_t o = size_t(j * op.n_meas + a);
             const bool empty = a0[s] == T(0) && a1[s] == T(0);
-            if (bin) bin[o] = empty ? -1 : int32_t(b[s]);
+            if (bin) bin[o] = empty ? -1 : int32_t(base[bi]) + int32_t(rel[s]);
             if (v0) v0[o] = double(a0[s]);
             if (v1) v1[o] = double(a1[s]);
         }

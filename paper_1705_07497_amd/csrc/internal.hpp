@@ -19,21 +19,30 @@ namespace sct {
 // ray so that a lane reads 4 slots with one 16-byte load:
 //   slot(t, r) = off + ((t/4)*16 + r)*4 + t%4.
 constexpr int kFwdLanes = 16;
-// Adjoint layout: one group = 64 consecutive pixels (row-major).  Slot (a, l)
-// covers pixel g*64 + l at measured angle a; quads of 4 consecutive angles of
-// one pixel are contiguous:
-//   slot(j, a) = ((g*nq + a/4)*64 + l)*4 + a%4,  g = j/64, l = j%64,
-// with nq = ceil(n_meas/4) (angles past n_meas in the last quad are zero).
+// Adjoint layout: one group = an 8x8 pixel tile (tile (ty, tx) is group
+// g = ty*tiles + tx, tiles = ceil(n/8); lane l = (iy%8)*8 + ix%8), chosen
+// because an 8x8 tile projects onto at most 14 adjacent bins at any angle, so
+// the 64 lanes' sinogram gathers hit one or two cache lines.  Slot (a, l)
+// covers the lane's pixel at measured angle a; quads of 4 consecutive angles
+// of one pixel are contiguous:
+//   slot(g, l, a) = ((g*nq + a/4)*64 + l)*4 + a%4,
+// with nq = ceil(n_meas/4) (angles past n_meas in the last quad are zero;
+// lanes outside the image are zero too).  A slot stores its first bin as an
+// 8-bit offset from the tile's lowest bin at that angle (the tile's bins span
+// at most 13, so bin and bin+1 fall in a 16-bin band starting at the base).
 constexpr int kAdjLanes = 64;
+constexpr int kAdjBand = 16;
 
 __host__ __device__ inline int64_t fwd_slot(int64_t off, int t, int r)
 {
     return off + ((int64_t(t >> 2) * kFwdLanes + r) << 2) + (t & 3);
 }
 
-__host__ __device__ inline int64_t adj_slot(int64_t j, int a, int nq)
+__host__ __device__ inline int64_t adj_slot(int iy, int ix, int a, int nq, int tiles)
 {
-    return ((((j >> 6) * nq + (a >> 2)) * kAdjLanes + (j & 63)) << 2) + (a & 3);
+    const int64_t g = int64_t(iy >> 3) * tiles + (ix >> 3);
+    const int l = ((iy & 7) << 3) | (ix & 7);
+    return (((g * nq + (a >> 2)) * kAdjLanes + l) << 2) + (a & 3);
 }
 
 struct FwdBundle {
@@ -74,7 +83,9 @@ struct Op {
     // adjoint pixel-group layout (device)
     int64_t n_ag = 0, a_slots = 0;
     int32_t n_aq = 0;                // angle quads per pixel: ceil(n_meas / 4)
-    uint16_t *a_bin = nullptr;
+    int32_t tiles = 0;               // 8x8 tiles per image side: ceil(n / 8)
+    uint16_t *a_base = nullptr;      // [n_ag][n_aq][4]: lowest bin the tile meets at each angle
+    uint8_t *a_rel = nullptr;        // per slot: first bin of the pixel minus the tile's base
     void *a_v0 = nullptr, *a_v1 = nullptr;
 
     int64_t device_bytes = 0;
@@ -156,6 +167,11 @@ int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStr
 template <class TM, class TV>
 int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, double lambda,
                double sigma, double *part, int batch, hipStream_t s);
+// Persistent product kernels use a fixed grid of 8 workgroups per CU (256 CUs)
+// that loop over the work items; the adjoint leaves one <x, out> partial per
+// workgroup, adj_blocks(op) of them per right-hand side.
+constexpr int kPersistentBlocks = 2048;
+int adj_blocks(const Op &op);
 // sum part[batch][count] -> dst[batch] (fixed order)
 int launch_sum_partials(const double *part, int64_t count, double *dst, int batch, hipStream_t s);
 

@@ -13,9 +13,18 @@
 
 namespace sct {
 
-struct CgScal {
-    double rho, rho0, a, beta, gamma;
+// Per right-hand side CG state at the start of an iteration, in a two-slot
+// ring indexed by iteration parity: every kernel reads slot it%2 and only a
+// later kernel writes slot (it+1)%2, so no kernel reads what it writes.
+struct CgState {
+    double rho, rho0;
     int32_t stopped, iters, breakdown, pad;
+};
+
+// Result of the step-length decision of one iteration (also a 2-slot ring).
+struct CgStep {
+    double a, gamma;
+    int32_t stopped, pad;
 };
 
 struct SbScal {
@@ -95,75 +104,66 @@ __device__ inline double sum_part_block(const double *__restrict__ part, int64_t
     return block_sum(v, red);
 }
 
-// rho_0 = sum of partials; resets the per-solve state.  A set SB stop flag
-// starts the solve stopped (the outer loop has finished).
+// rho_0 = sum of partials; resets the per-solve state (ring slot 0).  A set
+// SB stop flag starts the solve stopped (the outer loop has finished).
 __global__ __launch_bounds__(256) void k_cg_begin(const double *__restrict__ part, int64_t count,
-                                                  CgScal *__restrict__ sc,
+                                                  CgState *__restrict__ st,
                                                   const SbScal *__restrict__ sbs)
 {
     __shared__ double red[256];
     const int b = blockIdx.x;
     const double rho = sum_part_block(part + int64_t(b) * count, count, red);
     if (threadIdx.x == 0) {
-        CgScal c;
+        CgState c;
         c.rho = rho;
         c.rho0 = rho;
-        c.a = 0.0;
-        c.beta = 0.0;
-        c.gamma = 0.0;
         c.stopped = (sbs && sbs[b].stop) ? 1 : 0;
         c.iters = 0;
         c.breakdown = 0;
         c.pad = 0;
-        sc[b] = c;
+        st[b] = c;
     }
 }
 
-// gamma = <p, Ap>; stop on rho == 0, on the relative tolerance, or on a
-// breakdown (gamma <= 0 or non-finite); a = rho / gamma otherwise.
-__global__ __launch_bounds__(256) void k_cg_alpha(const double *__restrict__ part, int64_t count,
-                                                  CgScal *__restrict__ sc, double rtol, int it)
-{
-    __shared__ double red[256];
-    const int b = blockIdx.x;
-    const double gamma = sum_part_block(part + int64_t(b) * count, count, red);
-    if (threadIdx.x == 0) {
-        CgScal c = sc[b];
-        c.gamma = gamma;
-        c.a = 0.0;
-        if (!c.stopped) {
-            if (c.rho == 0.0 || (rtol > 0.0 && sqrt(c.rho) <= rtol * sqrt(c.rho0))) {
-                c.stopped = 1;
-            } else if (!(gamma > 0.0) || !isfinite(gamma)) {
-                c.stopped = 1;
-                c.breakdown = it + 1;
-            } else {
-                c.a = c.rho / gamma;
-            }
-        }
-        sc[b] = c;
-    }
-}
-
-// x += a p ; r -= a q ; partial <r, r>
+// Step length and update: gamma = <p, Ap> from the adjoint's partials (every
+// block sums them in the same fixed order); stop on rho == 0, on the relative
+// tolerance, or on a breakdown (gamma <= 0 or non-finite); otherwise
+// a = rho / gamma, x += a p, r -= a q and partial <r, r>.  Block 0 records the
+// decision in `step` for the p update.
 template <class T>
-__global__ __launch_bounds__(kVecThreads) void k_cg_xr(T *__restrict__ x, T *__restrict__ r,
-                                                        const T *__restrict__ p,
-                                                        const T *__restrict__ q,
-                                                        const CgScal *__restrict__ sc,
-                                                        double *__restrict__ part, int64_t nn)
+__global__ __launch_bounds__(kVecThreads) void k_cg_xr(
+    T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q,
+    const double *__restrict__ part_adj, int64_t n_adj, const CgState *__restrict__ st,
+    CgStep *__restrict__ step, double rtol, double *__restrict__ part, int64_t nn)
 {
     __shared__ double red[kVecThreads];
     const int64_t b = blockIdx.y;
-    if (sc[b].stopped) return;   // uniform per block; the partials are then unused
-    const T a = T(sc[b].a);
+    const double gamma = sum_part_block(part_adj + b * n_adj, n_adj, red);
+    const CgState c = st[b];
+    int stop = c.stopped;
+    double a = 0.0;
+    if (!stop) {
+        if (c.rho == 0.0 || (rtol > 0.0 && sqrt(c.rho) <= rtol * sqrt(c.rho0))) stop = 1;
+        else if (!(gamma > 0.0) || !isfinite(gamma)) stop = 2;   // breakdown
+        else a = c.rho / gamma;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        CgStep o;
+        o.a = a;
+        o.gamma = gamma;
+        o.stopped = stop;
+        o.pad = 0;
+        step[b] = o;
+    }
+    if (stop) return;   // uniform per block; the partials are then unused
+    const T at = T(a);
     const int64_t off = b * nn;
     double acc = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
          i += int64_t(gridDim.x) * kVecThreads) {
         const int64_t j = off + i;
-        x[j] = fma(a, p[j], x[j]);
-        const T rn = fma(-a, q[j], r[j]);
+        x[j] = fma(at, p[j], x[j]);
+        const T rn = fma(-at, q[j], r[j]);
         r[j] = rn;
         acc += double(rn) * double(rn);
     }
@@ -171,44 +171,53 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_xr(T *__restrict__ x, T *__r
     if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_cg_beta(const double *__restrict__ part, int64_t count,
-                                                 CgScal *__restrict__ sc)
-{
-    __shared__ double red[256];
-    const int b = blockIdx.x;
-    const double rn = sum_part_block(part + int64_t(b) * count, count, red);
-    if (threadIdx.x == 0) {
-        CgScal c = sc[b];
-        if (!c.stopped) {
-            c.beta = rn / c.rho;
-            c.rho = rn;
-            c.iters += 1;
-        } else {
-            c.beta = 0.0;
-        }
-        sc[b] = c;
-    }
-}
-
-// p = r + beta p, with the transposed copy.
+// beta = rho'/rho from the update's partials (summed by every block in the
+// same order), p = r + beta p with its transposed copy; block 0 writes the
+// next iteration's state.
 template <class T>
 __global__ __launch_bounds__(256) void k_cg_p(const T *__restrict__ r, T *__restrict__ p,
-                                              T *__restrict__ pT, const CgScal *__restrict__ sc,
-                                              int n, int64_t nn)
+                                              T *__restrict__ pT, const double *__restrict__ part,
+                                              int64_t n_part, const CgState *__restrict__ st,
+                                              const CgStep *__restrict__ step,
+                                              CgState *__restrict__ st_next, int it, int n,
+                                              int64_t nn)
 {
     __shared__ T tile[32][33];
+    __shared__ double red[256];
     const int64_t b = blockIdx.z;
-    if (sc[b].stopped) return;
-    const T beta = T(sc[b].beta);
+    const CgState c = st[b];
+    const int stop = step[b].stopped;
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0;
+    if (stop) {
+        if (lead) {
+            CgState o = c;
+            o.stopped = 1;
+            if (stop == 2 && !c.stopped) o.breakdown = it + 1;
+            st_next[b] = o;
+        }
+        return;
+    }
+    double v = 0.0;
+    const int t = threadIdx.y * 32 + threadIdx.x;
+    for (int64_t i = t; i < n_part; i += 256) v += part[b * n_part + i];
+    const double rn = block_sum(v, red);
+    const double beta_d = rn / c.rho;
+    if (lead) {
+        CgState o = c;
+        o.rho = rn;
+        o.iters = c.iters + 1;
+        st_next[b] = o;
+    }
+    const T beta = T(beta_d);
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int64_t off = b * nn;
     for (int i = threadIdx.y; i < 32; i += 8) {
         const int iy = by + i, ix = bx + threadIdx.x;
         if (iy < n && ix < n) {
             const int64_t j = off + int64_t(iy) * n + ix;
-            const T v = fma(beta, p[j], r[j]);
-            p[j] = v;
-            tile[i][threadIdx.x] = v;
+            const T v2 = fma(beta, p[j], r[j]);
+            p[j] = v2;
+            tile[i][threadIdx.x] = v2;
         }
     }
     if (!pT) return;
@@ -219,15 +228,15 @@ __global__ __launch_bounds__(256) void k_cg_p(const T *__restrict__ r, T *__rest
     }
 }
 
-__global__ void k_cg_info(const CgScal *__restrict__ sc, radon_cg_info *__restrict__ info, int batch)
+__global__ void k_cg_info(const CgState *__restrict__ st, radon_cg_info *__restrict__ info, int batch)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     radon_cg_info o;
-    o.iterations = sc[b].iters;
-    o.breakdown = sc[b].breakdown;
-    o.rho0 = sc[b].rho0;
-    o.rho = sc[b].rho;
+    o.iterations = st[b].iters;
+    o.breakdown = st[b].breakdown;
+    o.rho0 = st[b].rho0;
+    o.rho = st[b].rho;
     info[b] = o;
 }
 
@@ -339,7 +348,7 @@ __global__ __launch_bounds__(kVecThreads) void k_sb_carry(T *__restrict__ r,
 
 __global__ __launch_bounds__(256) void k_sb_update(const double *__restrict__ part, int64_t count,
                                                    SbScal *__restrict__ sbs,
-                                                   const CgScal *__restrict__ sc, double tol)
+                                                   const CgState *__restrict__ sc, double tol)
 {
     __shared__ double red[256];
     const int b = blockIdx.x;
@@ -400,7 +409,8 @@ template <class T>
 struct CgBufs {
     T *r = nullptr, *p = nullptr, *pT = nullptr, *q = nullptr, *y = nullptr;
     double *part_adj = nullptr, *part_vec = nullptr;
-    CgScal *sc = nullptr;
+    CgState *st = nullptr;   // [2][batch]
+    CgStep *step = nullptr;  // [2][batch]
 };
 
 template <class T>
@@ -416,7 +426,8 @@ static void carve_cg(const Op &op, int batch, Carver &c, CgBufs<T> &w)
     const int64_t tl = int64_t(tiles_of(op.n)) * tiles_of(op.n);
     const int64_t pv = tl > 2 * vec_blocks(op.nn) ? tl : 2 * vec_blocks(op.nn);
     w.part_vec = c.take<double>(pv * batch);
-    w.sc = c.take<CgScal>(batch);
+    w.st = c.take<CgState>(2 * int64_t(batch));
+    w.step = c.take<CgStep>(2 * int64_t(batch));
 }
 
 int64_t cg_ws_bytes(const Op &op, int batch)
@@ -470,7 +481,8 @@ int64_t sb_ws_bytes(const Op &op, int batch)
     return c.used;
 }
 
-// One CG solve on A(alpha, lambda, sigma) from x with the residual already in w.r.
+// One CG solve on A(alpha, lambda, sigma) from x with the residual already in
+// w.r; the final state is left in ring slot n_iter % 2.
 template <class TM, class T>
 static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x, int batch,
                   int n_iter, double rtol, CgBufs<T> &w, T *u_for_prev, T *uprev,
@@ -481,23 +493,26 @@ static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x,
     const int64_t ntiles = int64_t(t) * t;
     k_cg_start<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, u_for_prev, uprev, w.part_vec, op.n, op.nn);
     SCT_TRY(check_launch("k_cg_start"));
-    k_cg_begin<<<unsigned(batch), 256, 0, s>>>(w.part_vec, ntiles, w.sc, sbs);
+    k_cg_begin<<<unsigned(batch), 256, 0, s>>>(w.part_vec, ntiles, w.st, sbs);
     SCT_TRY(check_launch("k_cg_begin"));
     const int vb = vec_blocks(op.nn);
     for (int it = 0; it < n_iter; ++it) {
+        CgState *cur = w.st + int64_t(it & 1) * batch, *nxt = w.st + int64_t((it + 1) & 1) * batch;
+        CgStep *stp = w.step + int64_t(it & 1) * batch;
         SCT_TRY((launch_fwd<TM, T>(op, w.p, w.pT, w.y, batch, s)));
         SCT_TRY((launch_adj<TM, T>(op, w.y, w.p, w.q, alpha, lambda, sigma, w.part_adj, batch, s)));
-        k_cg_alpha<<<unsigned(batch), 256, 0, s>>>(w.part_adj, op.n_ag, w.sc, rtol, it);
-        SCT_TRY(check_launch("k_cg_alpha"));
-        k_cg_xr<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(x, w.r, w.p, w.q, w.sc,
-                                                                               w.part_vec, op.nn);
+        k_cg_xr<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
+            x, w.r, w.p, w.q, w.part_adj, adj_blocks(op), cur, stp, rtol, w.part_vec, op.nn);
         SCT_TRY(check_launch("k_cg_xr"));
-        k_cg_beta<<<unsigned(batch), 256, 0, s>>>(w.part_vec, vb, w.sc);
-        SCT_TRY(check_launch("k_cg_beta"));
-        k_cg_p<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, w.sc, op.n, op.nn);
+        k_cg_p<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, w.part_vec, vb, cur, stp, nxt, it, op.n, op.nn);
         SCT_TRY(check_launch("k_cg_p"));
     }
     return RADON_OK;
+}
+
+static const CgState *final_state(const CgState *st, int n_iter, int batch)
+{
+    return st + int64_t(n_iter & 1) * batch;
 }
 
 // w.q = A x (uses w.pT and w.y as temporaries)
@@ -535,7 +550,8 @@ static int cg_typed(const Op &op, double alpha, double lambda, double sigma, con
     SCT_TRY((cg_run<TM, T>(op, alpha, lambda, sigma, x, batch, n_iter, rtol, w, nullptr, nullptr,
                            nullptr, s)));
     if (info) {
-        k_cg_info<<<unsigned((batch + 63) / 64), 64, 0, s>>>(w.sc, info, batch);
+        k_cg_info<<<unsigned((batch + 63) / 64), 64, 0, s>>>(final_state(w.st, n_iter, batch), info,
+                                                             batch);
         SCT_TRY(check_launch("k_cg_info"));
     }
     return RADON_OK;
@@ -582,7 +598,8 @@ static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, voi
         k_sb_carry<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
             w.cg.r, w.dwx, w.dwy, T(lambda), w.sbs, op.n, op.nn);
         SCT_TRY(check_launch("k_sb_carry"));
-        k_sb_update<<<unsigned(batch), 256, 0, s>>>(w.part, vb, w.sbs, w.cg.sc, P.tol);
+        k_sb_update<<<unsigned(batch), 256, 0, s>>>(w.part, vb, w.sbs,
+                                                    final_state(w.cg.st, P.n_cg, batch), P.tol);
         SCT_TRY(check_launch("k_sb_update"));
     }
     if (info) {
