@@ -51,10 +51,57 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-applies", type=int, default=0,
                     help="oracle normal applies to time (0: sized to ~15 s)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the fused multi-image legs")
     ap.add_argument("--profile", action="store_true",
                     help="profiler mode: 20 fwd, 20 adj, 20 normal applies, one CG(20) solve and a "
                          "plain 1 GiB device copy (counter calibration), then exit")
     return ap.parse_args()
+
+
+def bench_batched(sct, W, torch, dev, vdt):
+    """Fused multi-image normal_apply (every matrix load shared by a chunk of up
+    to 16 images) against the same images applied one at a time."""
+    out = {}
+    for name in ("grad_16x512_f32", "volume_64x1024_f32"):
+        w = W.WORKLOADS[name]
+        op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                         device=dev)
+        B = w.batch
+        X = torch.randn((B, op.nn), dtype=vdt, device=dev)
+        O = torch.empty_like(X)
+        o1 = torch.empty((1, op.nn), dtype=vdt, device=dev)
+        singles = [X[b:b + 1] for b in range(B)]
+        alpha, lam = (w.alpha, w.lam) if w.lam > 0 else (w.extra["tau"] * w.alpha, 0.0)
+        sigma = 0.0 if w.lam > 0 else 1.0
+
+        def fused():
+            op.normal(X, alpha, lam, sigma, out=O)
+
+        def looped():
+            for xb in singles:
+                op.normal(xb, alpha, lam, sigma, out=o1)
+
+        def t(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps / 1e3
+
+        tf, tl = t(fused, 5), t(looped, 2)
+        out[name] = {"batch": B, "n": w.n, "measured_angles": w.n_meas, "bins": w.n_bins,
+                     "nnz": op.info.nnz, "fused_ms": round(tf * 1e3, 3),
+                     "per_image_loop_ms": round(tl * 1e3, 3), "speedup": round(tl / tf, 2),
+                     "image_applies_per_s": round(B / tf, 1)}
+        print(f"# batched {name}: fused {tf * 1e3:.2f} ms vs loop {tl * 1e3:.2f} ms "
+              f"({tl / tf:.2f}x)", file=sys.stderr, flush=True)
+        del op
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -177,6 +224,9 @@ def main():
         "build_s": round(build_s, 3),
         "roofline": roofline,
     }
+
+    if not args.no_batched:
+        result["batched"] = bench_batched(sct, W, torch, dev, vdt)
 
     if not args.no_verify or not args.no_cpu:
         import oracle

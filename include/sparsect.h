@@ -237,6 +237,27 @@ int split_bregman_tv(const radon_op *op, const radon_sb_params *params, const vo
                      radon_sb_info *info, void *stream);
 
 /*
+ * Launch tuning of an operator (not part of the method: it only changes how
+ * the products are scheduled; the waves-per-item counts split each sum
+ * differently, so results change at the rounding level; the fused chunk
+ * sizes change no summation order).
+ *   fwd_waves  waves per ray bundle in the forward product: 2 or 4;
+ *   adj_waves  waves per 8x8 tile in the adjoint: 1, 2 or 4 (0: chosen from
+ *              the number of measured angles);
+ *   fwd_rhs, adj_rhs  largest number of images (right-hand sides) that share
+ *              each matrix load in a fused multi-image product: 1, 4, 8, 16.
+ * radon_set_tuning must not overlap with enqueued work on the operator.
+ * The binding's autotuner times the candidates and caches the best per
+ * geometry (see paper_1705_07497_amd.autotune).
+ */
+typedef struct {
+    int32_t fwd_waves, adj_waves, fwd_rhs, adj_rhs;
+} radon_tuning;
+
+int radon_set_tuning(radon_op *op, const radon_tuning *t);
+int radon_get_tuning(const radon_op *op, radon_tuning *out);
+
+/*
  * radon_export_csr -- copy the CSR of MR to host memory (synchronous; for
  * checks and external tools).  row_ptr int64[n_meas_rays+1], col int32[nnz],
  * val double[nnz] (entries widened from the operator dtype), each NULL to

@@ -58,6 +58,14 @@ class SbParams(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("fwd_waves", ctypes.c_int32), ("adj_waves", ctypes.c_int32),
+                ("fwd_rhs", ctypes.c_int32), ("adj_rhs", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class SbInfo(ctypes.Structure):
     _fields_ = [("outer", ctypes.c_int32), ("breakdowns", ctypes.c_int32),
                 ("upd_b_first", ctypes.c_double), ("upd_b", ctypes.c_double),
@@ -80,6 +88,8 @@ SIGNATURES = {
                                 ctypes.c_int64, _vp, _vp]),
     "split_bregman_tv": (ctypes.c_int, [_vp, ctypes.POINTER(SbParams), _vp, _vp, ctypes.c_int32, _vp,
                                         ctypes.c_int64, _vp, _vp]),
+    "radon_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "radon_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "radon_export_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "radon_export_adj": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
 }
@@ -133,7 +143,7 @@ class RadonOp:
     vectors and multiply-adds."""
 
     def __init__(self, n: int, n_angles: int, n_bins: int, measured=None, dtype=None, device=None,
-                 vec_dtype=None):
+                 vec_dtype=None, tuning: str = "cache"):
         torch = _torch()
         if not torch.cuda.is_available():
             raise SparsectError("no GPU visible: libsparsect runs on AMD Instinct GPUs only")
@@ -170,6 +180,29 @@ class RadonOp:
         self.rows = inf.n_meas_rays
         self.nn = inf.n_pixels
         self._ws = {}
+        if tuning == "cache":
+            from . import autotune
+            autotune.apply_cached(self)
+        elif tuning == "tune":
+            from . import autotune
+            autotune.autotune(self)
+        elif tuning != "default":
+            raise SparsectError("tuning must be 'cache', 'tune' or 'default'")
+
+    @property
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().radon_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    @tuning.setter
+    def tuning(self, d: dict) -> None:
+        t = Tuning()
+        _check(lib().radon_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in d.items():
+            setattr(t, k, int(v))
+        _torch().cuda.synchronize(self.device)
+        _check(lib().radon_set_tuning(self._h, ctypes.byref(t)))
 
     def __del__(self):
         h = getattr(self, "_h", None)

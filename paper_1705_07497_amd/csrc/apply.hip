@@ -66,18 +66,22 @@ __device__ inline V stream_load(const V *p)
 // same image line at neighbouring positions.  Wave w covers its share of the
 // bundle's quads; partial sums are combined over q with shuffles and over the
 // waves in LDS, in a fixed order.
-template <class TM, class TV, int W>
+// Several right-hand sides: blockIdx.y selects a chunk of up to BC images that
+// share every matrix load (the fused multi-RHS product), one accumulator each.
+template <class TM, class TV, int W, int BC>
 __global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb,
                                                 const int32_t *__restrict__ order, int64_t n_order,
                                                 const uint16_t *__restrict__ idx,
                                                 const TM *__restrict__ v0, const TM *__restrict__ v1,
                                                 const TV *__restrict__ x, const TV *__restrict__ xT,
-                                                TV *__restrict__ y, int n, int64_t nn, int64_t rows)
+                                                TV *__restrict__ y, int n, int64_t nn, int64_t rows,
+                                                int batch)
 {
     using Q = typename Quad<TM>::type;
     using P = typename PairU<TV>::type;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t bat = blockIdx.y;
+    const int b0 = int(blockIdx.y) * BC;
+    const int nbc = min(BC, batch - b0);
     const int r = lane & 15, q = lane >> 4;
     // persistent: the grid is a multiple of 8 blocks, so block i stays on XCD
     // i % 8 and order[] keeps one gather class per XCD
@@ -85,13 +89,15 @@ __global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb
         const int B = order[o];
         if (B < 0) continue;           // padding entry (uniform per block)
         const FwdBundle d = fb[B];
-        const TV *__restrict__ img = (d.horiz ? xT : x) + bat * nn;
+        const TV *__restrict__ img = (d.horiz ? xT : x) + int64_t(b0) * nn;
         const int nq = d.nrows >> 2;
         const int s0 = (nq * wave) / W, s1 = (nq * (wave + 1)) / W;
         const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
         const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
         const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
-        TV acc = TV(0);
+        TV acc[BC];
+#pragma unroll
+        for (int c = 0; c < BC; ++c) acc[c] = TV(0);
 #pragma unroll 2
         for (int tq = s0 + q; tq < s1; tq += 4) {
             const int e = tq * kFwdLanes + r;
@@ -101,34 +107,53 @@ __global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int m = min(d.m0 + 4 * tq + k, n - 1);
-                const TV *__restrict__ line = img + int64_t(m) * n;
                 const int i0 = i4[k];
-                if (n >= 2) {
-                    // one load for both pixels; a slot at the last column has no
-                    // second pixel (weight 0), so the pair starts at n-2 there
-                    const int ic = i0 < n - 1 ? i0 : n - 2;
-                    const P pr = *reinterpret_cast<const P *>(line + ic);
-                    acc = fma(TV(a4[k]), i0 == ic ? pr.x : pr.y, acc);
-                    acc = fma(TV(b4[k]), pr.y, acc);
-                } else {
-                    acc = fma(TV(a4[k]), line[0], acc);
+                // one load for both pixels; a slot at the last column has no
+                // second pixel (weight 0), so the pair starts at n-2 there
+                const int ic = i0 < n - 1 ? i0 : (n >= 2 ? n - 2 : 0);
+                const int64_t at = int64_t(m) * n + ic;
+#pragma unroll
+                for (int c = 0; c < BC; ++c) {
+                    if (BC == 1 || c < nbc) {
+                        const TV *__restrict__ line = img + int64_t(c) * nn;
+                        if (n >= 2) {
+                            const P pr = *reinterpret_cast<const P *>(line + at);
+                            acc[c] = fma(TV(a4[k]), i0 == ic ? pr.x : pr.y, acc[c]);
+                            acc[c] = fma(TV(b4[k]), pr.y, acc[c]);
+                        } else {
+                            acc[c] = fma(TV(a4[k]), line[0], acc[c]);
+                        }
+                    }
                 }
             }
         }
-        acc += __shfl_xor(acc, 16);
-        acc += __shfl_xor(acc, 32);
+#pragma unroll
+        for (int c = 0; c < BC; ++c) {
+            acc[c] += __shfl_xor(acc[c], 16);
+            acc[c] += __shfl_xor(acc[c], 32);
+        }
         if constexpr (W > 1) {
-            __shared__ TV red[W][kFwdLanes];
-            if (q == 0) red[wave][r] = acc;
+            __shared__ TV red[W][BC][kFwdLanes];
+            if (q == 0) {
+#pragma unroll
+                for (int c = 0; c < BC; ++c) red[wave][c][r] = acc[c];
+            }
             __syncthreads();
             if (wave == 0) {
-                acc = red[0][r];
 #pragma unroll
-                for (int w = 1; w < W; ++w) acc += red[w][r];
+                for (int c = 0; c < BC; ++c) {
+                    acc[c] = red[0][c][r];
+#pragma unroll
+                    for (int w = 1; w < W; ++w) acc[c] += red[w][c][r];
+                }
             }
             __syncthreads();   // red is reused by the next bundle
         }
-        if (wave == 0 && q == 0 && r < d.nrays) y[bat * rows + d.ray0 + r] = acc;
+        if (wave == 0 && q == 0 && r < d.nrays) {
+#pragma unroll
+            for (int c = 0; c < BC; ++c)
+                if (c < nbc) y[int64_t(b0 + c) * rows + d.ray0 + r] = acc[c];
+        }
     }
 }
 
@@ -151,16 +176,10 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// Adjoint: one workgroup of W waves per 8x8 pixel tile (persistent loop over
-// tiles).  Wave w sums its share of the measured-angle quads for the tile's
-// 64 pixels.  Per quad it stages the tile's sinogram band (16 bins from the
-// tile's base bin, for each of the 4 angles: exactly one 64-lane load) in LDS
-// and reads the pixel's two bins from there, so the vector-memory pipeline
-// only carries the three matrix streams and the band.  The wave shares are
-// added in wave order, and wave 0 applies the epilogue
-// out = alpha*acc + lambda*(K^T K x) + sigma*x and the FP64 partial <x, out>.
+// Single right-hand side version of k_adj below (kept separate: the fused
+// multi-RHS form compiles to a slower loop for one image).
 template <class TM, class T, int W>
-__global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
+__global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel,
                                                 const uint16_t *__restrict__ base,
                                                 const TM *__restrict__ v0, const TM *__restrict__ v1,
                                                 int64_t n_ag, int n_meas, int n_aq, int nb,
@@ -236,6 +255,119 @@ __global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
     }
 }
 
+// Adjoint: one workgroup of W waves per 8x8 pixel tile (persistent loop over
+// tiles).  Wave w sums its share of the measured-angle quads for the tile's
+// 64 pixels.  Per quad it stages the tile's sinogram band (16 bins from the
+// tile's base bin, for each of the 4 angles: exactly one 64-lane load) in LDS
+// and reads the pixel's two bins from there, so the vector-memory pipeline
+// only carries the three matrix streams and the band.  The wave shares are
+// added in wave order, and wave 0 applies the epilogue
+// out = alpha*acc + lambda*(K^T K x) + sigma*x and the FP64 partial <x, out>.
+// Several right-hand sides: blockIdx.y selects a chunk of up to BC sinograms
+// that share every matrix load; each gets its own band and accumulator.
+template <class TM, class T, int W, int BC>
+__global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
+                                                const uint16_t *__restrict__ base,
+                                                const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                int64_t n_ag, int n_meas, int n_aq, int nb,
+                                                const T *__restrict__ y, const T *__restrict__ x,
+                                                T *__restrict__ out, T alpha, T lambda, T sigma,
+                                                double *__restrict__ part, int n, int tiles,
+                                                int64_t nn, int64_t rows, int batch)
+{
+    using Q = typename Quad<TM>::type;
+    __shared__ T band[W][BC][4 * kAdjBand];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b0 = int(blockIdx.y) * BC;
+    const int nbc = min(BC, batch - b0);
+    const T *__restrict__ yb = y + int64_t(b0) * rows;
+    const int q0 = (n_aq * wave) / W, q1 = (n_aq * (wave + 1)) / W;
+    const uint32_t *__restrict__ Rl = reinterpret_cast<const uint32_t *>(rel);
+    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0);
+    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1);
+    const int kk = lane >> 4, ee = lane & 15;   // this lane's band element
+    double dsum[BC];                            // this block's share of <x, out>
+#pragma unroll
+    for (int c = 0; c < BC; ++c) dsum[c] = 0.0;
+    for (int64_t g = blockIdx.x; g < n_ag; g += gridDim.x) {
+        T acc[BC];
+#pragma unroll
+        for (int c = 0; c < BC; ++c) acc[c] = T(0);
+#pragma unroll 2
+        for (int aq = q0; aq < q1; ++aq) {
+            const int64_t gq = g * n_aq + aq;
+            const int a_band = min(4 * aq + kk, n_meas - 1);
+            const int64_t band_at = int64_t(a_band) * nb + min(int(base[gq * 4 + kk]) + ee, nb - 1);
+            T yv[BC];
+#pragma unroll
+            for (int c = 0; c < BC; ++c)
+                if (BC == 1 || c < nbc) yv[c] = yb[int64_t(c) * rows + band_at];
+            const int64_t e = gq * kAdjLanes + lane;
+            const uint32_t r4 = stream_load(Rl + e);
+            const Q a4 = stream_load(A + e);
+            const Q c4 = stream_load(Bv + e);
+#pragma unroll
+            for (int c = 0; c < BC; ++c)
+                if (BC == 1 || c < nbc) band[wave][c][lane] = yv[c];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int rb = k * kAdjBand + int((r4 >> (8 * k)) & 0xffu);
+#pragma unroll
+                for (int c = 0; c < BC; ++c) {
+                    if (BC == 1 || c < nbc) {
+                        acc[c] = fma(T(a4[k]), band[wave][c][rb], acc[c]);
+                        acc[c] = fma(T(c4[k]), band[wave][c][rb + 1], acc[c]);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if constexpr (W > 1) {
+            __shared__ T red[W][BC][64];
+#pragma unroll
+            for (int c = 0; c < BC; ++c) red[wave][c][lane] = acc[c];
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int c = 0; c < BC; ++c) {
+                    acc[c] = red[0][c][lane];
+#pragma unroll
+                    for (int w = 1; w < W; ++w) acc[c] += red[w][c][lane];
+                }
+            }
+            __syncthreads();   // red is reused by the next tile
+        }
+        if (wave == 0) {
+            const int iy = int(g / tiles) * 8 + (lane >> 3), ix = int(g % tiles) * 8 + (lane & 7);
+            const int64_t j = int64_t(iy) * n + ix;
+            if (iy < n && ix < n) {
+#pragma unroll
+                for (int c = 0; c < BC; ++c) {
+                    if (BC == 1 || c < nbc) {
+                        T o = alpha * acc[c];
+                        if (x) {
+                            const T *__restrict__ xb = x + int64_t(b0 + c) * nn;
+                            const T xj = xb[j];
+                            if (lambda != T(0)) o += lambda * ktk_at(xb, j, n, xj);
+                            if (sigma != T(0)) o += sigma * xj;
+                            dsum[c] += double(xj) * double(o);
+                        }
+                        out[int64_t(b0 + c) * nn + j] = o;
+                    }
+                }
+            }
+        }
+    }
+    if (part && wave == 0) {
+#pragma unroll
+        for (int c = 0; c < BC; ++c) {
+            const double v = wave_sum(dsum[c]);
+            if (c < nbc && lane == 0) part[int64_t(b0 + c) * gridDim.x + blockIdx.x] = v;
+        }
+    }
+}
+
 // dst[b] = sum_i part[b][i], in a fixed order (one block per b).
 __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part,
                                                       int64_t count, double *__restrict__ dst)
@@ -272,39 +404,92 @@ int launch_transpose(const Op &op, const TV *x, TV *xT, int batch, hipStream_t s
     return check_launch("k_transpose");
 }
 
+// Right-hand sides per fused chunk: the largest supported chunk that fits the
+// batch and the operator's tuning limit.
+static int rhs_chunk(int batch, int limit)
+{
+    for (int c : {16, 8, 4})
+        if (c <= batch && c <= limit) return c;
+    return 1;
+}
+
+template <class TM, class TV, int W, int BC>
+static void fwd_wbc(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
+{
+    const int64_t g = op.n_order < kPersistentBlocks ? op.n_order : kPersistentBlocks;
+    const unsigned chunks = unsigned((batch + BC - 1) / BC);
+    k_fwd<TM, TV, W, BC><<<dim3(unsigned(g), chunks), 64 * W, 0, s>>>(
+        op.fb, op.fb_order, op.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
+        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, y, op.n, op.nn, op.rows, batch);
+}
+
+template <class TM, class TV, int BC>
+static void fwd_bc(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
+{
+    if (op.tune.fwd_waves == 2) fwd_wbc<TM, TV, 2, BC>(op, x, xT, y, batch, s);
+    else fwd_wbc<TM, TV, 4, BC>(op, x, xT, y, batch, s);
+}
+
 template <class TM, class TV>
 int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
 {
     SCT_TRY(check_grid_y(batch));
-    constexpr int W = 4;
-    const int64_t g = op.n_order < kPersistentBlocks ? op.n_order : kPersistentBlocks;
-    k_fwd<TM, TV, W><<<dim3(unsigned(g), unsigned(batch)), 64 * W, 0, s>>>(
-        op.fb, op.fb_order, op.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
-        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, y, op.n, op.nn, op.rows);
+    switch (rhs_chunk(batch, op.tune.fwd_rhs)) {
+    case 16: fwd_bc<TM, TV, 16>(op, x, xT, y, batch, s); break;
+    case 8: fwd_bc<TM, TV, 8>(op, x, xT, y, batch, s); break;
+    case 4: fwd_bc<TM, TV, 4>(op, x, xT, y, batch, s); break;
+    default: fwd_bc<TM, TV, 1>(op, x, xT, y, batch, s); break;
+    }
     return check_launch("k_fwd");
 }
 
 int adj_blocks(const Op &op) { return int(op.n_ag < kPersistentBlocks ? op.n_ag : kPersistentBlocks); }
+
+static int adj_waves(const Op &op)
+{
+    if (op.tune.adj_waves == 1 || op.tune.adj_waves == 2 || op.tune.adj_waves == 4) return op.tune.adj_waves;
+    return op.n_meas >= 128 ? 4 : (op.n_meas >= 48 ? 2 : 1);
+}
+
+template <class TM, class TV, int W, int BC>
+static void adj_wbc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV la, TV si,
+                    double *part, int batch, hipStream_t s)
+{
+    const dim3 grid(unsigned(adj_blocks(op)), unsigned((batch + BC - 1) / BC));
+    const TM *a0 = static_cast<const TM *>(op.a_v0), *a1 = static_cast<const TM *>(op.a_v1);
+    if constexpr (BC == 1)
+        k_adj1<TM, TV, W><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.n_ag, op.n_meas,
+                                                 op.n_aq, op.n_bins, y, x, out, al, la, si, part,
+                                                 op.n, op.tiles, op.nn, op.rows);
+    else
+        k_adj<TM, TV, W, BC><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.n_ag, op.n_meas,
+                                                    op.n_aq, op.n_bins, y, x, out, al, la, si, part,
+                                                    op.n, op.tiles, op.nn, op.rows, batch);
+}
+
+template <class TM, class TV, int BC>
+static void adj_bc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV la, TV si,
+                   double *part, int batch, hipStream_t s)
+{
+    switch (adj_waves(op)) {
+    case 4: adj_wbc<TM, TV, 4, BC>(op, y, x, out, al, la, si, part, batch, s); break;
+    case 2: adj_wbc<TM, TV, 2, BC>(op, y, x, out, al, la, si, part, batch, s); break;
+    default: adj_wbc<TM, TV, 1, BC>(op, y, x, out, al, la, si, part, batch, s); break;
+    }
+}
 
 template <class TM, class TV>
 int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, double lambda,
                double sigma, double *part, int batch, hipStream_t s)
 {
     SCT_TRY(check_grid_y(batch));
-    const dim3 grid(unsigned(adj_blocks(op)), unsigned(batch));
-    const uint8_t *rel = op.a_rel;
-    const uint16_t *bs = op.a_base;
-    const TM *a0 = static_cast<const TM *>(op.a_v0), *a1 = static_cast<const TM *>(op.a_v1);
     const TV al = TV(alpha), la = TV(lambda), si = TV(sigma);
-    if (op.n_meas >= 128)
-        k_adj<TM, TV, 4><<<grid, 256, 0, s>>>(rel, bs, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y,
-                                              x, out, al, la, si, part, op.n, op.tiles, op.nn, op.rows);
-    else if (op.n_meas >= 48)
-        k_adj<TM, TV, 2><<<grid, 128, 0, s>>>(rel, bs, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y,
-                                              x, out, al, la, si, part, op.n, op.tiles, op.nn, op.rows);
-    else
-        k_adj<TM, TV, 1><<<grid, 64, 0, s>>>(rel, bs, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins, y,
-                                             x, out, al, la, si, part, op.n, op.tiles, op.nn, op.rows);
+    switch (rhs_chunk(batch, op.tune.adj_rhs)) {
+    case 16: adj_bc<TM, TV, 16>(op, y, x, out, al, la, si, part, batch, s); break;
+    case 8: adj_bc<TM, TV, 8>(op, y, x, out, al, la, si, part, batch, s); break;
+    case 4: adj_bc<TM, TV, 4>(op, y, x, out, al, la, si, part, batch, s); break;
+    default: adj_bc<TM, TV, 1>(op, y, x, out, al, la, si, part, batch, s); break;
+    }
     return check_launch("k_adj");
 }
 
@@ -431,4 +616,29 @@ extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, doub
         if (dot_out) SCT_TRY(launch_sum_partials(part, adj_blocks(op), dot_out, batch, s));
         return RADON_OK;
     });
+}
+
+extern "C" int radon_set_tuning(radon_op *p, const radon_tuning *t)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    if (!t) return set_error(RADON_EINVAL, "tuning is NULL");
+    if (t->fwd_waves != 2 && t->fwd_waves != 4)
+        return set_error(RADON_EINVAL, "fwd_waves must be 2 or 4 (got %d)", t->fwd_waves);
+    if (t->adj_waves != 0 && t->adj_waves != 1 && t->adj_waves != 2 && t->adj_waves != 4)
+        return set_error(RADON_EINVAL, "adj_waves must be 0, 1, 2 or 4 (got %d)", t->adj_waves);
+    for (int v : {t->fwd_rhs, t->adj_rhs})
+        if (v != 1 && v != 4 && v != 8 && v != 16)
+            return set_error(RADON_EINVAL, "fwd_rhs and adj_rhs must be 1, 4, 8 or 16 (got %d)", v);
+    as_op(p)->tune = *t;
+    return RADON_OK;
+}
+
+extern "C" int radon_get_tuning(const radon_op *p, radon_tuning *out)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    *out = as_op(p)->tune;
+    return RADON_OK;
 }

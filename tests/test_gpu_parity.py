@@ -125,6 +125,45 @@ def test_adjoint_identity_fp64():
     assert abs(Rx @ y - x @ Rty) <= 1e-12 * np.linalg.norm(Rx) * np.linalg.norm(y)
 
 
+@pytest.mark.parametrize("batch", [4, 8, 16, 21])
+@pytest.mark.parametrize("mode", ["mixed", "f32"])
+def test_fused_batch_products_equal_single_image(batch, mode):
+    """Chunks of 4/8/16 right-hand sides share every matrix load; each image's
+    result must be bitwise the single-image result (same summation order)."""
+    n, na = 40, 30
+    op = make_op(n, na, W.n_bins_for(n), W.angle_mask(na, 2), mode)
+    dt = MODES[mode][1]
+    rng = np.random.default_rng(batch)
+    X = to_dev(rng.standard_normal((batch, n * n)), dt)
+    Yb = op.fwd(X)
+    Ab, Db = op.normal(X, 2.0, 0.5, 0.25, dot=True)
+    Tb = op.adj(Yb)
+    for b in (0, batch // 2, batch - 1):
+        xb = X[b:b + 1].contiguous()
+        assert torch.equal(op.fwd(xb)[0], Yb[b])
+        a1, d1 = op.normal(xb, 2.0, 0.5, 0.25, dot=True)
+        assert torch.equal(a1[0], Ab[b]) and torch.equal(d1[0], Db[b])
+        assert torch.equal(op.adj(Yb[b:b + 1].contiguous())[0], Tb[b])
+
+
+def test_fused_batch_split_bregman_and_cg():
+    w, ref, mu, f = workload_problem("small_64_f64")
+    op = make_op(w.n, w.n_angles, w.n_bins, w.mask, "mixed")
+    rng = np.random.default_rng(3)
+    F = np.stack([f * (1 + 0.1 * k) + rng.standard_normal(f.size) for k in range(6)])
+    Fd = to_dev(F, F64)
+    U, info = op.sb(Fd, w.alpha, w.lam, 5, 5)
+    X, cinfo = op.cg(Fd[:, :0].new_zeros((6, op.nn)) + 1.0, w.alpha, w.lam, 0.5, n_iter=7)
+    for b in (0, 5):
+        u1, _ = op.sb(Fd[b:b + 1].contiguous(), w.alpha, w.lam, 5, 5, ws_key="single")
+        assert torch.equal(u1[0], U[b])
+    uo = ref.sb(F[5], w.alpha, w.lam, 5, 5)[0]
+    assert rel_l2(host(U[5]), uo) <= 1e-5
+    assert [d["outer"] for d in sct.decode_sb_info(info)] == [5] * 6
+    x1, _ = op.cg(torch.ones((1, op.nn), dtype=F64, device="cuda"), w.alpha, w.lam, 0.5, n_iter=7)
+    assert torch.equal(x1[0], X[3])
+
+
 def test_batch_equals_per_slice_and_is_deterministic():
     n, na, nb = 48, 20, W.n_bins_for(48)
     op = sct.RadonOp(n, na, nb, W.angle_mask(na, 2), dtype=F32)
@@ -310,3 +349,31 @@ def test_workspace_and_argument_errors_on_gpu():
         op.fwd(torch.zeros(255, dtype=F32, device="cuda"))
     with pytest.raises(sct.SparsectError):
         op.fwd(torch.zeros(256, dtype=F64, device="cuda"))
+
+
+def test_tuning_setter_autotune_and_parity(tmp_path, monkeypatch):
+    monkeypatch.setenv("SPARSECT_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_1705_07497_amd import autotune
+    n, na = 48, 30
+    mask = W.angle_mask(na, 2)
+    ref = oracle.OracleOp(n, na, W.n_bins_for(n), mask)
+    op = make_op(n, na, W.n_bins_for(n), mask, "mixed")
+    assert op.tuning == {"fwd_waves": 4, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8}
+    with pytest.raises(sct.SparsectError):
+        op.tuning = {"fwd_waves": 3}
+    with pytest.raises(sct.SparsectError):
+        op.tuning = {"adj_rhs": 5}
+    x = rounded(np.random.default_rng(1).standard_normal((6, n * n)), F64)
+    want = [ref.normal(x[b], 1.0, 0.5, 0.1) for b in range(6)]
+    for fw in (2, 4):
+        for aw in (1, 2, 4):
+            for fr, ar in ((1, 1), (4, 8), (8, 4)):
+                op.tuning = {"fwd_waves": fw, "adj_waves": aw, "fwd_rhs": fr, "adj_rhs": ar}
+                got = host(op.normal(to_dev(x, F64), 1.0, 0.5, 0.1))
+                for b in range(6):
+                    assert rel_l2(got[b], want[b]) <= 1e-5, (fw, aw, fr, ar, b)
+    entry = autotune.autotune(op, batch=8, reps=2)
+    assert set(entry["tuning"]) == set(autotune.DEFAULT)
+    assert op.tuning == entry["tuning"]
+    op2 = make_op(n, na, W.n_bins_for(n), mask, "mixed")   # picks the cached entry up
+    assert op2.tuning == entry["tuning"]
