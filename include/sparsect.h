@@ -237,6 +237,54 @@ int split_bregman_tv(const radon_op *op, const radon_sb_params *params, const vo
                      radon_sb_info *info, void *stream);
 
 /*
+ * Unrolled CG with reverse mode, for gradients through a fixed number of CG
+ * iterations on A = alpha R^T M^T M R + lambda K^T K + sigma I (the resolvent
+ * system eq:PD_resolve of Section 2 with alpha <- tau*alpha, lambda = 0,
+ * sigma = 1; any SPD choice works).  x_n = CG_n(rhs) from x_0 = 0 is a
+ * nonlinear function of rhs (the step lengths and the beta_k depend on it);
+ * cg_unrolled_vjp returns (d x_n / d rhs)^T gx exactly for the iterations the
+ * forward ran, by reverse-mode differentiation of each Hestenes-Stiefel
+ * update.  The forward keeps (r, p, rho) every `ckpt` iterations in a tape;
+ * the reverse replays each ckpt-long segment from its checkpoint with the
+ * same kernels (bitwise the forward's iterates) before sweeping back through
+ * it, so memory is n_iter/ckpt checkpoints plus one segment of records.
+ * An iteration that stopped (rho == 0 or a breakdown) passes the adjoints
+ * through unchanged.
+ *
+ * radon_unrolled_sizes -- bytes of the tape (tape_bytes), of the forward's
+ * workspace (ws_fwd_bytes) and of the reverse's workspace (ws_vjp_bytes) for
+ * these sizes; each pointer may be NULL.
+ */
+int radon_unrolled_sizes(const radon_op *op, int32_t n_iter, int32_t ckpt, int32_t batch,
+                         int64_t *tape_bytes, int64_t *ws_fwd_bytes, int64_t *ws_vjp_bytes);
+
+/*
+ * cg_unrolled -- x = CG_n(rhs) from x_0 = 0, no tolerance stop; writes the tape.
+ *   rhs, x  device [batch][n*n], operator dtype; x must not alias rhs.
+ *   tape    device, tape_bytes >= radon_unrolled_sizes' tape_bytes; owned by
+ *           the caller, read by cg_unrolled_vjp with the same op, alpha,
+ *           lambda, sigma, batch, n_iter and ckpt.
+ *   ws      device, radon_unrolled_sizes' ws_fwd_bytes; scratch.
+ */
+int cg_unrolled(const radon_op *op, double alpha, double lambda, double sigma,
+                const void *rhs, void *x, int32_t batch, int32_t n_iter, int32_t ckpt,
+                void *tape, int64_t tape_bytes, void *ws, int64_t ws_bytes, void *stream);
+
+/*
+ * cg_unrolled_vjp -- grhs = (d x_n / d rhs)^T gx for the solve cg_unrolled
+ * recorded in `tape` (rhs itself is the tape's first checkpoint).
+ *   gx      device [batch][n*n]: dL/dx_n.
+ *   grhs    device [batch][n*n]: dL/drhs, written; may alias gx.
+ *   ws      device, radon_unrolled_sizes' ws_vjp_bytes; scratch.
+ * Errors: RADON_EWORKSPACE for a short tape or workspace, RADON_EINVAL for
+ * n_iter < 0, ckpt < 1 or NULL vectors.
+ */
+int cg_unrolled_vjp(const radon_op *op, double alpha, double lambda, double sigma,
+                    const void *tape, int64_t tape_bytes, const void *gx, void *grhs,
+                    int32_t batch, int32_t n_iter, int32_t ckpt, void *ws, int64_t ws_bytes,
+                    void *stream);
+
+/*
  * Launch tuning of an operator (not part of the method: it only changes how
  * the products are scheduled; the waves-per-item counts split each sum
  * differently, so results change at the rounding level; the fused chunk

@@ -184,13 +184,20 @@ def gradT(n: int, vx: np.ndarray, vy: np.ndarray) -> np.ndarray:
 class OracleOp:
     """MR and (MR)^T for one geometry; measured rays in ascending angle order."""
 
-    def __init__(self, n: int, n_angles: int, n_bins: int, measured=None):
+    def __init__(self, n: int, n_angles: int, n_bins: int, measured=None, values: str = "f64"):
+        """values="f32" rounds every matrix entry once to binary32 (and back to
+        float64): the matrix of an operator that stores its values in single
+        precision, everything else still FP64."""
         self.n, self.n_angles, self.n_bins = n, n_angles, n_bins
         if measured is None:
             measured = np.ones(n_angles, dtype=np.uint8)
         self.measured = np.asarray(measured, dtype=np.uint8)
         self.angles = np.nonzero(self.measured)[0].astype(np.int32)
         self.MR = build_R(n, n_angles, n_bins, self.angles)
+        if values == "f32":
+            self.MR.v = self.MR.v.astype(np.float32).astype(np.float64)
+        elif values != "f64":
+            raise ValueError("values must be 'f64' or 'f32'")
         self.MRT = self.MR.transpose()
         self.rows = self.MR.rows
         self._s = _OraOp(n, self.rows, _p(self.MR.rp, _i64p), _p(self.MR.ci, _i32p),

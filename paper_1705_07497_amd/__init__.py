@@ -92,6 +92,16 @@ SIGNATURES = {
     "radon_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "radon_export_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "radon_export_adj": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "radon_unrolled_sizes": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int64)]),
+    "cg_unrolled": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
+                                   _vp, ctypes.c_int64, _vp]),
+    "cg_unrolled_vjp": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp,
+                                       ctypes.c_int64, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
 }
 
 _lib = None
@@ -329,6 +339,45 @@ class RadonOp:
         _check(lib().split_bregman_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b,
                                       self._p(ws), nb, self._p(info), self._stream()))
         return mu, info
+
+    def unrolled_sizes(self, n_iter: int, ckpt: int, batch: int) -> tuple[int, int, int]:
+        """(tape, forward workspace, reverse workspace) bytes of an unrolled CG."""
+        t, wf, wv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().radon_unrolled_sizes(self._h, int(n_iter), int(ckpt), int(batch), ctypes.byref(t),
+                                          ctypes.byref(wf), ctypes.byref(wv)))
+        return int(t.value), int(wf.value), int(wv.value)
+
+    def cg_unrolled(self, rhs, alpha: float, lam: float, sigma: float, n_iter: int, ckpt: int):
+        """x = CG_n(rhs) from 0 with a checkpoint tape; returns (x, tape)."""
+        torch = _torch()
+        b = self._img(rhs, "rhs")
+        tb, wf, _ = self.unrolled_sizes(n_iter, ckpt, b)
+        tape = torch.empty(max(tb, 1), dtype=torch.uint8, device=self.device)
+        x = torch.empty((b, self.nn), dtype=self.dtype, device=self.device)
+        ws, nb = self.workspace(WS_CG, b)
+        assert nb >= wf
+        _check(lib().cg_unrolled(self._h, float(alpha), float(lam), float(sigma), self._p(rhs),
+                                 self._p(x), b, int(n_iter), int(ckpt), self._p(tape), tb,
+                                 self._p(ws), nb, self._stream()))
+        return x, tape
+
+    def cg_unrolled_vjp(self, tape, gx, alpha: float, lam: float, sigma: float, n_iter: int,
+                        ckpt: int):
+        """(d x_n / d rhs)^T gx for the solve recorded in tape."""
+        torch = _torch()
+        b = self._img(gx, "gx")
+        tb, _, wv = self.unrolled_sizes(n_iter, ckpt, b)
+        if tape.numel() < tb:
+            raise SparsectError("tape is smaller than this solve needs")
+        g = torch.empty((b, self.nn), dtype=self.dtype, device=self.device)
+        ws = self._ws.get(("vjp", b))
+        if ws is None or ws.numel() < wv:
+            ws = torch.empty(max(wv, 1), dtype=torch.uint8, device=self.device)
+            self._ws[("vjp", b)] = ws
+        _check(lib().cg_unrolled_vjp(self._h, float(alpha), float(lam), float(sigma), self._p(tape),
+                                     tape.numel(), self._p(gx), self._p(g), b, int(n_iter), int(ckpt),
+                                     self._p(ws), ws.numel(), self._stream()))
+        return g
 
     # -- host copies ------------------------------------------------------------
     def export_csr(self):

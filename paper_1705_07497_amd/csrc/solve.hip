@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_xr(
     for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
          i += int64_t(gridDim.x) * kVecThreads) {
         const int64_t j = off + i;
-        x[j] = fma(at, p[j], x[j]);
+        if (x) x[j] = fma(at, p[j], x[j]);   // a replay only needs r
         const T rn = fma(-at, q[j], r[j]);
         r[j] = rn;
         acc += double(rn) * double(rn);
@@ -481,12 +481,10 @@ int64_t sb_ws_bytes(const Op &op, int batch)
     return c.used;
 }
 
-// One CG solve on A(alpha, lambda, sigma) from x with the residual already in
-// w.r; the final state is left in ring slot n_iter % 2.
-template <class TM, class T>
-static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x, int batch,
-                  int n_iter, double rtol, CgBufs<T> &w, T *u_for_prev, T *uprev,
-                  const SbScal *sbs, hipStream_t s)
+// CG start: p = r (+ transposed copy), rho_0, state in ring slot 0.
+template <class T>
+static int cg_start(const Op &op, int batch, CgBufs<T> &w, T *u_for_prev, T *uprev,
+                    const SbScal *sbs, hipStream_t s)
 {
     const unsigned t = unsigned(tiles_of(op.n));
     const dim3 tg{t, t, unsigned(batch)}, tb{32, 8, 1};
@@ -494,19 +492,45 @@ static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x,
     k_cg_start<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, u_for_prev, uprev, w.part_vec, op.n, op.nn);
     SCT_TRY(check_launch("k_cg_start"));
     k_cg_begin<<<unsigned(batch), 256, 0, s>>>(w.part_vec, ntiles, w.st, sbs);
-    SCT_TRY(check_launch("k_cg_begin"));
+    return check_launch("k_cg_begin");
+}
+
+// CG iteration `it`: q = A p, step length, x/r update, p update; state moves
+// from ring slot it % 2 to (it + 1) % 2.
+template <class TM, class T>
+static int cg_iter(const Op &op, double alpha, double lambda, double sigma, T *x, int batch, int it,
+                   double rtol, CgBufs<T> &w, hipStream_t s, T *rec_q = nullptr,
+                   T *rec_p = nullptr, T *rec_r = nullptr)
+{
+    const unsigned t = unsigned(tiles_of(op.n));
+    const dim3 tg{t, t, unsigned(batch)}, tb{32, 8, 1};
     const int vb = vec_blocks(op.nn);
-    for (int it = 0; it < n_iter; ++it) {
-        CgState *cur = w.st + int64_t(it & 1) * batch, *nxt = w.st + int64_t((it + 1) & 1) * batch;
-        CgStep *stp = w.step + int64_t(it & 1) * batch;
-        SCT_TRY((launch_fwd<TM, T>(op, w.p, w.pT, w.y, batch, s)));
-        SCT_TRY((launch_adj<TM, T>(op, w.y, w.p, w.q, alpha, lambda, sigma, w.part_adj, batch, s)));
-        k_cg_xr<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
-            x, w.r, w.p, w.q, w.part_adj, adj_blocks(op), cur, stp, rtol, w.part_vec, op.nn);
-        SCT_TRY(check_launch("k_cg_xr"));
-        k_cg_p<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, w.part_vec, vb, cur, stp, nxt, it, op.n, op.nn);
-        SCT_TRY(check_launch("k_cg_p"));
-    }
+    const int64_t cnt = op.nn * batch;
+    const int vbc = vec_blocks(cnt);
+    CgState *cur = w.st + int64_t(it & 1) * batch, *nxt = w.st + int64_t((it + 1) & 1) * batch;
+    CgStep *stp = w.step + int64_t(it & 1) * batch;
+    SCT_TRY((launch_fwd<TM, T>(op, w.p, w.pT, w.y, batch, s)));
+    SCT_TRY((launch_adj<TM, T>(op, w.y, w.p, w.q, alpha, lambda, sigma, w.part_adj, batch, s)));
+    if (rec_q) k_copy<T><<<vbc, kVecThreads, 0, s>>>(w.q, rec_q, cnt);
+    if (rec_p) k_copy<T><<<vbc, kVecThreads, 0, s>>>(w.p, rec_p, cnt);
+    k_cg_xr<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
+        x, w.r, w.p, w.q, w.part_adj, adj_blocks(op), cur, stp, rtol, w.part_vec, op.nn);
+    SCT_TRY(check_launch("k_cg_xr"));
+    if (rec_r) k_copy<T><<<vbc, kVecThreads, 0, s>>>(w.r, rec_r, cnt);
+    k_cg_p<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, w.part_vec, vb, cur, stp, nxt, it, op.n, op.nn);
+    return check_launch("k_cg_p");
+}
+
+// One CG solve on A(alpha, lambda, sigma) from x with the residual already in
+// w.r; the final state is left in ring slot n_iter % 2.
+template <class TM, class T>
+static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x, int batch,
+                  int n_iter, double rtol, CgBufs<T> &w, T *u_for_prev, T *uprev,
+                  const SbScal *sbs, hipStream_t s)
+{
+    SCT_TRY(cg_start<T>(op, batch, w, u_for_prev, uprev, sbs, s));
+    for (int it = 0; it < n_iter; ++it)
+        SCT_TRY((cg_iter<TM, T>(op, alpha, lambda, sigma, x, batch, it, rtol, w, s)));
     return RADON_OK;
 }
 
@@ -609,6 +633,377 @@ static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, voi
     return RADON_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Unrolled CG: forward with a checkpoint tape, and its vector-Jacobian product
+// ---------------------------------------------------------------------------
+// Forward: x_0 = 0, r_0 = rhs, n_iter CG iterations (an iteration with
+// rho == 0 or a breakdown does nothing).  Every ckpt iterations the tape
+// keeps (r, p, state).  The VJP maps dL/dx_n to dL/drhs by a reverse sweep
+// through the iterations, one segment of ckpt iterations at a time: the
+// segment is first replayed from its checkpoint (bitwise the same kernels,
+// recording p_i, q_i = A p_i, r_{i+1} and the scalars), then reversed.
+// Adjoints of one iteration (u_{i+1} = u_i + a p_i, r_{i+1} = r_i - a q_i,
+// rho_{i+1} = <r_{i+1}, r_{i+1}>, beta = rho_{i+1}/rho_i, p_{i+1} = r_{i+1} +
+// beta p_i, a = rho_i/gamma, gamma = <p_i, q_i>, q_i = A p_i with A symmetric):
+//   betabar = <pbar, p_i>;  rbar += pbar;  pbar = beta pbar;
+//   rhobar_{i+1} += betabar/rho_i;  rbar += 2 rhobar_{i+1} r_{i+1};
+//   abar = <ubar, p_i> - <rbar, q_i>;  qbar = -a rbar;  pbar += a ubar;
+//   rhobar_i = -betabar rho_{i+1}/rho_i^2 + abar/gamma;  gbar = -abar rho_i/gamma^2;
+//   pbar += gbar q_i;  qbar += gbar p_i;  pbar += A qbar.
+// and at the start p_0 = r_0 = rhs, rho_0 = <r_0, r_0>:
+//   drhs = rbar + pbar + 2 rhobar_0 r_0.
+
+struct IterRec {
+    double rho, rho_next, a, gamma;
+    int32_t active, pad[3];
+};
+
+struct RevScal {
+    double carry;       // rhobar of the state after the step being reversed
+    double betabar, up, rhobar_next;
+};
+
+__global__ void k_rec_scalars(const CgState *__restrict__ cur, const CgStep *__restrict__ stp,
+                              const CgState *__restrict__ nxt, IterRec *__restrict__ rec, int batch)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    IterRec o;
+    o.rho = cur[b].rho;
+    o.rho_next = nxt[b].rho;
+    o.a = stp[b].a;
+    o.gamma = stp[b].gamma;
+    o.active = stp[b].stopped ? 0 : 1;
+    o.pad[0] = o.pad[1] = o.pad[2] = 0;
+    rec[b] = o;
+}
+
+__global__ void k_state_copy(const CgState *__restrict__ src, CgState *__restrict__ dst, int batch)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < batch) dst[b] = src[b];
+}
+
+__global__ void k_rev_reset(RevScal *__restrict__ rs, int batch)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    RevScal z;
+    z.carry = z.betabar = z.up = z.rhobar_next = 0.0;
+    rs[b] = z;
+}
+
+// pbar += (A qbar of the later step); partials <pbar, p_i>, <ubar, p_i>.
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_rev_dots(T *__restrict__ pbar, T *__restrict__ aqb,
+                                                           const T *__restrict__ p,
+                                                           const T *__restrict__ ubar,
+                                                           const IterRec *__restrict__ rec,
+                                                           double *__restrict__ part, int64_t nn)
+{
+    __shared__ double red[kVecThreads];
+    const int64_t b = blockIdx.y;
+    const bool active = rec[b].active != 0;
+    const int64_t off = b * nn;
+    double d1 = 0.0, d2 = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
+         i += int64_t(gridDim.x) * kVecThreads) {
+        const int64_t j = off + i;
+        const T pb = pbar[j] + aqb[j];
+        pbar[j] = pb;
+        if (!active) continue;
+        d1 += double(pb) * double(p[j]);
+        d2 += double(ubar[j]) * double(p[j]);
+    }
+    const double t1 = block_sum(d1, red);
+    const double t2 = block_sum(d2, red);
+    if (threadIdx.x == 0) {
+        part[(b * gridDim.x + blockIdx.x) * 2 + 0] = t1;
+        part[(b * gridDim.x + blockIdx.x) * 2 + 1] = t2;
+    }
+}
+
+// rhobar_{i+1} = carry + betabar/rho_i; rbar += pbar + 2 rhobar_{i+1} r_{i+1};
+// pbar *= beta; partial <rbar, q_i>.
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_rev_r(T *__restrict__ rbar, T *__restrict__ pbar,
+                                                        const T *__restrict__ rn,
+                                                        const T *__restrict__ q,
+                                                        const IterRec *__restrict__ rec,
+                                                        RevScal *__restrict__ rs,
+                                                        const double *__restrict__ part_in,
+                                                        int64_t n_in, double *__restrict__ part,
+                                                        int64_t nn)
+{
+    __shared__ double red[kVecThreads];
+    const int64_t b = blockIdx.y;
+    const IterRec R = rec[b];
+    if (!R.active) return;
+    double v1 = 0.0, v2 = 0.0;
+    for (int64_t i = threadIdx.x; i < n_in; i += kVecThreads) {
+        v1 += part_in[(b * n_in + i) * 2 + 0];
+        v2 += part_in[(b * n_in + i) * 2 + 1];
+    }
+    const double betabar = block_sum(v1, red);
+    const double up = block_sum(v2, red);
+    const double rhobar_next = rs[b].carry + betabar / R.rho;
+    const double beta = R.rho_next / R.rho;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        RevScal o = rs[b];
+        o.betabar = betabar;
+        o.up = up;
+        o.rhobar_next = rhobar_next;
+        rs[b] = o;
+    }
+    const T two_rb = T(2.0 * rhobar_next), bt = T(beta);
+    const int64_t off = b * nn;
+    double acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
+         i += int64_t(gridDim.x) * kVecThreads) {
+        const int64_t j = off + i;
+        const T pb = pbar[j];
+        const T rb = rbar[j] + pb + two_rb * rn[j];
+        rbar[j] = rb;
+        pbar[j] = bt * pb;
+        acc += double(rb) * double(q[j]);
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = tot;
+}
+
+// abar = <ubar, p_i> - <rbar, q_i>; gbar = -abar rho_i/gamma^2;
+// qbar = -a rbar + gbar p_i (and its transposed copy); pbar += a ubar + gbar q_i;
+// the carried rhobar becomes rhobar_i.
+template <class T>
+__global__ __launch_bounds__(256) void k_rev_q(const T *__restrict__ rbar, T *__restrict__ pbar,
+                                               T *__restrict__ qbar, T *__restrict__ qbarT,
+                                               const T *__restrict__ p, const T *__restrict__ q,
+                                               const T *__restrict__ ubar,
+                                               const IterRec *__restrict__ rec,
+                                               RevScal *__restrict__ rs,
+                                               const double *__restrict__ part_in, int64_t n_in,
+                                               int n, int64_t nn)
+{
+    __shared__ T tile[32][33];
+    __shared__ double red[256];
+    const int64_t b = blockIdx.z;
+    const IterRec R = rec[b];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int64_t off = b * nn;
+    if (!R.active) {
+        // an inactive step passes every adjoint through: qbar = 0, so A qbar = 0
+        for (int i = threadIdx.y; i < 32; i += 8) {
+            const int iy = by + i, ix = bx + threadIdx.x;
+            if (iy < n && ix < n) {
+                qbar[off + int64_t(iy) * n + ix] = T(0);
+                if (qbarT) qbarT[off + int64_t(ix) * n + iy] = T(0);
+            }
+        }
+        return;
+    }
+    const int t = threadIdx.y * 32 + threadIdx.x;
+    double v = 0.0;
+    for (int64_t i = t; i < n_in; i += 256) v += part_in[b * n_in + i];
+    const double rq = block_sum(v, red);
+    const RevScal S = rs[b];
+    const double abar = S.up - rq;
+    const double gbar = -abar * R.rho / (R.gamma * R.gamma);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+        RevScal o = S;
+        o.carry = -S.betabar * R.rho_next / (R.rho * R.rho) + abar / R.gamma;
+        rs[b] = o;
+    }
+    const T a = T(R.a), g = T(gbar);
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int iy = by + i, ix = bx + threadIdx.x;
+        if (iy < n && ix < n) {
+            const int64_t j = off + int64_t(iy) * n + ix;
+            const T qb = -a * rbar[j] + g * p[j];
+            qbar[j] = qb;
+            pbar[j] = pbar[j] + a * ubar[j] + g * q[j];
+            tile[i][threadIdx.x] = qb;
+        }
+    }
+    if (!qbarT) return;
+    __syncthreads();
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int ix = bx + i, iy = by + threadIdx.x;
+        if (ix < n && iy < n) qbarT[off + int64_t(ix) * n + iy] = tile[threadIdx.x][i];
+    }
+}
+
+// drhs = rbar + pbar + (A qbar of step 0) + 2 rhobar_0 rhs
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_rev_final(const T *__restrict__ rbar,
+                                                            const T *__restrict__ pbar,
+                                                            const T *__restrict__ aqb,
+                                                            const T *__restrict__ rhs,
+                                                            const RevScal *__restrict__ rs,
+                                                            T *__restrict__ out, int64_t nn)
+{
+    const int64_t b = blockIdx.y;
+    const T two_r = T(2.0 * rs[b].carry);
+    const int64_t off = b * nn;
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
+         i += int64_t(gridDim.x) * kVecThreads) {
+        const int64_t j = off + i;
+        out[j] = rbar[j] + pbar[j] + aqb[j] + two_r * rhs[j];
+    }
+}
+
+template <class T>
+struct Tape {
+    T *r = nullptr, *p = nullptr;   // [nseg][batch][nn]
+    CgState *st = nullptr;          // [nseg][batch]
+};
+
+static int n_segments(int n_iter, int ckpt) { return n_iter <= 0 ? 0 : (n_iter + ckpt - 1) / ckpt; }
+
+template <class T>
+static void carve_tape(const Op &op, int batch, int n_iter, int ckpt, Carver &c, Tape<T> &t)
+{
+    const int64_t ns = n_segments(n_iter, ckpt);
+    t.r = c.take<T>(ns * op.nn * batch);
+    t.p = c.take<T>(ns * op.nn * batch);
+    t.st = c.take<CgState>(ns * batch);
+}
+
+template <class T>
+struct VjpBufs {
+    CgBufs<T> cg;
+    T *rec_p, *rec_q, *rec_r;            // [ckpt][batch][nn]
+    IterRec *rec;                        // [ckpt][batch]
+    T *pbar, *rbar, *qbar, *qbarT, *aqb;
+    double *part;                        // [batch][vec_blocks][2]
+    RevScal *rs;
+};
+
+template <class T>
+static void carve_vjp(const Op &op, int batch, int ckpt, Carver &c, VjpBufs<T> &w)
+{
+    const int64_t nb = op.nn * batch;
+    carve_cg(op, batch, c, w.cg);
+    w.rec_p = c.take<T>(int64_t(ckpt) * nb);
+    w.rec_q = c.take<T>(int64_t(ckpt) * nb);
+    w.rec_r = c.take<T>(int64_t(ckpt) * nb);
+    w.rec = c.take<IterRec>(int64_t(ckpt) * batch);
+    w.pbar = c.take<T>(nb);
+    w.rbar = c.take<T>(nb);
+    w.qbar = c.take<T>(nb);
+    w.qbarT = op.need_T ? c.take<T>(nb) : nullptr;
+    w.aqb = c.take<T>(nb);
+    w.part = c.take<double>(int64_t(2) * vec_blocks(op.nn) * batch);
+    w.rs = c.take<RevScal>(batch);
+}
+
+static int64_t unrolled_bytes(const Op &op, int which, int n_iter, int ckpt, int batch)
+{
+    Carver c(nullptr);
+    if (op.vsize == 4) {
+        if (which == 0) { Tape<float> t; carve_tape(op, batch, n_iter, ckpt, c, t); }
+        else { VjpBufs<float> w; carve_vjp(op, batch, ckpt, c, w); }
+    } else {
+        if (which == 0) { Tape<double> t; carve_tape(op, batch, n_iter, ckpt, c, t); }
+        else { VjpBufs<double> w; carve_vjp(op, batch, ckpt, c, w); }
+    }
+    return c.used;
+}
+
+template <class TM, class T>
+static int unrolled_fwd_typed(const Op &op, double alpha, double lambda, double sigma,
+                              const T *rhs, T *x, int batch, int n_iter, int ckpt, void *tape_mem,
+                              void *ws, hipStream_t s)
+{
+    Carver tc(tape_mem);
+    Tape<T> tape;
+    carve_tape(op, batch, n_iter, ckpt, tc, tape);
+    Carver c(ws);
+    CgBufs<T> w;
+    carve_cg(op, batch, c, w);
+    const int64_t cnt = op.nn * batch;
+    const int vbc = vec_blocks(cnt);
+    k_fill<T><<<vbc, kVecThreads, 0, s>>>(x, T(0), cnt);
+    k_copy<T><<<vbc, kVecThreads, 0, s>>>(rhs, w.r, cnt);
+    SCT_TRY(check_launch("k_copy"));
+    SCT_TRY(cg_start<T>(op, batch, w, nullptr, nullptr, nullptr, s));
+    for (int it = 0; it < n_iter; ++it) {
+        if (it % ckpt == 0) {
+            const int64_t sg = it / ckpt;
+            k_copy<T><<<vbc, kVecThreads, 0, s>>>(w.r, tape.r + sg * cnt, cnt);
+            k_copy<T><<<vbc, kVecThreads, 0, s>>>(w.p, tape.p + sg * cnt, cnt);
+            k_state_copy<<<unsigned((batch + 63) / 64), 64, 0, s>>>(w.st + int64_t(it & 1) * batch,
+                                                                   tape.st + sg * batch, batch);
+            SCT_TRY(check_launch("tape"));
+        }
+        SCT_TRY((cg_iter<TM, T>(op, alpha, lambda, sigma, x, batch, it, 0.0, w, s)));
+    }
+    return RADON_OK;
+}
+
+template <class TM, class T>
+static int unrolled_vjp_typed(const Op &op, double alpha, double lambda, double sigma,
+                              const void *tape_mem, const T *gx, T *grhs, int batch, int n_iter,
+                              int ckpt, void *ws, hipStream_t s)
+{
+    Carver tc(const_cast<void *>(tape_mem));
+    Tape<T> tape;
+    carve_tape(op, batch, n_iter, ckpt, tc, tape);
+    Carver c(ws);
+    VjpBufs<T> w;
+    carve_vjp(op, batch, ckpt, c, w);
+    const int64_t cnt = op.nn * batch;
+    const int vbc = vec_blocks(cnt), vb = vec_blocks(op.nn);
+    const unsigned t = unsigned(tiles_of(op.n));
+    const dim3 tg{t, t, unsigned(batch)}, tb{32, 8, 1};
+    const unsigned sb = unsigned((batch + 63) / 64);
+    for (T *z : {w.pbar, w.rbar, w.aqb}) k_fill<T><<<vbc, kVecThreads, 0, s>>>(z, T(0), cnt);
+    k_rev_reset<<<sb, 64, 0, s>>>(w.rs, batch);
+    SCT_TRY(check_launch("k_rev_reset"));
+    for (int sg = n_segments(n_iter, ckpt) - 1; sg >= 0; --sg) {
+        const int k0 = sg * ckpt, k1 = (k0 + ckpt < n_iter) ? k0 + ckpt : n_iter;
+        // replay the segment from its checkpoint, recording what the reverse needs
+        k_copy<T><<<vbc, kVecThreads, 0, s>>>(tape.r + int64_t(sg) * cnt, w.cg.r, cnt);
+        k_copy<T><<<vbc, kVecThreads, 0, s>>>(tape.p + int64_t(sg) * cnt, w.cg.p, cnt);
+        if (w.cg.pT) SCT_TRY(launch_transpose<T>(op, w.cg.p, w.cg.pT, batch, s));
+        k_state_copy<<<sb, 64, 0, s>>>(tape.st + int64_t(sg) * batch, w.cg.st + int64_t(k0 & 1) * batch,
+                                       batch);
+        SCT_TRY(check_launch("replay"));
+        for (int it = k0; it < k1; ++it) {
+            const int64_t o = int64_t(it - k0) * cnt;
+            SCT_TRY((cg_iter<TM, T>(op, alpha, lambda, sigma, nullptr, batch, it, 0.0, w.cg, s,
+                                    w.rec_q + o, w.rec_p + o, w.rec_r + o)));
+            k_rec_scalars<<<sb, 64, 0, s>>>(w.cg.st + int64_t(it & 1) * batch,
+                                            w.cg.step + int64_t(it & 1) * batch,
+                                            w.cg.st + int64_t((it + 1) & 1) * batch,
+                                            w.rec + int64_t(it - k0) * batch, batch);
+            SCT_TRY(check_launch("k_rec_scalars"));
+        }
+        // reverse through the segment
+        for (int it = k1 - 1; it >= k0; --it) {
+            const int64_t o = int64_t(it - k0) * cnt;
+            const IterRec *R = w.rec + int64_t(it - k0) * batch;
+            const T *p_i = w.rec_p + o, *q_i = w.rec_q + o, *r_n = w.rec_r + o;
+            k_rev_dots<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
+                w.pbar, w.aqb, p_i, gx, R, w.part, op.nn);
+            SCT_TRY(check_launch("k_rev_dots"));
+            k_rev_r<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
+                w.rbar, w.pbar, r_n, q_i, R, w.rs, w.part, vb, w.cg.part_vec, op.nn);
+            SCT_TRY(check_launch("k_rev_r"));
+            k_rev_q<T><<<tg, tb, 0, s>>>(w.rbar, w.pbar, w.qbar, w.qbarT, p_i, q_i, gx, R, w.rs,
+                                         w.cg.part_vec, vb, op.n, op.nn);
+            SCT_TRY(check_launch("k_rev_q"));
+            // A qbar, added to pbar by the next (earlier) step or the final kernel
+            SCT_TRY((launch_fwd<TM, T>(op, w.qbar, w.qbarT, w.cg.y, batch, s)));
+            SCT_TRY((launch_adj<TM, T>(op, w.cg.y, w.qbar, w.aqb, alpha, lambda, sigma, nullptr,
+                                       batch, s)));
+        }
+    }
+    // r_0 = rhs is the first checkpoint's residual (x_0 = 0)
+    k_rev_final<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
+        w.rbar, w.pbar, w.aqb, tape.r, w.rs, grhs, op.nn);
+    return check_launch("k_rev_final");
+}
+
 }  // namespace sct
 
 using namespace sct;
@@ -657,5 +1052,87 @@ extern "C" int split_bregman_tv(const radon_op *p, const radon_sb_params *params
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
         return sb_typed<TM, TV>(op, *params, f, mu, batch, ws, info, s);
+    });
+}
+
+extern "C" int radon_unrolled_sizes(const radon_op *p, int32_t n_iter, int32_t ckpt, int32_t batch,
+                                    int64_t *tape_bytes, int64_t *ws_fwd_bytes,
+                                    int64_t *ws_vjp_bytes)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (n_iter < 0) return set_error(RADON_EINVAL, "n_iter must be >= 0 (got %d)", n_iter);
+    if (ckpt < 1) return set_error(RADON_EINVAL, "ckpt must be >= 1 (got %d)", ckpt);
+    const Op &op = *as_op(p);
+    const int k = ckpt < n_iter ? ckpt : (n_iter > 0 ? n_iter : 1);
+    if (tape_bytes) *tape_bytes = unrolled_bytes(op, 0, n_iter, ckpt, batch);
+    if (ws_fwd_bytes) *ws_fwd_bytes = cg_ws_bytes(op, batch);
+    if (ws_vjp_bytes) *ws_vjp_bytes = unrolled_bytes(op, 1, n_iter, k, batch);
+    return RADON_OK;
+}
+
+static int check_unrolled(const radon_op *p, int32_t batch, int32_t n_iter, int32_t ckpt,
+                          const void *tape, int64_t tape_bytes)
+{
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (n_iter < 0) return set_error(RADON_EINVAL, "n_iter must be >= 0 (got %d)", n_iter);
+    if (ckpt < 1) return set_error(RADON_EINVAL, "ckpt must be >= 1 (got %d)", ckpt);
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    const int64_t need = unrolled_bytes(*as_op(p), 0, n_iter, ckpt, batch);
+    if (need > 0 && !tape) return set_error(RADON_EWORKSPACE, "tape is NULL (%lld bytes needed)",
+                                            (long long)need);
+    if (tape_bytes < need)
+        return set_error(RADON_EWORKSPACE, "tape of %lld bytes, %lld needed", (long long)tape_bytes,
+                         (long long)need);
+    return RADON_OK;
+}
+
+extern "C" int cg_unrolled(const radon_op *p, double alpha, double lambda, double sigma,
+                           const void *rhs, void *x, int32_t batch, int32_t n_iter, int32_t ckpt,
+                           void *tape, int64_t tape_bytes, void *ws, int64_t ws_bytes,
+                           void *stream)
+{
+    clear_error();
+    SCT_TRY(check_unrolled(p, batch, n_iter, ckpt, tape, tape_bytes));
+    if (!rhs || !x) return set_error(RADON_EINVAL, "rhs and x must be non-NULL");
+    if (rhs == x) return set_error(RADON_EINVAL, "x must not alias rhs");
+    const Op &op = *as_op(p);
+    SCT_TRY(check_ws(ws, ws_bytes, cg_ws_bytes(op, batch), "cg_unrolled"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return unrolled_fwd_typed<TM, TV>(op, alpha, lambda, sigma, static_cast<const TV *>(rhs),
+                                          static_cast<TV *>(x), batch, n_iter, ckpt, tape, ws, s);
+    });
+}
+
+extern "C" int cg_unrolled_vjp(const radon_op *p, double alpha, double lambda, double sigma,
+                               const void *tape, int64_t tape_bytes, const void *gx, void *grhs,
+                               int32_t batch, int32_t n_iter, int32_t ckpt, void *ws,
+                               int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_unrolled(p, batch, n_iter, ckpt, tape, tape_bytes));
+    if (!gx || !grhs) return set_error(RADON_EINVAL, "gx and grhs must be non-NULL");
+    const Op &op = *as_op(p);
+    const int k = ckpt < n_iter ? ckpt : (n_iter > 0 ? n_iter : 1);
+    SCT_TRY(check_ws(ws, ws_bytes, unrolled_bytes(op, 1, n_iter, k, batch), "cg_unrolled_vjp"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n_iter == 0) {
+        // x = 0 whatever the rhs: the gradient is zero
+        const int64_t cnt = op.nn * batch;
+        if (op.vsize == 4)
+            k_fill<float><<<vec_blocks(cnt), kVecThreads, 0, s>>>(static_cast<float *>(grhs), 0.f, cnt);
+        else
+            k_fill<double><<<vec_blocks(cnt), kVecThreads, 0, s>>>(static_cast<double *>(grhs), 0.0, cnt);
+        return check_launch("k_fill");
+    }
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return unrolled_vjp_typed<TM, TV>(op, alpha, lambda, sigma, tape,
+                                          static_cast<const TV *>(gx), static_cast<TV *>(grhs),
+                                          batch, n_iter, k, ws, s);
     });
 }

@@ -97,3 +97,23 @@ def test_point_spread_function_decay():
         got = psf[ring].mean()
         want = alpha * na / (math.pi * r)
         assert abs(got / want - 1) < 0.1, (r, got, want)
+
+
+def test_single_precision_values_option():
+    """values="f32": every entry is the FP64 entry rounded once to binary32, in
+    both the matrix and its transpose, and products move by at most the
+    binary32 unit roundoff relative to the FP64 operator."""
+    n, na = 24, 13
+    nb = W.n_bins_for(n)
+    a = oracle.OracleOp(n, na, nb)
+    b = oracle.OracleOp(n, na, nb, values="f32")
+    np.testing.assert_array_equal(b.MR.rp, a.MR.rp)
+    np.testing.assert_array_equal(b.MR.ci, a.MR.ci)
+    np.testing.assert_array_equal(b.MR.v, a.MR.v.astype(np.float32).astype(np.float64))
+    np.testing.assert_array_equal(b.MRT.v, a.MRT.v.astype(np.float32).astype(np.float64))
+    assert np.any(b.MR.v != a.MR.v)
+    x = np.abs(np.random.default_rng(0).standard_normal(n * n))
+    ya, yb = a.fwd(x), b.fwd(x)
+    assert np.max(np.abs(ya - yb) / np.maximum(ya, 1e-300)) <= 2.0 ** -24
+    with pytest.raises(ValueError):
+        oracle.OracleOp(n, na, nb, values="f16")
