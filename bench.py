@@ -3,7 +3,7 @@
 
 Workload: the 512 x 512 random-ellipse phantom (10 ellipses), 360 angles on
 [0, pi) of which every second one is measured (180), 725 bins, 2% noise,
-split Bregman with alpha = 10, lambda = 1, 50 outer x 20 CG iterations.  The
+split Bregman with alpha = 0.01, lambda = 1, 50 outer x 20 CG iterations.  The
 operator streams its matrix in FP32 and keeps vectors and multiply-adds in
 FP64 (the FP32-matrix / FP64-vector operator kind): with FP32 vectors the CG
 iterates drift ~1e-2 from exact arithmetic, far outside the 1e-5 the
@@ -58,10 +58,28 @@ def parse():
     return ap.parse_args()
 
 
+def event_time(torch, fn, reps):
+    """Seconds per call of fn (one untimed call first), HIP events on the
+    current stream, which every library call here is enqueued on."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
 def bench_batched(sct, W, torch, dev, vdt):
     """Fused multi-image normal_apply (every matrix load shared by a chunk of up
     to 16 images) against the same images applied one at a time."""
     out = {}
+
+    def t(fn, reps):
+        return event_time(torch, fn, reps)
+
     for name in ("grad_16x512_f32", "volume_64x1024_f32"):
         w = W.WORKLOADS[name]
         op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
@@ -81,17 +99,6 @@ def bench_batched(sct, W, torch, dev, vdt):
             for xb in singles:
                 op.normal(xb, alpha, lam, sigma, out=o1)
 
-        def t(fn, reps):
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                fn()
-            e1.record()
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / reps / 1e3
-
         tf, tl = t(fused, 5), t(looped, 2)
         out[name] = {"batch": B, "n": w.n, "measured_angles": w.n_meas, "bins": w.n_bins,
                      "nnz": op.info.nnz, "fused_ms": round(tf * 1e3, 3),
@@ -99,9 +106,79 @@ def bench_batched(sct, W, torch, dev, vdt):
                      "image_applies_per_s": round(B / tf, 1)}
         print(f"# batched {name}: fused {tf * 1e3:.2f} ms vs loop {tl * 1e3:.2f} ms "
               f"({tl / tf:.2f}x)", file=sys.stderr, flush=True)
+        if name == "grad_16x512_f32":
+            out["grad_16x512_f32_autograd"] = bench_autograd(op, w, torch, dev, vdt, t)
         del op
         torch.cuda.empty_cache()
+    out["mixed_batch_32"] = bench_mixed_batch(sct, W, torch, dev, vdt, t)
     return out
+
+
+def bench_mixed_batch(sct, W, torch, dev, vdt, t):
+    """The uneven batch: 32 instances (N in {256, 512, 1024}, 60-180 angles),
+    CG(10) on each instance's split-Bregman inner operator (alpha = 0.01,
+    lambda = 1): one captured graph replay (one launch per phase over all
+    instances, 6 phases per iteration) against the eager group call and
+    against 32 separate cg_solve calls."""
+    specs = [(n, na, W.n_bins_for(n)) for n, na in W.mixed_batch_specs(32)]
+    ops = [sct.RadonOp(n, na, nb, None, dtype=torch.float32, vec_dtype=vdt, device=dev)
+           for n, na, nb in specs]
+    g = sct.RadonMulti(ops, 0.01, 1.0, 0.0)
+    rhs = [torch.randn((1, o.nn), dtype=vdt, device=dev) for o in ops]
+    R = g.pack_images(rhs)
+    graph = g.cg_graph(n_iter=10)
+    graph.rhs.copy_(R)
+    xs = [torch.empty_like(r) for r in rhs]
+
+    def replay():
+        graph.launch()
+
+    def eager():
+        g.cg(R, n_iter=10)
+
+    def looped():
+        for o, r, x in zip(ops, rhs, xs):
+            o.cg(r, 0.01, 1.0, 0.0, n_iter=10, out=x)
+
+    tg, te, tl = t(replay, 5), t(eager, 5), t(looped, 2)
+    nnz = sum(o.info.nnz for o in ops)
+    print(f"# mixed batch 32 instances: graph {tg * 1e3:.2f} ms, eager group {te * 1e3:.2f} ms, "
+          f"per-instance loop {tl * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    out = {"instances": len(ops), "sizes": sorted({s[0] for s in specs}),
+           "angles": [min(s[1] for s in specs), max(s[1] for s in specs)], "nnz_total": nnz,
+           "cg_iterations": 10, "graph_ms": round(tg * 1e3, 3), "eager_group_ms": round(te * 1e3, 3),
+           "per_instance_loop_ms": round(tl * 1e3, 3), "speedup_vs_loop": round(tl / tg, 2),
+           "instance_applies_per_s": round(len(ops) * 10 / tg, 1)}
+    del graph, g, ops
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_autograd(op, w, torch, dev, vdt, t):
+    """Loss and gradient through 10 unrolled CG iterations checkpointed every 5
+    (forward 10 applies, reverse 10 replayed + 10 adjoint applies), the 16
+    images fused against one image at a time."""
+    from paper_1705_07497_amd import autograd as AG
+    ta = w.extra["tau"] * w.alpha
+    B, ck = w.batch, w.extra["ckpt"]
+    M = torch.randn((B, op.nn), dtype=vdt, device=dev, requires_grad=True)
+    F = torch.randn((B, op.rows), dtype=vdt, device=dev, requires_grad=True)
+    singles = [(M[b:b + 1].detach().clone().requires_grad_(True),
+                F[b:b + 1].detach().clone().requires_grad_(True)) for b in range(B)]
+
+    def fused():
+        AG.loss_unrolled(op, M, F, ta, w.n_cg, ck).sum().backward()
+
+    def looped():
+        for m, f in singles:
+            AG.loss_unrolled(op, m, f, ta, w.n_cg, ck).sum().backward()
+
+    tf, tl = t(fused, 3), t(looped, 1)
+    print(f"# autograd {w.name}: fused {tf * 1e3:.2f} ms vs loop {tl * 1e3:.2f} ms "
+          f"({tl / tf:.2f}x)", file=sys.stderr, flush=True)
+    return {"batch": B, "cg_iterations": w.n_cg, "ckpt": ck, "fused_ms": round(tf * 1e3, 3),
+            "per_image_loop_ms": round(tl * 1e3, 3), "speedup": round(tl / tf, 2),
+            "image_grads_per_s": round(B / tf, 1)}
 
 
 def main():

@@ -285,6 +285,73 @@ int cg_unrolled_vjp(const radon_op *op, double alpha, double lambda, double sigm
                     void *stream);
 
 /*
+ * Mixed batches: several operators of different geometry (image size, angle
+ * and bin counts) in one group, so that each phase of a product or of a CG
+ * iteration is a single launch over all instances instead of one launch per
+ * instance.  The instance count, sizes and weights are fixed at creation.
+ *
+ * Packed vectors: instance i's image occupies elements
+ * [img_off[i], img_off[i] + n_i*n_i) of one device vector of img_off[count]
+ * elements (operator dtype), its measured sinogram
+ * [sino_off[i], sino_off[i] + n_meas_rays_i) of one vector of
+ * sino_off[count]; each start is 256-byte aligned and the gaps are ignored.
+ */
+typedef struct radon_multi radon_multi;   /* opaque group handle */
+typedef struct radon_graph radon_graph;   /* opaque captured-graph handle */
+
+/*
+ * radon_multi_create -- group `count` operators (all of one dtype).  The
+ * group borrows the operators: they must outlive it.  alpha, lambda, sigma:
+ * host arrays of `count` weights of each instance's normal operator
+ * A_i = alpha_i R_i^T M_i^T M_i R_i + lambda_i K^T K + sigma_i I (Section 2),
+ * or NULL for 1, 0, 0.  Synchronous (copies the work lists to the device).
+ */
+int radon_multi_create(const radon_op *const *ops, int32_t count, const double *alpha,
+                       const double *lambda, const double *sigma, radon_multi **out);
+void radon_multi_destroy(radon_multi *m);
+
+/*
+ * radon_multi_info -- packed-vector offsets (host int64[count+1] each, NULL
+ * to skip), workspace bytes of radon_multi_apply and radon_multi_cg, and the
+ * waves per 8x8 tile the group's adjoint uses.
+ */
+int radon_multi_info(const radon_multi *m, int64_t *img_off, int64_t *sino_off,
+                     int64_t *ws_products, int64_t *ws_cg, int32_t *adj_waves);
+
+/*
+ * radon_multi_apply -- which = 0: y_i = M_i R_i x_i (in: packed images, out:
+ * packed sinograms); 1: x_i = R_i^T M_i^T y_i (packed sinograms -> images);
+ * 2: out_i = A_i x_i (packed images -> images).  ws: ws_products bytes.
+ */
+int radon_multi_apply(const radon_multi *m, int32_t which, const void *in, void *out,
+                      void *ws, int64_t ws_bytes, void *stream);
+
+/*
+ * radon_multi_cg -- CG (Hestenes-Stiefel) on A_i x_i = rhs_i from x_i = 0,
+ * one independent solve per instance with FP64 scalars (as cg_solve).
+ *   rhs, x  packed images; x must not alias rhs.
+ *   info    optional device radon_cg_info[count].
+ *   ws      ws_cg bytes.
+ */
+int radon_multi_cg(const radon_multi *m, const void *rhs, void *x, int32_t n_iter, double rtol,
+                   void *ws, int64_t ws_bytes, radon_cg_info *info, void *stream);
+
+/*
+ * radon_multi_cg_graph -- capture the radon_multi_cg call with these
+ * arguments into a HIP graph (nothing runs yet).  Each radon_graph_launch
+ * then runs the whole solve with one launch, reading rhs and writing x, info
+ * and ws at the captured addresses: those buffers, the group and its
+ * operators must stay alive while the graph exists.  The graph holds no
+ * memset nodes.  Replays on one stream run in order; replays that overlap
+ * (other streams) race on the captured buffers.
+ */
+int radon_multi_cg_graph(const radon_multi *m, const void *rhs, void *x, int32_t n_iter,
+                         double rtol, void *ws, int64_t ws_bytes, radon_cg_info *info,
+                         radon_graph **out);
+int radon_graph_launch(const radon_graph *g, void *stream);
+void radon_graph_destroy(radon_graph *g);
+
+/*
  * Launch tuning of an operator (not part of the method: it only changes how
  * the products are scheduled; the waves-per-item counts split each sum
  * differently, so results change at the rounding level; the fused chunk

@@ -99,6 +99,18 @@ SIGNATURES = {
     "cg_unrolled": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
                                    _vp, ctypes.c_int64, _vp]),
+    "radon_multi_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, _vp,
+                                          ctypes.POINTER(_vp)]),
+    "radon_multi_destroy": (None, [_vp]),
+    "radon_multi_info": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    "radon_multi_apply": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "radon_multi_cg": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, _vp,
+                                      ctypes.c_int64, _vp, _vp]),
+    "radon_multi_cg_graph": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, _vp,
+                                            ctypes.c_int64, _vp, ctypes.POINTER(_vp)]),
+    "radon_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "radon_graph_destroy": (None, [_vp]),
     "cg_unrolled_vjp": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp,
                                        ctypes.c_int64, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
@@ -396,6 +408,161 @@ class RadonOp:
         _check(lib().radon_export_adj(self._h, b.ctypes.data_as(_vp), v0.ctypes.data_as(_vp),
                                       v1.ctypes.data_as(_vp)))
         return b, v0, v1
+
+
+class RadonMulti:
+    """A mixed batch: several RadonOps of different geometry (and one dtype
+    kind) whose products and CG solves run as one launch per phase.  Weights
+    alpha, lam, sigma (scalars or one per instance) fix each instance's normal
+    operator.  Vectors are packed: instance i's image is
+    packed[img_off[i] : img_off[i] + n_i**2]."""
+
+    def __init__(self, ops, alpha=1.0, lam=0.0, sigma=0.0):
+        torch = _torch()
+        self.ops = list(ops)   # keeps the operators alive as long as the group
+        k = len(self.ops)
+        if k < 1:
+            raise SparsectError("a group needs at least one operator")
+        self.dtype, self.device = self.ops[0].dtype, self.ops[0].device
+
+        def arr(v):
+            a = np.broadcast_to(np.asarray(v, dtype=np.float64), (k,)).copy()
+            return a
+
+        self.alpha, self.lam, self.sigma = arr(alpha), arr(lam), arr(sigma)
+        handles = (_vp * k)(*[o._h for o in self.ops])
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib().radon_multi_create(handles, k, self.alpha.ctypes.data_as(_vp),
+                                            self.lam.ctypes.data_as(_vp),
+                                            self.sigma.ctypes.data_as(_vp), ctypes.byref(h)))
+        self._h = h
+        self.img_off = np.zeros(k + 1, dtype=np.int64)
+        self.sino_off = np.zeros(k + 1, dtype=np.int64)
+        wp, wc, aw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().radon_multi_info(self._h, self.img_off.ctypes.data_as(_vp),
+                                      self.sino_off.ctypes.data_as(_vp), ctypes.byref(wp),
+                                      ctypes.byref(wc), ctypes.byref(aw)))
+        self.ws_products, self.ws_cg, self.adj_waves = int(wp.value), int(wc.value), int(aw.value)
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _torch().cuda.synchronize(self.device)
+            except Exception:
+                pass
+            _lib.radon_multi_destroy(h)
+            self._h = None
+
+    def _stream(self):
+        return _vp(_torch().cuda.current_stream(self.device).cuda_stream)
+
+    def _buf(self, key, nbytes):
+        torch = _torch()
+        b = self._ws.get(key)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+            self._ws[key] = b
+        return b
+
+    def empty_images(self):
+        return _torch().zeros(int(self.img_off[-1]), dtype=self.dtype, device=self.device)
+
+    def empty_sinograms(self):
+        return _torch().zeros(int(self.sino_off[-1]), dtype=self.dtype, device=self.device)
+
+    def pack_images(self, imgs):
+        out = self.empty_images()
+        for i, (o, x) in enumerate(zip(self.ops, imgs)):
+            out[self.img_off[i]:self.img_off[i] + o.nn] = x.reshape(-1)
+        return out
+
+    def pack_sinograms(self, sinos):
+        out = self.empty_sinograms()
+        for i, (o, y) in enumerate(zip(self.ops, sinos)):
+            out[self.sino_off[i]:self.sino_off[i] + o.rows] = y.reshape(-1)
+        return out
+
+    def image(self, packed, i):
+        return packed[self.img_off[i]:self.img_off[i] + self.ops[i].nn]
+
+    def sinogram(self, packed, i):
+        return packed[self.sino_off[i]:self.sino_off[i] + self.ops[i].rows]
+
+    def _check_vec(self, t, n, name):
+        torch = _torch()
+        if (not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != self.dtype
+                or not t.is_contiguous() or t.numel() != n):
+            raise SparsectError(f"{name} must be a contiguous {self.dtype} tensor of {n} elements "
+                                f"on {self.device}")
+
+    def apply(self, which: int, x, out=None):
+        """0: packed images -> sinograms (M R); 1: sinograms -> images (R^T M^T);
+        2: images -> images (A_i)."""
+        ni, ns = int(self.img_off[-1]), int(self.sino_off[-1])
+        self._check_vec(x, ns if which == 1 else ni, "input")
+        if out is None:
+            out = self.empty_sinograms() if which == 0 else self.empty_images()
+        self._check_vec(out, ns if which == 0 else ni, "out")
+        ws = self._buf("products", self.ws_products)
+        _check(lib().radon_multi_apply(self._h, int(which), _vp(x.data_ptr()), _vp(out.data_ptr()),
+                                       _vp(ws.data_ptr()), ws.numel(), self._stream()))
+        return out
+
+    def cg(self, rhs, n_iter: int = 10, rtol: float = 0.0, out=None):
+        """CG on every instance from 0; returns (x, info tensor of CgInfo bytes)."""
+        torch = _torch()
+        ni = int(self.img_off[-1])
+        self._check_vec(rhs, ni, "rhs")
+        x = self.empty_images() if out is None else out
+        self._check_vec(x, ni, "out")
+        info = torch.zeros(len(self.ops) * ctypes.sizeof(CgInfo), dtype=torch.uint8, device=self.device)
+        ws = self._buf("cg", self.ws_cg)
+        _check(lib().radon_multi_cg(self._h, _vp(rhs.data_ptr()), _vp(x.data_ptr()), int(n_iter),
+                                    float(rtol), _vp(ws.data_ptr()), ws.numel(), _vp(info.data_ptr()),
+                                    self._stream()))
+        return x, info
+
+    def cg_graph(self, n_iter: int = 10, rtol: float = 0.0) -> "MultiCgGraph":
+        """Capture a CG solve into a HIP graph over buffers it owns (see MultiCgGraph)."""
+        return MultiCgGraph(self, n_iter, rtol)
+
+
+class MultiCgGraph:
+    """A captured radon_multi_cg: write the packed right-hand sides into
+    .rhs, call launch(), read .x and .info.  The graph keeps its buffers."""
+
+    def __init__(self, group: RadonMulti, n_iter: int, rtol: float):
+        torch = _torch()
+        self.group = group
+        self.rhs = group.empty_images()
+        self.x = group.empty_images()
+        self.info = torch.zeros(len(group.ops) * ctypes.sizeof(CgInfo), dtype=torch.uint8,
+                                device=group.device)
+        self.ws = torch.empty(max(group.ws_cg, 1), dtype=torch.uint8, device=group.device)
+        torch.cuda.synchronize(group.device)
+        h = _vp()
+        with torch.cuda.device(group.device):
+            _check(lib().radon_multi_cg_graph(group._h, _vp(self.rhs.data_ptr()),
+                                              _vp(self.x.data_ptr()), int(n_iter), float(rtol),
+                                              _vp(self.ws.data_ptr()), self.ws.numel(),
+                                              _vp(self.info.data_ptr()), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().radon_graph_launch(self._h, self.group._stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _torch().cuda.synchronize(self.group.device)
+            except Exception:
+                pass
+            _lib.radon_graph_destroy(h)
+            self._h = None
 
 
 def decode_cg_info(info) -> list[dict]:

@@ -1,0 +1,231 @@
+// Device-side bodies of the sparse products, shared by the single-operator
+// kernels (apply.hip) and the multi-operator kernels (multi.hip).
+#pragma once
+
+#include "internal.hpp"
+
+namespace sct {
+
+// xT[b][ix][iy] = x[b][iy][ix] through a padded 32x32 LDS tile.
+template <class T>
+__global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ x, T *__restrict__ xT,
+                                                   int n, int64_t nn)
+{
+    __shared__ T tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int64_t boff = int64_t(blockIdx.z) * nn;
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int iy = by + i, ix = bx + threadIdx.x;
+        if (iy < n && ix < n) tile[i][threadIdx.x] = x[boff + int64_t(iy) * n + ix];
+    }
+    __syncthreads();
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int ix = bx + i, iy = by + threadIdx.x;
+        if (ix < n && iy < n) xT[boff + int64_t(ix) * n + iy] = tile[threadIdx.x][i];
+    }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+template <class T> struct Quad;
+template <> struct Quad<float> { using type = f32x4; };
+template <> struct Quad<double> { using type = f64x4; };
+
+// Two adjacent vector elements fetched with one 16-byte load (8-byte aligned).
+typedef double f64x2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f32x2u __attribute__((ext_vector_type(2), aligned(4)));
+template <class T> struct PairU;
+template <> struct PairU<float> { using type = f32x2u; };
+template <> struct PairU<double> { using type = f64x2u; };
+
+// The matrix streams are read exactly once per product: non-temporal loads
+// keep them from evicting the gathered vector from the caches.
+template <class V>
+__device__ inline V stream_load(const V *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// One workgroup of W waves per ray bundle (block -> bundle through `order`,
+// which places bundles of rays closer to vertical and closer to horizontal on
+// different XCDs, so each XCD's L2 caches only x or only its transpose).
+// Lane = (quad offset q in 0..3, ray r in 0..15): a lane reads a quad (4
+// consecutive major lines of its ray) with 16-byte loads, the 64 lanes of a
+// wave read 64 consecutive quads, and the 16 lanes of one q gather from the
+// same image line at neighbouring positions.  Wave w covers its share of the
+// bundle's quads; partial sums are combined over q with shuffles and over the
+// waves in LDS, in a fixed order.
+// Several right-hand sides: blockIdx.y selects a chunk of up to BC images that
+// share every matrix load (the fused multi-RHS product), one accumulator each.
+// fwd_bundle does one bundle for up to BC images (img and y point at the
+// first image of the chunk, nbc of them present); k_fwd loops over the
+// bundles of one operator, k_multi_fwd over those of several.
+template <class TM, class TV, int W, int BC>
+__device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *__restrict__ idx,
+                                           const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                           const TV *__restrict__ img, TV *__restrict__ y, int n,
+                                           int64_t nn, int64_t rows, int nbc)
+{
+    using Q = typename Quad<TM>::type;
+    using P = typename PairU<TV>::type;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int nq = d.nrows >> 2;
+    const int s0 = (nq * wave) / W, s1 = (nq * (wave + 1)) / W;
+    const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
+    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
+    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
+    TV acc[BC];
+#pragma unroll
+    for (int c = 0; c < BC; ++c) acc[c] = TV(0);
+#pragma unroll 2
+    for (int tq = s0 + q; tq < s1; tq += 4) {
+        const int e = tq * kFwdLanes + r;
+        const u16x4 i4 = stream_load(I + e);
+        const Q a4 = stream_load(A + e);
+        const Q b4 = stream_load(Bv + e);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int m = min(d.m0 + 4 * tq + k, n - 1);
+            const int i0 = i4[k];
+            // one load for both pixels; a slot at the last column has no
+            // second pixel (weight 0), so the pair starts at n-2 there
+            const int ic = i0 < n - 1 ? i0 : (n >= 2 ? n - 2 : 0);
+            const int64_t at = int64_t(m) * n + ic;
+#pragma unroll
+            for (int c = 0; c < BC; ++c) {
+                if (BC == 1 || c < nbc) {
+                    const TV *__restrict__ line = img + int64_t(c) * nn;
+                    if (n >= 2) {
+                        const P pr = *reinterpret_cast<const P *>(line + at);
+                        acc[c] = fma(TV(a4[k]), i0 == ic ? pr.x : pr.y, acc[c]);
+                        acc[c] = fma(TV(b4[k]), pr.y, acc[c]);
+                    } else {
+                        acc[c] = fma(TV(a4[k]), line[0], acc[c]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < BC; ++c) {
+        acc[c] += __shfl_xor(acc[c], 16);
+        acc[c] += __shfl_xor(acc[c], 32);
+    }
+    if constexpr (W > 1) {
+        __shared__ TV red[W][BC][kFwdLanes];
+        if (q == 0) {
+#pragma unroll
+            for (int c = 0; c < BC; ++c) red[wave][c][r] = acc[c];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int c = 0; c < BC; ++c) {
+                acc[c] = red[0][c][r];
+#pragma unroll
+                for (int w = 1; w < W; ++w) acc[c] += red[w][c][r];
+            }
+        }
+        __syncthreads();   // red is reused by the next bundle
+    }
+    if (wave == 0 && q == 0 && r < d.nrays) {
+#pragma unroll
+        for (int c = 0; c < BC; ++c)
+            if (c < nbc) y[int64_t(c) * rows + d.ray0 + r] = acc[c];
+    }
+}
+
+template <class T>
+__device__ inline T ktk_at(const T *__restrict__ xb, int64_t j, int n, T xj)
+{
+    const int iy = int(j / n), ix = int(j % n);
+    T k = T(0);
+    if (ix > 0) k += xj - xb[j - 1];
+    if (ix < n - 1) k += xj - xb[j + 1];
+    if (iy > 0) k += xj - xb[j - n];
+    if (iy < n - 1) k += xj - xb[j + n];
+    return k;
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Single right-hand side adjoint sum for 8x8 tile g (the layout and the band
+// staging are described at k_adj below): returns the tile's 64 sums in the
+// lanes of wave 0 (other waves return their own share).  `band` is this
+// block's [W][4][kAdjBand] LDS staging area.
+template <class TM, class T, int W>
+__device__ __forceinline__ T adj_tile1(int64_t g, const uint32_t *__restrict__ Rl,
+                                       const uint16_t *__restrict__ base,
+                                       const typename Quad<TM>::type *__restrict__ A,
+                                       const typename Quad<TM>::type *__restrict__ Bv, int n_meas,
+                                       int n_aq, int nb, const T *__restrict__ yb, T *band)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q0 = (n_aq * wave) / W, q1 = (n_aq * (wave + 1)) / W;
+    const int kk = lane >> 4, ee = lane & 15;   // this lane's band element
+    T *__restrict__ my = band + wave * 4 * kAdjBand;
+    T acc = T(0);
+#pragma unroll 2
+    for (int aq = q0; aq < q1; ++aq) {
+        const int64_t gq = g * n_aq + aq;
+        const int a_band = min(4 * aq + kk, n_meas - 1);
+        const int b_band = min(int(base[gq * 4 + kk]) + ee, nb - 1);
+        const T yv = yb[int64_t(a_band) * nb + b_band];
+        const int64_t e = gq * kAdjLanes + lane;
+        const uint32_t r4 = stream_load(Rl + e);
+        const auto a4 = stream_load(A + e);
+        const auto c4 = stream_load(Bv + e);
+        my[lane] = yv;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int rb = int((r4 >> (8 * k)) & 0xffu);
+            acc = fma(T(a4[k]), my[k * kAdjBand + rb], acc);
+            acc = fma(T(c4[k]), my[k * kAdjBand + rb + 1], acc);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if constexpr (W > 1) {
+        __shared__ T red[W][64];
+        red[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0) {
+            acc = red[0][lane];
+#pragma unroll
+            for (int w = 1; w < W; ++w) acc += red[w][lane];
+        }
+        __syncthreads();   // red is reused by the next tile
+    }
+    return acc;
+}
+
+// Epilogue of tile g for wave 0's lane: out = alpha*acc + lambda*(K^T K x) +
+// sigma*x; returns x_j * out_j (0 outside the image or without x).
+template <class T>
+__device__ __forceinline__ double adj_epilogue(int64_t g, int lane, T acc, const T *__restrict__ xb,
+                                               T *__restrict__ ob, T alpha, T lambda, T sigma,
+                                               int n, int tiles)
+{
+    const int iy = int(g / tiles) * 8 + (lane >> 3), ix = int(g % tiles) * 8 + (lane & 7);
+    if (iy >= n || ix >= n) return 0.0;
+    const int64_t j = int64_t(iy) * n + ix;
+    T o = alpha * acc;
+    double d = 0.0;
+    if (xb) {
+        const T xj = xb[j];
+        if (lambda != T(0)) o += lambda * ktk_at(xb, j, n, xj);
+        if (sigma != T(0)) o += sigma * xj;
+        d = double(xj) * double(o);
+    }
+    ob[j] = o;
+    return d;
+}
+
+}  // namespace sct

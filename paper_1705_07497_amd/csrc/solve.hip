@@ -7,56 +7,16 @@
 // beta_k live in FP64 on the device and are updated by single-block kernels,
 // so nothing is read back to the host inside a solve.  Every reduction sums
 // FP64 partials in a fixed order, which makes runs bitwise reproducible.
-#include "internal.hpp"
+#include "cg.hpp"
 
 #include <cmath>
 
 namespace sct {
 
-// Per right-hand side CG state at the start of an iteration, in a two-slot
-// ring indexed by iteration parity: every kernel reads slot it%2 and only a
-// later kernel writes slot (it+1)%2, so no kernel reads what it writes.
-struct CgState {
-    double rho, rho0;
-    int32_t stopped, iters, breakdown, pad;
-};
-
-// Result of the step-length decision of one iteration (also a 2-slot ring).
-struct CgStep {
-    double a, gamma;
-    int32_t stopped, pad;
-};
-
 struct SbScal {
     double first, upd_b, upd_u;
     int32_t outer, stop, breakdowns, pad;
 };
-
-constexpr int kVecThreads = 256;
-
-static int vec_blocks(int64_t nn)
-{
-    const int64_t b = (nn + 4 * kVecThreads - 1) / (4 * kVecThreads);
-    return int(b < 1 ? 1 : (b > 1024 ? 1024 : b));
-}
-
-static int tiles_of(int n) { return (n + 31) / 32; }
-
-__device__ inline double block_sum(double v, double *red)
-{
-    // fixed-order tree over the block (blockDim.x * blockDim.y threads, a power of two)
-    const int nt = blockDim.x * blockDim.y;
-    const int t = threadIdx.y * blockDim.x + threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int o = nt / 2; o >= 1; o >>= 1) {
-        if (t < o) red[t] += red[t + o];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
 
 // ---------------------------------------------------------------------------
 // CG kernels
@@ -97,13 +57,6 @@ __global__ __launch_bounds__(256) void k_cg_start(const T *__restrict__ r, T *__
         part[int64_t(blockIdx.z) * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = tot;
 }
 
-__device__ inline double sum_part_block(const double *__restrict__ part, int64_t count, double *red)
-{
-    double v = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) v += part[i];
-    return block_sum(v, red);
-}
-
 // rho_0 = sum of partials; resets the per-solve state (ring slot 0).  A set
 // SB stop flag starts the solve stopped (the outer loop has finished).
 __global__ __launch_bounds__(256) void k_cg_begin(const double *__restrict__ part, int64_t count,
@@ -139,14 +92,8 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_xr(
     __shared__ double red[kVecThreads];
     const int64_t b = blockIdx.y;
     const double gamma = sum_part_block(part_adj + b * n_adj, n_adj, red);
-    const CgState c = st[b];
-    int stop = c.stopped;
-    double a = 0.0;
-    if (!stop) {
-        if (c.rho == 0.0 || (rtol > 0.0 && sqrt(c.rho) <= rtol * sqrt(c.rho0))) stop = 1;
-        else if (!(gamma > 0.0) || !isfinite(gamma)) stop = 2;   // breakdown
-        else a = c.rho / gamma;
-    }
+    double a;
+    const int stop = cg_decide(st[b], gamma, rtol, &a);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         CgStep o;
         o.a = a;
@@ -240,14 +187,6 @@ __global__ void k_cg_info(const CgState *__restrict__ st, radon_cg_info *__restr
     info[b] = o;
 }
 
-template <class T>
-__global__ __launch_bounds__(kVecThreads) void k_fill(T *__restrict__ x, T v, int64_t count)
-{
-    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < count;
-         i += int64_t(gridDim.x) * kVecThreads)
-        x[i] = v;
-}
-
 // r = a - b (a may alias r)
 template <class T>
 __global__ __launch_bounds__(kVecThreads) void k_sub(const T *a, const T *__restrict__ b, T *r,
@@ -256,15 +195,6 @@ __global__ __launch_bounds__(kVecThreads) void k_sub(const T *a, const T *__rest
     for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < count;
          i += int64_t(gridDim.x) * kVecThreads)
         r[i] = a[i] - b[i];
-}
-
-template <class T>
-__global__ __launch_bounds__(kVecThreads) void k_copy(const T *__restrict__ a, T *__restrict__ r,
-                                                       int64_t count)
-{
-    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < count;
-         i += int64_t(gridDim.x) * kVecThreads)
-        r[i] = a[i];
 }
 
 // ---------------------------------------------------------------------------

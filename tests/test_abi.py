@@ -104,3 +104,28 @@ def test_binding_refuses_without_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(sct.SparsectError):
         sct.RadonOp(8, 4, 13)
+
+
+def test_group_and_graph_entry_points_validate_without_gpu():
+    L = sct.lib()
+    h = ctypes.c_void_p()
+    assert L.radon_multi_create(None, 1, None, None, None, ctypes.byref(h)) == -1
+    assert "ops is NULL" in L.radon_last_error().decode()
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.radon_multi_create(arr, 0, None, None, None, ctypes.byref(h)) == -1
+    assert "count" in L.radon_last_error().decode()
+    assert L.radon_multi_create(arr, 1, None, None, None, ctypes.byref(h)) == -1
+    assert L.radon_multi_create(arr, 1, None, None, None, None) == -1
+    assert L.radon_multi_info(None, None, None, None, None, None) == -1
+    assert L.radon_multi_apply(None, 0, None, None, None, 0, None) == -1
+    assert L.radon_multi_cg(None, None, None, 1, 0.0, None, 0, None, None) == -1
+    assert L.radon_multi_cg_graph(None, None, None, 1, 0.0, None, 0, None, ctypes.byref(h)) == -1
+    assert L.radon_graph_launch(None, None) == -1
+    L.radon_graph_destroy(None)
+    L.radon_multi_destroy(None)
+    t, wf, wv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    assert L.radon_unrolled_sizes(None, 10, 5, 1, ctypes.byref(t), ctypes.byref(wf),
+                                  ctypes.byref(wv)) == -1
+    assert L.cg_unrolled(None, 1.0, 0.0, 1.0, None, None, 1, 10, 5, None, 0, None, 0, None) == -1
+    assert L.cg_unrolled_vjp(None, 1.0, 0.0, 1.0, None, 0, None, None, 1, 10, 5, None, 0,
+                             None) == -1
