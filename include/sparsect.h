@@ -85,6 +85,10 @@ typedef struct {
     int64_t device_bytes;       /* device memory held by the operator */
     int32_t dtype;
     int32_t n, n_angles, n_bins;
+    int32_t needs_transpose;    /* 1: some measured angle is closer to horizontal
+                                   than vertical, so the forward product gathers
+                                   from the transposed image too */
+    int32_t reserved;
 } radon_info;
 
 /*
@@ -146,6 +150,16 @@ int64_t radon_workspace_bytes(const radon_op *op, int32_t which, int32_t batch);
  */
 int radon_fwd(const radon_op *op, const void *x, void *y, int32_t batch,
               void *ws, int64_t ws_bytes, void *stream);
+
+/*
+ * radon_fwd_xt -- y = M R x when the caller already holds the transposed
+ * images xT[b][ix][iy] = x[b][iy][ix] (device [batch][n*n]; NULL allowed
+ * only when no measured angle is closer to horizontal than vertical, see
+ * radon_op_info).  This is the single kernel radon_fwd runs after its
+ * transpose; CG keeps the transposed direction up to date itself.
+ */
+int radon_fwd_xt(const radon_op *op, const void *x, const void *xT, void *y, int32_t batch,
+                 void *stream);
 
 /*
  * radon_adj -- x = R^T M^T y (the adjoint in eq:KKT, eq:PD_resolve,

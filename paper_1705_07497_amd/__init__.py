@@ -44,7 +44,8 @@ class _Info(ctypes.Structure):
                 ("n_meas_rays", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("fwd_slots", ctypes.c_int64), ("adj_slots", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("dtype", ctypes.c_int32),
-                ("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32)]
+                ("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("needs_transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CgInfo(ctypes.Structure):
@@ -81,6 +82,7 @@ SIGNATURES = {
     "radon_workspace_bytes": (ctypes.c_int64, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "radon_fwd": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
     "radon_adj": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
+    "radon_fwd_xt": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp]),
     "normal_apply": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
                                     _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
     "cg_solve": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
@@ -200,6 +202,7 @@ class RadonOp:
         self.info = OpInfo(inf.n_pixels, inf.n_meas_angles, inf.n_meas_rays, inf.nnz, inf.fwd_slots,
                            inf.adj_slots, inf.device_bytes)
         self.rows = inf.n_meas_rays
+        self.needs_transpose = bool(inf.needs_transpose)
         self.nn = inf.n_pixels
         self._ws = {}
         if tuning == "cache":
@@ -287,6 +290,17 @@ class RadonOp:
         self._sino(y, "out")
         ws, nb = self.workspace(WS_FWD, b)
         _check(lib().radon_fwd(self._h, self._p(x), self._p(y), b, self._p(ws), nb, self._stream()))
+        return y
+
+    def fwd_xt(self, x, xT, out=None):
+        """y = M R x from x and its transposed copy xT (the forward kernel alone)."""
+        torch = _torch()
+        b = self._img(x)
+        if xT is not None and self._img(xT, "xT") != b:
+            raise SparsectError("xT must hold as many images as x")
+        y = torch.empty((b, self.rows), dtype=self.dtype, device=self.device) if out is None else out
+        self._sino(y, "out")
+        _check(lib().radon_fwd_xt(self._h, self._p(x), self._p(xT), self._p(y), b, self._stream()))
         return y
 
     def adj(self, y, out=None):

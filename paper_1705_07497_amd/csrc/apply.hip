@@ -382,6 +382,24 @@ extern "C" int radon_fwd(const radon_op *p, const void *x, void *y, int32_t batc
     });
 }
 
+extern "C" int radon_fwd_xt(const radon_op *p, const void *x, const void *xT, void *y,
+                            int32_t batch, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!x || !y) return set_error(RADON_EINVAL, "x and y must be non-NULL");
+    const Op &op = *as_op(p);
+    if (op.need_T && !xT)
+        return set_error(RADON_EINVAL, "this geometry gathers from the transposed image: xT is required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return launch_fwd<TM, TV>(op, static_cast<const TV *>(x), static_cast<const TV *>(xT),
+                                  static_cast<TV *>(y), batch, s);
+    });
+}
+
 extern "C" int radon_adj(const radon_op *p, const void *y, void *x, int32_t batch, void *stream)
 {
     clear_error();

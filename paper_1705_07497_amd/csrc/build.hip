@@ -659,6 +659,8 @@ extern "C" int radon_op_info(const radon_op *p, radon_info *out)
     out->n = op->n;
     out->n_angles = op->n_angles;
     out->n_bins = op->n_bins;
+    out->needs_transpose = op->need_T ? 1 : 0;
+    out->reserved = 0;
     return RADON_OK;
 }
 

@@ -134,10 +134,11 @@ __global__ __launch_bounds__(64 * W) void k_multi_adj(const int64_t *__restrict_
     const int64_t n_grp = grp_start[count];
     const int64_t G = gridDim.x;
     int cur = -1;
+    int64_t cur_lo = 0, cur_hi = 0;   // tile groups of instance cur
     double dsum = 0.0;
     for (int64_t g = blockIdx.x; g < n_grp; g += G) {
-        const int i = find_inst(grp_start, count, g);
-        if (i != cur) {
+        if (g >= cur_hi) {   // g only grows: search when it leaves the current instance
+            const int i = find_inst(grp_start, count, g);
             if (part && wave == 0) {
                 if (cur >= 0) {
                     const double v = wave_sum(dsum);
@@ -147,10 +148,12 @@ __global__ __launch_bounds__(64 * W) void k_multi_adj(const int64_t *__restrict_
                     if (lane == 0) part[int64_t(k) * G + blockIdx.x] = 0.0;
             }
             cur = i;
+            cur_lo = grp_start[i];
+            cur_hi = grp_start[i + 1];
             dsum = 0.0;
         }
-        const MultiInst &I = inst[i];
-        const int64_t gl = g - grp_start[i];
+        const MultiInst &I = inst[cur];
+        const int64_t gl = g - cur_lo;
         const T acc = adj_tile1<TM, T, W>(gl, reinterpret_cast<const uint32_t *>(I.a_rel), I.a_base,
                                           static_cast<const Q *>(I.a_v0),
                                           static_cast<const Q *>(I.a_v1), I.n_meas, I.n_aq, I.nb,

@@ -42,6 +42,7 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct.CgInfo) == 24
     assert ctypes.sizeof(sct.SbParams) == 40
     assert ctypes.sizeof(sct.SbInfo) == 32
+    assert ctypes.sizeof(sct._Info) == 80
 
 
 def _build(n, na, nb, dtype=0, measured=None):

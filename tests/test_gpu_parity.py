@@ -125,6 +125,23 @@ def test_adjoint_identity_fp64():
     assert abs(Rx @ y - x @ Rty) <= 1e-12 * np.linalg.norm(Rx) * np.linalg.norm(y)
 
 
+@pytest.mark.parametrize("geom", [(64, 45, 91, 1), (33, 10, 47, 2), (8, 1, 13, 1)], ids=_ids)
+def test_forward_kernel_with_caller_transpose(geom):
+    """radon_fwd_xt (the caller holds the transposed image) equals radon_fwd
+    bitwise; without xT it is refused where some angle needs it."""
+    n, na, nb, ev = geom
+    op = make_op(n, na, nb, W.angle_mask(na, ev), "mixed")
+    rng = np.random.default_rng(6)
+    X = to_dev(rng.standard_normal((3, n * n)), F64)
+    XT = X.reshape(3, n, n).transpose(1, 2).contiguous().reshape(3, -1)
+    assert torch.equal(op.fwd_xt(X, XT), op.fwd(X))
+    if op.needs_transpose:
+        with pytest.raises(sct.SparsectError, match="transposed"):
+            op.fwd_xt(X, None)
+    else:
+        assert torch.equal(op.fwd_xt(X, None), op.fwd(X))
+
+
 @pytest.mark.parametrize("batch", [4, 8, 16, 21])
 @pytest.mark.parametrize("mode", ["mixed", "f32"])
 def test_fused_batch_products_equal_single_image(batch, mode):
