@@ -327,10 +327,12 @@ void radon_multi_destroy(radon_multi *m);
 /*
  * radon_multi_info -- packed-vector offsets (host int64[count+1] each, NULL
  * to skip), workspace bytes of radon_multi_apply and radon_multi_cg, and the
- * waves per 8x8 tile the group's adjoint uses.
+ * waves per ray bundle and per 8x8 tile the group's products use (a single
+ * operator tuned to the same counts computes bitwise the same products).
  */
 int radon_multi_info(const radon_multi *m, int64_t *img_off, int64_t *sino_off,
-                     int64_t *ws_products, int64_t *ws_cg, int32_t *adj_waves);
+                     int64_t *ws_products, int64_t *ws_cg, int32_t *fwd_waves,
+                     int32_t *adj_waves);
 
 /*
  * radon_multi_apply -- which = 0: y_i = M_i R_i x_i (in: packed images, out:

@@ -105,7 +105,8 @@ SIGNATURES = {
                                           ctypes.POINTER(_vp)]),
     "radon_multi_destroy": (None, [_vp]),
     "radon_multi_info": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64),
-                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "radon_multi_apply": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "radon_multi_cg": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, _vp,
                                       ctypes.c_int64, _vp, _vp]),
@@ -453,11 +454,12 @@ class RadonMulti:
         self._h = h
         self.img_off = np.zeros(k + 1, dtype=np.int64)
         self.sino_off = np.zeros(k + 1, dtype=np.int64)
-        wp, wc, aw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        wp, wc, fw, aw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().radon_multi_info(self._h, self.img_off.ctypes.data_as(_vp),
                                       self.sino_off.ctypes.data_as(_vp), ctypes.byref(wp),
-                                      ctypes.byref(wc), ctypes.byref(aw)))
-        self.ws_products, self.ws_cg, self.adj_waves = int(wp.value), int(wc.value), int(aw.value)
+                                      ctypes.byref(wc), ctypes.byref(fw), ctypes.byref(aw)))
+        self.ws_products, self.ws_cg = int(wp.value), int(wc.value)
+        self.fwd_waves, self.adj_waves = int(fw.value), int(aw.value)
         self._ws = {}
 
     def __del__(self):

@@ -17,7 +17,7 @@ import hashlib
 import json
 import os
 
-DEFAULT = {"fwd_waves": 4, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8}
+DEFAULT = {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8}
 
 
 def cache_path() -> str:

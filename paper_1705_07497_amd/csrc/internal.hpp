@@ -91,7 +91,7 @@ struct Op {
     int64_t device_bytes = 0;
     std::vector<void *> owned;       // every hipMalloc of the handle
 
-    radon_tuning tune{4, 0, 4, 8};   // launch tuning (see radon_set_tuning)
+    radon_tuning tune{2, 0, 4, 8};   // launch tuning (see radon_set_tuning)
 };
 
 // thread-local error state

@@ -94,24 +94,53 @@ __global__ __launch_bounds__(256) void k_multi_transpose(const T *__restrict__ x
     }
 }
 
-// Forward products of every instance: persistent loop over the concatenated
-// (instance, bundle) list.  Each instance's segment keeps its XCD-aware order
-// and starts at a multiple of 8, and the grid is a multiple of 8, so block i
-// stays on XCD i % 8 as in the single-operator product.
+// Ticket counters of the group forward: one per XCD, each on its own
+// 256-byte line (device-scope atomics on one line serialize at one channel).
+constexpr int kTicketStride = 64;
+
+__global__ void k_multi_reset(uint32_t *__restrict__ tickets)
+{
+    if (threadIdx.x < 8) tickets[threadIdx.x * kTicketStride] = 0u;
+}
+
+// Forward products of every instance over the concatenated (instance, bundle)
+// list.  Each instance's segment keeps its XCD-aware order and starts at a
+// multiple of 8; the grid is a multiple of 8, so block i runs on XCD i % 8 and
+// takes only entries o with o % 8 == i % 8, as in the single-operator product.
+// The entries are handed out in list order through one ticket counter per
+// XCD: a static round-robin would let blocks drift apart over the instances,
+// keeping many instances' images live in the caches at once.
 template <class TM, class TV, int W>
 __global__ __launch_bounds__(64 * W) void k_multi_fwd(const int2 *__restrict__ work, int64_t n_work,
                                                       const MultiInst *__restrict__ inst,
                                                       const TV *__restrict__ x,
-                                                      const TV *__restrict__ xT, TV *__restrict__ y)
+                                                      const TV *__restrict__ xT, TV *__restrict__ y,
+                                                      uint32_t *__restrict__ tickets)
 {
-    for (int64_t o = blockIdx.x; o < n_work; o += gridDim.x) {
+    __shared__ int64_t next;
+    const int xcd = int(blockIdx.x & 7u);
+    uint32_t *const counter = tickets + xcd * kTicketStride;
+    if (threadIdx.x == 0) next = 8 * int64_t(atomicAdd(counter, 1u)) + xcd;
+    __syncthreads();
+    int64_t o = next;
+    while (o < n_work) {
+        // the following ticket is taken now and read only after this bundle,
+        // so the atomic's round trip overlaps the bundle's work
+        uint32_t ticket = 0;
+        if (threadIdx.x == 0) ticket = atomicAdd(counter, 1u);
         const int2 w = work[o];
-        if (w.y < 0) continue;   // padding entry (uniform per block)
-        const MultiInst &I = inst[w.x];
-        const FwdBundle d = I.fb[w.y];
-        fwd_bundle<TM, TV, W, 1>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
-                                 static_cast<const TM *>(I.f_v1), (d.horiz ? xT : x) + I.img_off,
-                                 y + I.sino_off, I.n, I.nn, I.rows, 1);
+        if (w.y >= 0) {   // uniform per block; padding entries carry no bundle
+            const MultiInst &I = inst[w.x];
+            const FwdBundle d = I.fb[w.y];
+            fwd_bundle<TM, TV, W, 1>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
+                                     static_cast<const TM *>(I.f_v1),
+                                     (d.horiz ? xT : x) + I.img_off, y + I.sino_off, I.n, I.nn,
+                                     I.rows, 1);
+        }
+        __syncthreads();   // every wave has read `next`
+        if (threadIdx.x == 0) next = 8 * int64_t(ticket) + xcd;
+        __syncthreads();
+        o = next;
     }
 }
 
@@ -367,11 +396,15 @@ __global__ void k_multi_info(const CgState *__restrict__ st, radon_cg_info *__re
 // host side
 // ---------------------------------------------------------------------------
 
+// waves per ray bundle of the group forward (the single-operator default)
+constexpr int kMultiFwdWaves = 2;
+
 static int64_t adj_grid(const Multi &m) { return m.n_grp < kPersistentBlocks ? m.n_grp : kPersistentBlocks; }
 static int64_t fwd_grid(const Multi &m) { return m.n_fwork < kPersistentBlocks ? m.n_fwork : kPersistentBlocks; }
 
 template <class T>
 struct MultiBufs {
+    uint32_t *tickets = nullptr;                   // [8 * kTicketStride] forward work counters
     T *xT = nullptr, *y = nullptr;                 // products
     T *r = nullptr, *p = nullptr, *pT = nullptr, *q = nullptr;
     double *part_adj = nullptr, *part_t = nullptr, *part_vb = nullptr;
@@ -383,6 +416,7 @@ template <class T>
 static void carve_multi(const Multi &m, bool cg, Carver &c, MultiBufs<T> &w)
 {
     const int64_t ni = m.img_off[size_t(m.count)], ns = m.sino_off[size_t(m.count)];
+    w.tickets = c.take<uint32_t>(8 * kTicketStride);
     w.y = c.take<T>(ns);
     if (!cg) {
         w.xT = m.any_T ? c.take<T>(ni) : nullptr;
@@ -413,10 +447,13 @@ static int64_t multi_ws_bytes(const Multi &m, bool cg)
 }
 
 template <class TM, class TV>
-static int multi_launch_fwd(const Multi &m, const TV *x, const TV *xT, TV *y, hipStream_t s)
+static int multi_launch_fwd(const Multi &m, const TV *x, const TV *xT, TV *y, uint32_t *tickets,
+                            hipStream_t s)
 {
-    k_multi_fwd<TM, TV, 4><<<unsigned(fwd_grid(m)), 256, 0, s>>>(m.fwork, m.n_fwork, m.inst, x,
-                                                                  xT ? xT : x, y);
+    k_multi_reset<<<1, 64, 0, s>>>(tickets);
+    SCT_TRY(check_launch("k_multi_reset"));
+    k_multi_fwd<TM, TV, kMultiFwdWaves><<<unsigned(fwd_grid(m)), 64 * kMultiFwdWaves, 0, s>>>(
+        m.fwork, m.n_fwork, m.inst, x, xT ? xT : x, y, tickets);
     return check_launch("k_multi_fwd");
 }
 
@@ -458,12 +495,12 @@ static int multi_products(const Multi &m, int which, const void *in, void *out_v
     TV *out = static_cast<TV *>(out_v);
     if (which == 0) {   // forward
         SCT_TRY(multi_launch_transpose<TV>(m, x, w.xT, s));
-        return multi_launch_fwd<TM, TV>(m, x, w.xT, out, s);
+        return multi_launch_fwd<TM, TV>(m, x, w.xT, out, w.tickets, s);
     }
     if (which == 1)     // adjoint
         return multi_launch_adj<TM, TV>(m, x, nullptr, out, 0, nullptr, s);
     SCT_TRY(multi_launch_transpose<TV>(m, x, w.xT, s));   // normal operator
-    SCT_TRY((multi_launch_fwd<TM, TV>(m, x, w.xT, w.y, s)));
+    SCT_TRY((multi_launch_fwd<TM, TV>(m, x, w.xT, w.y, w.tickets, s)));
     return multi_launch_adj<TM, TV>(m, w.y, x, out, 1, nullptr, s);
 }
 
@@ -489,7 +526,7 @@ static int multi_cg(const Multi &m, const void *rhs_v, void *x_v, int n_iter, do
     SCT_TRY(check_launch("k_multi_begin"));
     for (int it = 0; it < n_iter; ++it) {
         CgState *cur = w.st + int64_t(it & 1) * m.count, *nxt = w.st + int64_t((it + 1) & 1) * m.count;
-        SCT_TRY((multi_launch_fwd<TM, TV>(m, w.p, w.pT, w.y, s)));
+        SCT_TRY((multi_launch_fwd<TM, TV>(m, w.p, w.pT, w.y, w.tickets, s)));
         SCT_TRY((multi_launch_adj<TM, TV>(m, w.y, w.p, w.q, 1, w.part_adj, s)));
         k_multi_gamma<<<unsigned(m.count), 256, 0, s>>>(w.part_adj, adj_grid(m), cur, w.step, rtol);
         SCT_TRY(check_launch("k_multi_gamma"));
@@ -594,6 +631,8 @@ static int build_multi(Multi &m, const radon_op *const *ops, int count, const do
     m.n_fwork = int64_t(work.size());
     if (m.n_t32 > 0x7fffffffLL || m.n_vb > 0x7fffffffLL)
         return set_error(RADON_EUNSUPPORTED, "too many vector tiles in one group");
+    // the single-operator rule (by measured angles) applied to the mean over
+    // the instances (weighting by the instances' adjoint work measured slower)
     const int64_t avg = meas_sum / count;
     m.adj_w = avg >= 128 ? 4 : (avg >= 48 ? 2 : 1);
     SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.inst), int64_t(sizeof(MultiInst)) * count));
@@ -648,7 +687,8 @@ extern "C" int radon_multi_create(const radon_op *const *ops, int32_t count, con
 extern "C" void radon_multi_destroy(radon_multi *p) { free_multi(reinterpret_cast<Multi *>(p)); }
 
 extern "C" int radon_multi_info(const radon_multi *p, int64_t *img_off, int64_t *sino_off,
-                                int64_t *ws_products, int64_t *ws_cg, int32_t *adj_waves)
+                                int64_t *ws_products, int64_t *ws_cg, int32_t *fwd_waves,
+                                int32_t *adj_waves)
 {
     clear_error();
     SCT_TRY(check_multi(p));
@@ -659,6 +699,7 @@ extern "C" int radon_multi_info(const radon_multi *p, int64_t *img_off, int64_t 
     }
     if (ws_products) *ws_products = multi_ws_bytes(m, false);
     if (ws_cg) *ws_cg = multi_ws_bytes(m, true);
+    if (fwd_waves) *fwd_waves = kMultiFwdWaves;
     if (adj_waves) *adj_waves = m.adj_w;
     return RADON_OK;
 }

@@ -58,27 +58,20 @@ __device__ inline V stream_load(const V *p)
 // waves in LDS, in a fixed order.
 // Several right-hand sides: blockIdx.y selects a chunk of up to BC images that
 // share every matrix load (the fused multi-RHS product), one accumulator each.
-// fwd_bundle does one bundle for up to BC images (img and y point at the
-// first image of the chunk, nbc of them present); k_fwd loops over the
-// bundles of one operator, k_multi_fwd over those of several.
-template <class TM, class TV, int W, int BC>
-__device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *__restrict__ idx,
-                                           const TM *__restrict__ v0, const TM *__restrict__ v1,
-                                           const TV *__restrict__ img, TV *__restrict__ y, int n,
-                                           int64_t nn, int64_t rows, int nbc)
+// The quads of wave shares [s0, s1) of one bundle for up to BC images.
+// PAIR (n >= 2): one 16-byte load fetches both pixels of a slot; a slot at
+// the last column has no second pixel (weight 0), so its pair starts at n-2.
+// The test is a template parameter so that the loop body has no branch: a
+// branch around each gather makes every gather wait for all loads in flight.
+template <class TM, class TV, int BC, bool PAIR>
+__device__ __forceinline__ void fwd_quads(const FwdBundle &d, const u16x4 *__restrict__ I,
+                                          const typename Quad<TM>::type *__restrict__ A,
+                                          const typename Quad<TM>::type *__restrict__ Bv,
+                                          const TV *__restrict__ img, int n, int64_t nn, int nbc,
+                                          int s0, int s1, int q, int r, TV *acc)
 {
     using Q = typename Quad<TM>::type;
     using P = typename PairU<TV>::type;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = lane & 15, q = lane >> 4;
-    const int nq = d.nrows >> 2;
-    const int s0 = (nq * wave) / W, s1 = (nq * (wave + 1)) / W;
-    const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
-    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
-    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
-    TV acc[BC];
-#pragma unroll
-    for (int c = 0; c < BC; ++c) acc[c] = TV(0);
 #pragma unroll 2
     for (int tq = s0 + q; tq < s1; tq += 4) {
         const int e = tq * kFwdLanes + r;
@@ -89,15 +82,13 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
         for (int k = 0; k < 4; ++k) {
             const int m = min(d.m0 + 4 * tq + k, n - 1);
             const int i0 = i4[k];
-            // one load for both pixels; a slot at the last column has no
-            // second pixel (weight 0), so the pair starts at n-2 there
-            const int ic = i0 < n - 1 ? i0 : (n >= 2 ? n - 2 : 0);
+            const int ic = PAIR ? (i0 < n - 1 ? i0 : n - 2) : 0;
             const int64_t at = int64_t(m) * n + ic;
 #pragma unroll
             for (int c = 0; c < BC; ++c) {
                 if (BC == 1 || c < nbc) {
                     const TV *__restrict__ line = img + int64_t(c) * nn;
-                    if (n >= 2) {
+                    if constexpr (PAIR) {
                         const P pr = *reinterpret_cast<const P *>(line + at);
                         acc[c] = fma(TV(a4[k]), i0 == ic ? pr.x : pr.y, acc[c]);
                         acc[c] = fma(TV(b4[k]), pr.y, acc[c]);
@@ -108,6 +99,33 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
             }
         }
     }
+}
+
+// fwd_bundle does one bundle for up to BC images (img and y point at the
+// first image of the chunk, nbc of them present); k_fwd loops over the
+// bundles of one operator, k_multi_fwd over those of several.
+template <class TM, class TV, int W, int BC>
+__device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *__restrict__ idx,
+                                           const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                           const TV *__restrict__ img, TV *__restrict__ y, int n,
+                                           int64_t nn, int64_t rows, int nbc)
+{
+    using Q = typename Quad<TM>::type;
+    // the wave index is uniform: readfirstlane lets the compiler see that
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int nq = d.nrows >> 2;
+    const int s0 = (nq * wave) / W, s1 = (nq * (wave + 1)) / W;
+    const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
+    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
+    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
+    TV acc[BC];
+#pragma unroll
+    for (int c = 0; c < BC; ++c) acc[c] = TV(0);
+    if (n >= 2)
+        fwd_quads<TM, TV, BC, true>(d, I, A, Bv, img, n, nn, nbc, s0, s1, q, r, acc);
+    else
+        fwd_quads<TM, TV, BC, false>(d, I, A, Bv, img, n, nn, nbc, s0, s1, q, r, acc);
 #pragma unroll
     for (int c = 0; c < BC; ++c) {
         acc[c] += __shfl_xor(acc[c], 16);

@@ -117,7 +117,7 @@ def test_group_and_graph_entry_points_validate_without_gpu():
     assert "count" in L.radon_last_error().decode()
     assert L.radon_multi_create(arr, 1, None, None, None, ctypes.byref(h)) == -1
     assert L.radon_multi_create(arr, 1, None, None, None, None) == -1
-    assert L.radon_multi_info(None, None, None, None, None, None) == -1
+    assert L.radon_multi_info(None, None, None, None, None, None, None) == -1
     assert L.radon_multi_apply(None, 0, None, None, None, 0, None) == -1
     assert L.radon_multi_cg(None, None, None, 1, 0.0, None, 0, None, None) == -1
     assert L.radon_multi_cg_graph(None, None, None, 1, 0.0, None, 0, None, ctypes.byref(h)) == -1

@@ -51,7 +51,7 @@ def test_group_products_equal_single_products(mode):
     sigma = [0.0, 1.0, 0.25, 0.0, 0.5, 0.0, 0.0]
     ops, g = _group(SMALL_GROUP, mode, alpha, lam, sigma)
     for o in ops:
-        o.tuning = {"adj_waves": g.adj_waves}
+        o.tuning = {"fwd_waves": g.fwd_waves, "adj_waves": g.adj_waves}
     rng = np.random.default_rng(1)
     xs = [to_dev(rng.standard_normal(o.nn), dt) for o in ops]
     ys = [to_dev(rng.standard_normal(o.rows), dt) for o in ops]

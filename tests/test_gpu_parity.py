@@ -375,7 +375,7 @@ def test_tuning_setter_autotune_and_parity(tmp_path, monkeypatch):
     mask = W.angle_mask(na, 2)
     ref = oracle.OracleOp(n, na, W.n_bins_for(n), mask)
     op = make_op(n, na, W.n_bins_for(n), mask, "mixed")
-    assert op.tuning == {"fwd_waves": 4, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8}
+    assert op.tuning == {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8}
     with pytest.raises(sct.SparsectError):
         op.tuning = {"fwd_waves": 3}
     with pytest.raises(sct.SparsectError):
