@@ -54,6 +54,7 @@ __global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel
 {
     using Q = typename Quad<TM>::type;
     __shared__ T band[W * 4 * kAdjBand];
+    __shared__ uint16_t bases[W * kAdjLanes];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t bat = blockIdx.y;
     const T *__restrict__ yb = y + bat * rows;
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel
     const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1);
     double dsum = 0.0;   // this block's share of <x, out>, tiles in a fixed order
     for (int64_t g = blockIdx.x; g < n_ag; g += gridDim.x) {
-        const T acc = adj_tile1<TM, T, W>(g, Rl, base, A, Bv, n_meas, n_aq, nb, yb, band);
+        const T acc = adj_tile1<TM, T, W>(g, Rl, base, A, Bv, n_meas, n_aq, nb, yb, band, bases);
         if (wave == 0)
             dsum += adj_epilogue(g, lane, acc, xb, out + bat * nn, alpha, lambda, sigma, n, tiles);
     }
@@ -95,7 +96,8 @@ __global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
 {
     using Q = typename Quad<TM>::type;
     __shared__ T band[W][BC][4 * kAdjBand];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ uint16_t bases[W][kAdjLanes];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int b0 = int(blockIdx.y) * BC;
     const int nbc = min(BC, batch - b0);
     const T *__restrict__ yb = y + int64_t(b0) * rows;
@@ -111,35 +113,42 @@ __global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
         T acc[BC];
 #pragma unroll
         for (int c = 0; c < BC; ++c) acc[c] = T(0);
-#pragma unroll 2
-        for (int aq = q0; aq < q1; ++aq) {
-            const int64_t gq = g * n_aq + aq;
-            const int a_band = min(4 * aq + kk, n_meas - 1);
-            const int64_t band_at = int64_t(a_band) * nb + min(int(base[gq * 4 + kk]) + ee, nb - 1);
-            T yv[BC];
-#pragma unroll
-            for (int c = 0; c < BC; ++c)
-                if (BC == 1 || c < nbc) yv[c] = yb[int64_t(c) * rows + band_at];
-            const int64_t e = gq * kAdjLanes + lane;
-            const uint32_t r4 = stream_load(Rl + e);
-            const Q a4 = stream_load(A + e);
-            const Q c4 = stream_load(Bv + e);
-#pragma unroll
-            for (int c = 0; c < BC; ++c)
-                if (BC == 1 || c < nbc) band[wave][c][lane] = yv[c];
+        for (int c0 = q0; c0 < q1; c0 += kBaseChunk) {
+            const int nc = min(kBaseChunk, q1 - c0);
+            if (lane < 4 * nc) bases[wave][lane] = base[(g * n_aq + c0) * 4 + lane];
             __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+            for (int j = 0; j < nc; ++j) {
+                const int aq = c0 + j;
+                const int64_t gq = g * n_aq + aq;
+                const int a_band = min(4 * aq + kk, n_meas - 1);
+                const int64_t band_at =
+                    int64_t(a_band) * nb + min(int(bases[wave][4 * j + kk]) + ee, nb - 1);
+                T yv[BC];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int rb = k * kAdjBand + int((r4 >> (8 * k)) & 0xffu);
+                for (int c = 0; c < BC; ++c)
+                    if (BC == 1 || c < nbc) yv[c] = yb[int64_t(c) * rows + band_at];
+                const int64_t e = gq * kAdjLanes + lane;
+                const uint32_t r4 = stream_load(Rl + e);
+                const Q a4 = stream_load(A + e);
+                const Q c4 = stream_load(Bv + e);
 #pragma unroll
-                for (int c = 0; c < BC; ++c) {
-                    if (BC == 1 || c < nbc) {
-                        acc[c] = fma(T(a4[k]), band[wave][c][rb], acc[c]);
-                        acc[c] = fma(T(c4[k]), band[wave][c][rb + 1], acc[c]);
+                for (int c = 0; c < BC; ++c)
+                    if (BC == 1 || c < nbc) band[wave][c][lane] = yv[c];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int rb = k * kAdjBand + int((r4 >> (8 * k)) & 0xffu);
+#pragma unroll
+                    for (int c = 0; c < BC; ++c) {
+                        if (BC == 1 || c < nbc) {
+                            acc[c] = fma(T(a4[k]), band[wave][c][rb], acc[c]);
+                            acc[c] = fma(T(c4[k]), band[wave][c][rb + 1], acc[c]);
+                        }
                     }
                 }
+                __builtin_amdgcn_wave_barrier();
             }
-            __builtin_amdgcn_wave_barrier();
         }
         if constexpr (W > 1) {
             __shared__ T red[W][BC][64];
@@ -255,7 +264,7 @@ int adj_blocks(const Op &op) { return int(op.n_ag < kPersistentBlocks ? op.n_ag 
 static int adj_waves(const Op &op)
 {
     if (op.tune.adj_waves == 1 || op.tune.adj_waves == 2 || op.tune.adj_waves == 4) return op.tune.adj_waves;
-    return op.n_meas >= 128 ? 4 : (op.n_meas >= 48 ? 2 : 1);
+    return adj_waves_for(op.n_meas);
 }
 
 template <class TM, class TV, int W, int BC>

@@ -173,6 +173,11 @@ int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, do
 // that loop over the work items; the adjoint leaves one <x, out> partial per
 // workgroup, adj_blocks(op) of them per right-hand side.
 constexpr int kPersistentBlocks = 2048;
+// Waves per 8x8 tile of the adjoint when the operator's tuning leaves it open:
+// two once there are enough measured-angle quads to split (measured on the
+// 512 x 512 / 180-angle, 512 x 512 / 120-angle and 1024 x 1024 / 360-angle
+// operators, 2 beats 1 and 4).
+inline int adj_waves_for(int n_meas) { return n_meas >= 48 ? 2 : 1; }
 int adj_blocks(const Op &op);
 // sum part[batch][count] -> dst[batch] (fixed order)
 int launch_sum_partials(const double *part, int64_t count, double *dst, int batch, hipStream_t s);

@@ -159,6 +159,7 @@ __global__ __launch_bounds__(64 * W) void k_multi_adj(const int64_t *__restrict_
 {
     using Q = typename Quad<TM>::type;
     __shared__ T band[W * 4 * kAdjBand];
+    __shared__ uint16_t bases[W * kAdjLanes];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t n_grp = grp_start[count];
     const int64_t G = gridDim.x;
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(64 * W) void k_multi_adj(const int64_t *__restrict_
         const T acc = adj_tile1<TM, T, W>(gl, reinterpret_cast<const uint32_t *>(I.a_rel), I.a_base,
                                           static_cast<const Q *>(I.a_v0),
                                           static_cast<const Q *>(I.a_v1), I.n_meas, I.n_aq, I.nb,
-                                          y + I.sino_off, band);
+                                          y + I.sino_off, band, bases);
         if (wave == 0) {
             if (normal)
                 dsum += adj_epilogue(gl, lane, acc, x + I.img_off, out + I.img_off, T(I.alpha),
@@ -631,10 +632,8 @@ static int build_multi(Multi &m, const radon_op *const *ops, int count, const do
     m.n_fwork = int64_t(work.size());
     if (m.n_t32 > 0x7fffffffLL || m.n_vb > 0x7fffffffLL)
         return set_error(RADON_EUNSUPPORTED, "too many vector tiles in one group");
-    // the single-operator rule (by measured angles) applied to the mean over
-    // the instances (weighting by the instances' adjoint work measured slower)
-    const int64_t avg = meas_sum / count;
-    m.adj_w = avg >= 128 ? 4 : (avg >= 48 ? 2 : 1);
+    // the single-operator rule applied to the mean measured-angle count
+    m.adj_w = adj_waves_for(int(meas_sum / count));
     SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.inst), int64_t(sizeof(MultiInst)) * count));
     SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.fwork), int64_t(sizeof(int2)) * m.n_fwork));
     SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.grp_start), 8 * (int64_t(count) + 1)));

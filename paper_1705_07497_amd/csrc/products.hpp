@@ -174,41 +174,55 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// Quads of one tile whose base bins a wave stages in LDS at a time: one
+// 2-byte load per lane.  With the bases in LDS the band address of a quad
+// waits only on LDS, so the quad's matrix streams are not held back behind a
+// global load of its base.
+constexpr int kBaseChunk = kAdjLanes / 4;
+
 // Single right-hand side adjoint sum for 8x8 tile g (the layout and the band
 // staging are described at k_adj below): returns the tile's 64 sums in the
 // lanes of wave 0 (other waves return their own share).  `band` is this
-// block's [W][4][kAdjBand] LDS staging area.
+// block's [W][4][kAdjBand] LDS staging area, `bases` its [W][kAdjLanes] one.
 template <class TM, class T, int W>
 __device__ __forceinline__ T adj_tile1(int64_t g, const uint32_t *__restrict__ Rl,
                                        const uint16_t *__restrict__ base,
                                        const typename Quad<TM>::type *__restrict__ A,
                                        const typename Quad<TM>::type *__restrict__ Bv, int n_meas,
-                                       int n_aq, int nb, const T *__restrict__ yb, T *band)
+                                       int n_aq, int nb, const T *__restrict__ yb, T *band,
+                                       uint16_t *bases)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int q0 = (n_aq * wave) / W, q1 = (n_aq * (wave + 1)) / W;
     const int kk = lane >> 4, ee = lane & 15;   // this lane's band element
     T *__restrict__ my = band + wave * 4 * kAdjBand;
+    uint16_t *__restrict__ mb = bases + wave * kAdjLanes;
     T acc = T(0);
+    for (int c0 = q0; c0 < q1; c0 += kBaseChunk) {
+        const int nc = min(kBaseChunk, q1 - c0);
+        if (lane < 4 * nc) mb[lane] = base[(g * n_aq + c0) * 4 + lane];
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll 2
-    for (int aq = q0; aq < q1; ++aq) {
-        const int64_t gq = g * n_aq + aq;
-        const int a_band = min(4 * aq + kk, n_meas - 1);
-        const int b_band = min(int(base[gq * 4 + kk]) + ee, nb - 1);
-        const T yv = yb[int64_t(a_band) * nb + b_band];
-        const int64_t e = gq * kAdjLanes + lane;
-        const uint32_t r4 = stream_load(Rl + e);
-        const auto a4 = stream_load(A + e);
-        const auto c4 = stream_load(Bv + e);
-        my[lane] = yv;
-        __builtin_amdgcn_wave_barrier();
+        for (int j = 0; j < nc; ++j) {
+            const int aq = c0 + j;
+            const int64_t gq = g * n_aq + aq;
+            const int a_band = min(4 * aq + kk, n_meas - 1);
+            const int b_band = min(int(mb[4 * j + kk]) + ee, nb - 1);
+            const T yv = yb[int64_t(a_band) * nb + b_band];
+            const int64_t e = gq * kAdjLanes + lane;
+            const uint32_t r4 = stream_load(Rl + e);
+            const auto a4 = stream_load(A + e);
+            const auto c4 = stream_load(Bv + e);
+            my[lane] = yv;
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int rb = int((r4 >> (8 * k)) & 0xffu);
-            acc = fma(T(a4[k]), my[k * kAdjBand + rb], acc);
-            acc = fma(T(c4[k]), my[k * kAdjBand + rb + 1], acc);
+            for (int k = 0; k < 4; ++k) {
+                const int rb = int((r4 >> (8 * k)) & 0xffu);
+                acc = fma(T(a4[k]), my[k * kAdjBand + rb], acc);
+                acc = fma(T(c4[k]), my[k * kAdjBand + rb + 1], acc);
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
     }
     if constexpr (W > 1) {
         __shared__ T red[W][64];
