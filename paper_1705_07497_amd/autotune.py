@@ -65,7 +65,7 @@ def apply_cached(op, path: str | None = None) -> bool:
     entry = load_cache(path).get(op_key(op))
     if not entry:
         return False
-    op.tuning = {k: entry["tuning"][k] for k in DEFAULT}
+    op.tuning = {k: entry["tuning"].get(k, DEFAULT[k]) for k in DEFAULT}
     return True
 
 
