@@ -53,7 +53,7 @@ def parse():
                     help="oracle normal applies to time (0: sized to ~15 s)")
     ap.add_argument("--no-batched", action="store_true", help="skip the fused multi-image legs")
     ap.add_argument("--profile", action="store_true",
-                    help="profiler mode: 20 forward kernels, 20 adj, 20 normal applies, one CG(20) "
+                    help="profiler mode: 100 forward kernels, 100 adj, 20 normal applies, one CG(20) "
                          "solve and a plain 1 GiB device copy (counter calibration), then exit")
     ap.add_argument("--profile-multi", action="store_true",
                     help="profiler mode for the uneven 32-instance batch: one captured-graph CG(10), "
@@ -140,6 +140,7 @@ def bench_batched(sct, W, torch, dev, vdt):
         del op
         torch.cuda.empty_cache()
     out["mixed_batch_32"] = bench_mixed_batch(sct, W, torch, dev, vdt, t)
+    out["large_2048_f32"] = bench_large(sct, W, torch, dev, vdt, t)
     return out
 
 
@@ -181,6 +182,38 @@ def bench_mixed_batch(sct, W, torch, dev, vdt, t):
     del graph, g, ops
     torch.cuda.empty_cache()
     return out
+
+
+def bench_large(sct, W, torch, dev, vdt, t):
+    """The large under-resolved workload: 2048 x 2048, 90 angles, 2897 bins
+    (4.8e8 nonzeros), split Bregman 30 outer x 10 CG on a random-ellipse
+    phantom; the normal operator alone and whole reconstructions."""
+    w = W.WORKLOADS["large_2048_f32"]
+    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                     device=dev)
+    mu_np, eps_np = W.phantom_and_noise(w.n, w.n_ellipses, op.rows, seed=0)
+    mu = torch.as_tensor(mu_np, dtype=vdt, device=dev).reshape(1, -1)
+    y = op.fwd(mu)
+    f = (y + w.noise * torch.sqrt(torch.mean(y ** 2)).item()
+         * torch.as_tensor(eps_np, dtype=vdt, device=dev)).contiguous()
+    out = torch.empty_like(mu)
+    t_normal = t(lambda: op.normal(mu, w.alpha, w.lam, out=out), 20)
+    t_sb = t(lambda: op.sb(f, w.alpha, w.lam, w.n_outer, w.n_cg), 2)
+    u, _ = op.sb(f, w.alpha, w.lam, w.n_outer, w.n_cg)
+    err = float(torch.linalg.vector_norm(u.reshape(-1) - mu.reshape(-1))
+                / torch.linalg.vector_norm(mu))
+    nnz = op.info.nnz
+    bytes_normal = 2 * 8 * nnz + 4 * (op.rows + 1) + 4 * (op.nn + 1) + 8 * (3 * op.nn + 2 * op.rows)
+    print(f"# large 2048x2048/90 angles: normal {t_normal * 1e3:.3f} ms, split Bregman "
+          f"{t_sb * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    out_d = {"n": w.n, "angles": w.n_angles, "bins": w.n_bins, "nnz": nnz,
+             "normal_apply_ms": round(t_normal * 1e3, 3),
+             "normal_apply_gbs": round(bytes_normal / t_normal / 1e9, 1),
+             "sb_ms": round(t_sb * 1e3, 1), "sb_applies": w.n_outer * w.n_cg,
+             "recon_per_s": round(1.0 / t_sb, 3), "rel_err_to_phantom": round(err, 4)}
+    del op
+    torch.cuda.empty_cache()
+    return out_d
 
 
 def bench_autograd(op, w, torch, dev, vdt, t):
@@ -262,9 +295,9 @@ def main():
         print("# profile sequence done (mixed batch)", file=sys.stderr, flush=True)
         return
     if args.profile:
-        for _ in range(20):
+        for _ in range(100):
             op.fwd_xt(x, xT, out=ysb)
-        for _ in range(20):
+        for _ in range(100):
             op.adj(ysb, out=out)
         for _ in range(20):
             op.normal(x, w.alpha, w.lam, out=out)
