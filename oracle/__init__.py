@@ -48,7 +48,8 @@ def build(force: bool = True) -> str:
 class _OraOp(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("rows", ctypes.c_int64),
                 ("rp", _i64p), ("ci", _i32p), ("v", _dp),
-                ("trp", _i64p), ("tci", _i32p), ("tv", _dp)]
+                ("trp", _i64p), ("tci", _i32p), ("tv", _dp),
+                ("sur_r", ctypes.c_int32), ("sur_w", _dp)]
 
 
 _lib = None
@@ -82,6 +83,9 @@ def lib():
         L.ora_loss1.restype = ctypes.c_double
         L.ora_loss2.argtypes = [P, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         L.ora_loss2.restype = ctypes.c_double
+        L.ora_stencil.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+        L.ora_surrogate_weights.argtypes = [P, ctypes.c_int, _dp]
+        L.ora_surrogate_weights.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -202,7 +206,7 @@ class OracleOp:
         self.rows = self.MR.rows
         self._s = _OraOp(n, self.rows, _p(self.MR.rp, _i64p), _p(self.MR.ci, _i32p),
                          _p(self.MR.v), _p(self.MRT.rp, _i64p), _p(self.MRT.ci, _i32p),
-                         _p(self.MRT.v))
+                         _p(self.MRT.v), -1, None)
 
     @property
     def nn(self) -> int:
@@ -255,6 +259,37 @@ class OracleOp:
         gf = np.empty(self.rows)
         L = lib().ora_loss1(ctypes.byref(self._s), _p(mu), _p(f), _p(gm), _p(gf))
         return L, gm, gf
+
+    def surrogate_weights(self, radius: int) -> np.ndarray:
+        """Weights of the surrogate T of Section 3.2 (eq:def_sparse_surr) for
+        truncation radius r: (2r+1) x (2r+1), w[dy + r, dx + r] = the symmetric
+        part of the centre pixel's point-spread function at offset (dy, dx)
+        inside the disc |d| <= r, zero outside."""
+        k = 2 * radius + 1
+        w = np.zeros(k * k)
+        if lib().ora_surrogate_weights(ctypes.byref(self._s), int(radius), _p(w)) != 0:
+            raise ValueError("the disc of radius %d does not fit in the image" % radius)
+        return w.reshape(k, k)
+
+    def with_surrogate(self, radius: int) -> "OracleOp":
+        """A copy whose normal operator uses T in place of R^T M^T M R (the
+        data right-hand side of split Bregman keeps the exact (MR)^T), as in
+        eq:surr_SBupd."""
+        import copy
+        o = copy.copy(self)
+        o.sur_w = np.ascontiguousarray(self.surrogate_weights(radius).reshape(-1))
+        o._s = _OraOp(self.n, self.rows, _p(self.MR.rp, _i64p), _p(self.MR.ci, _i32p),
+                      _p(self.MR.v), _p(self.MRT.rp, _i64p), _p(self.MRT.ci, _i32p),
+                      _p(self.MRT.v), int(radius), _p(o.sur_w))
+        return o
+
+    def stencil(self, radius: int, w, x) -> np.ndarray:
+        """(T x) for weights w of radius r (plain loops)."""
+        x = _f64(x)
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(-1))
+        out = np.empty(self.nn)
+        lib().ora_stencil(self.n, int(radius), _p(w), _p(x), _p(out))
+        return out
 
     def loss2(self, mu, f, tau_alpha: float, n_iter: int):
         """Loss through n_iter unrolled CG steps; returns (L, g_mu, g_f, u_n)."""

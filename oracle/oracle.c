@@ -298,7 +298,57 @@ typedef struct {
     int64_t rows;                  /* measured rays */
     const int64_t *rp; const int32_t *ci; const double *v;     /* MR      */
     const int64_t *trp; const int32_t *tci; const double *tv;  /* (MR)^T  */
+    int32_t sur_r;                 /* >= 0: R^T M^T M R is replaced by the surrogate T */
+    const double *sur_w;           /* T's weights, (2 sur_r + 1)^2, row-major in (dy, dx) */
 } ora_op;
+
+/* Surrogate operator of Section 3.2 (eq:def_sparse_surr): T is the sum over
+ * all pixels q of the point-spread function P = R^T M^T M R e_c of the centre
+ * pixel c, moved to q and cut to the disc of radius r around q; entries that
+ * fall outside the image are dropped (the suppression of the opposite edge).
+ * So (T x)_p = sum over |d| <= r with p - d inside the image of
+ * w(d) x_{p - d}, w(d) = P_{c + d}.  Weights outside the disc are zero. */
+void ora_stencil(int n, int r, const double *w, const double *x, double *out)
+{
+    const int k = 2 * r + 1;
+    for (int py = 0; py < n; ++py)
+        for (int px = 0; px < n; ++px) {
+            double acc = 0.0;
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    const int qy = py - dy, qx = px - dx;
+                    if (qy < 0 || qy >= n || qx < 0 || qx >= n) continue;
+                    acc += w[(dy + r) * k + (dx + r)] * x[(int64_t)qy * n + qx];
+                }
+            out[(int64_t)py * n + px] = acc;
+        }
+}
+
+/* The weights w(d) = P_{c + d} for |d| <= r (Euclidean), c = (n/2, n/2),
+ * P = R^T M^T M R e_c; symmetrized as (w(d) + w(-d)) / 2 so that T is
+ * symmetric (the surrogate system is solved by CG).  w has (2r+1)^2 entries;
+ * returns -1 if the disc does not fit in the image. */
+int ora_surrogate_weights(const ora_op *op, int r, double *w)
+{
+    const int n = op->n, k = 2 * r + 1, cy = n / 2, cx = n / 2;
+    if (r < 0 || cy - r < 0 || cy + r >= n || cx - r < 0 || cx + r >= n) return -1;
+    const int64_t nn = (int64_t)n * n;
+    double *e = (double *)calloc((size_t)nn, sizeof(double));
+    double *y = (double *)malloc(sizeof(double) * (size_t)op->rows);
+    double *P = (double *)malloc(sizeof(double) * (size_t)nn);
+    e[(int64_t)cy * n + cx] = 1.0;
+    ora_spmv(op->rows, op->rp, op->ci, op->v, e, y);
+    ora_spmv(nn, op->trp, op->tci, op->tv, y, P);
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) {
+            double v = 0.0;
+            if (dy * dy + dx * dx <= r * r)
+                v = 0.5 * (P[(int64_t)(cy + dy) * n + (cx + dx)] + P[(int64_t)(cy - dy) * n + (cx - dx)]);
+            w[(dy + r) * k + (dx + r)] = v;
+        }
+    free(e); free(y); free(P);
+    return 0;
+}
 
 /* scratch: rows + 4*n*n doubles */
 static void normal_apply(const ora_op *op, double alpha, double lambda, double sigma,
@@ -307,8 +357,12 @@ static void normal_apply(const ora_op *op, double alpha, double lambda, double s
     const int64_t nn = (int64_t)op->n * op->n;
     double *y = scratch, *t = scratch + op->rows;
     double *gx = t + nn, *gy = gx + nn, *ktk = gy + nn;
-    ora_spmv(op->rows, op->rp, op->ci, op->v, x, y);
-    ora_spmv(nn, op->trp, op->tci, op->tv, y, t);
+    if (op->sur_r >= 0) {
+        ora_stencil(op->n, op->sur_r, op->sur_w, x, t);
+    } else {
+        ora_spmv(op->rows, op->rp, op->ci, op->v, x, y);
+        ora_spmv(nn, op->trp, op->tci, op->tv, y, t);
+    }
     ora_grad(op->n, x, gx, gy);
     ora_gradT(op->n, gx, gy, ktk);
     for (int64_t j = 0; j < nn; ++j) out[j] = alpha * t[j] + lambda * ktk[j] + sigma * x[j];
