@@ -184,6 +184,24 @@ def bench_mixed_batch(sct, W, torch, dev, vdt, t):
     return out
 
 
+def bench_surrogate(sct, op, w, f, mu, u_exact, torch, timed, stream):
+    """Split Bregman with the surrogate T of Section 3.2 (radius 1, the paper's
+    timing setting) in every inner solve, same workload and iteration counts;
+    both reconstructions' relative L2 error to the phantom."""
+    sur = sct.RadonSurrogate(op, 1)
+    op.sb(f, w.alpha, w.lam, w.n_outer, w.n_cg, surrogate=sur)
+    reps = 10
+    t = timed(lambda: op.sb(f, w.alpha, w.lam, w.n_outer, w.n_cg, surrogate=sur), reps) / reps
+    us, info = op.sb(f, w.alpha, w.lam, w.n_outer, w.n_cg, surrogate=sur)
+    nrm = torch.linalg.vector_norm(mu)
+    e_sur = float(torch.linalg.vector_norm(us - mu) / nrm)
+    e_ex = float(torch.linalg.vector_norm(u_exact - mu) / nrm)
+    print(f"# surrogate split Bregman (r=1): {t * 1e3:.2f} ms per reconstruction, error to phantom "
+          f"{e_sur:.4f} (exact {e_ex:.4f})", file=sys.stderr, flush=True)
+    return {"radius": 1, "ms_per_recon": round(t * 1e3, 3), "recon_per_s": round(1.0 / t, 1),
+            "rel_err_to_phantom": round(e_sur, 4), "exact_rel_err_to_phantom": round(e_ex, 4)}
+
+
 def bench_large(sct, W, torch, dev, vdt, t):
     """The large under-resolved workload: 2048 x 2048, 90 angles, 2897 bins
     (4.8e8 nonzeros), split Bregman 30 outer x 10 CG on a random-ellipse
@@ -368,6 +386,8 @@ def main():
         "build_s": round(build_s, 3),
         "roofline": roofline,
     }
+
+    result["surrogate"] = bench_surrogate(sct, op, w, f, mu, u, torch, timed, stream)
 
     if not args.no_batched:
         result["batched"] = bench_batched(sct, W, torch, dev, vdt)

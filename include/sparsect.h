@@ -368,6 +368,53 @@ int radon_graph_launch(const radon_graph *g, void *stream);
 void radon_graph_destroy(radon_graph *g);
 
 /*
+ * Surrogate operator T (Section 3.2, eq:def_sparse_surr): the sum over all
+ * pixels q of the point-spread function P = R^T M^T M R e_c of the centre
+ * pixel c = (n/2, n/2) (0-based), moved to q and cut to the disc |d| <= r
+ * around q, entries outside the image dropped (no wrap-around).  T is taken
+ * as the symmetric part of that sum: weight w(d) = (P_{c+d} + P_{c-d}) / 2
+ * for |d| <= r, so (T x)_p = sum_d w(d) x_{p-d} over taps inside the image.
+ * It replaces R^T M^T M R in the split-Bregman update (eq:surr_SBupd), where
+ * the data right-hand side keeps the exact adjoint.
+ */
+typedef struct radon_surrogate radon_surrogate;   /* opaque surrogate handle */
+
+/*
+ * radon_surrogate_create -- build T of radius r (0 <= r <= 8; the disc must
+ * fit in the image) from `op`'s own products.  Synchronous on `stream`.  The
+ * handle owns its weights (device and host) and does not borrow `op`.
+ */
+int radon_surrogate_create(const radon_op *op, int32_t radius, void *stream,
+                           radon_surrogate **out);
+void radon_surrogate_destroy(radon_surrogate *s);
+
+/* radon_surrogate_weights -- radius, and the (2r+1)^2 weights (host double,
+ * row-major in (dy, dx), zero outside the disc); either pointer may be NULL. */
+int radon_surrogate_weights(const radon_surrogate *s, int32_t *radius, double *w);
+
+/*
+ * surrogate_apply -- out = alpha T x + lambda K^T K x + sigma x (x, out
+ * device [batch][n*n] in the operator dtype, out must not alias x); with
+ * dot_out (device double[batch]) also <x, out> per image, which needs a
+ * workspace ws of 8 * ceil(n/32)^2 * batch bytes (none otherwise).
+ */
+int surrogate_apply(const radon_surrogate *s, double alpha, double lambda, double sigma,
+                    const void *x, void *out, double *dot_out, int32_t batch, void *ws,
+                    int64_t ws_bytes, void *stream);
+
+/*
+ * split_bregman_tv_surrogate -- split_bregman_tv with every inner CG solve
+ * on alpha T + lambda K^T K (eq:surr_SBupd) instead of the exact normal
+ * operator; the data term alpha (MR)^T f, the shrink and Bregman steps and
+ * the workspace (RADON_WS_SB) are those of split_bregman_tv.  A run with
+ * RADON_SB_WARM can start the exact solver from its result.
+ */
+int split_bregman_tv_surrogate(const radon_op *op, const radon_surrogate *s,
+                               const radon_sb_params *params, const void *f, void *mu,
+                               int32_t batch, void *ws, int64_t ws_bytes, radon_sb_info *info,
+                               void *stream);
+
+/*
  * Launch tuning of an operator (not part of the method: it only changes how
  * the products are scheduled; the waves-per-item counts split each sum
  * differently, so results change at the rounding level; the fused chunk

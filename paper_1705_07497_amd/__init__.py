@@ -114,6 +114,13 @@ SIGNATURES = {
                                             ctypes.c_int64, _vp, ctypes.POINTER(_vp)]),
     "radon_graph_launch": (ctypes.c_int, [_vp, _vp]),
     "radon_graph_destroy": (None, [_vp]),
+    "radon_surrogate_create": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.POINTER(_vp)]),
+    "radon_surrogate_destroy": (None, [_vp]),
+    "radon_surrogate_weights": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), _vp]),
+    "surrogate_apply": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp,
+                                       _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
+    "split_bregman_tv_surrogate": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(SbParams), _vp, _vp,
+                                                  ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]),
     "cg_unrolled_vjp": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp,
                                        ctypes.c_int64, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
@@ -343,9 +350,11 @@ class RadonOp:
         return x, info
 
     def sb(self, f, alpha: float, lam: float, n_outer: int, n_cg: int, tol: float = 0.0,
-           mu0=None, resume: bool = False, out=None, ws_key="sb"):
+           mu0=None, resume: bool = False, out=None, ws_key="sb", surrogate=None):
         """Split Bregman TV; returns (mu, info tensor of SbInfo bytes).  The state
-        (d, b, carried residual) stays in a cached workspace so resume=True continues."""
+        (d, b, carried residual) stays in a cached workspace so resume=True continues.
+        With surrogate (a RadonSurrogate of this operator) every inner solve uses
+        alpha T + lam K^T K (eq:surr_SBupd)."""
         torch = _torch()
         b = self._sino(f, "f")
         flags = 0
@@ -363,8 +372,13 @@ class RadonOp:
         P = SbParams(float(alpha), float(lam), float(tol), int(n_outer), int(n_cg), flags, 0)
         info = torch.zeros(b * ctypes.sizeof(SbInfo), dtype=torch.uint8, device=self.device)
         ws, nb = self.workspace(WS_SB, b, key=(ws_key, b))
-        _check(lib().split_bregman_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b,
-                                      self._p(ws), nb, self._p(info), self._stream()))
+        if surrogate is None:
+            _check(lib().split_bregman_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b,
+                                          self._p(ws), nb, self._p(info), self._stream()))
+        else:
+            _check(lib().split_bregman_tv_surrogate(self._h, surrogate._h, ctypes.byref(P),
+                                                    self._p(f), self._p(mu), b, self._p(ws), nb,
+                                                    self._p(info), self._stream()))
         return mu, info
 
     def unrolled_sizes(self, n_iter: int, ckpt: int, batch: int) -> tuple[int, int, int]:
@@ -423,6 +437,48 @@ class RadonOp:
         _check(lib().radon_export_adj(self._h, b.ctypes.data_as(_vp), v0.ctypes.data_as(_vp),
                                       v1.ctypes.data_as(_vp)))
         return b, v0, v1
+
+
+class RadonSurrogate:
+    """The surrogate T of Section 3.2 built from a RadonOp's own products: the
+    centre pixel's point-spread function cut to radius r and applied as a
+    translated stencil (symmetric part, no wrap-around at the edges)."""
+
+    def __init__(self, op: RadonOp, radius: int):
+        torch = _torch()
+        self.op, self.radius = op, int(radius)
+        self.n, self.nn, self.dtype, self.device = op.n, op.nn, op.dtype, op.device
+        h = _vp()
+        with torch.cuda.device(op.device):
+            _check(lib().radon_surrogate_create(op._h, self.radius, op._stream(), ctypes.byref(h)))
+        self._h = h
+        k = 2 * self.radius + 1
+        w = np.zeros(k * k)
+        _check(lib().radon_surrogate_weights(self._h, None, w.ctypes.data_as(_vp)))
+        self.weights = w.reshape(k, k)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.radon_surrogate_destroy(h)
+            self._h = None
+
+    def apply(self, x, alpha: float = 1.0, lam: float = 0.0, sigma: float = 0.0, out=None,
+              dot: bool = False):
+        """alpha T x + lam K^T K x + sigma x (and <x, out> per image if dot)."""
+        torch = _torch()
+        b = self.op._img(x)
+        o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self.op._img(o, "out")
+        d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
+        t = (self.n + 31) // 32
+        nbytes = 8 * t * t * b if dot else 0
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        _check(lib().surrogate_apply(self._h, float(alpha), float(lam), float(sigma),
+                                     _vp(x.data_ptr()), _vp(o.data_ptr()),
+                                     _vp(d.data_ptr()) if dot else None, b, _vp(ws.data_ptr()),
+                                     nbytes, self.op._stream()))
+        return (o, d) if dot else o
 
 
 class RadonMulti:

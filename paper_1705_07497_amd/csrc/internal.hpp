@@ -179,6 +179,21 @@ constexpr int kPersistentBlocks = 2048;
 // operators, 2 beats 1 and 4).
 inline int adj_waves_for(int n_meas) { return n_meas >= 48 ? 2 : 1; }
 int adj_blocks(const Op &op);
+
+// Surrogate operator T of Section 3.2 (surrogate.hip): a translated stencil of
+// radius r over the image, weights w[(dy + r)(2r + 1) + dx + r].
+struct Sur {
+    int32_t n = 0, r = 0, dtype = 0, vsize = 4;
+    int64_t nn = 0;
+    std::vector<double> w;     // host copy of the weights
+    void *w_dev = nullptr;     // weights in the vector type
+};
+// out = alpha T x + lambda K^T K x + sigma x for `batch` images; partial
+// <x, out> per 32x32 tile into part[batch][surrogate_parts] when part != nullptr.
+template <class TV>
+int launch_surrogate(const Sur &s, double alpha, double lambda, double sigma, const TV *x, TV *out,
+                     double *part, int batch, hipStream_t st);
+int64_t surrogate_parts(const Sur &s);
 // sum part[batch][count] -> dst[batch] (fixed order)
 int launch_sum_partials(const double *part, int64_t count, double *dst, int batch, hipStream_t s);
 

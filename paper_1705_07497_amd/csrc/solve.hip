@@ -411,6 +411,37 @@ int64_t sb_ws_bytes(const Op &op, int batch)
     return c.used;
 }
 
+// The operator A of a CG solve.  ExactA is the normal operator of Section 2
+// through the stored matrices (forward product into y, then the adjoint with
+// the fused epilogue); SurA is the surrogate of Section 3.2 (a stencil, no
+// transposed copy needed).  Both leave one FP64 partial of <p, A p> per block
+// in part, n_part() of them per right-hand side.
+template <class TM, class T>
+struct ExactA {
+    const Op &op;
+    double alpha, lambda, sigma;
+    int64_t n_part() const { return adj_blocks(op); }
+    bool needs_T() const { return op.need_T; }
+    int operator()(const T *p, const T *pT, T *q, T *y, double *part, int batch,
+                   hipStream_t s) const
+    {
+        SCT_TRY((launch_fwd<TM, T>(op, p, pT, y, batch, s)));
+        return launch_adj<TM, T>(op, y, p, q, alpha, lambda, sigma, part, batch, s);
+    }
+};
+
+template <class T>
+struct SurA {
+    const Sur &sur;
+    double alpha, lambda, sigma;
+    int64_t n_part() const { return surrogate_parts(sur); }
+    bool needs_T() const { return false; }
+    int operator()(const T *p, const T *, T *q, T *, double *part, int batch, hipStream_t s) const
+    {
+        return launch_surrogate<T>(sur, alpha, lambda, sigma, p, q, part, batch, s);
+    }
+};
+
 // CG start: p = r (+ transposed copy), rho_0, state in ring slot 0.
 template <class T>
 static int cg_start(const Op &op, int batch, CgBufs<T> &w, T *u_for_prev, T *uprev,
@@ -427,10 +458,9 @@ static int cg_start(const Op &op, int batch, CgBufs<T> &w, T *u_for_prev, T *upr
 
 // CG iteration `it`: q = A p, step length, x/r update, p update; state moves
 // from ring slot it % 2 to (it + 1) % 2.
-template <class TM, class T>
-static int cg_iter(const Op &op, double alpha, double lambda, double sigma, T *x, int batch, int it,
-                   double rtol, CgBufs<T> &w, hipStream_t s, T *rec_q = nullptr,
-                   T *rec_p = nullptr, T *rec_r = nullptr)
+template <class T, class AOp>
+static int cg_iter(const Op &op, const AOp &A, T *x, int batch, int it, double rtol, CgBufs<T> &w,
+                   hipStream_t s, T *rec_q = nullptr, T *rec_p = nullptr, T *rec_r = nullptr)
 {
     const unsigned t = unsigned(tiles_of(op.n));
     const dim3 tg{t, t, unsigned(batch)}, tb{32, 8, 1};
@@ -439,12 +469,11 @@ static int cg_iter(const Op &op, double alpha, double lambda, double sigma, T *x
     const int vbc = vec_blocks(cnt);
     CgState *cur = w.st + int64_t(it & 1) * batch, *nxt = w.st + int64_t((it + 1) & 1) * batch;
     CgStep *stp = w.step + int64_t(it & 1) * batch;
-    SCT_TRY((launch_fwd<TM, T>(op, w.p, w.pT, w.y, batch, s)));
-    SCT_TRY((launch_adj<TM, T>(op, w.y, w.p, w.q, alpha, lambda, sigma, w.part_adj, batch, s)));
+    SCT_TRY(A(w.p, w.pT, w.q, w.y, w.part_adj, batch, s));
     if (rec_q) k_copy<T><<<vbc, kVecThreads, 0, s>>>(w.q, rec_q, cnt);
     if (rec_p) k_copy<T><<<vbc, kVecThreads, 0, s>>>(w.p, rec_p, cnt);
     k_cg_xr<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
-        x, w.r, w.p, w.q, w.part_adj, adj_blocks(op), cur, stp, rtol, w.part_vec, op.nn);
+        x, w.r, w.p, w.q, w.part_adj, A.n_part(), cur, stp, rtol, w.part_vec, op.nn);
     SCT_TRY(check_launch("k_cg_xr"));
     if (rec_r) k_copy<T><<<vbc, kVecThreads, 0, s>>>(w.r, rec_r, cnt);
     k_cg_p<T><<<tg, tb, 0, s>>>(w.r, w.p, w.pT, w.part_vec, vb, cur, stp, nxt, it, op.n, op.nn);
@@ -453,14 +482,12 @@ static int cg_iter(const Op &op, double alpha, double lambda, double sigma, T *x
 
 // One CG solve on A(alpha, lambda, sigma) from x with the residual already in
 // w.r; the final state is left in ring slot n_iter % 2.
-template <class TM, class T>
-static int cg_run(const Op &op, double alpha, double lambda, double sigma, T *x, int batch,
-                  int n_iter, double rtol, CgBufs<T> &w, T *u_for_prev, T *uprev,
-                  const SbScal *sbs, hipStream_t s)
+template <class T, class AOp>
+static int cg_run(const Op &op, const AOp &A, T *x, int batch, int n_iter, double rtol,
+                  CgBufs<T> &w, T *u_for_prev, T *uprev, const SbScal *sbs, hipStream_t s)
 {
     SCT_TRY(cg_start<T>(op, batch, w, u_for_prev, uprev, sbs, s));
-    for (int it = 0; it < n_iter; ++it)
-        SCT_TRY((cg_iter<TM, T>(op, alpha, lambda, sigma, x, batch, it, rtol, w, s)));
+    for (int it = 0; it < n_iter; ++it) SCT_TRY((cg_iter<T>(op, A, x, batch, it, rtol, w, s)));
     return RADON_OK;
 }
 
@@ -470,13 +497,12 @@ static const CgState *final_state(const CgState *st, int n_iter, int batch)
 }
 
 // w.q = A x (uses w.pT and w.y as temporaries)
-template <class TM, class T>
-static int apply_A_into_q(const Op &op, double alpha, double lambda, double sigma, const T *x,
-                          int batch, CgBufs<T> &w, hipStream_t s)
+template <class T, class AOp>
+static int apply_A_into_q(const Op &op, const AOp &A, const T *x, int batch, CgBufs<T> &w,
+                          hipStream_t s)
 {
-    if (w.pT) SCT_TRY(launch_transpose<T>(op, x, w.pT, batch, s));
-    SCT_TRY((launch_fwd<TM, T>(op, x, w.pT, w.y, batch, s)));
-    return launch_adj<TM, T>(op, w.y, x, w.q, alpha, lambda, sigma, nullptr, batch, s);
+    if (w.pT && A.needs_T()) SCT_TRY(launch_transpose<T>(op, x, w.pT, batch, s));
+    return A(x, w.pT, w.q, w.y, nullptr, batch, s);
 }
 
 template <class TM, class T>
@@ -492,7 +518,7 @@ static int cg_typed(const Op &op, double alpha, double lambda, double sigma, con
     const int64_t cnt = op.nn * batch;
     const int vb = vec_blocks(cnt);
     if (x0_given) {
-        SCT_TRY((apply_A_into_q<TM, T>(op, alpha, lambda, sigma, x, batch, w, s)));
+        SCT_TRY((apply_A_into_q<T>(op, ExactA<TM, T>{op, alpha, lambda, sigma}, x, batch, w, s)));
         k_sub<T><<<vb, kVecThreads, 0, s>>>(rhs, w.q, w.r, cnt);
         SCT_TRY(check_launch("k_sub"));
     } else {
@@ -501,8 +527,8 @@ static int cg_typed(const Op &op, double alpha, double lambda, double sigma, con
         k_copy<T><<<vb, kVecThreads, 0, s>>>(rhs, w.r, cnt);
         SCT_TRY(check_launch("k_copy"));
     }
-    SCT_TRY((cg_run<TM, T>(op, alpha, lambda, sigma, x, batch, n_iter, rtol, w, nullptr, nullptr,
-                           nullptr, s)));
+    SCT_TRY((cg_run<T>(op, ExactA<TM, T>{op, alpha, lambda, sigma}, x, batch, n_iter, rtol, w,
+                       nullptr, nullptr, nullptr, s)));
     if (info) {
         k_cg_info<<<unsigned((batch + 63) / 64), 64, 0, s>>>(final_state(w.st, n_iter, batch), info,
                                                              batch);
@@ -511,13 +537,17 @@ static int cg_typed(const Op &op, double alpha, double lambda, double sigma, con
     return RADON_OK;
 }
 
-template <class TM, class T>
-static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, void *mu_v, int batch,
-                    void *ws, radon_sb_info *info, hipStream_t s)
+// Split Bregman with the inner CG on A (exact or surrogate); the data
+// right-hand side alpha (MR)^T f always uses the stored adjoint (eq:SB_solve,
+// eq:surr_SBupd).
+template <class TM, class T, class AOp>
+static int sb_run(const Op &op, const AOp &A, const radon_sb_params &P, const void *f_v,
+                  void *mu_v, int batch, void *ws, radon_sb_info *info, hipStream_t s)
 {
     Carver c(ws);
     SbBufs<T> w;
     carve_sb(op, batch, c, w);
+    if (!A.needs_T()) w.cg.pT = nullptr;   // no transposed direction to keep
     const T *f = static_cast<const T *>(f_v);
     T *u = static_cast<T *>(mu_v);
     const int64_t cnt = op.nn * batch;
@@ -532,7 +562,7 @@ static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, voi
         // r = alpha (MR)^T f - A u
         SCT_TRY((launch_adj<TM, T>(op, f, nullptr, w.cg.r, alpha, 0.0, 0.0, nullptr, batch, s)));
         if (P.flags & RADON_SB_WARM) {
-            SCT_TRY((apply_A_into_q<TM, T>(op, alpha, lambda, 0.0, u, batch, w.cg, s)));
+            SCT_TRY((apply_A_into_q<T>(op, A, u, batch, w.cg, s)));
             k_sub<T><<<vbc, kVecThreads, 0, s>>>(w.cg.r, w.cg.q, w.cg.r, cnt);
             SCT_TRY(check_launch("k_sub"));
         } else {
@@ -544,8 +574,7 @@ static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, voi
     SCT_TRY(check_launch("k_sb_reset"));
     const T thresh = T(1.0 / lambda);
     for (int k = 0; k < P.n_outer; ++k) {
-        SCT_TRY((cg_run<TM, T>(op, alpha, lambda, 0.0, u, batch, P.n_cg, 0.0, w.cg, u, w.uprev, w.sbs,
-                               s)));
+        SCT_TRY((cg_run<T>(op, A, u, batch, P.n_cg, 0.0, w.cg, u, w.uprev, w.sbs, s)));
         k_sb_shrink<T><<<dim3(unsigned(vb), unsigned(batch)), kVecThreads, 0, s>>>(
             u, w.uprev, w.dx, w.dy, w.bx, w.by, w.dwx, w.dwy, thresh, w.sbs, w.part, op.n, op.nn);
         SCT_TRY(check_launch("k_sb_shrink"));
@@ -561,6 +590,17 @@ static int sb_typed(const Op &op, const radon_sb_params &P, const void *f_v, voi
         SCT_TRY(check_launch("k_sb_info"));
     }
     return RADON_OK;
+}
+
+template <class TM, class T>
+static int sb_typed(const Op &op, const Sur *sur, const radon_sb_params &P, const void *f_v,
+                    void *mu_v, int batch, void *ws, radon_sb_info *info, hipStream_t s)
+{
+    if (sur)
+        return sb_run<TM, T>(op, SurA<T>{*sur, P.alpha, P.lambda, 0.0}, P, f_v, mu_v, batch, ws,
+                             info, s);
+    return sb_run<TM, T>(op, ExactA<TM, T>{op, P.alpha, P.lambda, 0.0}, P, f_v, mu_v, batch, ws,
+                         info, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -865,7 +905,7 @@ static int unrolled_fwd_typed(const Op &op, double alpha, double lambda, double 
                                                                    tape.st + sg * batch, batch);
             SCT_TRY(check_launch("tape"));
         }
-        SCT_TRY((cg_iter<TM, T>(op, alpha, lambda, sigma, x, batch, it, 0.0, w, s)));
+        SCT_TRY((cg_iter<T>(op, ExactA<TM, T>{op, alpha, lambda, sigma}, x, batch, it, 0.0, w, s)));
     }
     return RADON_OK;
 }
@@ -900,8 +940,8 @@ static int unrolled_vjp_typed(const Op &op, double alpha, double lambda, double 
         SCT_TRY(check_launch("replay"));
         for (int it = k0; it < k1; ++it) {
             const int64_t o = int64_t(it - k0) * cnt;
-            SCT_TRY((cg_iter<TM, T>(op, alpha, lambda, sigma, nullptr, batch, it, 0.0, w.cg, s,
-                                    w.rec_q + o, w.rec_p + o, w.rec_r + o)));
+            SCT_TRY((cg_iter<T>(op, ExactA<TM, T>{op, alpha, lambda, sigma}, nullptr, batch, it, 0.0,
+                                w.cg, s, w.rec_q + o, w.rec_p + o, w.rec_r + o)));
             k_rec_scalars<<<sb, 64, 0, s>>>(w.cg.st + int64_t(it & 1) * batch,
                                             w.cg.step + int64_t(it & 1) * batch,
                                             w.cg.st + int64_t((it + 1) & 1) * batch,
@@ -981,7 +1021,37 @@ extern "C" int split_bregman_tv(const radon_op *p, const radon_sb_params *params
     hipStream_t s = static_cast<hipStream_t>(stream);
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
-        return sb_typed<TM, TV>(op, *params, f, mu, batch, ws, info, s);
+        return sb_typed<TM, TV>(op, nullptr, *params, f, mu, batch, ws, info, s);
+    });
+}
+
+extern "C" int split_bregman_tv_surrogate(const radon_op *p, const radon_surrogate *sp,
+                                          const radon_sb_params *params, const void *f, void *mu,
+                                          int32_t batch, void *ws, int64_t ws_bytes,
+                                          radon_sb_info *info, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!params) return set_error(RADON_EINVAL, "params is NULL");
+    if (!f || !mu) return set_error(RADON_EINVAL, "f and mu must be non-NULL");
+    if (!(params->lambda > 0.0)) return set_error(RADON_EINVAL, "lambda must be > 0");
+    if (params->n_outer < 0 || params->n_cg < 0)
+        return set_error(RADON_EINVAL, "n_outer and n_cg must be >= 0");
+    if (!(params->tol >= 0.0)) return set_error(RADON_EINVAL, "tol must be >= 0");
+    if (params->flags & ~(RADON_SB_WARM | RADON_SB_RESUME))
+        return set_error(RADON_EINVAL, "unknown flags 0x%x", params->flags);
+    const Op &op = *as_op(p);
+    if (!sp) return set_error(RADON_EINVAL, "surrogate is NULL");
+    const Sur &sur = *reinterpret_cast<const Sur *>(sp);
+    if (sur.n != op.n || sur.dtype != op.dtype)
+        return set_error(RADON_EINVAL, "the surrogate belongs to an operator of another size or dtype");
+    SCT_TRY(check_ws(ws, ws_bytes, sb_ws_bytes(op, batch), "split_bregman_tv_surrogate"));
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return sb_typed<TM, TV>(op, &sur, *params, f, mu, batch, ws, info, s);
     });
 }
 
