@@ -84,6 +84,9 @@ def lib():
         L.ora_loss2.argtypes = [P, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         L.ora_loss2.restype = ctypes.c_double
         L.ora_stencil.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+        L.ora_pd.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.ora_pd.restype = ctypes.c_int
         L.ora_surrogate_weights.argtypes = [P, ctypes.c_int, _dp]
         L.ora_surrogate_weights.restype = ctypes.c_int
         _lib = L
@@ -252,6 +255,15 @@ class OracleOp:
         k = lib().ora_sb(ctypes.byref(self._s), alpha, lam, n_outer, n_cg, tol, _p(f), _p(u),
                          int(u0 is not None), _p(st), int(resume), _p(ub), _p(uu))
         return u, ub[:k], uu[:k], k, st
+
+    def pd(self, f, alpha, tau, sigma, n_outer, n_cg, u0=None):
+        """Chambolle-Pock TV with inexact resolvent solves (n_cg CG steps of
+        eq:PD_resolve per outer step).  Returns u."""
+        f = _f64(f)
+        u = np.zeros(self.nn) if u0 is None else _f64(u0).copy()
+        lib().ora_pd(ctypes.byref(self._s), float(alpha), float(tau), float(sigma), int(n_outer),
+                     int(n_cg), _p(f), _p(u), int(u0 is not None))
+        return u
 
     def loss1(self, mu, f):
         mu, f = _f64(mu), _f64(f)

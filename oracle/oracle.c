@@ -500,6 +500,57 @@ int ora_sb(const ora_op *op, double alpha, double lambda, int n_outer, int n_cg,
     return k;
 }
 
+/* Chambolle-Pock primal-dual method (the method whose primal step is
+ * eq:PD_resolve, Section 2) for min_u ||K u||_1 + alpha/2 ||M R u - f||^2
+ * with anisotropic TV:
+ *   y <- clip(y + sigma K ubar, -1, 1)               (prox of the dual of ||.||_1)
+ *   u_new solves (I + tau alpha R^T M^T M R) u_new = u - tau K^T y + tau alpha R^T M^T f
+ *         approximately: n_cg CG steps from u_new = u with the true residual
+ *   ubar <- 2 u_new - u                              (extrapolation, theta = 1)
+ * u (in/out: the start if warm, else set to 0), y and ubar start as 0 and u.
+ * Returns the number of outer iterations. */
+int ora_pd(const ora_op *op, double alpha, double tau, double sigma, int n_outer, int n_cg,
+           const double *f, double *u, int warm)
+{
+    const int n = op->n;
+    const int64_t nn = (int64_t)n * n;
+    double *yx = (double *)calloc((size_t)nn, sizeof(double));
+    double *yy = (double *)calloc((size_t)nn, sizeof(double));
+    double *ub = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *uo = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *g = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *gx = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *gy = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *kt = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *r = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *au = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *scratch = (double *)malloc(sizeof(double) * (size_t)(op->rows + 4 * nn));
+    if (!warm) memset(u, 0, sizeof(double) * (size_t)nn);
+    memcpy(ub, u, sizeof(double) * (size_t)nn);
+    ora_spmv(nn, op->trp, op->tci, op->tv, f, g);              /* (MR)^T f */
+    for (int64_t j = 0; j < nn; ++j) g[j] *= tau * alpha;
+    int k;
+    for (k = 0; k < n_outer; ++k) {
+        ora_grad(n, ub, gx, gy);
+        for (int64_t j = 0; j < nn; ++j) {
+            const double vx = yx[j] + sigma * gx[j], vy = yy[j] + sigma * gy[j];
+            yx[j] = vx > 1.0 ? 1.0 : (vx < -1.0 ? -1.0 : vx);
+            yy[j] = vy > 1.0 ? 1.0 : (vy < -1.0 ? -1.0 : vy);
+        }
+        ora_gradT(n, yx, yy, kt);
+        memcpy(uo, u, sizeof(double) * (size_t)nn);
+        /* r = (u - tau K^T y + g) - (I + tau alpha R^T M^T M R) u */
+        normal_apply(op, tau * alpha, 0.0, 1.0, u, au, scratch);
+        for (int64_t j = 0; j < nn; ++j) r[j] = (u[j] - tau * kt[j] + g[j]) - au[j];
+        int bd = 0;
+        ora_cg(op, tau * alpha, 0.0, 1.0, u, r, n_cg, 0.0, NULL, &bd);
+        for (int64_t j = 0; j < nn; ++j) ub[j] = 2.0 * u[j] - uo[j];
+    }
+    free(yx); free(yy); free(ub); free(uo); free(g); free(gx); free(gy); free(kt); free(r);
+    free(au); free(scratch);
+    return k;
+}
+
 /* L1 = 0.5 ||MR mu - f||^2 ; g_mu = (MR)^T (MR mu - f) ; g_f = f - MR mu. */
 double ora_loss1(const ora_op *op, const double *mu, const double *f, double *g_mu, double *g_f)
 {

@@ -6,6 +6,9 @@
 * split Bregman with exact inner solves converges to the unique minimiser of
   alpha/2 ||MRu - f||^2 + ||Ku||_1 (eq:objmin with p = 1, K = grad), checked
   against an independent primal-dual (Chambolle-Pock) solve;
+* the primal-dual (Chambolle-Pock) iteration with CG resolvents of
+  eq:PD_resolve equals the same iteration with a dense inverse, and with
+  inexact resolvents reaches the split-Bregman minimiser;
 * split Bregman resume is bitwise, the carried residual stays consistent with
   the right-hand side of eq:SB_solve, and truncated inner solves still reduce
   the error (the error-forgetting behaviour of Section 3.2);
@@ -267,3 +270,54 @@ def test_loss2_gradient_matches_complex_step(n_iter, tol):
         assert abs(cs - an) <= tol * abs(an), (cs, an)
     # the real part reproduces the loss (to the same rounding spread)
     assert abs(_loss2_complex(op, mu + 0j, f + 0j, ta, n_iter).real - L) <= tol * 1e-2 * L
+
+
+def _dense_K(n):
+    m = n * n
+    Kd = np.zeros((2 * m, m))
+    for j in range(m):
+        e = np.zeros(m)
+        e[j] = 1.0
+        gx, gy = oracle.grad(n, e)
+        Kd[:m, j], Kd[m:, j] = gx, gy
+    return Kd
+
+
+def test_primal_dual_with_exact_resolvent_is_dense_chambolle_pock():
+    """With the resolvent of eq:PD_resolve solved to convergence by CG, the
+    oracle's primal-dual iterates are those of the same iteration with the
+    resolvent applied as a dense inverse (numpy), after every outer step."""
+    n, na = 8, 12
+    op = small_op(n, na, 1)
+    A = op.MR.to_dense()
+    Kd = _dense_K(n)
+    mu = W.phantom(n, 3, seed=7)
+    f = A @ mu + 0.05 * np.random.default_rng(7).standard_normal(A.shape[0])
+    alpha = 2.0
+    L = np.linalg.norm(Kd, 2)
+    tau = sigma = 0.99 / L
+    for iters in (1, 7, 60):
+        u_cg = op.pd(f, alpha, tau, sigma, n_outer=iters, n_cg=200)
+        u_dense = solve_tv_pdhg(A, Kd, f, alpha, iters=iters)
+        assert np.linalg.norm(u_cg - u_dense) <= 1e-10 * max(1.0, np.linalg.norm(u_dense)), iters
+
+
+def test_primal_dual_reaches_tv_minimiser_and_warm_start():
+    """Inexact resolvents (10 CG steps from the previous iterate) still reach
+    the unique minimiser that split Bregman reaches (to the 5e-7 floor those
+    inexact steps leave); a warm start begins at the given image."""
+    n, na = 8, 12
+    op = small_op(n, na, 1)
+    A = op.MR.to_dense()
+    Kd = _dense_K(n)
+    mu = W.phantom(n, 3, seed=5)
+    f = A @ mu + 0.05 * np.random.default_rng(5).standard_normal(A.shape[0])
+    alpha, lam = 2.0, 1.0
+    tau = sigma = 0.99 / np.sqrt(8.0)
+    u_pd = op.pd(f, alpha, tau, sigma, n_outer=20000, n_cg=10)
+    u_sb = op.sb(f, alpha, lam, n_outer=3000, n_cg=200)[0]
+    assert np.linalg.norm(u_pd - u_sb) <= 1e-6 * np.linalg.norm(u_sb)
+    # the warm start is the given image (the dual variable starts at 0)
+    assert np.array_equal(op.pd(f, alpha, tau, sigma, n_outer=0, n_cg=10, u0=u_sb), u_sb)
+    assert not np.array_equal(op.pd(f, alpha, tau, sigma, 3, 10, u0=u_sb),
+                              op.pd(f, alpha, tau, sigma, 3, 10))
