@@ -202,6 +202,22 @@ def bench_surrogate(sct, op, w, f, mu, u_exact, torch, timed, stream):
             "rel_err_to_phantom": round(e_sur, 4), "exact_rel_err_to_phantom": round(e_ex, 4)}
 
 
+def bench_pd(op, w, f, mu, torch, timed):
+    """Chambolle-Pock TV on the same workload: 50 primal-dual steps, each a
+    10-step CG resolvent of eq:PD_resolve from the current iterate (11
+    normal-operator applies per step)."""
+    n_outer, n_cg = 50, 10
+    op.pd(f, w.alpha, n_outer, n_cg)
+    reps = 3
+    t = timed(lambda: op.pd(f, w.alpha, n_outer, n_cg), reps) / reps
+    u = op.pd(f, w.alpha, n_outer, n_cg)
+    err = float(torch.linalg.vector_norm(u - mu) / torch.linalg.vector_norm(mu))
+    print(f"# Chambolle-Pock {n_outer} x {n_cg}: {t * 1e3:.1f} ms per reconstruction, error to "
+          f"phantom {err:.4f}", file=sys.stderr, flush=True)
+    return {"n_outer": n_outer, "n_cg": n_cg, "ms_per_recon": round(t * 1e3, 2),
+            "applies_per_s": round(n_outer * (n_cg + 1) / t, 1), "rel_err_to_phantom": round(err, 4)}
+
+
 def bench_large(sct, W, torch, dev, vdt, t):
     """The large under-resolved workload: 2048 x 2048, 90 angles, 2897 bins
     (4.8e8 nonzeros), split Bregman 30 outer x 10 CG on a random-ellipse
@@ -388,6 +404,7 @@ def main():
     }
 
     result["surrogate"] = bench_surrogate(sct, op, w, f, mu, u, torch, timed, stream)
+    result["primal_dual"] = bench_pd(op, w, f, mu, torch, timed)
 
     if not args.no_batched:
         result["batched"] = bench_batched(sct, W, torch, dev, vdt)

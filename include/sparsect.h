@@ -135,6 +135,7 @@ const char *radon_last_error(void);
 #define RADON_WS_NORMAL   1
 #define RADON_WS_CG       2
 #define RADON_WS_SB       3
+#define RADON_WS_PD       4
 
 /* Bytes of device workspace a call of the given kind needs for `batch`
  * right-hand sides (>= 0; negative = error status). */
@@ -366,6 +367,33 @@ int radon_multi_cg_graph(const radon_multi *m, const void *rhs, void *x, int32_t
                          radon_graph **out);
 int radon_graph_launch(const radon_graph *g, void *stream);
 void radon_graph_destroy(radon_graph *g);
+
+/*
+ * chambolle_pock_tv -- the primal-dual method of Chambolle and Pock, whose
+ * primal step is the resolvent system eq:PD_resolve (Section 2), for
+ * min_u ||K u||_1 + alpha/2 ||M R u - f||^2 (anisotropic TV):
+ *   y <- clip(y + sigma K ubar, -1, 1);
+ *   u_new: n_cg CG steps on (I + tau alpha R^T M^T M R) u_new
+ *          = u - tau K^T y + tau alpha R^T M^T f, from u_new = u with its true
+ *          residual;
+ *   ubar <- 2 u_new - u.
+ * y starts at 0, ubar at u; convergence needs tau sigma ||K||^2 < 1, and
+ * ||K||^2 <= 8.  Each outer step costs n_cg + 1 normal-operator applies.
+ *   f   device [batch][n_meas_rays];  mu device [batch][n*n]: the start if
+ *       flags has RADON_SB_WARM (else zeroed), receives u.
+ *   ws  radon_workspace_bytes(op, RADON_WS_PD, batch) bytes.
+ */
+typedef struct {
+    double alpha;         /* data weight (eq:objmin) */
+    double tau, sigma;    /* primal and dual step sizes */
+    int32_t n_outer;      /* primal-dual iterations */
+    int32_t n_cg;         /* CG steps per resolvent solve */
+    int32_t flags;        /* RADON_SB_WARM */
+    int32_t reserved;
+} radon_pd_params;
+
+int chambolle_pock_tv(const radon_op *op, const radon_pd_params *params, const void *f,
+                      void *mu, int32_t batch, void *ws, int64_t ws_bytes, void *stream);
 
 /*
  * Surrogate operator T (Section 3.2, eq:def_sparse_surr): the sum over all

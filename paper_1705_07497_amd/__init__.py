@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsparsect.so")
 
 F32, F64, F32_F64 = 0, 1, 2
-WS_FWD, WS_NORMAL, WS_CG, WS_SB = 0, 1, 2, 3
+WS_FWD, WS_NORMAL, WS_CG, WS_SB, WS_PD = 0, 1, 2, 3, 4
 SB_WARM, SB_RESUME = 1, 2
 
 _vp = ctypes.c_void_p
@@ -55,6 +55,12 @@ class CgInfo(ctypes.Structure):
 
 class SbParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("lambda_", ctypes.c_double), ("tol", ctypes.c_double),
+                ("n_outer", ctypes.c_int32), ("n_cg", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class PdParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("n_outer", ctypes.c_int32), ("n_cg", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
@@ -114,6 +120,8 @@ SIGNATURES = {
                                             ctypes.c_int64, _vp, ctypes.POINTER(_vp)]),
     "radon_graph_launch": (ctypes.c_int, [_vp, _vp]),
     "radon_graph_destroy": (None, [_vp]),
+    "chambolle_pock_tv": (ctypes.c_int, [_vp, ctypes.POINTER(PdParams), _vp, _vp, ctypes.c_int32,
+                                          _vp, ctypes.c_int64, _vp]),
     "radon_surrogate_create": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.POINTER(_vp)]),
     "radon_surrogate_destroy": (None, [_vp]),
     "radon_surrogate_weights": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), _vp]),
@@ -419,6 +427,28 @@ class RadonOp:
                                      tape.numel(), self._p(gx), self._p(g), b, int(n_iter), int(ckpt),
                                      self._p(ws), ws.numel(), self._stream()))
         return g
+
+    def pd(self, f, alpha: float, n_outer: int, n_cg: int, tau: float | None = None,
+           sigma: float | None = None, mu0=None, out=None):
+        """Chambolle-Pock TV (primal step eq:PD_resolve); tau = sigma = 0.99/sqrt(8)
+        by default.  Returns mu."""
+        torch = _torch()
+        b = self._sino(f, "f")
+        step = 0.99 / np.sqrt(8.0)
+        tau = step if tau is None else tau
+        sigma = step if sigma is None else sigma
+        flags = 0
+        if mu0 is not None:
+            flags |= SB_WARM
+            mu = mu0.clone() if out is None else out.copy_(mu0)
+        else:
+            mu = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self._img(mu, "mu")
+        P = PdParams(float(alpha), float(tau), float(sigma), int(n_outer), int(n_cg), flags, 0)
+        ws, nb = self.workspace(WS_PD, b)
+        _check(lib().chambolle_pock_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b,
+                                       self._p(ws), nb, self._stream()))
+        return mu
 
     # -- host copies ------------------------------------------------------------
     def export_csr(self):

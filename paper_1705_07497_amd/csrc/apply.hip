@@ -348,6 +348,7 @@ static int64_t normal_ws_bytes(const Op &op, int batch)
 
 int64_t cg_ws_bytes(const Op &op, int batch);   // solve.hip
 int64_t sb_ws_bytes(const Op &op, int batch);   // solve.hip
+int64_t pd_ws_bytes(const Op &op, int batch);   // solve.hip
 
 }  // namespace sct
 
@@ -364,6 +365,7 @@ extern "C" int64_t radon_workspace_bytes(const radon_op *p, int32_t which, int32
     case RADON_WS_NORMAL: return normal_ws_bytes(op, batch);
     case RADON_WS_CG: return cg_ws_bytes(op, batch);
     case RADON_WS_SB: return sb_ws_bytes(op, batch);
+    case RADON_WS_PD: return pd_ws_bytes(op, batch);
     default: return set_error(RADON_EINVAL, "unknown workspace kind %d", which);
     }
 }

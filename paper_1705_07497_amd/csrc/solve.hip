@@ -603,6 +603,140 @@ static int sb_typed(const Op &op, const Sur *sur, const radon_sb_params &P, cons
                          info, s);
 }
 
+
+// ---------------------------------------------------------------------------
+// Chambolle-Pock primal-dual TV (the method whose primal step is eq:PD_resolve)
+// ---------------------------------------------------------------------------
+
+// y <- clip(y + sigma K ubar, -1, 1) per component (anisotropic TV dual)
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_pd_dual(const T *__restrict__ ub,
+                                                          T *__restrict__ yx, T *__restrict__ yy,
+                                                          T sigma, int n, int64_t nn)
+{
+    const int64_t off = int64_t(blockIdx.y) * nn;
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
+         i += int64_t(gridDim.x) * kVecThreads) {
+        const int iy = int(i / n), ix = int(i % n);
+        const int64_t j = off + i;
+        const T u = ub[j];
+        const T gx = ix < n - 1 ? ub[j + 1] - u : T(0);
+        const T gy = iy < n - 1 ? ub[j + n] - u : T(0);
+        yx[j] = fmin(fmax(yx[j] + sigma * gx, T(-1)), T(1));
+        yy[j] = fmin(fmax(yy[j] + sigma * gy, T(-1)), T(1));
+    }
+}
+
+// r <- u - tau K^T y + g (the right-hand side of eq:PD_resolve, g = tau alpha
+// (MR)^T f); uo <- u
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_pd_rhs(const T *__restrict__ u,
+                                                         const T *__restrict__ yx,
+                                                         const T *__restrict__ yy,
+                                                         const T *__restrict__ g, T tau,
+                                                         T *__restrict__ r, T *__restrict__ uo,
+                                                         int n, int64_t nn)
+{
+    const int64_t off = int64_t(blockIdx.y) * nn;
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
+         i += int64_t(gridDim.x) * kVecThreads) {
+        const int iy = int(i / n), ix = int(i % n);
+        const int64_t j = off + i;
+        T kt = T(0);
+        if (ix >= 1) kt += yx[j - 1];
+        if (ix <= n - 2) kt -= yx[j];
+        if (iy >= 1) kt += yy[j - n];
+        if (iy <= n - 2) kt -= yy[j];
+        const T uj = u[j];
+        r[j] = (uj - tau * kt) + g[j];
+        uo[j] = uj;
+    }
+}
+
+// ubar <- 2 u - uo (extrapolation with theta = 1)
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_pd_extrap(const T *__restrict__ u,
+                                                            const T *__restrict__ uo,
+                                                            T *__restrict__ ub, int64_t count)
+{
+    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < count;
+         i += int64_t(gridDim.x) * kVecThreads)
+        ub[i] = T(2) * u[i] - uo[i];
+}
+
+template <class T>
+struct PdBufs {
+    CgBufs<T> cg;
+    T *yx, *yy, *ub, *uo, *g;
+};
+
+template <class T>
+static void carve_pd(const Op &op, int batch, Carver &c, PdBufs<T> &w)
+{
+    const int64_t nb = op.nn * batch;
+    carve_cg(op, batch, c, w.cg);
+    w.yx = c.take<T>(nb);
+    w.yy = c.take<T>(nb);
+    w.ub = c.take<T>(nb);
+    w.uo = c.take<T>(nb);
+    w.g = c.take<T>(nb);
+}
+
+int64_t pd_ws_bytes(const Op &op, int batch)
+{
+    Carver c(nullptr);
+    if (op.vsize == 4) {
+        PdBufs<float> w;
+        carve_pd(op, batch, c, w);
+    } else {
+        PdBufs<double> w;
+        carve_pd(op, batch, c, w);
+    }
+    return c.used;
+}
+
+template <class TM, class T>
+static int pd_typed(const Op &op, const radon_pd_params &P, const void *f_v, void *mu_v, int batch,
+                    void *ws, hipStream_t s)
+{
+    Carver c(ws);
+    PdBufs<T> w;
+    carve_pd(op, batch, c, w);
+    const T *f = static_cast<const T *>(f_v);
+    T *u = static_cast<T *>(mu_v);
+    const int64_t cnt = op.nn * batch;
+    const int vbc = vec_blocks(cnt), vb = vec_blocks(op.nn);
+    const dim3 vg{unsigned(vb), unsigned(batch), 1u};
+    const double ta = P.tau * P.alpha;
+    const ExactA<TM, T> A{op, ta, 0.0, 1.0};   // I + tau alpha R^T M^T M R
+    if (!(P.flags & RADON_SB_WARM)) {
+        k_fill<T><<<vbc, kVecThreads, 0, s>>>(u, T(0), cnt);
+        SCT_TRY(check_launch("k_fill"));
+    }
+    for (T *z : {w.yx, w.yy}) {
+        k_fill<T><<<vbc, kVecThreads, 0, s>>>(z, T(0), cnt);
+        SCT_TRY(check_launch("k_fill"));
+    }
+    k_copy<T><<<vbc, kVecThreads, 0, s>>>(u, w.ub, cnt);
+    SCT_TRY(check_launch("k_copy"));
+    SCT_TRY((launch_adj<TM, T>(op, f, nullptr, w.g, ta, 0.0, 0.0, nullptr, batch, s)));
+    for (int k = 0; k < P.n_outer; ++k) {
+        k_pd_dual<T><<<vg, kVecThreads, 0, s>>>(w.ub, w.yx, w.yy, T(P.sigma), op.n, op.nn);
+        SCT_TRY(check_launch("k_pd_dual"));
+        k_pd_rhs<T><<<vg, kVecThreads, 0, s>>>(u, w.yx, w.yy, w.g, T(P.tau), w.cg.r, w.uo, op.n,
+                                                op.nn);
+        SCT_TRY(check_launch("k_pd_rhs"));
+        // CG from the current iterate with its true residual r = rhs - A u
+        SCT_TRY((apply_A_into_q<T>(op, A, u, batch, w.cg, s)));
+        k_sub<T><<<vbc, kVecThreads, 0, s>>>(w.cg.r, w.cg.q, w.cg.r, cnt);
+        SCT_TRY(check_launch("k_sub"));
+        SCT_TRY((cg_run<T>(op, A, u, batch, P.n_cg, 0.0, w.cg, nullptr, nullptr, nullptr, s)));
+        k_pd_extrap<T><<<vbc, kVecThreads, 0, s>>>(u, w.uo, w.ub, cnt);
+        SCT_TRY(check_launch("k_pd_extrap"));
+    }
+    return RADON_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Unrolled CG: forward with a checkpoint tape, and its vector-Jacobian product
 // ---------------------------------------------------------------------------
@@ -1134,5 +1268,29 @@ extern "C" int cg_unrolled_vjp(const radon_op *p, double alpha, double lambda, d
         return unrolled_vjp_typed<TM, TV>(op, alpha, lambda, sigma, tape,
                                           static_cast<const TV *>(gx), static_cast<TV *>(grhs),
                                           batch, n_iter, k, ws, s);
+    });
+}
+
+extern "C" int chambolle_pock_tv(const radon_op *p, const radon_pd_params *params, const void *f,
+                                 void *mu, int32_t batch, void *ws, int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!params) return set_error(RADON_EINVAL, "params is NULL");
+    if (!f || !mu) return set_error(RADON_EINVAL, "f and mu must be non-NULL");
+    if (!(params->tau > 0.0) || !(params->sigma > 0.0))
+        return set_error(RADON_EINVAL, "tau and sigma must be > 0");
+    if (!(params->alpha >= 0.0)) return set_error(RADON_EINVAL, "alpha must be >= 0");
+    if (params->n_outer < 0 || params->n_cg < 0)
+        return set_error(RADON_EINVAL, "n_outer and n_cg must be >= 0");
+    if (params->flags & ~RADON_SB_WARM) return set_error(RADON_EINVAL, "unknown flags 0x%x", params->flags);
+    const Op &op = *as_op(p);
+    SCT_TRY(check_ws(ws, ws_bytes, pd_ws_bytes(op, batch), "chambolle_pock_tv"));
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return pd_typed<TM, TV>(op, *params, f, mu, batch, ws, s);
     });
 }

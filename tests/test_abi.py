@@ -43,6 +43,8 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct.SbParams) == 40
     assert ctypes.sizeof(sct.SbInfo) == 32
     assert ctypes.sizeof(sct._Info) == 80
+    assert ctypes.sizeof(sct.PdParams) == 40
+    assert int(consts["RADON_WS_PD"]) == sct.WS_PD
 
 
 def _build(n, na, nb, dtype=0, measured=None):
