@@ -9,7 +9,9 @@ Every function follows the paper (Barnard & Archibald, arXiv 1705.07497):
 the objective eq:objmin (Section 1), the normal operator of eq:KKT,
 eq:PD_resolve and eq:SB_solve (Section 2), conjugate gradients for those
 systems (Section 2) and anisotropic-TV split Bregman (Section 4), with the
-Radon transform as an exact Siddon intersection-length matrix.
+Radon transform as an exact Siddon intersection-length matrix.  The Fourier
+form of the problem (eq:four_obj, eq:SBFFT) and its convolution-fused normal
+operator (eq:fusedop) live in ``oracle/fourier.py`` (numpy, FP64).
 
 Parity: pinned by tests/test_oracle_*.py (brute-force clipping, closed forms,
 invariants, dense solves, an independent primal-dual solver, finite and
