@@ -443,6 +443,99 @@ int split_bregman_tv_surrogate(const radon_op *op, const radon_surrogate *s,
                                void *stream);
 
 /*
+ * Fourier-domain operator (Sections 2 and 3.1: eq:four_obj, eq:SBFFT,
+ * eq:fusedop).  By the Fourier slice theorem, the 1-D DFT of the projection
+ * at measured angle theta_k = pi k / n_angles and radial frequency
+ * rho_q = 2 pi q / n_bins samples the 2-D Fourier transform of the image at
+ *   xi_p = rho_q (cos theta_k, sin theta_k),  q = -Q .. Q,  Q = (n_bins-1)/2
+ * (integer division, so the set is closed under xi -> -xi).  Point p =
+ * a (2Q + 1) + q + Q for the a-th measured angle.  With pixel modes
+ * m = (ix - n/2, iy - n/2) (integer division) the forward map is
+ *   (F^* mu)_p = sum_m mu_m exp(-i xi_p . m),
+ * its adjoint (F fhat)_m = sum_p fhat_p exp(+i xi_p . m), and the split-
+ * Bregman system eq:SBFFT needs H = Re(F F^*).  All three are evaluated by
+ * Gaussian gridding (the NUFFT of Greengard and Lee) on an M x M frequency
+ * grid (M a power of two, 2n <= M <= 4096), with the heat kernel
+ * exp(-|xi - eta|^2 / (4 tau)) over the 2 m_sp nearest grid points per
+ * dimension and the deconvolution A = (pi / tau) exp(|m|^2 tau):
+ *   F^* ~ B^* F_D^* A,   F ~ A F_D B,
+ *   H   ~ Re(A F_D (B B^*) F_D^* A)   with B B^* precomputed as one sparse
+ *         grid-to-grid matrix (RADON_FOURIER_FUSED, eq:fusedop), or as the
+ *         product of the two gridded transforms (RADON_FOURIER_NUFFT).
+ * Complex arrays are interleaved (re, im) pairs of the operator's vector type
+ * (float for SPARSECT_F32, double otherwise); the stored gridding weights and
+ * B B^* use the matrix value type.  The handle borrows `op` (which must
+ * outlive it) and owns its tables.
+ */
+typedef struct radon_fourier radon_fourier;   /* opaque Fourier-operator handle */
+
+typedef struct {
+    int64_t n_points;       /* P = n_meas_angles * (2Q + 1) */
+    int32_t grid;           /* M */
+    int32_t m_sp;           /* half window, grid points per dimension */
+    double tau;             /* heat-kernel width */
+    int64_t fused_tiles;    /* stored 8 x 8 grid tiles of B B^* (the others are zero) */
+    int64_t fused_bytes;    /* bytes of their coefficients */
+    int64_t spread_nnz;     /* entries of the gridding matrix B: P (2 m_sp)^2 */
+    int64_t device_bytes;   /* device memory held by the handle */
+} radon_fourier_info;
+
+#define RADON_FOURIER_FUSED 0   /* H through the precomputed B B^* */
+#define RADON_FOURIER_NUFFT 1   /* H as the gridded F composed with the gridded F^* */
+
+#define RADON_FWS_TRANSFORM 0   /* fourier_fwd, fourier_adj, fourier_normal */
+#define RADON_FWS_SB        1   /* split_bregman_tv_fourier */
+
+/*
+ * radon_fourier_create -- point set, gridding tables and B B^* of `op`'s
+ * geometry.  m_sp in [1, 12] (6 and 12 give about 6 and 12 digits); tau 0
+ * selects 4 m_sp / M^2 (= m_sp / n^2 on the 2n grid); grid 0 selects the
+ * smallest power of two >= 2n.  B B^* is stored as a variable-coefficient
+ * stencil: for each grid point s of a non-empty 8 x 8 tile, its
+ * (4 m_sp - 1)^2 coefficients C[s][d] = sum_p g_p(s) g_p(s + d) (periodic
+ * indices).  Synchronous on `stream`; the handle owns all its device memory.
+ */
+int radon_fourier_create(const radon_op *op, int32_t m_sp, double tau, int32_t grid, void *stream,
+                         radon_fourier **out);
+void radon_fourier_destroy(radon_fourier *f);
+int radon_fourier_get_info(const radon_fourier *f, radon_fourier_info *out);
+/* workspace bytes for `which` (RADON_FWS_*) and `batch` images; -1 on error */
+int64_t radon_fourier_workspace_bytes(const radon_fourier *f, int32_t which, int32_t batch);
+
+/*
+ * fourier_fwd -- fhat = F^* mu (gridded): mu device [batch][n*n], fhat device
+ * [batch][P] complex.  ws: radon_fourier_workspace_bytes(RADON_FWS_TRANSFORM).
+ */
+int fourier_fwd(const radon_fourier *f, const void *mu, void *fhat, int32_t batch, void *ws,
+                int64_t ws_bytes, void *stream);
+
+/*
+ * fourier_adj -- x = alpha Re(F fhat) (gridded): fhat device [batch][P]
+ * complex, x device [batch][n*n].  This is the data term of eq:SBFFT.
+ */
+int fourier_adj(const radon_fourier *f, const void *fhat, void *x, double alpha, int32_t batch,
+                void *ws, int64_t ws_bytes, void *stream);
+
+/*
+ * fourier_normal -- out = alpha H x + lambda K^T K x + sigma x with H by
+ * `path` (RADON_FOURIER_FUSED or RADON_FOURIER_NUFFT); with dot_out (device
+ * double[batch]) also <x, out>.  out must not alias x.
+ */
+int fourier_normal(const radon_fourier *f, int32_t path, double alpha, double lambda, double sigma,
+                   const void *x, void *out, double *dot_out, int32_t batch, void *ws,
+                   int64_t ws_bytes, void *stream);
+
+/*
+ * split_bregman_tv_fourier -- split_bregman_tv on eq:SBFFT: every inner CG
+ * solve is on alpha H + lambda K^T K (H by `path`), the data term is
+ * alpha Re(F fhat) with fhat device [batch][P] complex; params, mu and info
+ * as for split_bregman_tv.  ws: radon_fourier_workspace_bytes(RADON_FWS_SB).
+ */
+int split_bregman_tv_fourier(const radon_fourier *f, int32_t path, const radon_sb_params *params,
+                             const void *fhat, void *mu, int32_t batch, void *ws, int64_t ws_bytes,
+                             radon_sb_info *info, void *stream);
+
+/*
  * Launch tuning of an operator (not part of the method: it only changes how
  * the products are scheduled; the waves-per-item counts split each sum
  * differently, so results change at the rounding level; the fused chunk

@@ -115,14 +115,26 @@ class Gridding:
     """The pieces A, F_D, B of eq:fusedop for one image size and point set."""
 
     def __init__(self, n: int, xi: np.ndarray, m_sp: int = 6, tau: float | None = None,
-                 grid: int | None = None):
+                 grid: int | None = None, values: str = "f64"):
+        """values="f32" rounds the stored tables as a library that keeps them
+        in FP32 does: every entry of S (each window product g_y g_x) and every
+        entry of S S^T (formed from the unrounded S), each rounded once; the
+        rest stays FP64."""
         self.n, self.xi = n, np.asarray(xi, dtype=float)
+        self.values = values
         self.m_sp = m_sp
         self.M = default_grid(n) if grid is None else int(grid)
         self.tau = default_tau(self.M, m_sp) if tau is None else float(tau)
         if self.M < 2 * n:
             raise ValueError("grid must be at least 2n")
         self.S = self._spread_matrix()
+        self.S_used = self.S if values == "f64" else self._round32(self.S)
+
+    @staticmethod
+    def _round32(A):
+        A = A.copy()
+        A.data = A.data.astype(np.float32).astype(np.float64)
+        return A
 
     def a_diag(self) -> np.ndarray:
         """A on the image: product over the two dimensions of
@@ -180,16 +192,19 @@ class Gridding:
     def nufft_fwd(self, mu: np.ndarray) -> np.ndarray:
         """Gridded F_nu^* mu = B^* F_D^* A mu (type-2 NUFFT)."""
         h = self.grid_of_image(mu).ravel()
-        return (self.S.T @ h) / (self.M * self.M)
+        return (self.S_used.T @ h) / (self.M * self.M)
 
     def nufft_adj(self, fh: np.ndarray) -> np.ndarray:
         """Gridded F_nu fhat = A F_D B fhat (type-1 NUFFT), complex image."""
-        s = (self.S @ np.asarray(fh, dtype=complex)) / (self.M * self.M)
+        s = (self.S_used @ np.asarray(fh, dtype=complex)) / (self.M * self.M)
         return self.image_of_grid(s)
 
     def fused_matrix(self):
         """B B^* = S S^T / M^4: the grid-to-grid matrix of eq:fusedop."""
-        return (self.S @ self.S.T) / float(self.M) ** 4
+        SS = (self.S @ self.S.T).tocsr()
+        if self.values != "f64":
+            SS = self._round32(SS)
+        return SS / float(self.M) ** 4
 
     def fused_normal(self, mu: np.ndarray, BB=None) -> np.ndarray:
         """Re(A F_D (B B^*) F_D^* A mu), eq:fusedop with B B^* precomputed."""

@@ -65,6 +65,16 @@ class PdParams(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class FourierInfo(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("grid", ctypes.c_int32), ("m_sp", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("fused_tiles", ctypes.c_int64), ("fused_bytes", ctypes.c_int64),
+                ("spread_nnz", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+FOURIER_FUSED, FOURIER_NUFFT = 0, 1
+FWS_TRANSFORM, FWS_SB = 0, 1
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("fwd_waves", ctypes.c_int32), ("adj_waves", ctypes.c_int32),
                 ("fwd_rhs", ctypes.c_int32), ("adj_rhs", ctypes.c_int32)]
@@ -129,6 +139,19 @@ SIGNATURES = {
                                        _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
     "split_bregman_tv_surrogate": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(SbParams), _vp, _vp,
                                                   ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]),
+    "radon_fourier_create": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp,
+                                            ctypes.POINTER(_vp)]),
+    "radon_fourier_destroy": (None, [_vp]),
+    "radon_fourier_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(FourierInfo)]),
+    "radon_fourier_workspace_bytes": (ctypes.c_int64, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "fourier_fwd": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
+    "fourier_adj": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, ctypes.c_int64,
+                                   _vp]),
+    "fourier_normal": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, _vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64,
+                                      _vp]),
+    "split_bregman_tv_fourier": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(SbParams), _vp, _vp,
+                                                ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]),
     "cg_unrolled_vjp": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp,
                                        ctypes.c_int64, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
@@ -509,6 +532,123 @@ class RadonSurrogate:
                                      _vp(d.data_ptr()) if dot else None, b, _vp(ws.data_ptr()),
                                      nbytes, self.op._stream()))
         return (o, d) if dot else o
+
+
+class RadonFourier:
+    """The Fourier-domain operator of a RadonOp's geometry (Sections 2 and
+    3.1): the gridded transforms F^* (image -> polar Fourier samples, one per
+    measured angle and radial DFT frequency) and F, and the normal operator
+    H = Re(F F^*) of eq:SBFFT, either through the precomputed B B^* of
+    eq:fusedop (path "fused") or through the two transforms ("nufft").
+    Fourier samples are real tensors [batch, P, 2] (re, im) of the operator's
+    vector dtype."""
+
+    PATHS = {"fused": FOURIER_FUSED, "nufft": FOURIER_NUFFT}
+
+    def __init__(self, op: RadonOp, m_sp: int = 6, tau: float = 0.0, grid: int = 0):
+        torch = _torch()
+        self.op = op   # borrowed by the handle: keep it alive
+        self.n, self.nn, self.dtype, self.device = op.n, op.nn, op.dtype, op.device
+        h = _vp()
+        with torch.cuda.device(op.device):
+            _check(lib().radon_fourier_create(op._h, int(m_sp), float(tau), int(grid), op._stream(),
+                                              ctypes.byref(h)))
+        self._h = h
+        info = FourierInfo()
+        _check(lib().radon_fourier_get_info(self._h, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in FourierInfo._fields_}
+        self.P, self.grid, self.m_sp, self.tau = info.n_points, info.grid, info.m_sp, info.tau
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.radon_fourier_destroy(h)
+            self._h = None
+
+    def _stream(self):
+        return self.op._stream()
+
+    def workspace(self, which: int, batch: int):
+        torch = _torch()
+        nbytes = lib().radon_fourier_workspace_bytes(self._h, which, batch)
+        if nbytes < 0:
+            _check(int(nbytes))
+        buf = self._ws.get((which, batch))
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+            self._ws[(which, batch)] = buf
+        return buf, int(nbytes)
+
+    def _samples(self, f, name="fhat"):
+        torch = _torch()
+        if not isinstance(f, torch.Tensor) or f.device != self.device or f.dtype != self.dtype:
+            raise SparsectError(f"{name} must be a {self.dtype} tensor on {self.device}")
+        if not f.is_contiguous() or f.numel() % (2 * self.P):
+            raise SparsectError(f"{name} must be contiguous with a multiple of 2 P = {2 * self.P} elements")
+        return f.numel() // (2 * self.P)
+
+    def fwd(self, mu, out=None):
+        """fhat = F^* mu (gridded), [batch, P, 2]."""
+        torch = _torch()
+        b = self.op._img(mu, "mu")
+        o = torch.empty((b, self.P, 2), dtype=self.dtype, device=self.device) if out is None else out
+        self._samples(o, "out")
+        ws, nb = self.workspace(FWS_TRANSFORM, b)
+        _check(lib().fourier_fwd(self._h, _vp(mu.data_ptr()), _vp(o.data_ptr()), b, _vp(ws.data_ptr()),
+                                 nb, self._stream()))
+        return o
+
+    def adj(self, fhat, alpha: float = 1.0, out=None):
+        """x = alpha Re(F fhat) (gridded), [batch, n*n]."""
+        torch = _torch()
+        b = self._samples(fhat)
+        o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self.op._img(o, "out")
+        ws, nb = self.workspace(FWS_TRANSFORM, b)
+        _check(lib().fourier_adj(self._h, _vp(fhat.data_ptr()), _vp(o.data_ptr()), float(alpha), b,
+                                 _vp(ws.data_ptr()), nb, self._stream()))
+        return o
+
+    def normal(self, x, alpha: float = 1.0, lam: float = 0.0, sigma: float = 0.0, path: str = "fused",
+               out=None, dot: bool = False):
+        """alpha H x + lam K^T K x + sigma x (and <x, out> per image if dot)."""
+        torch = _torch()
+        b = self.op._img(x)
+        o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self.op._img(o, "out")
+        d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
+        ws, nb = self.workspace(FWS_TRANSFORM, b)
+        _check(lib().fourier_normal(self._h, self.PATHS[path], float(alpha), float(lam), float(sigma),
+                                    _vp(x.data_ptr()), _vp(o.data_ptr()),
+                                    _vp(d.data_ptr()) if dot else None, b, _vp(ws.data_ptr()), nb,
+                                    self._stream()))
+        return (o, d) if dot else o
+
+    def sb(self, fhat, alpha: float, lam: float, n_outer: int, n_cg: int, tol: float = 0.0,
+           path: str = "fused", mu0=None, resume: bool = False, out=None):
+        """Split Bregman TV on eq:SBFFT; returns (mu, info tensor of SbInfo bytes)."""
+        torch = _torch()
+        b = self._samples(fhat)
+        flags = 0
+        if resume:
+            flags |= SB_RESUME
+            if out is None:
+                raise SparsectError("resume needs out= (the image of the previous call)")
+            mu = out
+        elif mu0 is not None:
+            flags |= SB_WARM
+            mu = mu0.clone() if out is None else out.copy_(mu0)
+        else:
+            mu = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self.op._img(mu, "mu")
+        P = SbParams(float(alpha), float(lam), float(tol), int(n_outer), int(n_cg), flags, 0)
+        info = torch.zeros(b * ctypes.sizeof(SbInfo), dtype=torch.uint8, device=self.device)
+        ws, nb = self.workspace(FWS_SB, b)
+        _check(lib().split_bregman_tv_fourier(self._h, self.PATHS[path], ctypes.byref(P),
+                                              _vp(fhat.data_ptr()), _vp(mu.data_ptr()), b,
+                                              _vp(ws.data_ptr()), nb, _vp(info.data_ptr()), self._stream()))
+        return mu, info
 
 
 class RadonMulti:

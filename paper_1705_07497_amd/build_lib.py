@@ -15,7 +15,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsparsect.so")
-SOURCES = ["build.hip", "apply.hip", "solve.hip", "multi.hip", "surrogate.hip"]
+SOURCES = ["build.hip", "apply.hip", "solve.hip", "multi.hip", "surrogate.hip", "fourier.hip"]
 ARCH = os.environ.get("SPARSECT_ARCH", "gfx950")
 
 COMMON = [

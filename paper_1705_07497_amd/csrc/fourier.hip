@@ -1,0 +1,878 @@
+// Fourier-domain operator of Sections 2 and 3.1 (eq:four_obj, eq:SBFFT,
+// eq:fusedop).
+//
+// The measured projections' 1-D DFTs sample the image's 2-D Fourier transform
+// on polar points xi_p (Fourier slice theorem).  The normal operator of the
+// Fourier-domain problem, H = Re(F F^*) with (F^* mu)_p = sum_m mu_m
+// exp(-i xi_p . m), is evaluated by Greengard-Lee Gaussian gridding on an
+// M x M frequency grid:
+//
+//   F^* ~ B^* F_D^* A,   F ~ A F_D B,   H ~ Re(A F_D (B B^*) F_D^* A)
+//
+// with A the deconvolution (pi/tau) exp(|m|^2 tau), F_D^* / F_D the unscaled
+// DFTs onto and off the grid, B^* the heat-kernel interpolation at the points
+// and B the spreading.  eq:fusedop precomputes B B^*: here it is stored as a
+// variable-coefficient stencil over the grid (every nonzero of a row lies
+// within 2 m_sp - 1 grid points per dimension), in 8 x 8 tiles of grid points
+// with the 64 points' coefficients for one offset contiguous, so the product
+// streams the coefficients once with full-line loads and reads the grid from
+// LDS.  Tiles that no point's window reaches hold no coefficients.
+//
+// The grid is kept in centred order: grid point s stands for the frequency
+// (s - M/2) 2 pi / M.  The resulting (-1)^m factors and the two 1/M^2 of the
+// trapezoid rule are folded into the per-mode scale a1 = sqrt(pi/tau)
+// exp(m^2 tau) (-1)^m / M applied at zero-padding and at cropping.  The DFTs
+// are radix-2 transforms of whole grid lines in LDS (row pass, column pass);
+// rows that hold no image mode are skipped on the way in and not written on
+// the way out.
+#include "cg.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+namespace sct {
+
+template <class T>
+struct alignas(2 * sizeof(T)) C2 {
+    T x, y;
+};
+
+constexpr int kFouMaxMsp = 12;
+constexpr int kFouMaxGrid = 4096;
+constexpr int kFftThreads = 256;
+constexpr int kFftLdsBudget = 80 * 1024;   // per workgroup, two per CU
+
+__device__ inline int brev(int i, int logM) { return int(__brev(unsigned(i)) >> (32 - logM)); }
+
+// In-place radix-2 DFT of `lines` lines of M points held in bit-reversed
+// order in buf (line stride `stride`); natural order on return.  sign -1 for
+// exp(-2 pi i j k / M) (F_D^*), +1 for its adjoint F_D; tw[k] =
+// exp(-2 pi i k / M), k < M/2.
+template <class T>
+__device__ void lds_fft(C2<T> *buf, int lines, int M, int logM, int stride, const C2<T> *tw, int sign)
+{
+    const int half = M >> 1;
+    for (int st = 0; st < logM; ++st) {
+        const int hs = 1 << st;
+        for (int j = threadIdx.x; j < lines * half; j += blockDim.x) {
+            const int line = j >> (logM - 1);
+            const int jj = j & (half - 1);
+            const int k = jj & (hs - 1);
+            const int i0 = ((jj >> st) << (st + 1)) + k;
+            C2<T> w = tw[k << (logM - 1 - st)];
+            if (sign > 0) w.y = -w.y;
+            C2<T> *b = buf + line * stride;
+            const C2<T> a = b[i0], c = b[i0 + hs];
+            const T tx = c.x * w.x - c.y * w.y, ty = c.x * w.y + c.y * w.x;
+            b[i0] = C2<T>{a.x + tx, a.y + ty};
+            b[i0 + hs] = C2<T>{a.x - tx, a.y - ty};
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+__device__ inline void load_tw(C2<T> *tw_l, const C2<T> *__restrict__ tw, int M)
+{
+    for (int k = threadIdx.x; k < (M >> 1); k += blockDim.x) tw_l[k] = tw[k];
+}
+
+// grid line index i -> image index along that axis, -1 if i holds no mode
+__device__ inline int mode_of(int i, int n, int M)
+{
+    const int h = n >> 1;
+    if (i < n - h) return i + h;
+    if (i >= M - h) return i - M + h;
+    return -1;
+}
+
+// Row pass of F_D^* A: image rows -> grid rows (m_y mod M), zero-padded and
+// scaled by a1[iy] a1[ix].
+template <class T>
+__global__ __launch_bounds__(kFftThreads) void k_fou_rows_fwd(const T *__restrict__ x, C2<T> *__restrict__ G,
+                                                              const T *__restrict__ a1,
+                                                              const C2<T> *__restrict__ tw, int n,
+                                                              int M, int logM, int L, int64_t nn,
+                                                              int64_t MM)
+{
+    extern __shared__ char smem[];
+    C2<T> *tw_l = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = tw_l + (M >> 1);
+    const int stride = M + 1;
+    const int64_t xo = int64_t(blockIdx.y) * nn, go = int64_t(blockIdx.y) * MM;
+    const int iy0 = blockIdx.x * L;
+    load_tw(tw_l, tw, M);
+    for (int e = threadIdx.x; e < L * M; e += blockDim.x) {
+        const int line = e >> logM, i = e & (M - 1);
+        const int iy = iy0 + line;
+        C2<T> v{T(0), T(0)};
+        const int ix = mode_of(i, n, M);
+        if (iy < n && ix >= 0) v.x = a1[iy] * a1[ix] * x[xo + int64_t(iy) * n + ix];
+        buf[line * stride + brev(i, logM)] = v;
+    }
+    __syncthreads();
+    lds_fft(buf, L, M, logM, stride, tw_l, -1);
+    const int h = n >> 1;
+    for (int e = threadIdx.x; e < L * M; e += blockDim.x) {
+        const int line = e >> logM, i = e & (M - 1);
+        const int iy = iy0 + line;
+        if (iy >= n) continue;
+        const int g = (iy - h) & (M - 1);
+        G[go + int64_t(g) * M + i] = buf[line * stride + i];
+    }
+}
+
+// Column pass over L adjacent columns.  FWD: load only the rows that hold
+// image modes (the rest are zero), transform with sign -1, store every row.
+// !FWD: load every row, transform with sign +1, store only the mode rows.
+template <class T, bool FWD>
+__global__ __launch_bounds__(kFftThreads) void k_fou_cols(C2<T> *__restrict__ G,
+                                                          const C2<T> *__restrict__ tw, int n,
+                                                          int M, int logM, int L, int logL,
+                                                          int64_t MM)
+{
+    extern __shared__ char smem[];
+    C2<T> *tw_l = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = tw_l + (M >> 1);
+    const int stride = M + 1;
+    const int64_t go = int64_t(blockIdx.y) * MM;
+    const int c0 = blockIdx.x * L;
+    load_tw(tw_l, tw, M);
+    for (int e = threadIdx.x; e < L * M; e += blockDim.x) {
+        const int line = e & (L - 1), i = e >> logL;
+        C2<T> v{T(0), T(0)};
+        if (!FWD || mode_of(i, n, M) >= 0) v = G[go + int64_t(i) * M + c0 + line];
+        buf[line * stride + brev(i, logM)] = v;
+    }
+    __syncthreads();
+    lds_fft(buf, L, M, logM, stride, tw_l, FWD ? -1 : 1);
+    for (int e = threadIdx.x; e < L * M; e += blockDim.x) {
+        const int line = e & (L - 1), i = e >> logL;
+        if (FWD || mode_of(i, n, M) >= 0) G[go + int64_t(i) * M + c0 + line] = buf[line * stride + i];
+    }
+}
+
+// Row pass of A F_D with the crop and the normal-operator epilogue:
+// h = Re(a1[iy] a1[ix] (F_D v)_m) for the image's modes, then
+// out = alpha h + lambda K^T K x + sigma x and one FP64 partial <x, out> per
+// workgroup (x may be nullptr when lambda = sigma = 0 and part = nullptr).
+template <class T>
+__global__ __launch_bounds__(kFftThreads) void k_fou_rows_inv(const C2<T> *__restrict__ G,
+                                                              const T *__restrict__ x,
+                                                              T *__restrict__ out,
+                                                              const T *__restrict__ a1,
+                                                              const C2<T> *__restrict__ tw,
+                                                              T alpha, T lambda, T sigma,
+                                                              double *__restrict__ part, int n,
+                                                              int M, int logM, int L, int64_t nn,
+                                                              int64_t MM)
+{
+    extern __shared__ char smem[];
+    __shared__ double red[kFftThreads];
+    C2<T> *tw_l = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = tw_l + (M >> 1);
+    const int stride = M + 1;
+    const int64_t xo = int64_t(blockIdx.y) * nn, go = int64_t(blockIdx.y) * MM;
+    const int iy0 = blockIdx.x * L, h = n >> 1;
+    load_tw(tw_l, tw, M);
+    for (int e = threadIdx.x; e < L * M; e += blockDim.x) {
+        const int line = e >> logM, i = e & (M - 1);
+        const int iy = iy0 + line;
+        C2<T> v{T(0), T(0)};
+        if (iy < n) v = G[go + int64_t((iy - h) & (M - 1)) * M + i];
+        buf[line * stride + brev(i, logM)] = v;
+    }
+    __syncthreads();
+    lds_fft(buf, L, M, logM, stride, tw_l, 1);
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < L * n; e += blockDim.x) {
+        const int line = e / n, ix = e - line * n;
+        const int iy = iy0 + line;
+        if (iy >= n) continue;
+        const int i = (ix - h) & (M - 1);
+        const T hv = a1[iy] * a1[ix] * buf[line * stride + i].x;
+        T o = alpha * hv;
+        if (x) {
+            const int64_t j = xo + int64_t(iy) * n + ix;
+            const T xj = x[j];
+            if (lambda != T(0)) {
+                T ktk = T(0);   // Neumann 5-point K^T K
+                if (ix > 0) ktk += xj - x[j - 1];
+                if (ix < n - 1) ktk += xj - x[j + 1];
+                if (iy > 0) ktk += xj - x[j - n];
+                if (iy < n - 1) ktk += xj - x[j + n];
+                o += lambda * ktk;
+            }
+            if (sigma != T(0)) o += sigma * xj;
+            acc += double(xj) * double(o);
+        }
+        out[xo + int64_t(iy) * n + ix] = o;
+    }
+    if (!part) return;
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+}
+
+// v = (B B^*) u on the grid: 16 x 16 grid points per workgroup (four 8 x 8
+// tiles, one wave each); the region plus a periodic halo of R = 2 m_sp - 1 is
+// staged in LDS, the coefficients stream from HBM (64 lanes x one offset per
+// load).  A tile without coefficients writes zeros.
+template <class TM, class T>
+__global__ __launch_bounds__(256) void k_fou_stencil(const C2<T> *__restrict__ u,
+                                                     C2<T> *__restrict__ v,
+                                                     const TM *__restrict__ coef,
+                                                     const int32_t *__restrict__ tile_map, int M,
+                                                     int R, int64_t MM)
+{
+    extern __shared__ char smem[];
+    C2<T> *reg = reinterpret_cast<C2<T> *>(smem);
+    const int side = 16 + 2 * R, D = 2 * R + 1;
+    const int rx0 = blockIdx.x * 16, ry0 = blockIdx.y * 16;
+    const int64_t go = int64_t(blockIdx.z) * MM;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tpr = M >> 3;
+    const int blk = tile_map[((ry0 >> 3) + (w >> 1)) * tpr + (rx0 >> 3) + (w & 1)];
+    const int any = __syncthreads_or(blk >= 0);
+    const int ly = ((w >> 1) << 3) + (lane >> 3), lx = ((w & 1) << 3) + (lane & 7);
+    C2<T> acc{T(0), T(0)};
+    if (any) {
+        for (int e = threadIdx.x; e < side * side; e += blockDim.x) {
+            const int ey = e / side, ex = e - ey * side;
+            const int gy = (ry0 + ey - R) & (M - 1), gx = (rx0 + ex - R) & (M - 1);
+            reg[e] = u[go + int64_t(gy) * M + gx];
+        }
+        __syncthreads();
+        if (blk >= 0) {
+            const TM *c = coef + int64_t(blk) * D * D * 64 + lane;
+            for (int dy = 0; dy < D; ++dy) {
+                const C2<T> *row = reg + (ly + dy) * side + lx;
+                const TM *cr = c + int64_t(dy) * D * 64;
+#pragma unroll 4
+                for (int dx = 0; dx < D; ++dx) {
+                    const T cc = T(cr[dx * 64]);
+                    const C2<T> uv = row[dx];
+                    acc.x += cc * uv.x;
+                    acc.y += cc * uv.y;
+                }
+            }
+        }
+    }
+    v[go + int64_t(ry0 + ly) * M + rx0 + lx] = acc;
+}
+
+// fhat_p = sum over p's window of G[s] g_p(s) (B^* F_D^* A mu with the
+// scales already in G): one thread per point.
+template <class TM, class T>
+__global__ __launch_bounds__(256) void k_fou_interp(const C2<T> *__restrict__ G,
+                                                    const int32_t *__restrict__ pbase,
+                                                    const double *__restrict__ w1d,
+                                                    C2<T> *__restrict__ fhat, int64_t P, int M,
+                                                    int m_sp, int64_t MM)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int W = 2 * m_sp;
+    const int64_t go = int64_t(blockIdx.y) * MM;
+    const int y0 = pbase[2 * p] - m_sp + 1, x0 = pbase[2 * p + 1] - m_sp + 1;
+    const double *wy = w1d + p * 2 * W, *wx = wy + W;
+    T ax = T(0), ay = T(0);
+    for (int ky = 0; ky < W; ++ky) {
+        const C2<T> *row = G + go + int64_t((y0 + ky) & (M - 1)) * M;
+        for (int kx = 0; kx < W; ++kx) {
+            const T g = T(TM(wy[ky] * wx[kx]));
+            const C2<T> val = row[(x0 + kx) & (M - 1)];
+            ax += g * val.x;
+            ay += g * val.y;
+        }
+    }
+    fhat[int64_t(blockIdx.y) * P + p] = C2<T>{ax, ay};
+}
+
+// G[s] = sum_p g_p(s) fhat_p (the spreading B, CSR over grid points).
+template <class TM, class T>
+__global__ __launch_bounds__(256) void k_fou_spread(const C2<T> *__restrict__ fhat,
+                                                    const int64_t *__restrict__ sp_ptr,
+                                                    const int32_t *__restrict__ sp_pt,
+                                                    const TM *__restrict__ sp_w,
+                                                    C2<T> *__restrict__ G, int64_t P, int64_t MM)
+{
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= MM) return;
+    const C2<T> *f = fhat + int64_t(blockIdx.y) * P;
+    T ax = T(0), ay = T(0);
+    for (int64_t k = sp_ptr[s]; k < sp_ptr[s + 1]; ++k) {
+        const T g = T(sp_w[k]);
+        const C2<T> val = f[sp_pt[k]];
+        ax += g * val.x;
+        ay += g * val.y;
+    }
+    G[int64_t(blockIdx.y) * MM + s] = C2<T>{ax, ay};
+}
+
+// B B^* coefficients of one stored tile and one chunk of 64 offsets:
+// C[s][d] = sum over points p whose window holds s of g_p(s) g_p(s + d),
+// accumulated in FP64 in a fixed order (cells by row, points by index) and
+// stored in the matrix value type.  A point p in cell b (per dimension) holds
+// grid points b - m_sp + 1 .. b + m_sp, so the points that reach the tile
+// [t0, t0 + 8) sit in cells t0 - m_sp .. t0 + m_sp + 6 (periodic); each cell
+// is visited in the unwrapped frame of the tile, where s + d is measured.
+template <class TM>
+__global__ __launch_bounds__(64) void k_fou_build(const int32_t *__restrict__ tiles,
+                                                  const int32_t *__restrict__ cell_ptr,
+                                                  const int32_t *__restrict__ cell_pts,
+                                                  const double *__restrict__ w1d,
+                                                  TM *__restrict__ coef, int M, int m_sp)
+{
+    __shared__ double wl[4 * kFouMaxMsp];
+    __shared__ int dyx[2][64];
+    const int W = 2 * m_sp, R = W - 1, D = 2 * R + 1, DD = D * D;
+    const int blk = blockIdx.x, d0 = blockIdx.y * 64;
+    const int tpr = M >> 3;
+    const int t = tiles[blk];
+    const int t0y = (t / tpr) << 3, t0x = (t % tpr) << 3;
+    const int lane = threadIdx.x;
+    const int sy = t0y + (lane >> 3), sx = t0x + (lane & 7);
+    const int nd = min(64, DD - d0);
+    if (lane < nd) {
+        dyx[0][lane] = (d0 + lane) / D - R;
+        dyx[1][lane] = (d0 + lane) % D - R;
+    }
+    double acc[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) acc[j] = 0.0;
+    for (int cyu = t0y - m_sp; cyu <= t0y + m_sp + 6; ++cyu) {
+        const int cy = cyu & (M - 1);
+        const int ky = sy - (cyu - m_sp + 1);
+        for (int cxu = t0x - m_sp; cxu <= t0x + m_sp + 6; ++cxu) {
+            const int c = cy * M + (cxu & (M - 1));
+            const int kx = sx - (cxu - m_sp + 1);
+            const int k1 = cell_ptr[c + 1];
+            for (int k = cell_ptr[c]; k < k1; ++k) {
+                const int64_t p = cell_pts[k];
+                __syncthreads();
+                if (lane < 2 * W) wl[lane] = w1d[p * 2 * W + lane];
+                __syncthreads();
+                if (ky < 0 || ky >= W || kx < 0 || kx >= W) continue;
+                const double ws = wl[ky] * wl[W + kx];
+#pragma unroll
+                for (int j = 0; j < 64; ++j) {
+                    if (j < nd) {
+                        const int ky2 = ky + dyx[0][j], kx2 = kx + dyx[1][j];
+                        if (ky2 >= 0 && ky2 < W && kx2 >= 0 && kx2 < W)
+                            acc[j] += ws * (wl[ky2] * wl[W + kx2]);
+                    }
+                }
+            }
+        }
+    }
+    TM *out = coef + int64_t(blk) * DD * 64 + int64_t(d0) * 64 + lane;
+#pragma unroll
+    for (int j = 0; j < 64; ++j)
+        if (j < nd) out[int64_t(j) * 64] = TM(acc[j]);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <class T>
+static int64_t fft_lds_bytes(int M, int L)
+{
+    return int64_t(sizeof(C2<T>)) * (int64_t(M / 2) + int64_t(L) * (M + 1));
+}
+
+template <class T>
+static int fft_lines(int M)
+{
+    int L = 16;
+    while (L > 1 && fft_lds_bytes<T>(M, L) > kFftLdsBudget) L >>= 1;
+    return L;
+}
+
+static int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+int64_t fourier_parts(const Fou &f) { return (f.n + f.L - 1) / f.L; }
+
+// two M x M complex grids and the point values, per image
+int64_t fourier_grid_bytes(const Fou &f, int batch)
+{
+    const int64_t g = int64_t(f.vsize) * 2 * int64_t(f.M) * f.M * batch;
+    const int64_t pv = int64_t(f.vsize) * 2 * f.P * batch;
+    return 2 * ((g + 255) & ~int64_t(255)) + ((pv + 255) & ~int64_t(255));
+}
+
+template <class T>
+static void split_grids(const Fou &f, void *grids, int batch, C2<T> **g0, C2<T> **g1, C2<T> **fh)
+{
+    Carver c(grids);
+    *g0 = c.take<C2<T>>(int64_t(f.M) * f.M * batch);
+    *g1 = c.take<C2<T>>(int64_t(f.M) * f.M * batch);
+    *fh = c.take<C2<T>>(f.P * batch);
+}
+
+// G = F_D^* A x (scaled, centred grid)
+template <class T>
+static int fwd_to_grid(const Fou &f, const T *x, C2<T> *G, int batch, hipStream_t s)
+{
+    const int64_t MM = int64_t(f.M) * f.M;
+    const size_t lds = size_t(fft_lds_bytes<T>(f.M, f.L));
+    k_fou_rows_fwd<T><<<dim3(unsigned((f.n + f.L - 1) / f.L), unsigned(batch)), kFftThreads, lds, s>>>(
+        x, G, static_cast<const T *>(f.a1), static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.L,
+        f.op->nn, MM);
+    SCT_TRY(check_launch("k_fou_rows_fwd"));
+    k_fou_cols<T, true><<<dim3(unsigned(f.M / f.L), unsigned(batch)), kFftThreads, lds, s>>>(
+        G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.L, ilog2(f.L), MM);
+    return check_launch("k_fou_cols<fwd>");
+}
+
+// out = alpha Re(A F_D G) (+ lambda K^T K x + sigma x, partials); G is
+// overwritten.
+template <class T>
+static int grid_to_image(const Fou &f, C2<T> *G, const T *x, T *out, double alpha, double lambda,
+                         double sigma, double *part, int batch, hipStream_t s)
+{
+    const int64_t MM = int64_t(f.M) * f.M;
+    const size_t lds = size_t(fft_lds_bytes<T>(f.M, f.L));
+    k_fou_cols<T, false><<<dim3(unsigned(f.M / f.L), unsigned(batch)), kFftThreads, lds, s>>>(
+        G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.L, ilog2(f.L), MM);
+    SCT_TRY(check_launch("k_fou_cols<inv>"));
+    k_fou_rows_inv<T><<<dim3(unsigned(fourier_parts(f)), unsigned(batch)), kFftThreads, lds, s>>>(
+        G, x, out, static_cast<const T *>(f.a1), static_cast<const C2<T> *>(f.tw), T(alpha),
+        T(lambda), T(sigma), part, f.n, f.M, f.logM, f.L, f.op->nn, MM);
+    return check_launch("k_fou_rows_inv");
+}
+
+template <class TM, class T>
+static int interp(const Fou &f, const C2<T> *G, C2<T> *fhat, int batch, hipStream_t s)
+{
+    k_fou_interp<TM, T><<<dim3(unsigned((f.P + 255) / 256), unsigned(batch)), 256, 0, s>>>(
+        G, f.pbase, f.w1d, fhat, f.P, f.M, f.m_sp, int64_t(f.M) * f.M);
+    return check_launch("k_fou_interp");
+}
+
+template <class TM, class T>
+static int spread(const Fou &f, const C2<T> *fhat, C2<T> *G, int batch, hipStream_t s)
+{
+    const int64_t MM = int64_t(f.M) * f.M;
+    k_fou_spread<TM, T><<<dim3(unsigned((MM + 255) / 256), unsigned(batch)), 256, 0, s>>>(
+        fhat, f.sp_ptr, f.sp_pt, static_cast<const TM *>(f.sp_w), G, f.P, MM);
+    return check_launch("k_fou_spread");
+}
+
+template <class TM, class T>
+static int stencil(const Fou &f, const C2<T> *u, C2<T> *v, int batch, hipStream_t s)
+{
+    const int R = f.D / 2;
+    const size_t lds = sizeof(C2<T>) * size_t(16 + 2 * R) * size_t(16 + 2 * R);
+    const unsigned g = unsigned(f.M / 16);
+    k_fou_stencil<TM, T><<<dim3(g, g, unsigned(batch)), 256, lds, s>>>(
+        u, v, static_cast<const TM *>(f.coef), f.tile_map, f.M, R, int64_t(f.M) * f.M);
+    return check_launch("k_fou_stencil");
+}
+
+template <class TM, class TV>
+int launch_fourier_normal(const Fou &f, int path, double alpha, double lambda, double sigma,
+                          const TV *x, TV *out, double *part, int batch, void *grids, hipStream_t s)
+{
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    C2<TV> *g0, *g1, *fh;
+    split_grids<TV>(f, grids, batch, &g0, &g1, &fh);
+    SCT_TRY(fwd_to_grid<TV>(f, x, g0, batch, s));
+    if (path == RADON_FOURIER_FUSED) {
+        SCT_TRY((stencil<TM, TV>(f, g0, g1, batch, s)));
+    } else {   // F^* to the points, then F back to the grid
+        SCT_TRY((interp<TM, TV>(f, g0, fh, batch, s)));
+        SCT_TRY((spread<TM, TV>(f, fh, g1, batch, s)));
+    }
+    return grid_to_image<TV>(f, g1, x, out, alpha, lambda, sigma, part, batch, s);
+}
+
+template <class TM, class TV>
+int launch_fourier_adj(const Fou &f, const TV *fhat, TV *x, double alpha, int batch, void *grids,
+                       hipStream_t s)
+{
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    C2<TV> *g0, *g1, *fh;
+    split_grids<TV>(f, grids, batch, &g0, &g1, &fh);
+    SCT_TRY((spread<TM, TV>(f, reinterpret_cast<const C2<TV> *>(fhat), g0, batch, s)));
+    return grid_to_image<TV>(f, g0, nullptr, x, alpha, 0.0, 0.0, nullptr, batch, s);
+}
+
+#define SCT_FOU_INST(TM, TV)                                                                       \
+    template int launch_fourier_normal<TM, TV>(const Fou &, int, double, double, double,           \
+                                               const TV *, TV *, double *, int, void *,            \
+                                               hipStream_t);                                       \
+    template int launch_fourier_adj<TM, TV>(const Fou &, const TV *, TV *, double, int, void *,    \
+                                            hipStream_t);
+SCT_FOU_INST(float, float)
+SCT_FOU_INST(double, double)
+SCT_FOU_INST(float, double)
+#undef SCT_FOU_INST
+
+template <class T>
+static int set_fft_lds(int64_t bytes)
+{
+    if (bytes <= 64 * 1024) return RADON_OK;
+    for (const void *k : {reinterpret_cast<const void *>(&k_fou_rows_fwd<T>),
+                          reinterpret_cast<const void *>(&k_fou_cols<T, true>),
+                          reinterpret_cast<const void *>(&k_fou_cols<T, false>),
+                          reinterpret_cast<const void *>(&k_fou_rows_inv<T>)})
+        SCT_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+    return RADON_OK;
+}
+
+// ---------------------------------------------------------------------------
+// construction
+// ---------------------------------------------------------------------------
+
+static void free_fou(Fou *f)
+{
+    if (!f) return;
+    for (void *p : f->owned) (void)hipFree(p);
+    delete f;
+}
+
+static int fou_alloc(Fou &f, void **p, int64_t bytes)
+{
+    *p = nullptr;
+    const hipError_t e = hipMalloc(p, size_t(bytes > 0 ? bytes : 256));
+    if (e != hipSuccess)
+        return set_error(RADON_EHIP, "hipMalloc of %lld bytes failed: %s", (long long)bytes,
+                         hipGetErrorString(e));
+    f.owned.push_back(*p);
+    f.device_bytes += bytes;
+    return RADON_OK;
+}
+
+template <class U>
+static int fou_upload(Fou &f, U **dst, const std::vector<U> &src)
+{
+    SCT_TRY(fou_alloc(f, reinterpret_cast<void **>(dst), int64_t(sizeof(U)) * int64_t(src.size())));
+    if (!src.empty())
+        SCT_HIP(hipMemcpy(*dst, src.data(), sizeof(U) * src.size(), hipMemcpyHostToDevice));
+    return RADON_OK;
+}
+
+// Points, windows and weights (host, FP64), the gridding CSR, the tile map;
+// then B B^* on the device.
+template <class TM, class TV>
+static int build_fou(Fou &f, hipStream_t st)
+{
+    const Op &op = *f.op;
+    const int M = f.M, W = 2 * f.m_sp;
+    const int Q = (op.n_bins - 1) / 2;
+    const int nq = 2 * Q + 1;
+    f.P = int64_t(op.n_meas) * nq;
+    const double h = 2.0 * M_PI / M;
+    std::vector<int32_t> pbase(size_t(2 * f.P));
+    std::vector<double> w1d(size_t(f.P) * size_t(2 * W));
+    for (int a = 0; a < op.n_meas; ++a) {
+        const double th = M_PI * op.meas[size_t(a)] / op.n_angles;
+        const double ct = std::cos(th), sn = std::sin(th);
+        for (int q = -Q; q <= Q; ++q) {
+            const int64_t p = int64_t(a) * nq + q + Q;
+            const double rho = 2.0 * M_PI * q / op.n_bins;
+            const double xi[2] = {sn * rho, ct * rho};   // (y, x)
+            for (int dim = 0; dim < 2; ++dim) {
+                const int64_t b = int64_t(std::floor(xi[dim] / h));
+                pbase[size_t(2 * p + dim)] = int32_t(b + M / 2);
+                for (int k = 0; k < W; ++k) {
+                    const double l = double(b - f.m_sp + 1 + k);
+                    const double dlt = xi[dim] - l * h;
+                    w1d[size_t(p * 2 * W + dim * W + k)] = std::exp(-(dlt * dlt) / (4.0 * f.tau));
+                }
+            }
+        }
+    }
+    // cells (base grid point) -> points, ascending
+    const int64_t MM = int64_t(M) * M;
+    std::vector<int32_t> cell_ptr(size_t(MM + 1), 0), cell_pts(size_t(f.P));
+    for (int64_t p = 0; p < f.P; ++p) ++cell_ptr[size_t(int64_t(pbase[size_t(2 * p)]) * M + pbase[size_t(2 * p + 1)] + 1)];
+    for (int64_t c = 0; c < MM; ++c) cell_ptr[size_t(c + 1)] += cell_ptr[size_t(c)];
+    {
+        std::vector<int32_t> fill(cell_ptr.begin(), cell_ptr.end() - 1);
+        for (int64_t p = 0; p < f.P; ++p)
+            cell_pts[size_t(fill[size_t(int64_t(pbase[size_t(2 * p)]) * M + pbase[size_t(2 * p + 1)])]++)] = int32_t(p);
+    }
+    // gridding B as CSR over grid points, points ascending within a row
+    f.sp_nnz = f.P * W * W;
+    std::vector<int64_t> sp_ptr(size_t(MM + 1), 0);
+    auto grid_of = [&](int64_t p, int ky, int kx) {
+        const int gy = (pbase[size_t(2 * p)] - f.m_sp + 1 + ky) & (M - 1);
+        const int gx = (pbase[size_t(2 * p + 1)] - f.m_sp + 1 + kx) & (M - 1);
+        return int64_t(gy) * M + gx;
+    };
+    for (int64_t p = 0; p < f.P; ++p)
+        for (int ky = 0; ky < W; ++ky)
+            for (int kx = 0; kx < W; ++kx) ++sp_ptr[size_t(grid_of(p, ky, kx) + 1)];
+    for (int64_t c = 0; c < MM; ++c) sp_ptr[size_t(c + 1)] += sp_ptr[size_t(c)];
+    std::vector<int32_t> sp_pt(size_t(f.sp_nnz));
+    std::vector<TM> sp_w(size_t(f.sp_nnz));
+    {
+        std::vector<int64_t> fill(sp_ptr.begin(), sp_ptr.end() - 1);
+        for (int64_t p = 0; p < f.P; ++p)
+            for (int ky = 0; ky < W; ++ky)
+                for (int kx = 0; kx < W; ++kx) {
+                    const int64_t k = fill[size_t(grid_of(p, ky, kx))]++;
+                    sp_pt[size_t(k)] = int32_t(p);
+                    sp_w[size_t(k)] = TM(w1d[size_t(p * 2 * W + ky)] * w1d[size_t(p * 2 * W + W + kx)]);
+                }
+    }
+    // 8 x 8 tiles that some window reaches
+    const int tpr = M / 8;
+    std::vector<int32_t> tile_map(size_t(tpr) * size_t(tpr), -1);
+    for (int64_t p = 0; p < f.P; ++p)
+        for (int ky = 0; ky < W; ++ky) {
+            const int ty = ((pbase[size_t(2 * p)] - f.m_sp + 1 + ky) & (M - 1)) >> 3;
+            for (int kx = 0; kx < W; ++kx) {
+                const int tx = ((pbase[size_t(2 * p + 1)] - f.m_sp + 1 + kx) & (M - 1)) >> 3;
+                tile_map[size_t(ty * tpr + tx)] = 0;
+            }
+        }
+    std::vector<int32_t> tiles;
+    for (int t = 0; t < tpr * tpr; ++t)
+        if (tile_map[size_t(t)] == 0) {
+            tile_map[size_t(t)] = int32_t(tiles.size());
+            tiles.push_back(t);
+        }
+    f.n_tiles = int64_t(tiles.size());
+    // scales and twiddles
+    std::vector<TV> a1(size_t(f.n));
+    for (int ix = 0; ix < f.n; ++ix) {
+        const int m = ix - f.n / 2;
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        a1[size_t(ix)] = TV(std::sqrt(M_PI / f.tau) * std::exp(double(m) * m * f.tau) * sg / M);
+    }
+    std::vector<C2<TV>> tw(size_t(M / 2));
+    for (int k = 0; k < M / 2; ++k)
+        tw[size_t(k)] = C2<TV>{TV(std::cos(2.0 * M_PI * k / M)), TV(-std::sin(2.0 * M_PI * k / M))};
+
+    int32_t *d_cell_ptr = nullptr, *d_cell_pts = nullptr, *d_tiles = nullptr;
+    TM *d_spw = nullptr;
+    TV *d_a1 = nullptr;
+    C2<TV> *d_tw = nullptr;
+    SCT_TRY(fou_upload(f, &f.pbase, pbase));
+    SCT_TRY(fou_upload(f, &f.w1d, w1d));
+    SCT_TRY(fou_upload(f, &f.sp_ptr, sp_ptr));
+    SCT_TRY(fou_upload(f, &f.sp_pt, sp_pt));
+    SCT_TRY(fou_upload(f, &d_spw, sp_w));
+    f.sp_w = d_spw;
+    SCT_TRY(fou_upload(f, &f.tile_map, tile_map));
+    SCT_TRY(fou_upload(f, &d_a1, a1));
+    f.a1 = d_a1;
+    SCT_TRY(fou_upload(f, &d_tw, tw));
+    f.tw = d_tw;
+    // build-only tables: freed at the end of the build
+    Fou tmp;
+    SCT_TRY(fou_upload(tmp, &d_cell_ptr, cell_ptr));
+    struct Guard {
+        Fou &t;
+        ~Guard()
+        {
+            for (void *p : t.owned) (void)hipFree(p);
+            t.owned.clear();
+        }
+    } guard{tmp};
+    SCT_TRY(fou_upload(tmp, &d_cell_pts, cell_pts));
+    SCT_TRY(fou_upload(tmp, &d_tiles, tiles));
+    const int64_t DD = int64_t(f.D) * f.D;
+    SCT_TRY(fou_alloc(f, &f.coef, int64_t(sizeof(TM)) * f.n_tiles * DD * 64));
+    if (f.n_tiles > 0) {
+        if (f.n_tiles > 0x7fffffff) return set_error(RADON_EOVERFLOW, "too many tiles");
+        const unsigned chunks = unsigned((DD + 63) / 64);
+        k_fou_build<TM><<<dim3(unsigned(f.n_tiles), chunks), 64, 0, st>>>(d_tiles, d_cell_ptr, d_cell_pts,
+                                                                          f.w1d, static_cast<TM *>(f.coef),
+                                                                          M, f.m_sp);
+        SCT_TRY(check_launch("k_fou_build"));
+    }
+    SCT_HIP(hipStreamSynchronize(st));
+    SCT_TRY(set_fft_lds<TV>(fft_lds_bytes<TV>(f.M, f.L)));
+    const int R = f.D / 2;
+    const int64_t slds = int64_t(sizeof(C2<TV>)) * (16 + 2 * R) * (16 + 2 * R);
+    if (slds > 64 * 1024)
+        SCT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fou_stencil<TM, TV>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(slds)));
+    return RADON_OK;
+}
+
+static const Fou *as_fou(const radon_fourier *p) { return reinterpret_cast<const Fou *>(p); }
+
+static int check_fou(const radon_fourier *p)
+{
+    if (!p) return set_error(RADON_EINVAL, "Fourier operator is NULL");
+    return RADON_OK;
+}
+
+}  // namespace sct
+
+using namespace sct;
+
+extern "C" int radon_fourier_create(const radon_op *p, int32_t m_sp, double tau, int32_t grid,
+                                    void *stream, radon_fourier **out)
+{
+    clear_error();
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    *out = nullptr;
+    SCT_TRY(check_op(p));
+    const Op &op = *as_op(p);
+    if (m_sp < 1 || m_sp > kFouMaxMsp)
+        return set_error(RADON_EINVAL, "m_sp must be in [1, %d] (got %d)", kFouMaxMsp, m_sp);
+    int M = grid;
+    if (M == 0) {
+        M = 16;
+        while (M < 2 * op.n) M *= 2;
+    }
+    if (M < 16 || (M & (M - 1)) || M < 2 * op.n)
+        return set_error(RADON_EINVAL, "grid must be a power of two >= max(16, 2n) (got %d, n = %d)",
+                         grid, op.n);
+    if (M > kFouMaxGrid)
+        return set_error(RADON_EUNSUPPORTED, "grid %d exceeds %d (n <= %d)", M, kFouMaxGrid,
+                         kFouMaxGrid / 2);
+    if (2 * m_sp > M) return set_error(RADON_EINVAL, "window 2 m_sp = %d exceeds the grid %d", 2 * m_sp, M);
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return set_error(RADON_EINVAL, "tau must be >= 0 and finite");
+    if (op.n_bins < 1 || op.n_meas < 1) return set_error(RADON_EINVAL, "no measured rays");
+    Fou *f = new (std::nothrow) Fou;
+    if (!f) return set_error(RADON_EINVAL, "out of host memory");
+    f->op = &op;
+    f->n = op.n;
+    f->M = M;
+    f->logM = ilog2(M);
+    f->m_sp = m_sp;
+    f->D = 4 * m_sp - 1;
+    f->tau = tau > 0.0 ? tau : 4.0 * m_sp / (double(M) * M);
+    f->dtype = op.dtype;
+    f->msize = op.msize;
+    f->vsize = op.vsize;
+    f->L = op.vsize == 4 ? fft_lines<float>(M) : fft_lines<double>(M);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int rc = dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return build_fou<TM, TV>(*f, st);
+    });
+    if (rc != RADON_OK) {
+        free_fou(f);
+        return rc;
+    }
+    *out = reinterpret_cast<radon_fourier *>(f);
+    return RADON_OK;
+}
+
+extern "C" void radon_fourier_destroy(radon_fourier *f) { free_fou(reinterpret_cast<Fou *>(f)); }
+
+extern "C" int radon_fourier_get_info(const radon_fourier *p, radon_fourier_info *out)
+{
+    clear_error();
+    SCT_TRY(check_fou(p));
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    const Fou &f = *as_fou(p);
+    out->n_points = f.P;
+    out->grid = f.M;
+    out->m_sp = f.m_sp;
+    out->tau = f.tau;
+    out->fused_tiles = f.n_tiles;
+    out->fused_bytes = f.n_tiles * int64_t(f.D) * f.D * 64 * f.msize;
+    out->spread_nnz = f.sp_nnz;
+    out->device_bytes = f.device_bytes;
+    return RADON_OK;
+}
+
+namespace sct {
+int64_t sb_ws_bytes(const Op &op, int batch);
+}
+
+static int64_t transform_ws(const Fou &f, int batch)
+{
+    Carver c(nullptr);
+    c.take<char>(fourier_grid_bytes(f, batch));
+    c.take<double>(fourier_parts(f) * batch);
+    return c.used;
+}
+
+extern "C" int64_t radon_fourier_workspace_bytes(const radon_fourier *p, int32_t which, int32_t batch)
+{
+    clear_error();
+    if (check_fou(p) != RADON_OK || check_batch(batch) != RADON_OK) return -1;
+    const Fou &f = *as_fou(p);
+    if (which == RADON_FWS_TRANSFORM) return transform_ws(f, batch);
+    if (which == RADON_FWS_SB) {
+        Carver c(nullptr);
+        c.take<char>(sb_ws_bytes(*f.op, batch));
+        c.take<char>(fourier_grid_bytes(f, batch));
+        return c.used;
+    }
+    set_error(RADON_EINVAL, "unknown workspace kind %d", which);
+    return -1;
+}
+
+extern "C" int fourier_fwd(const radon_fourier *p, const void *mu, void *fhat, int32_t batch, void *ws,
+                           int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_fou(p));
+    SCT_TRY(check_batch(batch));
+    if (!mu || !fhat) return set_error(RADON_EINVAL, "mu and fhat must be non-NULL");
+    const Fou &f = *as_fou(p);
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    SCT_TRY(check_ws(ws, ws_bytes, transform_ws(f, batch), "fourier_fwd"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dispatch(*f.op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        C2<TV> *g0, *g1, *fh;
+        split_grids<TV>(f, ws, batch, &g0, &g1, &fh);
+        SCT_TRY(fwd_to_grid<TV>(f, static_cast<const TV *>(mu), g0, batch, s));
+        return interp<TM, TV>(f, g0, static_cast<C2<TV> *>(fhat), batch, s);
+    });
+}
+
+extern "C" int fourier_adj(const radon_fourier *p, const void *fhat, void *x, double alpha,
+                           int32_t batch, void *ws, int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_fou(p));
+    SCT_TRY(check_batch(batch));
+    if (!fhat || !x) return set_error(RADON_EINVAL, "fhat and x must be non-NULL");
+    const Fou &f = *as_fou(p);
+    SCT_TRY(check_ws(ws, ws_bytes, transform_ws(f, batch), "fourier_adj"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dispatch(*f.op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        return launch_fourier_adj<TM, TV>(f, static_cast<const TV *>(fhat), static_cast<TV *>(x), alpha,
+                                          batch, ws, s);
+    });
+}
+
+extern "C" int fourier_normal(const radon_fourier *p, int32_t path, double alpha, double lambda,
+                              double sigma, const void *x, void *out, double *dot_out, int32_t batch,
+                              void *ws, int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_fou(p));
+    SCT_TRY(check_batch(batch));
+    if (path != RADON_FOURIER_FUSED && path != RADON_FOURIER_NUFFT)
+        return set_error(RADON_EINVAL, "unknown path %d", path);
+    if (!x || !out) return set_error(RADON_EINVAL, "x and out must be non-NULL");
+    if (x == out) return set_error(RADON_EINVAL, "out must not alias x");
+    const Fou &f = *as_fou(p);
+    SCT_TRY(check_ws(ws, ws_bytes, transform_ws(f, batch), "fourier_normal"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver c(ws);
+    void *grids = c.take<char>(fourier_grid_bytes(f, batch));
+    double *part = c.take<double>(fourier_parts(f) * batch);
+    return dispatch(*f.op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        SCT_TRY((launch_fourier_normal<TM, TV>(f, path, alpha, lambda, sigma, static_cast<const TV *>(x),
+                                               static_cast<TV *>(out), dot_out ? part : nullptr, batch,
+                                               grids, s)));
+        if (dot_out) SCT_TRY(launch_sum_partials(part, fourier_parts(f), dot_out, batch, s));
+        return RADON_OK;
+    });
+}

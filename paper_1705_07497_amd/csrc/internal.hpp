@@ -194,6 +194,40 @@ template <class TV>
 int launch_surrogate(const Sur &s, double alpha, double lambda, double sigma, const TV *x, TV *out,
                      double *part, int batch, hipStream_t st);
 int64_t surrogate_parts(const Sur &s);
+
+// Fourier-domain operator of Sections 2 and 3.1 (fourier.hip): Gaussian
+// gridding on an M x M frequency grid held in centred order (grid point s
+// stands for the frequency 2 pi (s - M/2) / M per dimension).
+struct Fou {
+    const Op *op = nullptr;          // borrowed: geometry, sizes and the solver buffers
+    int32_t n = 0, M = 0, logM = 0, m_sp = 0, D = 0;   // D = 4 m_sp - 1 stencil side
+    int32_t L = 0;                   // FFT lines per workgroup
+    int32_t dtype = 0, msize = 4, vsize = 4;
+    double tau = 0.0;
+    int64_t P = 0, n_tiles = 0, sp_nnz = 0, device_bytes = 0;
+    int32_t *pbase = nullptr;        // [P][2]: first window cell minus (1 - m_sp), i.e. floor(xi/h) + M/2, (y, x)
+    double *w1d = nullptr;           // [P][2][2 m_sp]: heat-kernel weights along y, then x
+    int64_t *sp_ptr = nullptr;       // gridding B as CSR over grid points: [M*M + 1]
+    int32_t *sp_pt = nullptr;        // point of each entry
+    void *sp_w = nullptr;            // its weight (matrix value type)
+    int32_t *tile_map = nullptr;     // [(M/8)^2]: coefficient block of an 8 x 8 tile, -1 if zero
+    void *coef = nullptr;            // B B^*: [n_tiles][D*D][64] (matrix value type)
+    void *tw = nullptr;              // [M/2] exp(-2 pi i k / M) (vector type pairs)
+    void *a1 = nullptr;              // [n] sqrt(pi/tau) exp(m^2 tau) (-1)^m / M (vector type)
+    std::vector<void *> owned;
+};
+// out = alpha H x + lambda K^T K x + sigma x (H by path: 0 fused, 1 NUFFT);
+// partial <x, out> per workgroup into part[batch][fourier_parts] when part !=
+// nullptr.  grids: fourier_grid_bytes(f, batch) bytes of scratch.
+template <class TM, class TV>
+int launch_fourier_normal(const Fou &f, int path, double alpha, double lambda, double sigma,
+                          const TV *x, TV *out, double *part, int batch, void *grids, hipStream_t s);
+// x = alpha Re(F fhat), fhat [batch][P] complex.
+template <class TM, class TV>
+int launch_fourier_adj(const Fou &f, const TV *fhat, TV *x, double alpha, int batch, void *grids,
+                       hipStream_t s);
+int64_t fourier_parts(const Fou &f);
+int64_t fourier_grid_bytes(const Fou &f, int batch);
 // sum part[batch][count] -> dst[batch] (fixed order)
 int launch_sum_partials(const double *part, int64_t count, double *dst, int batch, hipStream_t s);
 

@@ -442,6 +442,22 @@ struct SurA {
     }
 };
 
+// H of the Fourier-domain problem (eq:SBFFT) by gridding, fused (eq:fusedop)
+// or through the two transforms; grids is its scratch.
+template <class TM, class T>
+struct FouA {
+    const Fou &fou;
+    int path;
+    double alpha, lambda, sigma;
+    void *grids;
+    int64_t n_part() const { return fourier_parts(fou); }
+    bool needs_T() const { return false; }
+    int operator()(const T *p, const T *, T *q, T *, double *part, int batch, hipStream_t s) const
+    {
+        return launch_fourier_normal<TM, T>(fou, path, alpha, lambda, sigma, p, q, part, batch, grids, s);
+    }
+};
+
 // CG start: p = r (+ transposed copy), rho_0, state in ring slot 0.
 template <class T>
 static int cg_start(const Op &op, int batch, CgBufs<T> &w, T *u_for_prev, T *uprev,
@@ -537,30 +553,30 @@ static int cg_typed(const Op &op, double alpha, double lambda, double sigma, con
     return RADON_OK;
 }
 
-// Split Bregman with the inner CG on A (exact or surrogate); the data
-// right-hand side alpha (MR)^T f always uses the stored adjoint (eq:SB_solve,
-// eq:surr_SBupd).
-template <class TM, class T, class AOp>
-static int sb_run(const Op &op, const AOp &A, const radon_sb_params &P, const void *f_v,
+// Split Bregman with the inner CG on A (exact, surrogate or Fourier-domain);
+// data_rhs(r) writes the data term of the right-hand side: alpha (MR)^T f
+// through the stored adjoint for the sinogram problems (eq:SB_solve,
+// eq:surr_SBupd), alpha Re(F fhat) for the Fourier-domain one (eq:SBFFT).
+template <class T, class AOp, class RhsF>
+static int sb_run(const Op &op, const AOp &A, const RhsF &data_rhs, const radon_sb_params &P,
                   void *mu_v, int batch, void *ws, radon_sb_info *info, hipStream_t s)
 {
     Carver c(ws);
     SbBufs<T> w;
     carve_sb(op, batch, c, w);
     if (!A.needs_T()) w.cg.pT = nullptr;   // no transposed direction to keep
-    const T *f = static_cast<const T *>(f_v);
     T *u = static_cast<T *>(mu_v);
     const int64_t cnt = op.nn * batch;
     const int vbc = vec_blocks(cnt);
     const int vb = vec_blocks(op.nn);
-    const double alpha = P.alpha, lambda = P.lambda;
+    const double lambda = P.lambda;
     if (!(P.flags & RADON_SB_RESUME)) {
         for (T *z : {w.dx, w.dy, w.bx, w.by}) {
             k_fill<T><<<vbc, kVecThreads, 0, s>>>(z, T(0), cnt);
             SCT_TRY(check_launch("k_fill"));
         }
-        // r = alpha (MR)^T f - A u
-        SCT_TRY((launch_adj<TM, T>(op, f, nullptr, w.cg.r, alpha, 0.0, 0.0, nullptr, batch, s)));
+        // r = (data term) - A u
+        SCT_TRY(data_rhs(w.cg.r));
         if (P.flags & RADON_SB_WARM) {
             SCT_TRY((apply_A_into_q<T>(op, A, u, batch, w.cg, s)));
             k_sub<T><<<vbc, kVecThreads, 0, s>>>(w.cg.r, w.cg.q, w.cg.r, cnt);
@@ -596,11 +612,14 @@ template <class TM, class T>
 static int sb_typed(const Op &op, const Sur *sur, const radon_sb_params &P, const void *f_v,
                     void *mu_v, int batch, void *ws, radon_sb_info *info, hipStream_t s)
 {
+    // data term alpha (MR)^T f through the stored adjoint
+    auto rhs = [&](T *r) {
+        return launch_adj<TM, T>(op, static_cast<const T *>(f_v), nullptr, r, P.alpha, 0.0, 0.0,
+                                 nullptr, batch, s);
+    };
     if (sur)
-        return sb_run<TM, T>(op, SurA<T>{*sur, P.alpha, P.lambda, 0.0}, P, f_v, mu_v, batch, ws,
-                             info, s);
-    return sb_run<TM, T>(op, ExactA<TM, T>{op, P.alpha, P.lambda, 0.0}, P, f_v, mu_v, batch, ws,
-                         info, s);
+        return sb_run<T>(op, SurA<T>{*sur, P.alpha, P.lambda, 0.0}, rhs, P, mu_v, batch, ws, info, s);
+    return sb_run<T>(op, ExactA<TM, T>{op, P.alpha, P.lambda, 0.0}, rhs, P, mu_v, batch, ws, info, s);
 }
 
 
@@ -1186,6 +1205,46 @@ extern "C" int split_bregman_tv_surrogate(const radon_op *p, const radon_surroga
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
         return sb_typed<TM, TV>(op, &sur, *params, f, mu, batch, ws, info, s);
+    });
+}
+
+extern "C" int split_bregman_tv_fourier(const radon_fourier *fp, int32_t path,
+                                        const radon_sb_params *params, const void *fhat, void *mu,
+                                        int32_t batch, void *ws, int64_t ws_bytes,
+                                        radon_sb_info *info, void *stream)
+{
+    clear_error();
+    if (!fp) return set_error(RADON_EINVAL, "Fourier operator is NULL");
+    SCT_TRY(check_batch(batch));
+    if (!params) return set_error(RADON_EINVAL, "params is NULL");
+    if (!fhat || !mu) return set_error(RADON_EINVAL, "fhat and mu must be non-NULL");
+    if (path != RADON_FOURIER_FUSED && path != RADON_FOURIER_NUFFT)
+        return set_error(RADON_EINVAL, "unknown path %d", path);
+    if (!(params->lambda > 0.0)) return set_error(RADON_EINVAL, "lambda must be > 0");
+    if (params->n_outer < 0 || params->n_cg < 0)
+        return set_error(RADON_EINVAL, "n_outer and n_cg must be >= 0");
+    if (!(params->tol >= 0.0)) return set_error(RADON_EINVAL, "tol must be >= 0");
+    if (params->flags & ~(RADON_SB_WARM | RADON_SB_RESUME))
+        return set_error(RADON_EINVAL, "unknown flags 0x%x", params->flags);
+    const Fou &fou = *reinterpret_cast<const Fou *>(fp);
+    const Op &op = *fou.op;
+    if (fourier_parts(fou) > op.n_ag)
+        return set_error(RADON_EUNSUPPORTED, "more Fourier partials than the solver buffers hold");
+    Carver c(ws);
+    c.take<char>(sb_ws_bytes(op, batch));
+    void *grids = c.take<char>(fourier_grid_bytes(fou, batch));
+    SCT_TRY(check_ws(ws, ws_bytes, c.used, "split_bregman_tv_fourier"));
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const radon_sb_params &P = *params;
+    return dispatch(op, [&](auto *tm, auto *tv) {
+        SCT_TYPES(tm, tv);
+        auto rhs = [&](TV *r) {
+            return launch_fourier_adj<TM, TV>(fou, static_cast<const TV *>(fhat), r, P.alpha, batch,
+                                              grids, s);
+        };
+        return sb_run<TV>(op, FouA<TM, TV>{fou, path, P.alpha, P.lambda, 0.0, grids}, rhs, P, mu,
+                          batch, ws, info, s);
     });
 }
 

@@ -132,3 +132,25 @@ def test_group_and_graph_entry_points_validate_without_gpu():
     assert L.cg_unrolled(None, 1.0, 0.0, 1.0, None, None, 1, 10, 5, None, 0, None, 0, None) == -1
     assert L.cg_unrolled_vjp(None, 1.0, 0.0, 1.0, None, 0, None, None, 1, 10, 5, None, 0,
                              None) == -1
+
+
+def test_fourier_entry_points_validate_without_gpu():
+    L = sct.lib()
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define\s+(\w+)\s+(-?\d+)", text))
+    assert int(consts["RADON_FOURIER_FUSED"]) == sct.FOURIER_FUSED
+    assert int(consts["RADON_FOURIER_NUFFT"]) == sct.FOURIER_NUFFT
+    assert int(consts["RADON_FWS_SB"]) == sct.FWS_SB
+    assert ctypes.sizeof(sct.FourierInfo) == 56
+    h = ctypes.c_void_p()
+    assert L.radon_fourier_create(None, 6, 0.0, 0, None, ctypes.byref(h)) == -1
+    assert L.radon_fourier_create(None, 6, 0.0, 0, None, None) == -1
+    assert "out is NULL" in L.radon_last_error().decode()
+    assert L.radon_fourier_get_info(None, None) == -1
+    assert L.radon_fourier_workspace_bytes(None, 0, 1) == -1
+    assert L.fourier_fwd(None, None, None, 1, None, 0, None) == -1
+    assert L.fourier_adj(None, None, None, 1.0, 1, None, 0, None) == -1
+    assert L.fourier_normal(None, 0, 1.0, 0.0, 0.0, None, None, None, 1, None, 0, None) == -1
+    assert "Fourier operator is NULL" in L.radon_last_error().decode()
+    assert L.split_bregman_tv_fourier(None, 0, None, None, None, 1, None, 0, None, None) == -1
+    L.radon_fourier_destroy(None)

@@ -192,3 +192,17 @@ def test_split_bregman_on_the_fused_system_reaches_its_minimiser():
     u_pd = pdhg(Q, b, Kd, alpha)
     assert np.linalg.norm(u_sb - u_pd) <= 1e-6 * np.linalg.norm(u_pd)
     assert upd[-1] < 1e-8 * upd[0]
+
+
+def test_f32_tables_are_rounded_once():
+    n = 16
+    xi = F.points(12, 23)
+    g64 = F.Gridding(n, xi, 6)
+    g32 = F.Gridding(n, xi, 6, values="f32")
+    np.testing.assert_array_equal(g32.S_used.data, g64.S.data.astype(np.float32))
+    BB64, BB32 = g64.fused_matrix(), g32.fused_matrix()
+    scale = float(g64.M) ** 4
+    np.testing.assert_array_equal((BB32 * scale).data, (BB64 * scale).data.astype(np.float32))
+    mu = np.random.default_rng(1).standard_normal(n * n)
+    a, b = g64.fused_normal(mu, BB64), g32.fused_normal(mu, BB32)
+    assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(a)
