@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--profile-multi", action="store_true",
                     help="profiler mode for the uneven 32-instance batch: one captured-graph CG(10), "
                          "one eager group CG(10) and the 32 per-instance CG(10) solves, then exit")
+    ap.add_argument("--profile-fourier", action="store_true",
+                    help="profiler mode for the Fourier-domain operator: its build, 20 fused and 20 "
+                         "NUFFT normal applies and a plain 1 GiB device copy, then exit")
     return ap.parse_args()
 
 
@@ -218,6 +221,61 @@ def bench_pd(op, w, f, mu, torch, timed):
             "applies_per_s": round(n_outer * (n_cg + 1) / t, 1), "rel_err_to_phantom": round(err, 4)}
 
 
+def bench_fourier(sct, op, w, mu, torch, timed, profile=False):
+    """The Fourier-domain problem of eq:four_obj / eq:SBFFT on the same
+    geometry: gridded transforms with m_sp = 6 (about 6 digits), the normal
+    operator through the precomputed B B^* of eq:fusedop and through the two
+    transforms (the paper's fusing and NUFFT rows), and split Bregman 50 x 20
+    on the fused system with 1% complex noise on F^* mu."""
+    t0 = time.perf_counter()
+    fo = sct.RadonFourier(op, 6)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    x = torch.randn((1, op.nn), dtype=mu.dtype, device=mu.device)
+    out = torch.empty_like(x)
+    if profile:
+        for path in ("fused", "nufft"):
+            for _ in range(20):
+                fo.normal(x, w.alpha, w.lam, path=path, out=out)
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=mu.device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)   # counter calibration
+        torch.cuda.synchronize()
+        return None
+    reps = 50
+    res = {"m_sp": fo.m_sp, "grid": fo.grid, "points": fo.P, "build_s": round(build_s, 3),
+           "fused_tiles": fo.info["fused_tiles"], "fused_bytes": fo.info["fused_bytes"],
+           "spread_nnz": fo.info["spread_nnz"]}
+    for path in ("fused", "nufft"):
+        fo.normal(x, w.alpha, w.lam, path=path, out=out)
+        t = timed(lambda: fo.normal(x, w.alpha, w.lam, path=path, out=out), reps) / reps
+        res[f"{path}_normal_us"] = round(t * 1e6, 1)
+    fh = fo.fwd(mu)
+    g = torch.Generator(device=mu.device).manual_seed(0)
+    noise = torch.randn(fh.shape, dtype=fh.dtype, device=fh.device, generator=g)
+    fh = (fh + 0.01 * torch.sqrt(torch.mean(fh ** 2)) * noise).contiguous()
+    for path in ("fused", "nufft"):
+        fo.sb(fh, w.alpha, w.lam, w.n_outer, w.n_cg, path=path)
+        t_sb = timed(lambda: fo.sb(fh, w.alpha, w.lam, w.n_outer, w.n_cg, path=path), 3) / 3
+        u, _ = fo.sb(fh, w.alpha, w.lam, w.n_outer, w.n_cg, path=path)
+        err = float(torch.linalg.vector_norm(u - mu) / torch.linalg.vector_norm(mu))
+        res.update({f"sb_{path}_ms_per_recon": round(t_sb * 1e3, 2),
+                    f"sb_{path}_applies_per_s": round(w.n_outer * w.n_cg / t_sb, 1),
+                    f"sb_{path}_rel_err_to_phantom": round(err, 4)})
+    # algorithmic bytes of one fused apply: the stored coefficients once, the
+    # image in and out, and the grid passes (two M x M complex grids written
+    # and read by the transforms and the stencil)
+    grid_bytes = 16 * fo.grid * fo.grid
+    fused_alg = fo.info["fused_bytes"] + 2 * 8 * op.nn + 6 * grid_bytes
+    res["fused_normal_gbs"] = round(fused_alg / (res["fused_normal_us"] * 1e-6) / 1e9, 1)
+    print(f"# Fourier (m_sp 6, grid {fo.grid}, {fo.P} points): build {build_s:.2f} s, "
+          f"B B^* {fo.info['fused_bytes'] / 1e9:.2f} GB; normal fused {res['fused_normal_us']:.0f} us, "
+          f"NUFFT {res['nufft_normal_us']:.0f} us; split Bregman fused {res['sb_fused_ms_per_recon']:.1f} ms, "
+          f"NUFFT {res['sb_nufft_ms_per_recon']:.1f} ms, error to phantom "
+          f"{res['sb_fused_rel_err_to_phantom']:.4f}", file=sys.stderr, flush=True)
+    return res
+
+
 def bench_large(sct, W, torch, dev, vdt, t):
     """The large under-resolved workload: 2048 x 2048, 90 angles, 2897 bins
     (4.8e8 nonzeros), split Bregman 30 outer x 10 CG on a random-ellipse
@@ -324,6 +382,11 @@ def main():
     out = torch.empty_like(x)
     ysb = torch.empty((1, op.rows), dtype=vdt, device=dev)
     xT = x.reshape(w.n, w.n).t().contiguous().reshape(1, -1)
+    if args.profile_fourier:
+        bench_fourier(sct, op, w, mu, torch, timed, profile=True)
+        print("# profile sequence done (Fourier normal operator, fused and NUFFT)", file=sys.stderr,
+              flush=True)
+        return
     if args.profile_multi:
         bench_mixed_batch(sct, W, torch, dev, vdt, lambda fn, reps: event_time(torch, fn, 1))
         print("# profile sequence done (mixed batch)", file=sys.stderr, flush=True)
@@ -405,6 +468,7 @@ def main():
 
     result["surrogate"] = bench_surrogate(sct, op, w, f, mu, u, torch, timed, stream)
     result["primal_dual"] = bench_pd(op, w, f, mu, torch, timed)
+    result["fourier"] = bench_fourier(sct, op, w, mu, torch, timed)
 
     if not args.no_batched:
         result["batched"] = bench_batched(sct, W, torch, dev, vdt)

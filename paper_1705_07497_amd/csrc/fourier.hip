@@ -41,6 +41,17 @@ struct alignas(2 * sizeof(T)) C2 {
     T x, y;
 };
 
+// four consecutive stencil coefficients of one grid point: one 16-byte (FP32)
+// or two 16-byte (FP64) loads per lane
+template <class TM> struct QuadOf;
+template <> struct QuadOf<float> { using type = float4; };
+template <> struct QuadOf<double> { using type = double4; };
+template <class TM> using Quad = typename QuadOf<TM>::type;
+
+// padded stencil width: offsets dx in [0, Dp) with Dp = D rounded up to 4, the
+// padding coefficients zero
+__host__ __device__ inline int pad4(int d) { return (d + 3) & ~3; }
+
 constexpr int kFouMaxMsp = 12;
 constexpr int kFouMaxGrid = 4096;
 constexpr int kFftThreads = 256;
@@ -218,19 +229,21 @@ __global__ __launch_bounds__(kFftThreads) void k_fou_rows_inv(const C2<T> *__res
 }
 
 // v = (B B^*) u on the grid: 16 x 16 grid points per workgroup (four 8 x 8
-// tiles, one wave each); the region plus a periodic halo of R = 2 m_sp - 1 is
-// staged in LDS, the coefficients stream from HBM (64 lanes x one offset per
+// tiles, one wave each); the region plus a periodic halo of R = 2 m_sp - 1
+// (one more column for the padded offsets) is staged in LDS, the
+// coefficients stream from HBM as quads of offsets (64 lanes x 16 bytes per
 // load).  A tile without coefficients writes zeros.
 template <class TM, class T>
 __global__ __launch_bounds__(256) void k_fou_stencil(const C2<T> *__restrict__ u,
                                                      C2<T> *__restrict__ v,
-                                                     const TM *__restrict__ coef,
+                                                     const Quad<TM> *__restrict__ coef,
                                                      const int32_t *__restrict__ tile_map, int M,
                                                      int R, int64_t MM)
 {
     extern __shared__ char smem[];
     C2<T> *reg = reinterpret_cast<C2<T> *>(smem);
-    const int side = 16 + 2 * R, D = 2 * R + 1;
+    const int D = 2 * R + 1, Dp = pad4(D), nqx = Dp >> 2;
+    const int sh = 16 + 2 * R, sw = 15 + Dp;
     const int rx0 = blockIdx.x * 16, ry0 = blockIdx.y * 16;
     const int64_t go = int64_t(blockIdx.z) * MM;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -240,23 +253,24 @@ __global__ __launch_bounds__(256) void k_fou_stencil(const C2<T> *__restrict__ u
     const int ly = ((w >> 1) << 3) + (lane >> 3), lx = ((w & 1) << 3) + (lane & 7);
     C2<T> acc{T(0), T(0)};
     if (any) {
-        for (int e = threadIdx.x; e < side * side; e += blockDim.x) {
-            const int ey = e / side, ex = e - ey * side;
+        for (int e = threadIdx.x; e < sh * sw; e += blockDim.x) {
+            const int ey = e / sw, ex = e - ey * sw;
             const int gy = (ry0 + ey - R) & (M - 1), gx = (rx0 + ex - R) & (M - 1);
             reg[e] = u[go + int64_t(gy) * M + gx];
         }
         __syncthreads();
         if (blk >= 0) {
-            const TM *c = coef + int64_t(blk) * D * D * 64 + lane;
+            const Quad<TM> *c = coef + int64_t(blk) * D * nqx * 64 + lane;
             for (int dy = 0; dy < D; ++dy) {
-                const C2<T> *row = reg + (ly + dy) * side + lx;
-                const TM *cr = c + int64_t(dy) * D * 64;
-#pragma unroll 4
-                for (int dx = 0; dx < D; ++dx) {
-                    const T cc = T(cr[dx * 64]);
-                    const C2<T> uv = row[dx];
-                    acc.x += cc * uv.x;
-                    acc.y += cc * uv.y;
+                const C2<T> *row = reg + (ly + dy) * sw + lx;
+                const Quad<TM> *cr = c + int64_t(dy) * nqx * 64;
+#pragma unroll 2
+                for (int qx = 0; qx < nqx; ++qx) {
+                    const Quad<TM> q = cr[qx * 64];
+                    const C2<T> u0 = row[4 * qx], u1 = row[4 * qx + 1], u2 = row[4 * qx + 2],
+                                u3 = row[4 * qx + 3];
+                    acc.x += T(q.x) * u0.x + T(q.y) * u1.x + T(q.z) * u2.x + T(q.w) * u3.x;
+                    acc.y += T(q.x) * u0.y + T(q.y) * u1.y + T(q.z) * u2.y + T(q.w) * u3.y;
                 }
             }
         }
@@ -264,8 +278,16 @@ __global__ __launch_bounds__(256) void k_fou_stencil(const C2<T> *__restrict__ u
     v[go + int64_t(ry0 + ly) * M + rx0 + lx] = acc;
 }
 
+// Sum over the 16 lanes of a group (xor tree: a fixed order).
+template <class T>
+__device__ inline T group16_sum(T v)
+{
+    for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
+    return v;
+}
+
 // fhat_p = sum over p's window of G[s] g_p(s) (B^* F_D^* A mu with the
-// scales already in G): one thread per point.
+// scales already in G): 16 lanes per point, lane j taking taps j, j + 16, ...
 template <class TM, class T>
 __global__ __launch_bounds__(256) void k_fou_interp(const C2<T> *__restrict__ G,
                                                     const int32_t *__restrict__ pbase,
@@ -273,26 +295,29 @@ __global__ __launch_bounds__(256) void k_fou_interp(const C2<T> *__restrict__ G,
                                                     C2<T> *__restrict__ fhat, int64_t P, int M,
                                                     int m_sp, int64_t MM)
 {
-    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    const int64_t p = int64_t(blockIdx.x) * 16 + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
     const int W = 2 * m_sp;
     const int64_t go = int64_t(blockIdx.y) * MM;
-    const int y0 = pbase[2 * p] - m_sp + 1, x0 = pbase[2 * p + 1] - m_sp + 1;
-    const double *wy = w1d + p * 2 * W, *wx = wy + W;
     T ax = T(0), ay = T(0);
-    for (int ky = 0; ky < W; ++ky) {
-        const C2<T> *row = G + go + int64_t((y0 + ky) & (M - 1)) * M;
-        for (int kx = 0; kx < W; ++kx) {
+    if (p < P) {
+        const int y0 = pbase[2 * p] - m_sp + 1, x0 = pbase[2 * p + 1] - m_sp + 1;
+        const double *wy = w1d + p * 2 * W, *wx = wy + W;
+        for (int t = j; t < W * W; t += 16) {
+            const int ky = t / W, kx = t - ky * W;
             const T g = T(TM(wy[ky] * wx[kx]));
-            const C2<T> val = row[(x0 + kx) & (M - 1)];
+            const C2<T> val = G[go + int64_t((y0 + ky) & (M - 1)) * M + ((x0 + kx) & (M - 1))];
             ax += g * val.x;
             ay += g * val.y;
         }
     }
-    fhat[int64_t(blockIdx.y) * P + p] = C2<T>{ax, ay};
+    ax = group16_sum(ax);
+    ay = group16_sum(ay);
+    if (p < P && j == 0) fhat[int64_t(blockIdx.y) * P + p] = C2<T>{ax, ay};
 }
 
-// G[s] = sum_p g_p(s) fhat_p (the spreading B, CSR over grid points).
+// G[s] = sum_p g_p(s) fhat_p (the spreading B, CSR over grid points): 16
+// lanes per grid point (rows near the origin hold over a thousand entries).
 template <class TM, class T>
 __global__ __launch_bounds__(256) void k_fou_spread(const C2<T> *__restrict__ fhat,
                                                     const int64_t *__restrict__ sp_ptr,
@@ -300,46 +325,53 @@ __global__ __launch_bounds__(256) void k_fou_spread(const C2<T> *__restrict__ fh
                                                     const TM *__restrict__ sp_w,
                                                     C2<T> *__restrict__ G, int64_t P, int64_t MM)
 {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= MM) return;
+    const int64_t s = int64_t(blockIdx.x) * 16 + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
     const C2<T> *f = fhat + int64_t(blockIdx.y) * P;
     T ax = T(0), ay = T(0);
-    for (int64_t k = sp_ptr[s]; k < sp_ptr[s + 1]; ++k) {
-        const T g = T(sp_w[k]);
-        const C2<T> val = f[sp_pt[k]];
-        ax += g * val.x;
-        ay += g * val.y;
+    if (s < MM) {
+        for (int64_t k = sp_ptr[s] + j; k < sp_ptr[s + 1]; k += 16) {
+            const T g = T(sp_w[k]);
+            const C2<T> val = f[sp_pt[k]];
+            ax += g * val.x;
+            ay += g * val.y;
+        }
     }
-    G[int64_t(blockIdx.y) * MM + s] = C2<T>{ax, ay};
+    ax = group16_sum(ax);
+    ay = group16_sum(ay);
+    if (s < MM && j == 0) G[int64_t(blockIdx.y) * MM + s] = C2<T>{ax, ay};
 }
 
-// B B^* coefficients of one stored tile and one chunk of 64 offsets:
-// C[s][d] = sum over points p whose window holds s of g_p(s) g_p(s + d),
-// accumulated in FP64 in a fixed order (cells by row, points by index) and
-// stored in the matrix value type.  A point p in cell b (per dimension) holds
-// grid points b - m_sp + 1 .. b + m_sp, so the points that reach the tile
-// [t0, t0 + 8) sit in cells t0 - m_sp .. t0 + m_sp + 6 (periodic); each cell
-// is visited in the unwrapped frame of the tile, where s + d is measured.
+// B B^* coefficients of one stored tile and one chunk of 64 padded offsets
+// (d' = dy Dp + dx): C[s][d] = sum over points p whose window holds s of
+// g_p(s) g_p(s + d), accumulated in FP64 in a fixed order (cells by row,
+// points by index) and stored in the matrix value type, in quads of four
+// consecutive offsets per grid point.  A point p in cell b (per dimension)
+// holds grid points b - m_sp + 1 .. b + m_sp, so the points that reach the
+// tile [t0, t0 + 8) sit in cells t0 - m_sp .. t0 + m_sp + 6 (periodic); each
+// cell is visited in the unwrapped frame of the tile, where s + d is
+// measured.
 template <class TM>
 __global__ __launch_bounds__(64) void k_fou_build(const int32_t *__restrict__ tiles,
                                                   const int32_t *__restrict__ cell_ptr,
                                                   const int32_t *__restrict__ cell_pts,
                                                   const double *__restrict__ w1d,
-                                                  TM *__restrict__ coef, int M, int m_sp)
+                                                  Quad<TM> *__restrict__ coef, int M, int m_sp)
 {
     __shared__ double wl[4 * kFouMaxMsp];
     __shared__ int dyx[2][64];
-    const int W = 2 * m_sp, R = W - 1, D = 2 * R + 1, DD = D * D;
+    const int W = 2 * m_sp, R = W - 1, D = 2 * R + 1, Dp = pad4(D), DDp = D * Dp;
     const int blk = blockIdx.x, d0 = blockIdx.y * 64;
     const int tpr = M >> 3;
     const int t = tiles[blk];
     const int t0y = (t / tpr) << 3, t0x = (t % tpr) << 3;
     const int lane = threadIdx.x;
     const int sy = t0y + (lane >> 3), sx = t0x + (lane & 7);
-    const int nd = min(64, DD - d0);
+    const int nd = min(64, DDp - d0);   // a multiple of 4
     if (lane < nd) {
-        dyx[0][lane] = (d0 + lane) / D - R;
-        dyx[1][lane] = (d0 + lane) % D - R;
+        const int d = d0 + lane, dx = d % Dp;
+        dyx[0][lane] = d / Dp - R;
+        dyx[1][lane] = dx < D ? dx - R : 4 * kFouMaxMsp;   // padding: never inside a window
     }
     double acc[64];
 #pragma unroll
@@ -369,10 +401,17 @@ __global__ __launch_bounds__(64) void k_fou_build(const int32_t *__restrict__ ti
             }
         }
     }
-    TM *out = coef + int64_t(blk) * DD * 64 + int64_t(d0) * 64 + lane;
+    Quad<TM> *out = coef + (int64_t(blk) * (DDp >> 2) + (d0 >> 2)) * 64 + lane;
 #pragma unroll
-    for (int j = 0; j < 64; ++j)
-        if (j < nd) out[int64_t(j) * 64] = TM(acc[j]);
+    for (int jq = 0; jq < 16; ++jq)
+        if (4 * jq < nd) {
+            Quad<TM> q;
+            q.x = TM(acc[4 * jq]);
+            q.y = TM(acc[4 * jq + 1]);
+            q.z = TM(acc[4 * jq + 2]);
+            q.w = TM(acc[4 * jq + 3]);
+            out[int64_t(jq) * 64] = q;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -400,7 +439,7 @@ static int ilog2(int v)
     return l;
 }
 
-int64_t fourier_parts(const Fou &f) { return (f.n + f.L - 1) / f.L; }
+int64_t fourier_parts(const Fou &f) { return (f.n + f.Lr - 1) / f.Lr; }
 
 // two M x M complex grids and the point values, per image
 int64_t fourier_grid_bytes(const Fou &f, int batch)
@@ -424,13 +463,13 @@ template <class T>
 static int fwd_to_grid(const Fou &f, const T *x, C2<T> *G, int batch, hipStream_t s)
 {
     const int64_t MM = int64_t(f.M) * f.M;
-    const size_t lds = size_t(fft_lds_bytes<T>(f.M, f.L));
-    k_fou_rows_fwd<T><<<dim3(unsigned((f.n + f.L - 1) / f.L), unsigned(batch)), kFftThreads, lds, s>>>(
-        x, G, static_cast<const T *>(f.a1), static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.L,
+    const size_t lr = size_t(fft_lds_bytes<T>(f.M, f.Lr)), lc = size_t(fft_lds_bytes<T>(f.M, f.Lc));
+    k_fou_rows_fwd<T><<<dim3(unsigned((f.n + f.Lr - 1) / f.Lr), unsigned(batch)), kFftThreads, lr, s>>>(
+        x, G, static_cast<const T *>(f.a1), static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.Lr,
         f.op->nn, MM);
     SCT_TRY(check_launch("k_fou_rows_fwd"));
-    k_fou_cols<T, true><<<dim3(unsigned(f.M / f.L), unsigned(batch)), kFftThreads, lds, s>>>(
-        G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.L, ilog2(f.L), MM);
+    k_fou_cols<T, true><<<dim3(unsigned(f.M / f.Lc), unsigned(batch)), kFftThreads, lc, s>>>(
+        G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.Lc, ilog2(f.Lc), MM);
     return check_launch("k_fou_cols<fwd>");
 }
 
@@ -441,20 +480,20 @@ static int grid_to_image(const Fou &f, C2<T> *G, const T *x, T *out, double alph
                          double sigma, double *part, int batch, hipStream_t s)
 {
     const int64_t MM = int64_t(f.M) * f.M;
-    const size_t lds = size_t(fft_lds_bytes<T>(f.M, f.L));
-    k_fou_cols<T, false><<<dim3(unsigned(f.M / f.L), unsigned(batch)), kFftThreads, lds, s>>>(
-        G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.L, ilog2(f.L), MM);
+    const size_t lr = size_t(fft_lds_bytes<T>(f.M, f.Lr)), lc = size_t(fft_lds_bytes<T>(f.M, f.Lc));
+    k_fou_cols<T, false><<<dim3(unsigned(f.M / f.Lc), unsigned(batch)), kFftThreads, lc, s>>>(
+        G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.Lc, ilog2(f.Lc), MM);
     SCT_TRY(check_launch("k_fou_cols<inv>"));
-    k_fou_rows_inv<T><<<dim3(unsigned(fourier_parts(f)), unsigned(batch)), kFftThreads, lds, s>>>(
+    k_fou_rows_inv<T><<<dim3(unsigned(fourier_parts(f)), unsigned(batch)), kFftThreads, lr, s>>>(
         G, x, out, static_cast<const T *>(f.a1), static_cast<const C2<T> *>(f.tw), T(alpha),
-        T(lambda), T(sigma), part, f.n, f.M, f.logM, f.L, f.op->nn, MM);
+        T(lambda), T(sigma), part, f.n, f.M, f.logM, f.Lr, f.op->nn, MM);
     return check_launch("k_fou_rows_inv");
 }
 
 template <class TM, class T>
 static int interp(const Fou &f, const C2<T> *G, C2<T> *fhat, int batch, hipStream_t s)
 {
-    k_fou_interp<TM, T><<<dim3(unsigned((f.P + 255) / 256), unsigned(batch)), 256, 0, s>>>(
+    k_fou_interp<TM, T><<<dim3(unsigned((f.P + 15) / 16), unsigned(batch)), 256, 0, s>>>(
         G, f.pbase, f.w1d, fhat, f.P, f.M, f.m_sp, int64_t(f.M) * f.M);
     return check_launch("k_fou_interp");
 }
@@ -463,7 +502,7 @@ template <class TM, class T>
 static int spread(const Fou &f, const C2<T> *fhat, C2<T> *G, int batch, hipStream_t s)
 {
     const int64_t MM = int64_t(f.M) * f.M;
-    k_fou_spread<TM, T><<<dim3(unsigned((MM + 255) / 256), unsigned(batch)), 256, 0, s>>>(
+    k_fou_spread<TM, T><<<dim3(unsigned((MM + 15) / 16), unsigned(batch)), 256, 0, s>>>(
         fhat, f.sp_ptr, f.sp_pt, static_cast<const TM *>(f.sp_w), G, f.P, MM);
     return check_launch("k_fou_spread");
 }
@@ -472,10 +511,10 @@ template <class TM, class T>
 static int stencil(const Fou &f, const C2<T> *u, C2<T> *v, int batch, hipStream_t s)
 {
     const int R = f.D / 2;
-    const size_t lds = sizeof(C2<T>) * size_t(16 + 2 * R) * size_t(16 + 2 * R);
+    const size_t lds = sizeof(C2<T>) * size_t(16 + 2 * R) * size_t(15 + pad4(f.D));
     const unsigned g = unsigned(f.M / 16);
     k_fou_stencil<TM, T><<<dim3(g, g, unsigned(batch)), 256, lds, s>>>(
-        u, v, static_cast<const TM *>(f.coef), f.tile_map, f.M, R, int64_t(f.M) * f.M);
+        u, v, static_cast<const Quad<TM> *>(f.coef), f.tile_map, f.M, R, int64_t(f.M) * f.M);
     return check_launch("k_fou_stencil");
 }
 
@@ -684,20 +723,19 @@ static int build_fou(Fou &f, hipStream_t st)
     } guard{tmp};
     SCT_TRY(fou_upload(tmp, &d_cell_pts, cell_pts));
     SCT_TRY(fou_upload(tmp, &d_tiles, tiles));
-    const int64_t DD = int64_t(f.D) * f.D;
-    SCT_TRY(fou_alloc(f, &f.coef, int64_t(sizeof(TM)) * f.n_tiles * DD * 64));
+    const int64_t DDp = int64_t(f.D) * pad4(f.D);
+    SCT_TRY(fou_alloc(f, &f.coef, int64_t(sizeof(TM)) * f.n_tiles * DDp * 64));
     if (f.n_tiles > 0) {
         if (f.n_tiles > 0x7fffffff) return set_error(RADON_EOVERFLOW, "too many tiles");
-        const unsigned chunks = unsigned((DD + 63) / 64);
-        k_fou_build<TM><<<dim3(unsigned(f.n_tiles), chunks), 64, 0, st>>>(d_tiles, d_cell_ptr, d_cell_pts,
-                                                                          f.w1d, static_cast<TM *>(f.coef),
-                                                                          M, f.m_sp);
+        const unsigned chunks = unsigned((DDp + 63) / 64);
+        k_fou_build<TM><<<dim3(unsigned(f.n_tiles), chunks), 64, 0, st>>>(
+            d_tiles, d_cell_ptr, d_cell_pts, f.w1d, static_cast<Quad<TM> *>(f.coef), M, f.m_sp);
         SCT_TRY(check_launch("k_fou_build"));
     }
     SCT_HIP(hipStreamSynchronize(st));
-    SCT_TRY(set_fft_lds<TV>(fft_lds_bytes<TV>(f.M, f.L)));
+    SCT_TRY(set_fft_lds<TV>(fft_lds_bytes<TV>(f.M, std::max(f.Lr, f.Lc))));
     const int R = f.D / 2;
-    const int64_t slds = int64_t(sizeof(C2<TV>)) * (16 + 2 * R) * (16 + 2 * R);
+    const int64_t slds = int64_t(sizeof(C2<TV>)) * (16 + 2 * R) * (15 + pad4(f.D));
     if (slds > 64 * 1024)
         SCT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fou_stencil<TM, TV>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(slds)));
@@ -752,7 +790,18 @@ extern "C" int radon_fourier_create(const radon_op *p, int32_t m_sp, double tau,
     f->dtype = op.dtype;
     f->msize = op.msize;
     f->vsize = op.vsize;
-    f->L = op.vsize == 4 ? fft_lines<float>(M) : fft_lines<double>(M);
+    // lines per FFT workgroup: as many as the LDS budget allows, but few enough
+    // that a pass has at least 512 workgroups when the image allows it
+    {
+        const int Lmax = op.vsize == 4 ? fft_lines<float>(M) : fft_lines<double>(M);
+        auto lines_for = [&](int count) {
+            int L = 1;
+            while (2 * L <= Lmax && count / (2 * L) >= 512) L *= 2;
+            return L;
+        };
+        f->Lr = lines_for(op.n);
+        f->Lc = lines_for(M);
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int rc = dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
@@ -779,7 +828,7 @@ extern "C" int radon_fourier_get_info(const radon_fourier *p, radon_fourier_info
     out->m_sp = f.m_sp;
     out->tau = f.tau;
     out->fused_tiles = f.n_tiles;
-    out->fused_bytes = f.n_tiles * int64_t(f.D) * f.D * 64 * f.msize;
+    out->fused_bytes = f.n_tiles * int64_t(f.D) * pad4(f.D) * 64 * f.msize;
     out->spread_nnz = f.sp_nnz;
     out->device_bytes = f.device_bytes;
     return RADON_OK;

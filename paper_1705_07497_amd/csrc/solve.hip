@@ -352,7 +352,9 @@ static void carve_cg(const Op &op, int batch, Carver &c, CgBufs<T> &w)
     w.pT = op.need_T ? c.take<T>(nb) : nullptr;
     w.q = c.take<T>(nb);
     w.y = c.take<T>(op.rows * batch);
-    w.part_adj = c.take<double>(op.n_ag * batch);
+    // one partial per adjoint workgroup, or per image row (the Fourier-domain
+    // operator's row pass)
+    w.part_adj = c.take<double>((op.n_ag > op.n ? op.n_ag : int64_t(op.n)) * batch);
     const int64_t tl = int64_t(tiles_of(op.n)) * tiles_of(op.n);
     const int64_t pv = tl > 2 * vec_blocks(op.nn) ? tl : 2 * vec_blocks(op.nn);
     w.part_vec = c.take<double>(pv * batch);
@@ -1228,7 +1230,7 @@ extern "C" int split_bregman_tv_fourier(const radon_fourier *fp, int32_t path,
         return set_error(RADON_EINVAL, "unknown flags 0x%x", params->flags);
     const Fou &fou = *reinterpret_cast<const Fou *>(fp);
     const Op &op = *fou.op;
-    if (fourier_parts(fou) > op.n_ag)
+    if (fourier_parts(fou) > std::max<int64_t>(op.n_ag, op.n))
         return set_error(RADON_EUNSUPPORTED, "more Fourier partials than the solver buffers hold");
     Carver c(ws);
     c.take<char>(sb_ws_bytes(op, batch));
