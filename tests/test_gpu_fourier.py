@@ -7,7 +7,8 @@ eq:fusedop) on the GPU against the oracle.
   above 2n) and half-window widths;
 * the normal operator through the fused B B^* and through the two transforms
   matches the oracle's, with the K^T K and sigma terms and <x, out>;
-* split Bregman on eq:SBFFT matches the oracle's split Bregman;
+* split Bregman on eq:SBFFT matches the oracle's split Bregman; a batch of
+  images and a resumed run equal single and uninterrupted runs bitwise;
 * at 512 x 512 (180 of 360 angles, 725 bins): sampled outputs of F^* and F
   against the dense definition within the gridding accuracy, the adjoint
   identity, and the fused and unfused normal operators agreeing;
@@ -124,6 +125,25 @@ def test_split_bregman_matches_oracle(mode, tol, path):
     assert inf["outer"] == 20 and inf["breakdowns"] == 0
     if mode != "f32":
         assert inf["upd_b"] == pytest.approx(upd[-1], rel=1e-6)
+
+
+def test_batch_and_resume_are_bitwise():
+    """Three images in one call equal three single calls, and 10 + resumed 10
+    Bregman steps equal 20, bitwise (per-image arithmetic and state)."""
+    need_gpu()
+    case = (24, 20, 35, 1)
+    op, fo, g = setup(case, "mixed", 6)
+    rng = np.random.default_rng(8)
+    fh = to_dev(rng.standard_normal((3, fo.P, 2)), torch.float64)
+    for path in ("fused", "nufft"):
+        U, _ = fo.sb(fh, 0.05, 1.0, 6, 8, path=path)
+        for b in range(3):
+            u, _ = fo.sb(fh[b:b + 1].contiguous(), 0.05, 1.0, 6, 8, path=path)
+            assert torch.equal(u[0], U[b])
+        u20, _ = fo.sb(fh[:1].contiguous(), 0.05, 1.0, 20, 8, path=path)
+        u10, _ = fo.sb(fh[:1].contiguous(), 0.05, 1.0, 10, 8, path=path)
+        u10b, _ = fo.sb(fh[:1].contiguous(), 0.05, 1.0, 10, 8, path=path, resume=True, out=u10)
+        assert torch.equal(u10b, u20)
 
 
 def test_full_size_sampled_against_the_definition():
