@@ -611,6 +611,8 @@ static int build_fou(Fou &f, hipStream_t st)
     const int Q = (op.n_bins - 1) / 2;
     const int nq = 2 * Q + 1;
     f.P = int64_t(op.n_meas) * nq;
+    if (f.P * W * W >= (int64_t(1) << 40) || f.P > 0x7fffffff)
+        return set_error(RADON_EOVERFLOW, "%lld sample points exceed the gridding tables", (long long)f.P);
     const double h = 2.0 * M_PI / M;
     std::vector<int32_t> pbase(size_t(2 * f.P));
     std::vector<double> w1d(size_t(f.P) * size_t(2 * W));
