@@ -21,10 +21,10 @@
 // The grid is kept in centred order: grid point s stands for the frequency
 // (s - M/2) 2 pi / M.  The resulting (-1)^m factors and the two 1/M^2 of the
 // trapezoid rule are folded into the per-mode scale a1 = sqrt(pi/tau)
-// exp(m^2 tau) (-1)^m / M applied at zero-padding and at cropping.  The DFTs
-// are radix-2 transforms of whole grid lines in LDS (row pass, column pass);
-// rows that hold no image mode are skipped on the way in and not written on
-// the way out.
+// exp(m^2 tau) (-1)^m / M applied at zero-padding and at cropping.  The 2-D
+// DFTs are a row pass (radix-2 transforms of whole grid rows in LDS) and two
+// four-step column passes; rows that hold no image mode are skipped on the
+// way in and not written on the way out.
 #include "cg.hpp"
 
 #include <hip/hip_runtime.h>
@@ -102,7 +102,7 @@ __device__ inline int mode_of(int i, int n, int M)
 }
 
 // Row pass of F_D^* A: image rows -> grid rows (m_y mod M), zero-padded and
-// scaled by a1[iy] a1[ix].
+// scaled by a1[iy] a1[ix].  Rows without image modes are not written.
 template <class T>
 __global__ __launch_bounds__(kFftThreads) void k_fou_rows_fwd(const T *__restrict__ x, C2<T> *__restrict__ G,
                                                               const T *__restrict__ a1,
@@ -137,33 +137,65 @@ __global__ __launch_bounds__(kFftThreads) void k_fou_rows_fwd(const T *__restric
     }
 }
 
-// Column pass over L adjacent columns.  FWD: load only the rows that hold
-// image modes (the rest are zero), transform with sign -1, store every row.
-// !FWD: load every row, transform with sign +1, store only the mode rows.
-template <class T, bool FWD>
-__global__ __launch_bounds__(kFftThreads) void k_fou_cols(C2<T> *__restrict__ G,
-                                                          const C2<T> *__restrict__ tw, int n,
-                                                          int M, int logM, int L, int logL,
-                                                          int64_t MM)
+// Column DFTs of length M = M1 M2 in two passes over 16 adjacent columns
+// (four-step form): with row n = M2 n1 + n2 and frequency k = k1 + M1 k2,
+//   X[k1 + M1 k2] = sum_n2 W_M2^(n2 k2) W_M^(n2 k1) sum_n1 x[M2 n1 + n2] W_M1^(n1 k1).
+// Pass 1 (one n2 per workgroup) does the inner M1-point DFTs and the twiddle
+// W_M^(n2 k1), in place: it reads and writes the same rows n2 (mod M2).
+// Pass 2 (one k1 per workgroup) does the outer M2-point DFTs from rows
+// k1 M2 + n2 to rows k1 + M1 k2 of another buffer.  Every load and store is a
+// 256-byte row segment.  FWD: rows without image modes are zero on input.
+// !FWD: only the rows of image modes are written in pass 2.
+constexpr int kColW = 16;
+constexpr int kColMaxLen = 64;
+
+template <class T>
+__device__ inline C2<T> tw_pow(const C2<T> *__restrict__ tw, int e, int M, int sign)
 {
-    extern __shared__ char smem[];
-    C2<T> *tw_l = reinterpret_cast<C2<T> *>(smem);
-    C2<T> *buf = tw_l + (M >> 1);
-    const int stride = M + 1;
-    const int64_t go = int64_t(blockIdx.y) * MM;
-    const int c0 = blockIdx.x * L;
-    load_tw(tw_l, tw, M);
-    for (int e = threadIdx.x; e < L * M; e += blockDim.x) {
-        const int line = e & (L - 1), i = e >> logL;
+    // exp(sign 2 pi i e / M) for 0 <= e < M from the half table
+    C2<T> w = e < (M >> 1) ? tw[e] : C2<T>{-tw[e - (M >> 1)].x, -tw[e - (M >> 1)].y};
+    if (sign > 0) w.y = -w.y;
+    return w;
+}
+
+template <class T, bool FWD, int PASS>
+__global__ __launch_bounds__(kFftThreads) void k_fou_cols4(const C2<T> *__restrict__ src,
+                                                           C2<T> *__restrict__ dst,
+                                                           const C2<T> *__restrict__ tw, int n,
+                                                           int M, int logM, int logM1, int logM2,
+                                                           int64_t MM)
+{
+    __shared__ C2<T> buf[kColW * (kColMaxLen + 1)];
+    __shared__ C2<T> twl[kColMaxLen / 2];
+    const int loglen = PASS == 1 ? logM1 : logM2, len = 1 << loglen;
+    const int stride = len + 1;
+    const int sel = blockIdx.y;   // n2 in pass 1, k1 in pass 2
+    const int c0 = blockIdx.x * kColW;
+    const int64_t go = int64_t(blockIdx.z) * MM;
+    const int sign = FWD ? -1 : 1;
+    for (int k = threadIdx.x; k < (len >> 1); k += blockDim.x) twl[k] = tw[k << (logM - loglen)];
+    for (int e = threadIdx.x; e < len * kColW; e += blockDim.x) {
+        const int j = e >> 4, col = e & (kColW - 1);
+        const int row = PASS == 1 ? (j << logM2) + sel : (sel << logM2) + j;
         C2<T> v{T(0), T(0)};
-        if (!FWD || mode_of(i, n, M) >= 0) v = G[go + int64_t(i) * M + c0 + line];
-        buf[line * stride + brev(i, logM)] = v;
+        if (!(FWD && PASS == 1) || mode_of(row, n, M) >= 0) v = src[go + int64_t(row) * M + c0 + col];
+        buf[col * stride + brev(j, loglen)] = v;
     }
     __syncthreads();
-    lds_fft(buf, L, M, logM, stride, tw_l, FWD ? -1 : 1);
-    for (int e = threadIdx.x; e < L * M; e += blockDim.x) {
-        const int line = e & (L - 1), i = e >> logL;
-        if (FWD || mode_of(i, n, M) >= 0) G[go + int64_t(i) * M + c0 + line] = buf[line * stride + i];
+    lds_fft(buf, kColW, len, loglen, stride, twl, sign);
+    for (int e = threadIdx.x; e < len * kColW; e += blockDim.x) {
+        const int k = e >> 4, col = e & (kColW - 1);
+        C2<T> v = buf[col * stride + k];
+        int row;
+        if (PASS == 1) {
+            row = (k << logM2) + sel;
+            const C2<T> w = tw_pow(tw, (sel * k) & (M - 1), M, sign);
+            v = C2<T>{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+        } else {
+            row = sel + (k << logM1);
+            if (!FWD && mode_of(row, n, M) < 0) continue;
+        }
+        dst[go + int64_t(row) * M + c0 + col] = v;
     }
 }
 
@@ -458,34 +490,45 @@ static void split_grids(const Fou &f, void *grids, int batch, C2<T> **g0, C2<T> 
     *fh = c.take<C2<T>>(f.P * batch);
 }
 
-// G = F_D^* A x (scaled, centred grid)
-template <class T>
-static int fwd_to_grid(const Fou &f, const T *x, C2<T> *G, int batch, hipStream_t s)
+// Column passes of a 2-D DFT: G (in place, pass 1) then G -> out (pass 2).
+template <class T, bool FWD>
+static int col_passes(const Fou &f, C2<T> *G, C2<T> *out, int batch, hipStream_t s)
 {
     const int64_t MM = int64_t(f.M) * f.M;
-    const size_t lr = size_t(fft_lds_bytes<T>(f.M, f.Lr)), lc = size_t(fft_lds_bytes<T>(f.M, f.Lc));
+    const int l1 = (f.logM + 1) / 2, l2 = f.logM - l1;
+    const unsigned cb = unsigned(f.M / kColW);
+    k_fou_cols4<T, FWD, 1><<<dim3(cb, unsigned(1 << l2), unsigned(batch)), kFftThreads, 0, s>>>(
+        G, G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, l1, l2, MM);
+    SCT_TRY(check_launch("k_fou_cols4<1>"));
+    k_fou_cols4<T, FWD, 2><<<dim3(cb, unsigned(1 << l1), unsigned(batch)), kFftThreads, 0, s>>>(
+        G, out, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, l1, l2, MM);
+    return check_launch("k_fou_cols4<2>");
+}
+
+// out = F_D^* A x (scaled, centred grid); G is scratch.
+template <class T>
+static int fwd_to_grid(const Fou &f, const T *x, C2<T> *G, C2<T> *out, int batch, hipStream_t s)
+{
+    const int64_t MM = int64_t(f.M) * f.M;
+    const size_t lr = size_t(fft_lds_bytes<T>(f.M, f.Lr));
     k_fou_rows_fwd<T><<<dim3(unsigned((f.n + f.Lr - 1) / f.Lr), unsigned(batch)), kFftThreads, lr, s>>>(
         x, G, static_cast<const T *>(f.a1), static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.Lr,
         f.op->nn, MM);
     SCT_TRY(check_launch("k_fou_rows_fwd"));
-    k_fou_cols<T, true><<<dim3(unsigned(f.M / f.Lc), unsigned(batch)), kFftThreads, lc, s>>>(
-        G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.Lc, ilog2(f.Lc), MM);
-    return check_launch("k_fou_cols<fwd>");
+    return col_passes<T, true>(f, G, out, batch, s);
 }
 
 // out = alpha Re(A F_D G) (+ lambda K^T K x + sigma x, partials); G is
-// overwritten.
+// overwritten and S is scratch.
 template <class T>
-static int grid_to_image(const Fou &f, C2<T> *G, const T *x, T *out, double alpha, double lambda,
-                         double sigma, double *part, int batch, hipStream_t s)
+static int grid_to_image(const Fou &f, C2<T> *G, C2<T> *S, const T *x, T *out, double alpha,
+                         double lambda, double sigma, double *part, int batch, hipStream_t s)
 {
     const int64_t MM = int64_t(f.M) * f.M;
-    const size_t lr = size_t(fft_lds_bytes<T>(f.M, f.Lr)), lc = size_t(fft_lds_bytes<T>(f.M, f.Lc));
-    k_fou_cols<T, false><<<dim3(unsigned(f.M / f.Lc), unsigned(batch)), kFftThreads, lc, s>>>(
-        G, static_cast<const C2<T> *>(f.tw), f.n, f.M, f.logM, f.Lc, ilog2(f.Lc), MM);
-    SCT_TRY(check_launch("k_fou_cols<inv>"));
+    const size_t lr = size_t(fft_lds_bytes<T>(f.M, f.Lr));
+    SCT_TRY((col_passes<T, false>(f, G, S, batch, s)));
     k_fou_rows_inv<T><<<dim3(unsigned(fourier_parts(f)), unsigned(batch)), kFftThreads, lr, s>>>(
-        G, x, out, static_cast<const T *>(f.a1), static_cast<const C2<T> *>(f.tw), T(alpha),
+        S, x, out, static_cast<const T *>(f.a1), static_cast<const C2<T> *>(f.tw), T(alpha),
         T(lambda), T(sigma), part, f.n, f.M, f.logM, f.Lr, f.op->nn, MM);
     return check_launch("k_fou_rows_inv");
 }
@@ -525,14 +568,14 @@ int launch_fourier_normal(const Fou &f, int path, double alpha, double lambda, d
     if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
     C2<TV> *g0, *g1, *fh;
     split_grids<TV>(f, grids, batch, &g0, &g1, &fh);
-    SCT_TRY(fwd_to_grid<TV>(f, x, g0, batch, s));
+    SCT_TRY(fwd_to_grid<TV>(f, x, g0, g1, batch, s));
     if (path == RADON_FOURIER_FUSED) {
-        SCT_TRY((stencil<TM, TV>(f, g0, g1, batch, s)));
+        SCT_TRY((stencil<TM, TV>(f, g1, g0, batch, s)));
     } else {   // F^* to the points, then F back to the grid
-        SCT_TRY((interp<TM, TV>(f, g0, fh, batch, s)));
-        SCT_TRY((spread<TM, TV>(f, fh, g1, batch, s)));
+        SCT_TRY((interp<TM, TV>(f, g1, fh, batch, s)));
+        SCT_TRY((spread<TM, TV>(f, fh, g0, batch, s)));
     }
-    return grid_to_image<TV>(f, g1, x, out, alpha, lambda, sigma, part, batch, s);
+    return grid_to_image<TV>(f, g0, g1, x, out, alpha, lambda, sigma, part, batch, s);
 }
 
 template <class TM, class TV>
@@ -543,7 +586,7 @@ int launch_fourier_adj(const Fou &f, const TV *fhat, TV *x, double alpha, int ba
     C2<TV> *g0, *g1, *fh;
     split_grids<TV>(f, grids, batch, &g0, &g1, &fh);
     SCT_TRY((spread<TM, TV>(f, reinterpret_cast<const C2<TV> *>(fhat), g0, batch, s)));
-    return grid_to_image<TV>(f, g0, nullptr, x, alpha, 0.0, 0.0, nullptr, batch, s);
+    return grid_to_image<TV>(f, g0, g1, nullptr, x, alpha, 0.0, 0.0, nullptr, batch, s);
 }
 
 #define SCT_FOU_INST(TM, TV)                                                                       \
@@ -562,8 +605,6 @@ static int set_fft_lds(int64_t bytes)
 {
     if (bytes <= 64 * 1024) return RADON_OK;
     for (const void *k : {reinterpret_cast<const void *>(&k_fou_rows_fwd<T>),
-                          reinterpret_cast<const void *>(&k_fou_cols<T, true>),
-                          reinterpret_cast<const void *>(&k_fou_cols<T, false>),
                           reinterpret_cast<const void *>(&k_fou_rows_inv<T>)})
         SCT_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
     return RADON_OK;
@@ -735,7 +776,7 @@ static int build_fou(Fou &f, hipStream_t st)
         SCT_TRY(check_launch("k_fou_build"));
     }
     SCT_HIP(hipStreamSynchronize(st));
-    SCT_TRY(set_fft_lds<TV>(fft_lds_bytes<TV>(f.M, std::max(f.Lr, f.Lc))));
+    SCT_TRY(set_fft_lds<TV>(fft_lds_bytes<TV>(f.M, f.Lr)));
     const int R = f.D / 2;
     const int64_t slds = int64_t(sizeof(C2<TV>)) * (16 + 2 * R) * (15 + pad4(f.D));
     if (slds > 64 * 1024)
@@ -802,7 +843,6 @@ extern "C" int radon_fourier_create(const radon_op *p, int32_t m_sp, double tau,
             return L;
         };
         f->Lr = lines_for(op.n);
-        f->Lc = lines_for(M);
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int rc = dispatch(op, [&](auto *tm, auto *tv) {
@@ -879,8 +919,8 @@ extern "C" int fourier_fwd(const radon_fourier *p, const void *mu, void *fhat, i
         SCT_TYPES(tm, tv);
         C2<TV> *g0, *g1, *fh;
         split_grids<TV>(f, ws, batch, &g0, &g1, &fh);
-        SCT_TRY(fwd_to_grid<TV>(f, static_cast<const TV *>(mu), g0, batch, s));
-        return interp<TM, TV>(f, g0, static_cast<C2<TV> *>(fhat), batch, s);
+        SCT_TRY(fwd_to_grid<TV>(f, static_cast<const TV *>(mu), g0, g1, batch, s));
+        return interp<TM, TV>(f, g1, static_cast<C2<TV> *>(fhat), batch, s);
     });
 }
 

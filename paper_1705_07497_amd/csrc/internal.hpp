@@ -201,7 +201,7 @@ int64_t surrogate_parts(const Sur &s);
 struct Fou {
     const Op *op = nullptr;          // borrowed: geometry, sizes and the solver buffers
     int32_t n = 0, M = 0, logM = 0, m_sp = 0, D = 0;   // D = 4 m_sp - 1 stencil side
-    int32_t Lr = 0, Lc = 0;          // FFT lines per workgroup: row passes, column passes
+    int32_t Lr = 0;                  // FFT lines per workgroup of the row passes
     int32_t dtype = 0, msize = 4, vsize = 4;
     double tau = 0.0;
     int64_t P = 0, n_tiles = 0, sp_nnz = 0, device_bytes = 0;
