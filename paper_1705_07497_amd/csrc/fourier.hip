@@ -349,19 +349,24 @@ __global__ __launch_bounds__(256) void k_fou_interp(const C2<T> *__restrict__ G,
 }
 
 // G[s] = sum_p g_p(s) fhat_p (the spreading B, CSR over grid points): 16
-// lanes per grid point (rows near the origin hold over a thousand entries).
+// lanes per grid point, the grid points visited longest row first (rows near
+// the origin hold over a thousand entries, the median about 16), so the long
+// rows do not form the tail of the launch.
 template <class TM, class T>
 __global__ __launch_bounds__(256) void k_fou_spread(const C2<T> *__restrict__ fhat,
                                                     const int64_t *__restrict__ sp_ptr,
                                                     const int32_t *__restrict__ sp_pt,
                                                     const TM *__restrict__ sp_w,
+                                                    const int32_t *__restrict__ sp_order,
                                                     C2<T> *__restrict__ G, int64_t P, int64_t MM)
 {
-    const int64_t s = int64_t(blockIdx.x) * 16 + (threadIdx.x >> 4);
+    const int64_t o = int64_t(blockIdx.x) * 16 + (threadIdx.x >> 4);
     const int j = threadIdx.x & 15;
     const C2<T> *f = fhat + int64_t(blockIdx.y) * P;
+    const int64_t s = o < MM ? sp_order[o] : 0;
     T ax = T(0), ay = T(0);
-    if (s < MM) {
+    if (o < MM) {
+#pragma unroll 4
         for (int64_t k = sp_ptr[s] + j; k < sp_ptr[s + 1]; k += 16) {
             const T g = T(sp_w[k]);
             const C2<T> val = f[sp_pt[k]];
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(256) void k_fou_spread(const C2<T> *__restrict__ fh
     }
     ax = group16_sum(ax);
     ay = group16_sum(ay);
-    if (s < MM && j == 0) G[int64_t(blockIdx.y) * MM + s] = C2<T>{ax, ay};
+    if (o < MM && j == 0) G[int64_t(blockIdx.y) * MM + s] = C2<T>{ax, ay};
 }
 
 // B B^* coefficients of one stored tile and one chunk of 64 padded offsets
@@ -546,7 +551,7 @@ static int spread(const Fou &f, const C2<T> *fhat, C2<T> *G, int batch, hipStrea
 {
     const int64_t MM = int64_t(f.M) * f.M;
     k_fou_spread<TM, T><<<dim3(unsigned((MM + 15) / 16), unsigned(batch)), 256, 0, s>>>(
-        fhat, f.sp_ptr, f.sp_pt, static_cast<const TM *>(f.sp_w), G, f.P, MM);
+        fhat, f.sp_ptr, f.sp_pt, static_cast<const TM *>(f.sp_w), f.sp_order, G, f.P, MM);
     return check_launch("k_fou_spread");
 }
 
@@ -709,6 +714,17 @@ static int build_fou(Fou &f, hipStream_t st)
                     sp_w[size_t(k)] = TM(w1d[size_t(p * 2 * W + ky)] * w1d[size_t(p * 2 * W + W + kx)]);
                 }
     }
+    // grid points by descending row length (ties by index), for the spreading
+    std::vector<int32_t> sp_order(static_cast<size_t>(MM));
+    {
+        int64_t maxlen = 0;
+        for (int64_t c = 0; c < MM; ++c) maxlen = std::max(maxlen, sp_ptr[size_t(c + 1)] - sp_ptr[size_t(c)]);
+        std::vector<int64_t> start(size_t(maxlen + 2), 0);
+        for (int64_t c = 0; c < MM; ++c) ++start[size_t(maxlen - (sp_ptr[size_t(c + 1)] - sp_ptr[size_t(c)]) + 1)];
+        for (int64_t l = 0; l <= maxlen; ++l) start[size_t(l + 1)] += start[size_t(l)];
+        for (int64_t c = 0; c < MM; ++c)
+            sp_order[size_t(start[size_t(maxlen - (sp_ptr[size_t(c + 1)] - sp_ptr[size_t(c)]))]++)] = int32_t(c);
+    }
     // 8 x 8 tiles that some window reaches
     const int tpr = M / 8;
     std::vector<int32_t> tile_map(size_t(tpr) * size_t(tpr), -1);
@@ -748,6 +764,7 @@ static int build_fou(Fou &f, hipStream_t st)
     SCT_TRY(fou_upload(f, &f.sp_pt, sp_pt));
     SCT_TRY(fou_upload(f, &d_spw, sp_w));
     f.sp_w = d_spw;
+    SCT_TRY(fou_upload(f, &f.sp_order, sp_order));
     SCT_TRY(fou_upload(f, &f.tile_map, tile_map));
     SCT_TRY(fou_upload(f, &d_a1, a1));
     f.a1 = d_a1;

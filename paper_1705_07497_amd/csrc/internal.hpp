@@ -210,6 +210,7 @@ struct Fou {
     int64_t *sp_ptr = nullptr;       // gridding B as CSR over grid points: [M*M + 1]
     int32_t *sp_pt = nullptr;        // point of each entry
     void *sp_w = nullptr;            // its weight (matrix value type)
+    int32_t *sp_order = nullptr;     // grid points by descending row length
     int32_t *tile_map = nullptr;     // [(M/8)^2]: coefficient block of an 8 x 8 tile, -1 if zero
     void *coef = nullptr;            // B B^*: [n_tiles][D*D][64] (matrix value type)
     void *tw = nullptr;              // [M/2] exp(-2 pi i k / M) (vector type pairs)
