@@ -6,12 +6,17 @@ Bregman with at most 5 CG steps per Bregman update runs until the L1 norm of
 an update falls below 1e-8 of the first update or 6000 updates.  For each
 threshold 1e-2, 1e-4, 1e-6, 1e-8 the table lists the updates and GPU time
 needed to get below it and the relative L1 error of the image at that point.
-Solvers: the exact sparse operator and the surrogate T of radius 3.
+Solvers: the exact sparse operator and the surrogate T of radius 3 on the
+sinogram problem, and convolution fusing (the Fourier-domain problem
+eq:SBFFT through the precomputed B B^* of eq:fusedop, m_sp = 6) on the
+gridded Fourier samples of the same phantom with 1% complex noise and the
+data weight alpha / n_bins.
 
 The phantom is a random-ellipse image (the workload generator's recipe), the
 data carry 1% noise, and the weights are alpha = 0.01, lambda = 1 (the
 reading used for the 512 x 512 workloads).  Run:
     python -m paper_1705_07497_amd.study [--max-updates 6000] [--d 1 2 4]
+                                          [--solvers exact surrogate fusing]
 """
 from __future__ import annotations
 
@@ -23,7 +28,8 @@ THRESHOLDS = (1e-2, 1e-4, 1e-6, 1e-8)
 
 
 def run_case(sct, W, torch, d: int, max_updates: int, surrogate_radius: int | None,
-             alpha: float = 0.01, lam: float = 1.0, n_cg: int = 5, seed: int = 0):
+             alpha: float = 0.01, lam: float = 1.0, n_cg: int = 5, seed: int = 0,
+             fourier: bool = False):
     n = 512
     na = int(round(n * math.pi / (4 * d)))
     nb = W.n_bins_for(n)
@@ -32,9 +38,27 @@ def run_case(sct, W, torch, d: int, max_updates: int, surrogate_radius: int | No
     sur = sct.RadonSurrogate(op, surrogate_radius) if surrogate_radius is not None else None
     mu_np, eps = W.phantom_and_noise(n, 10, op.rows, seed=seed)
     mu = torch.as_tensor(mu_np, dtype=torch.float64, device=dev).reshape(1, -1)
-    y = op.fwd(mu)
-    f = (y + 0.01 * torch.sqrt(torch.mean(y ** 2)).item()
-         * torch.as_tensor(eps, dtype=torch.float64, device=dev)).contiguous()
+    if fourier:
+        # eq:SBFFT with the fused B B^* of eq:fusedop: the data are the gridded
+        # Fourier samples of the phantom with 1% complex noise
+        fo = sct.RadonFourier(op, 6)
+        y = fo.fwd(mu)
+        g = torch.Generator(device=dev).manual_seed(seed)
+        noise = torch.randn(y.shape, dtype=y.dtype, device=dev, generator=g)
+        f = (y + 0.01 * torch.sqrt(torch.mean(y ** 2)).item() * noise).contiguous()
+        # the unscaled DFT of a projection carries n_bins times its energy
+        # (Parseval), so alpha / n_bins weights the data term as alpha does in
+        # the sinogram problem
+        alpha_f = alpha / nb
+        step = lambda k, u: fo.sb(f, alpha_f, lam, 1, n_cg, resume=k > 0, out=u, path="fused")
+        label = "convolution fusing"
+    else:
+        y = op.fwd(mu)
+        f = (y + 0.01 * torch.sqrt(torch.mean(y ** 2)).item()
+             * torch.as_tensor(eps, dtype=torch.float64, device=dev)).contiguous()
+        step = lambda k, u: op.sb(f, alpha, lam, 1, n_cg, resume=k > 0, out=u, ws_key=("study", d),
+                                  surrogate=sur)
+        label = "exact" if sur is None else f"surrogate r={surrogate_radius}"
     mu_l1 = float(mu.abs().sum())
     u = torch.empty_like(mu)
     first = None
@@ -44,8 +68,7 @@ def run_case(sct, W, torch, d: int, max_updates: int, surrogate_radius: int | No
     k = 0
     while k < max_updates and len(found) < len(THRESHOLDS):
         e0.record()
-        _, info = op.sb(f, alpha, lam, 1, n_cg, resume=k > 0, out=u, ws_key=("study", d),
-                        surrogate=sur)
+        _, info = step(k, u)
         e1.record()
         torch.cuda.synchronize()
         elapsed += e0.elapsed_time(e1) / 1e3
@@ -58,8 +81,7 @@ def run_case(sct, W, torch, d: int, max_updates: int, surrogate_radius: int | No
             if t not in found and rel < t:
                 err = float((u - mu).abs().sum()) / mu_l1
                 found[t] = (k, elapsed, err)
-    return {"d": d, "angles": na, "updates": k, "time_s": elapsed, "found": found,
-            "solver": "exact" if sur is None else f"surrogate r={surrogate_radius}"}
+    return {"d": d, "angles": na, "updates": k, "time_s": elapsed, "found": found, "solver": label}
 
 
 def table(rows) -> str:
@@ -82,14 +104,19 @@ def main(argv=None) -> None:
     ap.add_argument("--max-updates", type=int, default=6000)
     ap.add_argument("--d", type=int, nargs="+", default=[1, 2, 4])
     ap.add_argument("--surrogate-radius", type=int, default=3)
+    ap.add_argument("--solvers", nargs="+", default=["exact", "surrogate", "fusing"],
+                    choices=["exact", "surrogate", "fusing"])
     args = ap.parse_args(argv)
     import torch
     import workloads as W
     import paper_1705_07497_amd as sct
     rows = []
     for d in args.d:
-        for radius in (None, args.surrogate_radius):
-            r = run_case(sct, W, torch, d, args.max_updates, radius)
+        cases = {"exact": (None, False), "surrogate": (args.surrogate_radius, False),
+                 "fusing": (None, True)}
+        for name in args.solvers:
+            radius, fourier = cases[name]
+            r = run_case(sct, W, torch, d, args.max_updates, radius, fourier=fourier)
             rows.append(r)
             print(f"# d={d} {r['solver']}: {r['updates']} updates, {r['time_s']:.2f} s", file=sys.stderr,
                   flush=True)
