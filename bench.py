@@ -250,6 +250,14 @@ def bench_fourier(sct, op, w, mu, torch, timed, profile=False):
         fo.normal(x, w.alpha, w.lam, path=path, out=out)
         t = timed(lambda: fo.normal(x, w.alpha, w.lam, path=path, out=out), reps) / reps
         res[f"{path}_normal_us"] = round(t * 1e6, 1)
+    # four images per call: the fused path shares each B B^* coefficient
+    # load between two grids
+    x4 = torch.randn((4, op.nn), dtype=mu.dtype, device=mu.device)
+    out4 = torch.empty_like(x4)
+    for path in ("fused", "nufft"):
+        fo.normal(x4, w.alpha, w.lam, path=path, out=out4)
+        t = timed(lambda: fo.normal(x4, w.alpha, w.lam, path=path, out=out4), 20) / 20
+        res[f"{path}_normal_batch4_us_per_image"] = round(t / 4 * 1e6, 1)
     fh = fo.fwd(mu)
     g = torch.Generator(device=mu.device).manual_seed(0)
     noise = torch.randn(fh.shape, dtype=fh.dtype, device=fh.device, generator=g)
@@ -275,7 +283,9 @@ def bench_fourier(sct, op, w, mu, torch, timed, profile=False):
     res["fused_normal_gbs"] = round(fused_alg / (res["fused_normal_us"] * 1e-6) / 1e9, 1)
     print(f"# Fourier (m_sp 6, grid {fo.grid}, {fo.P} points): build {build_s:.2f} s, "
           f"B B^* {fo.info['fused_bytes'] / 1e9:.2f} GB; normal fused {res['fused_normal_us']:.0f} us, "
-          f"NUFFT {res['nufft_normal_us']:.0f} us; split Bregman fused {res['sb_fused_ms_per_recon']:.1f} ms, "
+          f"NUFFT {res['nufft_normal_us']:.0f} us (4 images: {res['fused_normal_batch4_us_per_image']:.0f} and "
+          f"{res['nufft_normal_batch4_us_per_image']:.0f} us per image); split Bregman fused "
+          f"{res['sb_fused_ms_per_recon']:.1f} ms, "
           f"NUFFT {res['sb_nufft_ms_per_recon']:.1f} ms, error to phantom "
           f"{res['sb_fused_rel_err_to_phantom']:.4f}", file=sys.stderr, flush=True)
     return res

@@ -264,50 +264,65 @@ __global__ __launch_bounds__(kFftThreads) void k_fou_rows_inv(const C2<T> *__res
 // tiles, one wave each); the region plus a periodic halo of R = 2 m_sp - 1
 // (one more column for the padded offsets) is staged in LDS, the
 // coefficients stream from HBM as quads of offsets (64 lanes x 16 bytes per
-// load).  A tile without coefficients writes zeros.
-template <class TM, class T>
+// load).  BC images (blockIdx.z selects a chunk of them, nbc present) share
+// every coefficient load; with BC = 2 the LDS reads still keep pace with the
+// stream.  A tile without coefficients writes zeros.
+template <class TM, class T, int BC>
 __global__ __launch_bounds__(256) void k_fou_stencil(const C2<T> *__restrict__ u,
                                                      C2<T> *__restrict__ v,
                                                      const Quad<TM> *__restrict__ coef,
                                                      const int32_t *__restrict__ tile_map, int M,
-                                                     int R, int64_t MM)
+                                                     int R, int64_t MM, int batch)
 {
     extern __shared__ char smem[];
     C2<T> *reg = reinterpret_cast<C2<T> *>(smem);
     const int D = 2 * R + 1, Dp = pad4(D), nqx = Dp >> 2;
-    const int sh = 16 + 2 * R, sw = 15 + Dp;
+    const int sh = 16 + 2 * R, sw = 15 + Dp, area = sh * sw;
     const int rx0 = blockIdx.x * 16, ry0 = blockIdx.y * 16;
-    const int64_t go = int64_t(blockIdx.z) * MM;
+    const int b0 = blockIdx.z * BC;
+    const int nbc = min(BC, batch - b0);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tpr = M >> 3;
     const int blk = tile_map[((ry0 >> 3) + (w >> 1)) * tpr + (rx0 >> 3) + (w & 1)];
     const int any = __syncthreads_or(blk >= 0);
     const int ly = ((w >> 1) << 3) + (lane >> 3), lx = ((w & 1) << 3) + (lane & 7);
-    C2<T> acc{T(0), T(0)};
+    C2<T> acc[BC];
+#pragma unroll
+    for (int c = 0; c < BC; ++c) acc[c] = C2<T>{T(0), T(0)};
     if (any) {
-        for (int e = threadIdx.x; e < sh * sw; e += blockDim.x) {
-            const int ey = e / sw, ex = e - ey * sw;
-            const int gy = (ry0 + ey - R) & (M - 1), gx = (rx0 + ex - R) & (M - 1);
-            reg[e] = u[go + int64_t(gy) * M + gx];
+        for (int c = 0; c < nbc; ++c) {
+            const int64_t go = int64_t(b0 + c) * MM;
+            for (int e = threadIdx.x; e < area; e += blockDim.x) {
+                const int ey = e / sw, ex = e - ey * sw;
+                const int gy = (ry0 + ey - R) & (M - 1), gx = (rx0 + ex - R) & (M - 1);
+                reg[c * area + e] = u[go + int64_t(gy) * M + gx];
+            }
         }
         __syncthreads();
         if (blk >= 0) {
-            const Quad<TM> *c = coef + int64_t(blk) * D * nqx * 64 + lane;
+            const Quad<TM> *cq = coef + int64_t(blk) * D * nqx * 64 + lane;
             for (int dy = 0; dy < D; ++dy) {
                 const C2<T> *row = reg + (ly + dy) * sw + lx;
-                const Quad<TM> *cr = c + int64_t(dy) * nqx * 64;
+                const Quad<TM> *cr = cq + int64_t(dy) * nqx * 64;
 #pragma unroll 2
                 for (int qx = 0; qx < nqx; ++qx) {
                     const Quad<TM> q = cr[qx * 64];
-                    const C2<T> u0 = row[4 * qx], u1 = row[4 * qx + 1], u2 = row[4 * qx + 2],
-                                u3 = row[4 * qx + 3];
-                    acc.x += T(q.x) * u0.x + T(q.y) * u1.x + T(q.z) * u2.x + T(q.w) * u3.x;
-                    acc.y += T(q.x) * u0.y + T(q.y) * u1.y + T(q.z) * u2.y + T(q.w) * u3.y;
+#pragma unroll
+                    for (int c = 0; c < BC; ++c) {
+                        if (BC == 1 || c < nbc) {
+                            const C2<T> *rc = row + c * area + 4 * qx;
+                            const C2<T> u0 = rc[0], u1 = rc[1], u2 = rc[2], u3 = rc[3];
+                            acc[c].x += T(q.x) * u0.x + T(q.y) * u1.x + T(q.z) * u2.x + T(q.w) * u3.x;
+                            acc[c].y += T(q.x) * u0.y + T(q.y) * u1.y + T(q.z) * u2.y + T(q.w) * u3.y;
+                        }
+                    }
                 }
             }
         }
     }
-    v[go + int64_t(ry0 + ly) * M + rx0 + lx] = acc;
+#pragma unroll
+    for (int c = 0; c < BC; ++c)
+        if (BC == 1 || c < nbc) v[int64_t(b0 + c) * MM + int64_t(ry0 + ly) * M + rx0 + lx] = acc[c];
 }
 
 // Sum over the 16 lanes of a group (xor tree: a fixed order).
@@ -559,10 +574,17 @@ template <class TM, class T>
 static int stencil(const Fou &f, const C2<T> *u, C2<T> *v, int batch, hipStream_t s)
 {
     const int R = f.D / 2;
-    const size_t lds = sizeof(C2<T>) * size_t(16 + 2 * R) * size_t(15 + pad4(f.D));
+    const size_t area = size_t(16 + 2 * R) * size_t(15 + pad4(f.D));
     const unsigned g = unsigned(f.M / 16);
-    k_fou_stencil<TM, T><<<dim3(g, g, unsigned(batch)), 256, lds, s>>>(
-        u, v, static_cast<const Quad<TM> *>(f.coef), f.tile_map, f.M, R, int64_t(f.M) * f.M);
+    const int64_t MM = int64_t(f.M) * f.M;
+    const Quad<TM> *c = static_cast<const Quad<TM> *>(f.coef);
+    if (batch >= 2) {
+        k_fou_stencil<TM, T, 2><<<dim3(g, g, unsigned((batch + 1) / 2)), 256, 2 * area * sizeof(C2<T>), s>>>(
+            u, v, c, f.tile_map, f.M, R, MM, batch);
+    } else {
+        k_fou_stencil<TM, T, 1><<<dim3(g, g, 1), 256, area * sizeof(C2<T>), s>>>(
+            u, v, c, f.tile_map, f.M, R, MM, batch);
+    }
     return check_launch("k_fou_stencil");
 }
 
@@ -797,8 +819,11 @@ static int build_fou(Fou &f, hipStream_t st)
     const int R = f.D / 2;
     const int64_t slds = int64_t(sizeof(C2<TV>)) * (16 + 2 * R) * (15 + pad4(f.D));
     if (slds > 64 * 1024)
-        SCT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fou_stencil<TM, TV>),
+        SCT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fou_stencil<TM, TV, 1>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(slds)));
+    if (2 * slds > 64 * 1024)
+        SCT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fou_stencil<TM, TV, 2>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(2 * slds)));
     return RADON_OK;
 }
 
