@@ -98,6 +98,25 @@ def test_normal_operator_matches_oracle(mode, case, path):
             assert abs(dot[b] - x[b] @ want) <= 10 * TOL[mode] * np.abs(x[b]).dot(np.abs(want))
 
 
+@pytest.mark.parametrize("mode", ["f64", "mixed"])
+@pytest.mark.parametrize("case", [(16, 12, 23, 1), (32, 25, 47, 2)])
+def test_wide_window_m_sp_12(mode, case):
+    """M_sp = 12 (about 12 digits): 47 x 48 stencil coefficients per grid
+    point, wider than the 32-point grid at n = 16 (the stencil wraps), and
+    the two-image stencil's LDS above 64 KB."""
+    need_gpu()
+    op, fo, g = setup(case, mode, 12)
+    dt = MODES[mode][1]
+    rng = np.random.default_rng(12)
+    x = rounded(rng.standard_normal((3, op.nn)), dt)
+    BB = g.fused_matrix()
+    for path, H in (("fused", lambda v: g.fused_normal(v, BB)),
+                    ("nufft", lambda v: g.nufft_adj(g.nufft_fwd(v)).real)):
+        out = host(fo.normal(to_dev(x, dt), 1.5, 0.5, 0.0, path=path))
+        for b in range(3):
+            assert rel_l2(out[b], F.normal(H, case[0], x[b], 1.5, 0.5)) <= TOL[mode], (path, b)
+
+
 @pytest.mark.parametrize("mode,tol", [("f64", 1e-9), ("mixed", 1e-8), ("f32", 5e-2)])
 @pytest.mark.parametrize("path", ["fused", "nufft"])
 def test_split_bregman_matches_oracle(mode, tol, path):
