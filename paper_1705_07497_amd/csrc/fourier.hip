@@ -872,6 +872,15 @@ extern "C" int radon_fourier_create(const radon_op *p, int32_t m_sp, double tau,
     f->m_sp = m_sp;
     f->D = 4 * m_sp - 1;
     f->tau = tau > 0.0 ? tau : 4.0 * m_sp / (double(M) * M);
+    {
+        // the deconvolution exp(|m|^2 tau) at the image corner must stay finite
+        const double h = double(op.n / 2 + 1);
+        if (2.0 * h * h * f->tau > 600.0) {
+            delete f;
+            return set_error(RADON_EINVAL, "tau %g is too large for n = %d (the deconvolution overflows)",
+                             f->tau, op.n);
+        }
+    }
     f->dtype = op.dtype;
     f->msize = op.msize;
     f->vsize = op.vsize;

@@ -216,6 +216,8 @@ def test_errors():
         sct.RadonFourier(op, 6, grid=48)
     with pytest.raises(sct.SparsectError, match="power of two"):
         sct.RadonFourier(op, 6, grid=16)
+    with pytest.raises(sct.SparsectError, match="tau"):
+        sct.RadonFourier(op, 6, tau=20.0)
     fo = sct.RadonFourier(op, 2)
     L = sct.lib()
     x = torch.zeros((1, op.nn), dtype=torch.float64, device="cuda")
