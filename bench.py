@@ -505,7 +505,7 @@ def main():
             for _ in range(reps):
                 ref.normal(xr, w.alpha, w.lam)
             tc = time.perf_counter() - t0
-            cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+            cores = oracle.set_threads()
             result["cpu_baseline"] = {
                 "value": round(reps / tc, 2), "unit": "normal applies/s", "cores": cores,
                 "kind": "oracle",
@@ -514,6 +514,21 @@ def main():
             }
             print(f"# cpu oracle: {reps / tc:.2f} applies/s on {cores} threads", file=sys.stderr,
                   flush=True)
+            # the same on one thread, a ~5 s sample
+            oracle.set_threads(1)
+            t0 = time.perf_counter()
+            ref.normal(xr, w.alpha, w.lam)
+            one1 = time.perf_counter() - t0
+            reps1 = max(2, min(500, int(5.0 / max(one1, 1e-4))))
+            t0 = time.perf_counter()
+            for _ in range(reps1):
+                ref.normal(xr, w.alpha, w.lam)
+            tc1 = time.perf_counter() - t0
+            oracle.set_threads(cores)
+            result["cpu_baseline_1thread"] = {
+                "value": round(reps1 / tc1, 2), "unit": "normal applies/s", "cores": 1, "kind": "oracle",
+                "sample": f"{reps1} FP64 normal applies of the same operator ({tc1:.1f} s)"}
+            print(f"# cpu oracle: {reps1 / tc1:.2f} applies/s on 1 thread", file=sys.stderr, flush=True)
         if not args.no_verify:
             t0 = time.perf_counter()
             uo = ref.sb(fr, w.alpha, w.lam, w.n_outer, w.n_cg)[0]

@@ -91,8 +91,16 @@ def lib():
         L.ora_pd.restype = ctypes.c_int
         L.ora_surrogate_weights.argtypes = [P, ctypes.c_int, _dp]
         L.ora_surrogate_weights.restype = ctypes.c_int
+        L.ora_set_threads.argtypes = [ctypes.c_int]
+        L.ora_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP thread count (n > 0) and return the count in
+    effect.  Timing only: results do not depend on it."""
+    return int(lib().ora_set_threads(int(n)))
 
 
 def _p(a, typ=_dp):

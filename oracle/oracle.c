@@ -39,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define SLIVER 1e-12
 
@@ -656,4 +659,18 @@ double ora_loss2(const ora_op *op, double ta, int n_iter, const double *mu, cons
     free(P); free(Rr); free(Q); free(rho); free(gam); free(aa); free(bb); free(active);
     free(u); free(scratch); free(y); free(ub); free(rb); free(pb); free(qb); free(aq); free(rhob);
     return loss;
+}
+
+/* Threads of the OpenMP loops (timing only; the results do not depend on
+ * it: every parallel loop writes disjoint rows and the sums are sequential).
+ * Returns the count in effect. */
+int ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
