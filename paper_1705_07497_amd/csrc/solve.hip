@@ -91,6 +91,26 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_xr(
 {
     __shared__ double red[kVecThreads];
     const int64_t b = blockIdx.y;
+    const int64_t off = b * nn;
+    const int64_t i0 = int64_t(blockIdx.x) * kVecThreads + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * kVecThreads;
+    // the first kPre elements' operands are loaded before the step length is
+    // known, so their latency overlaps the reduction of the partials
+    constexpr int kPre = 4;
+    T px[kPre], pp[kPre], pq[kPre], pr[kPre];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        const int64_t i = i0 + k * stride;
+        if (i < nn) {
+            const int64_t j = off + i;
+            if (x) {
+                px[k] = x[j];
+                pp[k] = p[j];
+            }
+            pq[k] = q[j];
+            pr[k] = r[j];
+        }
+    }
     const double gamma = sum_part_block(part_adj + b * n_adj, n_adj, red);
     double a;
     const int stop = cg_decide(st[b], gamma, rtol, &a);
@@ -104,12 +124,21 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_xr(
     }
     if (stop) return;   // uniform per block; the partials are then unused
     const T at = T(a);
-    const int64_t off = b * nn;
     double acc = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * kVecThreads + threadIdx.x; i < nn;
-         i += int64_t(gridDim.x) * kVecThreads) {
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        const int64_t i = i0 + k * stride;
+        if (i < nn) {
+            const int64_t j = off + i;
+            if (x) x[j] = fma(at, pp[k], px[k]);   // a replay only needs r
+            const T rn = fma(-at, pq[k], pr[k]);
+            r[j] = rn;
+            acc += double(rn) * double(rn);
+        }
+    }
+    for (int64_t i = i0 + kPre * stride; i < nn; i += stride) {
         const int64_t j = off + i;
-        if (x) x[j] = fma(at, p[j], x[j]);   // a replay only needs r
+        if (x) x[j] = fma(at, p[j], x[j]);
         const T rn = fma(-at, q[j], r[j]);
         r[j] = rn;
         acc += double(rn) * double(rn);
@@ -144,6 +173,20 @@ __global__ __launch_bounds__(256) void k_cg_p(const T *__restrict__ r, T *__rest
         }
         return;
     }
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int64_t off = b * nn;
+    // the tile's r and p are loaded before beta is known (the reduction of
+    // the partials overlaps their latency)
+    T rr[4], pp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int iy = by + threadIdx.y + 8 * k, ix = bx + threadIdx.x;
+        if (iy < n && ix < n) {
+            const int64_t j = off + int64_t(iy) * n + ix;
+            rr[k] = r[j];
+            pp[k] = p[j];
+        }
+    }
     double v = 0.0;
     const int t = threadIdx.y * 32 + threadIdx.x;
     for (int64_t i = t; i < n_part; i += 256) v += part[b * n_part + i];
@@ -156,13 +199,13 @@ __global__ __launch_bounds__(256) void k_cg_p(const T *__restrict__ r, T *__rest
         st_next[b] = o;
     }
     const T beta = T(beta_d);
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    const int64_t off = b * nn;
-    for (int i = threadIdx.y; i < 32; i += 8) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = threadIdx.y + 8 * k;
         const int iy = by + i, ix = bx + threadIdx.x;
         if (iy < n && ix < n) {
             const int64_t j = off + int64_t(iy) * n + ix;
-            const T v2 = fma(beta, p[j], r[j]);
+            const T v2 = fma(beta, pp[k], rr[k]);
             p[j] = v2;
             tile[i][threadIdx.x] = v2;
         }
