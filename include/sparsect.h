@@ -504,7 +504,8 @@ int64_t radon_fourier_workspace_bytes(const radon_fourier *f, int32_t which, int
 
 /*
  * fourier_fwd -- fhat = F^* mu (gridded): mu device [batch][n*n], fhat device
- * [batch][P] complex.  ws: radon_fourier_workspace_bytes(RADON_FWS_TRANSFORM).
+ * [batch][P] complex.  ws: radon_fourier_workspace_bytes(RADON_FWS_TRANSFORM);
+ * errors and stream as for fourier_normal.
  */
 int fourier_fwd(const radon_fourier *f, const void *mu, void *fhat, int32_t batch, void *ws,
                 int64_t ws_bytes, void *stream);
@@ -512,6 +513,7 @@ int fourier_fwd(const radon_fourier *f, const void *mu, void *fhat, int32_t batc
 /*
  * fourier_adj -- x = alpha Re(F fhat) (gridded): fhat device [batch][P]
  * complex, x device [batch][n*n].  This is the data term of eq:SBFFT.
+ * ws, errors and stream as for fourier_normal.
  */
 int fourier_adj(const radon_fourier *f, const void *fhat, void *x, double alpha, int32_t batch,
                 void *ws, int64_t ws_bytes, void *stream);
@@ -519,7 +521,11 @@ int fourier_adj(const radon_fourier *f, const void *fhat, void *x, double alpha,
 /*
  * fourier_normal -- out = alpha H x + lambda K^T K x + sigma x with H by
  * `path` (RADON_FOURIER_FUSED or RADON_FOURIER_NUFFT); with dot_out (device
- * double[batch]) also <x, out>.  out must not alias x.
+ * double[batch]) also <x, out>.  x, out device [batch][n*n]; out must not
+ * alias x.  ws: radon_fourier_workspace_bytes(RADON_FWS_TRANSFORM) (two
+ * M x M complex grids and the sample values per image).  Errors: EINVAL for
+ * a NULL handle or pointer, an unknown path, aliasing or a short workspace;
+ * EUNSUPPORTED for batch > 65535.  Asynchronous on `stream`.
  */
 int fourier_normal(const radon_fourier *f, int32_t path, double alpha, double lambda, double sigma,
                    const void *x, void *out, double *dot_out, int32_t batch, void *ws,
