@@ -10,7 +10,10 @@
  * once, offline, and every evaluation inside the solver becomes a sparse
  * product).  On top of that it provides the normal operator of eq:KKT,
  * eq:PD_resolve and eq:SB_solve (Section 2), conjugate gradients for those
- * systems, and anisotropic-TV split Bregman (Section 4).
+ * systems, and anisotropic-TV split Bregman (Section 4); the Chambolle-Pock
+ * method whose primal step is eq:PD_resolve; the surrogate T of Section 3.2;
+ * and the Fourier-domain problem of Section 3.1 (eq:four_obj, eq:SBFFT) with
+ * its convolution-fused normal operator (eq:fusedop).
  *
  * Geometry (the paper leaves it open; this is the library's convention):
  *   image of n x n unit pixels on [-n/2, n/2]^2, pixel (iy, ix) covers
