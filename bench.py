@@ -481,6 +481,23 @@ def main():
         "roofline": roofline,
     }
 
+    # the same normal operator in the pure FP32 kind (FP32 vectors too): its
+    # split Bregman drifts from exact arithmetic by ~1e-2, so it is a
+    # throughput figure only
+    op32 = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, device=dev)
+    x32 = x.float()
+    out32 = torch.empty_like(x32)
+    for _ in range(10):
+        op32.normal(x32, w.alpha, w.lam, out=out32)
+    t32 = timed(lambda: op32.normal(x32, w.alpha, w.lam, out=out32), args.applies) / args.applies
+    bytes32 = 2 * 8 * nnz + 4 * (rows + 1) + 4 * (nn + 1) + 4 * (2 * nn + 2 * rows)
+    result["normal_apply_f32_kind"] = {"us": round(t32 * 1e6, 1), "per_s": round(1.0 / t32, 1),
+                                       "gbs": round(bytes32 / t32 / 1e9, 1),
+                                       "frac": round(bytes32 / t32 / 1e9 / HBM_PEAK_GBS, 4)}
+    print(f"# normal operator, FP32 kind: {t32 * 1e6:.1f} us, {bytes32 / t32 / 1e9:.0f} GB/s",
+          file=sys.stderr, flush=True)
+    del op32
+
     result["surrogate"] = bench_surrogate(sct, op, w, f, mu, u, torch, timed, stream)
     result["primal_dual"] = bench_pd(op, w, f, mu, torch, timed)
     result["fourier"] = bench_fourier(sct, op, w, mu, torch, timed)
