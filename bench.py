@@ -441,10 +441,28 @@ def main():
         u, info = op.sb(f, w.alpha, w.lam, w.n_outer, w.n_cg)
     e1.record(stream)
     torch.cuda.synchronize()
-    t_sb = e0.elapsed_time(e1) / 1e3
+    t_sb_eager = e0.elapsed_time(e1) / 1e3
+    # the same reconstruction captured once as a HIP graph (one launch per
+    # reconstruction, no host work between its ~4,000 kernels); it must equal
+    # the eager result bitwise
+    sbg = op.sb_graph(f, w.alpha, w.lam, w.n_outer, w.n_cg)
+    for _ in range(args.warmup):
+        sbg.launch()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        sbg.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_sb_graph = e0.elapsed_time(e1) / 1e3
+    if not torch.equal(sbg.mu, u):
+        raise RuntimeError("the captured split-Bregman graph differs from the eager solve")
+    t_sb = min(t_sb_eager, t_sb_graph)
     applies_per_recon = w.n_outer * w.n_cg
     recon_per_s = args.steps / t_sb
     value = applies_per_recon * recon_per_s
+    print(f"# split Bregman: eager {t_sb_eager / args.steps * 1e3:.2f} ms, graph "
+          f"{t_sb_graph / args.steps * 1e3:.2f} ms per reconstruction", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (algorithmic CSR bytes: 4 B FP32 value + 4 B
     # index per nonzero, int32 row pointers, FP64 vectors read and written once)
@@ -474,6 +492,8 @@ def main():
                    "measured_angles": w.n_meas, "bins": w.n_bins, "n_outer": w.n_outer,
                    "n_cg": w.n_cg, "nnz": nnz, "batch": 1},
         "recon_per_s": round(recon_per_s, 3),
+        "sb_eager_ms": round(t_sb_eager / args.steps * 1e3, 3),
+        "sb_graph_ms": round(t_sb_graph / args.steps * 1e3, 3),
         "normal_apply_per_s": round(args.applies / t_normal, 1),
         "normal_apply_gbs": round(normal_bytes / (t_normal / args.applies) / 1e9, 1),
         "fwd_us": round(avg_fwd * 1e6, 2), "adj_us": round(avg_adj * 1e6, 2),

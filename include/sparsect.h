@@ -446,6 +446,20 @@ int split_bregman_tv_surrogate(const radon_op *op, const radon_surrogate *s,
                                void *stream);
 
 /*
+ * split_bregman_tv_graph -- split_bregman_tv (exact operator) captured once
+ * as a HIP graph: every kernel of the n_outer x n_cg solve becomes one node,
+ * so a reconstruction is one radon_graph_launch with no host work between
+ * kernels.  Each launch reads f and writes mu, ws and info at the addresses
+ * given here, and runs the whole solve from the start (from mu with
+ * RADON_SB_WARM, else from 0); RADON_SB_RESUME cannot be captured.  The
+ * buffers must stay allocated while the graph is used.  Release with
+ * radon_graph_destroy.  Arguments and errors as for split_bregman_tv.
+ */
+int split_bregman_tv_graph(const radon_op *op, const radon_sb_params *params, const void *f,
+                           void *mu, int32_t batch, void *ws, int64_t ws_bytes, radon_sb_info *info,
+                           radon_graph **out);
+
+/*
  * Fourier-domain operator (Sections 2 and 3.1: eq:four_obj, eq:SBFFT,
  * eq:fusedop).  By the Fourier slice theorem, the 1-D DFT of the projection
  * at measured angle theta_k = pi k / n_angles and radial frequency

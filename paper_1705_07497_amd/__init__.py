@@ -129,6 +129,8 @@ SIGNATURES = {
     "radon_multi_cg_graph": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, _vp,
                                             ctypes.c_int64, _vp, ctypes.POINTER(_vp)]),
     "radon_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "split_bregman_tv_graph": (ctypes.c_int, [_vp, ctypes.POINTER(SbParams), _vp, _vp, ctypes.c_int32,
+                                              _vp, ctypes.c_int64, _vp, ctypes.POINTER(_vp)]),
     "radon_graph_destroy": (None, [_vp]),
     "chambolle_pock_tv": (ctypes.c_int, [_vp, ctypes.POINTER(PdParams), _vp, _vp, ctypes.c_int32,
                                           _vp, ctypes.c_int64, _vp]),
@@ -411,6 +413,11 @@ class RadonOp:
                                                     self._p(f), self._p(mu), b, self._p(ws), nb,
                                                     self._p(info), self._stream()))
         return mu, info
+
+    def sb_graph(self, f, alpha: float, lam: float, n_outer: int, n_cg: int, tol: float = 0.0):
+        """split_bregman_tv captured as one HIP graph (SbGraph): write the data
+        into .f, call launch(), read .mu and .info."""
+        return SbGraph(self, f, alpha, lam, n_outer, n_cg, tol)
 
     def unrolled_sizes(self, n_iter: int, ckpt: int, batch: int) -> tuple[int, int, int]:
         """(tape, forward workspace, reverse workspace) bytes of an unrolled CG."""
@@ -770,6 +777,46 @@ class RadonMulti:
     def cg_graph(self, n_iter: int = 10, rtol: float = 0.0) -> "MultiCgGraph":
         """Capture a CG solve into a HIP graph over buffers it owns (see MultiCgGraph)."""
         return MultiCgGraph(self, n_iter, rtol)
+
+
+class SbGraph:
+    """A captured split_bregman_tv of one operator: each launch() runs the
+    whole n_outer x n_cg solve from 0 on the data in .f into .mu and .info.
+    The graph owns (keeps alive) its buffers."""
+
+    def __init__(self, op: RadonOp, f, alpha: float, lam: float, n_outer: int, n_cg: int,
+                 tol: float = 0.0):
+        torch = _torch()
+        self.op = op
+        b = op._sino(f, "f")
+        self.f = f.clone()
+        self.mu = torch.empty((b, op.nn), dtype=op.dtype, device=op.device)
+        self.info = torch.zeros(b * ctypes.sizeof(SbInfo), dtype=torch.uint8, device=op.device)
+        nbytes = lib().radon_workspace_bytes(op._h, WS_SB, b)
+        if nbytes < 0:
+            _check(int(nbytes))
+        self.ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=op.device)
+        P = SbParams(float(alpha), float(lam), float(tol), int(n_outer), int(n_cg), 0, 0)
+        torch.cuda.synchronize(op.device)
+        h = _vp()
+        with torch.cuda.device(op.device):
+            _check(lib().split_bregman_tv_graph(op._h, ctypes.byref(P), _vp(self.f.data_ptr()),
+                                                _vp(self.mu.data_ptr()), b, _vp(self.ws.data_ptr()),
+                                                int(nbytes), _vp(self.info.data_ptr()), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().radon_graph_launch(self._h, self.op._stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _torch().cuda.synchronize(self.op.device)
+            except Exception:
+                pass
+            _lib.radon_graph_destroy(h)
+            self._h = None
 
 
 class MultiCgGraph:

@@ -12,6 +12,8 @@
 #include "cg.hpp"
 #include "products.hpp"
 
+#include <functional>
+
 #include <algorithm>
 #include <new>
 
@@ -739,21 +741,11 @@ extern "C" int radon_multi_cg(const radon_multi *p, const void *rhs, void *x, in
     });
 }
 
-extern "C" int radon_multi_cg_graph(const radon_multi *p, const void *rhs, void *x, int32_t n_iter,
-                                    double rtol, void *ws, int64_t ws_bytes, radon_cg_info *info,
-                                    radon_graph **out)
+namespace sct {
+// Record body(stream) on a private non-blocking stream of default priority and
+// instantiate it as a radon_graph.
+int capture_graph(const std::function<int(hipStream_t)> &body, radon_graph **out)
 {
-    clear_error();
-    if (!out) return set_error(RADON_EINVAL, "out is NULL");
-    *out = nullptr;
-    SCT_TRY(check_multi(p));
-    if (!rhs || !x) return set_error(RADON_EINVAL, "rhs and x must be non-NULL");
-    if (rhs == x) return set_error(RADON_EINVAL, "x must not alias rhs");
-    if (n_iter < 0) return set_error(RADON_EINVAL, "n_iter must be >= 0 (got %d)", n_iter);
-    if (!(rtol >= 0.0)) return set_error(RADON_EINVAL, "rtol must be >= 0");
-    const Multi &m = *as_multi(p);
-    SCT_TRY(check_ws(ws, ws_bytes, multi_ws_bytes(m, true), "radon_multi_cg_graph"));
-    // capture on a private stream of default priority
     hipStream_t cs = nullptr;
     SCT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -761,10 +753,7 @@ extern "C" int radon_multi_cg_graph(const radon_multi *p, const void *rhs, void 
         (void)hipStreamDestroy(cs);
         return set_error(RADON_EHIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
     }
-    const int rc = multi_dispatch(m, [&](auto *tm, auto *tv) {
-        SCT_TYPES(tm, tv);
-        return multi_cg<TM, TV>(m, rhs, x, n_iter, rtol, ws, info, cs);
-    });
+    const int rc = body(cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
@@ -787,6 +776,31 @@ extern "C" int radon_multi_cg_graph(const radon_multi *p, const void *rhs, void 
     }
     *out = reinterpret_cast<radon_graph *>(G);
     return RADON_OK;
+}
+}  // namespace sct
+
+extern "C" int radon_multi_cg_graph(const radon_multi *p, const void *rhs, void *x, int32_t n_iter,
+                                    double rtol, void *ws, int64_t ws_bytes, radon_cg_info *info,
+                                    radon_graph **out)
+{
+    clear_error();
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    *out = nullptr;
+    SCT_TRY(check_multi(p));
+    if (!rhs || !x) return set_error(RADON_EINVAL, "rhs and x must be non-NULL");
+    if (rhs == x) return set_error(RADON_EINVAL, "x must not alias rhs");
+    if (n_iter < 0) return set_error(RADON_EINVAL, "n_iter must be >= 0 (got %d)", n_iter);
+    if (!(rtol >= 0.0)) return set_error(RADON_EINVAL, "rtol must be >= 0");
+    const Multi &m = *as_multi(p);
+    SCT_TRY(check_ws(ws, ws_bytes, multi_ws_bytes(m, true), "radon_multi_cg_graph"));
+    return capture_graph(
+        [&](hipStream_t cs) {
+            return multi_dispatch(m, [&](auto *tm, auto *tv) {
+                SCT_TYPES(tm, tv);
+                return multi_cg<TM, TV>(m, rhs, x, n_iter, rtol, ws, info, cs);
+            });
+        },
+        out);
 }
 
 extern "C" int radon_graph_launch(const radon_graph *p, void *stream)

@@ -9,6 +9,8 @@
 // FP64 partials in a fixed order, which makes runs bitwise reproducible.
 #include "cg.hpp"
 
+#include <functional>
+
 #include <cmath>
 
 namespace sct {
@@ -1251,6 +1253,41 @@ extern "C" int split_bregman_tv_surrogate(const radon_op *p, const radon_surroga
         SCT_TYPES(tm, tv);
         return sb_typed<TM, TV>(op, &sur, *params, f, mu, batch, ws, info, s);
     });
+}
+
+namespace sct {
+int capture_graph(const std::function<int(hipStream_t)> &body, radon_graph **out);
+}
+
+extern "C" int split_bregman_tv_graph(const radon_op *p, const radon_sb_params *params,
+                                      const void *f, void *mu, int32_t batch, void *ws,
+                                      int64_t ws_bytes, radon_sb_info *info, radon_graph **out)
+{
+    clear_error();
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    *out = nullptr;
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!params) return set_error(RADON_EINVAL, "params is NULL");
+    if (!f || !mu) return set_error(RADON_EINVAL, "f and mu must be non-NULL");
+    if (!(params->lambda > 0.0)) return set_error(RADON_EINVAL, "lambda must be > 0");
+    if (params->n_outer < 0 || params->n_cg < 0)
+        return set_error(RADON_EINVAL, "n_outer and n_cg must be >= 0");
+    if (!(params->tol >= 0.0)) return set_error(RADON_EINVAL, "tol must be >= 0");
+    if (params->flags & ~RADON_SB_WARM)
+        return set_error(RADON_EINVAL, "flags 0x%x: only RADON_SB_WARM can be captured", params->flags);
+    const Op &op = *as_op(p);
+    SCT_TRY(check_ws(ws, ws_bytes, sb_ws_bytes(op, batch), "split_bregman_tv_graph"));
+    if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
+    const radon_sb_params P = *params;
+    return capture_graph(
+        [&](hipStream_t cs) {
+            return dispatch(op, [&](auto *tm, auto *tv) {
+                SCT_TYPES(tm, tv);
+                return sb_typed<TM, TV>(op, nullptr, P, f, mu, batch, ws, info, cs);
+            });
+        },
+        out);
 }
 
 extern "C" int split_bregman_tv_fourier(const radon_fourier *fp, int32_t path,

@@ -154,3 +154,11 @@ def test_fourier_entry_points_validate_without_gpu():
     assert "Fourier operator is NULL" in L.radon_last_error().decode()
     assert L.split_bregman_tv_fourier(None, 0, None, None, None, 1, None, 0, None, None) == -1
     L.radon_fourier_destroy(None)
+
+
+def test_sb_graph_entry_point_validates_without_gpu():
+    L = sct.lib()
+    h = ctypes.c_void_p()
+    assert L.split_bregman_tv_graph(None, None, None, None, 1, None, 0, None, ctypes.byref(h)) == -1
+    assert L.split_bregman_tv_graph(None, None, None, None, 1, None, 0, None, None) == -1
+    assert "out is NULL" in L.radon_last_error().decode()
