@@ -201,6 +201,56 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
     if (threadIdx.x == 0) dst[b] = red[0];
 }
 
+// Line-banded forward: work item (bundle, band) covers the bundle's quads
+// whose first line lies in lines [band L, (band + 1) L).  Items are ordered
+// band-major on each XCD, so the blocks of an XCD gather from one band of
+// the image (or its transpose) at a time and keep it in that XCD's L2 across
+// all angles.  Each item writes its partial sums to part[image][band][ray].
+template <class TM, class TV, int W>
+__global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict__ fb,
+                                                     const int2 *__restrict__ order, int64_t n_order,
+                                                     const uint16_t *__restrict__ idx,
+                                                     const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                     const TV *__restrict__ x, const TV *__restrict__ xT,
+                                                     TV *__restrict__ part, int n, int64_t nn,
+                                                     int64_t rows, int n_bands)
+{
+    const int b = blockIdx.y;
+    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+        const int2 it = order[o];
+        if (it.x < 0) continue;        // padding entry (uniform per block)
+        const FwdBundle d = fb[it.x];
+        const int nq = d.nrows >> 2;
+        const int lo = it.y * kBandLines - d.m0, hi = lo + kBandLines;
+        const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
+        const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
+        fwd_bundle<TM, TV, W, 1>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b) * nn,
+                                 part + (int64_t(b) * n_bands + it.y) * rows, n, nn, rows, 1, tq0,
+                                 tq1);
+    }
+}
+
+// y[ray] = sum of the ray's band partials, in band order (the bands its
+// bundle's quads start in; none for a bundle that misses the image).
+template <class TV>
+__global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restrict__ fb,
+                                                      const TV *__restrict__ part, TV *__restrict__ y,
+                                                      int64_t rows, int nb, int nbpa, int n_bands)
+{
+    const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (ray >= rows) return;
+    const int b = blockIdx.y;
+    const int a = int(ray / nb), bin = int(ray % nb);
+    const FwdBundle d = fb[int64_t(a) * nbpa + bin / kFwdLanes];
+    TV acc = TV(0);
+    if (d.nrows > 0) {
+        const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
+        const TV *p = part + int64_t(b) * n_bands * rows + ray;
+        for (int band = lo; band <= hi; ++band) acc += p[int64_t(band) * rows];
+    }
+    y[int64_t(b) * rows + ray] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -246,10 +296,34 @@ static void fwd_bc(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hi
     else fwd_wbc<TM, TV, 4, BC>(op, x, xT, y, batch, s);
 }
 
+int64_t fwd_part_elems(const Op &op, int batch)
+{
+    if (op.n_bands <= 0 || rhs_chunk(batch, op.tune.fwd_rhs) != 1) return 0;
+    return int64_t(op.n_bands) * op.rows * batch;
+}
+
+template <class TM, class TV, int W>
+static void fwd_band_w(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
+                       hipStream_t s)
+{
+    const int64_t g = op.n_band_order < kPersistentBlocks ? op.n_band_order : kPersistentBlocks;
+    k_fwd_band<TM, TV, W><<<dim3(unsigned(g), unsigned(batch)), 64 * W, 0, s>>>(
+        op.fb, op.fb_band_order, op.n_band_order, op.f_idx, static_cast<const TM *>(op.f_v0),
+        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, op.n_bands);
+    const int nbpa = (op.n_bins + kFwdLanes - 1) / kFwdLanes;
+    k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(batch)), 256, 0, s>>>(
+        op.fb, part, y, op.rows, op.n_bins, nbpa, op.n_bands);
+}
+
 template <class TM, class TV>
-int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
+int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s, TV *part)
 {
     SCT_TRY(check_grid_y(batch));
+    if (part && fwd_part_elems(op, batch) > 0) {
+        if (op.tune.fwd_waves == 2) fwd_band_w<TM, TV, 2>(op, x, xT, y, part, batch, s);
+        else fwd_band_w<TM, TV, 4>(op, x, xT, y, part, batch, s);
+        return check_launch("k_fwd_band");
+    }
     switch (rhs_chunk(batch, op.tune.fwd_rhs)) {
     case 16: fwd_bc<TM, TV, 16>(op, x, xT, y, batch, s); break;
     case 8: fwd_bc<TM, TV, 8>(op, x, xT, y, batch, s); break;
@@ -318,7 +392,8 @@ int launch_sum_partials(const double *part, int64_t count, double *dst, int batc
 template int launch_transpose<float>(const Op &, const float *, float *, int, hipStream_t);
 template int launch_transpose<double>(const Op &, const double *, double *, int, hipStream_t);
 #define SCT_INST(TM, TV)                                                                          \
-    template int launch_fwd<TM, TV>(const Op &, const TV *, const TV *, TV *, int, hipStream_t);  \
+    template int launch_fwd<TM, TV>(const Op &, const TV *, const TV *, TV *, int, hipStream_t,   \
+                                    TV *);                                                        \
     template int launch_adj<TM, TV>(const Op &, const TV *, const TV *, TV *, double, double,     \
                                     double, double *, int, hipStream_t);
 SCT_INST(float, float)
@@ -334,6 +409,7 @@ static int64_t fwd_ws_bytes(const Op &op, int batch)
 {
     Carver c(nullptr);
     if (op.need_T) c.take<char>(int64_t(op.vsize) * op.nn * batch);
+    c.take<char>(int64_t(op.vsize) * fwd_part_elems(op, batch));
     return c.used;
 }
 
@@ -343,6 +419,7 @@ static int64_t normal_ws_bytes(const Op &op, int batch)
     if (op.need_T) c.take<char>(int64_t(op.vsize) * op.nn * batch);
     c.take<char>(int64_t(op.vsize) * op.rows * batch);
     c.take<double>(op.n_ag * batch);
+    c.take<char>(int64_t(op.vsize) * fwd_part_elems(op, batch));
     return c.used;
 }
 
@@ -389,7 +466,9 @@ extern "C" int radon_fwd(const radon_op *p, const void *x, void *y, int32_t batc
             xT = c.take<TV>(op.nn * batch);
             SCT_TRY(launch_transpose<TV>(op, xx, xT, batch, s));
         }
-        return launch_fwd<TM, TV>(op, xx, xT, static_cast<TV *>(y), batch, s);
+        const int64_t pe = fwd_part_elems(op, batch);
+        TV *part = c.take<TV>(pe);
+        return launch_fwd<TM, TV>(op, xx, xT, static_cast<TV *>(y), batch, s, pe ? part : nullptr);
     });
 }
 
@@ -444,9 +523,11 @@ extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, doub
         TV *xT = op.need_T ? c.take<TV>(op.nn * batch) : nullptr;
         TV *y = c.take<TV>(op.rows * batch);
         double *part = c.take<double>(op.n_ag * batch);
+        const int64_t pe = fwd_part_elems(op, batch);
+        TV *ypart = c.take<TV>(pe);
         const TV *xx = static_cast<const TV *>(x);
         if (xT) SCT_TRY(launch_transpose<TV>(op, xx, xT, batch, s));
-        SCT_TRY(launch_fwd<TM, TV>(op, xx, xT, y, batch, s));
+        SCT_TRY(launch_fwd<TM, TV>(op, xx, xT, y, batch, s, pe ? ypart : nullptr));
         SCT_TRY(launch_adj<TM, TV>(op, y, xx, static_cast<TV *>(out), alpha, lambda, sigma,
                                    dot_out ? part : nullptr, batch, s));
         if (dot_out) SCT_TRY(launch_sum_partials(part, adj_blocks(op), dot_out, batch, s));

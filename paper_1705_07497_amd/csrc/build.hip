@@ -564,6 +564,41 @@ static int build_typed(Op &op, const std::vector<double> &cs_host, hipStream_t s
         op.n_order = int64_t(order.size());
         SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.fb_order), 4 * op.n_order));
         SCT_HIP(hipMemcpyAsync(op.fb_order, order.data(), 4 * order.size(), hipMemcpyHostToDevice, st));
+
+        // Line-banded order for large images: (bundle, band) items, band-major
+        // within each gather class, on the same XCD split.  Item (B, band)
+        // exists when a quad of B starts in the band.
+        if (op.n >= kBandMinN) {
+            op.n_bands = (op.n + kBandLines - 1) / kBandLines;
+            std::vector<int2> BV, BH;
+            for (int band = 0; band < op.n_bands; ++band)
+                for (int64_t b = 0; b < op.n_fb; ++b) {
+                    const FwdBundle &d = hb[size_t(b)];
+                    if (d.nrows <= 0) continue;
+                    const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
+                    if (band < lo || band > hi) continue;
+                    (d.horiz ? BH : BV).push_back(make_int2(int(b), band));
+                }
+            const int64_t bv = kv ? (int64_t(BV.size()) + kv - 1) / kv : 0;
+            const int64_t bh = kv < nx ? (int64_t(BH.size()) + (nx - kv) - 1) / (nx - kv) : 0;
+            const int64_t brounds = bv > bh ? bv : bh;
+            std::vector<int2> border(size_t(brounds * nx > 0 ? brounds * nx : 1), make_int2(-1, -1));
+            for (int64_t i = 0; i < brounds * nx; ++i) {
+                const int xcd = int(i % nx);
+                const int64_t j = i / nx;
+                if (xcd < kv) {
+                    const int64_t k = j * kv + xcd;
+                    if (k < int64_t(BV.size())) border[size_t(i)] = BV[size_t(k)];
+                } else {
+                    const int64_t k = j * (nx - kv) + (xcd - kv);
+                    if (k < int64_t(BH.size())) border[size_t(i)] = BH[size_t(k)];
+                }
+            }
+            op.n_band_order = int64_t(border.size());
+            SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.fb_band_order), 8 * op.n_band_order));
+            SCT_HIP(hipMemcpyAsync(op.fb_band_order, border.data(), 8 * border.size(),
+                                   hipMemcpyHostToDevice, st));
+        }
     }
 
     int32_t bad_h = 0;

@@ -31,6 +31,10 @@ constexpr int kFwdLanes = 16;
 // 8-bit offset from the tile's lowest bin at that angle (the tile's bins span
 // at most 13, so bin and bin+1 fall in a 16-bin band starting at the base).
 constexpr int kAdjLanes = 64;
+// Line bands of the forward product: 128 lines of a 2048-pixel FP64 image are
+// 2 MB, half an XCD's L2; images from 2048 pixels on use them.
+constexpr int kBandLines = 128;
+constexpr int kBandMinN = 2048;
 constexpr int kAdjBand = 16;
 
 __host__ __device__ inline int64_t fwd_slot(int64_t off, int t, int r)
@@ -90,6 +94,13 @@ struct Op {
 
     int64_t device_bytes = 0;
     std::vector<void *> owned;       // every hipMalloc of the handle
+
+    // line bands of the forward product for images larger than an XCD's L2:
+    // work items (bundle, band) in band-major order per XCD, one partial sum
+    // per band and ray, added in band order by k_fwd_band_sum
+    int32_t n_bands = 0;             // 0: no banded path
+    int2 *fb_band_order = nullptr;   // (bundle, band), padding (-1, -1)
+    int64_t n_band_order = 0;
 
     radon_tuning tune{2, 0, 4, 8};   // launch tuning (see radon_set_tuning)
 };
@@ -161,8 +172,13 @@ int dispatch(const Op &op, F &&f)
 template <class TV>
 int launch_transpose(const Op &op, const TV *x, TV *xT, int batch, hipStream_t s);
 // y = MR x, gathering from x and (for horizontal bundles) xT.
+// With part (fwd_part_elems(op, batch) elements) the forward runs line-banded
+// when the operator has bands.
 template <class TM, class TV>
-int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s);
+int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s,
+               TV *part = nullptr);
+// Scratch elements of the banded forward for `batch` images (0: not banded).
+int64_t fwd_part_elems(const Op &op, int batch);
 // out = alpha (MR)^T y + lambda K^T K x + sigma x; partial <x, out> per group
 // into part[batch][n_ag] when part != nullptr.  x may be nullptr when
 // lambda == sigma == 0 and part == nullptr.

@@ -104,18 +104,21 @@ __device__ __forceinline__ void fwd_quads(const FwdBundle &d, const u16x4 *__res
 // fwd_bundle does one bundle for up to BC images (img and y point at the
 // first image of the chunk, nbc of them present); k_fwd loops over the
 // bundles of one operator, k_multi_fwd over those of several.
+// [tq0, tq1) restricts the bundle to a range of its quads (the line-banded
+// forward); the default is the whole bundle.
 template <class TM, class TV, int W, int BC>
 __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *__restrict__ idx,
                                            const TM *__restrict__ v0, const TM *__restrict__ v1,
                                            const TV *__restrict__ img, TV *__restrict__ y, int n,
-                                           int64_t nn, int64_t rows, int nbc)
+                                           int64_t nn, int64_t rows, int nbc, int tq0 = 0,
+                                           int tq1 = -1)
 {
     using Q = typename Quad<TM>::type;
     // the wave index is uniform: readfirstlane lets the compiler see that
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
-    const int nq = d.nrows >> 2;
-    const int s0 = (nq * wave) / W, s1 = (nq * (wave + 1)) / W;
+    const int nq = tq1 < 0 ? (d.nrows >> 2) - tq0 : tq1 - tq0;
+    const int s0 = tq0 + (nq * wave) / W, s1 = tq0 + (nq * (wave + 1)) / W;
     const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
     const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
     const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);

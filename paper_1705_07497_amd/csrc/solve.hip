@@ -396,7 +396,8 @@ static void carve_cg(const Op &op, int batch, Carver &c, CgBufs<T> &w)
     w.p = c.take<T>(nb);
     w.pT = op.need_T ? c.take<T>(nb) : nullptr;
     w.q = c.take<T>(nb);
-    w.y = c.take<T>(op.rows * batch);
+    // the forward's band partials (if any) follow y
+    w.y = c.take<T>(op.rows * batch + fwd_part_elems(op, batch));
     // one partial per adjoint workgroup, or per image row (the Fourier-domain
     // operator's row pass)
     w.part_adj = c.take<double>((op.n_ag > op.n ? op.n_ag : int64_t(op.n)) * batch);
@@ -472,7 +473,9 @@ struct ExactA {
     int operator()(const T *p, const T *pT, T *q, T *y, double *part, int batch,
                    hipStream_t s) const
     {
-        SCT_TRY((launch_fwd<TM, T>(op, p, pT, y, batch, s)));
+        // y comes from carve_cg, with room for the band partials after it
+        T *yp = fwd_part_elems(op, batch) ? y + op.rows * batch : nullptr;
+        SCT_TRY((launch_fwd<TM, T>(op, p, pT, y, batch, s, yp)));
         return launch_adj<TM, T>(op, y, p, q, alpha, lambda, sigma, part, batch, s);
     }
 };
