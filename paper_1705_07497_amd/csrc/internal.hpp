@@ -31,10 +31,13 @@ constexpr int kFwdLanes = 16;
 // 8-bit offset from the tile's lowest bin at that angle (the tile's bins span
 // at most 13, so bin and bin+1 fall in a 16-bin band starting at the base).
 constexpr int kAdjLanes = 64;
-// Line bands of the forward product: 128 lines of a 2048-pixel FP64 image are
-// 2 MB, half an XCD's L2; images from 2048 pixels on use them.
+// Line bands of the forward product: 128 lines of a 1024- or 2048-pixel FP64
+// image are 1 or 2 MB of an XCD's 4 MB L2.  Images from 1024 pixels on (8 MB
+// and more per gather class) use them; at 512 the whole image already stays
+// in L2 and the bands only add work (measured on the 512 x 512, 1024 x 1024
+// and 2048 x 2048 operators; 64- and 256-line bands were slower).
 constexpr int kBandLines = 128;
-constexpr int kBandMinN = 2048;
+constexpr int kBandMinN = 1024;
 constexpr int kAdjBand = 16;
 
 __host__ __device__ inline int64_t fwd_slot(int64_t off, int t, int r)
