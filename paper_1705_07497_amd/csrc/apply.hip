@@ -206,16 +206,20 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
 // band-major on each XCD, so the blocks of an XCD gather from one band of
 // the image (or its transpose) at a time and keep it in that XCD's L2 across
 // all angles.  Each item writes its partial sums to part[image][band][ray].
-template <class TM, class TV, int W>
+// Several images: blockIdx.y selects a chunk of up to BC images that share
+// every matrix load, as in k_fwd.
+template <class TM, class TV, int W, int BC>
 __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict__ fb,
                                                      const int2 *__restrict__ order, int64_t n_order,
                                                      const uint16_t *__restrict__ idx,
                                                      const TM *__restrict__ v0, const TM *__restrict__ v1,
                                                      const TV *__restrict__ x, const TV *__restrict__ xT,
                                                      TV *__restrict__ part, int n, int64_t nn,
-                                                     int64_t rows, int n_bands)
+                                                     int64_t rows, int n_bands, int batch)
 {
-    const int b = blockIdx.y;
+    const int b0 = int(blockIdx.y) * BC;
+    const int nbc = min(BC, batch - b0);
+    const int64_t stride = int64_t(n_bands) * rows;   // one image's partials
     for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
         const int2 it = order[o];
         if (it.x < 0) continue;        // padding entry (uniform per block)
@@ -224,9 +228,9 @@ __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict
         const int lo = it.y * kBandLines - d.m0, hi = lo + kBandLines;
         const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
         const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
-        fwd_bundle<TM, TV, W, 1>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b) * nn,
-                                 part + (int64_t(b) * n_bands + it.y) * rows, n, nn, rows, 1, tq0,
-                                 tq1);
+        fwd_bundle<TM, TV, W, BC>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b0) * nn,
+                                  part + int64_t(b0) * stride + int64_t(it.y) * rows, n, nn, stride,
+                                  nbc, tq0, tq1);
     }
 }
 
@@ -296,23 +300,36 @@ static void fwd_bc(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hi
     else fwd_wbc<TM, TV, 4, BC>(op, x, xT, y, batch, s);
 }
 
+// The band partials of a call: one per band, ray and image (none beyond
+// 4 GiB of scratch; such calls keep the bundle order).
 int64_t fwd_part_elems(const Op &op, int batch)
 {
-    if (op.n_bands <= 0 || rhs_chunk(batch, op.tune.fwd_rhs) != 1) return 0;
-    return int64_t(op.n_bands) * op.rows * batch;
+    if (op.n_bands <= 0) return 0;
+    const int64_t e = int64_t(op.n_bands) * op.rows * batch;
+    return e * op.vsize > (int64_t(1) << 32) ? 0 : e;
 }
 
-template <class TM, class TV, int W>
-static void fwd_band_w(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
-                       hipStream_t s)
+template <class TM, class TV, int W, int BC>
+static void fwd_band_wbc(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
+                         hipStream_t s)
 {
     const int64_t g = op.n_band_order < kPersistentBlocks ? op.n_band_order : kPersistentBlocks;
-    k_fwd_band<TM, TV, W><<<dim3(unsigned(g), unsigned(batch)), 64 * W, 0, s>>>(
+    const unsigned chunks = unsigned((batch + BC - 1) / BC);
+    k_fwd_band<TM, TV, W, BC><<<dim3(unsigned(g), chunks), 64 * W, 0, s>>>(
         op.fb, op.fb_band_order, op.n_band_order, op.f_idx, static_cast<const TM *>(op.f_v0),
-        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, op.n_bands);
+        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, op.n_bands,
+        batch);
     const int nbpa = (op.n_bins + kFwdLanes - 1) / kFwdLanes;
     k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(batch)), 256, 0, s>>>(
         op.fb, part, y, op.rows, op.n_bins, nbpa, op.n_bands);
+}
+
+template <class TM, class TV, int BC>
+static void fwd_band_bc(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
+                        hipStream_t s)
+{
+    if (op.tune.fwd_waves == 2) fwd_band_wbc<TM, TV, 2, BC>(op, x, xT, y, part, batch, s);
+    else fwd_band_wbc<TM, TV, 4, BC>(op, x, xT, y, part, batch, s);
 }
 
 template <class TM, class TV>
@@ -320,8 +337,12 @@ int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStr
 {
     SCT_TRY(check_grid_y(batch));
     if (part && fwd_part_elems(op, batch) > 0) {
-        if (op.tune.fwd_waves == 2) fwd_band_w<TM, TV, 2>(op, x, xT, y, part, batch, s);
-        else fwd_band_w<TM, TV, 4>(op, x, xT, y, part, batch, s);
+        switch (rhs_chunk(batch, op.tune.fwd_rhs)) {
+        case 16: fwd_band_bc<TM, TV, 16>(op, x, xT, y, part, batch, s); break;
+        case 8: fwd_band_bc<TM, TV, 8>(op, x, xT, y, part, batch, s); break;
+        case 4: fwd_band_bc<TM, TV, 4>(op, x, xT, y, part, batch, s); break;
+        default: fwd_band_bc<TM, TV, 1>(op, x, xT, y, part, batch, s); break;
+        }
         return check_launch("k_fwd_band");
     }
     switch (rhs_chunk(batch, op.tune.fwd_rhs)) {
