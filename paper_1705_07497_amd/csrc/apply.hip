@@ -234,27 +234,6 @@ __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict
     }
 }
 
-// y[ray] = sum of the ray's band partials, in band order (the bands its
-// bundle's quads start in; none for a bundle that misses the image).
-template <class TV>
-__global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restrict__ fb,
-                                                      const TV *__restrict__ part, TV *__restrict__ y,
-                                                      int64_t rows, int nb, int nbpa, int n_bands)
-{
-    const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (ray >= rows) return;
-    const int b = blockIdx.y;
-    const int a = int(ray / nb), bin = int(ray % nb);
-    const FwdBundle d = fb[int64_t(a) * nbpa + bin / kFwdLanes];
-    TV acc = TV(0);
-    if (d.nrows > 0) {
-        const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
-        const TV *p = part + int64_t(b) * n_bands * rows + ray;
-        for (int band = lo; band <= hi; ++band) acc += p[int64_t(band) * rows];
-    }
-    y[int64_t(b) * rows + ray] = acc;
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------

@@ -29,17 +29,22 @@ struct MultiInst {
     const void *a_v0, *a_v1;
     int64_t n_ag, nn, rows;
     int64_t img_off, sino_off;   // element offsets in the packed image / sinogram vectors
+    int64_t part_off;            // element offset of the band partials (banded forward)
     double alpha, lambda, sigma;
-    int32_t n, n_meas, n_aq, nb, tiles8, tiles32, need_T, pad;
+    int32_t n, n_meas, n_aq, nb, tiles8, tiles32, need_T;
+    int32_t n_bands;             // > 0: the forward entries are (bundle, band) items
 };
 
 struct Multi {
     int count = 0, dtype = 0, vsize = 0;
     std::vector<const Op *> ops;
     std::vector<int64_t> img_off, sino_off;   // host, count + 1 entries
+    std::vector<int64_t> part_off;            // host: band partial offset, -1 if not banded
     MultiInst *inst = nullptr;                // device [count]
-    int2 *fwork = nullptr;                    // device (instance, bundle); bundle -1 = padding
+    int2 *fwork = nullptr;                    // device (instance, bundle); bundle -1 = padding;
+                                              // (instance, band << 24 | bundle) for banded instances
     int64_t n_fwork = 0;
+    int64_t n_fpart = 0;                      // band partial elements of all banded instances
     int64_t *grp_start = nullptr;             // device [count + 1]: first adjoint tile group
     int64_t *t32_start = nullptr;             // device [count + 1]: first 32x32 vector tile
     int64_t *vb_start = nullptr;              // device [count + 1]: first vector block
@@ -117,6 +122,7 @@ __global__ __launch_bounds__(64 * W) void k_multi_fwd(const int2 *__restrict__ w
                                                       const MultiInst *__restrict__ inst,
                                                       const TV *__restrict__ x,
                                                       const TV *__restrict__ xT, TV *__restrict__ y,
+                                                      TV *__restrict__ part,
                                                       uint32_t *__restrict__ tickets)
 {
     __shared__ int64_t next;
@@ -133,11 +139,25 @@ __global__ __launch_bounds__(64 * W) void k_multi_fwd(const int2 *__restrict__ w
         const int2 w = work[o];
         if (w.y >= 0) {   // uniform per block; padding entries carry no bundle
             const MultiInst &I = inst[w.x];
-            const FwdBundle d = I.fb[w.y];
-            fwd_bundle<TM, TV, W, 1>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
-                                     static_cast<const TM *>(I.f_v1),
-                                     (d.horiz ? xT : x) + I.img_off, y + I.sino_off, I.n, I.nn,
-                                     I.rows, 1);
+            if (I.n_bands > 0) {   // a (bundle, band) item, as in k_fwd_band
+                const int band = w.y >> 24;
+                const FwdBundle d = I.fb[w.y & 0xffffff];
+                const int nq = d.nrows >> 2;
+                const int lo = band * kBandLines - d.m0, hi = lo + kBandLines;
+                const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
+                const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
+                fwd_bundle<TM, TV, W, 1>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
+                                         static_cast<const TM *>(I.f_v1),
+                                         (d.horiz ? xT : x) + I.img_off,
+                                         part + I.part_off + int64_t(band) * I.rows, I.n, I.nn,
+                                         I.rows, 1, tq0, tq1);
+            } else {
+                const FwdBundle d = I.fb[w.y];
+                fwd_bundle<TM, TV, W, 1>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
+                                         static_cast<const TM *>(I.f_v1),
+                                         (d.horiz ? xT : x) + I.img_off, y + I.sino_off, I.n, I.nn,
+                                         I.rows, 1);
+            }
         }
         __syncthreads();   // every wave has read `next`
         if (threadIdx.x == 0) next = 8 * int64_t(ticket) + xcd;
@@ -409,6 +429,7 @@ template <class T>
 struct MultiBufs {
     uint32_t *tickets = nullptr;                   // [8 * kTicketStride] forward work counters
     T *xT = nullptr, *y = nullptr;                 // products
+    T *fpart = nullptr;                            // band partials of the banded instances
     T *r = nullptr, *p = nullptr, *pT = nullptr, *q = nullptr;
     double *part_adj = nullptr, *part_t = nullptr, *part_vb = nullptr;
     CgState *st = nullptr;                         // [2][count]
@@ -421,6 +442,7 @@ static void carve_multi(const Multi &m, bool cg, Carver &c, MultiBufs<T> &w)
     const int64_t ni = m.img_off[size_t(m.count)], ns = m.sino_off[size_t(m.count)];
     w.tickets = c.take<uint32_t>(8 * kTicketStride);
     w.y = c.take<T>(ns);
+    w.fpart = c.take<T>(m.n_fpart);
     if (!cg) {
         w.xT = m.any_T ? c.take<T>(ni) : nullptr;
         return;
@@ -450,14 +472,25 @@ static int64_t multi_ws_bytes(const Multi &m, bool cg)
 }
 
 template <class TM, class TV>
-static int multi_launch_fwd(const Multi &m, const TV *x, const TV *xT, TV *y, uint32_t *tickets,
-                            hipStream_t s)
+static int multi_launch_fwd(const Multi &m, const TV *x, const TV *xT, TV *y, TV *fpart,
+                            uint32_t *tickets, hipStream_t s)
 {
     k_multi_reset<<<1, 64, 0, s>>>(tickets);
     SCT_TRY(check_launch("k_multi_reset"));
     k_multi_fwd<TM, TV, kMultiFwdWaves><<<unsigned(fwd_grid(m)), 64 * kMultiFwdWaves, 0, s>>>(
-        m.fwork, m.n_fwork, m.inst, x, xT ? xT : x, y, tickets);
-    return check_launch("k_multi_fwd");
+        m.fwork, m.n_fwork, m.inst, x, xT ? xT : x, y, fpart, tickets);
+    SCT_TRY(check_launch("k_multi_fwd"));
+    // banded instances: their band partials into their sinograms
+    for (int i = 0; i < m.count; ++i) {
+        const Op &op = *m.ops[size_t(i)];
+        if (m.part_off[size_t(i)] < 0) continue;
+        const int nbpa = (op.n_bins + kFwdLanes - 1) / kFwdLanes;
+        k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), 1u), 256, 0, s>>>(
+            op.fb, fpart + m.part_off[size_t(i)], y + m.sino_off[size_t(i)], op.rows, op.n_bins, nbpa,
+            op.n_bands);
+        SCT_TRY(check_launch("k_fwd_band_sum"));
+    }
+    return RADON_OK;
 }
 
 template <class TM, class TV>
@@ -498,12 +531,12 @@ static int multi_products(const Multi &m, int which, const void *in, void *out_v
     TV *out = static_cast<TV *>(out_v);
     if (which == 0) {   // forward
         SCT_TRY(multi_launch_transpose<TV>(m, x, w.xT, s));
-        return multi_launch_fwd<TM, TV>(m, x, w.xT, out, w.tickets, s);
+        return multi_launch_fwd<TM, TV>(m, x, w.xT, out, w.fpart, w.tickets, s);
     }
     if (which == 1)     // adjoint
         return multi_launch_adj<TM, TV>(m, x, nullptr, out, 0, nullptr, s);
     SCT_TRY(multi_launch_transpose<TV>(m, x, w.xT, s));   // normal operator
-    SCT_TRY((multi_launch_fwd<TM, TV>(m, x, w.xT, w.y, w.tickets, s)));
+    SCT_TRY((multi_launch_fwd<TM, TV>(m, x, w.xT, w.y, w.fpart, w.tickets, s)));
     return multi_launch_adj<TM, TV>(m, w.y, x, out, 1, nullptr, s);
 }
 
@@ -529,7 +562,7 @@ static int multi_cg(const Multi &m, const void *rhs_v, void *x_v, int n_iter, do
     SCT_TRY(check_launch("k_multi_begin"));
     for (int it = 0; it < n_iter; ++it) {
         CgState *cur = w.st + int64_t(it & 1) * m.count, *nxt = w.st + int64_t((it + 1) & 1) * m.count;
-        SCT_TRY((multi_launch_fwd<TM, TV>(m, w.p, w.pT, w.y, w.tickets, s)));
+        SCT_TRY((multi_launch_fwd<TM, TV>(m, w.p, w.pT, w.y, w.fpart, w.tickets, s)));
         SCT_TRY((multi_launch_adj<TM, TV>(m, w.y, w.p, w.q, 1, w.part_adj, s)));
         k_multi_gamma<<<unsigned(m.count), 256, 0, s>>>(w.part_adj, adj_grid(m), cur, w.step, rtol);
         SCT_TRY(check_launch("k_multi_gamma"));
@@ -585,6 +618,7 @@ static int build_multi(Multi &m, const radon_op *const *ops, int count, const do
     std::vector<int2> work;
     m.img_off.assign(size_t(count) + 1, 0);
     m.sino_off.assign(size_t(count) + 1, 0);
+    m.part_off.assign(size_t(count), -1);
     int64_t meas_sum = 0;
     for (int i = 0; i < count; ++i) {
         const Op &op = *as_op(ops[i]);
@@ -613,7 +647,16 @@ static int build_multi(Multi &m, const radon_op *const *ops, int count, const do
         I.tiles8 = op.tiles;
         I.tiles32 = tiles_of(op.n);
         I.need_T = op.need_T ? 1 : 0;
-        I.pad = 0;
+        // banded forward for instances that have bands and fit the packed
+        // (band << 24 | bundle) entries
+        const bool banded = op.n_bands > 0 && op.n_bands < 128 && op.n_fb < (int64_t(1) << 24);
+        I.n_bands = banded ? op.n_bands : 0;
+        I.part_off = banded ? m.n_fpart : 0;
+        m.part_off[size_t(i)] = banded ? m.n_fpart : -1;
+        if (banded) {
+            const int64_t al = 256 / m.vsize;
+            m.n_fpart += (int64_t(op.n_bands) * op.rows + al - 1) / al * al;
+        }
         m.any_T = m.any_T || op.need_T;
         meas_sum += op.n_meas;
         // offsets: 256-byte aligned starts keep every instance's loads aligned
@@ -623,9 +666,16 @@ static int build_multi(Multi &m, const radon_op *const *ops, int count, const do
         grp[size_t(i) + 1] = grp[size_t(i)] + op.n_ag;
         t32[size_t(i) + 1] = t32[size_t(i)] + int64_t(I.tiles32) * I.tiles32;
         vbs[size_t(i) + 1] = vbs[size_t(i)] + vec_blocks(op.nn);
-        std::vector<int32_t> order(size_t(op.n_order));
-        SCT_HIP(hipMemcpy(order.data(), op.fb_order, 4 * size_t(op.n_order), hipMemcpyDeviceToHost));
-        for (int32_t b : order) work.push_back(make_int2(i, b));
+        if (banded) {
+            std::vector<int2> border(size_t(op.n_band_order));
+            SCT_HIP(hipMemcpy(border.data(), op.fb_band_order, 8 * size_t(op.n_band_order),
+                              hipMemcpyDeviceToHost));
+            for (const int2 &e : border) work.push_back(make_int2(i, e.x < 0 ? -1 : (e.y << 24) | e.x));
+        } else {
+            std::vector<int32_t> order(size_t(op.n_order));
+            SCT_HIP(hipMemcpy(order.data(), op.fb_order, 4 * size_t(op.n_order), hipMemcpyDeviceToHost));
+            for (int32_t b : order) work.push_back(make_int2(i, b));
+        }
         while (work.size() % 8) work.push_back(make_int2(i, -1));
     }
     m.n_grp = grp[size_t(count)];

@@ -158,6 +158,27 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
     }
 }
 
+// y[ray] = sum of the ray's band partials, in band order (the bands its
+// bundle's quads start in; none for a bundle that misses the image).
+template <class TV>
+__global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restrict__ fb,
+                                                      const TV *__restrict__ part, TV *__restrict__ y,
+                                                      int64_t rows, int nb, int nbpa, int n_bands)
+{
+    const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (ray >= rows) return;
+    const int b = blockIdx.y;
+    const int a = int(ray / nb), bin = int(ray % nb);
+    const FwdBundle d = fb[int64_t(a) * nbpa + bin / kFwdLanes];
+    TV acc = TV(0);
+    if (d.nrows > 0) {
+        const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
+        const TV *p = part + int64_t(b) * n_bands * rows + ray;
+        for (int band = lo; band <= hi; ++band) acc += p[int64_t(band) * rows];
+    }
+    y[int64_t(b) * rows + ray] = acc;
+}
+
 template <class T>
 __device__ inline T ktk_at(const T *__restrict__ xb, int64_t j, int n, T xj)
 {
