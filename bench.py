@@ -143,17 +143,21 @@ def bench_batched(sct, W, torch, dev, vdt):
         del op
         torch.cuda.empty_cache()
     out["mixed_batch_32"] = bench_mixed_batch(sct, W, torch, dev, vdt, t)
+    out["small_batch_64"] = bench_mixed_batch(
+        sct, W, torch, dev, vdt, t,
+        specs=[(n, na, W.n_bins_for(n)) for n, na in W.small_batch_specs(64)], label="small batch")
     out["large_2048_f32"] = bench_large(sct, W, torch, dev, vdt, t)
     return out
 
 
-def bench_mixed_batch(sct, W, torch, dev, vdt, t):
+def bench_mixed_batch(sct, W, torch, dev, vdt, t, specs=None, label="mixed batch"):
     """The uneven batch: 32 instances (N in {256, 512, 1024}, 60-180 angles),
     CG(10) on each instance's split-Bregman inner operator (alpha = 0.01,
     lambda = 1): one captured graph replay (one launch per phase over all
     instances, 6 phases per iteration) against the eager group call and
-    against 32 separate cg_solve calls."""
-    specs = [(n, na, W.n_bins_for(n)) for n, na in W.mixed_batch_specs(32)]
+    against 32 separate cg_solve calls.  `specs` replaces the instance list."""
+    if specs is None:
+        specs = [(n, na, W.n_bins_for(n)) for n, na in W.mixed_batch_specs(32)]
     ops = [sct.RadonOp(n, na, nb, None, dtype=torch.float32, vec_dtype=vdt, device=dev)
            for n, na, nb in specs]
     g = sct.RadonMulti(ops, 0.01, 1.0, 0.0)
@@ -175,7 +179,7 @@ def bench_mixed_batch(sct, W, torch, dev, vdt, t):
 
     tg, te, tl = t(replay, 5), t(eager, 5), t(looped, 2)
     nnz = sum(o.info.nnz for o in ops)
-    print(f"# mixed batch 32 instances: graph {tg * 1e3:.2f} ms, eager group {te * 1e3:.2f} ms, "
+    print(f"# {label} {len(ops)} instances: graph {tg * 1e3:.2f} ms, eager group {te * 1e3:.2f} ms, "
           f"per-instance loop {tl * 1e3:.2f} ms", file=sys.stderr, flush=True)
     out = {"instances": len(ops), "sizes": sorted({s[0] for s in specs}),
            "angles": [min(s[1] for s in specs), max(s[1] for s in specs)], "nnz_total": nnz,

@@ -145,6 +145,19 @@ WORKLOADS = {
 }
 
 
+def small_batch_specs(count: int = 64, seed: int = 0) -> list[tuple[int, int]]:
+    """(N, n_angles) of a batch of small instances, where launches rather
+    than bandwidth bound a per-instance loop: N in {32, 64, 128}, angles in
+    16..64."""
+    rng = np.random.default_rng([seed, 2000])
+    out = []
+    for _ in range(count):
+        n = int(rng.choice([32, 64, 128]))
+        na = int(rng.integers(16, 65))
+        out.append((n, na))
+    return out
+
+
 def mixed_batch_specs(count: int = 32, seed: int = 0) -> list[tuple[int, int]]:
     """(N, n_angles) of the uneven-size instances: N in {256,512,1024}, angles in 60..180."""
     rng = np.random.default_rng([seed, 1000])
