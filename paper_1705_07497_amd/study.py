@@ -17,6 +17,7 @@ data carry 1% noise, and the weights are alpha = 0.01, lambda = 1 (the
 reading used for the 512 x 512 workloads).  Run:
     python -m paper_1705_07497_amd.study [--max-updates 6000] [--d 1 2 4]
                                           [--solvers exact surrogate fusing]
+    python -m paper_1705_07497_amd.study --table1
 """
 from __future__ import annotations
 
@@ -99,6 +100,47 @@ def table(rows) -> str:
     return "\n".join(out)
 
 
+def table1(sct, W, torch, sizes=(128, 256, 512), m_sps=(2, 6, 12)) -> str:
+    """Per-evaluation time of the normal operator in the configurations of
+    Table 1 (N, N pi / 4 evenly spaced angles, M_sp): the Fourier-domain
+    operator through the fused B B^* and through the two gridded transforms,
+    and the sparse Siddon operator of the same geometry (mixed kind)."""
+    dev = torch.device("cuda", 0)
+
+    def timed(fn, reps=50):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows = ["| N | angles | M_sp | fused B B^* (ms) | two transforms (ms) | sparse Siddon (ms) | B B^* GB |",
+            "|---|---|---|---|---|---|---|"]
+    for n in sizes:
+        na = int(round(n * math.pi / 4))
+        op = sct.RadonOp(n, na, W.n_bins_for(n), None, dtype=torch.float32, vec_dtype=torch.float64,
+                         device=dev)
+        x = torch.randn((1, op.nn), dtype=torch.float64, device=dev)
+        out = torch.empty_like(x)
+        t_sp = timed(lambda: op.normal(x, 1.0, 1.0, out=out))
+        for m_sp in m_sps:
+            fo = sct.RadonFourier(op, m_sp)
+            t_f = timed(lambda: fo.normal(x, 1.0, 1.0, path="fused", out=out))
+            t_u = timed(lambda: fo.normal(x, 1.0, 1.0, path="nufft", out=out))
+            rows.append(f"| {n} | {na} | {m_sp} | {t_f:.3f} | {t_u:.3f} | {t_sp:.3f} | "
+                        f"{fo.info['fused_bytes'] / 1e9:.2f} |")
+            print(f"# table 1: n={n} m_sp={m_sp} done", file=sys.stderr, flush=True)
+            del fo
+            torch.cuda.empty_cache()
+        del op
+    return "\n".join(rows)
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--max-updates", type=int, default=6000)
@@ -106,10 +148,15 @@ def main(argv=None) -> None:
     ap.add_argument("--surrogate-radius", type=int, default=3)
     ap.add_argument("--solvers", nargs="+", default=["exact", "surrogate", "fusing"],
                     choices=["exact", "surrogate", "fusing"])
+    ap.add_argument("--table1", action="store_true",
+                    help="per-evaluation times in the configurations of Table 1 instead")
     args = ap.parse_args(argv)
     import torch
     import workloads as W
     import paper_1705_07497_amd as sct
+    if args.table1:
+        print(table1(sct, W, torch))
+        return
     rows = []
     for d in args.d:
         cases = {"exact": (None, False), "surrogate": (args.surrogate_radius, False),
