@@ -150,7 +150,10 @@ int64_t radon_workspace_bytes(const radon_op *op, int32_t which, int32_t batch);
  *   y   device, [batch][n_meas_rays], written.
  *   ws  device workspace of radon_workspace_bytes(op, RADON_WS_FWD, batch)
  *       bytes (holds the transposed image the ray-bundle layout gathers from
- *       for rays closer to horizontal than vertical).
+ *       for rays closer to horizontal than vertical and, for images from
+ *       1024 pixels on, one partial sum per ray and 128-line band: the
+ *       product then runs band by band so each band of the image stays in
+ *       cache, and adds the partials in band order).
  */
 int radon_fwd(const radon_op *op, const void *x, void *y, int32_t batch,
               void *ws, int64_t ws_bytes, void *stream);
@@ -160,7 +163,9 @@ int radon_fwd(const radon_op *op, const void *x, void *y, int32_t batch,
  * images xT[b][ix][iy] = x[b][iy][ix] (device [batch][n*n]; NULL allowed
  * only when no measured angle is closer to horizontal than vertical, see
  * radon_op_info).  This is the single kernel radon_fwd runs after its
- * transpose; CG keeps the transposed direction up to date itself.
+ * transpose (for images below 1024 pixels; larger ones are banded there,
+ * which this call, having no workspace, does not do); CG keeps the
+ * transposed direction up to date itself.
  */
 int radon_fwd_xt(const radon_op *op, const void *x, const void *xT, void *y, int32_t batch,
                  void *stream);
