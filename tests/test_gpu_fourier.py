@@ -3,8 +3,8 @@ eq:fusedop) on the GPU against the oracle.
 
 * the point set, grid and tau agree with the oracle's;
 * the gridded transforms F^* and F match the oracle's (on the tables the kind
-  stores) for several sizes, ragged image sides (n not a power of two, grid
-  above 2n) and half-window widths;
+  stores) for several sizes, ragged image sides (n not a power of two, odd n,
+  grid above 2n), an even bin count and half-window widths;
 * the normal operator through the fused B B^* and through the two transforms
   matches the oracle's, with the K^T K and sigma terms and <x, out>;
 * split Bregman on eq:SBFFT matches the oracle's split Bregman; a batch of
@@ -31,7 +31,7 @@ MODES = {"f64": (torch.float64, torch.float64), "mixed": (torch.float32, torch.f
 # the FP32 kind carries FP32 grids and transforms
 TOL = {"f64": 1e-11, "mixed": 1e-9, "f32": 2e-4}
 
-CASES = [(8, 7, 13, 1), (16, 12, 23, 1), (24, 20, 35, 1), (32, 25, 47, 2)]
+CASES = [(8, 7, 13, 1), (16, 12, 23, 1), (24, 20, 35, 1), (32, 25, 47, 2), (33, 19, 48, 1)]
 
 
 def setup(case, mode, m_sp):
