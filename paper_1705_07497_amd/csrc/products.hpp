@@ -174,7 +174,16 @@ __global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restric
     if (d.nrows > 0) {
         const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
         const TV *p = part + int64_t(b) * n_bands * rows + ray;
-        for (int band = lo; band <= hi; ++band) acc += p[int64_t(band) * rows];
+        // groups of four loads in flight, added in band order
+        int band = lo;
+        for (; band + 3 <= hi; band += 4) {
+            TV t[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t[k] = p[int64_t(band + k) * rows];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += t[k];
+        }
+        for (; band <= hi; ++band) acc += p[int64_t(band) * rows];
     }
     y[int64_t(b) * rows + ray] = acc;
 }
