@@ -85,13 +85,17 @@ __global__ __launch_bounds__(256) void k_cg_begin(const double *__restrict__ par
 // tolerance, or on a breakdown (gamma <= 0 or non-finite); otherwise
 // a = rho / gamma, x += a p, r -= a q and partial <r, r>.  Block 0 records the
 // decision in `step` for the p update.
-template <class T>
-__global__ __launch_bounds__(kVecThreads) void k_cg_xr(
-    T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q,
-    const double *__restrict__ part_adj, int64_t n_adj, const CgState *__restrict__ st,
-    CgStep *__restrict__ step, double rtol, double *__restrict__ part, int64_t nn)
+// FULL: every thread's kPre elements lie in range, so the loads and stores
+// carry no per-element test.  (A branch around each store would make the next
+// store wait until the previous one has completed.)
+template <class T, bool FULL>
+__device__ __forceinline__ void cg_xr_body(T *__restrict__ x, T *__restrict__ r,
+                                           const T *__restrict__ p, const T *__restrict__ q,
+                                           const double *__restrict__ part_adj, int64_t n_adj,
+                                           const CgState *__restrict__ st, CgStep *__restrict__ step,
+                                           double rtol, double *__restrict__ part, int64_t nn,
+                                           double *red)
 {
-    __shared__ double red[kVecThreads];
     const int64_t b = blockIdx.y;
     const int64_t off = b * nn;
     const int64_t i0 = int64_t(blockIdx.x) * kVecThreads + threadIdx.x;
@@ -99,11 +103,11 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_xr(
     // the first kPre elements' operands are loaded before the step length is
     // known, so their latency overlaps the reduction of the partials
     constexpr int kPre = 4;
-    T px[kPre], pp[kPre], pq[kPre], pr[kPre];
+    T px[kPre] = {}, pp[kPre] = {}, pq[kPre] = {}, pr[kPre] = {};
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
         const int64_t i = i0 + k * stride;
-        if (i < nn) {
+        if (FULL || i < nn) {
             const int64_t j = off + i;
             if (x) {
                 px[k] = x[j];
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_xr(
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
         const int64_t i = i0 + k * stride;
-        if (i < nn) {
+        if (FULL || i < nn) {
             const int64_t j = off + i;
             if (x) x[j] = fma(at, pp[k], px[k]);   // a replay only needs r
             const T rn = fma(-at, pq[k], pr[k]);
@@ -149,9 +153,80 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_xr(
     if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = tot;
 }
 
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_cg_xr(
+    T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q,
+    const double *__restrict__ part_adj, int64_t n_adj, const CgState *__restrict__ st,
+    CgStep *__restrict__ step, double rtol, double *__restrict__ part, int64_t nn)
+{
+    __shared__ double red[kVecThreads];
+    const int64_t stride = int64_t(gridDim.x) * kVecThreads;
+    const bool full = int64_t(blockIdx.x) * kVecThreads + (kVecThreads - 1) + 3 * stride < nn;
+    if (full)
+        cg_xr_body<T, true>(x, r, p, q, part_adj, n_adj, st, step, rtol, part, nn, red);
+    else
+        cg_xr_body<T, false>(x, r, p, q, part_adj, n_adj, st, step, rtol, part, nn, red);
+}
+
 // beta = rho'/rho from the update's partials (summed by every block in the
 // same order), p = r + beta p with its transposed copy; block 0 writes the
 // next iteration's state.
+// FULL: the 32 x 32 tile lies inside the image, so the loads and stores carry
+// no per-element test (see cg_xr_body).
+template <class T, bool FULL>
+__device__ __forceinline__ void cg_p_body(const T *__restrict__ r, T *__restrict__ p,
+                                          T *__restrict__ pT, const double *__restrict__ part,
+                                          int64_t n_part, const CgState &c,
+                                          CgState *__restrict__ st_next, bool lead, int n,
+                                          int64_t nn, T (*tile)[33], double *red)
+{
+    const int64_t b = blockIdx.z;
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int64_t off = b * nn;
+    // the tile's r and p are loaded before beta is known (the reduction of
+    // the partials overlaps their latency)
+    T rr[4] = {}, pp[4] = {};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int iy = by + threadIdx.y + 8 * k, ix = bx + threadIdx.x;
+        if (FULL || (iy < n && ix < n)) {
+            const int64_t j = off + int64_t(iy) * n + ix;
+            rr[k] = r[j];
+            pp[k] = p[j];
+        }
+    }
+    double v = 0.0;
+    const int t = threadIdx.y * 32 + threadIdx.x;
+    for (int64_t i = t; i < n_part; i += 256) v += part[b * n_part + i];
+    const double rn = block_sum(v, red);
+    const double beta_d = rn / c.rho;
+    if (lead) {
+        CgState o = c;
+        o.rho = rn;
+        o.iters = c.iters + 1;
+        st_next[b] = o;
+    }
+    const T beta = T(beta_d);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = threadIdx.y + 8 * k;
+        const int iy = by + i, ix = bx + threadIdx.x;
+        if (FULL || (iy < n && ix < n)) {
+            const T v2 = fma(beta, pp[k], rr[k]);
+            p[off + int64_t(iy) * n + ix] = v2;
+            tile[i][threadIdx.x] = v2;
+        }
+    }
+    if (!pT) return;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = threadIdx.y + 8 * k;
+        const int ix = bx + i, iy = by + threadIdx.x;
+        if (FULL || (ix < n && iy < n)) pT[off + int64_t(ix) * n + iy] = tile[threadIdx.x][i];
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_cg_p(const T *__restrict__ r, T *__restrict__ p,
                                               T *__restrict__ pT, const double *__restrict__ part,
@@ -175,49 +250,11 @@ __global__ __launch_bounds__(256) void k_cg_p(const T *__restrict__ r, T *__rest
         }
         return;
     }
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    const int64_t off = b * nn;
-    // the tile's r and p are loaded before beta is known (the reduction of
-    // the partials overlaps their latency)
-    T rr[4], pp[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int iy = by + threadIdx.y + 8 * k, ix = bx + threadIdx.x;
-        if (iy < n && ix < n) {
-            const int64_t j = off + int64_t(iy) * n + ix;
-            rr[k] = r[j];
-            pp[k] = p[j];
-        }
-    }
-    double v = 0.0;
-    const int t = threadIdx.y * 32 + threadIdx.x;
-    for (int64_t i = t; i < n_part; i += 256) v += part[b * n_part + i];
-    const double rn = block_sum(v, red);
-    const double beta_d = rn / c.rho;
-    if (lead) {
-        CgState o = c;
-        o.rho = rn;
-        o.iters = c.iters + 1;
-        st_next[b] = o;
-    }
-    const T beta = T(beta_d);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = threadIdx.y + 8 * k;
-        const int iy = by + i, ix = bx + threadIdx.x;
-        if (iy < n && ix < n) {
-            const int64_t j = off + int64_t(iy) * n + ix;
-            const T v2 = fma(beta, pp[k], rr[k]);
-            p[j] = v2;
-            tile[i][threadIdx.x] = v2;
-        }
-    }
-    if (!pT) return;
-    __syncthreads();
-    for (int i = threadIdx.y; i < 32; i += 8) {
-        const int ix = bx + i, iy = by + threadIdx.x;
-        if (ix < n && iy < n) pT[off + int64_t(ix) * n + iy] = tile[threadIdx.x][i];
-    }
+    const bool full = int(blockIdx.x) * 32 + 32 <= n && int(blockIdx.y) * 32 + 32 <= n;
+    if (full)
+        cg_p_body<T, true>(r, p, pT, part, n_part, c, st_next, lead, n, nn, tile, red);
+    else
+        cg_p_body<T, false>(r, p, pT, part, n_part, c, st_next, lead, n, nn, tile, red);
 }
 
 __global__ void k_cg_info(const CgState *__restrict__ st, radon_cg_info *__restrict__ info, int batch)
