@@ -217,6 +217,30 @@ def test_cg_matches_oracle(mode, tol):
             assert abs(inf["rho"] - hist[-1]) <= {"f64": 1e-6, "mixed": 1e-4}[mode] * hist[-1]
 
 
+@pytest.mark.parametrize("geom", [(100, 30, 143, 3), (33, 10, 47, 2), (64, 45, 91, 1)], ids=_ids)
+@pytest.mark.parametrize("mode,tol", [("f64", 1e-7), ("mixed", 1e-5)])
+def test_cg_matches_oracle_ragged_batch(geom, mode, tol):
+    """CG on three right-hand sides at once.  At 100 and 33 pixels the vector
+    kernels' last blocks and tiles are partial (the path with per-element
+    tests); at 64 every block is whole.  Each image must match its own
+    oracle solve."""
+    n, na, nb, every = geom
+    mask = W.angle_mask(na, every)
+    say(f"cg ragged batch {geom} {mode}")
+    op = make_op(n, na, nb, mask, mode)
+    ref = oracle.OracleOp(n, na, nb, mask, values="f32" if mode == "mixed" else "f64")
+    dtype = MODES[mode][1]
+    rng = np.random.default_rng([3, n])
+    rhs = rounded(rng.standard_normal((3, n * n)), dtype)
+    x, info = op.cg(to_dev(rhs, dtype), 0.5, 1.0, 0.1, n_iter=12)
+    got = host(x)
+    for b in range(3):
+        xo = ref.cg(0.5, 1.0, 0.1, rhs=rhs[b], n_iter=12)[0]
+        assert rel_l2(got[b], xo) <= tol, (geom, mode, b)
+    infos = sct.decode_cg_info(info)
+    assert all(i["iterations"] == 12 and i["breakdown"] == 0 for i in infos)
+
+
 def test_cg_guards_on_gpu():
     n = 8
     op = sct.RadonOp(n, 4, W.n_bins_for(n), np.array([1, 0, 0, 0], np.uint8), dtype=F64)
