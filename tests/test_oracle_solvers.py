@@ -321,3 +321,27 @@ def test_primal_dual_reaches_tv_minimiser_and_warm_start():
     assert np.array_equal(op.pd(f, alpha, tau, sigma, n_outer=0, n_cg=10, u0=u_sb), u_sb)
     assert not np.array_equal(op.pd(f, alpha, tau, sigma, 3, 10, u0=u_sb),
                               op.pd(f, alpha, tau, sigma, 3, 10))
+
+
+def test_results_do_not_depend_on_thread_count():
+    """The oracle's parallel loops only split independent rows, pixels and
+    rays; every sum runs in one thread in a fixed order.  So the build, the
+    products and whole solves are bitwise the same on 1 and 4 threads."""
+    n, na, nb = 48, 30, W.n_bins_for(48)
+    mask = W.angle_mask(na, 2)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(n * n)
+    prev = oracle.set_threads(0)
+    try:
+        out = []
+        for t in (1, 4):
+            oracle.set_threads(t)
+            op = oracle.OracleOp(n, na, nb, mask)
+            f = op.fwd(x)
+            out.append((op.MR.ci.copy(), op.MR.v.copy(), f, op.adj(f), op.normal(x, 0.3, 1.0, 0.1),
+                        op.cg(0.3, 1.0, 0.1, rhs=x, n_iter=15)[0],
+                        op.sb(f, 0.3, 1.0, 4, 5)[0]))
+    finally:
+        oracle.set_threads(prev)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
