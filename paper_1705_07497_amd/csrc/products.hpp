@@ -188,15 +188,20 @@ __global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restric
     y[int64_t(b) * rows + ray] = acc;
 }
 
+// (K^T K x)_j, the Neumann 5-point Laplacian.  The four neighbours load
+// unconditionally, so their latencies overlap: a neighbour missing at the
+// image edge reads x_j itself, whose difference is exactly zero.
 template <class T>
 __device__ inline T ktk_at(const T *__restrict__ xb, int64_t j, int n, T xj)
 {
     const int iy = int(j / n), ix = int(j % n);
+    const T l = xb[ix > 0 ? j - 1 : j], r = xb[ix < n - 1 ? j + 1 : j];
+    const T d = xb[iy > 0 ? j - n : j], u = xb[iy < n - 1 ? j + n : j];
     T k = T(0);
-    if (ix > 0) k += xj - xb[j - 1];
-    if (ix < n - 1) k += xj - xb[j + 1];
-    if (iy > 0) k += xj - xb[j - n];
-    if (iy < n - 1) k += xj - xb[j + n];
+    k += xj - l;
+    k += xj - r;
+    k += xj - d;
+    k += xj - u;
     return k;
 }
 
