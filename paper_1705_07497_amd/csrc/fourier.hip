@@ -63,11 +63,51 @@ __device__ inline int brev(int i, int logM) { return int(__brev(unsigned(i)) >> 
 // order in buf (line stride `stride`); natural order on return.  sign -1 for
 // exp(-2 pi i j k / M) (F_D^*), +1 for its adjoint F_D; tw[k] =
 // exp(-2 pi i k / M), k < M/2.
+// Stages st and st + 1 run as one sweep: a thread takes the four points
+// i0 + {0, 1, 2, 3} hs of a group of 4 hs, applies the stage-st butterflies
+// (twiddle W_2hs^k) to both pairs and then the stage-(st + 1) butterflies
+// (W_4hs^k and W_4hs^(k + hs)) in registers, so each pair of stages costs one
+// pass over LDS and one barrier.  An odd last stage runs alone.
+template <class T>
+__device__ inline C2<T> cmul(C2<T> c, C2<T> w)
+{
+    return C2<T>{c.x * w.x - c.y * w.y, c.x * w.y + c.y * w.x};
+}
+
 template <class T>
 __device__ void lds_fft(C2<T> *buf, int lines, int M, int logM, int stride, const C2<T> *tw, int sign)
 {
-    const int half = M >> 1;
-    for (int st = 0; st < logM; ++st) {
+    const int half = M >> 1, quarter = M >> 2;
+    int st0 = 0;
+    for (; st0 + 1 < logM; st0 += 2) {
+        const int hs = 1 << st0;
+        for (int j = threadIdx.x; j < lines * quarter; j += blockDim.x) {
+            const int line = j >> (logM - 2);
+            const int jj = j & (quarter - 1);
+            const int k = jj & (hs - 1);
+            const int i0 = ((jj >> st0) << (st0 + 2)) + k;
+            C2<T> w1 = tw[k << (logM - 1 - st0)];
+            C2<T> w2 = tw[k << (logM - 2 - st0)];
+            C2<T> w3 = tw[(k + hs) << (logM - 2 - st0)];
+            if (sign > 0) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+                w3.y = -w3.y;
+            }
+            C2<T> *b = buf + line * stride;
+            const C2<T> a0 = b[i0], a1 = b[i0 + hs], a2 = b[i0 + 2 * hs], a3 = b[i0 + 3 * hs];
+            const C2<T> t1 = cmul(a1, w1), t3 = cmul(a3, w1);
+            const C2<T> c0{a0.x + t1.x, a0.y + t1.y}, c1{a0.x - t1.x, a0.y - t1.y};
+            const C2<T> c2{a2.x + t3.x, a2.y + t3.y}, c3{a2.x - t3.x, a2.y - t3.y};
+            const C2<T> u2 = cmul(c2, w2), u3 = cmul(c3, w3);
+            b[i0] = C2<T>{c0.x + u2.x, c0.y + u2.y};
+            b[i0 + 2 * hs] = C2<T>{c0.x - u2.x, c0.y - u2.y};
+            b[i0 + hs] = C2<T>{c1.x + u3.x, c1.y + u3.y};
+            b[i0 + 3 * hs] = C2<T>{c1.x - u3.x, c1.y - u3.y};
+        }
+        __syncthreads();
+    }
+    for (int st = st0; st < logM; ++st) {
         const int hs = 1 << st;
         for (int j = threadIdx.x; j < lines * half; j += blockDim.x) {
             const int line = j >> (logM - 1);
