@@ -22,7 +22,7 @@
 // (s - M/2) 2 pi / M.  The resulting (-1)^m factors and the two 1/M^2 of the
 // trapezoid rule are folded into the per-mode scale a1 = sqrt(pi/tau)
 // exp(m^2 tau) (-1)^m / M applied at zero-padding and at cropping.  The 2-D
-// DFTs are a row pass (radix-2 transforms of whole grid rows in LDS) and two
+// DFTs are a row pass (transforms of whole grid rows in LDS) and two
 // four-step column passes; rows that hold no image mode are skipped on the
 // way in and not written on the way out.
 #include "cg.hpp"
@@ -59,7 +59,8 @@ constexpr int kFftLdsBudget = 80 * 1024;   // per workgroup, two per CU
 
 __device__ inline int brev(int i, int logM) { return int(__brev(unsigned(i)) >> (32 - logM)); }
 
-// In-place radix-2 DFT of `lines` lines of M points held in bit-reversed
+// In-place decimation-in-time DFT (radix-2 butterflies, two stages per pass
+// over LDS) of `lines` lines of M points held in bit-reversed
 // order in buf (line stride `stride`); natural order on return.  sign -1 for
 // exp(-2 pi i j k / M) (F_D^*), +1 for its adjoint F_D; tw[k] =
 // exp(-2 pi i k / M), k < M/2.
