@@ -43,8 +43,12 @@
  *   - Every call returns RADON_OK (0) or a negative status; radon_last_error()
  *     returns a message for the calling thread's most recent failure.
  *   - Argument checks happen before anything is enqueued.
- *   - Results are deterministic: no atomics on any apply path and all
- *     reductions in a fixed order.
+ *   - Results are deterministic: every output element and every partial sum
+ *     is written by exactly one thread, and all reductions run in a fixed
+ *     order.  No floating-point atomics are used.  The one integer atomic on
+ *     an apply path is the work ticket of the mixed-batch forward product
+ *     (radon_multi_apply, radon_multi_cg): it only decides which workgroup
+ *     takes which ray bundle next, never the order of any sum.
  */
 #ifndef SPARSECT_H
 #define SPARSECT_H

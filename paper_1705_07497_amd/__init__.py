@@ -318,6 +318,18 @@ class RadonOp:
             raise SparsectError(f"{name} has {y.numel()} elements, not a multiple of {self.rows}")
         return y.numel() // self.rows
 
+    def _img_n(self, x, b, name):
+        """_img, and the image count must be b (a caller's output buffer)."""
+        got = self._img(x, name)
+        if got != b:
+            raise SparsectError(f"{name} holds {got} images, the call needs {b}")
+
+    def _sino_n(self, y, b, name):
+        """_sino, and the sinogram count must be b."""
+        got = self._sino(y, name)
+        if got != b:
+            raise SparsectError(f"{name} holds {got} sinograms, the call needs {b}")
+
     @staticmethod
     def _p(t):
         return _vp(t.data_ptr()) if t is not None else None
@@ -328,7 +340,7 @@ class RadonOp:
         torch = _torch()
         b = self._img(x)
         y = torch.empty((b, self.rows), dtype=self.dtype, device=self.device) if out is None else out
-        self._sino(y, "out")
+        self._sino_n(y, b, "out")
         ws, nb = self.workspace(WS_FWD, b)
         _check(lib().radon_fwd(self._h, self._p(x), self._p(y), b, self._p(ws), nb, self._stream()))
         return y
@@ -340,7 +352,7 @@ class RadonOp:
         if xT is not None and self._img(xT, "xT") != b:
             raise SparsectError("xT must hold as many images as x")
         y = torch.empty((b, self.rows), dtype=self.dtype, device=self.device) if out is None else out
-        self._sino(y, "out")
+        self._sino_n(y, b, "out")
         _check(lib().radon_fwd_xt(self._h, self._p(x), self._p(xT), self._p(y), b, self._stream()))
         return y
 
@@ -349,7 +361,7 @@ class RadonOp:
         torch = _torch()
         b = self._sino(y)
         x = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
-        self._img(x, "out")
+        self._img_n(x, b, "out")
         _check(lib().radon_adj(self._h, self._p(y), self._p(x), b, self._stream()))
         return x
 
@@ -358,7 +370,7 @@ class RadonOp:
         torch = _torch()
         b = self._img(x)
         o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
-        self._img(o, "out")
+        self._img_n(o, b, "out")
         d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
         ws, nb = self.workspace(WS_NORMAL, b)
         _check(lib().normal_apply(self._h, float(alpha), float(lam), float(sigma), self._p(x),
@@ -370,8 +382,10 @@ class RadonOp:
         """CG on A(alpha, lam, sigma) x = rhs; returns (x, info tensor of CgInfo bytes)."""
         torch = _torch()
         b = self._img(rhs, "rhs")
+        if out is not None:
+            self._img_n(out, b, "out")
         if x0 is not None:
-            self._img(x0, "x0")
+            self._img_n(x0, b, "x0")
             x = x0.clone() if out is None else out.copy_(x0)
         else:
             x = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
@@ -390,6 +404,10 @@ class RadonOp:
         alpha T + lam K^T K (eq:surr_SBupd)."""
         torch = _torch()
         b = self._sino(f, "f")
+        if out is not None:
+            self._img_n(out, b, "out")
+        if mu0 is not None:
+            self._img_n(mu0, b, "mu0")
         flags = 0
         if resume:
             flags |= SB_RESUME
@@ -401,7 +419,7 @@ class RadonOp:
             mu = mu0.clone() if out is None else out.copy_(mu0)
         else:
             mu = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
-        self._img(mu, "mu")
+        self._img_n(mu, b, "mu")
         P = SbParams(float(alpha), float(lam), float(tol), int(n_outer), int(n_cg), flags, 0)
         info = torch.zeros(b * ctypes.sizeof(SbInfo), dtype=torch.uint8, device=self.device)
         ws, nb = self.workspace(WS_SB, b, key=(ws_key, b))
@@ -467,13 +485,17 @@ class RadonOp:
         step = 0.99 / np.sqrt(8.0)
         tau = step if tau is None else tau
         sigma = step if sigma is None else sigma
+        if out is not None:
+            self._img_n(out, b, "out")
+        if mu0 is not None:
+            self._img_n(mu0, b, "mu0")
         flags = 0
         if mu0 is not None:
             flags |= SB_WARM
             mu = mu0.clone() if out is None else out.copy_(mu0)
         else:
             mu = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
-        self._img(mu, "mu")
+        self._img_n(mu, b, "mu")
         P = PdParams(float(alpha), float(tau), float(sigma), int(n_outer), int(n_cg), flags, 0)
         ws, nb = self.workspace(WS_PD, b)
         _check(lib().chambolle_pock_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b,
@@ -529,7 +551,7 @@ class RadonSurrogate:
         torch = _torch()
         b = self.op._img(x)
         o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
-        self.op._img(o, "out")
+        self.op._img_n(o, b, "out")
         d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
         t = (self.n + 31) // 32
         nbytes = 8 * t * t * b if dot else 0
@@ -600,7 +622,8 @@ class RadonFourier:
         torch = _torch()
         b = self.op._img(mu, "mu")
         o = torch.empty((b, self.P, 2), dtype=self.dtype, device=self.device) if out is None else out
-        self._samples(o, "out")
+        if self._samples(o, "out") != b:
+            raise SparsectError(f"out holds {self._samples(o, 'out')} sample sets, the call needs {b}")
         ws, nb = self.workspace(FWS_TRANSFORM, b)
         _check(lib().fourier_fwd(self._h, _vp(mu.data_ptr()), _vp(o.data_ptr()), b, _vp(ws.data_ptr()),
                                  nb, self._stream()))
@@ -611,7 +634,7 @@ class RadonFourier:
         torch = _torch()
         b = self._samples(fhat)
         o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
-        self.op._img(o, "out")
+        self.op._img_n(o, b, "out")
         ws, nb = self.workspace(FWS_TRANSFORM, b)
         _check(lib().fourier_adj(self._h, _vp(fhat.data_ptr()), _vp(o.data_ptr()), float(alpha), b,
                                  _vp(ws.data_ptr()), nb, self._stream()))
@@ -623,7 +646,7 @@ class RadonFourier:
         torch = _torch()
         b = self.op._img(x)
         o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
-        self.op._img(o, "out")
+        self.op._img_n(o, b, "out")
         d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
         ws, nb = self.workspace(FWS_TRANSFORM, b)
         _check(lib().fourier_normal(self._h, self.PATHS[path], float(alpha), float(lam), float(sigma),
@@ -637,6 +660,10 @@ class RadonFourier:
         """Split Bregman TV on eq:SBFFT; returns (mu, info tensor of SbInfo bytes)."""
         torch = _torch()
         b = self._samples(fhat)
+        if out is not None:
+            self.op._img_n(out, b, "out")
+        if mu0 is not None:
+            self.op._img_n(mu0, b, "mu0")
         flags = 0
         if resume:
             flags |= SB_RESUME
@@ -648,7 +675,7 @@ class RadonFourier:
             mu = mu0.clone() if out is None else out.copy_(mu0)
         else:
             mu = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
-        self.op._img(mu, "mu")
+        self.op._img_n(mu, b, "mu")
         P = SbParams(float(alpha), float(lam), float(tol), int(n_outer), int(n_cg), flags, 0)
         info = torch.zeros(b * ctypes.sizeof(SbInfo), dtype=torch.uint8, device=self.device)
         ws, nb = self.workspace(FWS_SB, b)

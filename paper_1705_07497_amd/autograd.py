@@ -30,47 +30,47 @@ def _c(t):
 class RadonFwd(torch.autograd.Function):
     @staticmethod
     def forward(ctx, op, x):
-        ctx.op = op
+        ctx.op, ctx.shape = op, x.shape
         return op.fwd(_c(x))
 
     @staticmethod
     def backward(ctx, gy):
-        return None, ctx.op.adj(_c(gy))
+        return None, ctx.op.adj(_c(gy)).reshape(ctx.shape)
 
 
 class RadonAdj(torch.autograd.Function):
     @staticmethod
     def forward(ctx, op, y):
-        ctx.op = op
+        ctx.op, ctx.shape = op, y.shape
         return op.adj(_c(y))
 
     @staticmethod
     def backward(ctx, gx):
-        return None, ctx.op.fwd(_c(gx))
+        return None, ctx.op.fwd(_c(gx)).reshape(ctx.shape)
 
 
 class NormalOp(torch.autograd.Function):
     @staticmethod
     def forward(ctx, op, x, alpha, lam, sigma):
-        ctx.op, ctx.coef = op, (alpha, lam, sigma)
+        ctx.op, ctx.coef, ctx.shape = op, (alpha, lam, sigma), x.shape
         return op.normal(_c(x), alpha, lam, sigma)
 
     @staticmethod
     def backward(ctx, g):
-        return None, ctx.op.normal(_c(g), *ctx.coef), None, None, None
+        return None, ctx.op.normal(_c(g), *ctx.coef).reshape(ctx.shape), None, None, None
 
 
 class UnrolledCG(torch.autograd.Function):
     @staticmethod
     def forward(ctx, op, rhs, alpha, lam, sigma, n_iter, ckpt):
         x, tape = op.cg_unrolled(_c(rhs), alpha, lam, sigma, n_iter, ckpt)
-        ctx.op, ctx.args, ctx.tape = op, (alpha, lam, sigma, n_iter, ckpt), tape
+        ctx.op, ctx.args, ctx.tape, ctx.shape = op, (alpha, lam, sigma, n_iter, ckpt), tape, rhs.shape
         return x
 
     @staticmethod
     def backward(ctx, gx):
         g = ctx.op.cg_unrolled_vjp(ctx.tape, _c(gx), *ctx.args)
-        return None, g, None, None, None, None, None
+        return None, g.reshape(ctx.shape), None, None, None, None, None
 
 
 def unrolled_cg(op, rhs, alpha: float, lam: float = 0.0, sigma: float = 1.0, n: int = 10,
