@@ -196,6 +196,28 @@ int normal_apply(const radon_op *op, double alpha, double lambda, double sigma,
                  const void *x, void *out, double *dot_out, int32_t batch,
                  void *ws, int64_t ws_bytes, void *stream);
 
+/*
+ * normal_apply_noalloc -- normal_apply for callers that cannot allocate or
+ * pass device memory for a workspace: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same operation, same
+ * kernels and bitwise the same result as normal_apply; the workspace is a
+ * fixed device array of RADON_NOALLOC_SCRATCH_BYTES inside the library, one
+ * copy per GPU, held until the process ends.  The call allocates nothing
+ * (no hipMalloc, no allocating library routine); its first call on a device
+ * looks the array's address up (hipGetSymbolAddress) with that device
+ * current.
+ *   x, out, dot_out, batch, stream: as for normal_apply.
+ * Errors: as normal_apply; RADON_EWORKSPACE when
+ * radon_workspace_bytes(op, RADON_WS_NORMAL, batch) exceeds the fixed size
+ * (nothing is enqueued then).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams, host threads or processes without ordering) race
+ * on it and give wrong results.  Nothing in it needs clearing between calls.
+ */
+#define RADON_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int normal_apply_noalloc(const radon_op *op, double alpha, double lambda, double sigma,
+                         const void *x, void *out, double *dot_out, int32_t batch, void *stream);
+
 typedef struct {
     int32_t iterations;   /* iterations that changed x */
     int32_t breakdown;    /* 0, or k+1 if iteration k met <p, Ap> <= 0 or non-finite */

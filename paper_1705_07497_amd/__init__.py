@@ -101,6 +101,8 @@ SIGNATURES = {
     "radon_fwd_xt": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp]),
     "normal_apply": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
                                     _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
+    "normal_apply_noalloc": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            _vp, _vp, _vp, ctypes.c_int32, _vp]),
     "cg_solve": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _vp,
                                 ctypes.c_int64, _vp, _vp]),
@@ -375,6 +377,20 @@ class RadonOp:
         ws, nb = self.workspace(WS_NORMAL, b)
         _check(lib().normal_apply(self._h, float(alpha), float(lam), float(sigma), self._p(x),
                                   self._p(o), self._p(d), b, self._p(ws), nb, self._stream()))
+        return (o, d) if dot else o
+
+    def normal_noalloc(self, x, alpha: float, lam: float, sigma: float = 0.0, out=None,
+                       dot: bool = False):
+        """normal() through normal_apply_noalloc: no workspace, the library's fixed
+        per-GPU scratch array instead (calls that overlap on one GPU race)."""
+        torch = _torch()
+        b = self._img(x)
+        o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        self._img_n(o, b, "out")
+        d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
+        with torch.cuda.device(self.device):
+            _check(lib().normal_apply_noalloc(self._h, float(alpha), float(lam), float(sigma),
+                                              self._p(x), self._p(o), self._p(d), b, self._stream()))
         return (o, d) if dot else o
 
     def cg(self, rhs, alpha: float, lam: float, sigma: float = 0.0, x0=None, n_iter: int = 10,

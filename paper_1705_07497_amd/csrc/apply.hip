@@ -10,6 +10,8 @@
 // multiplied touch a few cache lines per wave load.
 #include "products.hpp"
 
+#include <mutex>
+
 namespace sct {
 
 // ---------------------------------------------------------------------------
@@ -505,18 +507,11 @@ extern "C" int radon_adj(const radon_op *p, const void *y, void *x, int32_t batc
     });
 }
 
-extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, double sigma,
-                            const void *x, void *out, double *dot_out, int32_t batch, void *ws,
-                            int64_t ws_bytes, void *stream)
+// The body of normal_apply once the arguments are checked; ws holds at least
+// normal_ws_bytes(op, batch) bytes.
+static int normal_apply_into(const Op &op, double alpha, double lambda, double sigma, const void *x,
+                             void *out, double *dot_out, int32_t batch, void *ws, hipStream_t s)
 {
-    clear_error();
-    SCT_TRY(check_op(p));
-    SCT_TRY(check_batch(batch));
-    if (!x || !out) return set_error(RADON_EINVAL, "x and out must be non-NULL");
-    if (x == out) return set_error(RADON_EINVAL, "out must not alias x");
-    const Op &op = *as_op(p);
-    SCT_TRY(check_ws(ws, ws_bytes, normal_ws_bytes(op, batch), "normal_apply"));
-    hipStream_t s = static_cast<hipStream_t>(stream);
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
         Carver c(ws);
@@ -533,6 +528,81 @@ extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, doub
         if (dot_out) SCT_TRY(launch_sum_partials(part, adj_blocks(op), dot_out, batch, s));
         return RADON_OK;
     });
+}
+
+static int check_normal_args(const radon_op *p, const void *x, const void *out, int32_t batch)
+{
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    if (!x || !out) return set_error(RADON_EINVAL, "x and out must be non-NULL");
+    if (x == out) return set_error(RADON_EINVAL, "out must not alias x");
+    return RADON_OK;
+}
+
+extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, double sigma,
+                            const void *x, void *out, double *dot_out, int32_t batch, void *ws,
+                            int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_normal_args(p, x, out, batch));
+    const Op &op = *as_op(p);
+    SCT_TRY(check_ws(ws, ws_bytes, normal_ws_bytes(op, batch), "normal_apply"));
+    return normal_apply_into(op, alpha, lambda, sigma, x, out, dot_out, batch, ws,
+                             static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// normal_apply without a caller workspace: the transposed image, the
+// sinogram, the band partials and the <x, out> partials live in a file-scope
+// device array instead.  Each device that runs the library holds its own copy
+// of the array; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (the array's name in
+// host code is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[RADON_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Address of the current device's copy of `scratch` (looked up once per device).
+static int scratch_for_current_device(void **out)
+{
+    int dev = -1;
+    SCT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(RADON_EUNSUPPORTED, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        SCT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return set_error(RADON_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RADON_OK;
+}
+
+extern "C" int normal_apply_noalloc(const radon_op *p, double alpha, double lambda, double sigma,
+                                    const void *x, void *out, double *dot_out, int32_t batch,
+                                    void *stream)
+{
+    clear_error();
+    SCT_TRY(check_normal_args(p, x, out, batch));
+    const Op &op = *as_op(p);
+    const int64_t need = normal_ws_bytes(op, batch);
+    if (need > RADON_NOALLOC_SCRATCH_BYTES)
+        return set_error(RADON_EWORKSPACE,
+                         "normal_apply_noalloc: this operator needs %lld bytes of scratch for batch %d, "
+                         "beyond the library's fixed %lld; use normal_apply with a workspace",
+                         (long long)need, batch, (long long)RADON_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    SCT_TRY(scratch_for_current_device(&ws));
+    return normal_apply_into(op, alpha, lambda, sigma, x, out, dot_out, batch, ws,
+                             static_cast<hipStream_t>(stream));
 }
 
 extern "C" int radon_set_tuning(radon_op *p, const radon_tuning *t)
