@@ -26,8 +26,10 @@
  *
  * Conventions for every call:
  *   - Device pointers are HIP device memory owned by the caller (the Python
- *     binding passes torch tensors).  The operator's own matrix storage is
- *     allocated by build_radon_csr and released by radon_op_destroy.
+ *     binding passes torch tensors).  The operator's matrix storage is either
+ *     caller-owned (radon_csr_sizes, then build_radon_csr_into fills buffers
+ *     the caller allocated; the handle borrows them) or allocated by
+ *     build_radon_csr and released by radon_op_destroy.
  *   - Compute calls enqueue on `stream` (a hipStream_t; NULL = default
  *     stream) and return without synchronising.  build_radon_csr and the
  *     export calls synchronise.
@@ -80,6 +82,10 @@ typedef struct {
     int32_t dtype;              /* SPARSECT_F32, SPARSECT_F64 or SPARSECT_F32_F64 */
     const uint8_t *measured;    /* host array of n_angles flags (nonzero = measured),
                                    NULL = every angle measured; at least one set */
+    int32_t fwd_bundle;         /* rays per bundle of the forward layout: 16, 32 or
+                                   64 (0 = 16); a layout choice only, the products
+                                   equal each other to rounding */
+    int32_t reserved;
 } radon_geom;
 
 typedef struct {
@@ -95,7 +101,7 @@ typedef struct {
     int32_t needs_transpose;    /* 1: some measured angle is closer to horizontal
                                    than vertical, so the forward product gathers
                                    from the transposed image too */
-    int32_t reserved;
+    int32_t fwd_bundle;         /* rays per forward bundle (16, 32 or 64) */
 } radon_info;
 
 /*
@@ -108,8 +114,9 @@ typedef struct {
  *   - the CSR of MR: row = measured ray (angle-major, bins ascending), entries
  *     in the order the ray visits the pixels (int64 row pointers, int32 pixel
  *     indices);
- *   - a ray-bundle layout of MR for the forward product: groups of 16
- *     adjacent bins of one angle, one slot per (ray, image line along the
+ *   - a ray-bundle layout of MR for the forward product: groups of
+ *     g->fwd_bundle (16, 32 or 64) adjacent bins of one angle, one slot per
+ *     (ray, image line along the
  *     ray's major axis) holding the first pixel's offset along that line
  *     (uint16) and the lengths in that pixel and the next one (a ray meets at
  *     most two adjacent pixels of any line along its major axis);
@@ -127,6 +134,61 @@ typedef struct {
  */
 int build_radon_csr(const radon_geom *g, void *stream, radon_op **out);
 
+/*
+ * Caller-owned storage.  radon_csr_sizes counts the entries of every measured
+ * ray on the GPU and reports the exact sizes of each array of the operator;
+ * the caller allocates them (torch tensors in the Python binding) and
+ * build_radon_csr_into fills them.  The library allocates no device memory
+ * on this path; the handle it returns borrows the buffers, which must stay
+ * allocated and unmodified until radon_op_destroy.  build_radon_csr is the
+ * same build with the library allocating (and the handle owning) the arrays.
+ */
+typedef struct {
+    int64_t n_meas_rays;    /* rows of MR */
+    int64_t nnz;            /* nonzeros of MR (= of (MR)^T); -1 after a size-only query */
+    int64_t fwd_slots;      /* slots of the ray-bundle layout */
+    int64_t adj_slots;      /* slots of the pixel-group layout */
+    int64_t row_ptr_bytes;  /* int64 row pointers [n_meas_rays + 1] */
+    int64_t col_bytes;      /* int32 pixel indices [nnz] */
+    int64_t val_bytes;      /* values [nnz] in the matrix type (FP32, or FP64 for SPARSECT_F64) */
+    int64_t layout_bytes;   /* one block holding the forward and adjoint layouts and their work orders */
+    int64_t ws_bytes;       /* device workspace of radon_csr_sizes and build_radon_csr_into */
+} radon_sizes;
+
+typedef struct {
+    int64_t *row_ptr;       /* device, >= row_ptr_bytes: receives the CSR row pointers */
+    int32_t *col;           /* device, >= col_bytes: receives the CSR pixel indices */
+    void *val;              /* device, >= val_bytes: receives the CSR values */
+    void *layout;           /* device, >= layout_bytes: receives the derived layouts */
+    void *ws;               /* device, >= ws_bytes: scratch during the build only */
+    int64_t row_ptr_bytes, col_bytes, val_bytes, layout_bytes, ws_bytes;
+} radon_buffers;
+
+/*
+ * radon_csr_sizes -- exact storage sizes of the operator of geometry g
+ * (Section 3: the sparse operator is built once for the fixed geometry).
+ *   ws == NULL: host-only query; fills out->n_meas_rays and out->ws_bytes
+ *               (the workspace this call and build_radon_csr_into need),
+ *               sets out->nnz = -1, enqueues nothing.
+ *   ws != NULL: device workspace of >= ws_bytes (256-byte aligned); runs the
+ *               per-ray count kernels on `stream`, synchronises it and fills
+ *               every field of *out.
+ * Errors: as build_radon_csr; RADON_EWORKSPACE for a short workspace.
+ */
+int radon_csr_sizes(const radon_geom *g, void *ws, int64_t ws_bytes, void *stream,
+                     radon_sizes *out);
+
+/*
+ * build_radon_csr_into -- build_radon_csr into caller-allocated buffers (each
+ * pointer 256-byte aligned, each size at least the one radon_csr_sizes
+ * reported for the same geometry).  The contents are bitwise those
+ * build_radon_csr produces.  Synchronises `stream`; the workspace is free
+ * for other use once the call returns.
+ * Errors: as build_radon_csr; RADON_EINVAL for NULL or misaligned buffers;
+ * RADON_EWORKSPACE for a buffer smaller than its array.
+ */
+int build_radon_csr_into(const radon_geom *g, const radon_buffers *b, void *stream, radon_op **out);
+
 /* Sizes of a built operator (host call, no device work). */
 int radon_op_info(const radon_op *op, radon_info *out);
 
@@ -143,6 +205,7 @@ const char *radon_last_error(void);
 #define RADON_WS_CG       2
 #define RADON_WS_SB       3
 #define RADON_WS_PD       4
+#define RADON_WS_TUNE     5
 
 /* Bytes of device workspace a call of the given kind needs for `batch`
  * right-hand sides (>= 0; negative = error status). */
@@ -349,7 +412,8 @@ typedef struct radon_multi radon_multi;   /* opaque group handle */
 typedef struct radon_graph radon_graph;   /* opaque captured-graph handle */
 
 /*
- * radon_multi_create -- group `count` operators (all of one dtype).  The
+ * radon_multi_create -- group `count` operators (all of one dtype and one
+ * forward bundle width).  The
  * group borrows the operators: they must outlive it.  alpha, lambda, sigma:
  * host arrays of `count` weights of each instance's normal operator
  * A_i = alpha_i R_i^T M_i^T M_i R_i + lambda_i K^T K + sigma_i I (Section 2),
@@ -609,6 +673,46 @@ typedef struct {
 
 int radon_set_tuning(radon_op *op, const radon_tuning *t);
 int radon_get_tuning(const radon_op *op, radon_tuning *out);
+
+/*
+ * radon_autotune -- choose op's radon_tuning by timing the candidates on its
+ * own geometry (HIP events on `stream`): waves per forward bundle (2, 4) and
+ * per adjoint tile (1, 2, 4) on one image, then, for batch > 1, the images
+ * sharing each matrix load in each direction (1, 4, 8, 16; at most batch),
+ * one knob at a time in that order.  The forward bundle width is a layout
+ * choice made at build time (radon_geom.fwd_bundle), not tuned here.
+ *   batch       the batch the operator will run at (1 .. 65535).
+ *   ws          device, radon_workspace_bytes(op, RADON_WS_TUNE, batch) bytes
+ *               (test images and products; the values do not matter); may
+ *               be NULL with RADON_TUNE_CACHED_ONLY.
+ *   cache_path  NULL, or a text file of earlier results keyed by GPU
+ *               architecture, geometry, measured angles, dtype, bundle width
+ *               and batch: an entry found there is applied without timing;
+ *               a timed result is appended.
+ *   flags       RADON_TUNE_CACHED_ONLY: apply a cached entry if there is one,
+ *               never time (the tuning stays as it was otherwise).
+ *   source      optional host int: 0 = unchanged, 1 = from the cache,
+ *               2 = timed now.
+ * Synchronises `stream` when it times.  Must not overlap with other work on
+ * the operator.  Errors: RADON_EWORKSPACE, RADON_EINVAL (bad flags, a cache
+ * that cannot be written), RADON_EHIP.
+ */
+#define RADON_TUNE_CACHED_ONLY 1
+int radon_autotune(radon_op *op, int32_t batch, void *ws, int64_t ws_bytes, const char *cache_path,
+                   int32_t flags, void *stream, int32_t *source);
+
+/*
+ * radon_bandwidth_probe -- the practical HBM ceiling the products are
+ * measured against (not part of the method).  RADON_PROBE_COPY: dst = src
+ * (bytes read + bytes written); RADON_PROBE_READ: a read-only pass over src
+ * that leaves one 32-bit xor-sum per workgroup in dst (dst holds 2048 uint32).
+ * Both stream with 16-byte non-temporal loads over a fixed 2048-workgroup
+ * grid.  src, dst: device, 16-byte aligned; bytes: positive multiple of 16.
+ * Asynchronous on `stream`.  Errors: RADON_EINVAL.
+ */
+#define RADON_PROBE_COPY 0
+#define RADON_PROBE_READ 1
+int radon_bandwidth_probe(int32_t mode, const void *src, void *dst, int64_t bytes, void *stream);
 
 /*
  * radon_export_csr -- copy the CSR of MR to host memory (synchronous; for

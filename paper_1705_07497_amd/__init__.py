@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsparsect.so")
 
 F32, F64, F32_F64 = 0, 1, 2
-WS_FWD, WS_NORMAL, WS_CG, WS_SB, WS_PD = 0, 1, 2, 3, 4
+WS_FWD, WS_NORMAL, WS_CG, WS_SB, WS_PD, WS_TUNE = 0, 1, 2, 3, 4, 5
 SB_WARM, SB_RESUME = 1, 2
 
 _vp = ctypes.c_void_p
@@ -36,7 +36,8 @@ class SparsectError(RuntimeError):
 
 class _Geom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("measured", ctypes.POINTER(ctypes.c_uint8))]
+                ("dtype", ctypes.c_int32), ("measured", ctypes.POINTER(ctypes.c_uint8)),
+                ("fwd_bundle", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -45,7 +46,21 @@ class _Info(ctypes.Structure):
                 ("fwd_slots", ctypes.c_int64), ("adj_slots", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("dtype", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
-                ("needs_transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("needs_transpose", ctypes.c_int32), ("fwd_bundle", ctypes.c_int32)]
+
+
+class RadonSizes(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in (
+        "n_meas_rays", "nnz", "fwd_slots", "adj_slots", "row_ptr_bytes", "col_bytes", "val_bytes",
+        "layout_bytes", "ws_bytes")]
+
+
+class RadonBuffers(ctypes.Structure):
+    _fields_ = [("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("layout", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("row_ptr_bytes", ctypes.c_int64), ("col_bytes", ctypes.c_int64),
+                ("val_bytes", ctypes.c_int64), ("layout_bytes", ctypes.c_int64),
+                ("ws_bytes", ctypes.c_int64)]
 
 
 class CgInfo(ctypes.Structure):
@@ -92,6 +107,10 @@ class SbInfo(ctypes.Structure):
 # exported symbols and their signatures (kept in step with include/sparsect.h)
 SIGNATURES = {
     "build_radon_csr": (ctypes.c_int, [ctypes.POINTER(_Geom), _vp, ctypes.POINTER(_vp)]),
+    "radon_csr_sizes": (ctypes.c_int, [ctypes.POINTER(_Geom), _vp, ctypes.c_int64, _vp,
+                                       ctypes.POINTER(RadonSizes)]),
+    "build_radon_csr_into": (ctypes.c_int, [ctypes.POINTER(_Geom), ctypes.POINTER(RadonBuffers), _vp,
+                                            ctypes.POINTER(_vp)]),
     "radon_op_info": (ctypes.c_int, [_vp, ctypes.POINTER(_Info)]),
     "radon_op_destroy": (None, [_vp]),
     "radon_last_error": (ctypes.c_char_p, []),
@@ -110,7 +129,10 @@ SIGNATURES = {
                                         ctypes.c_int64, _vp, _vp]),
     "radon_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "radon_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "radon_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int64, ctypes.c_char_p,
+                                      ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32)]),
     "radon_export_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "radon_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp]),
     "radon_export_adj": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "radon_unrolled_sizes": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int64),
@@ -207,10 +229,22 @@ class RadonOp:
     dtype is the type the matrix values are stored in, vec_dtype the type of
     every vector the calls take and return (default: dtype).  float32 values
     with float64 vectors selects the mixed operator: FP32 matrix stream, FP64
-    vectors and multiply-adds."""
+    vectors and multiply-adds.
+
+    storage="library" lets build_radon_csr allocate the matrix storage (owned
+    by the handle); storage="torch" sizes it with radon_csr_sizes, allocates
+    every array as a torch tensor (kept on the object: .csr() returns the CSR
+    tensors) and fills them with build_radon_csr_into.
+
+    bundle is the forward layout's rays per bundle (16, 32 or 64; 0: the
+    cached choice for this geometry with tuning="cache", else 16).  tuning:
+    "cache" applies cached launch settings for tune_batch images, "tune"
+    chooses the bundle width and times the launch settings now (and caches
+    both), "default" leaves the library defaults."""
 
     def __init__(self, n: int, n_angles: int, n_bins: int, measured=None, dtype=None, device=None,
-                 vec_dtype=None, tuning: str = "cache"):
+                 vec_dtype=None, tuning: str = "cache", storage: str = "library", bundle: int = 0,
+                 tune_batch: int = 1):
         torch = _torch()
         if not torch.cuda.is_available():
             raise SparsectError("no GPU visible: libsparsect runs on AMD Instinct GPUs only")
@@ -234,11 +268,27 @@ class RadonOp:
             if self.measured.shape != (self.n_angles,):
                 raise SparsectError("measured must have one flag per angle")
         self.n_meas = int(np.count_nonzero(self.measured))
+        if tuning not in ("cache", "tune", "default"):
+            raise SparsectError("tuning must be 'cache', 'tune' or 'default'")
+        if bundle == 0 and tuning != "default":
+            from . import autotune
+            if tuning == "tune":
+                bundle = autotune.choose_bundle(self.n, self.n_angles, self.n_bins, self.measured,
+                                                dtype, vec_dtype, self.device, batch=tune_batch)["bundle"]
+            else:
+                bundle = autotune.cached_bundle(self.n, self.n_angles, self.n_bins, self.measured,
+                                                self.kind, self.device) or 0
         g = _Geom(self.n, self.n_angles, self.n_bins, self.kind,
-                  self.measured.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+                  self.measured.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(bundle), 0)
         h = _vp()
+        self._storage = None
         with torch.cuda.device(self.device):
-            _check(lib().build_radon_csr(ctypes.byref(g), self._stream(), ctypes.byref(h)))
+            if storage == "library":
+                _check(lib().build_radon_csr(ctypes.byref(g), self._stream(), ctypes.byref(h)))
+            elif storage == "torch":
+                self._storage = self._build_into(g, h)
+            else:
+                raise SparsectError("storage must be 'library' or 'torch'")
         self._h = h
         inf = _Info()
         _check(lib().radon_op_info(self._h, ctypes.byref(inf)))
@@ -247,15 +297,40 @@ class RadonOp:
         self.rows = inf.n_meas_rays
         self.needs_transpose = bool(inf.needs_transpose)
         self.nn = inf.n_pixels
+        self.bundle = int(inf.fwd_bundle)
         self._ws = {}
         if tuning == "cache":
             from . import autotune
-            autotune.apply_cached(self)
+            autotune.apply_cached(self, batch=tune_batch)
         elif tuning == "tune":
             from . import autotune
-            autotune.autotune(self)
-        elif tuning != "default":
-            raise SparsectError("tuning must be 'cache', 'tune' or 'default'")
+            autotune.autotune(self, batch=tune_batch)
+
+    def _build_into(self, g, h):
+        """radon_csr_sizes, torch allocations, build_radon_csr_into."""
+        torch = _torch()
+        sz = RadonSizes()
+        _check(lib().radon_csr_sizes(ctypes.byref(g), None, 0, self._stream(), ctypes.byref(sz)))
+        ws = torch.empty(max(int(sz.ws_bytes), 1), dtype=torch.uint8, device=self.device)
+        _check(lib().radon_csr_sizes(ctypes.byref(g), _vp(ws.data_ptr()), ws.numel(), self._stream(),
+                                     ctypes.byref(sz)))
+        rp = torch.empty(sz.n_meas_rays + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(sz.nnz, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(sz.nnz, 1), dtype=self.mat_dtype, device=self.device)
+        lay = torch.empty(max(int(sz.layout_bytes), 1), dtype=torch.uint8, device=self.device)
+        b = RadonBuffers(rp.data_ptr(), col.data_ptr(), val.data_ptr(), lay.data_ptr(), ws.data_ptr(),
+                         rp.numel() * 8, col.numel() * 4, val.numel() * val.element_size(),
+                         lay.numel(), ws.numel())
+        _check(lib().build_radon_csr_into(ctypes.byref(g), ctypes.byref(b), self._stream(),
+                                          ctypes.byref(h)))
+        self.sizes = {f: int(getattr(sz, f)) for f, _ in RadonSizes._fields_}
+        return rp, col[:sz.nnz], val[:sz.nnz], lay
+
+    def csr(self):
+        """(row_ptr int64, col int32, val) device tensors of MR when storage="torch"."""
+        if self._storage is None:
+            raise SparsectError("the CSR tensors exist only for storage='torch' (use export_csr)")
+        return self._storage[:3]
 
     @property
     def tuning(self) -> dict:
@@ -895,6 +970,18 @@ class MultiCgGraph:
                 pass
             _lib.radon_graph_destroy(h)
             self._h = None
+
+
+PROBE_COPY, PROBE_READ = 0, 1
+
+
+def bandwidth_probe(mode: int, src, dst, nbytes: int | None = None) -> None:
+    """radon_bandwidth_probe on the current stream: PROBE_COPY copies src into
+    dst, PROBE_READ streams src once (dst: >= 2048 uint32 of results)."""
+    torch = _torch()
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    _check(lib().radon_bandwidth_probe(int(mode), _vp(src.data_ptr()), _vp(dst.data_ptr()), n,
+                                       _vp(torch.cuda.current_stream(src.device).cuda_stream)))
 
 
 def decode_cg_info(info) -> list[dict]:

@@ -1,119 +1,144 @@
-"""Autotuner for the launch parameters of a RadonOp.
+"""Autotuner of a RadonOp: the forward bundle width (a layout chosen at build
+time) and the launch settings (chosen by the library's radon_autotune).
 
-It times the candidate launch shapes of the two products on the operator's own
-geometry (HIP events on the current stream) and keeps the fastest:
-  * waves per ray bundle in the forward product (2 or 4);
-  * waves per 8x8 tile in the adjoint (1, 2 or 4);
-  * images sharing each matrix load in a fused multi-image product, for each
-    direction (1, 4, 8 or 16), timed at the batch size asked for.
-Results are cached as JSON keyed by GPU architecture, geometry (n, angles,
-bins, measured-angle mask) and operator kind, at $SPARSECT_AUTOTUNE_CACHE or
-~/.cache/sparsect/autotune.json.  Tuning never changes what is computed; the
-waves-per-item counts only change how each sum is split (rounding level).
+* Launch settings: radon_autotune times, on the operator's own geometry, the
+  waves per forward bundle (2, 4), the waves per adjoint tile (1, 2, 4) and,
+  at the batch asked for, how many images share each matrix load (1, 4, 8,
+  16), and keeps the fastest.  Its cache is a text file with one
+  ``sparsect-tune <key> ...`` line per (architecture, geometry, measured
+  angles, kind, bundle width, batch).
+* Bundle width: rays per forward bundle, 16, 32 or 64.  Wider bundles make
+  one gather instruction cover more adjacent rays on one image line, at the
+  cost of more padded slots at oblique angles.  ``choose_bundle`` builds the
+  operator once per candidate, tunes its launch settings and times the normal
+  operator; the winner goes into the same file as a ``sparsect-bundle`` line.
+
+The file is $SPARSECT_AUTOTUNE_CACHE, else ~/.cache/sparsect/autotune.txt.
+Tuning never changes what is computed; the waves per item and the bundle
+width only change how each sum is split (rounding level).
 """
 from __future__ import annotations
 
+import ctypes
 import hashlib
-import json
 import os
 
 DEFAULT = {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8}
+BUNDLES = (16, 32, 64)
+SOURCES = {0: "unchanged", 1: "cache", 2: "timed"}
 
 
 def cache_path() -> str:
     return os.environ.get("SPARSECT_AUTOTUNE_CACHE",
-                          os.path.join(os.path.expanduser("~"), ".cache", "sparsect", "autotune.json"))
+                          os.path.join(os.path.expanduser("~"), ".cache", "sparsect", "autotune.txt"))
 
 
-def cache_key(arch: str, n: int, n_angles: int, n_bins: int, measured, kind: int) -> str:
+def geometry_key(arch: str, n: int, n_angles: int, n_bins: int, measured, kind: int) -> str:
+    """Key of a geometry and operator kind (no bundle width, no batch)."""
     mh = hashlib.sha1(bytes(bytearray(int(v) != 0 for v in measured))).hexdigest()[:12]
     return f"{arch}|n{n}|a{n_angles}|b{n_bins}|m{mh}|k{kind}"
 
 
-def _arch(op) -> str:
-    import torch
-    return getattr(torch.cuda.get_device_properties(op.device), "gcnArchName", "unknown")
-
-
-def load_cache(path: str | None = None) -> dict:
-    path = path or cache_path()
+def load_bundles(path: str | None = None) -> dict:
+    """geometry key -> bundle width from the cache file (the last line wins)."""
+    out = {}
     try:
-        with open(path) as fh:
-            data = json.load(fh)
-        return data if isinstance(data, dict) else {}
-    except (OSError, ValueError):
-        return {}
+        with open(path or cache_path()) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) == 3 and parts[0] == "sparsect-bundle" and parts[2].isdigit():
+                    bw = int(parts[2])
+                    if bw in BUNDLES:
+                        out[parts[1]] = bw
+    except OSError:
+        pass
+    return out
 
 
-def store(key: str, entry: dict, path: str | None = None) -> None:
+def store_bundle(key: str, bw: int, path: str | None = None) -> None:
     path = path or cache_path()
-    data = load_cache(path)
-    data[key] = entry
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
-    tmp = path + ".tmp%d" % os.getpid()
-    with open(tmp, "w") as fh:
-        json.dump(data, fh, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+    with open(path, "a") as fh:
+        fh.write(f"sparsect-bundle {key} {int(bw)}\n")
 
 
-def op_key(op) -> str:
-    return cache_key(_arch(op), op.n, op.n_angles, op.n_bins, op.measured, op.kind)
+def device_arch(device) -> str:
+    import torch
+    name = getattr(torch.cuda.get_device_properties(device), "gcnArchName", "unknown")
+    return name.split(":")[0]
 
 
-def apply_cached(op, path: str | None = None) -> bool:
-    """Set the cached tuning for this geometry if there is one."""
-    entry = load_cache(path).get(op_key(op))
-    if not entry:
+def cached_bundle(n, n_angles, n_bins, measured, kind, device, path=None) -> int | None:
+    key = geometry_key(device_arch(device), n, n_angles, n_bins, measured, kind)
+    return load_bundles(path).get(key)
+
+
+def _path_arg(path):
+    return None if path is None else os.fsencode(path)
+
+
+def apply_cached(op, batch: int = 1, path: str | None = None) -> bool:
+    """Apply the cached launch settings of this operator and batch, if any."""
+    from . import _check, _vp, lib
+    src = ctypes.c_int32(0)
+    p = path or cache_path()
+    if not os.path.exists(p):
         return False
-    op.tuning = {k: entry["tuning"].get(k, DEFAULT[k]) for k in DEFAULT}
-    return True
+    _check(lib().radon_autotune(op._h, int(batch), None, 0, _path_arg(p), 1, op._stream(),
+                                ctypes.byref(src)))
+    return src.value == 1
 
 
-def _time(op, fn, reps: int) -> float:
+def autotune(op, batch: int = 16, path: str | None = None, save: bool = True) -> dict:
+    """Time the launch candidates with radon_autotune and set the best on `op`
+    (or apply a cached entry); returns {"tuning", "batch", "source"}."""
     import torch
-    fn()
+
+    from . import WS_TUNE, _check, _vp, lib
+    nbytes = lib().radon_workspace_bytes(op._h, WS_TUNE, int(batch))
+    if nbytes < 0:
+        _check(int(nbytes))
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=op.device)
+    src = ctypes.c_int32(0)
+    p = (path or cache_path()) if save else None
+    if p is not None:
+        os.makedirs(os.path.dirname(p) or ".", exist_ok=True)
     torch.cuda.synchronize(op.device)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        fn()
-    e1.record()
-    torch.cuda.synchronize(op.device)
-    return e0.elapsed_time(e1) / reps / 1e3
+    _check(lib().radon_autotune(op._h, int(batch), _vp(ws.data_ptr()), int(nbytes), _path_arg(p), 0,
+                                op._stream(), ctypes.byref(src)))
+    return {"tuning": op.tuning, "batch": int(batch), "source": SOURCES[src.value]}
 
 
-def autotune(op, batch: int = 16, reps: int = 10, path: str | None = None, save: bool = True) -> dict:
-    """Time the candidates, set the best tuning on `op`, cache and return it."""
+def choose_bundle(n, n_angles, n_bins, measured=None, dtype=None, vec_dtype=None, device=None,
+                  batch: int = 1, reps: int = 10, path: str | None = None, save: bool = True) -> dict:
+    """Build the operator with each bundle width, tune its launch settings,
+    time its normal operator at `batch` and return the fastest width (stored
+    in the cache when save)."""
+    import numpy as np
     import torch
-    x1 = torch.randn((1, op.nn), dtype=op.dtype, device=op.device)
-    y1 = torch.empty((1, op.rows), dtype=op.dtype, device=op.device)
-    o1 = torch.empty_like(x1)
-    best = dict(DEFAULT)
-    timings = {}
 
-    def trial(field, value, fn):
-        op.tuning = {**best, field: value}
-        t = _time(op, fn, reps)
-        timings[f"{field}={value}"] = t
-        return t
-
-    fw = {v: trial("fwd_waves", v, lambda: op.fwd(x1, out=y1)) for v in (2, 4)}
-    best["fwd_waves"] = min(fw, key=fw.get)
-    op.fwd(x1, out=y1)
-    aw = {v: trial("adj_waves", v, lambda: op.adj(y1, out=o1)) for v in (1, 2, 4)}
-    best["adj_waves"] = min(aw, key=aw.get)
-    if batch > 1:
-        xb = torch.randn((batch, op.nn), dtype=op.dtype, device=op.device)
-        yb = torch.empty((batch, op.rows), dtype=op.dtype, device=op.device)
-        ob = torch.empty_like(xb)
-        cands = [c for c in (1, 4, 8, 16) if c <= batch]
-        fr = {c: trial("fwd_rhs", c, lambda: op.fwd(xb, out=yb)) for c in cands}
-        best["fwd_rhs"] = min(fr, key=fr.get)
-        op.fwd(xb, out=yb)
-        ar = {c: trial("adj_rhs", c, lambda: op.adj(yb, out=ob)) for c in cands}
-        best["adj_rhs"] = min(ar, key=ar.get)
-    op.tuning = best
-    entry = {"tuning": best, "batch": batch, "timings_s": timings}
+    from . import RadonOp
+    times = {}
+    kind = None
+    for bw in BUNDLES:
+        op = RadonOp(n, n_angles, n_bins, measured, dtype=dtype, device=device, vec_dtype=vec_dtype,
+                     tuning="default", bundle=bw)
+        kind, dev, meas = op.kind, op.device, op.measured
+        autotune(op, batch=batch, save=False)
+        x = torch.randn((batch, op.nn), dtype=op.dtype, device=op.device)
+        out = torch.empty_like(x)
+        op.normal(x, 1.0, 1.0, out=out)
+        torch.cuda.synchronize(op.device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op.normal(x, 1.0, 1.0, out=out)
+        e1.record()
+        torch.cuda.synchronize(op.device)
+        times[bw] = e0.elapsed_time(e1) / reps / 1e3
+        del op, x, out
+    best = min(times, key=times.get)
     if save:
-        store(op_key(op), entry, path)
-    return entry
+        m = np.ones(n_angles, np.uint8) if measured is None else measured
+        store_bundle(geometry_key(device_arch(dev), n, n_angles, n_bins, m, kind), best, path)
+    return {"bundle": best, "normal_s": times}

@@ -15,7 +15,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsparsect.so")
-SOURCES = ["build.hip", "apply.hip", "solve.hip", "multi.hip", "surrogate.hip", "fourier.hip"]
+SOURCES = ["build.hip", "apply.hip", "fwd16.hip", "fwd32.hip", "fwd64.hip", "solve.hip", "multi.hip",
+           "surrogate.hip", "fourier.hip", "tune.hip", "probe.hip"]
 ARCH = os.environ.get("SPARSECT_ARCH", "gfx950")
 
 COMMON = [

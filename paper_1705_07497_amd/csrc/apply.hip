@@ -18,30 +18,6 @@ namespace sct {
 // kernels
 // ---------------------------------------------------------------------------
 
-// Forward product of one operator: persistent loop over its ray bundles
-// (see fwd_bundle).
-template <class TM, class TV, int W, int BC>
-__global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb,
-                                                const int32_t *__restrict__ order, int64_t n_order,
-                                                const uint16_t *__restrict__ idx,
-                                                const TM *__restrict__ v0, const TM *__restrict__ v1,
-                                                const TV *__restrict__ x, const TV *__restrict__ xT,
-                                                TV *__restrict__ y, int n, int64_t nn, int64_t rows,
-                                                int batch)
-{
-    const int b0 = int(blockIdx.y) * BC;
-    const int nbc = min(BC, batch - b0);
-    // persistent: the grid is a multiple of 8 blocks, so block i stays on XCD
-    // i % 8 and order[] keeps one gather class per XCD
-    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
-        const int B = order[o];
-        if (B < 0) continue;           // padding entry (uniform per block)
-        const FwdBundle d = fb[B];
-        fwd_bundle<TM, TV, W, BC>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b0) * nn,
-                                  y + int64_t(b0) * rows, n, nn, rows, nbc);
-    }
-}
-
 // Single right-hand side version of k_adj below (kept separate: the fused
 // multi-RHS form compiles to a slower loop for one image).
 template <class TM, class T, int W>
@@ -203,39 +179,6 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
     if (threadIdx.x == 0) dst[b] = red[0];
 }
 
-// Line-banded forward: work item (bundle, band) covers the bundle's quads
-// whose first line lies in lines [band L, (band + 1) L).  Items are ordered
-// band-major on each XCD, so the blocks of an XCD gather from one band of
-// the image (or its transpose) at a time and keep it in that XCD's L2 across
-// all angles.  Each item writes its partial sums to part[image][band][ray].
-// Several images: blockIdx.y selects a chunk of up to BC images that share
-// every matrix load, as in k_fwd.
-template <class TM, class TV, int W, int BC>
-__global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict__ fb,
-                                                     const int2 *__restrict__ order, int64_t n_order,
-                                                     const uint16_t *__restrict__ idx,
-                                                     const TM *__restrict__ v0, const TM *__restrict__ v1,
-                                                     const TV *__restrict__ x, const TV *__restrict__ xT,
-                                                     TV *__restrict__ part, int n, int64_t nn,
-                                                     int64_t rows, int n_bands, int batch)
-{
-    const int b0 = int(blockIdx.y) * BC;
-    const int nbc = min(BC, batch - b0);
-    const int64_t stride = int64_t(n_bands) * rows;   // one image's partials
-    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
-        const int2 it = order[o];
-        if (it.x < 0) continue;        // padding entry (uniform per block)
-        const FwdBundle d = fb[it.x];
-        const int nq = d.nrows >> 2;
-        const int lo = it.y * kBandLines - d.m0, hi = lo + kBandLines;
-        const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
-        const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
-        fwd_bundle<TM, TV, W, BC>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b0) * nn,
-                                  part + int64_t(b0) * stride + int64_t(it.y) * rows, n, nn, stride,
-                                  nbc, tq0, tq1);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -264,23 +207,6 @@ static int rhs_chunk(int batch, int limit)
     return 1;
 }
 
-template <class TM, class TV, int W, int BC>
-static void fwd_wbc(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
-{
-    const int64_t g = op.n_order < kPersistentBlocks ? op.n_order : kPersistentBlocks;
-    const unsigned chunks = unsigned((batch + BC - 1) / BC);
-    k_fwd<TM, TV, W, BC><<<dim3(unsigned(g), chunks), 64 * W, 0, s>>>(
-        op.fb, op.fb_order, op.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
-        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, y, op.n, op.nn, op.rows, batch);
-}
-
-template <class TM, class TV, int BC>
-static void fwd_bc(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
-{
-    if (op.tune.fwd_waves == 2) fwd_wbc<TM, TV, 2, BC>(op, x, xT, y, batch, s);
-    else fwd_wbc<TM, TV, 4, BC>(op, x, xT, y, batch, s);
-}
-
 // The band partials of a call: one per band, ray and image (none beyond
 // 4 GiB of scratch; such calls keep the bundle order).
 int64_t fwd_part_elems(const Op &op, int batch)
@@ -290,49 +216,15 @@ int64_t fwd_part_elems(const Op &op, int batch)
     return e * op.vsize > (int64_t(1) << 32) ? 0 : e;
 }
 
-template <class TM, class TV, int W, int BC>
-static void fwd_band_wbc(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
-                         hipStream_t s)
-{
-    const int64_t g = op.n_band_order < kPersistentBlocks ? op.n_band_order : kPersistentBlocks;
-    const unsigned chunks = unsigned((batch + BC - 1) / BC);
-    k_fwd_band<TM, TV, W, BC><<<dim3(unsigned(g), chunks), 64 * W, 0, s>>>(
-        op.fb, op.fb_band_order, op.n_band_order, op.f_idx, static_cast<const TM *>(op.f_v0),
-        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, op.n_bands,
-        batch);
-    const int nbpa = (op.n_bins + kFwdLanes - 1) / kFwdLanes;
-    k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(batch)), 256, 0, s>>>(
-        op.fb, part, y, op.rows, op.n_bins, nbpa, op.n_bands);
-}
-
-template <class TM, class TV, int BC>
-static void fwd_band_bc(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
-                        hipStream_t s)
-{
-    if (op.tune.fwd_waves == 2) fwd_band_wbc<TM, TV, 2, BC>(op, x, xT, y, part, batch, s);
-    else fwd_band_wbc<TM, TV, 4, BC>(op, x, xT, y, part, batch, s);
-}
-
 template <class TM, class TV>
 int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s, TV *part)
 {
     SCT_TRY(check_grid_y(batch));
-    if (part && fwd_part_elems(op, batch) > 0) {
-        switch (rhs_chunk(batch, op.tune.fwd_rhs)) {
-        case 16: fwd_band_bc<TM, TV, 16>(op, x, xT, y, part, batch, s); break;
-        case 8: fwd_band_bc<TM, TV, 8>(op, x, xT, y, part, batch, s); break;
-        case 4: fwd_band_bc<TM, TV, 4>(op, x, xT, y, part, batch, s); break;
-        default: fwd_band_bc<TM, TV, 1>(op, x, xT, y, part, batch, s); break;
-        }
-        return check_launch("k_fwd_band");
+    switch (op.bw) {
+    case 64: return launch_fwd_bw<TM, TV, 64>(op, x, xT, y, batch, s, part);
+    case 32: return launch_fwd_bw<TM, TV, 32>(op, x, xT, y, batch, s, part);
+    default: return launch_fwd_bw<TM, TV, 16>(op, x, xT, y, batch, s, part);
     }
-    switch (rhs_chunk(batch, op.tune.fwd_rhs)) {
-    case 16: fwd_bc<TM, TV, 16>(op, x, xT, y, batch, s); break;
-    case 8: fwd_bc<TM, TV, 8>(op, x, xT, y, batch, s); break;
-    case 4: fwd_bc<TM, TV, 4>(op, x, xT, y, batch, s); break;
-    default: fwd_bc<TM, TV, 1>(op, x, xT, y, batch, s); break;
-    }
-    return check_launch("k_fwd");
 }
 
 int adj_blocks(const Op &op) { return int(op.n_ag < kPersistentBlocks ? op.n_ag : kPersistentBlocks); }
@@ -428,6 +320,7 @@ static int64_t normal_ws_bytes(const Op &op, int batch)
 int64_t cg_ws_bytes(const Op &op, int batch);   // solve.hip
 int64_t sb_ws_bytes(const Op &op, int batch);   // solve.hip
 int64_t pd_ws_bytes(const Op &op, int batch);   // solve.hip
+int64_t tune_ws_bytes(const Op &op, int batch); // tune.hip
 
 }  // namespace sct
 
@@ -445,6 +338,7 @@ extern "C" int64_t radon_workspace_bytes(const radon_op *p, int32_t which, int32
     case RADON_WS_CG: return cg_ws_bytes(op, batch);
     case RADON_WS_SB: return sb_ws_bytes(op, batch);
     case RADON_WS_PD: return pd_ws_bytes(op, batch);
+    case RADON_WS_TUNE: return tune_ws_bytes(op, batch);
     default: return set_error(RADON_EINVAL, "unknown workspace kind %d", which);
     }
 }

@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 
 namespace sct {
 
@@ -221,16 +222,16 @@ __global__ void k_ray_count(const double2 *__restrict__ cs, int n, int nb, int64
     mhi[ray] = hi;
 }
 
-// Bundle extents: union of the major ranges of up to 16 adjacent rays.
+// Bundle extents: union of the major ranges of up to bw adjacent rays.
 __global__ void k_bundle_span(const double2 *__restrict__ cs, const int32_t *__restrict__ mlo,
-                              const int32_t *__restrict__ mhi, int nb, int nbpa, int64_t n_fb,
+                              const int32_t *__restrict__ mhi, int nb, int nbpa, int bw, int64_t n_fb,
                               FwdBundle *__restrict__ fb, int64_t *__restrict__ slots)
 {
     const int64_t B = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (B >= n_fb) return;
     const int a = int(B / nbpa), t = int(B % nbpa);
-    const int ray0 = a * nb + t * kFwdLanes;
-    const int nrays = min(kFwdLanes, nb - t * kFwdLanes);
+    const int ray0 = a * nb + t * bw;
+    const int nrays = min(bw, nb - t * bw);
     int lo = INT_MAX, hi = -1;
     for (int r = 0; r < nrays; ++r) {
         if (mhi[ray0 + r] >= 0) {
@@ -247,21 +248,21 @@ __global__ void k_bundle_span(const double2 *__restrict__ cs, const int32_t *__r
     d.horiz = is_horiz(cs[a].x, cs[a].y) ? 1 : 0;
     d.pad = 0;
     fb[B] = d;
-    slots[B] = int64_t(d.nrows) * kFwdLanes;
+    slots[B] = int64_t(d.nrows) * bw;
 }
 
 __global__ void k_bundle_off(FwdBundle *__restrict__ fb, const int64_t *__restrict__ incl,
-                             int64_t n_fb)
+                             int64_t n_fb, int bw)
 {
     const int64_t B = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (B >= n_fb) return;
-    fb[B].off = incl[B] - int64_t(fb[B].nrows) * kFwdLanes;
+    fb[B].off = incl[B] - int64_t(fb[B].nrows) * bw;
 }
 
 // Pass 2: write the CSR row and the ray's forward slots, and mark the first
 // bin of every (pixel, angle) pair the ray touches.
 template <class T>
-__global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nbpa, int64_t rows,
+__global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nbpa, int bw, int64_t rows,
                            int n_aq, int tiles, const int64_t *__restrict__ rp, int32_t *__restrict__ col,
                            T *__restrict__ val, const FwdBundle *__restrict__ fb,
                            uint16_t *__restrict__ f_idx, T *__restrict__ f_v0,
@@ -274,8 +275,8 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nb
     const double c = cs[a].x, s = cs[a].y;
     const double sb = double(b) - 0.5 * double(nb - 1);
     const bool hz = is_horiz(c, s);
-    const FwdBundle d = fb[int64_t(a) * nbpa + b / kFwdLanes];
-    const int r = b % kFwdLanes;
+    const FwdBundle d = fb[int64_t(a) * nbpa + b / bw];
+    const int r = b % bw;
     int64_t o = rp[ray];
     int cur = -1, nline = 0, q0 = 0, q1 = 0;
     T w0 = T(0), w1 = T(0);
@@ -286,7 +287,7 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nb
             atomicOr(bad, 16);
             return;
         }
-        const int64_t slot = fwd_slot(d.off, cur - d.m0, r);
+        const int64_t slot = fwd_slot(d.off, cur - d.m0, r, bw);
         if (nline == 1) {
             f_idx[slot] = uint16_t(q0);
             f_v0[slot] = w0;
@@ -393,216 +394,249 @@ static int grid_for(int64_t count, int block, unsigned *grid)
     return RADON_OK;
 }
 
-static int op_alloc(Op &op, void **p, int64_t bytes)
-{
-    *p = nullptr;
-    if (bytes <= 0) bytes = 256;
-    SCT_HIP(hipMalloc(p, size_t(bytes)));
-    op.owned.push_back(*p);
-    op.device_bytes += bytes;
-    return RADON_OK;
-}
-
-struct TempBufs {
-    std::vector<void *> ptrs;
-    ~TempBufs()
+// Device memory of a build.  Every array comes either from buffers the caller
+// allocated (build_radon_csr_into: the CSR arrays, one block for the derived
+// layouts and one workspace) or from allocations the handle owns
+// (build_radon_csr); temporaries always come from the workspace.
+struct Carve {
+    char *base = nullptr;
+    int64_t cap = 0, used = 0;
+    const char *what = "";
+    template <class T>
+    int take(T **p, int64_t bytes)
     {
-        for (void *p : ptrs) (void)hipFree(p);
-    }
-    int alloc(void **p, int64_t bytes)
-    {
-        *p = nullptr;
-        if (bytes <= 0) bytes = 256;
-        SCT_HIP(hipMalloc(p, size_t(bytes)));
-        ptrs.push_back(*p);
+        used = (used + 255) & ~int64_t(255);
+        if (bytes <= 0) bytes = 1;
+        if (used + bytes > cap)
+            return set_error(RADON_EWORKSPACE, "%s: %lld bytes are not enough", what, (long long)cap);
+        *p = reinterpret_cast<T *>(base + used);
+        used += bytes;
         return RADON_OK;
     }
 };
 
-static void op_free(Op *op)
+// Sizes known once the rays are counted, and the host-side work orders.
+struct Plan {
+    int64_t nnz = 0, fslots = 0;
+    std::vector<int32_t> order;   // block -> bundle of the forward product
+    std::vector<int2> border;     // (bundle, band) items of the line-banded forward
+};
+
+static int64_t up256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+// Bytes of hipcub's scan temporaries for the two scans of the count phase.
+static int scan_bytes(int64_t rows, int64_t n_fb, size_t *out)
 {
-    if (!op) return;
-    for (void *p : op->owned) (void)hipFree(p);
-    delete op;
+    size_t a = 0, b = 0;
+    int64_t *dummy = nullptr;
+    SCT_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, a, dummy, dummy, rows, hipStream_t(nullptr)));
+    SCT_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, b, dummy, dummy, n_fb, hipStream_t(nullptr)));
+    *out = a > b ? a : b;
+    return RADON_OK;
 }
 
-template <class T>
-static int build_typed(Op &op, const std::vector<double> &cs_host, hipStream_t st)
+static int64_t n_fb_of(const Op &op) { return int64_t(op.n_meas) * ((op.n_bins + op.bw - 1) / op.bw); }
+
+// Workspace of a build: room for the row pointers and the bundle table (the
+// sizes query keeps them there), the count-phase arrays and the temporary
+// first-bin table of the adjoint layout.
+static int build_ws_bytes(const Op &op, int64_t *out)
 {
-    TempBufs tmp;
+    const int64_t rows = op.rows, n_fb = n_fb_of(op);
+    size_t sb = 0;
+    SCT_TRY(scan_bytes(rows, n_fb, &sb));
+    int64_t b = 0;
+    b += up256(8 * (rows + 1));                           // row pointers (sizes query)
+    b += up256(int64_t(sizeof(FwdBundle)) * n_fb);        // bundle table (sizes query)
+    b += up256(16 * int64_t(op.n_meas));                  // (cos, sin)
+    b += up256(8 * rows) + 2 * up256(4 * rows);           // counts, major-line ranges
+    b += up256(4);                                        // error flags
+    b += 2 * up256(8 * n_fb);                             // bundle slots and their scan
+    b += up256(int64_t(sb));                              // scan temporaries
+    b += up256(4 * op.a_slots);                           // first-bin table
+    *out = b;
+    return RADON_OK;
+}
+
+// Bytes of the derived layouts for a plan.
+static int64_t layout_bytes(const Op &op, const Plan &pl)
+{
+    const int64_t es = op.msize;
+    int64_t b = 0;
+    b += up256(int64_t(sizeof(FwdBundle)) * n_fb_of(op));
+    b += up256(2 * pl.fslots) + 2 * up256(es * pl.fslots);
+    b += up256(op.a_slots) + up256(2 * op.n_ag * op.n_aq * 4) + 2 * up256(es * op.a_slots);
+    b += up256(4 * int64_t(pl.order.size())) + up256(8 * int64_t(pl.border.size()));
+    return b;
+}
+
+// Temporaries of the count phase, carved from the workspace after the slots
+// for the row pointers and the bundle table.
+struct CountTmp {
+    double2 *cs = nullptr;
+    int64_t *cnt = nullptr, *bslots = nullptr, *bincl = nullptr;
+    int32_t *mlo = nullptr, *mhi = nullptr, *bad = nullptr;
+    void *scan = nullptr;
+    size_t scan_bytes = 0;
+    int32_t *bin_tmp = nullptr;
+};
+
+// Count phase: entries per ray into rp (scanned into row pointers), the bundle
+// table fb with each bundle's slot offset, then (host) nnz, the forward slot
+// count and the work orders.  Synchronises the stream.
+static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t st, Carve &ws,
+                       int64_t *rp, FwdBundle *fb, CountTmp &t, Plan &pl)
+{
     const int n = op.n, nb = op.n_bins;
     const int64_t rows = op.rows;
     const int blk = 128;
     unsigned g;
+    const int nbpa = (nb + op.bw - 1) / op.bw;
+    op.n_fb = int64_t(op.n_meas) * nbpa;
 
-    double2 *cs = nullptr;
-    SCT_TRY(tmp.alloc(reinterpret_cast<void **>(&cs), int64_t(sizeof(double2)) * op.n_meas));
-    SCT_HIP(hipMemcpyAsync(cs, cs_host.data(), sizeof(double2) * op.n_meas, hipMemcpyHostToDevice, st));
+    SCT_TRY(ws.take(&t.cs, int64_t(sizeof(double2)) * op.n_meas));
+    SCT_TRY(ws.take(&t.cnt, 8 * rows));
+    SCT_TRY(ws.take(&t.mlo, 4 * rows));
+    SCT_TRY(ws.take(&t.mhi, 4 * rows));
+    SCT_TRY(ws.take(&t.bad, 4));
+    SCT_TRY(ws.take(&t.bslots, 8 * op.n_fb));
+    SCT_TRY(ws.take(&t.bincl, 8 * op.n_fb));
+    SCT_TRY(scan_bytes(rows, op.n_fb, &t.scan_bytes));
+    SCT_TRY(ws.take(&t.scan, int64_t(t.scan_bytes)));
+    SCT_TRY(ws.take(&t.bin_tmp, 4 * op.a_slots));
 
-    int64_t *cnt = nullptr;
-    int32_t *mlo = nullptr, *mhi = nullptr, *bad = nullptr;
-    SCT_TRY(tmp.alloc(reinterpret_cast<void **>(&cnt), 8 * rows));
-    SCT_TRY(tmp.alloc(reinterpret_cast<void **>(&mlo), 4 * rows));
-    SCT_TRY(tmp.alloc(reinterpret_cast<void **>(&mhi), 4 * rows));
-    SCT_TRY(tmp.alloc(reinterpret_cast<void **>(&bad), 4));
-    SCT_HIP(hipMemsetAsync(bad, 0, 4, st));
-
+    SCT_HIP(hipMemcpyAsync(t.cs, cs_host.data(), sizeof(double2) * op.n_meas, hipMemcpyHostToDevice, st));
+    SCT_HIP(hipMemsetAsync(t.bad, 0, 4, st));
     SCT_TRY(grid_for(rows, blk, &g));
-    k_ray_count<<<g, blk, 0, st>>>(cs, n, nb, rows, cnt, mlo, mhi);
+    k_ray_count<<<g, blk, 0, st>>>(t.cs, n, nb, rows, t.cnt, t.mlo, t.mhi);
     SCT_TRY(check_launch("k_ray_count"));
 
-    // row pointers
-    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.rp), 8 * (rows + 1)));
-    SCT_HIP(hipMemsetAsync(op.rp, 0, 8, st));
-    size_t scan_bytes = 0, scan_bytes2 = 0;
-    SCT_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, cnt, op.rp + 1, rows, st));
-
-    // bundles
-    const int nbpa = (nb + kFwdLanes - 1) / kFwdLanes;
-    op.n_fb = int64_t(op.n_meas) * nbpa;
-    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.fb), int64_t(sizeof(FwdBundle)) * op.n_fb));
-    int64_t *bslots = nullptr, *bincl = nullptr;
-    SCT_TRY(tmp.alloc(reinterpret_cast<void **>(&bslots), 8 * op.n_fb));
-    SCT_TRY(tmp.alloc(reinterpret_cast<void **>(&bincl), 8 * op.n_fb));
-    SCT_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes2, bslots, bincl, op.n_fb, st));
-    void *scan_tmp = nullptr;
-    SCT_TRY(tmp.alloc(&scan_tmp, int64_t(scan_bytes > scan_bytes2 ? scan_bytes : scan_bytes2)));
-
-    SCT_HIP(hipcub::DeviceScan::InclusiveSum(scan_tmp, scan_bytes, cnt, op.rp + 1, rows, st));
+    SCT_HIP(hipMemsetAsync(rp, 0, 8, st));
+    size_t sb = t.scan_bytes;
+    SCT_HIP(hipcub::DeviceScan::InclusiveSum(t.scan, sb, t.cnt, rp + 1, rows, st));
     SCT_TRY(grid_for(op.n_fb, blk, &g));
-    k_bundle_span<<<g, blk, 0, st>>>(cs, mlo, mhi, nb, nbpa, op.n_fb, op.fb, bslots);
+    k_bundle_span<<<g, blk, 0, st>>>(t.cs, t.mlo, t.mhi, nb, nbpa, op.bw, op.n_fb, fb, t.bslots);
     SCT_TRY(check_launch("k_bundle_span"));
-    size_t sb2 = scan_bytes2;
-    SCT_HIP(hipcub::DeviceScan::InclusiveSum(scan_tmp, sb2, bslots, bincl, op.n_fb, st));
-    k_bundle_off<<<g, blk, 0, st>>>(op.fb, bincl, op.n_fb);
+    sb = t.scan_bytes;
+    SCT_HIP(hipcub::DeviceScan::InclusiveSum(t.scan, sb, t.bslots, t.bincl, op.n_fb, st));
+    k_bundle_off<<<g, blk, 0, st>>>(fb, t.bincl, op.n_fb, op.bw);
     SCT_TRY(check_launch("k_bundle_off"));
 
-    int64_t nnz = 0, fslots = 0;
-    SCT_HIP(hipMemcpyAsync(&nnz, op.rp + rows, 8, hipMemcpyDeviceToHost, st));
-    SCT_HIP(hipMemcpyAsync(&fslots, bincl + (op.n_fb - 1), 8, hipMemcpyDeviceToHost, st));
+    SCT_HIP(hipMemcpyAsync(&pl.nnz, rp + rows, 8, hipMemcpyDeviceToHost, st));
+    SCT_HIP(hipMemcpyAsync(&pl.fslots, t.bincl + (op.n_fb - 1), 8, hipMemcpyDeviceToHost, st));
+    std::vector<FwdBundle> hb(size_t(op.n_fb));
+    SCT_HIP(hipMemcpyAsync(hb.data(), fb, sizeof(FwdBundle) * op.n_fb, hipMemcpyDeviceToHost, st));
     SCT_HIP(hipStreamSynchronize(st));
-    op.nnz = nnz;
-    op.f_slots = fslots;
-    if (nnz >= (int64_t(1) << 40)) return set_error(RADON_EOVERFLOW, "nnz %lld too large", (long long)nnz);
-
-    const int64_t es = sizeof(T);
-    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.col), 4 * nnz));
-    SCT_TRY(op_alloc(op, &op.val, es * nnz));
-    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.f_idx), 2 * fslots));
-    SCT_TRY(op_alloc(op, &op.f_v0, es * fslots));
-    SCT_TRY(op_alloc(op, &op.f_v1, es * fslots));
-    SCT_HIP(hipMemsetAsync(op.f_idx, 0, size_t(2 * fslots), st));
-    SCT_HIP(hipMemsetAsync(op.f_v0, 0, size_t(es * fslots), st));
-    SCT_HIP(hipMemsetAsync(op.f_v1, 0, size_t(es * fslots), st));
-
-    op.tiles = (op.n + 7) / 8;
-    op.n_ag = int64_t(op.tiles) * op.tiles;
-    op.n_aq = (op.n_meas + 3) / 4;
-    op.a_slots = op.n_ag * kAdjLanes * 4 * op.n_aq;
-    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.a_rel), op.a_slots));
-    SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.a_base), 2 * op.n_ag * op.n_aq * 4));
-    SCT_TRY(op_alloc(op, &op.a_v0, es * op.a_slots));
-    SCT_TRY(op_alloc(op, &op.a_v1, es * op.a_slots));
-    SCT_HIP(hipMemsetAsync(op.a_v0, 0, size_t(es * op.a_slots), st));
-    SCT_HIP(hipMemsetAsync(op.a_v1, 0, size_t(es * op.a_slots), st));
-    int32_t *bin_tmp = nullptr;
-    SCT_TRY(tmp.alloc(reinterpret_cast<void **>(&bin_tmp), 4 * op.a_slots));
-    SCT_HIP(hipMemsetAsync(bin_tmp, 0x7f, size_t(4 * op.a_slots), st));   // 0x7f7f7f7f > any bin
-
-    SCT_TRY(grid_for(rows, blk, &g));
-    k_ray_fill<T><<<g, blk, 0, st>>>(cs, n, nb, nbpa, rows, op.n_aq, op.tiles, op.rp, op.col,
-                                     static_cast<T *>(op.val), op.fb, op.f_idx,
-                                     static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), bin_tmp,
-                                     bad);
-    SCT_TRY(check_launch("k_ray_fill"));
-    k_adj_fill<T><<<g, blk, 0, st>>>(n, nb, rows, op.n_aq, op.tiles, op.rp, op.col,
-                                     static_cast<const T *>(op.val), bin_tmp,
-                                     static_cast<T *>(op.a_v0), static_cast<T *>(op.a_v1), bad);
-    SCT_TRY(check_launch("k_adj_fill"));
-    SCT_TRY(grid_for(op.a_slots, 256, &g));
-    SCT_TRY(grid_for(op.n_ag * op.n_aq * 4, 256, &g));
-    k_adj_base<<<g, 256, 0, st>>>(bin_tmp, op.a_base, op.n_ag, op.n_aq);
-    SCT_TRY(check_launch("k_adj_base"));
-    SCT_TRY(grid_for(op.a_slots, 256, &g));
-    k_adj_finish<<<g, 256, 0, st>>>(bin_tmp, op.a_base, op.a_rel, op.a_slots, bad);
-    SCT_TRY(check_launch("k_adj_finish"));
+    if (pl.nnz >= (int64_t(1) << 40)) return set_error(RADON_EOVERFLOW, "nnz %lld too large", (long long)pl.nnz);
 
     // Block order for the forward product.  Workgroups are dispatched to the 8
     // XCDs round-robin by block index; bundles of vertical-class rays (gathering
     // from x) go to one set of XCDs and horizontal-class ones (gathering from
     // the transposed image) to the other, in proportion to their counts.
-    {
-        std::vector<FwdBundle> hb(size_t(op.n_fb));
-        SCT_HIP(hipMemcpyAsync(hb.data(), op.fb, sizeof(FwdBundle) * op.n_fb, hipMemcpyDeviceToHost, st));
-        SCT_HIP(hipStreamSynchronize(st));
-        std::vector<int32_t> V, H;
-        for (int64_t b = 0; b < op.n_fb; ++b)   // empty bundles too: they write zeros
-            (hb[size_t(b)].horiz ? H : V).push_back(int32_t(b));
-        const int nx = 8;
-        int kv = nx;
-        if (!V.empty() && !H.empty()) {
-            kv = int(std::lround(double(nx) * V.size() / double(V.size() + H.size())));
-            kv = kv < 1 ? 1 : (kv > nx - 1 ? nx - 1 : kv);
-        } else if (V.empty()) {
-            kv = 0;
+    std::vector<int32_t> V, H;
+    for (int64_t b = 0; b < op.n_fb; ++b)   // empty bundles too: they write zeros
+        (hb[size_t(b)].horiz ? H : V).push_back(int32_t(b));
+    const int nx = 8;
+    int kv = nx;
+    if (!V.empty() && !H.empty()) {
+        kv = int(std::lround(double(nx) * V.size() / double(V.size() + H.size())));
+        kv = kv < 1 ? 1 : (kv > nx - 1 ? nx - 1 : kv);
+    } else if (V.empty()) {
+        kv = 0;
+    }
+    const int64_t rv = kv ? (int64_t(V.size()) + kv - 1) / kv : 0;
+    const int64_t rh = kv < nx ? (int64_t(H.size()) + (nx - kv) - 1) / (nx - kv) : 0;
+    const int64_t rounds = rv > rh ? rv : rh;
+    pl.order.assign(size_t(rounds * nx > 0 ? rounds * nx : 1), -1);
+    for (int64_t i = 0; i < rounds * nx; ++i) {
+        const int xcd = int(i % nx);
+        const int64_t j = i / nx;
+        if (xcd < kv) {
+            const int64_t k = j * kv + xcd;
+            if (k < int64_t(V.size())) pl.order[size_t(i)] = V[size_t(k)];
+        } else {
+            const int64_t k = j * (nx - kv) + (xcd - kv);
+            if (k < int64_t(H.size())) pl.order[size_t(i)] = H[size_t(k)];
         }
-        const int64_t rv = kv ? (int64_t(V.size()) + kv - 1) / kv : 0;
-        const int64_t rh = kv < nx ? (int64_t(H.size()) + (nx - kv) - 1) / (nx - kv) : 0;
-        const int64_t rounds = rv > rh ? rv : rh;
-        std::vector<int32_t> order(size_t(rounds * nx > 0 ? rounds * nx : 1), -1);
-        for (int64_t i = 0; i < rounds * nx; ++i) {
+    }
+
+    // Line-banded order for large images: (bundle, band) items, band-major
+    // within each gather class, on the same XCD split.  Item (B, band)
+    // exists when a quad of B starts in the band.
+    pl.border.clear();
+    if (op.n >= kBandMinN) {
+        const int n_bands = (op.n + kBandLines - 1) / kBandLines;
+        std::vector<int2> BV, BH;
+        for (int band = 0; band < n_bands; ++band)
+            for (int64_t b = 0; b < op.n_fb; ++b) {
+                const FwdBundle &d = hb[size_t(b)];
+                if (d.nrows <= 0) continue;
+                const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
+                if (band < lo || band > hi) continue;
+                (d.horiz ? BH : BV).push_back(make_int2(int(b), band));
+            }
+        const int64_t bv = kv ? (int64_t(BV.size()) + kv - 1) / kv : 0;
+        const int64_t bh = kv < nx ? (int64_t(BH.size()) + (nx - kv) - 1) / (nx - kv) : 0;
+        const int64_t brounds = bv > bh ? bv : bh;
+        pl.border.assign(size_t(brounds * nx > 0 ? brounds * nx : 1), make_int2(-1, -1));
+        for (int64_t i = 0; i < brounds * nx; ++i) {
             const int xcd = int(i % nx);
             const int64_t j = i / nx;
             if (xcd < kv) {
                 const int64_t k = j * kv + xcd;
-                if (k < int64_t(V.size())) order[size_t(i)] = V[size_t(k)];
+                if (k < int64_t(BV.size())) pl.border[size_t(i)] = BV[size_t(k)];
             } else {
                 const int64_t k = j * (nx - kv) + (xcd - kv);
-                if (k < int64_t(H.size())) order[size_t(i)] = H[size_t(k)];
+                if (k < int64_t(BH.size())) pl.border[size_t(i)] = BH[size_t(k)];
             }
-        }
-        op.n_order = int64_t(order.size());
-        SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.fb_order), 4 * op.n_order));
-        SCT_HIP(hipMemcpyAsync(op.fb_order, order.data(), 4 * order.size(), hipMemcpyHostToDevice, st));
-
-        // Line-banded order for large images: (bundle, band) items, band-major
-        // within each gather class, on the same XCD split.  Item (B, band)
-        // exists when a quad of B starts in the band.
-        if (op.n >= kBandMinN) {
-            op.n_bands = (op.n + kBandLines - 1) / kBandLines;
-            std::vector<int2> BV, BH;
-            for (int band = 0; band < op.n_bands; ++band)
-                for (int64_t b = 0; b < op.n_fb; ++b) {
-                    const FwdBundle &d = hb[size_t(b)];
-                    if (d.nrows <= 0) continue;
-                    const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
-                    if (band < lo || band > hi) continue;
-                    (d.horiz ? BH : BV).push_back(make_int2(int(b), band));
-                }
-            const int64_t bv = kv ? (int64_t(BV.size()) + kv - 1) / kv : 0;
-            const int64_t bh = kv < nx ? (int64_t(BH.size()) + (nx - kv) - 1) / (nx - kv) : 0;
-            const int64_t brounds = bv > bh ? bv : bh;
-            std::vector<int2> border(size_t(brounds * nx > 0 ? brounds * nx : 1), make_int2(-1, -1));
-            for (int64_t i = 0; i < brounds * nx; ++i) {
-                const int xcd = int(i % nx);
-                const int64_t j = i / nx;
-                if (xcd < kv) {
-                    const int64_t k = j * kv + xcd;
-                    if (k < int64_t(BV.size())) border[size_t(i)] = BV[size_t(k)];
-                } else {
-                    const int64_t k = j * (nx - kv) + (xcd - kv);
-                    if (k < int64_t(BH.size())) border[size_t(i)] = BH[size_t(k)];
-                }
-            }
-            op.n_band_order = int64_t(border.size());
-            SCT_TRY(op_alloc(op, reinterpret_cast<void **>(&op.fb_band_order), 8 * op.n_band_order));
-            SCT_HIP(hipMemcpyAsync(op.fb_band_order, border.data(), 8 * border.size(),
-                                   hipMemcpyHostToDevice, st));
         }
     }
+    return RADON_OK;
+}
+
+// Fill phase: the CSR entries, both slotted layouts and the work orders, into
+// the arrays already set on op (rp, col, val, fb and the layout arrays).
+// Synchronises the stream.
+template <class T>
+static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
+{
+    const int n = op.n, nb = op.n_bins;
+    const int64_t rows = op.rows;
+    const int blk = 128;
+    const int nbpa = (nb + op.bw - 1) / op.bw;
+    const int64_t es = sizeof(T);
+    unsigned g;
+    SCT_HIP(hipMemsetAsync(op.f_idx, 0, size_t(2 * op.f_slots), st));
+    SCT_HIP(hipMemsetAsync(op.f_v0, 0, size_t(es * op.f_slots), st));
+    SCT_HIP(hipMemsetAsync(op.f_v1, 0, size_t(es * op.f_slots), st));
+    SCT_HIP(hipMemsetAsync(op.a_v0, 0, size_t(es * op.a_slots), st));
+    SCT_HIP(hipMemsetAsync(op.a_v1, 0, size_t(es * op.a_slots), st));
+    SCT_HIP(hipMemsetAsync(t.bin_tmp, 0x7f, size_t(4 * op.a_slots), st));   // 0x7f7f7f7f > any bin
+
+    SCT_TRY(grid_for(rows, blk, &g));
+    k_ray_fill<T><<<g, blk, 0, st>>>(t.cs, n, nb, nbpa, op.bw, rows, op.n_aq, op.tiles, op.rp, op.col,
+                                     static_cast<T *>(op.val), op.fb, op.f_idx,
+                                     static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), t.bin_tmp,
+                                     t.bad);
+    SCT_TRY(check_launch("k_ray_fill"));
+    k_adj_fill<T><<<g, blk, 0, st>>>(n, nb, rows, op.n_aq, op.tiles, op.rp, op.col,
+                                     static_cast<const T *>(op.val), t.bin_tmp,
+                                     static_cast<T *>(op.a_v0), static_cast<T *>(op.a_v1), t.bad);
+    SCT_TRY(check_launch("k_adj_fill"));
+    SCT_TRY(grid_for(op.n_ag * op.n_aq * 4, 256, &g));
+    k_adj_base<<<g, 256, 0, st>>>(t.bin_tmp, op.a_base, op.n_ag, op.n_aq);
+    SCT_TRY(check_launch("k_adj_base"));
+    SCT_TRY(grid_for(op.a_slots, 256, &g));
+    k_adj_finish<<<g, 256, 0, st>>>(t.bin_tmp, op.a_base, op.a_rel, op.a_slots, t.bad);
+    SCT_TRY(check_launch("k_adj_finish"));
+
+    SCT_HIP(hipMemcpyAsync(op.fb_order, pl.order.data(), 4 * pl.order.size(), hipMemcpyHostToDevice, st));
+    if (op.n_bands > 0)
+        SCT_HIP(hipMemcpyAsync(op.fb_band_order, pl.border.data(), 8 * pl.border.size(),
+                               hipMemcpyHostToDevice, st));
 
     int32_t bad_h = 0;
-    SCT_HIP(hipMemcpyAsync(&bad_h, bad, 4, hipMemcpyDeviceToHost, st));
+    SCT_HIP(hipMemcpyAsync(&bad_h, t.bad, 4, hipMemcpyDeviceToHost, st));
     SCT_HIP(hipStreamSynchronize(st));
     if (bad_h)
         return set_error(RADON_EUNSUPPORTED,
@@ -611,17 +645,65 @@ static int build_typed(Op &op, const std::vector<double> &cs_host, hipStream_t s
     return RADON_OK;
 }
 
+// Point op's derived-layout arrays into `lay` (which already holds the bundle
+// table at its start when `fb_taken`), after the plan is known.
+static int carve_layouts(Op &op, const Plan &pl, Carve &lay, bool fb_taken)
+{
+    const int64_t es = op.msize;
+    if (!fb_taken) SCT_TRY(lay.take(&op.fb, int64_t(sizeof(FwdBundle)) * op.n_fb));
+    SCT_TRY(lay.take(&op.f_idx, 2 * pl.fslots));
+    SCT_TRY(lay.take(&op.f_v0, es * pl.fslots));
+    SCT_TRY(lay.take(&op.f_v1, es * pl.fslots));
+    SCT_TRY(lay.take(&op.a_rel, op.a_slots));
+    SCT_TRY(lay.take(&op.a_base, 2 * op.n_ag * op.n_aq * 4));
+    SCT_TRY(lay.take(&op.a_v0, es * op.a_slots));
+    SCT_TRY(lay.take(&op.a_v1, es * op.a_slots));
+    op.n_order = int64_t(pl.order.size());
+    SCT_TRY(lay.take(&op.fb_order, 4 * op.n_order));
+    op.n_bands = pl.border.empty() ? 0 : (op.n + kBandLines - 1) / kBandLines;
+    op.n_band_order = int64_t(pl.border.size());
+    op.fb_band_order = nullptr;
+    if (op.n_bands > 0) SCT_TRY(lay.take(&op.fb_band_order, 8 * op.n_band_order));
+    return RADON_OK;
+}
+
+static void op_free(Op *op)
+{
+    if (!op) return;
+    for (void *p : op->owned) (void)hipFree(p);
+    delete op;
+}
+
+// Owns the hipMalloc'd blocks of build_radon_csr until they are handed to
+// the operator (or freed on failure).
+struct OwnedBlocks {
+    std::vector<void *> ptrs;
+    ~OwnedBlocks()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    int alloc(void **p, int64_t bytes)
+    {
+        *p = nullptr;
+        SCT_HIP(hipMalloc(p, size_t(bytes > 0 ? bytes : 256)));
+        ptrs.push_back(*p);
+        return RADON_OK;
+    }
+};
+
 }  // namespace sct
 
 using namespace sct;
 
 extern "C" const char *radon_last_error(void) { return sct::last_error(); }
 
-extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out)
+namespace sct {
+
+// Checks the geometry and fills the operator's sizes and angle table (no
+// device work).  On success *res owns a new handle without device arrays.
+static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
 {
-    clear_error();
-    if (!out) return set_error(RADON_EINVAL, "out is NULL");
-    *out = nullptr;
+    *res = nullptr;
     if (!g) return set_error(RADON_EINVAL, "geometry is NULL");
     if (g->n < 1 || g->n > 32767) return set_error(RADON_EINVAL, "n must be in [1, 32767] (got %d)", g->n);
     if (g->n_angles < 1) return set_error(RADON_EINVAL, "n_angles must be >= 1 (got %d)", g->n_angles);
@@ -630,6 +712,8 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     if (g->dtype != SPARSECT_F32 && g->dtype != SPARSECT_F64 && g->dtype != SPARSECT_F32_F64)
         return set_error(RADON_EINVAL, "dtype must be SPARSECT_F32, SPARSECT_F64 or SPARSECT_F32_F64 (got %d)",
                          g->dtype);
+    if (g->fwd_bundle != 0 && !valid_bundle_width(g->fwd_bundle))
+        return set_error(RADON_EINVAL, "fwd_bundle must be 0, 16, 32 or 64 (got %d)", g->fwd_bundle);
     std::vector<int32_t> meas;
     for (int k = 0; k < g->n_angles; ++k)
         if (!g->measured || g->measured[k]) meas.push_back(k);
@@ -653,25 +737,200 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     op->rows = rows;
     op->msize = g->dtype == SPARSECT_F64 ? 8 : 4;
     op->vsize = g->dtype == SPARSECT_F32 ? 4 : 8;
-
-    std::vector<double> cs(2 * meas.size());
+    op->bw = g->fwd_bundle ? g->fwd_bundle : kFwdLanes;
+    op->tiles = (op->n + 7) / 8;
+    op->n_ag = int64_t(op->tiles) * op->tiles;
+    op->n_aq = (op->n_meas + 3) / 4;
+    op->a_slots = aslots;
+    op->n_fb = n_fb_of(*op);
+    cs.assign(2 * meas.size(), 0.0);
     for (size_t a = 0; a < meas.size(); ++a) {
         angle_cos_sin(meas[a], g->n_angles, &cs[2 * a], &cs[2 * a + 1]);
         if (std::fabs(cs[2 * a + 1]) > std::fabs(cs[2 * a])) op->need_T = true;
     }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int rc;
+    *res = op;
+    return RADON_OK;
+}
+
+static int fill_typed(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
+{
     try {
-        rc = op->msize == 4 ? build_typed<float>(*op, cs, st) : build_typed<double>(*op, cs, st);
+        return op.msize == 4 ? fill_phase<float>(op, pl, st, t) : fill_phase<double>(op, pl, st, t);
     } catch (...) {
-        rc = set_error(RADON_EINVAL, "unexpected host exception during build");
+        return set_error(RADON_EINVAL, "unexpected host exception during build");
     }
+}
+
+static void fill_sizes(const Op &op, const Plan &pl, int64_t ws_need, radon_sizes *out)
+{
+    out->n_meas_rays = op.rows;
+    out->nnz = pl.nnz;
+    out->fwd_slots = pl.fslots;
+    out->adj_slots = op.a_slots;
+    out->row_ptr_bytes = 8 * (op.rows + 1);
+    out->col_bytes = 4 * pl.nnz;
+    out->val_bytes = int64_t(op.msize) * pl.nnz;
+    out->layout_bytes = layout_bytes(op, pl);
+    out->ws_bytes = ws_need;
+}
+
+}  // namespace sct (host entry helpers)
+
+extern "C" int radon_csr_sizes(const radon_geom *g, void *ws, int64_t ws_bytes, void *stream,
+                               radon_sizes *out)
+{
+    clear_error();
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    std::vector<double> cs;
+    Op *op = nullptr;
+    SCT_TRY(new_op(g, &op, cs));
+    std::unique_ptr<Op> hold(op);
+    int64_t need = 0;
+    SCT_TRY(build_ws_bytes(*op, &need));
+    std::memset(out, 0, sizeof *out);
+    out->n_meas_rays = op->rows;
+    out->nnz = -1;
+    out->ws_bytes = need;
+    if (!ws) return RADON_OK;   // query of the workspace size only
+    if (ws_bytes < need)
+        return set_error(RADON_EWORKSPACE, "radon_csr_sizes needs a workspace of %lld bytes (got %lld)",
+                         (long long)need, (long long)ws_bytes);
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return set_error(RADON_EINVAL, "ws must be 256-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carve w{static_cast<char *>(ws), ws_bytes, 0, "radon_csr_sizes workspace"};
+    int64_t *rp = nullptr;
+    FwdBundle *fb = nullptr;
+    SCT_TRY(w.take(&rp, 8 * (op->rows + 1)));
+    SCT_TRY(w.take(&fb, int64_t(sizeof(FwdBundle)) * op->n_fb));
+    CountTmp t;
+    Plan pl;
+    int rc = count_phase(*op, cs, st, w, rp, fb, t, pl);
     if (rc != RADON_OK) {
         (void)hipStreamSynchronize(st);
-        op_free(op);
         return rc;
     }
-    *out = reinterpret_cast<radon_op *>(op);
+    fill_sizes(*op, pl, need, out);
+    return RADON_OK;
+}
+
+extern "C" int build_radon_csr_into(const radon_geom *g, const radon_buffers *b, void *stream,
+                                    radon_op **out)
+{
+    clear_error();
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!b) return set_error(RADON_EINVAL, "buffers are NULL");
+    std::vector<double> cs;
+    Op *op = nullptr;
+    SCT_TRY(new_op(g, &op, cs));
+    std::unique_ptr<Op> hold(op);
+    int64_t need = 0;
+    SCT_TRY(build_ws_bytes(*op, &need));
+    if (!b->row_ptr || !b->col || !b->val || !b->layout || !b->ws)
+        return set_error(RADON_EINVAL, "every buffer of radon_buffers must be non-NULL");
+    for (const void *p : {(const void *)b->row_ptr, (const void *)b->col, (const void *)b->val,
+                          (const void *)b->layout, (const void *)b->ws})
+        if (reinterpret_cast<uintptr_t>(p) & 255)
+            return set_error(RADON_EINVAL, "radon_buffers pointers must be 256-byte aligned");
+    if (b->ws_bytes < need)
+        return set_error(RADON_EWORKSPACE, "build_radon_csr_into needs a workspace of %lld bytes (got %lld)",
+                         (long long)need, (long long)b->ws_bytes);
+    if (b->row_ptr_bytes < 8 * (op->rows + 1))
+        return set_error(RADON_EWORKSPACE, "row_ptr needs %lld bytes (got %lld)",
+                         (long long)(8 * (op->rows + 1)), (long long)b->row_ptr_bytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carve w{static_cast<char *>(b->ws), b->ws_bytes, 0, "build_radon_csr_into workspace"};
+    Carve lay{static_cast<char *>(b->layout), b->layout_bytes, 0, "build_radon_csr_into layout block"};
+    // the slots the sizes query uses for the row pointers and bundle table stay unused here
+    int64_t *rp_unused = nullptr;
+    FwdBundle *fb_unused = nullptr;
+    SCT_TRY(w.take(&rp_unused, 8 * (op->rows + 1)));
+    SCT_TRY(w.take(&fb_unused, int64_t(sizeof(FwdBundle)) * op->n_fb));
+    op->rp = b->row_ptr;
+    SCT_TRY(lay.take(&op->fb, int64_t(sizeof(FwdBundle)) * op->n_fb));
+    CountTmp t;
+    Plan pl;
+    int rc = count_phase(*op, cs, st, w, op->rp, op->fb, t, pl);
+    if (rc == RADON_OK) {
+        op->nnz = pl.nnz;
+        op->f_slots = pl.fslots;
+        if (b->col_bytes < 4 * pl.nnz || b->val_bytes < int64_t(op->msize) * pl.nnz)
+            rc = set_error(RADON_EWORKSPACE, "col and val need %lld and %lld bytes (got %lld and %lld)",
+                           (long long)(4 * pl.nnz), (long long)(op->msize * pl.nnz),
+                           (long long)b->col_bytes, (long long)b->val_bytes);
+    }
+    if (rc == RADON_OK) {
+        op->col = b->col;
+        op->val = b->val;
+        rc = carve_layouts(*op, pl, lay, true);
+    }
+    if (rc == RADON_OK) rc = fill_typed(*op, pl, st, t);
+    if (rc != RADON_OK) {
+        (void)hipStreamSynchronize(st);
+        return rc;
+    }
+    op->device_bytes = 8 * (op->rows + 1) + 4 * op->nnz + int64_t(op->msize) * op->nnz + lay.used;
+    *out = reinterpret_cast<radon_op *>(hold.release());
+    return RADON_OK;
+}
+
+extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out)
+{
+    clear_error();
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::vector<double> cs;
+    Op *op = nullptr;
+    SCT_TRY(new_op(g, &op, cs));
+    std::unique_ptr<Op, void (*)(Op *)> hold(op, op_free);
+    int64_t need = 0;
+    SCT_TRY(build_ws_bytes(*op, &need));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    OwnedBlocks tmp, keep;
+    void *wsp = nullptr, *rp = nullptr, *fbp = nullptr;
+    SCT_TRY(tmp.alloc(&wsp, need));
+    SCT_TRY(keep.alloc(&rp, 8 * (op->rows + 1)));
+    SCT_TRY(keep.alloc(&fbp, int64_t(sizeof(FwdBundle)) * op->n_fb));
+    Carve w{static_cast<char *>(wsp), need, 0, "build_radon_csr workspace"};
+    int64_t *rp_unused = nullptr;
+    FwdBundle *fb_unused = nullptr;
+    SCT_TRY(w.take(&rp_unused, 8 * (op->rows + 1)));
+    SCT_TRY(w.take(&fb_unused, int64_t(sizeof(FwdBundle)) * op->n_fb));
+    op->rp = static_cast<int64_t *>(rp);
+    op->fb = static_cast<FwdBundle *>(fbp);
+    CountTmp t;
+    Plan pl;
+    int rc = count_phase(*op, cs, st, w, op->rp, op->fb, t, pl);
+    void *col = nullptr, *val = nullptr, *layp = nullptr;
+    int64_t lb = 0;
+    if (rc == RADON_OK) {
+        op->nnz = pl.nnz;
+        op->f_slots = pl.fslots;
+        lb = layout_bytes(*op, pl);
+        rc = keep.alloc(&col, 4 * pl.nnz);
+        if (rc == RADON_OK) rc = keep.alloc(&val, int64_t(op->msize) * pl.nnz);
+        if (rc == RADON_OK) rc = keep.alloc(&layp, lb);
+    }
+    if (rc == RADON_OK) {
+        op->col = static_cast<int32_t *>(col);
+        op->val = val;
+        // the bundle table has its own block here: its room at the start of
+        // the layout block stays unused
+        Carve lay{static_cast<char *>(layp), lb, 0, "build_radon_csr layout block"};
+        FwdBundle *fb_room = nullptr;
+        rc = lay.take(&fb_room, int64_t(sizeof(FwdBundle)) * op->n_fb);
+        if (rc == RADON_OK) rc = carve_layouts(*op, pl, lay, true);
+    }
+    if (rc == RADON_OK) rc = fill_typed(*op, pl, st, t);
+    if (rc != RADON_OK) {
+        (void)hipStreamSynchronize(st);
+        return rc;
+    }
+    op->owned = keep.ptrs;
+    keep.ptrs.clear();
+    op->device_bytes = 8 * (op->rows + 1) + int64_t(sizeof(FwdBundle)) * op->n_fb + 4 * op->nnz +
+                       int64_t(op->msize) * op->nnz + lb;
+    *out = reinterpret_cast<radon_op *>(hold.release());
     return RADON_OK;
 }
 
@@ -695,7 +954,7 @@ extern "C" int radon_op_info(const radon_op *p, radon_info *out)
     out->n_angles = op->n_angles;
     out->n_bins = op->n_bins;
     out->needs_transpose = op->need_T ? 1 : 0;
-    out->reserved = 0;
+    out->fwd_bundle = op->bw;
     return RADON_OK;
 }
 

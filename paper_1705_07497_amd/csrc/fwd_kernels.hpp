@@ -1,0 +1,146 @@
+// Forward-product kernels and their launchers for one bundle width.  Each
+// width is compiled in a translation unit of its own (fwd16.hip, fwd32.hip,
+// fwd64.hip) that instantiates launch_fwd_bw for the three operator kinds;
+// apply.hip's launch_fwd picks the operator's width.
+#pragma once
+
+#include "products.hpp"
+
+namespace sct {
+
+// Forward product of one operator: persistent loop over its ray bundles
+// (see fwd_bundle).
+template <class TM, class TV, int W, int BC, int BW>
+__global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb,
+                                                const int32_t *__restrict__ order, int64_t n_order,
+                                                const uint16_t *__restrict__ idx,
+                                                const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                const TV *__restrict__ x, const TV *__restrict__ xT,
+                                                TV *__restrict__ y, int n, int64_t nn, int64_t rows,
+                                                int batch)
+{
+    const int b0 = int(blockIdx.y) * BC;
+    const int nbc = min(BC, batch - b0);
+    // persistent: the grid is a multiple of 8 blocks, so block i stays on XCD
+    // i % 8 and order[] keeps one gather class per XCD
+    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+        const int B = order[o];
+        if (B < 0) continue;           // padding entry (uniform per block)
+        const FwdBundle d = fb[B];
+        fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b0) * nn,
+                                      y + int64_t(b0) * rows, n, nn, rows, nbc);
+    }
+}
+
+// Line-banded forward: work item (bundle, band) covers the bundle's quads
+// whose first line lies in lines [band L, (band + 1) L).  Items are ordered
+// band-major on each XCD, so the blocks of an XCD gather from one band of
+// the image (or its transpose) at a time and keep it in that XCD's L2 across
+// all angles.  Each item writes its partial sums to part[image][band][ray].
+// Several images: blockIdx.y selects a chunk of up to BC images that share
+// every matrix load, as in k_fwd.
+template <class TM, class TV, int W, int BC, int BW>
+__global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict__ fb,
+                                                     const int2 *__restrict__ order, int64_t n_order,
+                                                     const uint16_t *__restrict__ idx,
+                                                     const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                     const TV *__restrict__ x, const TV *__restrict__ xT,
+                                                     TV *__restrict__ part, int n, int64_t nn,
+                                                     int64_t rows, int n_bands, int batch)
+{
+    const int b0 = int(blockIdx.y) * BC;
+    const int nbc = min(BC, batch - b0);
+    const int64_t stride = int64_t(n_bands) * rows;   // one image's partials
+    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+        const int2 it = order[o];
+        if (it.x < 0) continue;        // padding entry (uniform per block)
+        const FwdBundle d = fb[it.x];
+        const int nq = d.nrows >> 2;
+        const int lo = it.y * kBandLines - d.m0, hi = lo + kBandLines;
+        const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
+        const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
+        fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b0) * nn,
+                                      part + int64_t(b0) * stride + int64_t(it.y) * rows, n, nn,
+                                      stride, nbc, tq0, tq1);
+    }
+}
+
+// Right-hand sides per fused chunk: the largest supported chunk that fits the
+// batch and the operator's tuning limit.
+inline int fwd_rhs_chunk(int batch, int limit)
+{
+    for (int c : {16, 8, 4})
+        if (c <= batch && c <= limit) return c;
+    return 1;
+}
+
+template <class TM, class TV, int W, int BC, int BW>
+inline void fwd_wbc(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
+{
+    const int64_t g = op.n_order < kPersistentBlocks ? op.n_order : kPersistentBlocks;
+    const unsigned chunks = unsigned((batch + BC - 1) / BC);
+    k_fwd<TM, TV, W, BC, BW><<<dim3(unsigned(g), chunks), 64 * W, 0, s>>>(
+        op.fb, op.fb_order, op.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
+        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, y, op.n, op.nn, op.rows, batch);
+}
+
+template <class TM, class TV, int BC, int BW>
+inline void fwd_bcw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s)
+{
+    if (op.tune.fwd_waves == 2) fwd_wbc<TM, TV, 2, BC, BW>(op, x, xT, y, batch, s);
+    else fwd_wbc<TM, TV, 4, BC, BW>(op, x, xT, y, batch, s);
+}
+
+template <class TM, class TV, int W, int BC, int BW>
+inline void fwd_band_wbc(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
+                         hipStream_t s)
+{
+    const int64_t g = op.n_band_order < kPersistentBlocks ? op.n_band_order : kPersistentBlocks;
+    const unsigned chunks = unsigned((batch + BC - 1) / BC);
+    k_fwd_band<TM, TV, W, BC, BW><<<dim3(unsigned(g), chunks), 64 * W, 0, s>>>(
+        op.fb, op.fb_band_order, op.n_band_order, op.f_idx, static_cast<const TM *>(op.f_v0),
+        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, op.n_bands,
+        batch);
+    const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
+    k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(batch)), 256, 0, s>>>(
+        op.fb, part, y, op.rows, op.n_bins, nbpa, op.bw, op.n_bands);
+}
+
+template <class TM, class TV, int BC, int BW>
+inline void fwd_band_bcw(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
+                         hipStream_t s)
+{
+    if (op.tune.fwd_waves == 2) fwd_band_wbc<TM, TV, 2, BC, BW>(op, x, xT, y, part, batch, s);
+    else fwd_band_wbc<TM, TV, 4, BC, BW>(op, x, xT, y, part, batch, s);
+}
+
+template <class TM, class TV, int BW>
+int launch_fwd_bw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s, TV *part)
+{
+    if (part && fwd_part_elems(op, batch) > 0) {
+        switch (fwd_rhs_chunk(batch, op.tune.fwd_rhs)) {
+        case 16: fwd_band_bcw<TM, TV, 16, BW>(op, x, xT, y, part, batch, s); break;
+        case 8: fwd_band_bcw<TM, TV, 8, BW>(op, x, xT, y, part, batch, s); break;
+        case 4: fwd_band_bcw<TM, TV, 4, BW>(op, x, xT, y, part, batch, s); break;
+        default: fwd_band_bcw<TM, TV, 1, BW>(op, x, xT, y, part, batch, s); break;
+        }
+        return check_launch("k_fwd_band");
+    }
+    switch (fwd_rhs_chunk(batch, op.tune.fwd_rhs)) {
+    case 16: fwd_bcw<TM, TV, 16, BW>(op, x, xT, y, batch, s); break;
+    case 8: fwd_bcw<TM, TV, 8, BW>(op, x, xT, y, batch, s); break;
+    case 4: fwd_bcw<TM, TV, 4, BW>(op, x, xT, y, batch, s); break;
+    default: fwd_bcw<TM, TV, 1, BW>(op, x, xT, y, batch, s); break;
+    }
+    return check_launch("k_fwd");
+}
+
+#define SCT_FWD_INST(BW)                                                                          \
+    template int launch_fwd_bw<float, float, BW>(const Op &, const float *, const float *, float *, \
+                                                 int, hipStream_t, float *);                       \
+    template int launch_fwd_bw<double, double, BW>(const Op &, const double *, const double *,    \
+                                                   double *, int, hipStream_t, double *);          \
+    template int launch_fwd_bw<float, double, BW>(const Op &, const double *, const double *,     \
+                                                  double *, int, hipStream_t, double *);
+
+}  // namespace sct

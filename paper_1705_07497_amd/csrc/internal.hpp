@@ -12,13 +12,17 @@
 
 namespace sct {
 
-// Forward product layout: one bundle = up to 16 adjacent bins of one measured
-// angle.  Slot (t, r) covers ray r of the bundle on image line m0 + t along the
-// rays' major axis (rows for rays closer to vertical, columns for rays closer
-// to horizontal).  Slots are grouped in quads of 4 consecutive lines of one
-// ray so that a lane reads 4 slots with one 16-byte load:
-//   slot(t, r) = off + ((t/4)*16 + r)*4 + t%4.
-constexpr int kFwdLanes = 16;
+// Forward product layout: one bundle = up to BW adjacent bins of one measured
+// angle (BW, the bundle width, is 16, 32 or 64, chosen when the operator is
+// built).  Slot (t, r) covers ray r of the bundle on image line m0 + t along
+// the rays' major axis (rows for rays closer to vertical, columns for rays
+// closer to horizontal).  Slots are grouped in quads of 4 consecutive lines of
+// one ray so that a lane reads 4 slots with one 16-byte load:
+//   slot(t, r) = off + ((t/4)*BW + r)*4 + t%4.
+// A wave's 64 lanes cover BW rays and 64/BW consecutive quads, so one gather
+// instruction reads BW adjacent rays on each of 64/BW image lines.
+constexpr int kFwdLanes = 16;   // default bundle width
+inline bool valid_bundle_width(int bw) { return bw == 16 || bw == 32 || bw == 64; }
 // Adjoint layout: one group = an 8x8 pixel tile (tile (ty, tx) is group
 // g = ty*tiles + tx, tiles = ceil(n/8); lane l = (iy%8)*8 + ix%8), chosen
 // because an 8x8 tile projects onto at most 14 adjacent bins at any angle, so
@@ -40,9 +44,9 @@ constexpr int kBandLines = 128;
 constexpr int kBandMinN = 1024;
 constexpr int kAdjBand = 16;
 
-__host__ __device__ inline int64_t fwd_slot(int64_t off, int t, int r)
+__host__ __device__ inline int64_t fwd_slot(int64_t off, int t, int r, int bw)
 {
-    return off + ((int64_t(t >> 2) * kFwdLanes + r) << 2) + (t & 3);
+    return off + ((int64_t(t >> 2) * bw + r) << 2) + (t & 3);
 }
 
 __host__ __device__ inline int64_t adj_slot(int iy, int ix, int a, int nq, int tiles)
@@ -57,7 +61,7 @@ struct FwdBundle {
     int32_t m0;     // first major line
     int32_t nrows;  // major lines covered (multiple of 4, may be 0)
     int32_t ray0;   // first measured ray of the bundle
-    int32_t nrays;  // rays in the bundle (<= 16)
+    int32_t nrays;  // rays in the bundle (<= the bundle width)
     int32_t horiz;  // 1: major axis is x (gather from the transposed image)
     int32_t pad;
 };
@@ -73,6 +77,7 @@ struct Op {
     std::vector<int32_t> meas;       // measured angle indices (host)
     int32_t msize = 4;               // bytes per stored matrix value
     int32_t vsize = 4;               // bytes per vector element
+    int32_t bw = kFwdLanes;          // rays per forward bundle (16, 32 or 64)
 
     // CSR of MR (device)
     int64_t *rp = nullptr;
@@ -180,6 +185,10 @@ int launch_transpose(const Op &op, const TV *x, TV *xT, int batch, hipStream_t s
 template <class TM, class TV>
 int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s,
                TV *part = nullptr);
+// launch_fwd for operators of bundle width BW (fwd16.hip, fwd32.hip, fwd64.hip).
+template <class TM, class TV, int BW>
+int launch_fwd_bw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s,
+                  TV *part);
 // Scratch elements of the banded forward for `batch` images (0: not banded).
 int64_t fwd_part_elems(const Op &op, int batch);
 // out = alpha (MR)^T y + lambda K^T K x + sigma x; partial <x, out> per group

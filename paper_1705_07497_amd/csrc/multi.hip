@@ -37,6 +37,7 @@ struct MultiInst {
 
 struct Multi {
     int count = 0, dtype = 0, vsize = 0;
+    int bw = kFwdLanes;                       // bundle width shared by every instance
     std::vector<const Op *> ops;
     std::vector<int64_t> img_off, sino_off;   // host, count + 1 entries
     std::vector<int64_t> part_off;            // host: band partial offset, -1 if not banded
@@ -117,7 +118,7 @@ __global__ void k_multi_reset(uint32_t *__restrict__ tickets)
 // The entries are handed out in list order through one ticket counter per
 // XCD: a static round-robin would let blocks drift apart over the instances,
 // keeping many instances' images live in the caches at once.
-template <class TM, class TV, int W>
+template <class TM, class TV, int W, int BW>
 __global__ __launch_bounds__(64 * W) void k_multi_fwd(const int2 *__restrict__ work, int64_t n_work,
                                                       const MultiInst *__restrict__ inst,
                                                       const TV *__restrict__ x,
@@ -146,17 +147,17 @@ __global__ __launch_bounds__(64 * W) void k_multi_fwd(const int2 *__restrict__ w
                 const int lo = band * kBandLines - d.m0, hi = lo + kBandLines;
                 const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
                 const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
-                fwd_bundle<TM, TV, W, 1>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
-                                         static_cast<const TM *>(I.f_v1),
-                                         (d.horiz ? xT : x) + I.img_off,
-                                         part + I.part_off + int64_t(band) * I.rows, I.n, I.nn,
-                                         I.rows, 1, tq0, tq1);
+                fwd_bundle<TM, TV, W, 1, BW>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
+                                             static_cast<const TM *>(I.f_v1),
+                                             (d.horiz ? xT : x) + I.img_off,
+                                             part + I.part_off + int64_t(band) * I.rows, I.n, I.nn,
+                                             I.rows, 1, tq0, tq1);
             } else {
                 const FwdBundle d = I.fb[w.y];
-                fwd_bundle<TM, TV, W, 1>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
-                                         static_cast<const TM *>(I.f_v1),
-                                         (d.horiz ? xT : x) + I.img_off, y + I.sino_off, I.n, I.nn,
-                                         I.rows, 1);
+                fwd_bundle<TM, TV, W, 1, BW>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
+                                             static_cast<const TM *>(I.f_v1),
+                                             (d.horiz ? xT : x) + I.img_off, y + I.sino_off, I.n,
+                                             I.nn, I.rows, 1);
             }
         }
         __syncthreads();   // every wave has read `next`
@@ -477,17 +478,30 @@ static int multi_launch_fwd(const Multi &m, const TV *x, const TV *xT, TV *y, TV
 {
     k_multi_reset<<<1, 64, 0, s>>>(tickets);
     SCT_TRY(check_launch("k_multi_reset"));
-    k_multi_fwd<TM, TV, kMultiFwdWaves><<<unsigned(fwd_grid(m)), 64 * kMultiFwdWaves, 0, s>>>(
-        m.fwork, m.n_fwork, m.inst, x, xT ? xT : x, y, fpart, tickets);
+    const unsigned g = unsigned(fwd_grid(m)), bs = 64 * kMultiFwdWaves;
+    switch (m.bw) {
+    case 64:
+        k_multi_fwd<TM, TV, kMultiFwdWaves, 64><<<g, bs, 0, s>>>(m.fwork, m.n_fwork, m.inst, x,
+                                                                 xT ? xT : x, y, fpart, tickets);
+        break;
+    case 32:
+        k_multi_fwd<TM, TV, kMultiFwdWaves, 32><<<g, bs, 0, s>>>(m.fwork, m.n_fwork, m.inst, x,
+                                                                 xT ? xT : x, y, fpart, tickets);
+        break;
+    default:
+        k_multi_fwd<TM, TV, kMultiFwdWaves, 16><<<g, bs, 0, s>>>(m.fwork, m.n_fwork, m.inst, x,
+                                                                 xT ? xT : x, y, fpart, tickets);
+        break;
+    }
     SCT_TRY(check_launch("k_multi_fwd"));
     // banded instances: their band partials into their sinograms
     for (int i = 0; i < m.count; ++i) {
         const Op &op = *m.ops[size_t(i)];
         if (m.part_off[size_t(i)] < 0) continue;
-        const int nbpa = (op.n_bins + kFwdLanes - 1) / kFwdLanes;
+        const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
         k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), 1u), 256, 0, s>>>(
             op.fb, fpart + m.part_off[size_t(i)], y + m.sino_off[size_t(i)], op.rows, op.n_bins, nbpa,
-            op.n_bands);
+            op.bw, op.n_bands);
         SCT_TRY(check_launch("k_fwd_band_sum"));
     }
     return RADON_OK;
@@ -723,9 +737,12 @@ extern "C" int radon_multi_create(const radon_op *const *ops, int32_t count, con
         SCT_TRY(check_op(ops[i]));
         if (as_op(ops[i])->dtype != as_op(ops[0])->dtype)
             return set_error(RADON_EINVAL, "operator %d has another dtype than operator 0", i);
+        if (as_op(ops[i])->bw != as_op(ops[0])->bw)
+            return set_error(RADON_EINVAL, "operator %d has another forward bundle width than operator 0", i);
     }
     Multi *m = new (std::nothrow) Multi;
     if (!m) return set_error(RADON_EINVAL, "out of host memory");
+    m->bw = as_op(ops[0])->bw;
     const int rc = build_multi(*m, ops, count, alpha, lambda, sigma);
     if (rc != RADON_OK) {
         free_multi(m);

@@ -50,9 +50,9 @@ __device__ inline V stream_load(const V *p)
 // One workgroup of W waves per ray bundle (block -> bundle through `order`,
 // which places bundles of rays closer to vertical and closer to horizontal on
 // different XCDs, so each XCD's L2 caches only x or only its transpose).
-// Lane = (quad offset q in 0..3, ray r in 0..15): a lane reads a quad (4
-// consecutive major lines of its ray) with 16-byte loads, the 64 lanes of a
-// wave read 64 consecutive quads, and the 16 lanes of one q gather from the
+// Lane = (quad offset q in 0..64/BW-1, ray r in 0..BW-1): a lane reads a quad
+// (4 consecutive major lines of its ray) with 16-byte loads, the 64 lanes of
+// a wave read 64 consecutive quads, and the BW lanes of one q gather from the
 // same image line at neighbouring positions.  Wave w covers its share of the
 // bundle's quads; partial sums are combined over q with shuffles and over the
 // waves in LDS, in a fixed order.
@@ -63,7 +63,7 @@ __device__ inline V stream_load(const V *p)
 // the last column has no second pixel (weight 0), so its pair starts at n-2.
 // The test is a template parameter so that the loop body has no branch: a
 // branch around each gather makes every gather wait for all loads in flight.
-template <class TM, class TV, int BC, bool PAIR>
+template <class TM, class TV, int BC, bool PAIR, int BW>
 __device__ __forceinline__ void fwd_quads(const FwdBundle &d, const u16x4 *__restrict__ I,
                                           const typename Quad<TM>::type *__restrict__ A,
                                           const typename Quad<TM>::type *__restrict__ Bv,
@@ -72,9 +72,10 @@ __device__ __forceinline__ void fwd_quads(const FwdBundle &d, const u16x4 *__res
 {
     using Q = typename Quad<TM>::type;
     using P = typename PairU<TV>::type;
+    constexpr int G = 64 / BW;   // quads a wave covers per step
 #pragma unroll 2
-    for (int tq = s0 + q; tq < s1; tq += 4) {
-        const int e = tq * kFwdLanes + r;
+    for (int tq = s0 + q; tq < s1; tq += G) {
+        const int e = tq * BW + r;
         const u16x4 i4 = stream_load(I + e);
         const Q a4 = stream_load(A + e);
         const Q b4 = stream_load(Bv + e);
@@ -106,7 +107,7 @@ __device__ __forceinline__ void fwd_quads(const FwdBundle &d, const u16x4 *__res
 // bundles of one operator, k_multi_fwd over those of several.
 // [tq0, tq1) restricts the bundle to a range of its quads (the line-banded
 // forward); the default is the whole bundle.
-template <class TM, class TV, int W, int BC>
+template <class TM, class TV, int W, int BC, int BW>
 __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *__restrict__ idx,
                                            const TM *__restrict__ v0, const TM *__restrict__ v1,
                                            const TV *__restrict__ img, TV *__restrict__ y, int n,
@@ -114,9 +115,10 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
                                            int tq1 = -1)
 {
     using Q = typename Quad<TM>::type;
+    static_assert(BW == 16 || BW == 32 || BW == 64, "bundle width");
     // the wave index is uniform: readfirstlane lets the compiler see that
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int r = lane & 15, q = lane >> 4;
+    const int r = lane % BW, q = lane / BW;
     const int nq = tq1 < 0 ? (d.nrows >> 2) - tq0 : tq1 - tq0;
     const int s0 = tq0 + (nq * wave) / W, s1 = tq0 + (nq * (wave + 1)) / W;
     const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
@@ -126,16 +128,16 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
 #pragma unroll
     for (int c = 0; c < BC; ++c) acc[c] = TV(0);
     if (n >= 2)
-        fwd_quads<TM, TV, BC, true>(d, I, A, Bv, img, n, nn, nbc, s0, s1, q, r, acc);
+        fwd_quads<TM, TV, BC, true, BW>(d, I, A, Bv, img, n, nn, nbc, s0, s1, q, r, acc);
     else
-        fwd_quads<TM, TV, BC, false>(d, I, A, Bv, img, n, nn, nbc, s0, s1, q, r, acc);
+        fwd_quads<TM, TV, BC, false, BW>(d, I, A, Bv, img, n, nn, nbc, s0, s1, q, r, acc);
 #pragma unroll
     for (int c = 0; c < BC; ++c) {
-        acc[c] += __shfl_xor(acc[c], 16);
-        acc[c] += __shfl_xor(acc[c], 32);
+#pragma unroll
+        for (int o = BW; o < 64; o <<= 1) acc[c] += __shfl_xor(acc[c], o);
     }
     if constexpr (W > 1) {
-        __shared__ TV red[W][BC][kFwdLanes];
+        __shared__ TV red[W][BC][BW];
         if (q == 0) {
 #pragma unroll
             for (int c = 0; c < BC; ++c) red[wave][c][r] = acc[c];
@@ -163,13 +165,14 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
 template <class TV>
 __global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restrict__ fb,
                                                       const TV *__restrict__ part, TV *__restrict__ y,
-                                                      int64_t rows, int nb, int nbpa, int n_bands)
+                                                      int64_t rows, int nb, int nbpa, int bw,
+                                                      int n_bands)
 {
     const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ray >= rows) return;
     const int b = blockIdx.y;
     const int a = int(ray / nb), bin = int(ray % nb);
-    const FwdBundle d = fb[int64_t(a) * nbpa + bin / kFwdLanes];
+    const FwdBundle d = fb[int64_t(a) * nbpa + bin / bw];
     TV acc = TV(0);
     if (d.nrows > 0) {
         const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;

@@ -45,6 +45,11 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct._Info) == 80
     assert ctypes.sizeof(sct.PdParams) == 40
     assert int(consts["RADON_WS_PD"]) == sct.WS_PD
+    assert int(consts["RADON_WS_TUNE"]) == sct.WS_TUNE
+    assert ctypes.sizeof(sct._Geom) == 32
+    assert ctypes.sizeof(sct.RadonSizes) == 72
+    assert ctypes.sizeof(sct.RadonBuffers) == 80
+    assert ctypes.sizeof(sct.Tuning) == 16
 
 
 def _build(n, na, nb, dtype=0, measured=None):
@@ -162,3 +167,24 @@ def test_sb_graph_entry_point_validates_without_gpu():
     assert L.split_bregman_tv_graph(None, None, None, None, 1, None, 0, None, ctypes.byref(h)) == -1
     assert L.split_bregman_tv_graph(None, None, None, None, 1, None, 0, None, None) == -1
     assert "out is NULL" in L.radon_last_error().decode()
+
+
+def test_caller_storage_and_tuner_entry_points_validate_without_gpu():
+    L = sct.lib()
+    sz = sct.RadonSizes()
+    assert L.radon_csr_sizes(None, None, 0, None, ctypes.byref(sz)) == -1
+    g = sct._Geom(8, 4, 13, 0, None)
+    assert L.radon_csr_sizes(ctypes.byref(g), None, 0, None, None) == -1
+    assert "out is NULL" in L.radon_last_error().decode()
+    bad = sct._Geom(8, 4, 13, 0, None, 24, 0)   # not a supported bundle width
+    assert L.radon_csr_sizes(ctypes.byref(bad), None, 0, None, ctypes.byref(sz)) == -1
+    assert "fwd_bundle" in L.radon_last_error().decode()
+    h = ctypes.c_void_p()
+    assert L.build_radon_csr(ctypes.byref(bad), None, ctypes.byref(h)) == -1
+    assert L.build_radon_csr_into(ctypes.byref(g), None, None, ctypes.byref(h)) == -1
+    assert "buffers are NULL" in L.radon_last_error().decode()
+    b = sct.RadonBuffers()
+    assert L.build_radon_csr_into(ctypes.byref(g), ctypes.byref(b), None, None) == -1
+    src = ctypes.c_int32(7)
+    assert L.radon_autotune(None, 1, None, 0, None, 0, None, ctypes.byref(src)) == -1
+    assert L.normal_apply_noalloc(None, 1.0, 1.0, 0.0, None, None, None, 1, None) == -1

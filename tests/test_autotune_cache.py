@@ -1,26 +1,27 @@
-"""Host logic of the autotuner's cache (no GPU needed)."""
+"""Host logic of the autotuner's cache file (no GPU needed)."""
 import numpy as np
 
 from paper_1705_07497_amd import autotune
 
 
-def test_cache_key_distinguishes_geometry_and_mask():
+def test_geometry_key_distinguishes_geometry_mask_kind_and_arch():
     m1 = np.ones(10, np.uint8)
     m2 = m1.copy()
     m2[3] = 0
-    keys = {autotune.cache_key("gfx950", 64, 10, 91, m, k) for m in (m1, m2) for k in (0, 2)}
-    keys.add(autotune.cache_key("gfx950", 65, 10, 91, m1, 0))
-    keys.add(autotune.cache_key("gfx942", 64, 10, 91, m1, 0))
+    keys = {autotune.geometry_key("gfx950", 64, 10, 91, m, k) for m in (m1, m2) for k in (0, 2)}
+    keys.add(autotune.geometry_key("gfx950", 65, 10, 91, m1, 0))
+    keys.add(autotune.geometry_key("gfx942", 64, 10, 91, m1, 0))
     assert len(keys) == 6
 
 
-def test_cache_store_and_load_roundtrip(tmp_path):
-    path = str(tmp_path / "sub" / "tune.json")
-    assert autotune.load_cache(path) == {}
-    e1 = {"tuning": dict(autotune.DEFAULT, fwd_waves=2), "batch": 4, "timings_s": {}}
-    autotune.store("k1", e1, path)
-    autotune.store("k2", {"tuning": autotune.DEFAULT, "batch": 1, "timings_s": {}}, path)
-    data = autotune.load_cache(path)
-    assert data["k1"] == e1 and set(data) == {"k1", "k2"}
-    (tmp_path / "bad.json").write_text("not json")
-    assert autotune.load_cache(str(tmp_path / "bad.json")) == {}
+def test_bundle_cache_roundtrip_last_line_wins_and_foreign_lines_ignored(tmp_path):
+    path = str(tmp_path / "sub" / "tune.txt")
+    assert autotune.load_bundles(path) == {}
+    autotune.store_bundle("k1", 32, path)
+    autotune.store_bundle("k2", 16, path)
+    autotune.store_bundle("k1", 64, path)
+    with open(path, "a") as fh:   # the library's launch lines and junk share the file
+        fh.write("sparsect-tune gfx950|n64|a10|b91|m0|k0|bw16|B1 2 1 4 8\n")
+        fh.write("sparsect-bundle k3 48\n")   # not a valid width
+        fh.write("garbage\n")
+    assert autotune.load_bundles(path) == {"k1": 64, "k2": 16}
