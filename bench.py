@@ -54,10 +54,16 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the fused multi-image legs")
     ap.add_argument("--profile", action="store_true",
                     help="profiler mode: 100 forward kernels, 100 adj, 20 normal applies, one CG(20) "
-                         "solve and a plain 1 GiB device copy (counter calibration), then exit")
+                         "solve and the stream copy / read kernels over 1 GiB (counter "
+                         "calibration), then exit")
     ap.add_argument("--profile-multi", action="store_true",
                     help="profiler mode for the uneven 32-instance batch: one captured-graph CG(10), "
                          "one eager group CG(10) and the 32 per-instance CG(10) solves, then exit")
+    ap.add_argument("--profile-volume", action="store_true",
+                    help="profiler mode for the 64 x 1024^2 volume: 3 fused normal applies with the "
+                         "default chunks, 3 with 16-image chunks and 4 single-image applies, then exit")
+    ap.add_argument("--bundle", type=int, default=0,
+                    help="forward bundle width for the profiler modes (0: 16)")
     ap.add_argument("--profile-fourier", action="store_true",
                     help="profiler mode for the Fourier-domain operator: its build, 20 fused and 20 "
                          "NUFFT normal applies and a plain 1 GiB device copy, then exit")
@@ -90,6 +96,39 @@ def traffic_from_profile(kernel):
     return None
 
 
+def host_cpu():
+    """CPU model, socket count and OMP_NUM_THREADS of the host the oracle runs on."""
+    model, sockets = "unknown", set()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model == "unknown":
+                    model = v
+                elif k == "physical id":
+                    sockets.add(v)
+    except OSError:
+        pass
+    return {"cpu_model": model, "sockets": max(1, len(sockets)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS", "unset")}
+
+
+def bandwidth_ceiling(sct, torch, dev, nbytes=1 << 30, reps=20):
+    """The practical HBM ceiling: the project's own stream copy and read-only
+    stream kernels over 1 GiB (HIP events on the current stream)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    part = torch.empty(2048, dtype=torch.int32, device=dev)
+    t_copy = event_time(torch, lambda: sct.bandwidth_probe(sct.PROBE_COPY, src, dst), reps)
+    t_read = event_time(torch, lambda: sct.bandwidth_probe(sct.PROBE_READ, src, part), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_gbs": round(2 * nbytes / t_copy / 1e9, 1), "read_gbs": round(nbytes / t_read / 1e9, 1),
+            "bytes": nbytes, "kernels": "k_stream_copy, k_stream_read"}
+
+
 def event_time(torch, fn, reps):
     """Seconds per call of fn (one untimed call first), HIP events on the
     current stream, which every library call here is enqueued on."""
@@ -104,7 +143,7 @@ def event_time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-def bench_batched(sct, W, torch, dev, vdt):
+def bench_batched(sct, W, torch, dev, vdt, verify=True):
     """Fused multi-image normal_apply (every matrix load shared by a chunk of up
     to 16 images) against the same images applied one at a time."""
     out = {}
@@ -112,11 +151,12 @@ def bench_batched(sct, W, torch, dev, vdt):
     def t(fn, reps):
         return event_time(torch, fn, reps)
 
+    from paper_1705_07497_amd import autotune
     for name in ("grad_16x512_f32", "volume_64x1024_f32"):
         w = W.WORKLOADS[name]
-        op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
-                         device=dev)
         B = w.batch
+        op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                         device=dev, tuning="default")
         X = torch.randn((B, op.nn), dtype=vdt, device=dev)
         O = torch.empty_like(X)
         o1 = torch.empty((1, op.nn), dtype=vdt, device=dev)
@@ -124,29 +164,41 @@ def bench_batched(sct, W, torch, dev, vdt):
         alpha, lam = (w.alpha, w.lam) if w.lam > 0 else (w.extra["tau"] * w.alpha, 0.0)
         sigma = 0.0 if w.lam > 0 else 1.0
 
-        def fused():
-            op.normal(X, alpha, lam, sigma, out=O)
+        def fused(o):
+            return lambda: o.normal(X, alpha, lam, sigma, out=O)
 
         def looped():
             for xb in singles:
                 op.normal(xb, alpha, lam, sigma, out=o1)
 
-        tf, tl = t(fused, 5), t(looped, 2)
+        # library defaults (16-ray bundles), then the autotuned operator for this
+        # batch: bundle width chosen over 16/32/64, launch settings timed
+        tf_def, tl = t(fused(op), 5), t(looped, 2)
+        ch = autotune.choose_bundle(w.n, w.n_angles, w.n_bins, w.mask, torch.float32, vdt, dev,
+                                    batch=B, reps=3, save=False)
+        opt = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                          device=dev, tuning="default", bundle=ch["bundle"])
+        autotune.autotune(opt, batch=B, save=False)
+        tf = t(fused(opt), 5)
         out[name] = {"batch": B, "n": w.n, "measured_angles": w.n_meas, "bins": w.n_bins,
                      "nnz": op.info.nnz, "fused_ms": round(tf * 1e3, 3),
+                     "fused_default_ms": round(tf_def * 1e3, 3),
+                     "tuned": {"bundle": opt.bundle, **opt.tuning},
                      "per_image_loop_ms": round(tl * 1e3, 3), "speedup": round(tl / tf, 2),
+                     "speedup_default": round(tl / tf_def, 2),
                      "image_applies_per_s": round(B / tf, 1)}
-        print(f"# batched {name}: fused {tf * 1e3:.2f} ms vs loop {tl * 1e3:.2f} ms "
-              f"({tl / tf:.2f}x)", file=sys.stderr, flush=True)
+        print(f"# batched {name}: fused {tf * 1e3:.2f} ms tuned (bundle {opt.bundle}, {opt.tuning}), "
+              f"{tf_def * 1e3:.2f} ms default, loop {tl * 1e3:.2f} ms ({tl / tf:.2f}x)",
+              file=sys.stderr, flush=True)
         if name == "grad_16x512_f32":
-            out["grad_16x512_f32_autograd"] = bench_autograd(op, w, torch, dev, vdt, t)
-        del op
+            out["grad_16x512_f32_autograd"] = bench_autograd(opt, w, torch, dev, vdt, t)
+        del op, opt
         torch.cuda.empty_cache()
     out["mixed_batch_32"] = bench_mixed_batch(sct, W, torch, dev, vdt, t)
     out["small_batch_64"] = bench_mixed_batch(
         sct, W, torch, dev, vdt, t,
         specs=[(n, na, W.n_bins_for(n)) for n, na in W.small_batch_specs(64)], label="small batch")
-    out["large_2048_f32"] = bench_large(sct, W, torch, dev, vdt, t)
+    out["large_2048_f32"] = bench_large(sct, W, torch, dev, vdt, t, verify)
     return out
 
 
@@ -295,7 +347,7 @@ def bench_fourier(sct, op, w, mu, torch, timed, profile=False):
     return res
 
 
-def bench_large(sct, W, torch, dev, vdt, t):
+def bench_large(sct, W, torch, dev, vdt, t, verify=True):
     """The large under-resolved workload: 2048 x 2048, 90 angles, 2897 bins
     (4.8e8 nonzeros), split Bregman 30 outer x 10 CG on a random-ellipse
     phantom; the normal operator alone and whole reconstructions."""
@@ -317,14 +369,52 @@ def bench_large(sct, W, torch, dev, vdt, t):
     bytes_normal = 2 * 8 * nnz + 4 * (op.rows + 1) + 4 * (op.nn + 1) + 8 * (3 * op.nn + 2 * op.rows)
     print(f"# large 2048x2048/90 angles: normal {t_normal * 1e3:.3f} ms, split Bregman "
           f"{t_sb * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    out_d = {"n": w.n, "angles": w.n_angles, "bins": w.n_bins, "nnz": nnz,
+    out_d = {"n": w.n, "angles": w.n_angles, "bins": w.n_bins, "nnz": nnz, "bundle": op.bundle,
              "normal_apply_ms": round(t_normal * 1e3, 3),
              "normal_apply_gbs": round(bytes_normal / t_normal / 1e9, 1),
              "sb_ms": round(t_sb * 1e3, 1), "sb_applies": w.n_outer * w.n_cg,
              "recon_per_s": round(1.0 / t_sb, 3), "rel_err_to_phantom": round(err, 4)}
+    ug = u.double().cpu().numpy().reshape(-1)
+    fr = f.double().cpu().numpy().reshape(-1)
     del op
     torch.cuda.empty_cache()
+    if verify:
+        # the same reconstruction by the FP64 oracle from the same data (30
+        # outer iterations run as three resumed runs of 10, bitwise one run)
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.OracleOp(w.n, w.n_angles, w.n_bins, w.mask)
+        uo, st = None, None
+        for _ in range(w.n_outer // 10):
+            uo, _, _, _, st = ref.sb(fr, w.alpha, w.lam, 10, w.n_cg, u0=uo, state=st)
+            print("# large: oracle split Bregman, 10 more outer iterations", file=sys.stderr, flush=True)
+        out_d["sb_rel_l2_vs_oracle"] = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+        out_d["oracle_s"] = round(time.perf_counter() - t0, 1)
+        print(f"# large: split Bregman rel L2 vs FP64 oracle {out_d['sb_rel_l2_vs_oracle']:.3e}",
+              file=sys.stderr, flush=True)
+        del ref
     return out_d
+
+
+def profile_volume(sct, W, torch, dev, bundle):
+    """Kernel sequence of the 64-slice 1024^2 volume for rocprofv3: the fused
+    normal operator over all 64 slices (default chunks, then 16-image chunks)
+    and single-slice applies."""
+    w = W.WORKLOADS["volume_64x1024_f32"]
+    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=torch.float64,
+                     device=dev, tuning="default", bundle=bundle)
+    X = torch.randn((w.batch, op.nn), dtype=torch.float64, device=dev)
+    O = torch.empty_like(X)
+    for fr, ar in ((4, 8), (16, 16)):
+        op.tuning = {"fwd_rhs": fr, "adj_rhs": ar}
+        for _ in range(3):
+            op.normal(X, w.alpha, w.lam, out=O)
+        torch.cuda.synchronize()
+        print(f"# volume: 3 fused applies, chunks {fr}/{ar}", file=sys.stderr, flush=True)
+    for b in range(4):
+        op.normal(X[b:b + 1], w.alpha, w.lam, out=O[b:b + 1])
+    torch.cuda.synchronize()
+    print("# profile sequence done (volume)", file=sys.stderr, flush=True)
 
 
 def bench_autograd(op, w, torch, dev, vdt, t):
@@ -370,13 +460,33 @@ def main():
     w = W.WORKLOADS[WORKLOAD]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.profile_volume:
+        profile_volume(sct, W, torch, dev, args.bundle)
+        return
     t0 = time.perf_counter()
     vdt = torch.float64
-    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt, device=dev)
+    op_def = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                         device=dev, tuning="default")
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    print(f"# built operator: nnz={op.info.nnz} rows={op.rows} in {build_s:.2f} s", file=sys.stderr,
-          flush=True)
+    print(f"# built operator: nnz={op_def.info.nnz} rows={op_def.rows} in {build_s:.2f} s",
+          file=sys.stderr, flush=True)
+    # the autotuned operator the timed steps run: bundle width chosen over
+    # 16/32/64 by the normal operator's time, then the launch settings timed
+    from paper_1705_07497_amd import autotune
+    if args.profile or args.profile_fourier or args.profile_multi:
+        op = op_def
+        tuning_info = None
+    else:
+        t0 = time.perf_counter()
+        ch = autotune.choose_bundle(w.n, w.n_angles, w.n_bins, w.mask, torch.float32, vdt, dev, batch=1,
+                                    save=False)
+        op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                         device=dev, tuning="default", bundle=ch["bundle"])
+        autotune.autotune(op, batch=1, save=False)
+        tuning_info = {"bundle": op.bundle, **op.tuning, "tune_s": round(time.perf_counter() - t0, 2),
+                       "normal_us_by_bundle": {str(k): round(v * 1e6, 1) for k, v in ch["normal_s"].items()}}
+        print(f"# autotuned: bundle {op.bundle}, {op.tuning}", file=sys.stderr, flush=True)
 
     mu_np, eps_np = W.phantom_and_noise(w.n, w.n_ellipses, op.rows, seed=0)
     mu = torch.as_tensor(mu_np, dtype=vdt, device=dev).reshape(1, -1)
@@ -418,11 +528,17 @@ def main():
         for _ in range(20):
             op.normal(x, w.alpha, w.lam, out=out)
         op.cg(x, w.alpha, w.lam, n_iter=20)
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        # counter calibration: the project's stream kernels over 1 GiB, 5 times each
+        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        part = torch.empty(2048, dtype=torch.int32, device=dev)
+        for _ in range(5):
+            sct.bandwidth_probe(sct.PROBE_COPY, src, dst)
+        for _ in range(5):
+            sct.bandwidth_probe(sct.PROBE_READ, src, part)
         torch.cuda.synchronize()
-        print("# profile sequence done (copy of 1073741824 bytes)", file=sys.stderr, flush=True)
+        print("# profile sequence done (k_stream_copy and k_stream_read over 1073741824 bytes)",
+              file=sys.stderr, flush=True)
         return
     for _ in range(10):
         op.normal(x, w.alpha, w.lam, out=out)
@@ -436,6 +552,13 @@ def main():
     t_adj = timed(lambda: op.adj(ysb, out=out), args.applies)
     print(f"# normal {t_normal / args.applies * 1e6:.1f} us, fwd {t_fwd / args.applies * 1e6:.1f} us, "
           f"adj {t_adj / args.applies * 1e6:.1f} us", file=sys.stderr, flush=True)
+
+    x_def_out = torch.empty_like(x)
+    t_normal_def = timed(lambda: op_def.normal(x, w.alpha, w.lam, out=x_def_out), args.applies)
+    del op_def
+    ceiling = bandwidth_ceiling(sct, torch, dev)
+    print(f"# stream ceiling: copy {ceiling['copy_gbs']:.0f} GB/s, read {ceiling['read_gbs']:.0f} GB/s",
+          file=sys.stderr, flush=True)
 
     # timed split-Bregman reconstructions (the step)
     torch.cuda.synchronize()
@@ -483,7 +606,9 @@ def main():
     normal_bytes = bytes_fwd + bytes_adj
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(kname),
-                "kernel": kname, "avg_us": round(kavg * 1e6, 2), "algorithmic_bytes": kbytes}
+                "kernel": kname, "avg_us": round(kavg * 1e6, 2), "algorithmic_bytes": kbytes,
+                "ceiling_gbs": ceiling["read_gbs"],
+                "frac_of_ceiling": round(achieved / ceiling["read_gbs"], 4), "ceiling": ceiling}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "normal applies/s",
@@ -502,6 +627,8 @@ def main():
         "normal_apply_gbs": round(normal_bytes / (t_normal / args.applies) / 1e9, 1),
         "fwd_us": round(avg_fwd * 1e6, 2), "adj_us": round(avg_adj * 1e6, 2),
         "build_s": round(build_s, 3),
+        "tuning": tuning_info,
+        "normal_apply_default_per_s": round(args.applies / t_normal_def, 1),
         "roofline": roofline,
     }
 
@@ -527,7 +654,7 @@ def main():
     result["fourier"] = bench_fourier(sct, op, w, mu, torch, timed)
 
     if not args.no_batched:
-        result["batched"] = bench_batched(sct, W, torch, dev, vdt)
+        result["batched"] = bench_batched(sct, W, torch, dev, vdt, not args.no_verify)
 
     if not args.no_verify or not args.no_cpu:
         import oracle
@@ -552,6 +679,7 @@ def main():
                 "kind": "oracle",
                 "sample": f"{reps} FP64 normal applies of the same 512x512 / 180-angle operator "
                           f"({tc:.1f} s); oracle CSR build {oracle_build_s:.1f} s not included",
+                **host_cpu(),
             }
             print(f"# cpu oracle: {reps / tc:.2f} applies/s on {cores} threads", file=sys.stderr,
                   flush=True)

@@ -18,6 +18,7 @@ reading used for the 512 x 512 workloads).  Run:
     python -m paper_1705_07497_amd.study [--max-updates 6000] [--d 1 2 4]
                                           [--solvers exact surrogate fusing]
     python -m paper_1705_07497_amd.study --table1
+    python -m paper_1705_07497_amd.study --warm-start [K ...] [--d 1 2 4]
 """
 from __future__ import annotations
 
@@ -85,6 +86,86 @@ def run_case(sct, W, torch, d: int, max_updates: int, surrogate_radius: int | No
     return {"d": d, "angles": na, "updates": k, "time_s": elapsed, "found": found, "solver": label}
 
 
+def run_warm_start(sct, W, torch, d: int, k_sur: int, max_updates: int, radius: int = 3,
+                   alpha: float = 0.01, lam: float = 1.0, n_cg: int = 5, seed: int = 0,
+                   thresholds=(1e-2, 1e-4)):
+    """The surrogate as a warm start for the exact solver (Section 3.2 relies
+    on the outer iteration forgetting inner errors): k_sur surrogate updates,
+    then exact updates from that image (fresh d and b), against exact updates
+    from zero.  Update sizes are measured relative to the first update of the
+    cold exact run, so both variants stop at the same absolute size."""
+    n = 512
+    na = int(round(n * math.pi / (4 * d)))
+    nb = W.n_bins_for(n)
+    dev = torch.device("cuda", 0)
+    op = sct.RadonOp(n, na, nb, None, dtype=torch.float32, vec_dtype=torch.float64, device=dev)
+    sur = sct.RadonSurrogate(op, radius)
+    mu_np, eps = W.phantom_and_noise(n, 10, op.rows, seed=seed)
+    mu = torch.as_tensor(mu_np, dtype=torch.float64, device=dev).reshape(1, -1)
+    y = op.fwd(mu)
+    f = (y + 0.01 * torch.sqrt(torch.mean(y ** 2)).item()
+         * torch.as_tensor(eps, dtype=torch.float64, device=dev)).contiguous()
+    mu_l1 = float(mu.abs().sum())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1) / 1e3
+
+    def exact_until(u, warm, first, elapsed, key):
+        found, k = {}, 0
+        while k < max_updates and len(found) < len(thresholds):
+            if k == 0 and warm:
+                (_, info), dt = timed(lambda: op.sb(f, alpha, lam, 1, n_cg, mu0=u.clone(), out=u,
+                                                    ws_key=key))
+            else:
+                (_, info), dt = timed(lambda: op.sb(f, alpha, lam, 1, n_cg, resume=k > 0, out=u,
+                                                    ws_key=key))
+            elapsed += dt
+            k += 1
+            upd = sct.decode_sb_info(info)[0]["upd_b"]
+            first = upd if first is None else first
+            for t in thresholds:
+                if t not in found and upd / first < t:
+                    found[t] = (k, elapsed, float((u - mu).abs().sum()) / mu_l1)
+        return found, first, k
+
+    u = torch.empty_like(mu)
+    cold, first, _ = exact_until(u, False, None, 0.0, ("cold", d))
+    u = torch.empty_like(mu)
+    t_sur = 0.0
+    for k in range(k_sur):
+        _, dt = timed(lambda: op.sb(f, alpha, lam, 1, n_cg, resume=k > 0, out=u, ws_key=("sur", d),
+                                    surrogate=sur))
+        t_sur += dt
+    err_sur = float((u - mu).abs().sum()) / mu_l1
+    warm, _, _ = exact_until(u, True, first, t_sur, ("warm", d))
+    return {"d": d, "angles": na, "k_sur": k_sur, "sur_s": t_sur, "sur_err": err_sur, "cold": cold,
+            "warm": warm, "thresholds": thresholds}
+
+
+def warm_table(rows) -> str:
+    ts = rows[0]["thresholds"]
+    out = ["| d (angles) | surrogate updates (time, L1 err) | " +
+           " | ".join(f"{t:.0e}: exact alone | {t:.0e}: after surrogate" for t in ts) + " |",
+           "|---|---|" + "---|---|" * len(ts)]
+    for r in rows:
+        cells = []
+        for t in ts:
+            for v in (r["cold"], r["warm"]):
+                if t in v:
+                    k, s, e = v[t]
+                    cells.append(f"{k} upd, {s:.2f} s, err {e:.4g}")
+                else:
+                    cells.append("(*)")
+        out.append(f"| {r['d']} ({r['angles']}) | {r['k_sur']} ({r['sur_s']:.3f} s, {r['sur_err']:.3g}) | "
+                   + " | ".join(cells) + " |")
+    return "\n".join(out)
+
+
 def table(rows) -> str:
     out = ["| d (angles) | solver | " + " | ".join(f"{t:.0e}" for t in THRESHOLDS) + " |",
            "|---|---|" + "---|" * len(THRESHOLDS)]
@@ -150,12 +231,25 @@ def main(argv=None) -> None:
                     choices=["exact", "surrogate", "fusing"])
     ap.add_argument("--table1", action="store_true",
                     help="per-evaluation times in the configurations of Table 1 instead")
+    ap.add_argument("--warm-start", type=int, nargs="*", default=None, metavar="K",
+                    help="the surrogate as a warm start: K surrogate updates, then exact updates to "
+                         "1e-2 and 1e-4 of the cold run's first update, against exact alone")
     args = ap.parse_args(argv)
     import torch
     import workloads as W
     import paper_1705_07497_amd as sct
     if args.table1:
         print(table1(sct, W, torch))
+        return
+    if args.warm_start is not None:
+        rows = []
+        for d in args.d:
+            for k in args.warm_start or [10, 30, 100]:
+                r = run_warm_start(sct, W, torch, d, k, min(args.max_updates, 3000),
+                                   args.surrogate_radius)
+                rows.append(r)
+                print(f"# warm start d={d} k={k} done", file=sys.stderr, flush=True)
+        print(warm_table(rows))
         return
     rows = []
     for d in args.d:
