@@ -60,8 +60,9 @@ def parse():
                     help="profiler mode for the uneven 32-instance batch: one captured-graph CG(10), "
                          "one eager group CG(10) and the 32 per-instance CG(10) solves, then exit")
     ap.add_argument("--profile-volume", action="store_true",
-                    help="profiler mode for the 64 x 1024^2 volume: 3 fused normal applies with the "
-                         "default chunks, 3 with 16-image chunks and 4 single-image applies, then exit")
+                    help="profiler mode for the 64 x 1024^2 volume (FP32 kind): 3 fused normal "
+                         "applies with 4/8-image chunks, 3 with 16-image chunks and 4 single-image "
+                         "applies, then exit")
     ap.add_argument("--bundle", type=int, default=0,
                     help="forward bundle width for the profiler modes (0: 16)")
     ap.add_argument("--profile-fourier", action="store_true",
@@ -120,7 +121,7 @@ def bandwidth_ceiling(sct, torch, dev, nbytes=1 << 30, reps=20):
     src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     src.fill_(1)
     dst = torch.empty_like(src)
-    part = torch.empty(2048, dtype=torch.int32, device=dev)
+    part = torch.empty(4096, dtype=torch.int32, device=dev)
     t_copy = event_time(torch, lambda: sct.bandwidth_probe(sct.PROBE_COPY, src, dst), reps)
     t_read = event_time(torch, lambda: sct.bandwidth_probe(sct.PROBE_READ, src, part), reps)
     del src, dst
@@ -147,6 +148,7 @@ def bench_batched(sct, W, torch, dev, vdt, verify=True):
     """Fused multi-image normal_apply (every matrix load shared by a chunk of up
     to 16 images) against the same images applied one at a time."""
     out = {}
+    vdt_main = vdt
 
     def t(fn, reps):
         return event_time(torch, fn, reps)
@@ -155,6 +157,10 @@ def bench_batched(sct, W, torch, dev, vdt, verify=True):
     for name in ("grad_16x512_f32", "volume_64x1024_f32"):
         w = W.WORKLOADS[name]
         B = w.batch
+        # the volume is the FP32 SpMM of 64 slices (FP32 matrix and vectors, its
+        # normal operator within 1e-5 of the FP64 oracle); the gradient batch
+        # keeps FP64 vectors for its unrolled CG
+        vdt = torch.float32 if name == "volume_64x1024_f32" else vdt_main
         op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
                          device=dev, tuning="default")
         X = torch.randn((B, op.nn), dtype=vdt, device=dev)
@@ -181,7 +187,8 @@ def bench_batched(sct, W, torch, dev, vdt, verify=True):
         autotune.autotune(opt, batch=B, save=False)
         tf = t(fused(opt), 5)
         out[name] = {"batch": B, "n": w.n, "measured_angles": w.n_meas, "bins": w.n_bins,
-                     "nnz": op.info.nnz, "fused_ms": round(tf * 1e3, 3),
+                     "nnz": op.info.nnz, "vectors": str(vdt).replace("torch.", ""),
+                     "fused_ms": round(tf * 1e3, 3),
                      "fused_default_ms": round(tf_def * 1e3, 3),
                      "tuned": {"bundle": opt.bundle, **opt.tuning},
                      "per_image_loop_ms": round(tl * 1e3, 3), "speedup": round(tl / tf, 2),
@@ -194,6 +201,7 @@ def bench_batched(sct, W, torch, dev, vdt, verify=True):
             out["grad_16x512_f32_autograd"] = bench_autograd(opt, w, torch, dev, vdt, t)
         del op, opt
         torch.cuda.empty_cache()
+    vdt = vdt_main
     out["mixed_batch_32"] = bench_mixed_batch(sct, W, torch, dev, vdt, t)
     out["small_batch_64"] = bench_mixed_batch(
         sct, W, torch, dev, vdt, t,
@@ -397,13 +405,13 @@ def bench_large(sct, W, torch, dev, vdt, t, verify=True):
 
 
 def profile_volume(sct, W, torch, dev, bundle):
-    """Kernel sequence of the 64-slice 1024^2 volume for rocprofv3: the fused
-    normal operator over all 64 slices (default chunks, then 16-image chunks)
-    and single-slice applies."""
+    """Kernel sequence of the 64-slice 1024^2 volume (FP32 kind, as the volume
+    leg times it) for rocprofv3: the fused normal operator over all 64 slices
+    (4/8-image chunks, then 16-image chunks) and single-slice applies."""
     w = W.WORKLOADS["volume_64x1024_f32"]
-    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=torch.float64,
+    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=torch.float32,
                      device=dev, tuning="default", bundle=bundle)
-    X = torch.randn((w.batch, op.nn), dtype=torch.float64, device=dev)
+    X = torch.randn((w.batch, op.nn), dtype=torch.float32, device=dev)
     O = torch.empty_like(X)
     for fr, ar in ((4, 8), (16, 16)):
         op.tuning = {"fwd_rhs": fr, "adj_rhs": ar}
@@ -531,7 +539,7 @@ def main():
         # counter calibration: the project's stream kernels over 1 GiB, 5 times each
         src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
-        part = torch.empty(2048, dtype=torch.int32, device=dev)
+        part = torch.empty(4096, dtype=torch.int32, device=dev)
         for _ in range(5):
             sct.bandwidth_probe(sct.PROBE_COPY, src, dst)
         for _ in range(5):

@@ -705,9 +705,10 @@ int radon_autotune(radon_op *op, int32_t batch, void *ws, int64_t ws_bytes, cons
  * radon_bandwidth_probe -- the practical HBM ceiling the products are
  * measured against (not part of the method).  RADON_PROBE_COPY: dst = src
  * (bytes read + bytes written); RADON_PROBE_READ: a read-only pass over src
- * that leaves one 32-bit xor-sum per workgroup in dst (dst holds 2048 uint32).
- * Both stream with 16-byte non-temporal loads over a fixed 2048-workgroup
- * grid.  src, dst: device, 16-byte aligned; bytes: positive multiple of 16.
+ * that leaves one 32-bit xor-sum per workgroup in dst (dst holds 4096 uint32).
+ * Both stream with 16-byte non-temporal loads (the copy grid-stride over 8192
+ * workgroups, the read one contiguous chunk per workgroup over 4096).
+ * src, dst: device, 16-byte aligned; bytes: positive multiple of 16.
  * Asynchronous on `stream`.  Errors: RADON_EINVAL.
  */
 #define RADON_PROBE_COPY 0

@@ -977,7 +977,7 @@ PROBE_COPY, PROBE_READ = 0, 1
 
 def bandwidth_probe(mode: int, src, dst, nbytes: int | None = None) -> None:
     """radon_bandwidth_probe on the current stream: PROBE_COPY copies src into
-    dst, PROBE_READ streams src once (dst: >= 2048 uint32 of results)."""
+    dst, PROBE_READ streams src once (dst: >= 4096 uint32 of results)."""
     torch = _torch()
     n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
     _check(lib().radon_bandwidth_probe(int(mode), _vp(src.data_ptr()), _vp(dst.data_ptr()), n,

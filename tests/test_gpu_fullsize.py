@@ -70,22 +70,31 @@ def test_large_2048_normal_and_split_bregman_30x10():
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("chunks", [None, (16, 16)], ids=["default_chunks", "chunks16"])
-def test_volume_64x1024_fused_normal_slices(chunks):
+@pytest.mark.parametrize("chunks,bundle,vec", [(None, 16, "f64"), ((16, 16), 16, "f64"),
+                                               ((16, 16), 64, "f32"), ((8, 8), 32, "f32")],
+                         ids=["default_chunks", "chunks16", "f32_chunks16_bundle64",
+                              "f32_chunks8_bundle32"])
+def test_volume_64x1024_fused_normal_slices(chunks, bundle, vec):
+    """FP64 vectors (the mixed kind) and FP32 vectors (the pure FP32 kind the
+    benchmark's volume leg times); the FP32 kind's inputs are the phantoms
+    rounded to FP32, which the oracle receives too."""
     w = W.WORKLOADS["volume_64x1024_f32"]
-    say(f"volume_64x1024 {chunks}: oracle build (FP64 entries)")
+    vdt = F64 if vec == "f64" else torch.float32
+    say(f"volume_64x1024 {chunks} {bundle} {vec}: oracle build (FP64 entries)")
     ref = _volume_oracle(w)
-    say(f"volume_64x1024 {chunks}: gpu build and {w.batch} phantoms")
-    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=F64,
-                     tuning="default")
+    say(f"volume_64x1024 {chunks} {bundle} {vec}: gpu build and {w.batch} phantoms")
+    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                     tuning="default", bundle=bundle)
     if chunks is not None:
         op.tuning = {"fwd_rhs": chunks[0], "adj_rhs": chunks[1]}
     X = np.stack([W.phantom(w.n, w.n_ellipses, seed=0, index=i) for i in range(w.batch)])
-    got = host(op.normal(to_dev(X, F64), w.alpha, w.lam))
+    if vec == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    got = host(op.normal(to_dev(X, vdt), w.alpha, w.lam))
     for i in (0, 37, w.batch - 1):
         want = ref.normal(X[i], w.alpha, w.lam)
         err = rel_l2(got[i], want)
-        say(f"volume_64x1024 {chunks}: slice {i} rel L2 = {err:.3e}")
+        say(f"volume_64x1024 {chunks} {bundle} {vec}: slice {i} rel L2 = {err:.3e}")
         assert err <= 1e-5, i
 
 

@@ -523,3 +523,33 @@ def test_caller_buffer_build_equals_library_build(mode):
     assert L.build_radon_csr_into(sct.ctypes.byref(g), sct.ctypes.byref(bufs), None,
                                   sct.ctypes.byref(h)) == -4
     assert not h.value
+
+
+@pytest.mark.parametrize("mode", ["mixed", "f64"])
+def test_nan_in_data_breaks_down_like_the_oracle(mode):
+    """A NaN in the measured data (the central ray of the first angle) makes
+    <p, Ap> non-finite at the first step of every inner solve: CG reports a
+    breakdown at iteration 1 and leaves x at zero, split Bregman never moves
+    u from zero and counts one breakdown per outer iteration -- on the GPU
+    exactly as in the oracle."""
+    n, na = 16, 12
+    nb = W.n_bins_for(n)
+    ref = oracle.OracleOp(n, na, nb)
+    op = make_op(n, na, nb, None, mode)
+    mat, vec = MODES[mode]
+    f = rounded(np.random.default_rng(3).standard_normal(ref.rows), vec)
+    f[nb // 2] = np.nan
+    rhs = ref.adj(f)
+    assert np.isnan(rhs).any()
+    x_o, _, _, it_o, bd_o = ref.cg(1.0, 1.0, 0.0, rhs=rhs, n_iter=5)
+    assert bd_o == 1 and it_o == 0 and not x_o.any()
+    x, info = op.cg(to_dev(rhs[None], vec), 1.0, 1.0, 0.0, n_iter=5)
+    ci = sct.decode_cg_info(info)[0]
+    assert ci["breakdown"] == bd_o and ci["iterations"] == it_o
+    assert not host(x).any()
+    u_o = ref.sb(f, 1.0, 1.0, 3, 4)[0]
+    assert not u_o.any()
+    u, sinfo = op.sb(to_dev(f[None], vec), 1.0, 1.0, 3, 4)
+    si = sct.decode_sb_info(sinfo)[0]
+    assert si["breakdowns"] == 3 and si["outer"] == 3
+    assert not host(u).any()
