@@ -19,7 +19,8 @@ namespace sct {
 // ---------------------------------------------------------------------------
 
 // Single right-hand side version of k_adj below (kept separate: the fused
-// multi-RHS form compiles to a slower loop for one image).
+// multi-RHS form compiles to a slower loop for one image), over the same tile
+// order.
 template <class TM, class T, int W>
 __global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel,
                                                 const uint16_t *__restrict__ base,
@@ -28,7 +29,8 @@ __global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel
                                                 const T *__restrict__ y, const T *__restrict__ x,
                                                 T *__restrict__ out, T alpha, T lambda, T sigma,
                                                 double *__restrict__ part, int n, int tiles,
-                                                int64_t nn, int64_t rows)
+                                                int64_t nn, int64_t rows,
+                                                const int32_t *__restrict__ order, int64_t n_order)
 {
     using Q = typename Quad<TM>::type;
     __shared__ T band[W * 4 * kAdjBand];
@@ -41,7 +43,11 @@ __global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel
     const Q *__restrict__ A = reinterpret_cast<const Q *>(v0);
     const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1);
     double dsum = 0.0;   // this block's share of <x, out>, tiles in a fixed order
-    for (int64_t g = blockIdx.x; g < n_ag; g += gridDim.x) {
+    // the tiles in the XCD-compact order of k_adj: a block visits the same
+    // tiles as there, so one image's <x, out> partials equal a chunk's
+    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+        const int64_t g = order[o];
+        if (g < 0) continue;   // padding entry (uniform per block)
         const T acc = adj_tile1<TM, T, W>(g, Rl, base, A, Bv, n_meas, n_aq, nb, yb, band, bases);
         if (wave == 0)
             dsum += adj_epilogue(g, lane, acc, xb, out + bat * nn, alpha, lambda, sigma, n, tiles);
@@ -53,7 +59,9 @@ __global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel
 }
 
 // Adjoint: one workgroup of W waves per 8x8 pixel tile (persistent loop over
-// tiles).  Wave w sums its share of the measured-angle quads for the tile's
+// the tiles in `order`, the XCD-compact order: the tiles a workgroup on XCD x
+// visits lie in one compact region of the image, so the sinogram bands the
+// XCD's concurrent tiles read stay in its L2 for every image of the chunk).  Wave w sums its share of the measured-angle quads for the tile's
 // 64 pixels.  Per quad it stages the tile's sinogram band (16 bins from the
 // tile's base bin, for each of the 4 angles: exactly one 64-lane load) in LDS
 // and reads the pixel's two bins from there, so the vector-memory pipeline
@@ -70,7 +78,8 @@ __global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
                                                 const T *__restrict__ y, const T *__restrict__ x,
                                                 T *__restrict__ out, T alpha, T lambda, T sigma,
                                                 double *__restrict__ part, int n, int tiles,
-                                                int64_t nn, int64_t rows, int batch)
+                                                int64_t nn, int64_t rows, int batch,
+                                                const int32_t *__restrict__ order, int64_t n_order)
 {
     using Q = typename Quad<TM>::type;
     __shared__ T band[W][BC][4 * kAdjBand];
@@ -87,7 +96,9 @@ __global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
     double dsum[BC];                            // this block's share of <x, out>
 #pragma unroll
     for (int c = 0; c < BC; ++c) dsum[c] = 0.0;
-    for (int64_t g = blockIdx.x; g < n_ag; g += gridDim.x) {
+    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+        const int64_t g = order[o];
+        if (g < 0) continue;   // padding entry (uniform per block)
         T acc[BC];
 #pragma unroll
         for (int c = 0; c < BC; ++c) acc[c] = T(0);
@@ -207,13 +218,28 @@ static int rhs_chunk(int batch, int limit)
     return 1;
 }
 
-// The band partials of a call: one per band, ray and image (none beyond
-// 4 GiB of scratch; such calls keep the bundle order).
+int fwd_chunk(const Op &op, int batch) { return rhs_chunk(batch, op.tune.fwd_rhs); }
+
+const BandSet *band_set_for(const Op &op, int bc)
+{
+    const int64_t line = int64_t(op.n) * op.vsize;
+    if (op.n < kBandMinN && int64_t(bc) * op.n * line <= kBandBudget) return nullptr;
+    const BandSet *last = nullptr;
+    for (const BandSet &b : op.bands) {
+        if (b.n_bands <= 0) continue;
+        if (int64_t(bc) * b.lines * line <= kBandBudget) return &b;
+        last = &b;
+    }
+    return last;   // the lowest bands even where a chunk's band overflows the budget
+}
+
+// The band partials of a call: one per band, ray and image of one chunk.
 int64_t fwd_part_elems(const Op &op, int batch)
 {
-    if (op.n_bands <= 0) return 0;
-    const int64_t e = int64_t(op.n_bands) * op.rows * batch;
-    return e * op.vsize > (int64_t(1) << 32) ? 0 : e;
+    const int bc = fwd_chunk(op, batch);
+    const BandSet *b = band_set_for(op, bc);
+    if (!b) return 0;
+    return int64_t(b->n_bands) * op.rows * (batch < bc ? batch : bc);
 }
 
 template <class TM, class TV>
@@ -244,11 +270,20 @@ static void adj_wbc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV l
     if constexpr (BC == 1)
         k_adj1<TM, TV, W><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.n_ag, op.n_meas,
                                                  op.n_aq, op.n_bins, y, x, out, al, la, si, part,
-                                                 op.n, op.tiles, op.nn, op.rows);
-    else
-        k_adj<TM, TV, W, BC><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.n_ag, op.n_meas,
-                                                    op.n_aq, op.n_bins, y, x, out, al, la, si, part,
-                                                    op.n, op.tiles, op.nn, op.rows, batch);
+                                                 op.n, op.tiles, op.nn, op.rows, op.a_order,
+                                                 op.n_a_order);
+    else {
+        // chunks one after another: a chunk's sinograms share the XCDs' L2
+        const unsigned G = grid.x;
+        for (int c0 = 0; c0 < batch; c0 += BC) {
+            const int nb = batch - c0 < BC ? batch - c0 : BC;
+            k_adj<TM, TV, W, BC><<<dim3(G, 1u), 64 * W, 0, s>>>(
+                op.a_rel, op.a_base, a0, a1, op.n_ag, op.n_meas, op.n_aq, op.n_bins,
+                y + int64_t(c0) * op.rows, x ? x + int64_t(c0) * op.nn : nullptr,
+                out + int64_t(c0) * op.nn, al, la, si, part ? part + int64_t(c0) * G : nullptr, op.n,
+                op.tiles, op.nn, op.rows, nb, op.a_order, op.n_a_order);
+        }
+    }
 }
 
 template <class TM, class TV, int BC>

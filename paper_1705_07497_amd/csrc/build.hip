@@ -9,6 +9,7 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -419,7 +420,8 @@ struct Carve {
 struct Plan {
     int64_t nnz = 0, fslots = 0;
     std::vector<int32_t> order;   // block -> bundle of the forward product
-    std::vector<int2> border;     // (bundle, band) items of the line-banded forward
+    std::vector<int2> border[4];  // (bundle, band) items of the line-banded forward, per height
+    std::vector<int32_t> aorder;  // adjoint tile order of the fused products
 };
 
 static int64_t up256(int64_t b) { return (b + 255) & ~int64_t(255); }
@@ -466,7 +468,9 @@ static int64_t layout_bytes(const Op &op, const Plan &pl)
     b += up256(int64_t(sizeof(FwdBundle)) * n_fb_of(op));
     b += up256(2 * pl.fslots) + 2 * up256(es * pl.fslots);
     b += up256(op.a_slots) + up256(2 * op.n_ag * op.n_aq * 4) + 2 * up256(es * op.a_slots);
-    b += up256(4 * int64_t(pl.order.size())) + up256(8 * int64_t(pl.border.size()));
+    b += up256(4 * int64_t(pl.order.size()));
+    for (const auto &bo : pl.border) b += up256(8 * int64_t(bo.size()));
+    b += up256(4 * int64_t(pl.aorder.size()));
     return b;
 }
 
@@ -560,36 +564,63 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
         }
     }
 
-    // Line-banded order for large images: (bundle, band) items, band-major
-    // within each gather class, on the same XCD split.  Item (B, band)
+    // Line-banded orders: (bundle, band) items, band-major within each gather
+    // class, on the same XCD split, one list per band height.  Item (B, band)
     // exists when a quad of B starts in the band.
-    pl.border.clear();
-    if (op.n >= kBandMinN) {
-        const int n_bands = (op.n + kBandLines - 1) / kBandLines;
+    for (int h = 0; h < 4; ++h) {
+        pl.border[h].clear();
+        if (op.n < kBandSetMinN) continue;
+        const int L = kBandHeights[h];
+        const int n_bands = (op.n + L - 1) / L;
         std::vector<int2> BV, BH;
         for (int band = 0; band < n_bands; ++band)
             for (int64_t b = 0; b < op.n_fb; ++b) {
                 const FwdBundle &d = hb[size_t(b)];
                 if (d.nrows <= 0) continue;
-                const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
+                const int lo = d.m0 / L, hi = (d.m0 + d.nrows - 4) / L;
                 if (band < lo || band > hi) continue;
                 (d.horiz ? BH : BV).push_back(make_int2(int(b), band));
             }
         const int64_t bv = kv ? (int64_t(BV.size()) + kv - 1) / kv : 0;
         const int64_t bh = kv < nx ? (int64_t(BH.size()) + (nx - kv) - 1) / (nx - kv) : 0;
         const int64_t brounds = bv > bh ? bv : bh;
-        pl.border.assign(size_t(brounds * nx > 0 ? brounds * nx : 1), make_int2(-1, -1));
+        std::vector<int2> &border = pl.border[h];
+        border.assign(size_t(brounds * nx > 0 ? brounds * nx : 1), make_int2(-1, -1));
         for (int64_t i = 0; i < brounds * nx; ++i) {
             const int xcd = int(i % nx);
             const int64_t j = i / nx;
             if (xcd < kv) {
                 const int64_t k = j * kv + xcd;
-                if (k < int64_t(BV.size())) pl.border[size_t(i)] = BV[size_t(k)];
+                if (k < int64_t(BV.size())) border[size_t(i)] = BV[size_t(k)];
             } else {
                 const int64_t k = j * (nx - kv) + (xcd - kv);
-                if (k < int64_t(BH.size())) pl.border[size_t(i)] = BH[size_t(k)];
+                if (k < int64_t(BH.size())) border[size_t(i)] = BH[size_t(k)];
             }
         }
+    }
+
+    // Adjoint tile order of the fused products: tiles by Morton code of
+    // (tile row, tile column), cut into 8 consecutive runs; entry i belongs to
+    // run i % 8, so the workgroups of XCD x walk run x.
+    {
+        const int T = op.tiles;
+        std::vector<std::pair<uint64_t, int32_t>> mt;
+        mt.reserve(size_t(op.n_ag));
+        for (int ty = 0; ty < T; ++ty)
+            for (int tx = 0; tx < T; ++tx) {
+                uint64_t code = 0;
+                for (int bit = 0; bit < 16; ++bit)
+                    code |= (uint64_t((tx >> bit) & 1) << (2 * bit)) | (uint64_t((ty >> bit) & 1) << (2 * bit + 1));
+                mt.emplace_back(code, ty * T + tx);
+            }
+        std::sort(mt.begin(), mt.end());
+        const int64_t per = (op.n_ag + nx - 1) / nx;
+        pl.aorder.assign(size_t(per * nx), -1);
+        for (int64_t r = 0; r < nx; ++r)
+            for (int64_t j = 0; j < per; ++j) {
+                const int64_t k = r * per + j;
+                if (k < op.n_ag) pl.aorder[size_t(j * nx + r)] = mt[size_t(k)].second;
+            }
     }
     return RADON_OK;
 }
@@ -631,9 +662,11 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     SCT_TRY(check_launch("k_adj_finish"));
 
     SCT_HIP(hipMemcpyAsync(op.fb_order, pl.order.data(), 4 * pl.order.size(), hipMemcpyHostToDevice, st));
-    if (op.n_bands > 0)
-        SCT_HIP(hipMemcpyAsync(op.fb_band_order, pl.border.data(), 8 * pl.border.size(),
-                               hipMemcpyHostToDevice, st));
+    for (int h = 0; h < 4; ++h)
+        if (op.bands[h].n_bands > 0)
+            SCT_HIP(hipMemcpyAsync(op.bands[h].order, pl.border[h].data(), 8 * pl.border[h].size(),
+                                   hipMemcpyHostToDevice, st));
+    SCT_HIP(hipMemcpyAsync(op.a_order, pl.aorder.data(), 4 * pl.aorder.size(), hipMemcpyHostToDevice, st));
 
     int32_t bad_h = 0;
     SCT_HIP(hipMemcpyAsync(&bad_h, t.bad, 4, hipMemcpyDeviceToHost, st));
@@ -660,10 +693,21 @@ static int carve_layouts(Op &op, const Plan &pl, Carve &lay, bool fb_taken)
     SCT_TRY(lay.take(&op.a_v1, es * op.a_slots));
     op.n_order = int64_t(pl.order.size());
     SCT_TRY(lay.take(&op.fb_order, 4 * op.n_order));
-    op.n_bands = pl.border.empty() ? 0 : (op.n + kBandLines - 1) / kBandLines;
-    op.n_band_order = int64_t(pl.border.size());
-    op.fb_band_order = nullptr;
-    if (op.n_bands > 0) SCT_TRY(lay.take(&op.fb_band_order, 8 * op.n_band_order));
+    for (int h = 0; h < 4; ++h) {
+        BandSet &b = op.bands[h];
+        b.lines = kBandHeights[h];
+        b.n_bands = pl.border[h].empty() ? 0 : (op.n + b.lines - 1) / b.lines;
+        b.n_order = int64_t(pl.border[h].size());
+        b.order = nullptr;
+        if (b.n_bands > 0) SCT_TRY(lay.take(&b.order, 8 * b.n_order));
+    }
+    static_assert(kBandHeights[0] == kBandLines, "the first band set is the single-image one");
+    const bool single = op.n >= kBandMinN && op.bands[0].n_bands > 0;
+    op.n_bands = single ? op.bands[0].n_bands : 0;
+    op.n_band_order = single ? op.bands[0].n_order : 0;
+    op.fb_band_order = single ? op.bands[0].order : nullptr;
+    op.n_a_order = int64_t(pl.aorder.size());
+    SCT_TRY(lay.take(&op.a_order, 4 * op.n_a_order));
     return RADON_OK;
 }
 

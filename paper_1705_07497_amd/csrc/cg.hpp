@@ -45,16 +45,17 @@ inline int tiles_of(int n) { return (n + 31) / 32; }
 
 __device__ inline double block_sum(double v, double *red)
 {
-    // fixed-order tree over the block (blockDim.x * blockDim.y threads, a power of two)
+    // fixed order over the block (blockDim.x * blockDim.y threads, a multiple
+    // of 64): a butterfly inside each wave (every lane ends with the same
+    // bits, as IEEE addition commutes), then the wave sums in wave order
     const int nt = blockDim.x * blockDim.y;
     const int t = threadIdx.y * blockDim.x + threadIdx.x;
-    red[t] = v;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if ((t & 63) == 0) red[t >> 6] = v;
     __syncthreads();
-    for (int o = nt / 2; o >= 1; o >>= 1) {
-        if (t < o) red[t] += red[t + o];
-        __syncthreads();
-    }
-    const double r = red[0];
+    double r = red[0];
+    for (int w = 1; w < (nt >> 6); ++w) r += red[w];
     __syncthreads();
     return r;
 }

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict
                                                      const TM *__restrict__ v0, const TM *__restrict__ v1,
                                                      const TV *__restrict__ x, const TV *__restrict__ xT,
                                                      TV *__restrict__ part, int n, int64_t nn,
-                                                     int64_t rows, int n_bands, int batch)
+                                                     int64_t rows, int n_bands, int lines, int batch)
 {
     const int b0 = int(blockIdx.y) * BC;
     const int nbc = min(BC, batch - b0);
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict
         if (it.x < 0) continue;        // padding entry (uniform per block)
         const FwdBundle d = fb[it.x];
         const int nq = d.nrows >> 2;
-        const int lo = it.y * kBandLines - d.m0, hi = lo + kBandLines;
+        const int lo = it.y * lines - d.m0, hi = lo + lines;
         const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
         const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
         fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b0) * nn,
@@ -92,41 +92,56 @@ inline void fwd_bcw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, h
 }
 
 template <class TM, class TV, int W, int BC, int BW>
-inline void fwd_band_wbc(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
-                         hipStream_t s)
+inline void fwd_band_wbc(const Op &op, const BandSet &bs, const TV *x, const TV *xT, TV *y, TV *part,
+                         int batch, hipStream_t s)
 {
-    const int64_t g = op.n_band_order < kPersistentBlocks ? op.n_band_order : kPersistentBlocks;
-    const unsigned chunks = unsigned((batch + BC - 1) / BC);
-    k_fwd_band<TM, TV, W, BC, BW><<<dim3(unsigned(g), chunks), 64 * W, 0, s>>>(
-        op.fb, op.fb_band_order, op.n_band_order, op.f_idx, static_cast<const TM *>(op.f_v0),
-        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, op.n_bands,
-        batch);
+    const int64_t g = bs.n_order < kPersistentBlocks ? bs.n_order : kPersistentBlocks;
+    k_fwd_band<TM, TV, W, BC, BW><<<dim3(unsigned(g), 1u), 64 * W, 0, s>>>(
+        op.fb, bs.order, bs.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
+        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, bs.n_bands,
+        bs.lines, batch);
     const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
     k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(batch)), 256, 0, s>>>(
-        op.fb, part, y, op.rows, op.n_bins, nbpa, op.bw, op.n_bands);
+        op.fb, part, y, op.rows, op.n_bins, nbpa, op.bw, bs.n_bands, bs.lines);
 }
 
 template <class TM, class TV, int BC, int BW>
-inline void fwd_band_bcw(const Op &op, const TV *x, const TV *xT, TV *y, TV *part, int batch,
-                         hipStream_t s)
+inline void fwd_band_bcw(const Op &op, const BandSet &bs, const TV *x, const TV *xT, TV *y, TV *part,
+                         int batch, hipStream_t s)
 {
-    if (op.tune.fwd_waves == 2) fwd_band_wbc<TM, TV, 2, BC, BW>(op, x, xT, y, part, batch, s);
-    else fwd_band_wbc<TM, TV, 4, BC, BW>(op, x, xT, y, part, batch, s);
+    if (op.tune.fwd_waves == 2) fwd_band_wbc<TM, TV, 2, BC, BW>(op, bs, x, xT, y, part, batch, s);
+    else fwd_band_wbc<TM, TV, 4, BC, BW>(op, bs, x, xT, y, part, batch, s);
+}
+
+// Line-banded forward over chunks of bc images, one chunk after another (a
+// chunk's band of images is what an XCD's L2 holds; chunks launched side by
+// side would share it).  part holds one chunk's partials.
+template <class TM, class TV, int BC, int BW>
+inline void fwd_band_chunks(const Op &op, const BandSet &bs, const TV *x, const TV *xT, TV *y, TV *part,
+                            int batch, hipStream_t s)
+{
+    for (int c0 = 0; c0 < batch; c0 += BC) {
+        const int nb = batch - c0 < BC ? batch - c0 : BC;
+        fwd_band_bcw<TM, TV, BC, BW>(op, bs, x + int64_t(c0) * op.nn, xT ? xT + int64_t(c0) * op.nn : nullptr,
+                                     y + int64_t(c0) * op.rows, part, nb, s);
+    }
 }
 
 template <class TM, class TV, int BW>
 int launch_fwd_bw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s, TV *part)
 {
-    if (part && fwd_part_elems(op, batch) > 0) {
-        switch (fwd_rhs_chunk(batch, op.tune.fwd_rhs)) {
-        case 16: fwd_band_bcw<TM, TV, 16, BW>(op, x, xT, y, part, batch, s); break;
-        case 8: fwd_band_bcw<TM, TV, 8, BW>(op, x, xT, y, part, batch, s); break;
-        case 4: fwd_band_bcw<TM, TV, 4, BW>(op, x, xT, y, part, batch, s); break;
-        default: fwd_band_bcw<TM, TV, 1, BW>(op, x, xT, y, part, batch, s); break;
+    const int bc = fwd_rhs_chunk(batch, op.tune.fwd_rhs);
+    const BandSet *bs = part ? band_set_for(op, bc) : nullptr;
+    if (bs) {
+        switch (bc) {
+        case 16: fwd_band_chunks<TM, TV, 16, BW>(op, *bs, x, xT, y, part, batch, s); break;
+        case 8: fwd_band_chunks<TM, TV, 8, BW>(op, *bs, x, xT, y, part, batch, s); break;
+        case 4: fwd_band_chunks<TM, TV, 4, BW>(op, *bs, x, xT, y, part, batch, s); break;
+        default: fwd_band_chunks<TM, TV, 1, BW>(op, *bs, x, xT, y, part, batch, s); break;
         }
         return check_launch("k_fwd_band");
     }
-    switch (fwd_rhs_chunk(batch, op.tune.fwd_rhs)) {
+    switch (bc) {
     case 16: fwd_bcw<TM, TV, 16, BW>(op, x, xT, y, batch, s); break;
     case 8: fwd_bcw<TM, TV, 8, BW>(op, x, xT, y, batch, s); break;
     case 4: fwd_bcw<TM, TV, 4, BW>(op, x, xT, y, batch, s); break;

@@ -43,6 +43,19 @@ constexpr int kAdjLanes = 64;
 constexpr int kBandLines = 128;
 constexpr int kBandMinN = 1024;
 constexpr int kAdjBand = 16;
+// Fused multi-image forwards gather from every image of their chunk, so the
+// band that stays in an XCD's L2 is the chunk's images' band together: the
+// band height is the largest of these whose chunk band fits the budget.
+constexpr int kBandHeights[4] = {128, 64, 32, 16};
+constexpr int64_t kBandBudget = int64_t(2) << 20;
+constexpr int kBandSetMinN = 256;   // band sets are built from this image side on
+
+// One band height's work list of the line-banded forward.
+struct BandSet {
+    int32_t lines = 0, n_bands = 0;
+    int2 *order = nullptr;           // (bundle, band), padding (-1, -1)
+    int64_t n_order = 0;
+};
 
 __host__ __device__ inline int64_t fwd_slot(int64_t off, int t, int r, int bw)
 {
@@ -105,10 +118,21 @@ struct Op {
 
     // line bands of the forward product for images larger than an XCD's L2:
     // work items (bundle, band) in band-major order per XCD, one partial sum
-    // per band and ray, added in band order by k_fwd_band_sum
-    int32_t n_bands = 0;             // 0: no banded path
-    int2 *fb_band_order = nullptr;   // (bundle, band), padding (-1, -1)
+    // per band and ray, added in band order by k_fwd_band_sum.  bands[i] has
+    // kBandHeights[i] lines; the single-image path and the group use the
+    // 128-line set (n_bands > 0 from kBandMinN on), fused chunks the height
+    // their chunk fits.
+    BandSet bands[4];
+    int32_t n_bands = 0;             // 0: no banded single-image path
+    int2 *fb_band_order = nullptr;   // = bands[0].order when n_bands > 0
     int64_t n_band_order = 0;
+
+    // adjoint tile order of the fused multi-image product: the tiles in Morton
+    // order cut into 8 runs, run x taken by the workgroups on XCD x, so each
+    // XCD's concurrently active tiles form a compact region whose sinogram
+    // bands stay in its L2; entries -1 pad each run
+    int32_t *a_order = nullptr;
+    int64_t n_a_order = 0;
 
     radon_tuning tune{2, 0, 4, 8};   // launch tuning (see radon_set_tuning)
 };
@@ -189,8 +213,14 @@ int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStr
 template <class TM, class TV, int BW>
 int launch_fwd_bw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s,
                   TV *part);
-// Scratch elements of the banded forward for `batch` images (0: not banded).
+// Scratch elements of the banded forward for `batch` images (0: not banded):
+// one chunk's partials, the chunks run one after another.
 int64_t fwd_part_elems(const Op &op, int batch);
+// Images sharing each matrix load in a forward over `batch` images.
+int fwd_chunk(const Op &op, int batch);
+// The band set of a forward over chunks of bc images, or nullptr when the
+// chunk's whole images fit the budget (or the operator has no bands).
+const BandSet *band_set_for(const Op &op, int bc);
 // out = alpha (MR)^T y + lambda K^T K x + sigma x; partial <x, out> per group
 // into part[batch][n_ag] when part != nullptr.  x may be nullptr when
 // lambda == sigma == 0 and part == nullptr.

@@ -166,7 +166,7 @@ template <class TV>
 __global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restrict__ fb,
                                                       const TV *__restrict__ part, TV *__restrict__ y,
                                                       int64_t rows, int nb, int nbpa, int bw,
-                                                      int n_bands)
+                                                      int n_bands, int lines)
 {
     const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ray >= rows) return;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restric
     const FwdBundle d = fb[int64_t(a) * nbpa + bin / bw];
     TV acc = TV(0);
     if (d.nrows > 0) {
-        const int lo = d.m0 / kBandLines, hi = (d.m0 + d.nrows - 4) / kBandLines;
+        const int lo = d.m0 / lines, hi = (d.m0 + d.nrows - 4) / lines;
         const TV *p = part + int64_t(b) * n_bands * rows + ray;
         // groups of four loads in flight, added in band order
         int band = lo;

@@ -82,8 +82,21 @@ static int cache_append(const char *path, const std::string &key, const radon_tu
     return RADON_OK;
 }
 
+// Band partials of the largest of the forward's candidate chunkings.
+static int64_t tune_part_elems(const Op &op, int batch)
+{
+    int64_t m = 0;
+    for (int r : {1, 4, 8, 16}) {
+        const int bc = r <= batch ? r : 1;
+        const BandSet *b = band_set_for(op, bc);
+        const int64_t e = b ? int64_t(b->n_bands) * op.rows * bc : 0;
+        m = e > m ? e : m;
+    }
+    return m;
+}
+
 // Workspace of the tuner: x and its transpose, y and out for `batch` images,
-// and the forward's band partials.
+// and the forward's band partials for any candidate chunking.
 int64_t tune_ws_bytes(const Op &op, int batch)
 {
     Carver c(nullptr);
@@ -91,7 +104,7 @@ int64_t tune_ws_bytes(const Op &op, int batch)
     c.take<char>(int64_t(op.vsize) * op.nn * batch);     // x^T
     c.take<char>(int64_t(op.vsize) * op.rows * batch);   // y
     c.take<char>(int64_t(op.vsize) * op.nn * batch);     // out
-    c.take<char>(int64_t(op.vsize) * fwd_part_elems(op, batch));
+    c.take<char>(int64_t(op.vsize) * tune_part_elems(op, batch));
     return c.used;
 }
 
@@ -127,7 +140,7 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
     TV *xT = c.take<TV>(op.nn * batch);
     TV *y = c.take<TV>(op.rows * batch);
     TV *out = c.take<TV>(op.nn * batch);
-    const int64_t pe = fwd_part_elems(op, batch);
+    const int64_t pe = tune_part_elems(op, batch);
     TV *part = pe ? c.take<TV>(pe) : nullptr;
     // a smooth positive image (the products' timing does not depend on the values)
     k_fill<TV><<<vec_blocks(op.nn * batch), kVecThreads, 0, s>>>(x, TV(0.5), op.nn * batch);

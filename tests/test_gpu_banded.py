@@ -68,3 +68,41 @@ def test_group_with_banded_instance_equals_single():
     for i, o in enumerate(ops):
         assert torch.equal(g.sinogram(F, i), o.fwd(xs[i][None])[0]), i
         assert torch.equal(g.image(A, i), o.normal(xs[i][None], 1.0, 0.5, 0.0)[0]), i
+
+
+@pytest.mark.parametrize("n,na,ev,batch,rhs,vec", [
+    (512, 12, 1, 6, 4, "f64"),     # 4-image chunks of 512^2 FP64 overflow the band budget: 128-line bands
+    (600, 10, 2, 19, 16, "f64"),   # ragged side and chunk tail: 16-line bands
+    (1024, 8, 1, 10, 8, "f32"),    # FP32, 8-image chunks: 64-line bands
+    (300, 9, 1, 5, 4, "f32"),      # 4 x 300^2 FP32 fits the budget whole: no bands
+])
+def test_fused_chunks_band_to_their_chunk(n, na, ev, batch, rhs, vec):
+    """Fused multi-image products: the forward runs its chunks one after
+    another, each line-banded to the height the chunk's images fit (or not at
+    all when they fit whole), and the adjoint visits tiles in the XCD-compact
+    order.  Every image matches the oracle and its own single-image product."""
+    need_gpu()
+    say(f"fused chunks n={n} angles={na} batch={batch} rhs={rhs} {vec}")
+    vdt = torch.float64 if vec == "f64" else torch.float32
+    mat = torch.float64 if vec == "f64" else torch.float32
+    mask = W.angle_mask(na, ev)
+    nb = W.n_bins_for(n)
+    op = sct.RadonOp(n, na, nb, mask, dtype=mat, vec_dtype=vdt, tuning="default")
+    op.tuning = {"fwd_rhs": rhs, "adj_rhs": rhs}
+    ref = oracle.OracleOp(n, na, nb, mask)
+    rng = np.random.default_rng(n + batch)
+    X = rng.standard_normal((batch, n * n))
+    if vec == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    Xd = to_dev(X, vdt)
+    y = host(op.fwd(Xd))
+    o = host(op.normal(Xd, 0.5, 1.0, 0.25))
+    tol = 1e-12 if vec == "f64" else 1e-5
+    for b in (0, batch // 2, batch - 1):
+        assert rel_l2(y[b], ref.fwd(X[b])) <= tol, b
+        assert rel_l2(o[b], ref.normal(X[b], 0.5, 1.0, 0.25)) <= tol, b
+    op.tuning = {"fwd_rhs": 1, "adj_rhs": 1}
+    y1 = host(op.fwd(Xd))
+    o1 = host(op.normal(Xd, 0.5, 1.0, 0.25))
+    assert np.max(np.abs(y - y1)) <= (1e-12 if vec == "f64" else 1e-4) * np.max(np.abs(y1))
+    assert np.max(np.abs(o - o1)) <= (1e-12 if vec == "f64" else 1e-4) * np.max(np.abs(o1))
