@@ -677,9 +677,9 @@ int radon_get_tuning(const radon_op *op, radon_tuning *out);
 /*
  * radon_autotune -- choose op's radon_tuning by timing the candidates on its
  * own geometry (HIP events on `stream`): waves per forward bundle (2, 4) and
- * per adjoint tile (1, 2, 4) on one image, then, for batch > 1, the images
- * sharing each matrix load in each direction (1, 4, 8, 16; at most batch),
- * one knob at a time in that order.  The forward bundle width is a layout
+ * per adjoint tile (1, 2, 4) on one image, one knob at a time, then, for
+ * batch > 1, the images sharing each matrix load in the forward and in the
+ * adjoint (1, 4, 8, 16 each; at most batch), jointly on the two products.  The forward bundle width is a layout
  * choice made at build time (radon_geom.fwd_bundle), not tuned here.
  *   batch       the batch the operator will run at (1 .. 65535).
  *   ws          device, radon_workspace_bytes(op, RADON_WS_TUNE, batch) bytes

@@ -182,34 +182,30 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
         }
     }
     cur.adj_waves = best->adj_waves;
-    // several images: how many share each matrix load
+    // several images: how many share each matrix load, in both products
+    // together (the chunkings interact through the caches), timed on the
+    // normal operator's two products
     if (batch > 1) {
         bool first = true;
-        for (int r : {1, 4, 8, 16}) {
-            if (r > batch) continue;
-            op.tune = cur;
-            op.tune.fwd_rhs = r;
-            float t = 0.f;
-            SCT_TRY(time_calls(s, tm, reps, fwd(batch), &t));
-            if (first || t < bt) {
-                bt = t;
-                best->fwd_rhs = r;
+        for (int fr : {1, 4, 8, 16}) {
+            if (fr > batch) continue;
+            for (int ar : {1, 4, 8, 16}) {
+                if (ar > batch) continue;
+                op.tune = cur;
+                op.tune.fwd_rhs = fr;
+                op.tune.adj_rhs = ar;
+                float t = 0.f;
+                SCT_TRY(time_calls(s, tm, reps, [&]() {
+                    SCT_TRY((launch_fwd<TM, TV>(op, x, op.need_T ? xT : nullptr, y, batch, s, part)));
+                    return launch_adj<TM, TV>(op, y, x, out, 1.0, 1.0, 0.0, nullptr, batch, s);
+                }, &t));
+                if (first || t < bt) {
+                    bt = t;
+                    best->fwd_rhs = fr;
+                    best->adj_rhs = ar;
+                }
+                first = false;
             }
-            first = false;
-        }
-        cur.fwd_rhs = best->fwd_rhs;
-        first = true;
-        for (int r : {1, 4, 8, 16}) {
-            if (r > batch) continue;
-            op.tune = cur;
-            op.tune.adj_rhs = r;
-            float t = 0.f;
-            SCT_TRY(time_calls(s, tm, reps, adj(batch), &t));
-            if (first || t < bt) {
-                bt = t;
-                best->adj_rhs = r;
-            }
-            first = false;
         }
     }
     return RADON_OK;
