@@ -655,20 +655,32 @@ int split_bregman_tv_fourier(const radon_fourier *f, int32_t path, const radon_s
 
 /*
  * Launch tuning of an operator (not part of the method: it only changes how
- * the products are scheduled; the waves-per-item counts split each sum
- * differently, so results change at the rounding level; the fused chunk
- * sizes change no summation order).
+ * the products are scheduled; the waves-per-item counts, the band height and
+ * the gather layout split each sum differently, so results change at the
+ * rounding level).
  *   fwd_waves  waves per ray bundle in the forward product: 2 or 4;
  *   adj_waves  waves per 8x8 tile in the adjoint: 1, 2 or 4 (0: chosen from
  *              the number of measured angles);
  *   fwd_rhs, adj_rhs  largest number of images (right-hand sides) that share
- *              each matrix load in a fused multi-image product: 1, 4, 8, 16.
- * radon_set_tuning must not overlap with enqueued work on the operator.
- * The binding's autotuner times the candidates and caches the best per
- * geometry (see paper_1705_07497_amd.autotune).
+ *              each matrix load in a fused multi-image product: 1, 4, 8, 16;
+ *   fwd_layout how a fused forward chunk of 4 or more images gathers its
+ *              pixels: 0 = from each image in turn; 1 = from a pixel-major
+ *              copy of the chunk (a pixel's values for all images of the
+ *              chunk contiguous, so one 16-byte load serves 4 FP32 or 2 FP64
+ *              images), made in the call's workspace;
+ *   fwd_lines  height of the line bands of a forward that has a workspace:
+ *              0 = chosen from the chunk's image bytes (the largest of 128,
+ *              64, 32, 16 lines whose band of the chunk's images fits 2 MB;
+ *              none below 1024 pixels while the chunk's whole images fit);
+ *              16, 32, 64 or 128 = that height (operators from 256 pixels
+ *              on; smaller ones accept only 0).
+ * The workspace sizes of radon_workspace_bytes depend on the tuning at the
+ * time of the query.  radon_set_tuning must not overlap with enqueued work on
+ * the operator.  radon_autotune times the candidates and caches the best per
+ * geometry.
  */
 typedef struct {
-    int32_t fwd_waves, adj_waves, fwd_rhs, adj_rhs;
+    int32_t fwd_waves, adj_waves, fwd_rhs, adj_rhs, fwd_layout, fwd_lines;
 } radon_tuning;
 
 int radon_set_tuning(radon_op *op, const radon_tuning *t);
@@ -677,10 +689,14 @@ int radon_get_tuning(const radon_op *op, radon_tuning *out);
 /*
  * radon_autotune -- choose op's radon_tuning by timing the candidates on its
  * own geometry (HIP events on `stream`): waves per forward bundle (2, 4) and
- * per adjoint tile (1, 2, 4) on one image, one knob at a time, then, for
+ * per adjoint tile (1, 2, 4) on one image, one knob at a time; then, for
  * batch > 1, the images sharing each matrix load in the forward and in the
- * adjoint (1, 4, 8, 16 each; at most batch), jointly on the two products.  The forward bundle width is a layout
- * choice made at build time (radon_geom.fwd_bundle), not tuned here.
+ * adjoint (1, 4, 8, 16 each; at most batch), jointly on the normal
+ * operator's two products; then, at that adjoint chunk, every forward chunk
+ * of 4 or more images with each gather layout (fwd_layout) and band height
+ * (fwd_lines) the operator has.  The search starts from fwd_layout = 0 and
+ * fwd_lines = 0.  The forward bundle width is a layout choice made at build
+ * time (radon_geom.fwd_bundle), not tuned here.
  *   batch       the batch the operator will run at (1 .. 65535).
  *   ws          device, radon_workspace_bytes(op, RADON_WS_TUNE, batch) bytes
  *               (test images and products; the values do not matter); may

@@ -92,7 +92,8 @@ FWS_TRANSFORM, FWS_SB = 0, 1
 
 class Tuning(ctypes.Structure):
     _fields_ = [("fwd_waves", ctypes.c_int32), ("adj_waves", ctypes.c_int32),
-                ("fwd_rhs", ctypes.c_int32), ("adj_rhs", ctypes.c_int32)]
+                ("fwd_rhs", ctypes.c_int32), ("adj_rhs", ctypes.c_int32),
+                ("fwd_layout", ctypes.c_int32), ("fwd_lines", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -342,7 +343,10 @@ class RadonOp:
     def tuning(self, d: dict) -> None:
         t = Tuning()
         _check(lib().radon_get_tuning(self._h, ctypes.byref(t)))
+        names = [f for f, _ in Tuning._fields_]
         for k, v in d.items():
+            if k not in names:
+                raise SparsectError(f"unknown tuning key {k!r} (known: {', '.join(names)})")
             setattr(t, k, int(v))
         _torch().cuda.synchronize(self.device)
         _check(lib().radon_set_tuning(self._h, ctypes.byref(t)))

@@ -4,7 +4,8 @@ time) and the launch settings (chosen by the library's radon_autotune).
 * Launch settings: radon_autotune times, on the operator's own geometry, the
   waves per forward bundle (2, 4), the waves per adjoint tile (1, 2, 4) and,
   at the batch asked for, how many images share each matrix load (1, 4, 8,
-  16), and keeps the fastest.  Its cache is a text file with one
+  16) in each product, then the forward's gather layout (per image, or from
+  a pixel-major copy of each chunk) and band height, and keeps the fastest.  Its cache is a text file with one
   ``sparsect-tune <key> ...`` line per (architecture, geometry, measured
   angles, kind, bundle width, batch).
 * Bundle width: rays per forward bundle, 16, 32 or 64.  Wider bundles make
@@ -14,8 +15,9 @@ time) and the launch settings (chosen by the library's radon_autotune).
   operator; the winner goes into the same file as a ``sparsect-bundle`` line.
 
 The file is $SPARSECT_AUTOTUNE_CACHE, else ~/.cache/sparsect/autotune.txt.
-Tuning never changes what is computed; the waves per item and the bundle
-width only change how each sum is split (rounding level).
+Tuning never changes what is computed; the waves per item, the band height,
+the gather layout and the bundle width only change how each sum is split
+(rounding level).
 """
 from __future__ import annotations
 
@@ -23,7 +25,7 @@ import ctypes
 import hashlib
 import os
 
-DEFAULT = {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8}
+DEFAULT = {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8, "fwd_layout": 0, "fwd_lines": 0}
 BUNDLES = (16, 32, 64)
 SOURCES = {0: "unchanged", 1: "cache", 2: "timed"}
 

@@ -220,8 +220,13 @@ static int rhs_chunk(int batch, int limit)
 
 int fwd_chunk(const Op &op, int batch) { return rhs_chunk(batch, op.tune.fwd_rhs); }
 
-const BandSet *band_set_for(const Op &op, int bc)
+const BandSet *band_set_lines(const Op &op, int bc, int lines)
 {
+    if (lines > 0) {
+        for (const BandSet &b : op.bands)
+            if (b.n_bands > 0 && b.lines == lines) return &b;
+        return nullptr;   // not built (radon_set_tuning only accepts built heights)
+    }
     const int64_t line = int64_t(op.n) * op.vsize;
     if (op.n < kBandMinN && int64_t(bc) * op.n * line <= kBandBudget) return nullptr;
     const BandSet *last = nullptr;
@@ -233,13 +238,20 @@ const BandSet *band_set_for(const Op &op, int bc)
     return last;   // the lowest bands even where a chunk's band overflows the budget
 }
 
-// The band partials of a call: one per band, ray and image of one chunk.
+int64_t fwd_scratch_elems(const Op &op, int bc, int nb, int layout, int lines)
+{
+    const BandSet *b = band_set_lines(op, bc, lines);
+    int64_t e = b ? int64_t(b->n_bands) * op.rows * nb : 0;
+    if (fwd_pixel_major(layout, bc)) e += kPixelMajorSlack + int64_t(op.need_T ? 2 : 1) * bc * op.nn;
+    return e;
+}
+
+// One chunk's band partials and pixel-major copies (chunks run one after
+// another).
 int64_t fwd_part_elems(const Op &op, int batch)
 {
     const int bc = fwd_chunk(op, batch);
-    const BandSet *b = band_set_for(op, bc);
-    if (!b) return 0;
-    return int64_t(b->n_bands) * op.rows * (batch < bc ? batch : bc);
+    return fwd_scratch_elems(op, bc, batch < bc ? batch : bc, op.tune.fwd_layout, op.tune.fwd_lines);
 }
 
 template <class TM, class TV>
@@ -546,6 +558,16 @@ extern "C" int radon_set_tuning(radon_op *p, const radon_tuning *t)
     for (int v : {t->fwd_rhs, t->adj_rhs})
         if (v != 1 && v != 4 && v != 8 && v != 16)
             return set_error(RADON_EINVAL, "fwd_rhs and adj_rhs must be 1, 4, 8 or 16 (got %d)", v);
+    if (t->fwd_layout != 0 && t->fwd_layout != 1)
+        return set_error(RADON_EINVAL, "fwd_layout must be 0 or 1 (got %d)", t->fwd_layout);
+    if (t->fwd_lines != 0) {
+        bool built = false;
+        for (const BandSet &b : as_op(p)->bands) built = built || (b.n_bands > 0 && b.lines == t->fwd_lines);
+        if (!built)
+            return set_error(RADON_EINVAL,
+                             "fwd_lines must be 0, or 16, 32, 64 or 128 on an operator of 256 pixels or more (got %d)",
+                             t->fwd_lines);
+    }
     as_op(p)->tune = *t;
     return RADON_OK;
 }

@@ -4,7 +4,7 @@
 // apply.hip's launch_fwd picks the operator's width.
 #pragma once
 
-#include "products.hpp"
+#include "fwd_pm.hpp"
 
 namespace sct {
 
@@ -127,11 +127,62 @@ inline void fwd_band_chunks(const Op &op, const BandSet &bs, const TV *x, const 
     }
 }
 
+template <class TM, class TV, int W, int C, int BW>
+inline void fwd_pm_launch(const Op &op, const BandSet *bs, const TV *xp, const TV *xpT, TV *y, TV *part,
+                          int nb, hipStream_t s)
+{
+    const TM *v0 = static_cast<const TM *>(op.f_v0), *v1 = static_cast<const TM *>(op.f_v1);
+    if (bs) {
+        const int64_t g = bs->n_order < kPersistentBlocks ? bs->n_order : kPersistentBlocks;
+        k_fwd_pm_band<TM, TV, W, C, BW><<<unsigned(g), 64 * W, 0, s>>>(
+            op.fb, bs->order, bs->n_order, op.f_idx, v0, v1, xp, xpT, part, op.n, op.rows, bs->n_bands,
+            bs->lines, nb);
+        const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
+        k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(nb)), 256, 0, s>>>(
+            op.fb, part, y, op.rows, op.n_bins, nbpa, op.bw, bs->n_bands, bs->lines);
+    } else {
+        const int64_t g = op.n_order < kPersistentBlocks ? op.n_order : kPersistentBlocks;
+        k_fwd_pm<TM, TV, W, C, BW><<<unsigned(g), 64 * W, 0, s>>>(op.fb, op.fb_order, op.n_order, op.f_idx,
+                                                                  v0, v1, xp, xpT, y, op.n, op.rows, nb);
+    }
+}
+
+// Forward over chunks of C images from pixel-major copies, one chunk after
+// another: part holds the chunk's band partials (when banded), then, 16-byte
+// aligned, its pixel-major copy and (for operators with rays closer to
+// horizontal) the copy in transposed pixel order.
+template <class TM, class TV, int C, int BW>
+inline void fwd_pm_chunks(const Op &op, const BandSet *bs, const TV *x, TV *y, TV *part, int batch,
+                          hipStream_t s)
+{
+    const int64_t pe = bs ? int64_t(bs->n_bands) * op.rows * C : 0;
+    const uintptr_t a = (reinterpret_cast<uintptr_t>(part + pe) + 15) & ~uintptr_t(15);
+    TV *xp = reinterpret_cast<TV *>(a);
+    TV *xpT = op.need_T ? xp + int64_t(C) * op.nn : nullptr;
+    const unsigned t = unsigned((op.n + 15) / 16);
+    for (int c0 = 0; c0 < batch; c0 += C) {
+        const int nb = batch - c0 < C ? batch - c0 : C;
+        k_pixel_major<TV, C><<<dim3(t, t), 256, 0, s>>>(x + int64_t(c0) * op.nn, xp, xpT, op.n, op.nn, nb);
+        if (op.tune.fwd_waves == 2)
+            fwd_pm_launch<TM, TV, 2, C, BW>(op, bs, xp, xpT ? xpT : xp, y + int64_t(c0) * op.rows, part, nb, s);
+        else
+            fwd_pm_launch<TM, TV, 4, C, BW>(op, bs, xp, xpT ? xpT : xp, y + int64_t(c0) * op.rows, part, nb, s);
+    }
+}
+
 template <class TM, class TV, int BW>
 int launch_fwd_bw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s, TV *part)
 {
     const int bc = fwd_rhs_chunk(batch, op.tune.fwd_rhs);
     const BandSet *bs = part ? band_set_for(op, bc) : nullptr;
+    if (part && fwd_pixel_major(op.tune.fwd_layout, bc)) {
+        switch (bc) {
+        case 16: fwd_pm_chunks<TM, TV, 16, BW>(op, bs, x, y, part, batch, s); break;
+        case 8: fwd_pm_chunks<TM, TV, 8, BW>(op, bs, x, y, part, batch, s); break;
+        default: fwd_pm_chunks<TM, TV, 4, BW>(op, bs, x, y, part, batch, s); break;
+        }
+        return check_launch("k_fwd_pm");
+    }
     if (bs) {
         switch (bc) {
         case 16: fwd_band_chunks<TM, TV, 16, BW>(op, *bs, x, xT, y, part, batch, s); break;

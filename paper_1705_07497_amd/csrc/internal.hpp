@@ -134,7 +134,7 @@ struct Op {
     int32_t *a_order = nullptr;
     int64_t n_a_order = 0;
 
-    radon_tuning tune{2, 0, 4, 8};   // launch tuning (see radon_set_tuning)
+    radon_tuning tune{2, 0, 4, 8, 0, 0};   // launch tuning (see radon_set_tuning)
 };
 
 // thread-local error state
@@ -213,14 +213,24 @@ int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStr
 template <class TM, class TV, int BW>
 int launch_fwd_bw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s,
                   TV *part);
-// Scratch elements of the banded forward for `batch` images (0: not banded):
-// one chunk's partials, the chunks run one after another.
+// Scratch elements of a forward over `batch` images that has a workspace (0:
+// none needed): one chunk's band partials and, for the pixel-major gather
+// layout, the chunk's pixel-major copies; the chunks run one after another.
 int64_t fwd_part_elems(const Op &op, int batch);
+// The same for a chunk of bc images (nb of them present) under a given
+// gather layout and band height (tuning values).
+int64_t fwd_scratch_elems(const Op &op, int bc, int nb, int layout, int lines);
 // Images sharing each matrix load in a forward over `batch` images.
 int fwd_chunk(const Op &op, int batch);
-// The band set of a forward over chunks of bc images, or nullptr when the
-// chunk's whole images fit the budget (or the operator has no bands).
-const BandSet *band_set_for(const Op &op, int bc);
+// The band set of a forward over chunks of bc images at band height `lines`
+// (0: the budget rule), or nullptr when the chunk's whole images fit the
+// budget (or the operator has no bands).
+const BandSet *band_set_lines(const Op &op, int bc, int lines);
+inline const BandSet *band_set_for(const Op &op, int bc) { return band_set_lines(op, bc, op.tune.fwd_lines); }
+// Whether a forward chunk of bc images gathers from a pixel-major copy.
+inline bool fwd_pixel_major(int layout, int bc) { return layout == 1 && bc >= 4; }
+// Elements of alignment slack before the pixel-major copies in the scratch.
+constexpr int64_t kPixelMajorSlack = 64;
 // out = alpha (MR)^T y + lambda K^T K x + sigma x; partial <x, out> per group
 // into part[batch][n_ag] when part != nullptr.  x may be nullptr when
 // lambda == sigma == 0 and part == nullptr.

@@ -4,8 +4,8 @@
 // per item split each sum differently, so results move at the rounding level).
 //
 // The optional cache is a text file of lines
-//   sparsect-tune <key> <fwd_waves> <adj_waves> <fwd_rhs> <adj_rhs>
-// keyed by GPU architecture, geometry, measured-angle set, operator kind,
+//   sparsect-tune <key> <fwd_waves> <adj_waves> <fwd_rhs> <adj_rhs> <fwd_layout> <fwd_lines>
+// (the last two may be missing: 0) keyed by GPU architecture, geometry, measured-angle set, operator kind,
 // forward bundle width and batch; a later line for a key overrides an earlier
 // one, and lines of other kinds are ignored.
 #include "cg.hpp"
@@ -40,16 +40,25 @@ static int tune_key(const Op &op, int batch, std::string *key)
     return RADON_OK;
 }
 
-static bool tune_valid(const radon_tuning &t)
+static bool lines_built(const Op &op, int lines)
+{
+    if (lines == 0) return true;
+    for (const BandSet &b : op.bands)
+        if (b.n_bands > 0 && b.lines == lines) return true;
+    return false;
+}
+
+static bool tune_valid(const Op &op, const radon_tuning &t)
 {
     const auto rhs_ok = [](int v) { return v == 1 || v == 4 || v == 8 || v == 16; };
     return (t.fwd_waves == 2 || t.fwd_waves == 4) &&
            (t.adj_waves == 0 || t.adj_waves == 1 || t.adj_waves == 2 || t.adj_waves == 4) &&
-           rhs_ok(t.fwd_rhs) && rhs_ok(t.adj_rhs);
+           rhs_ok(t.fwd_rhs) && rhs_ok(t.adj_rhs) && (t.fwd_layout == 0 || t.fwd_layout == 1) &&
+           lines_built(op, t.fwd_lines);
 }
 
 // Last valid entry for `key` in the cache file (false if none or no file).
-static bool cache_lookup(const char *path, const std::string &key, radon_tuning *t)
+static bool cache_lookup(const Op &op, const char *path, const std::string &key, radon_tuning *t)
 {
     FILE *f = fopen(path, "r");
     if (!f) return false;
@@ -57,9 +66,10 @@ static bool cache_lookup(const char *path, const std::string &key, radon_tuning 
     char line[512], k[320];
     while (fgets(line, sizeof line, f)) {
         radon_tuning c{};
-        if (sscanf(line, "sparsect-tune %319s %d %d %d %d", k, &c.fwd_waves, &c.adj_waves, &c.fwd_rhs,
-                   &c.adj_rhs) == 5 &&
-            key == k && tune_valid(c)) {
+        const int got = sscanf(line, "sparsect-tune %319s %d %d %d %d %d %d", k, &c.fwd_waves, &c.adj_waves,
+                               &c.fwd_rhs, &c.adj_rhs, &c.fwd_layout, &c.fwd_lines);
+        if (got == 5) c.fwd_layout = c.fwd_lines = 0;
+        if ((got == 5 || got == 7) && key == k && tune_valid(op, c)) {
             *t = c;
             found = true;
         }
@@ -74,23 +84,27 @@ static int cache_append(const char *path, const std::string &key, const radon_tu
     if (!f) return set_error(RADON_EINVAL, "cannot open the tuning cache %s for writing", path);
     // one short line per write: concurrent writers append whole lines
     char line[512];
-    const int len = snprintf(line, sizeof line, "sparsect-tune %s %d %d %d %d\n", key.c_str(), t.fwd_waves,
-                             t.adj_waves, t.fwd_rhs, t.adj_rhs);
+    const int len = snprintf(line, sizeof line, "sparsect-tune %s %d %d %d %d %d %d\n", key.c_str(),
+                             t.fwd_waves, t.adj_waves, t.fwd_rhs, t.adj_rhs, t.fwd_layout, t.fwd_lines);
     const bool ok = fwrite(line, 1, size_t(len), f) == size_t(len);
     fclose(f);
     if (!ok) return set_error(RADON_EINVAL, "cannot write the tuning cache %s", path);
     return RADON_OK;
 }
 
-// Band partials of the largest of the forward's candidate chunkings.
+// Forward scratch of the largest of the candidate chunkings, gather layouts
+// and band heights.
 static int64_t tune_part_elems(const Op &op, int batch)
 {
     int64_t m = 0;
     for (int r : {1, 4, 8, 16}) {
         const int bc = r <= batch ? r : 1;
-        const BandSet *b = band_set_for(op, bc);
-        const int64_t e = b ? int64_t(b->n_bands) * op.rows * bc : 0;
-        m = e > m ? e : m;
+        for (int layout : {0, 1})
+            for (int lines : {0, 16, 32, 64, 128}) {
+                if (!lines_built(op, lines)) continue;
+                const int64_t e = fwd_scratch_elems(op, bc, bc, layout, lines);
+                m = e > m ? e : m;
+            }
     }
     return m;
 }
@@ -151,6 +165,7 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
     SCT_HIP(hipEventCreate(&tm.e0));
     SCT_HIP(hipEventCreate(&tm.e1));
     const int reps = 3;
+    best->fwd_layout = best->fwd_lines = 0;   // the search starts from the defaults
     radon_tuning cur = *best;
     auto fwd = [&](int b) {
         return [&, b]() { return launch_fwd<TM, TV>(op, x, op.need_T ? xT : nullptr, y, b, s, part); };
@@ -184,8 +199,13 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
     cur.adj_waves = best->adj_waves;
     // several images: how many share each matrix load, in both products
     // together (the chunkings interact through the caches), timed on the
-    // normal operator's two products
+    // normal operator's two products; then, at the best adjoint chunk, the
+    // forward's gather layout and band height for each forward chunk
     if (batch > 1) {
+        auto normal = [&]() {
+            SCT_TRY((launch_fwd<TM, TV>(op, x, op.need_T ? xT : nullptr, y, batch, s, part)));
+            return launch_adj<TM, TV>(op, y, x, out, 1.0, 1.0, 0.0, nullptr, batch, s);
+        };
         bool first = true;
         for (int fr : {1, 4, 8, 16}) {
             if (fr > batch) continue;
@@ -195,10 +215,7 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
                 op.tune.fwd_rhs = fr;
                 op.tune.adj_rhs = ar;
                 float t = 0.f;
-                SCT_TRY(time_calls(s, tm, reps, [&]() {
-                    SCT_TRY((launch_fwd<TM, TV>(op, x, op.need_T ? xT : nullptr, y, batch, s, part)));
-                    return launch_adj<TM, TV>(op, y, x, out, 1.0, 1.0, 0.0, nullptr, batch, s);
-                }, &t));
+                SCT_TRY(time_calls(s, tm, reps, normal, &t));
                 if (first || t < bt) {
                     bt = t;
                     best->fwd_rhs = fr;
@@ -206,6 +223,27 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
                 }
                 first = false;
             }
+        }
+        cur.fwd_rhs = best->fwd_rhs;
+        cur.adj_rhs = best->adj_rhs;
+        for (int fr : {4, 8, 16}) {
+            if (fr > batch) continue;
+            for (int layout : {0, 1})
+                for (int lines : {0, 16, 32, 64, 128}) {
+                    if (!lines_built(op, lines) || (fr == cur.fwd_rhs && layout == 0 && lines == 0)) continue;
+                    op.tune = cur;
+                    op.tune.fwd_rhs = fr;
+                    op.tune.fwd_layout = layout;
+                    op.tune.fwd_lines = lines;
+                    float t = 0.f;
+                    SCT_TRY(time_calls(s, tm, reps, normal, &t));
+                    if (t < bt) {
+                        bt = t;
+                        best->fwd_rhs = fr;
+                        best->fwd_layout = layout;
+                        best->fwd_lines = lines;
+                    }
+                }
         }
     }
     return RADON_OK;
@@ -229,7 +267,7 @@ extern "C" int radon_autotune(radon_op *p, int32_t batch, void *ws, int64_t ws_b
     if (cache_path) {
         SCT_TRY(tune_key(op, batch, &key));
         radon_tuning t{};
-        if (cache_lookup(cache_path, key, &t)) {
+        if (cache_lookup(op, cache_path, key, &t)) {
             op.tune = t;
             if (source) *source = 1;
             return RADON_OK;

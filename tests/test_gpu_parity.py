@@ -399,20 +399,27 @@ def test_tuning_setter_autotune_and_parity(tmp_path, monkeypatch):
     mask = W.angle_mask(na, 2)
     ref = oracle.OracleOp(n, na, W.n_bins_for(n), mask)
     op = make_op(n, na, W.n_bins_for(n), mask, "mixed")
-    assert op.tuning == {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8}
+    assert op.tuning == {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8, "fwd_layout": 0,
+                         "fwd_lines": 0}
     with pytest.raises(sct.SparsectError):
         op.tuning = {"fwd_waves": 3}
     with pytest.raises(sct.SparsectError):
         op.tuning = {"adj_rhs": 5}
+    with pytest.raises(sct.SparsectError):
+        op.tuning = {"fwd_layout": 2}
+    with pytest.raises(sct.SparsectError):
+        op.tuning = {"fwd_lines": 32}     # no band sets below 256 pixels
+    with pytest.raises(sct.SparsectError):
+        op.tuning = {"fwd_rhs_typo": 4}
     x = rounded(np.random.default_rng(1).standard_normal((6, n * n)), F64)
     want = [ref.normal(x[b], 1.0, 0.5, 0.1) for b in range(6)]
     for fw in (2, 4):
         for aw in (1, 2, 4):
-            for fr, ar in ((1, 1), (4, 8), (8, 4)):
-                op.tuning = {"fwd_waves": fw, "adj_waves": aw, "fwd_rhs": fr, "adj_rhs": ar}
+            for fr, ar, lay in ((1, 1, 0), (4, 8, 0), (8, 4, 0), (4, 8, 1), (8, 4, 1)):
+                op.tuning = {"fwd_waves": fw, "adj_waves": aw, "fwd_rhs": fr, "adj_rhs": ar, "fwd_layout": lay}
                 got = host(op.normal(to_dev(x, F64), 1.0, 0.5, 0.1))
                 for b in range(6):
-                    assert rel_l2(got[b], want[b]) <= 1e-5, (fw, aw, fr, ar, b)
+                    assert rel_l2(got[b], want[b]) <= 1e-5, (fw, aw, fr, ar, lay, b)
     entry = autotune.autotune(op, batch=8)
     assert entry["source"] == "timed"
     assert set(entry["tuning"]) == set(autotune.DEFAULT)
