@@ -199,6 +199,23 @@ void radon_op_destroy(radon_op *op);
 /* Message for the calling thread's most recent failed call ("" if none). */
 const char *radon_last_error(void);
 
+/*
+ * Layouts of batched vectors (the `layout` argument of radon_fwd, radon_adj,
+ * normal_apply, cg_solve and split_bregman_tv):
+ *   RADON_LAYOUT_IMAGE  [batch][count]: image (or sinogram) b is contiguous,
+ *                       element i of image b at b*count + i;
+ *   RADON_LAYOUT_PIXEL  [count][batch]: the batch is interleaved, element i
+ *                       of image b at i*batch + b (count = n*n for images,
+ *                       n_meas_rays for sinograms).
+ * Every input and output of one call uses the call's layout; with batch = 1
+ * the two are the same.  The products run image-major; a pixel-major call
+ * with batch > 1 relays its inputs and outputs through the end of its
+ * workspace (one tiled transpose each way, ordered on the call's stream) and
+ * computes exactly what the image-major call computes.
+ */
+#define RADON_LAYOUT_IMAGE 0
+#define RADON_LAYOUT_PIXEL 1
+
 /* Workspace kinds for radon_workspace_bytes. */
 #define RADON_WS_FWD      0
 #define RADON_WS_NORMAL   1
@@ -206,23 +223,32 @@ const char *radon_last_error(void);
 #define RADON_WS_SB       3
 #define RADON_WS_PD       4
 #define RADON_WS_TUNE     5
+#define RADON_WS_ADJ      6
+/* OR'ed into RADON_WS_FWD, _ADJ, _NORMAL, _CG or _SB: the size for a
+ * pixel-major call (RADON_LAYOUT_PIXEL), which adds its relay buffers after
+ * the image-major workspace. */
+#define RADON_WS_PIXEL_LAYOUT 0x100
 
 /* Bytes of device workspace a call of the given kind needs for `batch`
- * right-hand sides (>= 0; negative = error status). */
+ * right-hand sides (>= 0; negative = error status).  The sizes depend on the
+ * operator's tuning at the time of the query (radon_set_tuning). */
 int64_t radon_workspace_bytes(const radon_op *op, int32_t which, int32_t batch);
 
 /*
  * radon_fwd -- y = M R x for `batch` images (the data term of eq:objmin).
- *   x   device, [batch][n*n], operator dtype, read only.
- *   y   device, [batch][n_meas_rays], written.
- *   ws  device workspace of radon_workspace_bytes(op, RADON_WS_FWD, batch)
- *       bytes (holds the transposed image the ray-bundle layout gathers from
- *       for rays closer to horizontal than vertical and, for images from
- *       1024 pixels on, one partial sum per ray and 128-line band: the
- *       product then runs band by band so each band of the image stays in
- *       cache, and adds the partials in band order).
+ *   x       device, batch images of n*n, operator dtype, read only.
+ *   y       device, batch sinograms of n_meas_rays, written.
+ *   layout  RADON_LAYOUT_IMAGE or RADON_LAYOUT_PIXEL (both x and y).
+ *   ws      device workspace of radon_workspace_bytes(op, RADON_WS_FWD, batch)
+ *           bytes (| RADON_WS_PIXEL_LAYOUT for a pixel-major call).  It holds
+ *           the transposed image the ray-bundle layout gathers from for rays
+ *           closer to horizontal than vertical and, when the product runs in
+ *           line bands (images from 1024 pixels on, and fused chunks whose
+ *           images overflow the cache budget), one partial sum per ray and
+ *           band, added in band order; with fwd_layout = 1 tuning also the
+ *           pixel-major copy of a chunk.
  */
-int radon_fwd(const radon_op *op, const void *x, void *y, int32_t batch,
+int radon_fwd(const radon_op *op, const void *x, void *y, int32_t batch, int32_t layout,
               void *ws, int64_t ws_bytes, void *stream);
 
 /*
@@ -240,9 +266,13 @@ int radon_fwd_xt(const radon_op *op, const void *x, const void *xT, void *y, int
 /*
  * radon_adj -- x = R^T M^T y (the adjoint in eq:KKT, eq:PD_resolve,
  * eq:SB_solve), through the stored transpose: each output pixel is one
- * sequential sum, no atomics.  y [batch][n_meas_rays] -> x [batch][n*n].
+ * sequential sum, no atomics.  y: batch sinograms of n_meas_rays -> x: batch
+ * images of n*n, both in `layout`.
+ *   ws  radon_workspace_bytes(op, RADON_WS_ADJ, batch) bytes (0: may be
+ *       NULL), | RADON_WS_PIXEL_LAYOUT for a pixel-major call.
  */
-int radon_adj(const radon_op *op, const void *y, void *x, int32_t batch, void *stream);
+int radon_adj(const radon_op *op, const void *y, void *x, int32_t batch, int32_t layout,
+              void *ws, int64_t ws_bytes, void *stream);
 
 /*
  * normal_apply -- out = alpha R^T M^T M R x + lambda K^T K x + sigma x.
@@ -250,13 +280,14 @@ int radon_adj(const radon_op *op, const void *y, void *x, int32_t batch, void *s
  * alpha <- tau*alpha, lambda = 0, sigma = 1 that of eq:PD_resolve (Section 2).
  * K is the forward-difference gradient with a zero last difference
  * (Neumann), so K^T K is the 5-point grid Laplacian with Neumann boundary.
- *   x, out   device [batch][n*n]; out must not alias x.
+ *   x, out   device, batch images in `layout`; out must not alias x.
  *   dot_out  optional device double[batch]: <x, out> per image (FP64 sum of
  *            exact FP64 products, fixed order); NULL to skip.
- *   ws       radon_workspace_bytes(op, RADON_WS_NORMAL, batch) bytes.
+ *   ws       radon_workspace_bytes(op, RADON_WS_NORMAL, batch) bytes
+ *            (| RADON_WS_PIXEL_LAYOUT for a pixel-major call).
  */
 int normal_apply(const radon_op *op, double alpha, double lambda, double sigma,
-                 const void *x, void *out, double *dot_out, int32_t batch,
+                 const void *x, void *out, double *dot_out, int32_t batch, int32_t layout,
                  void *ws, int64_t ws_bytes, void *stream);
 
 /*
@@ -269,7 +300,7 @@ int normal_apply(const radon_op *op, double alpha, double lambda, double sigma,
  * (no hipMalloc, no allocating library routine); its first call on a device
  * looks the array's address up (hipGetSymbolAddress) with that device
  * current.
- *   x, out, dot_out, batch, stream: as for normal_apply.
+ *   x, out, dot_out, batch, stream: as for normal_apply (image-major).
  * Errors: as normal_apply; RADON_EWORKSPACE when
  * radon_workspace_bytes(op, RADON_WS_NORMAL, batch) exceeds the fixed size
  * (nothing is enqueued then).
@@ -294,17 +325,18 @@ typedef struct {
  * image (Section 2: the systems have no closed form and are solved
  * iteratively).  Vectors in the operator dtype, the scalars rho, gamma,
  * alpha_k and beta_k in FP64 on the device.
- *   rhs      device [batch][n*n].
- *   x        device [batch][n*n]: initial guess if x0_given, else zeroed;
- *            receives the iterate.  r_0 = rhs - A x_0.
+ *   rhs      device, batch images in `layout`.
+ *   x        device, batch images in `layout`: initial guess if x0_given,
+ *            else zeroed; receives the iterate.  r_0 = rhs - A x_0.
  *   n_iter   iteration cap; rtol > 0 also stops once ||r|| <= rtol ||r_0||;
  *            a zero residual stops; <p, Ap> <= 0 or non-finite stops and is
  *            reported as a breakdown.
  *   info     optional device radon_cg_info[batch].
- *   ws       radon_workspace_bytes(op, RADON_WS_CG, batch) bytes.
+ *   ws       radon_workspace_bytes(op, RADON_WS_CG, batch) bytes
+ *            (| RADON_WS_PIXEL_LAYOUT for a pixel-major call).
  */
 int cg_solve(const radon_op *op, double alpha, double lambda, double sigma,
-             const void *rhs, void *x, int32_t x0_given, int32_t batch,
+             const void *rhs, void *x, int32_t x0_given, int32_t batch, int32_t layout,
              int32_t n_iter, double rtol, void *ws, int64_t ws_bytes,
              radon_cg_info *info, void *stream);
 
@@ -338,14 +370,18 @@ typedef struct {
  *   (eq:SB_solve, read with K^* as the transpose and a plus sign), warm
  *   started from the previous u with the residual carried across iterations,
  *   then d = shrink(K u + b, 1/lambda), b <- b + K u - d.
- *   f     device [batch][n_meas_rays].
- *   mu    device [batch][n*n]; the start if RADON_SB_WARM, receives u.
- *   ws    radon_workspace_bytes(op, RADON_WS_SB, batch) bytes; holds d, b and
- *         the residual, so a later call with RADON_SB_RESUME continues.
- *   info  optional device radon_sb_info[batch].
+ *   f       device, batch sinograms of n_meas_rays in `layout`.
+ *   mu      device, batch images in `layout`; the start if RADON_SB_WARM,
+ *           receives u (and is read again by a RADON_SB_RESUME call).
+ *   layout  RADON_LAYOUT_IMAGE or RADON_LAYOUT_PIXEL.
+ *   ws      radon_workspace_bytes(op, RADON_WS_SB, batch) bytes
+ *           (| RADON_WS_PIXEL_LAYOUT for a pixel-major call); holds d, b
+ *           and the residual (always image-major), so a later call with
+ *           RADON_SB_RESUME continues, in either layout.
+ *   info    optional device radon_sb_info[batch].
  */
 int split_bregman_tv(const radon_op *op, const radon_sb_params *params, const void *f,
-                     void *mu, int32_t batch, void *ws, int64_t ws_bytes,
+                     void *mu, int32_t batch, int32_t layout, void *ws, int64_t ws_bytes,
                      radon_sb_info *info, void *stream);
 
 /*

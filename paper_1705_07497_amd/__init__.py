@@ -24,7 +24,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsparsect.so")
 
 F32, F64, F32_F64 = 0, 1, 2
-WS_FWD, WS_NORMAL, WS_CG, WS_SB, WS_PD, WS_TUNE = 0, 1, 2, 3, 4, 5
+WS_FWD, WS_NORMAL, WS_CG, WS_SB, WS_PD, WS_TUNE, WS_ADJ = 0, 1, 2, 3, 4, 5, 6
+WS_PIXEL_LAYOUT = 0x100
+LAYOUT_IMAGE, LAYOUT_PIXEL = 0, 1
 SB_WARM, SB_RESUME = 1, 2
 
 _vp = ctypes.c_void_p
@@ -116,18 +118,20 @@ SIGNATURES = {
     "radon_op_destroy": (None, [_vp]),
     "radon_last_error": (ctypes.c_char_p, []),
     "radon_workspace_bytes": (ctypes.c_int64, [_vp, ctypes.c_int32, ctypes.c_int32]),
-    "radon_fwd": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
-    "radon_adj": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
+    "radon_fwd": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
+                                 _vp]),
+    "radon_adj": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
+                                 _vp]),
     "radon_fwd_xt": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp]),
     "normal_apply": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
-                                    _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
+                                    _vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64, _vp]),
     "normal_apply_noalloc": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                             _vp, _vp, _vp, ctypes.c_int32, _vp]),
     "cg_solve": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
-                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _vp,
-                                ctypes.c_int64, _vp, _vp]),
-    "split_bregman_tv": (ctypes.c_int, [_vp, ctypes.POINTER(SbParams), _vp, _vp, ctypes.c_int32, _vp,
-                                        ctypes.c_int64, _vp, _vp]),
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_double, _vp, ctypes.c_int64, _vp, _vp]),
+    "split_bregman_tv": (ctypes.c_int, [_vp, ctypes.POINTER(SbParams), _vp, _vp, ctypes.c_int32,
+                                        ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]),
     "radon_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "radon_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "radon_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int64, ctypes.c_char_p,
@@ -375,7 +379,11 @@ class RadonOp:
         k = (which, batch) if key is None else key
         buf = self._ws.get(k)
         if buf is None or buf.numel() < nbytes:
-            buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+            grown = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+            if buf is not None:
+                # keep what a solver left there (split Bregman's state for a resumed call)
+                grown[:buf.numel()].copy_(buf)
+            buf = grown
             self._ws[k] = buf
         return buf, int(nbytes)
 
@@ -416,14 +424,26 @@ class RadonOp:
         return _vp(t.data_ptr()) if t is not None else None
 
     # -- products -------------------------------------------------------------
-    def fwd(self, x, out=None):
-        """y = M R x; x [..., n*n] (or [..., n, n]) -> y [batch, rows]."""
-        torch = _torch()
+    @staticmethod
+    def _ws_kind(which: int, layout: int) -> int:
+        if layout not in (LAYOUT_IMAGE, LAYOUT_PIXEL):
+            raise SparsectError("layout must be LAYOUT_IMAGE (0) or LAYOUT_PIXEL (1)")
+        return which | (WS_PIXEL_LAYOUT if layout == LAYOUT_PIXEL else 0)
+
+    def _new(self, b: int, count: int, layout: int):
+        """An output of b vectors of count elements in the given layout."""
+        shape = (count, b) if layout == LAYOUT_PIXEL else (b, count)
+        return _torch().empty(shape, dtype=self.dtype, device=self.device)
+
+    def fwd(self, x, out=None, layout: int = LAYOUT_IMAGE):
+        """y = M R x; x [..., n*n] (or [..., n, n]) -> y [batch, rows].  With
+        layout=LAYOUT_PIXEL, x is [n*n, batch] and y [rows, batch]."""
         b = self._img(x)
-        y = torch.empty((b, self.rows), dtype=self.dtype, device=self.device) if out is None else out
+        y = self._new(b, self.rows, layout) if out is None else out
         self._sino_n(y, b, "out")
-        ws, nb = self.workspace(WS_FWD, b)
-        _check(lib().radon_fwd(self._h, self._p(x), self._p(y), b, self._p(ws), nb, self._stream()))
+        ws, nb = self.workspace(self._ws_kind(WS_FWD, layout), b)
+        _check(lib().radon_fwd(self._h, self._p(x), self._p(y), b, layout, self._p(ws), nb,
+                               self._stream()))
         return y
 
     def fwd_xt(self, x, xT, out=None):
@@ -437,25 +457,27 @@ class RadonOp:
         _check(lib().radon_fwd_xt(self._h, self._p(x), self._p(xT), self._p(y), b, self._stream()))
         return y
 
-    def adj(self, y, out=None):
-        """x = R^T M^T y; y [..., rows] -> x [batch, n*n]."""
-        torch = _torch()
+    def adj(self, y, out=None, layout: int = LAYOUT_IMAGE):
+        """x = R^T M^T y; y [..., rows] -> x [batch, n*n] (layout as for fwd)."""
         b = self._sino(y)
-        x = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        x = self._new(b, self.nn, layout) if out is None else out
         self._img_n(x, b, "out")
-        _check(lib().radon_adj(self._h, self._p(y), self._p(x), b, self._stream()))
+        ws, nb = self.workspace(self._ws_kind(WS_ADJ, layout), b)
+        _check(lib().radon_adj(self._h, self._p(y), self._p(x), b, layout, self._p(ws) if nb else None,
+                               nb, self._stream()))
         return x
 
-    def normal(self, x, alpha: float, lam: float, sigma: float = 0.0, out=None, dot: bool = False):
+    def normal(self, x, alpha: float, lam: float, sigma: float = 0.0, out=None, dot: bool = False,
+               layout: int = LAYOUT_IMAGE):
         """alpha R^T M^T M R x + lam K^T K x + sigma x (and <x, out> per image if dot)."""
         torch = _torch()
         b = self._img(x)
-        o = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+        o = self._new(b, self.nn, layout) if out is None else out
         self._img_n(o, b, "out")
         d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
-        ws, nb = self.workspace(WS_NORMAL, b)
+        ws, nb = self.workspace(self._ws_kind(WS_NORMAL, layout), b)
         _check(lib().normal_apply(self._h, float(alpha), float(lam), float(sigma), self._p(x),
-                                  self._p(o), self._p(d), b, self._p(ws), nb, self._stream()))
+                                  self._p(o), self._p(d), b, layout, self._p(ws), nb, self._stream()))
         return (o, d) if dot else o
 
     def normal_noalloc(self, x, alpha: float, lam: float, sigma: float = 0.0, out=None,
@@ -473,7 +495,7 @@ class RadonOp:
         return (o, d) if dot else o
 
     def cg(self, rhs, alpha: float, lam: float, sigma: float = 0.0, x0=None, n_iter: int = 10,
-           rtol: float = 0.0, out=None):
+           rtol: float = 0.0, out=None, layout: int = LAYOUT_IMAGE):
         """CG on A(alpha, lam, sigma) x = rhs; returns (x, info tensor of CgInfo bytes)."""
         torch = _torch()
         b = self._img(rhs, "rhs")
@@ -483,16 +505,17 @@ class RadonOp:
             self._img_n(x0, b, "x0")
             x = x0.clone() if out is None else out.copy_(x0)
         else:
-            x = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+            x = self._new(b, self.nn, layout) if out is None else out
         info = torch.zeros(b * ctypes.sizeof(CgInfo), dtype=torch.uint8, device=self.device)
-        ws, nb = self.workspace(WS_CG, b)
+        ws, nb = self.workspace(self._ws_kind(WS_CG, layout), b)
         _check(lib().cg_solve(self._h, float(alpha), float(lam), float(sigma), self._p(rhs),
-                              self._p(x), int(x0 is not None), b, int(n_iter), float(rtol),
+                              self._p(x), int(x0 is not None), b, layout, int(n_iter), float(rtol),
                               self._p(ws), nb, self._p(info), self._stream()))
         return x, info
 
     def sb(self, f, alpha: float, lam: float, n_outer: int, n_cg: int, tol: float = 0.0,
-           mu0=None, resume: bool = False, out=None, ws_key="sb", surrogate=None):
+           mu0=None, resume: bool = False, out=None, ws_key="sb", surrogate=None,
+           layout: int = LAYOUT_IMAGE):
         """Split Bregman TV; returns (mu, info tensor of SbInfo bytes).  The state
         (d, b, carried residual) stays in a cached workspace so resume=True continues.
         With surrogate (a RadonSurrogate of this operator) every inner solve uses
@@ -513,15 +536,18 @@ class RadonOp:
             flags |= SB_WARM
             mu = mu0.clone() if out is None else out.copy_(mu0)
         else:
-            mu = torch.empty((b, self.nn), dtype=self.dtype, device=self.device) if out is None else out
+            mu = self._new(b, self.nn, layout) if out is None else out
         self._img_n(mu, b, "mu")
         P = SbParams(float(alpha), float(lam), float(tol), int(n_outer), int(n_cg), flags, 0)
         info = torch.zeros(b * ctypes.sizeof(SbInfo), dtype=torch.uint8, device=self.device)
-        ws, nb = self.workspace(WS_SB, b, key=(ws_key, b))
         if surrogate is None:
-            _check(lib().split_bregman_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b,
+            ws, nb = self.workspace(self._ws_kind(WS_SB, layout), b, key=(ws_key, b))
+            _check(lib().split_bregman_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b, layout,
                                           self._p(ws), nb, self._p(info), self._stream()))
         else:
+            if layout != LAYOUT_IMAGE:
+                raise SparsectError("the surrogate solver takes image-major vectors only")
+            ws, nb = self.workspace(WS_SB, b, key=(ws_key, b))
             _check(lib().split_bregman_tv_surrogate(self._h, surrogate._h, ctypes.byref(P),
                                                     self._p(f), self._p(mu), b, self._p(ws), nb,
                                                     self._p(info), self._stream()))

@@ -354,6 +354,96 @@ static int64_t fwd_ws_bytes(const Op &op, int batch)
     return c.used;
 }
 
+// dst = src between [batch][count] and [count][batch] through a 32 x 32
+// tile: blockIdx.x covers 32 elements of count, blockIdx.y 32 of the batch;
+// both the read and the write run along the contiguous index.
+template <class T>
+__global__ __launch_bounds__(256) void k_relayout(const T *__restrict__ src, T *__restrict__ dst,
+                                                  int64_t count, int batch, int to_pixel)
+{
+    __shared__ T tile[32][33];
+    const int64_t i0 = int64_t(blockIdx.x) * 32;
+    const int b0 = blockIdx.y * 32;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    if (to_pixel) {
+        for (int k = ty; k < 32; k += 8) {
+            const int b = b0 + k;
+            const int64_t i = i0 + tx;
+            if (b < batch && i < count) tile[k][tx] = src[int64_t(b) * count + i];
+        }
+        __syncthreads();
+        for (int k = ty; k < 32; k += 8) {
+            const int64_t i = i0 + k;
+            const int b = b0 + tx;
+            if (i < count && b < batch) dst[i * batch + b] = tile[tx][k];
+        }
+    } else {
+        for (int k = ty; k < 32; k += 8) {
+            const int64_t i = i0 + k;
+            const int b = b0 + tx;
+            if (i < count && b < batch) tile[k][tx] = src[i * batch + b];
+        }
+        __syncthreads();
+        for (int k = ty; k < 32; k += 8) {
+            const int b = b0 + k;
+            const int64_t i = i0 + tx;
+            if (b < batch && i < count) dst[int64_t(b) * count + i] = tile[tx][k];
+        }
+    }
+}
+
+template <class TV>
+int launch_relayout(const TV *src, TV *dst, int64_t count, int batch, bool to_pixel, hipStream_t s)
+{
+    const int64_t gx = (count + 31) / 32;
+    if (gx > 0x7fffffffll) return set_error(RADON_EUNSUPPORTED, "%lld elements per image are too many", (long long)count);
+    const dim3 grid(unsigned(gx), unsigned((batch + 31) / 32));
+    k_relayout<TV><<<grid, dim3(32, 8), 0, s>>>(src, dst, count, batch, to_pixel ? 1 : 0);
+    return check_launch("k_relayout");
+}
+template int launch_relayout<float>(const float *, float *, int64_t, int, bool, hipStream_t);
+template int launch_relayout<double>(const double *, double *, int64_t, int, bool, hipStream_t);
+
+int check_layout(int32_t layout)
+{
+    if (layout != RADON_LAYOUT_IMAGE && layout != RADON_LAYOUT_PIXEL)
+        return set_error(RADON_EINVAL, "layout must be RADON_LAYOUT_IMAGE or RADON_LAYOUT_PIXEL (got %d)", layout);
+    return RADON_OK;
+}
+
+int64_t pixel_layout_extra(const Op &op, int which, int batch)
+{
+    if (batch <= 1) return 0;
+    Carver c(nullptr);
+    const int64_t img = int64_t(op.vsize) * op.nn * batch, sino = int64_t(op.vsize) * op.rows * batch;
+    switch (which) {
+    case RADON_WS_FWD:
+    case RADON_WS_ADJ:
+    case RADON_WS_SB:
+        c.take<char>(img);
+        c.take<char>(sino);
+        break;
+    default:   // normal operator, CG: input and output images
+        c.take<char>(img);
+        c.take<char>(img);
+        break;
+    }
+    return c.used + 256;   // the relay buffers start at a 256-byte boundary after the workspace
+}
+
+// The relay buffers of a pixel-major call: after `base` bytes of ws, 256-byte
+// aligned; first of `n0` elements, second of `n1`.
+template <class TV>
+void relay_buffers(void *ws, int64_t base, int64_t n0, int64_t n1, TV **b0, TV **b1)
+{
+    char *p = static_cast<char *>(ws) + ((base + 255) & ~int64_t(255));
+    Carver c(p);
+    *b0 = c.take<TV>(n0);
+    *b1 = c.take<TV>(n1);
+}
+template void relay_buffers<float>(void *, int64_t, int64_t, int64_t, float **, float **);
+template void relay_buffers<double>(void *, int64_t, int64_t, int64_t, double **, double **);
+
 static int64_t normal_ws_bytes(const Op &op, int batch)
 {
     Carver c(nullptr);
@@ -379,27 +469,26 @@ extern "C" int64_t radon_workspace_bytes(const radon_op *p, int32_t which, int32
     SCT_TRY(check_op(p));
     SCT_TRY(check_batch(batch));
     const Op &op = *as_op(p);
-    switch (which) {
-    case RADON_WS_FWD: return fwd_ws_bytes(op, batch);
-    case RADON_WS_NORMAL: return normal_ws_bytes(op, batch);
-    case RADON_WS_CG: return cg_ws_bytes(op, batch);
-    case RADON_WS_SB: return sb_ws_bytes(op, batch);
+    const bool pixel = (which & RADON_WS_PIXEL_LAYOUT) != 0;
+    const int kind = which & ~RADON_WS_PIXEL_LAYOUT;
+    if (pixel && (kind == RADON_WS_PD || kind == RADON_WS_TUNE))
+        return set_error(RADON_EINVAL, "workspace kind %d has no pixel-major form", kind);
+    const int64_t extra = pixel ? pixel_layout_extra(op, kind, batch) : 0;
+    switch (kind) {
+    case RADON_WS_FWD: return fwd_ws_bytes(op, batch) + extra;
+    case RADON_WS_ADJ: return extra;
+    case RADON_WS_NORMAL: return normal_ws_bytes(op, batch) + extra;
+    case RADON_WS_CG: return cg_ws_bytes(op, batch) + extra;
+    case RADON_WS_SB: return sb_ws_bytes(op, batch) + extra;
     case RADON_WS_PD: return pd_ws_bytes(op, batch);
     case RADON_WS_TUNE: return tune_ws_bytes(op, batch);
     default: return set_error(RADON_EINVAL, "unknown workspace kind %d", which);
     }
 }
 
-extern "C" int radon_fwd(const radon_op *p, const void *x, void *y, int32_t batch, void *ws,
-                         int64_t ws_bytes, void *stream)
+// The image-major forward with its workspace.
+static int fwd_into(const Op &op, const void *x, void *y, int batch, void *ws, hipStream_t s)
 {
-    clear_error();
-    SCT_TRY(check_op(p));
-    SCT_TRY(check_batch(batch));
-    if (!x || !y) return set_error(RADON_EINVAL, "x and y must be non-NULL");
-    const Op &op = *as_op(p);
-    SCT_TRY(check_ws(ws, ws_bytes, fwd_ws_bytes(op, batch), "radon_fwd"));
-    hipStream_t s = static_cast<hipStream_t>(stream);
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
         Carver c(ws);
@@ -412,6 +501,32 @@ extern "C" int radon_fwd(const radon_op *p, const void *x, void *y, int32_t batc
         const int64_t pe = fwd_part_elems(op, batch);
         TV *part = c.take<TV>(pe);
         return launch_fwd<TM, TV>(op, xx, xT, static_cast<TV *>(y), batch, s, pe ? part : nullptr);
+    });
+}
+
+extern "C" int radon_fwd(const radon_op *p, const void *x, void *y, int32_t batch, int32_t layout,
+                         void *ws, int64_t ws_bytes, void *stream)
+{
+    clear_error();
+    SCT_TRY(check_op(p));
+    SCT_TRY(check_batch(batch));
+    SCT_TRY(check_layout(layout));
+    if (!x || !y) return set_error(RADON_EINVAL, "x and y must be non-NULL");
+    const Op &op = *as_op(p);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t base = fwd_ws_bytes(op, batch);
+    if (!relays(layout, batch)) {
+        SCT_TRY(check_ws(ws, ws_bytes, base, "radon_fwd"));
+        return fwd_into(op, x, y, batch, ws, s);
+    }
+    SCT_TRY(check_ws(ws, ws_bytes, base + pixel_layout_extra(op, RADON_WS_FWD, batch), "radon_fwd"));
+    return dispatch(op, [&](auto *, auto *tv) {
+        using TV = std::remove_pointer_t<decltype(tv)>;
+        TV *xi = nullptr, *yi = nullptr;
+        relay_buffers<TV>(ws, base, op.nn * batch, op.rows * batch, &xi, &yi);
+        SCT_TRY(launch_relayout<TV>(static_cast<const TV *>(x), xi, op.nn, batch, false, s));
+        SCT_TRY(fwd_into(op, xi, yi, batch, ws, s));
+        return launch_relayout<TV>(yi, static_cast<TV *>(y), op.rows, batch, true, s);
     });
 }
 
@@ -433,18 +548,31 @@ extern "C" int radon_fwd_xt(const radon_op *p, const void *x, const void *xT, vo
     });
 }
 
-extern "C" int radon_adj(const radon_op *p, const void *y, void *x, int32_t batch, void *stream)
+extern "C" int radon_adj(const radon_op *p, const void *y, void *x, int32_t batch, int32_t layout,
+                         void *ws, int64_t ws_bytes, void *stream)
 {
     clear_error();
     SCT_TRY(check_op(p));
     SCT_TRY(check_batch(batch));
+    SCT_TRY(check_layout(layout));
     if (!x || !y) return set_error(RADON_EINVAL, "x and y must be non-NULL");
     const Op &op = *as_op(p);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!relays(layout, batch)) {
+        return dispatch(op, [&](auto *tm, auto *tv) {
+            SCT_TYPES(tm, tv);
+            return launch_adj<TM, TV>(op, static_cast<const TV *>(y), nullptr, static_cast<TV *>(x), 1.0,
+                                      0.0, 0.0, nullptr, batch, s);
+        });
+    }
+    SCT_TRY(check_ws(ws, ws_bytes, pixel_layout_extra(op, RADON_WS_ADJ, batch), "radon_adj"));
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
-        return launch_adj<TM, TV>(op, static_cast<const TV *>(y), nullptr, static_cast<TV *>(x), 1.0,
-                                  0.0, 0.0, nullptr, batch, s);
+        TV *xi = nullptr, *yi = nullptr;
+        relay_buffers<TV>(ws, 0, op.nn * batch, op.rows * batch, &xi, &yi);
+        SCT_TRY(launch_relayout<TV>(static_cast<const TV *>(y), yi, op.rows, batch, false, s));
+        SCT_TRY((launch_adj<TM, TV>(op, yi, nullptr, xi, 1.0, 0.0, 0.0, nullptr, batch, s)));
+        return launch_relayout<TV>(xi, static_cast<TV *>(x), op.nn, batch, true, s);
     });
 }
 
@@ -481,15 +609,28 @@ static int check_normal_args(const radon_op *p, const void *x, const void *out, 
 }
 
 extern "C" int normal_apply(const radon_op *p, double alpha, double lambda, double sigma,
-                            const void *x, void *out, double *dot_out, int32_t batch, void *ws,
-                            int64_t ws_bytes, void *stream)
+                            const void *x, void *out, double *dot_out, int32_t batch, int32_t layout,
+                            void *ws, int64_t ws_bytes, void *stream)
 {
     clear_error();
     SCT_TRY(check_normal_args(p, x, out, batch));
+    SCT_TRY(check_layout(layout));
     const Op &op = *as_op(p);
-    SCT_TRY(check_ws(ws, ws_bytes, normal_ws_bytes(op, batch), "normal_apply"));
-    return normal_apply_into(op, alpha, lambda, sigma, x, out, dot_out, batch, ws,
-                             static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t base = normal_ws_bytes(op, batch);
+    if (!relays(layout, batch)) {
+        SCT_TRY(check_ws(ws, ws_bytes, base, "normal_apply"));
+        return normal_apply_into(op, alpha, lambda, sigma, x, out, dot_out, batch, ws, s);
+    }
+    SCT_TRY(check_ws(ws, ws_bytes, base + pixel_layout_extra(op, RADON_WS_NORMAL, batch), "normal_apply"));
+    return dispatch(op, [&](auto *, auto *tv) {
+        using TV = std::remove_pointer_t<decltype(tv)>;
+        TV *xi = nullptr, *oi = nullptr;
+        relay_buffers<TV>(ws, base, op.nn * batch, op.nn * batch, &xi, &oi);
+        SCT_TRY(launch_relayout<TV>(static_cast<const TV *>(x), xi, op.nn, batch, false, s));
+        SCT_TRY(normal_apply_into(op, alpha, lambda, sigma, xi, oi, dot_out, batch, ws, s));
+        return launch_relayout<TV>(oi, static_cast<TV *>(out), op.nn, batch, true, s);
+    });
 }
 
 // ---------------------------------------------------------------------------

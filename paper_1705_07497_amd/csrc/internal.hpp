@@ -237,6 +237,23 @@ constexpr int64_t kPixelMajorSlack = 64;
 template <class TM, class TV>
 int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, double lambda,
                double sigma, double *part, int batch, hipStream_t s);
+// Batched vectors at the C ABI come in RADON_LAYOUT_IMAGE ([batch][count])
+// or RADON_LAYOUT_PIXEL ([count][batch]); the kernels work on the former, so
+// a pixel-major call relays its inputs and outputs through its workspace.
+int check_layout(int32_t layout);
+// dst = src between [batch][count] and [count][batch] (to_pixel: from the
+// former to the latter), through 32 x 32 tiles in LDS.
+template <class TV>
+int launch_relayout(const TV *src, TV *dst, int64_t count, int batch, bool to_pixel, hipStream_t s);
+// Bytes a pixel-major call of workspace kind `which` needs after the
+// image-major workspace (0 for batch 1, where both layouts are one).
+int64_t pixel_layout_extra(const Op &op, int which, int batch);
+// The two relay buffers of a pixel-major call (n0 and n1 elements), 256-byte
+// aligned after the first `base` bytes of ws.
+template <class TV>
+void relay_buffers(void *ws, int64_t base, int64_t n0, int64_t n1, TV **b0, TV **b1);
+// Whether a call relays: pixel-major with more than one image.
+inline bool relays(int32_t layout, int batch) { return layout == RADON_LAYOUT_PIXEL && batch > 1; }
 // Persistent product kernels use a fixed grid of 8 workgroups per CU (256 CUs)
 // that loop over the work items; the adjoint leaves one <x, out> partial per
 // workgroup, adj_blocks(op) of them per right-hand side.

@@ -1202,8 +1202,10 @@ static int unrolled_vjp_typed(const Op &op, double alpha, double lambda, double 
             k_rev_q<T><<<tg, tb, 0, s>>>(w.rbar, w.pbar, w.qbar, w.qbarT, p_i, q_i, gx, R, w.rs,
                                          w.cg.part_vec, vb, op.n, op.nn);
             SCT_TRY(check_launch("k_rev_q"));
-            // A qbar, added to pbar by the next (earlier) step or the final kernel
-            SCT_TRY((launch_fwd<TM, T>(op, w.qbar, w.qbarT, w.cg.y, batch, s)));
+            // A qbar, added to pbar by the next (earlier) step or the final kernel;
+            // the forward's scratch follows y (see carve_cg)
+            T *yp = fwd_part_elems(op, batch) ? w.cg.y + op.rows * batch : nullptr;
+            SCT_TRY((launch_fwd<TM, T>(op, w.qbar, w.qbarT, w.cg.y, batch, s, yp)));
             SCT_TRY((launch_adj<TM, T>(op, w.cg.y, w.qbar, w.aqb, alpha, lambda, sigma, nullptr,
                                        batch, s)));
         }
@@ -1219,34 +1221,47 @@ static int unrolled_vjp_typed(const Op &op, double alpha, double lambda, double 
 using namespace sct;
 
 extern "C" int cg_solve(const radon_op *p, double alpha, double lambda, double sigma,
-                        const void *rhs, void *x, int32_t x0_given, int32_t batch, int32_t n_iter,
-                        double rtol, void *ws, int64_t ws_bytes, radon_cg_info *info, void *stream)
+                        const void *rhs, void *x, int32_t x0_given, int32_t batch, int32_t layout,
+                        int32_t n_iter, double rtol, void *ws, int64_t ws_bytes, radon_cg_info *info,
+                        void *stream)
 {
     clear_error();
     SCT_TRY(check_op(p));
     SCT_TRY(check_batch(batch));
+    SCT_TRY(check_layout(layout));
     if (!rhs || !x) return set_error(RADON_EINVAL, "rhs and x must be non-NULL");
     if (rhs == x) return set_error(RADON_EINVAL, "x must not alias rhs");
     if (n_iter < 0) return set_error(RADON_EINVAL, "n_iter must be >= 0 (got %d)", n_iter);
     if (!(rtol >= 0.0)) return set_error(RADON_EINVAL, "rtol must be >= 0");
     const Op &op = *as_op(p);
-    SCT_TRY(check_ws(ws, ws_bytes, cg_ws_bytes(op, batch), "cg_solve"));
+    const int64_t base = cg_ws_bytes(op, batch);
+    const bool relay = relays(layout, batch);
+    SCT_TRY(check_ws(ws, ws_bytes, base + (relay ? pixel_layout_extra(op, RADON_WS_CG, batch) : 0), "cg_solve"));
     if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
     hipStream_t s = static_cast<hipStream_t>(stream);
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
-        return cg_typed<TM, TV>(op, alpha, lambda, sigma, rhs, x, x0_given, batch, n_iter, rtol, ws,
-                                info, s);
+        if (!relay)
+            return cg_typed<TM, TV>(op, alpha, lambda, sigma, rhs, x, x0_given, batch, n_iter, rtol, ws,
+                                    info, s);
+        TV *ri = nullptr, *xi = nullptr;
+        relay_buffers<TV>(ws, base, op.nn * batch, op.nn * batch, &ri, &xi);
+        SCT_TRY(launch_relayout<TV>(static_cast<const TV *>(rhs), ri, op.nn, batch, false, s));
+        if (x0_given) SCT_TRY(launch_relayout<TV>(static_cast<const TV *>(x), xi, op.nn, batch, false, s));
+        SCT_TRY((cg_typed<TM, TV>(op, alpha, lambda, sigma, ri, xi, x0_given, batch, n_iter, rtol, ws,
+                                  info, s)));
+        return launch_relayout<TV>(xi, static_cast<TV *>(x), op.nn, batch, true, s);
     });
 }
 
 extern "C" int split_bregman_tv(const radon_op *p, const radon_sb_params *params, const void *f,
-                                void *mu, int32_t batch, void *ws, int64_t ws_bytes,
+                                void *mu, int32_t batch, int32_t layout, void *ws, int64_t ws_bytes,
                                 radon_sb_info *info, void *stream)
 {
     clear_error();
     SCT_TRY(check_op(p));
     SCT_TRY(check_batch(batch));
+    SCT_TRY(check_layout(layout));
     if (!params) return set_error(RADON_EINVAL, "params is NULL");
     if (!f || !mu) return set_error(RADON_EINVAL, "f and mu must be non-NULL");
     if (!(params->lambda > 0.0)) return set_error(RADON_EINVAL, "lambda must be > 0");
@@ -1256,12 +1271,22 @@ extern "C" int split_bregman_tv(const radon_op *p, const radon_sb_params *params
     if (params->flags & ~(RADON_SB_WARM | RADON_SB_RESUME))
         return set_error(RADON_EINVAL, "unknown flags 0x%x", params->flags);
     const Op &op = *as_op(p);
-    SCT_TRY(check_ws(ws, ws_bytes, sb_ws_bytes(op, batch), "split_bregman_tv"));
+    const int64_t base = sb_ws_bytes(op, batch);
+    const bool relay = relays(layout, batch);
+    SCT_TRY(check_ws(ws, ws_bytes, base + (relay ? pixel_layout_extra(op, RADON_WS_SB, batch) : 0),
+                     "split_bregman_tv"));
     if (batch > 65535) return set_error(RADON_EUNSUPPORTED, "batch %d exceeds 65535", batch);
     hipStream_t s = static_cast<hipStream_t>(stream);
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
-        return sb_typed<TM, TV>(op, nullptr, *params, f, mu, batch, ws, info, s);
+        if (!relay) return sb_typed<TM, TV>(op, nullptr, *params, f, mu, batch, ws, info, s);
+        TV *ui = nullptr, *fi = nullptr;
+        relay_buffers<TV>(ws, base, op.nn * batch, op.rows * batch, &ui, &fi);
+        SCT_TRY(launch_relayout<TV>(static_cast<const TV *>(f), fi, op.rows, batch, false, s));
+        if (params->flags & (RADON_SB_WARM | RADON_SB_RESUME))
+            SCT_TRY(launch_relayout<TV>(static_cast<const TV *>(mu), ui, op.nn, batch, false, s));
+        SCT_TRY((sb_typed<TM, TV>(op, nullptr, *params, fi, ui, batch, ws, info, s)));
+        return launch_relayout<TV>(ui, static_cast<TV *>(mu), op.nn, batch, true, s);
     });
 }
 

@@ -46,6 +46,11 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct.PdParams) == 40
     assert int(consts["RADON_WS_PD"]) == sct.WS_PD
     assert int(consts["RADON_WS_TUNE"]) == sct.WS_TUNE
+    assert int(consts["RADON_WS_ADJ"]) == sct.WS_ADJ
+    assert int(consts["RADON_LAYOUT_IMAGE"]) == sct.LAYOUT_IMAGE
+    assert int(consts["RADON_LAYOUT_PIXEL"]) == sct.LAYOUT_PIXEL
+    hexes = dict(re.findall(r"#define\s+(\w+)\s+0x([0-9a-fA-F]+)", text))
+    assert int(hexes["RADON_WS_PIXEL_LAYOUT"], 16) == sct.WS_PIXEL_LAYOUT
     assert ctypes.sizeof(sct._Geom) == 32
     assert ctypes.sizeof(sct.RadonSizes) == 72
     assert ctypes.sizeof(sct.RadonBuffers) == 80
@@ -93,12 +98,12 @@ def test_null_handles_are_rejected():
     assert L.build_radon_csr(None, None, None) == -1
     h = ctypes.c_void_p()
     assert L.build_radon_csr(None, None, ctypes.byref(h)) == -1
-    assert L.radon_fwd(None, None, None, 1, None, 0, None) == -1
+    assert L.radon_fwd(None, None, None, 1, 0, None, 0, None) == -1
     assert "NULL" in L.radon_last_error().decode()
-    assert L.radon_adj(None, None, None, 1, None) == -1
-    assert L.normal_apply(None, 1.0, 1.0, 0.0, None, None, None, 1, None, 0, None) == -1
-    assert L.cg_solve(None, 1.0, 1.0, 0.0, None, None, 0, 1, 5, 0.0, None, 0, None, None) == -1
-    assert L.split_bregman_tv(None, None, None, None, 1, None, 0, None, None) == -1
+    assert L.radon_adj(None, None, None, 1, 0, None, 0, None) == -1
+    assert L.normal_apply(None, 1.0, 1.0, 0.0, None, None, None, 1, 0, None, 0, None) == -1
+    assert L.cg_solve(None, 1.0, 1.0, 0.0, None, None, 0, 1, 0, 5, 0.0, None, 0, None, None) == -1
+    assert L.split_bregman_tv(None, None, None, None, 1, 0, None, 0, None, None) == -1
     assert L.radon_workspace_bytes(None, 0, 1) == -1
     info = sct._Info()
     assert L.radon_op_info(None, ctypes.byref(info)) == -1

@@ -380,10 +380,10 @@ def test_workspace_and_argument_errors_on_gpu():
     x = torch.zeros(256, dtype=F32, device="cuda")
     out = torch.zeros(256, dtype=F32, device="cuda")
     ws, nbytes = op.workspace(sct.WS_NORMAL, 1)
-    rc = L.normal_apply(op._h, 1.0, 1.0, 0.0, sct._vp(x.data_ptr()), sct._vp(out.data_ptr()), None, 1,
+    rc = L.normal_apply(op._h, 1.0, 1.0, 0.0, sct._vp(x.data_ptr()), sct._vp(out.data_ptr()), None, 1, 0,
                         sct._vp(ws.data_ptr()), nbytes - 1, None)
     assert rc == -4 and "workspace" in L.radon_last_error().decode()
-    rc = L.normal_apply(op._h, 1.0, 1.0, 0.0, sct._vp(x.data_ptr()), sct._vp(x.data_ptr()), None, 1,
+    rc = L.normal_apply(op._h, 1.0, 1.0, 0.0, sct._vp(x.data_ptr()), sct._vp(x.data_ptr()), None, 1, 0,
                         sct._vp(ws.data_ptr()), nbytes, None)
     assert rc == -1 and "alias" in L.radon_last_error().decode()
     with pytest.raises(sct.SparsectError):

@@ -34,7 +34,7 @@ def _abi_pair(op, x, alpha, lam, sigma):
     ws, nb = op.workspace(sct.WS_NORMAL, b)
     s = op._stream()
     rc = L.normal_apply(op._h, alpha, lam, sigma, _vp(x.data_ptr()), _vp(o_ws.data_ptr()),
-                        _vp(d_ws.data_ptr()), b, _vp(ws.data_ptr()), nb, s)
+                        _vp(d_ws.data_ptr()), b, 0, _vp(ws.data_ptr()), nb, s)
     assert rc == 0, L.radon_last_error()
     rc = L.normal_apply_noalloc(op._h, alpha, lam, sigma, _vp(x.data_ptr()), _vp(o_na.data_ptr()),
                                 _vp(d_na.data_ptr()), b, s)
