@@ -12,11 +12,13 @@
 // Lanes: the C / VW 16-byte groups of a pixel are split over GL adjacent
 // lanes of one ray (each lane takes IQ = C / (VW GL) groups), so the 16-byte
 // loads of GL neighbouring lanes are one contiguous run; the rest of the
-// wave's 64 / BW lanes per ray take Q different quads of the bundle, as in
-// fwd_quads.  Lane = (q, r, gl), gl fastest.
+// wave's 64 / BW lanes per ray take Q different runs of GL quads of the
+// bundle.  Lane = (q, r, gl), gl fastest.
 #pragma once
 
 #include "products.hpp"
+
+#include <type_traits>
 
 namespace sct {
 
@@ -65,8 +67,50 @@ __global__ __launch_bounds__(256) void k_pixel_major(const TV *__restrict__ x, T
     }
 }
 
+// Compile-time loop: f(std::integral_constant<int, J>) for J = J0 .. N-1.
+template <int J, int N>
+struct StaticFor {
+    template <class F>
+    __device__ __forceinline__ static void run(F &&f)
+    {
+        f(std::integral_constant<int, J>{});
+        StaticFor<J + 1, N>::run(f);
+    }
+};
+template <int N>
+struct StaticFor<N, N> {
+    template <class F>
+    __device__ __forceinline__ static void run(F &&)
+    {
+    }
+};
+
+// v as held by lane J of this lane's group of GL adjacent lanes (GL = 1, 2
+// or 4), through a DPP quad permutation of each 32-bit word (no LDS).
+template <int GL, int J, class V>
+__device__ __forceinline__ V group_bcast(const V &v)
+{
+    if constexpr (GL == 1) {
+        return v;
+    } else {
+        static_assert(sizeof(V) % 4 == 0, "32-bit words");
+        constexpr int perm = GL == 4 ? J * 0x55 : (J | (J << 2) | ((2 + J) << 4) | ((2 + J) << 6));
+        constexpr int nw = int(sizeof(V) / 4);
+        int w[nw];
+        __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+        for (int k = 0; k < nw; ++k) w[k] = __builtin_amdgcn_mov_dpp(w[k], perm, 0xf, 0xf, false);
+        V out;
+        __builtin_memcpy(&out, w, sizeof(V));
+        return out;
+    }
+}
+
 // The quads [s0, s1) of one bundle for the C images of a pixel-major chunk
-// (PAIR as in fwd_quads).
+// (PAIR as in fwd_quads).  The GL lanes of a (q, r) group load GL
+// consecutive quads of ray r with one set of stream loads and hand each
+// quad's slots to the whole group, so every matrix entry is loaded once; a
+// quad past s1 gets zero weights (in-bounds gathers, no branch).
 template <class TM, class TV, int C, bool PAIR, int BW>
 __device__ __forceinline__ void pm_quads(const FwdBundle &d, const u16x4 *__restrict__ I,
                                          const typename Quad<TM>::type *__restrict__ A,
@@ -78,36 +122,44 @@ __device__ __forceinline__ void pm_quads(const FwdBundle &d, const u16x4 *__rest
     using S = PmShape<TV, C, BW>;
     using Qv = typename Quad<TM>::type;
     using V = typename Vec16<TV>::type;
-#pragma unroll 2
-    for (int tq = s0 + q; tq < s1; tq += S::Q) {
-        const int e = tq * BW + r;
+    for (int tq = s0 + q * S::GL; tq < s1; tq += S::SUB) {
+        const bool live = tq + gl < s1;
+        const int e = (live ? tq + gl : tq) * BW + r;
         const u16x4 i4 = stream_load(I + e);
-        const Qv a4 = stream_load(A + e);
-        const Qv b4 = stream_load(Bv + e);
+        Qv a4 = stream_load(A + e);
+        Qv b4 = stream_load(Bv + e);
+        a4 = live ? a4 : Qv(0);
+        b4 = live ? b4 : Qv(0);
+        StaticFor<0, S::GL>::run([&](auto jc) {
+            constexpr int J = decltype(jc)::value;
+            const u16x4 ij = group_bcast<S::GL, J>(i4);
+            const Qv aj = group_bcast<S::GL, J>(a4);
+            const Qv bj = group_bcast<S::GL, J>(b4);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int m = min(d.m0 + 4 * tq + k, n - 1);
-            const int i0 = i4[k];
-            const int ic = PAIR ? (i0 < n - 1 ? i0 : n - 2) : 0;
-            const V *__restrict__ p = xp + (int64_t(m) * n + ic) * S::NG + gl;
-            const TV a = TV(a4[k]), b = TV(b4[k]);
+            for (int k = 0; k < 4; ++k) {
+                const int m = min(d.m0 + 4 * (tq + J) + k, n - 1);
+                const int i0 = ij[k];
+                const int ic = PAIR ? (i0 < n - 1 ? i0 : n - 2) : 0;
+                const V *__restrict__ p = xp + (int64_t(m) * n + ic) * S::NG + gl;
+                const TV a = TV(aj[k]), b = TV(bj[k]);
 #pragma unroll
-            for (int iq = 0; iq < S::IQ; ++iq) {
-                const V u = p[iq * S::GL];
-                if constexpr (PAIR) {
-                    const V w = p[S::NG + iq * S::GL];
-                    const V f = i0 == ic ? u : w;
+                for (int iq = 0; iq < S::IQ; ++iq) {
+                    const V u = p[iq * S::GL];
+                    if constexpr (PAIR) {
+                        const V w = p[S::NG + iq * S::GL];
+                        const V f = i0 == ic ? u : w;
 #pragma unroll
-                    for (int v = 0; v < S::VW; ++v) {
-                        acc[iq][v] = fma(a, f[v], acc[iq][v]);
-                        acc[iq][v] = fma(b, w[v], acc[iq][v]);
+                        for (int v = 0; v < S::VW; ++v) {
+                            acc[iq][v] = fma(a, f[v], acc[iq][v]);
+                            acc[iq][v] = fma(b, w[v], acc[iq][v]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < S::VW; ++v) acc[iq][v] = fma(a, u[v], acc[iq][v]);
                     }
-                } else {
-#pragma unroll
-                    for (int v = 0; v < S::VW; ++v) acc[iq][v] = fma(a, u[v], acc[iq][v]);
                 }
             }
-        }
+        });
     }
 }
 
