@@ -268,8 +268,10 @@ int radon_fwd_xt(const radon_op *op, const void *x, const void *xT, void *y, int
  * eq:SB_solve), through the stored transpose: each output pixel is one
  * sequential sum, no atomics.  y: batch sinograms of n_meas_rays -> x: batch
  * images of n*n, both in `layout`.
- *   ws  radon_workspace_bytes(op, RADON_WS_ADJ, batch) bytes (0: may be
- *       NULL), | RADON_WS_PIXEL_LAYOUT for a pixel-major call.
+ *   ws  radon_workspace_bytes(op, RADON_WS_ADJ, batch) bytes
+ *       (| RADON_WS_PIXEL_LAYOUT for a pixel-major call).  An image-major call
+ *       may pass NULL (or fewer bytes): it then stages every sinogram of a
+ *       chunk on its own, whatever adj_layout says.
  */
 int radon_adj(const radon_op *op, const void *y, void *x, int32_t batch, int32_t layout,
               void *ws, int64_t ws_bytes, void *stream);
@@ -704,6 +706,12 @@ int split_bregman_tv_fourier(const radon_fourier *f, int32_t path, const radon_s
  *              copy of the chunk (a pixel's values for all images of the
  *              chunk contiguous, so one 16-byte load serves 4 FP32 or 2 FP64
  *              images), made in the call's workspace;
+ *   adj_layout how a fused adjoint chunk of 4 or more sinograms stages its
+ *              bands: 0 = from each sinogram in turn; 1 = from a pixel-major
+ *              copy of the chunk's sinograms (a measurement's values for all
+ *              images contiguous), made in the call's workspace (radon_adj
+ *              uses it only when given a workspace of the size
+ *              radon_workspace_bytes reports);
  *   fwd_lines  height of the line bands of a forward that has a workspace:
  *              0 = chosen from the chunk's image bytes (the largest of 128,
  *              64, 32, 16 lines whose band of the chunk's images fits 2 MB;
@@ -716,7 +724,8 @@ int split_bregman_tv_fourier(const radon_fourier *f, int32_t path, const radon_s
  * geometry.
  */
 typedef struct {
-    int32_t fwd_waves, adj_waves, fwd_rhs, adj_rhs, fwd_layout, fwd_lines;
+    int32_t fwd_waves, adj_waves, fwd_rhs, adj_rhs, fwd_layout, fwd_lines, adj_layout;
+    int32_t reserved;   /* 0 */
 } radon_tuning;
 
 int radon_set_tuning(radon_op *op, const radon_tuning *t);
@@ -730,7 +739,8 @@ int radon_get_tuning(const radon_op *op, radon_tuning *out);
  * adjoint (1, 4, 8, 16 each; at most batch), jointly on the normal
  * operator's two products; then, at that adjoint chunk, every forward chunk
  * of 4 or more images with each gather layout (fwd_layout) and band height
- * (fwd_lines) the operator has.  The search starts from fwd_layout = 0 and
+ * (fwd_lines) the operator has, and the adjoint chunk's staging layout
+ * (adj_layout).  The search starts from fwd_layout = adj_layout = 0 and
  * fwd_lines = 0.  The forward bundle width is a layout choice made at build
  * time (radon_geom.fwd_bundle), not tuned here.
  *   batch       the batch the operator will run at (1 .. 65535).

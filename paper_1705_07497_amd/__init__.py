@@ -95,7 +95,8 @@ FWS_TRANSFORM, FWS_SB = 0, 1
 class Tuning(ctypes.Structure):
     _fields_ = [("fwd_waves", ctypes.c_int32), ("adj_waves", ctypes.c_int32),
                 ("fwd_rhs", ctypes.c_int32), ("adj_rhs", ctypes.c_int32),
-                ("fwd_layout", ctypes.c_int32), ("fwd_lines", ctypes.c_int32)]
+                ("fwd_layout", ctypes.c_int32), ("fwd_lines", ctypes.c_int32),
+                ("adj_layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -25,7 +25,8 @@ import ctypes
 import hashlib
 import os
 
-DEFAULT = {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8, "fwd_layout": 0, "fwd_lines": 0}
+DEFAULT = {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8, "fwd_layout": 0, "fwd_lines": 0,
+           "adj_layout": 0, "reserved": 0}
 BUNDLES = (16, 32, 64)
 SOURCES = {0: "unchanged", 1: "cache", 2: "timed"}
 

@@ -173,6 +173,136 @@ __global__ __launch_bounds__(64 * W) void k_adj(const uint8_t *__restrict__ rel,
     }
 }
 
+// Pixel-major copy of a chunk of nb sinograms: dst[i*C + c] = src[c*count + i]
+// for c < nb, 0 for nb <= c < C, through a tile of 64 measurements x C in LDS
+// (reads along i, writes along c).
+template <class T, int C>
+__global__ __launch_bounds__(256) void k_chunk_pm(const T *__restrict__ src, T *__restrict__ dst,
+                                                  int64_t count, int nb)
+{
+    __shared__ T tile[C][65];
+    const int64_t i0 = int64_t(blockIdx.x) * 64;
+    for (int k = threadIdx.x; k < 64 * C; k += 256) {
+        const int c = k / 64, i = k % 64;
+        tile[c][i] = (c < nb && i0 + i < count) ? src[int64_t(c) * count + i0 + i] : T(0);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 64 * C; k += 256) {
+        const int c = k % C, i = k / C;
+        if (i0 + i < count) dst[(i0 + i) * C + c] = tile[c][i];
+    }
+}
+
+// k_adj for one chunk of C sinograms given pixel-major (ypm[ray][c], the
+// slots of absent images zero): each lane stages its band element for all C
+// images with C / VW 16-byte loads and LDS writes, and reads a slot's two
+// bins for 4 FP32 or 2 FP64 images per 16-byte LDS read.  The per-image
+// staging of k_adj moves a 64-byte band run per angle and image through the
+// L1, most of a 128-byte line; here one angle's band for the chunk is
+// 16 x C x 4 or 8 contiguous bytes.  Tile order, wave split, summation order
+// per image and the epilogue are those of k_adj.
+template <class TM, class T, int W, int C>
+__global__ __launch_bounds__(64 * W) void k_adj_pm(const uint8_t *__restrict__ rel,
+                                                   const uint16_t *__restrict__ base,
+                                                   const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                   int n_meas, int n_aq, int nb, const T *__restrict__ ypm,
+                                                   const T *__restrict__ x, T *__restrict__ out, T alpha,
+                                                   T lambda, T sigma, double *__restrict__ part, int n,
+                                                   int tiles, int64_t nn, int nbc,
+                                                   const int32_t *__restrict__ order, int64_t n_order)
+{
+    using Q = typename Quad<TM>::type;
+    using V = typename Vec16<T>::type;
+    constexpr int VW = 16 / int(sizeof(T)), NG = C / VW;
+    __shared__ V band[W][4 * kAdjBand][NG];
+    __shared__ uint16_t bases[W][kAdjLanes];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int q0 = (n_aq * wave) / W, q1 = (n_aq * (wave + 1)) / W;
+    const uint32_t *__restrict__ Rl = reinterpret_cast<const uint32_t *>(rel);
+    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0);
+    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1);
+    const V *__restrict__ yv16 = reinterpret_cast<const V *>(ypm);
+    const int kk = lane >> 4, ee = lane & 15;   // this lane's band element
+    double dsum[C];                             // this block's share of <x, out>
+#pragma unroll
+    for (int c = 0; c < C; ++c) dsum[c] = 0.0;
+    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+        const int64_t g = order[o];
+        if (g < 0) continue;   // padding entry (uniform per block)
+        T acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = T(0);
+        for (int c0 = q0; c0 < q1; c0 += kBaseChunk) {
+            const int nc = min(kBaseChunk, q1 - c0);
+            if (lane < 4 * nc) bases[wave][lane] = base[(g * n_aq + c0) * 4 + lane];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+            for (int j = 0; j < nc; ++j) {
+                const int aq = c0 + j;
+                const int64_t gq = g * n_aq + aq;
+                const int a_band = min(4 * aq + kk, n_meas - 1);
+                const int64_t band_at =
+                    int64_t(a_band) * nb + min(int(bases[wave][4 * j + kk]) + ee, nb - 1);
+                V yv[NG];
+#pragma unroll
+                for (int h = 0; h < NG; ++h) yv[h] = yv16[band_at * NG + h];
+                const int64_t e = gq * kAdjLanes + lane;
+                const uint32_t r4 = stream_load(Rl + e);
+                const Q a4 = stream_load(A + e);
+                const Q c4 = stream_load(Bv + e);
+#pragma unroll
+                for (int h = 0; h < NG; ++h) band[wave][lane][h] = yv[h];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int rb = k * kAdjBand + int((r4 >> (8 * k)) & 0xffu);
+                    const T a = T(a4[k]), b = T(c4[k]);
+#pragma unroll
+                    for (int h = 0; h < NG; ++h) {
+                        const V u = band[wave][rb][h], w = band[wave][rb + 1][h];
+#pragma unroll
+                        for (int v = 0; v < VW; ++v) {
+                            acc[h * VW + v] = fma(a, u[v], acc[h * VW + v]);
+                            acc[h * VW + v] = fma(b, w[v], acc[h * VW + v]);
+                        }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if constexpr (W > 1) {
+            __shared__ T red[W][C][64];
+#pragma unroll
+            for (int c = 0; c < C; ++c) red[wave][c][lane] = acc[c];
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    acc[c] = red[0][c][lane];
+#pragma unroll
+                    for (int w = 1; w < W; ++w) acc[c] += red[w][c][lane];
+                }
+            }
+            __syncthreads();   // red is reused by the next tile
+        }
+        if (wave == 0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (c < nbc)
+                    dsum[c] += adj_epilogue(g, lane, acc[c], x ? x + int64_t(c) * nn : nullptr,
+                                            out + int64_t(c) * nn, alpha, lambda, sigma, n, tiles);
+            }
+        }
+    }
+    if (part && wave == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const double v = wave_sum(dsum[c]);
+            if (c < nbc && lane == 0) part[int64_t(c) * gridDim.x + blockIdx.x] = v;
+        }
+    }
+}
+
 // dst[b] = sum_i part[b][i], in a fixed order (one block per b).
 __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part,
                                                       int64_t count, double *__restrict__ dst)
@@ -275,10 +405,29 @@ static int adj_waves(const Op &op)
 
 template <class TM, class TV, int W, int BC>
 static void adj_wbc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV la, TV si,
-                    double *part, int batch, hipStream_t s)
+                    double *part, int batch, hipStream_t s, TV *scratch)
 {
     const dim3 grid(unsigned(adj_blocks(op)), unsigned((batch + BC - 1) / BC));
     const TM *a0 = static_cast<const TM *>(op.a_v0), *a1 = static_cast<const TM *>(op.a_v1);
+    if constexpr (BC > 1) {
+        if (scratch && op.tune.adj_layout == 1) {
+            // chunks one after another, each from its pixel-major copy
+            const uintptr_t a = (reinterpret_cast<uintptr_t>(scratch) + 15) & ~uintptr_t(15);
+            TV *ypm = reinterpret_cast<TV *>(a);
+            const unsigned G = grid.x;
+            for (int c0 = 0; c0 < batch; c0 += BC) {
+                const int nb = batch - c0 < BC ? batch - c0 : BC;
+                k_chunk_pm<TV, BC><<<unsigned((op.rows + 63) / 64), 256, 0, s>>>(y + int64_t(c0) * op.rows, ypm,
+                                                                                 op.rows, nb);
+                k_adj_pm<TM, TV, W, BC><<<dim3(G, 1u), 64 * W, 0, s>>>(
+                    op.a_rel, op.a_base, a0, a1, op.n_meas, op.n_aq, op.n_bins, ypm,
+                    x ? x + int64_t(c0) * op.nn : nullptr, out + int64_t(c0) * op.nn, al, la, si,
+                    part ? part + int64_t(c0) * G : nullptr, op.n, op.tiles, op.nn, nb, op.a_order,
+                    op.n_a_order);
+            }
+            return;
+        }
+    }
     if constexpr (BC == 1)
         k_adj1<TM, TV, W><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.n_ag, op.n_meas,
                                                  op.n_aq, op.n_bins, y, x, out, al, la, si, part,
@@ -300,26 +449,39 @@ static void adj_wbc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV l
 
 template <class TM, class TV, int BC>
 static void adj_bc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV la, TV si,
-                   double *part, int batch, hipStream_t s)
+                   double *part, int batch, hipStream_t s, TV *scratch)
 {
     switch (adj_waves(op)) {
-    case 4: adj_wbc<TM, TV, 4, BC>(op, y, x, out, al, la, si, part, batch, s); break;
-    case 2: adj_wbc<TM, TV, 2, BC>(op, y, x, out, al, la, si, part, batch, s); break;
-    default: adj_wbc<TM, TV, 1, BC>(op, y, x, out, al, la, si, part, batch, s); break;
+    case 4: adj_wbc<TM, TV, 4, BC>(op, y, x, out, al, la, si, part, batch, s, scratch); break;
+    case 2: adj_wbc<TM, TV, 2, BC>(op, y, x, out, al, la, si, part, batch, s, scratch); break;
+    default: adj_wbc<TM, TV, 1, BC>(op, y, x, out, al, la, si, part, batch, s, scratch); break;
     }
+}
+
+int64_t adj_scratch_elems(const Op &op, int batch)
+{
+    const int bc = rhs_chunk(batch, op.tune.adj_rhs);
+    if (op.tune.adj_layout != 1 || bc < 4) return 0;
+    return kPixelMajorSlack + int64_t(bc) * op.rows;
+}
+
+int64_t prod_scratch_elems(const Op &op, int batch)
+{
+    const int64_t f = fwd_part_elems(op, batch), a = adj_scratch_elems(op, batch);
+    return f > a ? f : a;
 }
 
 template <class TM, class TV>
 int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, double lambda,
-               double sigma, double *part, int batch, hipStream_t s)
+               double sigma, double *part, int batch, hipStream_t s, TV *scratch)
 {
     SCT_TRY(check_grid_y(batch));
     const TV al = TV(alpha), la = TV(lambda), si = TV(sigma);
     switch (rhs_chunk(batch, op.tune.adj_rhs)) {
-    case 16: adj_bc<TM, TV, 16>(op, y, x, out, al, la, si, part, batch, s); break;
-    case 8: adj_bc<TM, TV, 8>(op, y, x, out, al, la, si, part, batch, s); break;
-    case 4: adj_bc<TM, TV, 4>(op, y, x, out, al, la, si, part, batch, s); break;
-    default: adj_bc<TM, TV, 1>(op, y, x, out, al, la, si, part, batch, s); break;
+    case 16: adj_bc<TM, TV, 16>(op, y, x, out, al, la, si, part, batch, s, scratch); break;
+    case 8: adj_bc<TM, TV, 8>(op, y, x, out, al, la, si, part, batch, s, scratch); break;
+    case 4: adj_bc<TM, TV, 4>(op, y, x, out, al, la, si, part, batch, s, scratch); break;
+    default: adj_bc<TM, TV, 1>(op, y, x, out, al, la, si, part, batch, s, scratch); break;
     }
     return check_launch("k_adj");
 }
@@ -336,7 +498,7 @@ template int launch_transpose<double>(const Op &, const double *, double *, int,
     template int launch_fwd<TM, TV>(const Op &, const TV *, const TV *, TV *, int, hipStream_t,   \
                                     TV *);                                                        \
     template int launch_adj<TM, TV>(const Op &, const TV *, const TV *, TV *, double, double,     \
-                                    double, double *, int, hipStream_t);
+                                    double, double *, int, hipStream_t, TV *);
 SCT_INST(float, float)
 SCT_INST(double, double)
 SCT_INST(float, double)
@@ -450,9 +612,11 @@ static int64_t normal_ws_bytes(const Op &op, int batch)
     if (op.need_T) c.take<char>(int64_t(op.vsize) * op.nn * batch);
     c.take<char>(int64_t(op.vsize) * op.rows * batch);
     c.take<double>(op.n_ag * batch);
-    c.take<char>(int64_t(op.vsize) * fwd_part_elems(op, batch));
+    c.take<char>(int64_t(op.vsize) * prod_scratch_elems(op, batch));
     return c.used;
 }
+
+static int64_t adj_ws_bytes(const Op &op, int batch) { return int64_t(op.vsize) * adj_scratch_elems(op, batch); }
 
 int64_t cg_ws_bytes(const Op &op, int batch);   // solve.hip
 int64_t sb_ws_bytes(const Op &op, int batch);   // solve.hip
@@ -476,7 +640,7 @@ extern "C" int64_t radon_workspace_bytes(const radon_op *p, int32_t which, int32
     const int64_t extra = pixel ? pixel_layout_extra(op, kind, batch) : 0;
     switch (kind) {
     case RADON_WS_FWD: return fwd_ws_bytes(op, batch) + extra;
-    case RADON_WS_ADJ: return extra;
+    case RADON_WS_ADJ: return adj_ws_bytes(op, batch) + extra;
     case RADON_WS_NORMAL: return normal_ws_bytes(op, batch) + extra;
     case RADON_WS_CG: return cg_ws_bytes(op, batch) + extra;
     case RADON_WS_SB: return sb_ws_bytes(op, batch) + extra;
@@ -558,20 +722,25 @@ extern "C" int radon_adj(const radon_op *p, const void *y, void *x, int32_t batc
     if (!x || !y) return set_error(RADON_EINVAL, "x and y must be non-NULL");
     const Op &op = *as_op(p);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t base = adj_ws_bytes(op, batch);
     if (!relays(layout, batch)) {
+        // the workspace is optional here: without it every sinogram of a
+        // chunk is staged on its own
+        const bool scr = base > 0 && ws && ws_bytes >= base;
         return dispatch(op, [&](auto *tm, auto *tv) {
             SCT_TYPES(tm, tv);
             return launch_adj<TM, TV>(op, static_cast<const TV *>(y), nullptr, static_cast<TV *>(x), 1.0,
-                                      0.0, 0.0, nullptr, batch, s);
+                                      0.0, 0.0, nullptr, batch, s, scr ? static_cast<TV *>(ws) : nullptr);
         });
     }
-    SCT_TRY(check_ws(ws, ws_bytes, pixel_layout_extra(op, RADON_WS_ADJ, batch), "radon_adj"));
+    SCT_TRY(check_ws(ws, ws_bytes, base + pixel_layout_extra(op, RADON_WS_ADJ, batch), "radon_adj"));
     return dispatch(op, [&](auto *tm, auto *tv) {
         SCT_TYPES(tm, tv);
         TV *xi = nullptr, *yi = nullptr;
-        relay_buffers<TV>(ws, 0, op.nn * batch, op.rows * batch, &xi, &yi);
+        relay_buffers<TV>(ws, base, op.nn * batch, op.rows * batch, &xi, &yi);
         SCT_TRY(launch_relayout<TV>(static_cast<const TV *>(y), yi, op.rows, batch, false, s));
-        SCT_TRY((launch_adj<TM, TV>(op, yi, nullptr, xi, 1.0, 0.0, 0.0, nullptr, batch, s)));
+        SCT_TRY((launch_adj<TM, TV>(op, yi, nullptr, xi, 1.0, 0.0, 0.0, nullptr, batch, s,
+                                    base > 0 ? static_cast<TV *>(ws) : nullptr)));
         return launch_relayout<TV>(xi, static_cast<TV *>(x), op.nn, batch, true, s);
     });
 }
@@ -587,13 +756,13 @@ static int normal_apply_into(const Op &op, double alpha, double lambda, double s
         TV *xT = op.need_T ? c.take<TV>(op.nn * batch) : nullptr;
         TV *y = c.take<TV>(op.rows * batch);
         double *part = c.take<double>(op.n_ag * batch);
-        const int64_t pe = fwd_part_elems(op, batch);
-        TV *ypart = c.take<TV>(pe);
+        TV *scr = c.take<TV>(prod_scratch_elems(op, batch));
         const TV *xx = static_cast<const TV *>(x);
         if (xT) SCT_TRY(launch_transpose<TV>(op, xx, xT, batch, s));
-        SCT_TRY(launch_fwd<TM, TV>(op, xx, xT, y, batch, s, pe ? ypart : nullptr));
+        SCT_TRY(launch_fwd<TM, TV>(op, xx, xT, y, batch, s, fwd_part_elems(op, batch) ? scr : nullptr));
         SCT_TRY(launch_adj<TM, TV>(op, y, xx, static_cast<TV *>(out), alpha, lambda, sigma,
-                                   dot_out ? part : nullptr, batch, s));
+                                   dot_out ? part : nullptr, batch, s,
+                                   adj_scratch_elems(op, batch) ? scr : nullptr));
         if (dot_out) SCT_TRY(launch_sum_partials(part, adj_blocks(op), dot_out, batch, s));
         return RADON_OK;
     });
@@ -701,6 +870,9 @@ extern "C" int radon_set_tuning(radon_op *p, const radon_tuning *t)
             return set_error(RADON_EINVAL, "fwd_rhs and adj_rhs must be 1, 4, 8 or 16 (got %d)", v);
     if (t->fwd_layout != 0 && t->fwd_layout != 1)
         return set_error(RADON_EINVAL, "fwd_layout must be 0 or 1 (got %d)", t->fwd_layout);
+    if (t->adj_layout != 0 && t->adj_layout != 1)
+        return set_error(RADON_EINVAL, "adj_layout must be 0 or 1 (got %d)", t->adj_layout);
+    if (t->reserved != 0) return set_error(RADON_EINVAL, "reserved must be 0 (got %d)", t->reserved);
     if (t->fwd_lines != 0) {
         bool built = false;
         for (const BandSet &b : as_op(p)->bands) built = built || (b.n_bands > 0 && b.lines == t->fwd_lines);

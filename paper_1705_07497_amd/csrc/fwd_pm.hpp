@@ -22,11 +22,6 @@
 
 namespace sct {
 
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <class TV> struct Vec16;
-template <> struct Vec16<float> { using type = f32x4; };
-template <> struct Vec16<double> { using type = f64x2; };
-
 template <class TV, int C, int BW>
 struct PmShape {
     static constexpr int VW = 16 / int(sizeof(TV));   // images per 16-byte load

@@ -134,7 +134,7 @@ struct Op {
     int32_t *a_order = nullptr;
     int64_t n_a_order = 0;
 
-    radon_tuning tune{2, 0, 4, 8, 0, 0};   // launch tuning (see radon_set_tuning)
+    radon_tuning tune{2, 0, 4, 8, 0, 0, 0, 0};   // launch tuning (see radon_set_tuning)
 };
 
 // thread-local error state
@@ -233,10 +233,17 @@ inline bool fwd_pixel_major(int layout, int bc) { return layout == 1 && bc >= 4;
 constexpr int64_t kPixelMajorSlack = 64;
 // out = alpha (MR)^T y + lambda K^T K x + sigma x; partial <x, out> per group
 // into part[batch][n_ag] when part != nullptr.  x may be nullptr when
-// lambda == sigma == 0 and part == nullptr.
+// lambda == sigma == 0 and part == nullptr.  With scratch
+// (adj_scratch_elems(op, batch) elements) a chunk stages its bands from a
+// pixel-major copy of its sinograms when the tuning asks for it.
 template <class TM, class TV>
 int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, double lambda,
-               double sigma, double *part, int batch, hipStream_t s);
+               double sigma, double *part, int batch, hipStream_t s, TV *scratch = nullptr);
+// Scratch elements of a fused adjoint over `batch` sinograms (0: none).
+int64_t adj_scratch_elems(const Op &op, int batch);
+// Scratch of a normal-operator product (the forward's, then the adjoint's,
+// in one region: the adjoint starts after the forward has finished with it).
+int64_t prod_scratch_elems(const Op &op, int batch);
 // Batched vectors at the C ABI come in RADON_LAYOUT_IMAGE ([batch][count])
 // or RADON_LAYOUT_PIXEL ([count][batch]); the kernels work on the former, so
 // a pixel-major call relays its inputs and outputs through its workspace.

@@ -39,6 +39,12 @@ template <class T> struct PairU;
 template <> struct PairU<float> { using type = f32x2u; };
 template <> struct PairU<double> { using type = f64x2u; };
 
+// 16 bytes of vector elements (4 FP32 or 2 FP64), 16-byte aligned.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <class TV> struct Vec16;
+template <> struct Vec16<float> { using type = f32x4; };
+template <> struct Vec16<double> { using type = f64x2; };
+
 // The matrix streams are read exactly once per product: non-temporal loads
 // keep them from evicting the gathered vector from the caches.
 template <class V>

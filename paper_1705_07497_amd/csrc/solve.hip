@@ -433,8 +433,8 @@ static void carve_cg(const Op &op, int batch, Carver &c, CgBufs<T> &w)
     w.p = c.take<T>(nb);
     w.pT = op.need_T ? c.take<T>(nb) : nullptr;
     w.q = c.take<T>(nb);
-    // the forward's band partials (if any) follow y
-    w.y = c.take<T>(op.rows * batch + fwd_part_elems(op, batch));
+    // the products' scratch (band partials, pixel-major copies) follows y
+    w.y = c.take<T>(op.rows * batch + prod_scratch_elems(op, batch));
     // one partial per adjoint workgroup, or per image row (the Fourier-domain
     // operator's row pass)
     w.part_adj = c.take<double>((op.n_ag > op.n ? op.n_ag : int64_t(op.n)) * batch);
@@ -510,10 +510,11 @@ struct ExactA {
     int operator()(const T *p, const T *pT, T *q, T *y, double *part, int batch,
                    hipStream_t s) const
     {
-        // y comes from carve_cg, with room for the band partials after it
-        T *yp = fwd_part_elems(op, batch) ? y + op.rows * batch : nullptr;
-        SCT_TRY((launch_fwd<TM, T>(op, p, pT, y, batch, s, yp)));
-        return launch_adj<TM, T>(op, y, p, q, alpha, lambda, sigma, part, batch, s);
+        // y comes from carve_cg, with room for the products' scratch after it
+        T *scr = y + op.rows * batch;
+        SCT_TRY((launch_fwd<TM, T>(op, p, pT, y, batch, s, fwd_part_elems(op, batch) ? scr : nullptr)));
+        return launch_adj<TM, T>(op, y, p, q, alpha, lambda, sigma, part, batch, s,
+                                 adj_scratch_elems(op, batch) ? scr : nullptr);
     }
 };
 
@@ -1203,11 +1204,12 @@ static int unrolled_vjp_typed(const Op &op, double alpha, double lambda, double 
                                          w.cg.part_vec, vb, op.n, op.nn);
             SCT_TRY(check_launch("k_rev_q"));
             // A qbar, added to pbar by the next (earlier) step or the final kernel;
-            // the forward's scratch follows y (see carve_cg)
-            T *yp = fwd_part_elems(op, batch) ? w.cg.y + op.rows * batch : nullptr;
-            SCT_TRY((launch_fwd<TM, T>(op, w.qbar, w.qbarT, w.cg.y, batch, s, yp)));
+            // the products' scratch follows y (see carve_cg)
+            T *scr = w.cg.y + op.rows * batch;
+            SCT_TRY((launch_fwd<TM, T>(op, w.qbar, w.qbarT, w.cg.y, batch, s,
+                                       fwd_part_elems(op, batch) ? scr : nullptr)));
             SCT_TRY((launch_adj<TM, T>(op, w.cg.y, w.qbar, w.aqb, alpha, lambda, sigma, nullptr,
-                                       batch, s)));
+                                       batch, s, adj_scratch_elems(op, batch) ? scr : nullptr)));
         }
     }
     // r_0 = rhs is the first checkpoint's residual (x_0 = 0)

@@ -4,8 +4,8 @@
 // per item split each sum differently, so results move at the rounding level).
 //
 // The optional cache is a text file of lines
-//   sparsect-tune <key> <fwd_waves> <adj_waves> <fwd_rhs> <adj_rhs> <fwd_layout> <fwd_lines>
-// (the last two may be missing: 0) keyed by GPU architecture, geometry, measured-angle set, operator kind,
+//   sparsect-tune <key> <fwd_waves> <adj_waves> <fwd_rhs> <adj_rhs> <fwd_layout> <fwd_lines> <adj_layout>
+// (the last three may be missing: 0) keyed by GPU architecture, geometry, measured-angle set, operator kind,
 // forward bundle width and batch; a later line for a key overrides an earlier
 // one, and lines of other kinds are ignored.
 #include "cg.hpp"
@@ -54,7 +54,7 @@ static bool tune_valid(const Op &op, const radon_tuning &t)
     return (t.fwd_waves == 2 || t.fwd_waves == 4) &&
            (t.adj_waves == 0 || t.adj_waves == 1 || t.adj_waves == 2 || t.adj_waves == 4) &&
            rhs_ok(t.fwd_rhs) && rhs_ok(t.adj_rhs) && (t.fwd_layout == 0 || t.fwd_layout == 1) &&
-           lines_built(op, t.fwd_lines);
+           (t.adj_layout == 0 || t.adj_layout == 1) && t.reserved == 0 && lines_built(op, t.fwd_lines);
 }
 
 // Last valid entry for `key` in the cache file (false if none or no file).
@@ -66,10 +66,11 @@ static bool cache_lookup(const Op &op, const char *path, const std::string &key,
     char line[512], k[320];
     while (fgets(line, sizeof line, f)) {
         radon_tuning c{};
-        const int got = sscanf(line, "sparsect-tune %319s %d %d %d %d %d %d", k, &c.fwd_waves, &c.adj_waves,
-                               &c.fwd_rhs, &c.adj_rhs, &c.fwd_layout, &c.fwd_lines);
-        if (got == 5) c.fwd_layout = c.fwd_lines = 0;
-        if ((got == 5 || got == 7) && key == k && tune_valid(op, c)) {
+        const int got = sscanf(line, "sparsect-tune %319s %d %d %d %d %d %d %d", k, &c.fwd_waves, &c.adj_waves,
+                               &c.fwd_rhs, &c.adj_rhs, &c.fwd_layout, &c.fwd_lines, &c.adj_layout);
+        if (got < 7) c.fwd_layout = c.fwd_lines = 0;
+        if (got < 8) c.adj_layout = 0;
+        if ((got == 5 || got == 7 || got == 8) && key == k && tune_valid(op, c)) {
             *t = c;
             found = true;
         }
@@ -84,8 +85,9 @@ static int cache_append(const char *path, const std::string &key, const radon_tu
     if (!f) return set_error(RADON_EINVAL, "cannot open the tuning cache %s for writing", path);
     // one short line per write: concurrent writers append whole lines
     char line[512];
-    const int len = snprintf(line, sizeof line, "sparsect-tune %s %d %d %d %d %d %d\n", key.c_str(),
-                             t.fwd_waves, t.adj_waves, t.fwd_rhs, t.adj_rhs, t.fwd_layout, t.fwd_lines);
+    const int len = snprintf(line, sizeof line, "sparsect-tune %s %d %d %d %d %d %d %d\n", key.c_str(),
+                             t.fwd_waves, t.adj_waves, t.fwd_rhs, t.adj_rhs, t.fwd_layout, t.fwd_lines,
+                             t.adj_layout);
     const bool ok = fwrite(line, 1, size_t(len), f) == size_t(len);
     fclose(f);
     if (!ok) return set_error(RADON_EINVAL, "cannot write the tuning cache %s", path);
@@ -105,6 +107,9 @@ static int64_t tune_part_elems(const Op &op, int batch)
                 const int64_t e = fwd_scratch_elems(op, bc, bc, layout, lines);
                 m = e > m ? e : m;
             }
+        // the adjoint's pixel-major copy of a chunk
+        const int64_t a = bc >= 4 ? kPixelMajorSlack + int64_t(bc) * op.rows : 0;
+        m = a > m ? a : m;
     }
     return m;
 }
@@ -165,13 +170,13 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
     SCT_HIP(hipEventCreate(&tm.e0));
     SCT_HIP(hipEventCreate(&tm.e1));
     const int reps = 3;
-    best->fwd_layout = best->fwd_lines = 0;   // the search starts from the defaults
+    best->fwd_layout = best->fwd_lines = best->adj_layout = 0;   // the search starts from the defaults
     radon_tuning cur = *best;
     auto fwd = [&](int b) {
         return [&, b]() { return launch_fwd<TM, TV>(op, x, op.need_T ? xT : nullptr, y, b, s, part); };
     };
     auto adj = [&](int b) {
-        return [&, b]() { return launch_adj<TM, TV>(op, y, x, out, 1.0, 1.0, 0.0, nullptr, b, s); };
+        return [&, b]() { return launch_adj<TM, TV>(op, y, x, out, 1.0, 1.0, 0.0, nullptr, b, s, part); };
     };
     // one image: waves per forward bundle, then per adjoint tile
     float bt = 0.f;
@@ -204,7 +209,7 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
     if (batch > 1) {
         auto normal = [&]() {
             SCT_TRY((launch_fwd<TM, TV>(op, x, op.need_T ? xT : nullptr, y, batch, s, part)));
-            return launch_adj<TM, TV>(op, y, x, out, 1.0, 1.0, 0.0, nullptr, batch, s);
+            return launch_adj<TM, TV>(op, y, x, out, 1.0, 1.0, 0.0, nullptr, batch, s, part);
         };
         bool first = true;
         for (int fr : {1, 4, 8, 16}) {
@@ -244,6 +249,23 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
                         best->fwd_lines = lines;
                     }
                 }
+        }
+        cur.fwd_rhs = best->fwd_rhs;
+        cur.fwd_layout = best->fwd_layout;
+        cur.fwd_lines = best->fwd_lines;
+        // the adjoint chunk's staging layout, for each adjoint chunk
+        for (int ar : {4, 8, 16}) {
+            if (ar > batch) continue;
+            op.tune = cur;
+            op.tune.adj_rhs = ar;
+            op.tune.adj_layout = 1;
+            float t = 0.f;
+            SCT_TRY(time_calls(s, tm, reps, normal, &t));
+            if (t < bt) {
+                bt = t;
+                best->adj_rhs = ar;
+                best->adj_layout = 1;
+            }
         }
     }
     return RADON_OK;

@@ -54,7 +54,7 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct._Geom) == 32
     assert ctypes.sizeof(sct.RadonSizes) == 72
     assert ctypes.sizeof(sct.RadonBuffers) == 80
-    assert ctypes.sizeof(sct.Tuning) == 24
+    assert ctypes.sizeof(sct.Tuning) == 32
 
 
 def _build(n, na, nb, dtype=0, measured=None):

@@ -400,13 +400,17 @@ def test_tuning_setter_autotune_and_parity(tmp_path, monkeypatch):
     ref = oracle.OracleOp(n, na, W.n_bins_for(n), mask)
     op = make_op(n, na, W.n_bins_for(n), mask, "mixed")
     assert op.tuning == {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8, "fwd_layout": 0,
-                         "fwd_lines": 0}
+                         "fwd_lines": 0, "adj_layout": 0, "reserved": 0}
     with pytest.raises(sct.SparsectError):
         op.tuning = {"fwd_waves": 3}
     with pytest.raises(sct.SparsectError):
         op.tuning = {"adj_rhs": 5}
     with pytest.raises(sct.SparsectError):
         op.tuning = {"fwd_layout": 2}
+    with pytest.raises(sct.SparsectError):
+        op.tuning = {"adj_layout": -1}
+    with pytest.raises(sct.SparsectError):
+        op.tuning = {"reserved": 1}
     with pytest.raises(sct.SparsectError):
         op.tuning = {"fwd_lines": 32}     # no band sets below 256 pixels
     with pytest.raises(sct.SparsectError):
@@ -415,8 +419,9 @@ def test_tuning_setter_autotune_and_parity(tmp_path, monkeypatch):
     want = [ref.normal(x[b], 1.0, 0.5, 0.1) for b in range(6)]
     for fw in (2, 4):
         for aw in (1, 2, 4):
-            for fr, ar, lay in ((1, 1, 0), (4, 8, 0), (8, 4, 0), (4, 8, 1), (8, 4, 1)):
-                op.tuning = {"fwd_waves": fw, "adj_waves": aw, "fwd_rhs": fr, "adj_rhs": ar, "fwd_layout": lay}
+            for fr, ar, lay in ((1, 1, 0), (4, 8, 0), (8, 4, 0), (4, 8, 1), (8, 4, 1), (4, 16, 1)):
+                op.tuning = {"fwd_waves": fw, "adj_waves": aw, "fwd_rhs": fr, "adj_rhs": ar, "fwd_layout": lay,
+                             "adj_layout": lay}
                 got = host(op.normal(to_dev(x, F64), 1.0, 0.5, 0.1))
                 for b in range(6):
                     assert rel_l2(got[b], want[b]) <= 1e-5, (fw, aw, fr, ar, lay, b)
