@@ -61,8 +61,8 @@ def parse():
                          "one eager group CG(10) and the 32 per-instance CG(10) solves, then exit")
     ap.add_argument("--profile-volume", action="store_true",
                     help="profiler mode for the 64 x 1024^2 volume (FP32 kind): 3 fused normal "
-                         "applies with 4/8-image chunks, 3 with 16-image chunks and 4 single-image "
-                         "applies, then exit")
+                         "applies with 16-image chunks gathering per image, 3 from pixel-major chunk "
+                         "copies and 4 single-image applies, then exit")
     ap.add_argument("--bundle", type=int, default=0,
                     help="forward bundle width for the profiler modes (0: 16)")
     ap.add_argument("--profile-fourier", action="store_true",
@@ -407,18 +407,21 @@ def bench_large(sct, W, torch, dev, vdt, t, verify=True):
 def profile_volume(sct, W, torch, dev, bundle):
     """Kernel sequence of the 64-slice 1024^2 volume (FP32 kind, as the volume
     leg times it) for rocprofv3: the fused normal operator over all 64 slices
-    (4/8-image chunks, then 16-image chunks) and single-slice applies."""
+    with 16-image chunks, first gathering and staging per image, then from
+    pixel-major chunk copies (fwd_layout = adj_layout = 1), then single-slice
+    applies."""
     w = W.WORKLOADS["volume_64x1024_f32"]
     op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=torch.float32,
                      device=dev, tuning="default", bundle=bundle)
     X = torch.randn((w.batch, op.nn), dtype=torch.float32, device=dev)
     O = torch.empty_like(X)
-    for fr, ar in ((4, 8), (16, 16)):
-        op.tuning = {"fwd_rhs": fr, "adj_rhs": ar}
+    for lay in (0, 1):
+        op.tuning = {"fwd_rhs": 16, "adj_rhs": 16, "fwd_layout": lay, "adj_layout": lay, "fwd_lines": 0}
         for _ in range(3):
             op.normal(X, w.alpha, w.lam, out=O)
         torch.cuda.synchronize()
-        print(f"# volume: 3 fused applies, chunks {fr}/{ar}", file=sys.stderr, flush=True)
+        print(f"# volume: 3 fused applies, 16-image chunks, layout {lay}", file=sys.stderr, flush=True)
+    op.tuning = {"fwd_rhs": 1, "adj_rhs": 1, "fwd_layout": 0, "adj_layout": 0}
     for b in range(4):
         op.normal(X[b:b + 1], w.alpha, w.lam, out=O[b:b + 1])
     torch.cuda.synchronize()
