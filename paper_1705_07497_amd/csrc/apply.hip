@@ -371,8 +371,10 @@ const BandSet *band_set_lines(const Op &op, int bc, int lines)
 int64_t fwd_scratch_elems(const Op &op, int bc, int nb, int layout, int lines)
 {
     const BandSet *b = band_set_lines(op, bc, lines);
+    const bool pm = fwd_pixel_major(layout, bc);
     int64_t e = b ? int64_t(b->n_bands) * op.rows * nb : 0;
-    if (fwd_pixel_major(layout, bc)) e += kPixelMajorSlack + int64_t(op.need_T ? 2 : 1) * bc * op.nn;
+    if (b || pm) e += kTicketSlack;
+    if (pm) e += kPixelMajorSlack + int64_t(op.need_T ? 2 : 1) * bc * op.nn;
     return e;
 }
 

@@ -36,9 +36,12 @@ __global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb
 // whose first line lies in lines [band L, (band + 1) L).  Items are ordered
 // band-major on each XCD, so the blocks of an XCD gather from one band of
 // the image (or its transpose) at a time and keep it in that XCD's L2 across
-// all angles.  Each item writes its partial sums to part[image][band][ray].
-// Several images: blockIdx.y selects a chunk of up to BC images that share
-// every matrix load, as in k_fwd.
+// all angles.  The items are handed out in list order through one ticket
+// counter per XCD (entry o belongs to XCD o % 8, block i runs on XCD i % 8):
+// with a static round-robin the blocks of an XCD drift apart over the items
+// and work on several bands at once.  Each item writes its partial sums to
+// part[image][band][ray].  A chunk of up to BC images shares every matrix
+// load, as in k_fwd.
 template <class TM, class TV, int W, int BC, int BW>
 __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict__ fb,
                                                      const int2 *__restrict__ order, int64_t n_order,
@@ -46,12 +49,20 @@ __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict
                                                      const TM *__restrict__ v0, const TM *__restrict__ v1,
                                                      const TV *__restrict__ x, const TV *__restrict__ xT,
                                                      TV *__restrict__ part, int n, int64_t nn,
-                                                     int64_t rows, int n_bands, int lines, int batch)
+                                                     int64_t rows, int n_bands, int lines, int batch,
+                                                     uint32_t *__restrict__ tickets)
 {
-    const int b0 = int(blockIdx.y) * BC;
-    const int nbc = min(BC, batch - b0);
+    const int nbc = min(BC, batch);
     const int64_t stride = int64_t(n_bands) * rows;   // one image's partials
-    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+    __shared__ int64_t next;
+    const int xcd = int(blockIdx.x & 7u);
+    uint32_t *const counter = tickets + xcd * kTicketStride;
+    for (;;) {
+        if (threadIdx.x == 0) next = 8 * int64_t(atomicAdd(counter, 1u)) + xcd;
+        __syncthreads();
+        const int64_t o = next;
+        __syncthreads();   // next is written again only after every wave has read it
+        if (o >= n_order) break;
         const int2 it = order[o];
         if (it.x < 0) continue;        // padding entry (uniform per block)
         const FwdBundle d = fb[it.x];
@@ -59,8 +70,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict
         const int lo = it.y * lines - d.m0, hi = lo + lines;
         const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
         const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
-        fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b0) * nn,
-                                      part + int64_t(b0) * stride + int64_t(it.y) * rows, n, nn,
+        fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, d.horiz ? xT : x, part + int64_t(it.y) * rows, n, nn,
                                       stride, nbc, tq0, tq1);
     }
 }
@@ -95,11 +105,16 @@ template <class TM, class TV, int W, int BC, int BW>
 inline void fwd_band_wbc(const Op &op, const BandSet &bs, const TV *x, const TV *xT, TV *y, TV *part,
                          int batch, hipStream_t s)
 {
-    const int64_t g = bs.n_order < kPersistentBlocks ? bs.n_order : kPersistentBlocks;
+    // a multiple of 8 blocks, so that block i runs on XCD i % 8
+    const int64_t g = bs.n_order < kPersistentBlocks ? (bs.n_order + 7) / 8 * 8 : kPersistentBlocks;
+    uint32_t *tickets = nullptr;
+    TV *unused = nullptr;
+    fwd_scratch_layout(part, int64_t(bs.n_bands) * op.rows * BC, &tickets, &unused);
+    k_ticket_reset<<<1, 64, 0, s>>>(tickets);
     k_fwd_band<TM, TV, W, BC, BW><<<dim3(unsigned(g), 1u), 64 * W, 0, s>>>(
         op.fb, bs.order, bs.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
         static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, bs.n_bands,
-        bs.lines, batch);
+        bs.lines, batch, tickets);
     const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
     k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(batch)), 256, 0, s>>>(
         op.fb, part, y, op.rows, op.n_bins, nbpa, op.bw, bs.n_bands, bs.lines);
@@ -129,14 +144,16 @@ inline void fwd_band_chunks(const Op &op, const BandSet &bs, const TV *x, const 
 
 template <class TM, class TV, int W, int C, int BW>
 inline void fwd_pm_launch(const Op &op, const BandSet *bs, const TV *xp, const TV *xpT, TV *y, TV *part,
-                          int nb, hipStream_t s)
+                          int nb, uint32_t *tickets, hipStream_t s)
 {
     const TM *v0 = static_cast<const TM *>(op.f_v0), *v1 = static_cast<const TM *>(op.f_v1);
     if (bs) {
-        const int64_t g = bs->n_order < kPersistentBlocks ? bs->n_order : kPersistentBlocks;
+        // a multiple of 8 blocks, so that block i runs on XCD i % 8
+        const int64_t g = bs->n_order < kPersistentBlocks ? (bs->n_order + 7) / 8 * 8 : kPersistentBlocks;
+        k_ticket_reset<<<1, 64, 0, s>>>(tickets);
         k_fwd_pm_band<TM, TV, W, C, BW><<<unsigned(g), 64 * W, 0, s>>>(
             op.fb, bs->order, bs->n_order, op.f_idx, v0, v1, xp, xpT, part, op.n, op.rows, bs->n_bands,
-            bs->lines, nb);
+            bs->lines, nb, tickets);
         const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
         k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(nb)), 256, 0, s>>>(
             op.fb, part, y, op.rows, op.n_bins, nbpa, op.bw, bs->n_bands, bs->lines);
@@ -148,25 +165,27 @@ inline void fwd_pm_launch(const Op &op, const BandSet *bs, const TV *xp, const T
 }
 
 // Forward over chunks of C images from pixel-major copies, one chunk after
-// another: part holds the chunk's band partials (when banded), then, 16-byte
-// aligned, its pixel-major copy and (for operators with rays closer to
-// horizontal) the copy in transposed pixel order.
+// another: part holds the chunk's band partials (when banded), then, 256-byte
+// aligned, the ticket counters, its pixel-major copy and (for operators with
+// rays closer to horizontal) the copy in transposed pixel order.
 template <class TM, class TV, int C, int BW>
 inline void fwd_pm_chunks(const Op &op, const BandSet *bs, const TV *x, TV *y, TV *part, int batch,
                           hipStream_t s)
 {
-    const int64_t pe = bs ? int64_t(bs->n_bands) * op.rows * C : 0;
-    const uintptr_t a = (reinterpret_cast<uintptr_t>(part + pe) + 15) & ~uintptr_t(15);
-    TV *xp = reinterpret_cast<TV *>(a);
+    uint32_t *tickets = nullptr;
+    TV *xp = nullptr;
+    fwd_scratch_layout(part, bs ? int64_t(bs->n_bands) * op.rows * C : 0, &tickets, &xp);
     TV *xpT = op.need_T ? xp + int64_t(C) * op.nn : nullptr;
     const unsigned t = unsigned((op.n + 15) / 16);
     for (int c0 = 0; c0 < batch; c0 += C) {
         const int nb = batch - c0 < C ? batch - c0 : C;
         k_pixel_major<TV, C><<<dim3(t, t), 256, 0, s>>>(x + int64_t(c0) * op.nn, xp, xpT, op.n, op.nn, nb);
         if (op.tune.fwd_waves == 2)
-            fwd_pm_launch<TM, TV, 2, C, BW>(op, bs, xp, xpT ? xpT : xp, y + int64_t(c0) * op.rows, part, nb, s);
+            fwd_pm_launch<TM, TV, 2, C, BW>(op, bs, xp, xpT ? xpT : xp, y + int64_t(c0) * op.rows, part, nb,
+                                            tickets, s);
         else
-            fwd_pm_launch<TM, TV, 4, C, BW>(op, bs, xp, xpT ? xpT : xp, y + int64_t(c0) * op.rows, part, nb, s);
+            fwd_pm_launch<TM, TV, 4, C, BW>(op, bs, xp, xpT ? xpT : xp, y + int64_t(c0) * op.rows, part, nb,
+                                            tickets, s);
     }
 }
 

@@ -245,7 +245,10 @@ __global__ __launch_bounds__(64 * W) void k_fwd_pm(const FwdBundle *__restrict__
 }
 
 // Line-banded forward of one pixel-major chunk (as k_fwd_band): partials
-// part[image][band][ray].
+// part[image][band][ray].  The items are handed out in list order through
+// one ticket counter per XCD (entry o belongs to XCD o % 8, block i runs on
+// XCD i % 8): with a static round-robin the blocks of an XCD drift apart
+// over the items and work on several bands at once.
 template <class TM, class TV, int W, int C, int BW>
 __global__ __launch_bounds__(64 * W) void k_fwd_pm_band(const FwdBundle *__restrict__ fb,
                                                         const int2 *__restrict__ order, int64_t n_order,
@@ -255,10 +258,18 @@ __global__ __launch_bounds__(64 * W) void k_fwd_pm_band(const FwdBundle *__restr
                                                         const TV *__restrict__ xp,
                                                         const TV *__restrict__ xpT, TV *__restrict__ part,
                                                         int n, int64_t rows, int n_bands, int lines,
-                                                        int nbc)
+                                                        int nbc, uint32_t *__restrict__ tickets)
 {
     const int64_t stride = int64_t(n_bands) * rows;   // one image's partials
-    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+    __shared__ int64_t next;
+    const int xcd = int(blockIdx.x & 7u);
+    uint32_t *const counter = tickets + xcd * kTicketStride;
+    for (;;) {
+        if (threadIdx.x == 0) next = 8 * int64_t(atomicAdd(counter, 1u)) + xcd;
+        __syncthreads();
+        const int64_t o = next;
+        __syncthreads();   // next is written again only after every wave has read it
+        if (o >= n_order) break;
         const int2 it = order[o];
         if (it.x < 0) continue;        // padding entry (uniform per block)
         const FwdBundle d = fb[it.x];

@@ -229,8 +229,25 @@ const BandSet *band_set_lines(const Op &op, int bc, int lines);
 inline const BandSet *band_set_for(const Op &op, int bc) { return band_set_lines(op, bc, op.tune.fwd_lines); }
 // Whether a forward chunk of bc images gathers from a pixel-major copy.
 inline bool fwd_pixel_major(int layout, int bc) { return layout == 1 && bc >= 4; }
-// Elements of alignment slack before the pixel-major copies in the scratch.
+// Elements of alignment slack before a pixel-major copy in the scratch.
 constexpr int64_t kPixelMajorSlack = 64;
+// Ticket counters of work handed out in list order: one per XCD, each on its
+// own 256-byte line (device-scope atomics on one line serialize at one
+// channel).
+constexpr int kTicketStride = 64;
+constexpr int64_t kTicketBytes = 4 * 8 * kTicketStride;
+// Scratch elements (of 4 bytes or more) that hold the banded forward's ticket
+// counters after its partials, 256-byte aligned.
+constexpr int64_t kTicketSlack = (kTicketBytes + 256) / 4;
+// A forward chunk's scratch: band partials (part_elems), then the ticket
+// counters at the next 256-byte boundary, then the pixel-major copies.
+template <class TV>
+inline void fwd_scratch_layout(TV *part, int64_t part_elems, uint32_t **tickets, TV **xp)
+{
+    const uintptr_t a = (reinterpret_cast<uintptr_t>(part + part_elems) + 255) & ~uintptr_t(255);
+    *tickets = reinterpret_cast<uint32_t *>(a);
+    *xp = reinterpret_cast<TV *>(a + kTicketBytes);
+}
 // out = alpha (MR)^T y + lambda K^T K x + sigma x; partial <x, out> per group
 // into part[batch][n_ag] when part != nullptr.  x may be nullptr when
 // lambda == sigma == 0 and part == nullptr.  With scratch

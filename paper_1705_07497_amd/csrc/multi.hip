@@ -102,15 +102,6 @@ __global__ __launch_bounds__(256) void k_multi_transpose(const T *__restrict__ x
     }
 }
 
-// Ticket counters of the group forward: one per XCD, each on its own
-// 256-byte line (device-scope atomics on one line serialize at one channel).
-constexpr int kTicketStride = 64;
-
-__global__ void k_multi_reset(uint32_t *__restrict__ tickets)
-{
-    if (threadIdx.x < 8) tickets[threadIdx.x * kTicketStride] = 0u;
-}
-
 // Forward products of every instance over the concatenated (instance, bundle)
 // list.  Each instance's segment keeps its XCD-aware order and starts at a
 // multiple of 8; the grid is a multiple of 8, so block i runs on XCD i % 8 and
@@ -476,8 +467,8 @@ template <class TM, class TV>
 static int multi_launch_fwd(const Multi &m, const TV *x, const TV *xT, TV *y, TV *fpart,
                             uint32_t *tickets, hipStream_t s)
 {
-    k_multi_reset<<<1, 64, 0, s>>>(tickets);
-    SCT_TRY(check_launch("k_multi_reset"));
+    k_ticket_reset<<<1, 64, 0, s>>>(tickets);
+    SCT_TRY(check_launch("k_ticket_reset"));
     const unsigned g = unsigned(fwd_grid(m)), bs = 64 * kMultiFwdWaves;
     switch (m.bw) {
     case 64:

@@ -197,6 +197,14 @@ __global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restric
     y[int64_t(b) * rows + ray] = acc;
 }
 
+// Clears the 8 ticket counters (kTicketStride apart) before each launch that
+// uses them: a kernel, not a memset node, so the sequence can be captured in
+// a graph.
+__global__ inline void k_ticket_reset(uint32_t *__restrict__ tickets)
+{
+    if (threadIdx.x < 8) tickets[threadIdx.x * kTicketStride] = 0u;
+}
+
 // (K^T K x)_j, the Neumann 5-point Laplacian.  The four neighbours load
 // unconditionally, so their latencies overlap: a neighbour missing at the
 // image edge reads x_j itself, whose difference is exactly zero.
