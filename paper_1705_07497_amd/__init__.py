@@ -431,6 +431,17 @@ class RadonOp:
             raise SparsectError("layout must be LAYOUT_IMAGE (0) or LAYOUT_PIXEL (1)")
         return which | (WS_PIXEL_LAYOUT if layout == LAYOUT_PIXEL else 0)
 
+    @staticmethod
+    def _check_shape(t, count: int, layout: int, name: str) -> None:
+        """A 2-D tensor of several vectors must be [batch, count] image-major and
+        [count, batch] pixel-major (the memory alone cannot tell them apart)."""
+        if t is None or t.dim() != 2 or t.numel() == count:
+            return
+        want = 0 if layout == LAYOUT_PIXEL else 1
+        if t.shape[want] != count:
+            lay = "pixel-major [count, batch]" if layout == LAYOUT_PIXEL else "image-major [batch, count]"
+            raise SparsectError(f"{name} has shape {tuple(t.shape)}, not {lay} with count {count}")
+
     def _new(self, b: int, count: int, layout: int):
         """An output of b vectors of count elements in the given layout."""
         shape = (count, b) if layout == LAYOUT_PIXEL else (b, count)
@@ -442,6 +453,8 @@ class RadonOp:
         b = self._img(x)
         y = self._new(b, self.rows, layout) if out is None else out
         self._sino_n(y, b, "out")
+        self._check_shape(x, self.nn, layout, "x")
+        self._check_shape(y, self.rows, layout, "out")
         ws, nb = self.workspace(self._ws_kind(WS_FWD, layout), b)
         _check(lib().radon_fwd(self._h, self._p(x), self._p(y), b, layout, self._p(ws), nb,
                                self._stream()))
@@ -463,6 +476,8 @@ class RadonOp:
         b = self._sino(y)
         x = self._new(b, self.nn, layout) if out is None else out
         self._img_n(x, b, "out")
+        self._check_shape(y, self.rows, layout, "y")
+        self._check_shape(x, self.nn, layout, "out")
         ws, nb = self.workspace(self._ws_kind(WS_ADJ, layout), b)
         _check(lib().radon_adj(self._h, self._p(y), self._p(x), b, layout, self._p(ws) if nb else None,
                                nb, self._stream()))
@@ -476,6 +491,8 @@ class RadonOp:
         o = self._new(b, self.nn, layout) if out is None else out
         self._img_n(o, b, "out")
         d = torch.empty(b, dtype=torch.float64, device=self.device) if dot else None
+        self._check_shape(x, self.nn, layout, "x")
+        self._check_shape(o, self.nn, layout, "out")
         ws, nb = self.workspace(self._ws_kind(WS_NORMAL, layout), b)
         _check(lib().normal_apply(self._h, float(alpha), float(lam), float(sigma), self._p(x),
                                   self._p(o), self._p(d), b, layout, self._p(ws), nb, self._stream()))
@@ -508,6 +525,8 @@ class RadonOp:
         else:
             x = self._new(b, self.nn, layout) if out is None else out
         info = torch.zeros(b * ctypes.sizeof(CgInfo), dtype=torch.uint8, device=self.device)
+        self._check_shape(rhs, self.nn, layout, "rhs")
+        self._check_shape(x, self.nn, layout, "x")
         ws, nb = self.workspace(self._ws_kind(WS_CG, layout), b)
         _check(lib().cg_solve(self._h, float(alpha), float(lam), float(sigma), self._p(rhs),
                               self._p(x), int(x0 is not None), b, layout, int(n_iter), float(rtol),
@@ -542,6 +561,8 @@ class RadonOp:
         P = SbParams(float(alpha), float(lam), float(tol), int(n_outer), int(n_cg), flags, 0)
         info = torch.zeros(b * ctypes.sizeof(SbInfo), dtype=torch.uint8, device=self.device)
         if surrogate is None:
+            self._check_shape(f, self.rows, layout, "f")
+            self._check_shape(mu, self.nn, layout, "mu")
             ws, nb = self.workspace(self._ws_kind(WS_SB, layout), b, key=(ws_key, b))
             _check(lib().split_bregman_tv(self._h, ctypes.byref(P), self._p(f), self._p(mu), b, layout,
                                           self._p(ws), nb, self._p(info), self._stream()))

@@ -103,3 +103,20 @@ def test_autograd_gradients_keep_the_input_shape():
                                     (x.detach().clone().requires_grad_(True),))
     assert torch.autograd.gradcheck(lambda t: AG.RadonFwd.apply(op, t),
                                     (x.detach().clone().requires_grad_(True),))
+
+
+@pytest.mark.parametrize("call", [
+    lambda op: op.fwd(imgs(3, op), layout=sct.LAYOUT_PIXEL),
+    lambda op: op.fwd(imgs(3, op).t().contiguous(), layout=sct.LAYOUT_IMAGE),
+    lambda op: op.adj(sinos(3, op), layout=sct.LAYOUT_PIXEL),
+    lambda op: op.normal(imgs(3, op), 1.0, 1.0, layout=sct.LAYOUT_PIXEL),
+    lambda op: op.cg(imgs(3, op), 1.0, 1.0, layout=sct.LAYOUT_PIXEL),
+    lambda op: op.sb(sinos(3, op), 1.0, 1.0, 1, 1, layout=sct.LAYOUT_PIXEL),
+    lambda op: op.fwd(imgs(3, op), layout=2),
+])
+def test_layout_and_tensor_shape_must_agree(call):
+    """A 2-D tensor of several vectors is [batch, count] image-major and
+    [count, batch] pixel-major; a contradiction is refused before any launch."""
+    op = stub_op()
+    with pytest.raises(sct.SparsectError, match="shape|layout"):
+        call(op)
