@@ -53,9 +53,9 @@ def parse():
                     help="oracle normal applies to time (0: sized to ~15 s)")
     ap.add_argument("--no-batched", action="store_true", help="skip the fused multi-image legs")
     ap.add_argument("--profile", action="store_true",
-                    help="profiler mode: 100 forward kernels, 100 adj, 20 normal applies, one CG(20) "
-                         "solve and the stream copy / read kernels over 1 GiB (counter "
-                         "calibration), then exit")
+                    help="profiler mode: 100 forward kernels at each bundle width (16, 32, 64), 100 "
+                         "adj, 20 normal applies, one CG(20) solve and the stream copy / read kernels "
+                         "over 1 GiB (counter calibration), then exit")
     ap.add_argument("--profile-multi", action="store_true",
                     help="profiler mode for the uneven 32-instance batch: one captured-graph CG(10), "
                          "one eager group CG(10) and the 32 per-instance CG(10) solves, then exit")
@@ -74,10 +74,11 @@ def parse():
 PROFILE = os.path.join(ROOT, "profiles", "k_fwd_k_adj1_512x512_180angles.md")
 
 
-def traffic_from_profile(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter record
-    (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or None
-    when the record is missing or the kernel's sources changed since."""
+def traffic_from_profile(kernel, bundle=None):
+    """HBM bytes per launch of `kernel` (the forward: of the given bundle
+    width) from the committed counter record (FETCH_SIZE and WRITE_SIZE
+    scaled by the copy-kernel calibration), or None when the record is
+    missing or the kernel's sources changed since."""
     import hashlib
     try:
         text = open(PROFILE).read()
@@ -87,6 +88,8 @@ def traffic_from_profile(kernel):
         if not line.startswith("traffic-record ") or f"kernel={kernel} " not in line:
             continue
         kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+        if bundle is not None and kv.get("bundle") != str(bundle):
+            continue
         h = hashlib.sha256()
         for f in kv["sources"].split(","):
             h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -532,8 +535,16 @@ def main():
         print("# profile sequence done (mixed batch)", file=sys.stderr, flush=True)
         return
     if args.profile:
-        for _ in range(100):
-            op.fwd_xt(x, xT, out=ysb)
+        # the forward kernel of each bundle width (the benchmark times the
+        # width choose_bundle picks), then the adjoint, the normal operator and CG
+        for bw in (16, 32, 64):
+            op_b = op if bw == op.bundle else sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask,
+                                                           dtype=torch.float32, vec_dtype=vdt,
+                                                           device=dev, tuning="default", bundle=bw)
+            for _ in range(100):
+                op_b.fwd_xt(x, xT, out=ysb)
+            torch.cuda.synchronize()
+            del op_b
         for _ in range(100):
             op.adj(ysb, out=out)
         for _ in range(20):
@@ -616,7 +627,7 @@ def main():
     achieved = kbytes / kavg / 1e9
     normal_bytes = bytes_fwd + bytes_adj
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(kname),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(kname, op.bundle if kname == "k_fwd" else None),
                 "kernel": kname, "avg_us": round(kavg * 1e6, 2), "algorithmic_bytes": kbytes,
                 "ceiling_gbs": ceiling["read_gbs"],
                 "frac_of_ceiling": round(achieved / ceiling["read_gbs"], 4), "ceiling": ceiling}

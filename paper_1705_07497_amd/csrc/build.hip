@@ -537,9 +537,20 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
     // XCDs round-robin by block index; bundles of vertical-class rays (gathering
     // from x) go to one set of XCDs and horizontal-class ones (gathering from
     // the transposed image) to the other, in proportion to their counts.
+    // Within each class the bundles go longest first: block i takes entries
+    // i, i + G, ... of the list, so every block gets one of the longest
+    // bundles of its class, then one of the next longest, and so on, and no
+    // block is left at the end with several long bundles while the others
+    // idle (in bundle order the busiest of the 2048 blocks of the
+    // 512 x 512 / 180-angle operator had about 1.45x the mean work, longest
+    // first 1.19x; the forward went from 96.9 to 93.8 us at 16 rays per
+    // bundle and to 89.5 us at 64).
     std::vector<int32_t> V, H;
     for (int64_t b = 0; b < op.n_fb; ++b)   // empty bundles too: they write zeros
         (hb[size_t(b)].horiz ? H : V).push_back(int32_t(b));
+    const auto longer = [&](int32_t a, int32_t c) { return hb[size_t(a)].nrows > hb[size_t(c)].nrows; };
+    std::stable_sort(V.begin(), V.end(), longer);
+    std::stable_sort(H.begin(), H.end(), longer);
     const int nx = 8;
     int kv = nx;
     if (!V.empty() && !H.empty()) {
