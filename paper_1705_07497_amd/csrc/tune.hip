@@ -169,7 +169,10 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
     Timer tm;
     SCT_HIP(hipEventCreate(&tm.e0));
     SCT_HIP(hipEventCreate(&tm.e1));
-    const int reps = 3;
+    // single-image products take tens of microseconds: 20 calls per candidate
+    // keep the ranking above the run-to-run noise; fused products take
+    // milliseconds, and 3 calls do
+    const int reps1 = 20, reps = 3;
     best->fwd_layout = best->fwd_lines = best->adj_layout = 0;   // the search starts from the defaults
     radon_tuning cur = *best;
     auto fwd = [&](int b) {
@@ -184,7 +187,7 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
         op.tune = cur;
         op.tune.fwd_waves = w;
         float t = 0.f;
-        SCT_TRY(time_calls(s, tm, reps, fwd(1), &t));
+        SCT_TRY(time_calls(s, tm, reps1, fwd(1), &t));
         if (w == 2 || t < bt) {
             bt = t;
             best->fwd_waves = w;
@@ -195,7 +198,7 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
         op.tune = cur;
         op.tune.adj_waves = w;
         float t = 0.f;
-        SCT_TRY(time_calls(s, tm, reps, adj(1), &t));
+        SCT_TRY(time_calls(s, tm, reps1, adj(1), &t));
         if (w == 1 || t < bt) {
             bt = t;
             best->adj_waves = w;
