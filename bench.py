@@ -385,16 +385,22 @@ def bench_large(sct, W, torch, dev, vdt, t, verify=True):
              "normal_apply_gbs": round(bytes_normal / t_normal / 1e9, 1),
              "sb_ms": round(t_sb * 1e3, 1), "sb_applies": w.n_outer * w.n_cg,
              "recon_per_s": round(1.0 / t_sb, 3), "rel_err_to_phantom": round(err, 4)}
-    ug = u.double().cpu().numpy().reshape(-1)
-    fr = f.double().cpu().numpy().reshape(-1)
-    del op
-    torch.cuda.empty_cache()
     if verify:
-        # the same reconstruction by the FP64 oracle from the same data (30
-        # outer iterations run as three resumed runs of 10, bitwise one run)
+        # the reconstruction checked against the FP64 oracle, from data the
+        # oracle makes itself (its own forward of the phantom plus the same
+        # noise draw: no oracle input comes from the GPU); 30 outer iterations
+        # run as three resumed runs of 10, bitwise one run
         import oracle
         t0 = time.perf_counter()
         ref = oracle.OracleOp(w.n, w.n_angles, w.n_bins, w.mask)
+        y_ref = ref.fwd(mu_np)
+        fr = y_ref + w.noise * np.sqrt(np.mean(y_ref ** 2)) * eps_np
+        u_chk, _ = op.sb(torch.as_tensor(fr, dtype=vdt, device=dev).reshape(1, -1), w.alpha, w.lam,
+                         w.n_outer, w.n_cg)
+        ug = u_chk.double().cpu().numpy().reshape(-1)
+    del op
+    torch.cuda.empty_cache()
+    if verify:
         uo, st = None, None
         for _ in range(w.n_outer // 10):
             uo, _, _, _, st = ref.sb(fr, w.alpha, w.lam, 10, w.n_cg, u0=uo, state=st)
@@ -680,12 +686,11 @@ def main():
 
     if not args.no_verify or not args.no_cpu:
         import oracle
-        fr = f.double().cpu().numpy().reshape(-1)
         t0 = time.perf_counter()
         ref = oracle.OracleOp(w.n, w.n_angles, w.n_bins, w.mask)
         oracle_build_s = time.perf_counter() - t0
         if not args.no_cpu:
-            xr = x.double().cpu().numpy().reshape(-1)
+            xr = np.random.default_rng(0).standard_normal(op.nn)
             ref.normal(xr, w.alpha, w.lam)
             t0 = time.perf_counter()
             ref.normal(xr, w.alpha, w.lam)
@@ -721,9 +726,17 @@ def main():
                 "sample": f"{reps1} FP64 normal applies of the same operator ({tc1:.1f} s)"}
             print(f"# cpu oracle: {reps1 / tc1:.2f} applies/s on 1 thread", file=sys.stderr, flush=True)
         if not args.no_verify:
+            # the reconstruction checked against the FP64 oracle, from data
+            # the oracle makes itself (its own forward of the phantom plus the
+            # same noise draw: no oracle input comes from the GPU), solved once
+            # more by the timed operator
             t0 = time.perf_counter()
-            uo = ref.sb(fr, w.alpha, w.lam, w.n_outer, w.n_cg)[0]
-            ug = u.double().cpu().numpy().reshape(-1)
+            y_ref = ref.fwd(mu_np)
+            f_ref = y_ref + w.noise * np.sqrt(np.mean(y_ref ** 2)) * eps_np
+            uo = ref.sb(f_ref, w.alpha, w.lam, w.n_outer, w.n_cg)[0]
+            u_chk, _ = op.sb(torch.as_tensor(f_ref, dtype=vdt, device=dev).reshape(1, -1), w.alpha, w.lam,
+                             w.n_outer, w.n_cg)
+            ug = u_chk.double().cpu().numpy().reshape(-1)
             err = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
             result["sb_rel_l2_vs_oracle"] = err
             result["oracle_sb_s"] = round(time.perf_counter() - t0, 2)
