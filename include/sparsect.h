@@ -459,6 +459,21 @@ typedef struct radon_graph radon_graph;   /* opaque captured-graph handle */
  */
 int radon_multi_create(const radon_op *const *ops, int32_t count, const double *alpha,
                        const double *lambda, const double *sigma, radon_multi **out);
+
+/*
+ * The group with its device tables in caller storage: radon_multi_table_bytes
+ * reports the bytes of the group's tables (instance descriptors, the
+ * concatenated forward work list, instance start tables; synchronous, it
+ * reads the operators' work orders), and radon_multi_create_into builds the
+ * group as radon_multi_create does, into `tables` (device, 256-byte aligned,
+ * at least that many bytes, owned by the caller and kept alive and untouched
+ * while the group lives).  The handle then owns no device memory.
+ * Errors: as radon_multi_create; RADON_EWORKSPACE for too few bytes.
+ */
+int radon_multi_table_bytes(const radon_op *const *ops, int32_t count, int64_t *bytes);
+int radon_multi_create_into(const radon_op *const *ops, int32_t count, const double *alpha,
+                            const double *lambda, const double *sigma, void *tables,
+                            int64_t tables_bytes, radon_multi **out);
 void radon_multi_destroy(radon_multi *m);
 
 /*

@@ -149,6 +149,10 @@ SIGNATURES = {
                                    _vp, ctypes.c_int64, _vp]),
     "radon_multi_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, _vp,
                                           ctypes.POINTER(_vp)]),
+    "radon_multi_table_bytes": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int64)]),
+    "radon_multi_create_into": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, _vp, _vp,
+                                               ctypes.c_int64, ctypes.POINTER(_vp)]),
     "radon_multi_destroy": (None, [_vp]),
     "radon_multi_info": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
@@ -833,9 +837,11 @@ class RadonMulti:
     kind) whose products and CG solves run as one launch per phase.  Weights
     alpha, lam, sigma (scalars or one per instance) fix each instance's normal
     operator.  Vectors are packed: instance i's image is
-    packed[img_off[i] : img_off[i] + n_i**2]."""
+    packed[img_off[i] : img_off[i] + n_i**2].  storage="torch" keeps the
+    group's device tables in a torch tensor (radon_multi_create_into), so the
+    library allocates nothing for it."""
 
-    def __init__(self, ops, alpha=1.0, lam=0.0, sigma=0.0):
+    def __init__(self, ops, alpha=1.0, lam=0.0, sigma=0.0, storage: str = "library"):
         torch = _torch()
         self.ops = list(ops)   # keeps the operators alive as long as the group
         k = len(self.ops)
@@ -847,13 +853,27 @@ class RadonMulti:
             a = np.broadcast_to(np.asarray(v, dtype=np.float64), (k,)).copy()
             return a
 
+        if storage not in ("library", "torch"):
+            raise SparsectError("storage must be 'library' or 'torch'")
         self.alpha, self.lam, self.sigma = arr(alpha), arr(lam), arr(sigma)
         handles = (_vp * k)(*[o._h for o in self.ops])
         h = _vp()
+        self._tables = None
         with torch.cuda.device(self.device):
-            _check(lib().radon_multi_create(handles, k, self.alpha.ctypes.data_as(_vp),
-                                            self.lam.ctypes.data_as(_vp),
-                                            self.sigma.ctypes.data_as(_vp), ctypes.byref(h)))
+            if storage == "library":
+                _check(lib().radon_multi_create(handles, k, self.alpha.ctypes.data_as(_vp),
+                                                self.lam.ctypes.data_as(_vp),
+                                                self.sigma.ctypes.data_as(_vp), ctypes.byref(h)))
+            else:
+                nb = ctypes.c_int64()
+                _check(lib().radon_multi_table_bytes(handles, k, ctypes.byref(nb)))
+                # 256-byte aligned: torch's caching allocator hands out 512-byte aligned blocks
+                self._tables = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=self.device)
+                _check(lib().radon_multi_create_into(handles, k, self.alpha.ctypes.data_as(_vp),
+                                                     self.lam.ctypes.data_as(_vp),
+                                                     self.sigma.ctypes.data_as(_vp),
+                                                     _vp(self._tables.data_ptr()), int(nb.value),
+                                                     ctypes.byref(h)))
         self._h = h
         self.img_off = np.zeros(k + 1, dtype=np.int64)
         self.sino_off = np.zeros(k + 1, dtype=np.int64)

@@ -612,15 +612,64 @@ static int multi_alloc(Multi &m, void **p, int64_t bytes)
     return RADON_OK;
 }
 
-static int build_multi(Multi &m, const radon_op *const *ops, int count, const double *alpha,
-                       const double *lambda, const double *sigma)
+// Host side of a group: instance descriptors, the concatenated forward work
+// list and the instance start tables, before they go to the device.
+struct MultiPlan {
+    std::vector<MultiInst> hi;
+    std::vector<int64_t> grp, t32, vbs;
+    std::vector<int2> work;
+};
+
+// Bytes of the group's device tables, 256-byte aligned one after another.
+static int64_t multi_table_bytes(const Multi &m)
+{
+    Carver c(nullptr);
+    c.take<MultiInst>(m.count);
+    c.take<int2>(m.n_fwork);
+    for (int k = 0; k < 3; ++k) c.take<int64_t>(int64_t(m.count) + 1);
+    return c.used;
+}
+
+// The tables into `tables` (caller storage of multi_table_bytes(m) bytes), or
+// into allocations the handle owns when tables is NULL.
+static int place_multi(Multi &m, const MultiPlan &pl, void *tables)
+{
+    if (tables) {
+        Carver c(tables);
+        m.inst = c.take<MultiInst>(m.count);
+        m.fwork = c.take<int2>(m.n_fwork);
+        m.grp_start = c.take<int64_t>(int64_t(m.count) + 1);
+        m.t32_start = c.take<int64_t>(int64_t(m.count) + 1);
+        m.vb_start = c.take<int64_t>(int64_t(m.count) + 1);
+    } else {
+        SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.inst), int64_t(sizeof(MultiInst)) * m.count));
+        SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.fwork), int64_t(sizeof(int2)) * m.n_fwork));
+        SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.grp_start), 8 * (int64_t(m.count) + 1)));
+        SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.t32_start), 8 * (int64_t(m.count) + 1)));
+        SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.vb_start), 8 * (int64_t(m.count) + 1)));
+    }
+    SCT_HIP(hipMemcpy(m.inst, pl.hi.data(), sizeof(MultiInst) * pl.hi.size(), hipMemcpyHostToDevice));
+    SCT_HIP(hipMemcpy(m.fwork, pl.work.data(), sizeof(int2) * pl.work.size(), hipMemcpyHostToDevice));
+    SCT_HIP(hipMemcpy(m.grp_start, pl.grp.data(), 8 * pl.grp.size(), hipMemcpyHostToDevice));
+    SCT_HIP(hipMemcpy(m.t32_start, pl.t32.data(), 8 * pl.t32.size(), hipMemcpyHostToDevice));
+    SCT_HIP(hipMemcpy(m.vb_start, pl.vbs.data(), 8 * pl.vbs.size(), hipMemcpyHostToDevice));
+    return RADON_OK;
+}
+
+static int plan_multi(Multi &m, const radon_op *const *ops, int count, const double *alpha,
+                      const double *lambda, const double *sigma, MultiPlan &pl)
 {
     m.count = count;
     m.dtype = as_op(ops[0])->dtype;
     m.vsize = as_op(ops[0])->vsize;
-    std::vector<MultiInst> hi(static_cast<size_t>(count));
-    std::vector<int64_t> grp(size_t(count) + 1), t32(size_t(count) + 1), vbs(size_t(count) + 1);
-    std::vector<int2> work;
+    std::vector<MultiInst> &hi = pl.hi;
+    std::vector<int64_t> &grp = pl.grp, &t32 = pl.t32, &vbs = pl.vbs;
+    std::vector<int2> &work = pl.work;
+    hi.assign(static_cast<size_t>(count), MultiInst{});
+    grp.assign(size_t(count) + 1, 0);
+    t32.assign(size_t(count) + 1, 0);
+    vbs.assign(size_t(count) + 1, 0);
+    work.clear();
     m.img_off.assign(size_t(count) + 1, 0);
     m.sino_off.assign(size_t(count) + 1, 0);
     m.part_off.assign(size_t(count), -1);
@@ -691,16 +740,6 @@ static int build_multi(Multi &m, const radon_op *const *ops, int count, const do
         return set_error(RADON_EUNSUPPORTED, "too many vector tiles in one group");
     // the single-operator rule applied to the mean measured-angle count
     m.adj_w = adj_waves_for(int(meas_sum / count));
-    SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.inst), int64_t(sizeof(MultiInst)) * count));
-    SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.fwork), int64_t(sizeof(int2)) * m.n_fwork));
-    SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.grp_start), 8 * (int64_t(count) + 1)));
-    SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.t32_start), 8 * (int64_t(count) + 1)));
-    SCT_TRY(multi_alloc(m, reinterpret_cast<void **>(&m.vb_start), 8 * (int64_t(count) + 1)));
-    SCT_HIP(hipMemcpy(m.inst, hi.data(), sizeof(MultiInst) * size_t(count), hipMemcpyHostToDevice));
-    SCT_HIP(hipMemcpy(m.fwork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice));
-    SCT_HIP(hipMemcpy(m.grp_start, grp.data(), 8 * grp.size(), hipMemcpyHostToDevice));
-    SCT_HIP(hipMemcpy(m.t32_start, t32.data(), 8 * t32.size(), hipMemcpyHostToDevice));
-    SCT_HIP(hipMemcpy(m.vb_start, vbs.data(), 8 * vbs.size(), hipMemcpyHostToDevice));
     return RADON_OK;
 }
 
@@ -716,12 +755,8 @@ inline const Multi *as_multi(const radon_multi *p) { return reinterpret_cast<con
 
 using namespace sct;
 
-extern "C" int radon_multi_create(const radon_op *const *ops, int32_t count, const double *alpha,
-                                  const double *lambda, const double *sigma, radon_multi **out)
+static int check_group_ops(const radon_op *const *ops, int32_t count)
 {
-    clear_error();
-    if (!out) return set_error(RADON_EINVAL, "out is NULL");
-    *out = nullptr;
     if (!ops) return set_error(RADON_EINVAL, "ops is NULL");
     if (count < 1 || count > 65535) return set_error(RADON_EINVAL, "count must be in [1, 65535] (got %d)", count);
     for (int i = 0; i < count; ++i) {
@@ -731,16 +766,66 @@ extern "C" int radon_multi_create(const radon_op *const *ops, int32_t count, con
         if (as_op(ops[i])->bw != as_op(ops[0])->bw)
             return set_error(RADON_EINVAL, "operator %d has another forward bundle width than operator 0", i);
     }
+    return RADON_OK;
+}
+
+// Plans the group and places its tables (into `tables` when given).
+static int create_group(const radon_op *const *ops, int32_t count, const double *alpha,
+                        const double *lambda, const double *sigma, void *tables, int64_t tables_bytes,
+                        radon_multi **out)
+{
     Multi *m = new (std::nothrow) Multi;
     if (!m) return set_error(RADON_EINVAL, "out of host memory");
     m->bw = as_op(ops[0])->bw;
-    const int rc = build_multi(*m, ops, count, alpha, lambda, sigma);
+    MultiPlan pl;
+    int rc = plan_multi(*m, ops, count, alpha, lambda, sigma, pl);
+    if (rc == RADON_OK && tables && tables_bytes < multi_table_bytes(*m))
+        rc = set_error(RADON_EWORKSPACE, "the tables need %lld bytes, %lld given",
+                       (long long)multi_table_bytes(*m), (long long)tables_bytes);
+    if (rc == RADON_OK) rc = place_multi(*m, pl, tables);
     if (rc != RADON_OK) {
         free_multi(m);
         return rc;
     }
     *out = reinterpret_cast<radon_multi *>(m);
     return RADON_OK;
+}
+
+extern "C" int radon_multi_create(const radon_op *const *ops, int32_t count, const double *alpha,
+                                  const double *lambda, const double *sigma, radon_multi **out)
+{
+    clear_error();
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    *out = nullptr;
+    SCT_TRY(check_group_ops(ops, count));
+    return create_group(ops, count, alpha, lambda, sigma, nullptr, 0, out);
+}
+
+extern "C" int radon_multi_table_bytes(const radon_op *const *ops, int32_t count, int64_t *bytes)
+{
+    clear_error();
+    if (!bytes) return set_error(RADON_EINVAL, "bytes is NULL");
+    *bytes = 0;
+    SCT_TRY(check_group_ops(ops, count));
+    Multi m;
+    m.bw = as_op(ops[0])->bw;
+    MultiPlan pl;
+    SCT_TRY(plan_multi(m, ops, count, nullptr, nullptr, nullptr, pl));
+    *bytes = multi_table_bytes(m);
+    return RADON_OK;
+}
+
+extern "C" int radon_multi_create_into(const radon_op *const *ops, int32_t count, const double *alpha,
+                                       const double *lambda, const double *sigma, void *tables,
+                                       int64_t tables_bytes, radon_multi **out)
+{
+    clear_error();
+    if (!out) return set_error(RADON_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!tables) return set_error(RADON_EINVAL, "tables is NULL");
+    if (reinterpret_cast<uintptr_t>(tables) & 255) return set_error(RADON_EINVAL, "tables must be 256-byte aligned");
+    SCT_TRY(check_group_ops(ops, count));
+    return create_group(ops, count, alpha, lambda, sigma, tables, tables_bytes, out);
 }
 
 extern "C" void radon_multi_destroy(radon_multi *p) { free_multi(reinterpret_cast<Multi *>(p)); }

@@ -172,3 +172,36 @@ def test_uneven_batch_full_size():
         ref = _oracle(specs[i], "mixed")
         xo = ref.cg(alpha, lam, 0.0, rhs=host(rhs[i]), n_iter=10)[0]
         assert rel_l2(host(g.image(X, i)), xo) <= 1e-7
+
+
+def test_group_tables_in_caller_storage():
+    """radon_multi_create_into: the group's device tables in a torch tensor
+    (the library allocates nothing) give bitwise the products and the CG of
+    the self-allocating group; too small or misaligned storage is refused."""
+    need_gpu()
+    import ctypes
+    ops = [sct.RadonOp(n, na, nb, W.angle_mask(na, ev), dtype=torch.float32, vec_dtype=torch.float64,
+                       tuning="default") for n, na, nb, ev in SMALL_GROUP]
+    g_lib = sct.RadonMulti(ops, 1.5, 0.5, 0.25)
+    g_torch = sct.RadonMulti(ops, 1.5, 0.5, 0.25, storage="torch")
+    assert g_torch._tables is not None and g_lib._tables is None
+    rng = np.random.default_rng(7)
+    X = g_lib.pack_images([to_dev(rng.standard_normal(o.nn), torch.float64) for o in ops])
+    for which in (0, 2):
+        assert torch.equal(g_torch.apply(which, X), g_lib.apply(which, X)), which
+    x1, i1 = g_lib.cg(X, n_iter=6)
+    x2, i2 = g_torch.cg(X, n_iter=6)
+    assert torch.equal(x1, x2) and torch.equal(i1, i2)
+    L = sct.lib()
+    k = len(ops)
+    handles = (sct._vp * k)(*[o._h for o in ops])
+    nb = ctypes.c_int64()
+    assert L.radon_multi_table_bytes(handles, k, ctypes.byref(nb)) == 0 and nb.value > 0
+    buf = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device="cuda")
+    h = sct._vp()
+    rc = L.radon_multi_create_into(handles, k, None, None, None, sct._vp(buf.data_ptr()), nb.value - 1,
+                                   ctypes.byref(h))
+    assert rc == -4 and not h.value
+    rc = L.radon_multi_create_into(handles, k, None, None, None, sct._vp(buf.data_ptr() + 16), nb.value,
+                                   ctypes.byref(h))
+    assert rc == -1 and "aligned" in L.radon_last_error().decode()
