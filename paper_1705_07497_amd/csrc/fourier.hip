@@ -405,9 +405,10 @@ __global__ __launch_bounds__(256) void k_fou_interp(const C2<T> *__restrict__ G,
 }
 
 // G[s] = sum_p g_p(s) fhat_p (the spreading B, CSR over grid points): 16
-// lanes per grid point, the grid points visited longest row first (rows near
-// the origin hold over a thousand entries, the median about 16), so the long
-// rows do not form the tail of the launch.
+// lanes per grid point; each workgroup takes a run of 16 neighbouring grid
+// points, the runs in order of their longest row (rows near the origin hold
+// over a thousand entries, the median about 16), so the long rows do not
+// form the tail of the launch.
 template <class TM, class T>
 __global__ __launch_bounds__(256) void k_fou_spread(const C2<T> *__restrict__ fhat,
                                                     const int64_t *__restrict__ sp_ptr,
@@ -777,16 +778,24 @@ static int build_fou(Fou &f, hipStream_t st)
                     sp_w[size_t(k)] = TM(w1d[size_t(p * 2 * W + ky)] * w1d[size_t(p * 2 * W + W + kx)]);
                 }
     }
-    // grid points by descending row length (ties by index), for the spreading
+    // grid points for the spreading: runs of 16 consecutive grid points (one
+    // workgroup of k_fou_spread), the runs by descending longest row (ties by
+    // index), each run in grid order.  Long runs do not form the tail of the
+    // launch, and the rows of one workgroup are neighbours, whose entries lie
+    // next to each other in sp_pt and sp_w, so no cache line of them is read
+    // twice (with the rows one by one by length, a workgroup's 16 rows came
+    // from all over the grid).
     std::vector<int32_t> sp_order(static_cast<size_t>(MM));
     {
-        int64_t maxlen = 0;
-        for (int64_t c = 0; c < MM; ++c) maxlen = std::max(maxlen, sp_ptr[size_t(c + 1)] - sp_ptr[size_t(c)]);
-        std::vector<int64_t> start(size_t(maxlen + 2), 0);
-        for (int64_t c = 0; c < MM; ++c) ++start[size_t(maxlen - (sp_ptr[size_t(c + 1)] - sp_ptr[size_t(c)]) + 1)];
-        for (int64_t l = 0; l <= maxlen; ++l) start[size_t(l + 1)] += start[size_t(l)];
+        const int64_t runs = MM / 16;   // M is a power of two >= 16
+        std::vector<int64_t> len(static_cast<size_t>(runs), 0);
         for (int64_t c = 0; c < MM; ++c)
-            sp_order[size_t(start[size_t(maxlen - (sp_ptr[size_t(c + 1)] - sp_ptr[size_t(c)]))]++)] = int32_t(c);
+            len[size_t(c / 16)] = std::max(len[size_t(c / 16)], sp_ptr[size_t(c + 1)] - sp_ptr[size_t(c)]);
+        std::vector<int64_t> run(static_cast<size_t>(runs));
+        for (int64_t r = 0; r < runs; ++r) run[size_t(r)] = r;
+        std::stable_sort(run.begin(), run.end(), [&](int64_t a, int64_t c) { return len[size_t(a)] > len[size_t(c)]; });
+        for (int64_t i = 0; i < runs; ++i)
+            for (int k = 0; k < 16; ++k) sp_order[size_t(i * 16 + k)] = int32_t(run[size_t(i)] * 16 + k);
     }
     // 8 x 8 tiles that some window reaches
     const int tpr = M / 8;
