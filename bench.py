@@ -72,13 +72,16 @@ def parse():
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_fwd_k_adj1_512x512_180angles.md")
+# forward bundle layouts (rays, angles per bundle) of the --profile sequence, in launch order
+PROFILE_LAYOUTS = ((16, 1), (32, 1), (64, 1), (32, 2), (64, 2), (64, 4))
 
 
-def traffic_from_profile(kernel, bundle=None):
+def traffic_from_profile(kernel, bundle=None, angles=1, waves=None):
     """HBM bytes per launch of `kernel` (the forward: of the given bundle
-    width) from the committed counter record (FETCH_SIZE and WRITE_SIZE
-    scaled by the copy-kernel calibration), or None when the record is
-    missing or the kernel's sources changed since."""
+    layout, rays and angles per bundle, and waves per bundle) from the
+    committed counter record (FETCH_SIZE and WRITE_SIZE scaled by the
+    copy-kernel calibration), or None when the record is missing or the
+    kernel's sources changed since."""
     import hashlib
     try:
         text = open(PROFILE).read()
@@ -88,7 +91,9 @@ def traffic_from_profile(kernel, bundle=None):
         if not line.startswith("traffic-record ") or f"kernel={kernel} " not in line:
             continue
         kv = dict(tok.split("=", 1) for tok in line.split()[1:])
-        if bundle is not None and kv.get("bundle") != str(bundle):
+        if bundle is not None and (kv.get("bundle") != str(bundle) or kv.get("angles", "1") != str(angles)):
+            continue
+        if waves is not None and kv.get("waves", str(waves)) != str(waves):
             continue
         h = hashlib.sha256()
         for f in kv["sources"].split(","):
@@ -180,24 +185,26 @@ def bench_batched(sct, W, torch, dev, vdt, verify=True):
             for xb in singles:
                 op.normal(xb, alpha, lam, sigma, out=o1)
 
-        # library defaults (16-ray bundles), then the autotuned operator for this
-        # batch: bundle width chosen over 16/32/64, launch settings timed
+        # library defaults (16-ray bundles of one angle), then the autotuned
+        # operator for this batch: bundle layout chosen over the candidates of
+        # choose_bundle, launch settings timed
         tf_def, tl = t(fused(op), 5), t(looped, 2)
         ch = autotune.choose_bundle(w.n, w.n_angles, w.n_bins, w.mask, torch.float32, vdt, dev,
                                     batch=B, reps=3, save=False)
         opt = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
-                          device=dev, tuning="default", bundle=ch["bundle"])
+                          device=dev, tuning="default", bundle=ch["bundle"], bundle_angles=ch["angles"])
         autotune.autotune(opt, batch=B, save=False)
         tf = t(fused(opt), 5)
         out[name] = {"batch": B, "n": w.n, "measured_angles": w.n_meas, "bins": w.n_bins,
                      "nnz": op.info.nnz, "vectors": str(vdt).replace("torch.", ""),
                      "fused_ms": round(tf * 1e3, 3),
                      "fused_default_ms": round(tf_def * 1e3, 3),
-                     "tuned": {"bundle": opt.bundle, **opt.tuning},
+                     "tuned": {"bundle": opt.bundle, "bundle_angles": opt.bundle_angles, **opt.tuning},
                      "per_image_loop_ms": round(tl * 1e3, 3), "speedup": round(tl / tf, 2),
                      "speedup_default": round(tl / tf_def, 2),
                      "image_applies_per_s": round(B / tf, 1)}
-        print(f"# batched {name}: fused {tf * 1e3:.2f} ms tuned (bundle {opt.bundle}, {opt.tuning}), "
+        print(f"# batched {name}: fused {tf * 1e3:.2f} ms tuned (bundle {opt.bundle}x{opt.bundle_angles}, "
+              f"{opt.tuning}), "
               f"{tf_def * 1e3:.2f} ms default, loop {tl * 1e3:.2f} ms ({tl / tf:.2f}x)",
               file=sys.stderr, flush=True)
         if name == "grad_16x512_f32":
@@ -493,8 +500,9 @@ def main():
     build_s = time.perf_counter() - t0
     print(f"# built operator: nnz={op_def.info.nnz} rows={op_def.rows} in {build_s:.2f} s",
           file=sys.stderr, flush=True)
-    # the autotuned operator the timed steps run: bundle width chosen over
-    # 16/32/64 by the normal operator's time, then the launch settings timed
+    # the autotuned operator the timed steps run: bundle layout (rays and
+    # angles per bundle) chosen by the normal operator's time, then the launch
+    # settings timed
     from paper_1705_07497_amd import autotune
     if args.profile or args.profile_fourier or args.profile_multi:
         op = op_def
@@ -504,11 +512,12 @@ def main():
         ch = autotune.choose_bundle(w.n, w.n_angles, w.n_bins, w.mask, torch.float32, vdt, dev, batch=1,
                                     save=False)
         op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
-                         device=dev, tuning="default", bundle=ch["bundle"])
+                         device=dev, tuning="default", bundle=ch["bundle"], bundle_angles=ch["angles"])
         autotune.autotune(op, batch=1, save=False)
-        tuning_info = {"bundle": op.bundle, **op.tuning, "tune_s": round(time.perf_counter() - t0, 2),
+        tuning_info = {"bundle": op.bundle, "bundle_angles": op.bundle_angles, **op.tuning,
+                       "tune_s": round(time.perf_counter() - t0, 2),
                        "normal_us_by_bundle": {str(k): round(v * 1e6, 1) for k, v in ch["normal_s"].items()}}
-        print(f"# autotuned: bundle {op.bundle}, {op.tuning}", file=sys.stderr, flush=True)
+        print(f"# autotuned: bundle {op.bundle}x{op.bundle_angles}, {op.tuning}", file=sys.stderr, flush=True)
 
     mu_np, eps_np = W.phantom_and_noise(w.n, w.n_ellipses, op.rows, seed=0)
     mu = torch.as_tensor(mu_np, dtype=vdt, device=dev).reshape(1, -1)
@@ -544,14 +553,21 @@ def main():
         print("# profile sequence done (mixed batch)", file=sys.stderr, flush=True)
         return
     if args.profile:
-        # the forward kernel of each bundle width (the benchmark times the
-        # width choose_bundle picks), then the adjoint, the normal operator and CG
-        for bw in (16, 32, 64):
-            op_b = op if bw == op.bundle else sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask,
-                                                           dtype=torch.float32, vec_dtype=vdt,
-                                                           device=dev, tuning="default", bundle=bw)
-            for _ in range(100):
-                op_b.fwd_xt(x, xT, out=ysb)
+        # the forward kernel of each bundle layout (the benchmark times the
+        # layout choose_bundle picks) at 2 and 4 waves per bundle, 100
+        # launches each, layouts in the order of PROFILE_LAYOUTS (layouts of
+        # one width and wave count share a kernel name and are told apart by
+        # that order), then the adjoint, the normal operator and CG of the
+        # default operator
+        for bw, ang in PROFILE_LAYOUTS:
+            op_b = op if (bw, ang) == (op.bundle, op.bundle_angles) else sct.RadonOp(
+                w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt, device=dev,
+                tuning="default", bundle=bw, bundle_angles=ang)
+            for waves in (2, 4):
+                op_b.tuning = {"fwd_waves": waves}
+                for _ in range(100):
+                    op_b.fwd_xt(x, xT, out=ysb)
+            op_b.tuning = {"fwd_waves": 2}
             torch.cuda.synchronize()
             del op_b
         for _ in range(100):
@@ -635,8 +651,12 @@ def main():
         kname, kbytes, kavg = "k_fwd", bytes_fwd, avg_fwd
     achieved = kbytes / kavg / 1e9
     normal_bytes = bytes_fwd + bytes_adj
+    if kname == "k_fwd":
+        traffic = traffic_from_profile(kname, op.bundle, op.bundle_angles, op.tuning["fwd_waves"])
+    else:
+        traffic = traffic_from_profile(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(kname, op.bundle if kname == "k_fwd" else None),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "avg_us": round(kavg * 1e6, 2), "algorithmic_bytes": kbytes,
                 "ceiling_gbs": ceiling["read_gbs"],
                 "frac_of_ceiling": round(achieved / ceiling["read_gbs"], 4), "ceiling": ceiling}

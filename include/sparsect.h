@@ -85,7 +85,10 @@ typedef struct {
     int32_t fwd_bundle;         /* rays per bundle of the forward layout: 16, 32 or
                                    64 (0 = 16); a layout choice only, the products
                                    equal each other to rounding */
-    int32_t reserved;
+    int32_t fwd_angles;         /* consecutive measured angles per forward bundle:
+                                   1, 2 or 4 (0 = 1), with fwd_bundle / fwd_angles
+                                   >= 16 adjacent bins of each; a layout choice
+                                   only, like fwd_bundle */
 } radon_geom;
 
 typedef struct {
@@ -102,6 +105,7 @@ typedef struct {
                                    than vertical, so the forward product gathers
                                    from the transposed image too */
     int32_t fwd_bundle;         /* rays per forward bundle (16, 32 or 64) */
+    int32_t fwd_angles;         /* measured angles per forward bundle (1, 2 or 4) */
 } radon_info;
 
 /*
@@ -115,11 +119,12 @@ typedef struct {
  *     in the order the ray visits the pixels (int64 row pointers, int32 pixel
  *     indices);
  *   - a ray-bundle layout of MR for the forward product: groups of
- *     g->fwd_bundle (16, 32 or 64) adjacent bins of one angle, one slot per
- *     (ray, image line along the
- *     ray's major axis) holding the first pixel's offset along that line
- *     (uint16) and the lengths in that pixel and the next one (a ray meets at
- *     most two adjacent pixels of any line along its major axis);
+ *     g->fwd_bundle (16, 32 or 64) rays, g->fwd_bundle / g->fwd_angles
+ *     adjacent bins of each of g->fwd_angles consecutive measured angles of
+ *     one gather class, one slot per (ray, image line along the ray's major
+ *     axis) holding the first pixel's offset along that line (uint16) and
+ *     the lengths in that pixel and the next one (a ray meets at most two
+ *     adjacent pixels of any line along its major axis);
  *   - a pixel-group layout of (MR)^T for the adjoint: groups of 64 pixels,
  *     one slot per (pixel, measured angle) holding the first bin crossing
  *     the pixel (uint16) and the lengths for that bin and the next one (a
@@ -130,7 +135,9 @@ typedef struct {
  *   stream  stream for the build kernels; the call synchronises it.
  *   out     receives the handle (host object owning its device storage).
  * Errors: RADON_EINVAL (geometry out of range), RADON_EOVERFLOW (nnz or a
- * layout needs >= 2^31 entries per index type it uses), RADON_EHIP.
+ * layout needs >= 2^31 entries per index type it uses), RADON_EUNSUPPORTED
+ * (fwd_angles > 1 and the measured angles fall into more than four runs of
+ * one gather class; angles in index order make at most three), RADON_EHIP.
  */
 int build_radon_csr(const radon_geom *g, void *stream, radon_op **out);
 

@@ -39,7 +39,7 @@ class SparsectError(RuntimeError):
 class _Geom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("measured", ctypes.POINTER(ctypes.c_uint8)),
-                ("fwd_bundle", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fwd_bundle", ctypes.c_int32), ("fwd_angles", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -48,7 +48,8 @@ class _Info(ctypes.Structure):
                 ("fwd_slots", ctypes.c_int64), ("adj_slots", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("dtype", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
-                ("needs_transpose", ctypes.c_int32), ("fwd_bundle", ctypes.c_int32)]
+                ("needs_transpose", ctypes.c_int32), ("fwd_bundle", ctypes.c_int32),
+                ("fwd_angles", ctypes.c_int32)]
 
 
 class RadonSizes(ctypes.Structure):
@@ -246,15 +247,17 @@ class RadonOp:
     every array as a torch tensor (kept on the object: .csr() returns the CSR
     tensors) and fills them with build_radon_csr_into.
 
-    bundle is the forward layout's rays per bundle (16, 32 or 64; 0: the
-    cached choice for this geometry with tuning="cache", else 16).  tuning:
-    "cache" applies cached launch settings for tune_batch images, "tune"
-    chooses the bundle width and times the launch settings now (and caches
-    both), "default" leaves the library defaults."""
+    bundle is the forward layout's rays per bundle (16, 32 or 64) and
+    bundle_angles the consecutive measured angles those rays come from (1, 2
+    or 4, at least 16 bins of each); bundle 0 takes both from the cached
+    choice for this geometry with tuning="cache", else 16 rays of one angle.
+    tuning: "cache" applies cached launch settings for tune_batch images,
+    "tune" chooses the bundle layout and times the launch settings now (and
+    caches both), "default" leaves the library defaults."""
 
     def __init__(self, n: int, n_angles: int, n_bins: int, measured=None, dtype=None, device=None,
                  vec_dtype=None, tuning: str = "cache", storage: str = "library", bundle: int = 0,
-                 tune_batch: int = 1):
+                 tune_batch: int = 1, bundle_angles: int = 0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise SparsectError("no GPU visible: libsparsect runs on AMD Instinct GPUs only")
@@ -283,13 +286,16 @@ class RadonOp:
         if bundle == 0 and tuning != "default":
             from . import autotune
             if tuning == "tune":
-                bundle = autotune.choose_bundle(self.n, self.n_angles, self.n_bins, self.measured,
-                                                dtype, vec_dtype, self.device, batch=tune_batch)["bundle"]
+                ch = autotune.choose_bundle(self.n, self.n_angles, self.n_bins, self.measured,
+                                            dtype, vec_dtype, self.device, batch=tune_batch)
+                bundle, bundle_angles = ch["bundle"], ch["angles"]
             else:
-                bundle = autotune.cached_bundle(self.n, self.n_angles, self.n_bins, self.measured,
-                                                self.kind, self.device) or 0
+                bundle, bundle_angles = autotune.cached_bundle(self.n, self.n_angles, self.n_bins,
+                                                               self.measured, self.kind,
+                                                               self.device) or (0, 0)
         g = _Geom(self.n, self.n_angles, self.n_bins, self.kind,
-                  self.measured.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(bundle), 0)
+                  self.measured.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(bundle),
+                  int(bundle_angles))
         h = _vp()
         self._storage = None
         with torch.cuda.device(self.device):
@@ -308,6 +314,7 @@ class RadonOp:
         self.needs_transpose = bool(inf.needs_transpose)
         self.nn = inf.n_pixels
         self.bundle = int(inf.fwd_bundle)
+        self.bundle_angles = int(inf.fwd_angles)
         self._ws = {}
         if tuning == "cache":
             from . import autotune

@@ -8,15 +8,19 @@ time) and the launch settings (chosen by the library's radon_autotune).
   a pixel-major copy of each chunk) and band height, and keeps the fastest.  Its cache is a text file with one
   ``sparsect-tune <key> ...`` line per (architecture, geometry, measured
   angles, kind, bundle width, batch).
-* Bundle width: rays per forward bundle, 16, 32 or 64.  Wider bundles make
-  one gather instruction cover more adjacent rays on one image line, at the
-  cost of more padded slots at oblique angles.  ``choose_bundle`` builds the
-  operator once per candidate, tunes its launch settings and times the normal
-  operator; the winner goes into the same file as a ``sparsect-bundle`` line.
+* Bundle layout: rays per forward bundle (16, 32 or 64) and the consecutive
+  measured angles they come from (1, 2 or 4, at least 16 adjacent bins of
+  each).  One gather instruction covers a bundle's rays on one image line:
+  more adjacent bins, or the same bins of neighbouring angles, which cross
+  the line a few pixels apart, make it touch fewer cache lines, at the cost
+  of more padded slots where the rays' line ranges differ.
+  ``choose_bundle`` builds the operator once per candidate, tunes its launch
+  settings and times the normal operator; the winner goes into the same file
+  as a ``sparsect-bundle`` line.
 
 The file is $SPARSECT_AUTOTUNE_CACHE, else ~/.cache/sparsect/autotune.txt.
 Tuning never changes what is computed; the waves per item, the band height,
-the gather layout and the bundle width only change how each sum is split
+the gather layout and the bundle layout only change how each sum is split
 (rounding level).
 """
 from __future__ import annotations
@@ -28,6 +32,8 @@ import os
 DEFAULT = {"fwd_waves": 2, "adj_waves": 0, "fwd_rhs": 4, "adj_rhs": 8, "fwd_layout": 0, "fwd_lines": 0,
            "adj_layout": 0, "reserved": 0}
 BUNDLES = (16, 32, 64)
+# (rays per bundle, angles per bundle) candidates of choose_bundle
+LAYOUTS = ((16, 1), (32, 1), (64, 1), (32, 2), (64, 2), (64, 4))
 SOURCES = {0: "unchanged", 1: "cache", 2: "timed"}
 
 
@@ -43,26 +49,28 @@ def geometry_key(arch: str, n: int, n_angles: int, n_bins: int, measured, kind: 
 
 
 def load_bundles(path: str | None = None) -> dict:
-    """geometry key -> bundle width from the cache file (the last line wins)."""
+    """geometry key -> (rays, angles) per bundle from the cache file (the last
+    line wins; a line without the angle count means one angle)."""
     out = {}
     try:
         with open(path or cache_path()) as fh:
             for line in fh:
                 parts = line.split()
-                if len(parts) == 3 and parts[0] == "sparsect-bundle" and parts[2].isdigit():
-                    bw = int(parts[2])
-                    if bw in BUNDLES:
-                        out[parts[1]] = bw
+                if len(parts) in (3, 4) and parts[0] == "sparsect-bundle" and all(
+                        p.isdigit() for p in parts[2:]):
+                    lay = (int(parts[2]), int(parts[3]) if len(parts) == 4 else 1)
+                    if lay in LAYOUTS:
+                        out[parts[1]] = lay
     except OSError:
         pass
     return out
 
 
-def store_bundle(key: str, bw: int, path: str | None = None) -> None:
+def store_bundle(key: str, bw: int, angles: int = 1, path: str | None = None) -> None:
     path = path or cache_path()
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     with open(path, "a") as fh:
-        fh.write(f"sparsect-bundle {key} {int(bw)}\n")
+        fh.write(f"sparsect-bundle {key} {int(bw)} {int(angles)}\n")
 
 
 def device_arch(device) -> str:
@@ -71,7 +79,8 @@ def device_arch(device) -> str:
     return name.split(":")[0]
 
 
-def cached_bundle(n, n_angles, n_bins, measured, kind, device, path=None) -> int | None:
+def cached_bundle(n, n_angles, n_bins, measured, kind, device, path=None) -> tuple | None:
+    """(rays, angles) per bundle cached for this geometry, or None."""
     key = geometry_key(device_arch(device), n, n_angles, n_bins, measured, kind)
     return load_bundles(path).get(key)
 
@@ -114,21 +123,22 @@ def autotune(op, batch: int = 16, path: str | None = None, save: bool = True) ->
 
 def choose_bundle(n, n_angles, n_bins, measured=None, dtype=None, vec_dtype=None, device=None,
                   batch: int = 1, reps: int = 50, rounds: int = 3, path: str | None = None,
-                  save: bool = True) -> dict:
-    """Build the operator with each bundle width, tune its launch settings,
-    time its normal operator at `batch` (the best of `rounds` runs of `reps`
-    calls, so that a width is not ranked on one noisy run) and return the
-    fastest width (stored in the cache when save)."""
+                  save: bool = True, layouts=LAYOUTS) -> dict:
+    """Build the operator with each bundle layout (rays, angles), tune its
+    launch settings, time its normal operator at `batch` (the best of
+    `rounds` runs of `reps` calls, so that a layout is not ranked on one noisy
+    run) and return the fastest {"bundle": rays, "angles": angles} (stored in
+    the cache when save)."""
     import numpy as np
     import torch
 
     from . import RadonOp
     times = {}
     kind = None
-    for bw in BUNDLES:
+    for bw, ang in layouts:
         op = RadonOp(n, n_angles, n_bins, measured, dtype=dtype, device=device, vec_dtype=vec_dtype,
-                     tuning="default", bundle=bw)
-        kind, dev, meas = op.kind, op.device, op.measured
+                     tuning="default", bundle=bw, bundle_angles=ang)
+        kind, dev = op.kind, op.device
         autotune(op, batch=batch, save=False)
         x = torch.randn((batch, op.nn), dtype=op.dtype, device=op.device)
         out = torch.empty_like(x)
@@ -144,10 +154,11 @@ def choose_bundle(n, n_angles, n_bins, measured=None, dtype=None, vec_dtype=None
             torch.cuda.synchronize(op.device)
             s = e0.elapsed_time(e1) / reps / 1e3
             best_s = s if best_s is None else min(best_s, s)
-        times[bw] = best_s
+        times[(bw, ang)] = best_s
         del op, x, out
     best = min(times, key=times.get)
     if save:
         m = np.ones(n_angles, np.uint8) if measured is None else measured
-        store_bundle(geometry_key(device_arch(dev), n, n_angles, n_bins, m, kind), best, path)
-    return {"bundle": best, "normal_s": times}
+        store_bundle(geometry_key(device_arch(dev), n, n_angles, n_bins, m, kind), best[0], best[1], path)
+    return {"bundle": best[0], "angles": best[1],
+            "normal_s": {f"{bw}x{ang}": t for (bw, ang), t in times.items()}}

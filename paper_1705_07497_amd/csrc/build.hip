@@ -223,21 +223,27 @@ __global__ void k_ray_count(const double2 *__restrict__ cs, int n, int nb, int64
     mhi[ray] = hi;
 }
 
-// Bundle extents: union of the major ranges of up to bw adjacent rays.
+// Bundle extents: union of the major ranges of the bundle's rays (up to R
+// adjacent bins of each of its angles).
 __global__ void k_bundle_span(const double2 *__restrict__ cs, const int32_t *__restrict__ mlo,
-                              const int32_t *__restrict__ mhi, int nb, int nbpa, int bw, int64_t n_fb,
+                              const int32_t *__restrict__ mhi, int nb, BundleMap bm, int bw, int64_t n_fb,
                               FwdBundle *__restrict__ fb, int64_t *__restrict__ slots)
 {
     const int64_t B = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (B >= n_fb) return;
-    const int a = int(B / nbpa), t = int(B % nbpa);
-    const int ray0 = a * nb + t * bw;
-    const int nrays = min(bw, nb - t * bw);
+    int a0 = 0, na = 0;
+    bm.group(B / bm.nbpr, &a0, &na);
+    const int t = int(B % bm.nbpr);
+    const int ray0 = a0 * nb + t * bm.rpa;
+    const int nrays = min(bm.rpa, nb - t * bm.rpa);
     int lo = INT_MAX, hi = -1;
-    for (int r = 0; r < nrays; ++r) {
-        if (mhi[ray0 + r] >= 0) {
-            lo = min(lo, mlo[ray0 + r]);
-            hi = max(hi, mhi[ray0 + r]);
+    for (int j = 0; j < na; ++j) {
+        for (int r = 0; r < nrays; ++r) {
+            const int ray = ray0 + j * nb + r;
+            if (mhi[ray] >= 0) {
+                lo = min(lo, mlo[ray]);
+                hi = max(hi, mhi[ray]);
+            }
         }
     }
     FwdBundle d;
@@ -245,9 +251,11 @@ __global__ void k_bundle_span(const double2 *__restrict__ cs, const int32_t *__r
     d.m0 = hi >= 0 ? lo : 0;
     d.nrows = hi >= 0 ? ((hi - lo + 1 + 3) / 4) * 4 : 0;
     d.ray0 = ray0;
-    d.nrays = nrays;
-    d.horiz = is_horiz(cs[a].x, cs[a].y) ? 1 : 0;
-    d.pad = 0;
+    d.astride = nb;
+    d.nrays = int16_t(nrays);
+    d.nang = int16_t(na);
+    d.rshift = int16_t(__builtin_ctz(unsigned(bm.rpa)));
+    d.horiz = is_horiz(cs[a0].x, cs[a0].y) ? 1 : 0;
     fb[B] = d;
     slots[B] = int64_t(d.nrows) * bw;
 }
@@ -263,7 +271,7 @@ __global__ void k_bundle_off(FwdBundle *__restrict__ fb, const int64_t *__restri
 // Pass 2: write the CSR row and the ray's forward slots, and mark the first
 // bin of every (pixel, angle) pair the ray touches.
 template <class T>
-__global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nbpa, int bw, int64_t rows,
+__global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, BundleMap bm, int bw, int64_t rows,
                            int n_aq, int tiles, const int64_t *__restrict__ rp, int32_t *__restrict__ col,
                            T *__restrict__ val, const FwdBundle *__restrict__ fb,
                            uint16_t *__restrict__ f_idx, T *__restrict__ f_v0,
@@ -276,8 +284,8 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, int nb
     const double c = cs[a].x, s = cs[a].y;
     const double sb = double(b) - 0.5 * double(nb - 1);
     const bool hz = is_horiz(c, s);
-    const FwdBundle d = fb[int64_t(a) * nbpa + b / bw];
-    const int r = b % bw;
+    int r = 0;
+    const FwdBundle d = fb[bm.bundle_of(a, b, &r)];
     int64_t o = rp[ray];
     int cur = -1, nline = 0, q0 = 0, q1 = 0;
     T w0 = T(0), w1 = T(0);
@@ -437,7 +445,7 @@ static int scan_bytes(int64_t rows, int64_t n_fb, size_t *out)
     return RADON_OK;
 }
 
-static int64_t n_fb_of(const Op &op) { return int64_t(op.n_meas) * ((op.n_bins + op.bw - 1) / op.bw); }
+static int64_t n_fb_of(const Op &op) { return op.bmap.bundles(); }
 
 // Workspace of a build: room for the row pointers and the bundle table (the
 // sizes query keeps them there), the count-phase arrays and the temporary
@@ -495,8 +503,7 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
     const int64_t rows = op.rows;
     const int blk = 128;
     unsigned g;
-    const int nbpa = (nb + op.bw - 1) / op.bw;
-    op.n_fb = int64_t(op.n_meas) * nbpa;
+    op.n_fb = n_fb_of(op);
 
     SCT_TRY(ws.take(&t.cs, int64_t(sizeof(double2)) * op.n_meas));
     SCT_TRY(ws.take(&t.cnt, 8 * rows));
@@ -519,7 +526,7 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
     size_t sb = t.scan_bytes;
     SCT_HIP(hipcub::DeviceScan::InclusiveSum(t.scan, sb, t.cnt, rp + 1, rows, st));
     SCT_TRY(grid_for(op.n_fb, blk, &g));
-    k_bundle_span<<<g, blk, 0, st>>>(t.cs, t.mlo, t.mhi, nb, nbpa, op.bw, op.n_fb, fb, t.bslots);
+    k_bundle_span<<<g, blk, 0, st>>>(t.cs, t.mlo, t.mhi, nb, op.bmap, op.bw, op.n_fb, fb, t.bslots);
     SCT_TRY(check_launch("k_bundle_span"));
     sb = t.scan_bytes;
     SCT_HIP(hipcub::DeviceScan::InclusiveSum(t.scan, sb, t.bslots, t.bincl, op.n_fb, st));
@@ -645,7 +652,6 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     const int n = op.n, nb = op.n_bins;
     const int64_t rows = op.rows;
     const int blk = 128;
-    const int nbpa = (nb + op.bw - 1) / op.bw;
     const int64_t es = sizeof(T);
     unsigned g;
     SCT_HIP(hipMemsetAsync(op.f_idx, 0, size_t(2 * op.f_slots), st));
@@ -656,7 +662,7 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     SCT_HIP(hipMemsetAsync(t.bin_tmp, 0x7f, size_t(4 * op.a_slots), st));   // 0x7f7f7f7f > any bin
 
     SCT_TRY(grid_for(rows, blk, &g));
-    k_ray_fill<T><<<g, blk, 0, st>>>(t.cs, n, nb, nbpa, op.bw, rows, op.n_aq, op.tiles, op.rp, op.col,
+    k_ray_fill<T><<<g, blk, 0, st>>>(t.cs, n, nb, op.bmap, op.bw, rows, op.n_aq, op.tiles, op.rp, op.col,
                                      static_cast<T *>(op.val), op.fb, op.f_idx,
                                      static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), t.bin_tmp,
                                      t.bad);
@@ -754,6 +760,38 @@ extern "C" const char *radon_last_error(void) { return sct::last_error(); }
 
 namespace sct {
 
+// Angle runs of one gather class and their groups of op.bang angles (see
+// BundleMap), from the measured angles' (cos, sin).
+static int bundle_map(Op &op, const std::vector<double> &cs)
+{
+    BundleMap &m = op.bmap;
+    m = BundleMap();
+    m.angles = op.bang;
+    m.rpa = op.bw / op.bang;
+    m.nbpr = (op.n_bins + m.rpa - 1) / m.rpa;
+    m.runs = 0;
+    int groups = 0;
+    for (int a = 0; a < op.n_meas;) {
+        const bool hz = std::fabs(cs[2 * size_t(a) + 1]) > std::fabs(cs[2 * size_t(a)]);
+        int e = a + 1;
+        // with one angle per bundle the classes need no runs of their own
+        while (e < op.n_meas &&
+               (op.bang == 1 || (std::fabs(cs[2 * size_t(e) + 1]) > std::fabs(cs[2 * size_t(e)])) == hz))
+            ++e;
+        if (m.runs == kMaxAngleRuns)
+            return set_error(RADON_EUNSUPPORTED, "measured angles fall into more than %d runs of one gather class",
+                             kMaxAngleRuns);
+        m.start[m.runs] = a;
+        m.gbase[m.runs] = groups;
+        groups += (e - a + op.bang - 1) / op.bang;
+        ++m.runs;
+        a = e;
+    }
+    m.start[m.runs] = op.n_meas;
+    m.gbase[m.runs] = groups;
+    return RADON_OK;
+}
+
 // Checks the geometry and fills the operator's sizes and angle table (no
 // device work).  On success *res owns a new handle without device arrays.
 static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
@@ -769,6 +807,11 @@ static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
                          g->dtype);
     if (g->fwd_bundle != 0 && !valid_bundle_width(g->fwd_bundle))
         return set_error(RADON_EINVAL, "fwd_bundle must be 0, 16, 32 or 64 (got %d)", g->fwd_bundle);
+    const int bw = g->fwd_bundle ? g->fwd_bundle : kFwdLanes;
+    if (g->fwd_angles != 0 && !valid_bundle_angles(g->fwd_angles, bw))
+        return set_error(RADON_EINVAL,
+                         "fwd_angles must be 0, 1, 2 or 4 with at least 16 rays per angle "
+                         "(got %d angles for a bundle of %d rays)", g->fwd_angles, bw);
     std::vector<int32_t> meas;
     for (int k = 0; k < g->n_angles; ++k)
         if (!g->measured || g->measured[k]) meas.push_back(k);
@@ -792,17 +835,23 @@ static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
     op->rows = rows;
     op->msize = g->dtype == SPARSECT_F64 ? 8 : 4;
     op->vsize = g->dtype == SPARSECT_F32 ? 4 : 8;
-    op->bw = g->fwd_bundle ? g->fwd_bundle : kFwdLanes;
+    op->bw = bw;
+    op->bang = g->fwd_angles ? g->fwd_angles : 1;
     op->tiles = (op->n + 7) / 8;
     op->n_ag = int64_t(op->tiles) * op->tiles;
     op->n_aq = (op->n_meas + 3) / 4;
     op->a_slots = aslots;
-    op->n_fb = n_fb_of(*op);
     cs.assign(2 * meas.size(), 0.0);
     for (size_t a = 0; a < meas.size(); ++a) {
         angle_cos_sin(meas[a], g->n_angles, &cs[2 * a], &cs[2 * a + 1]);
         if (std::fabs(cs[2 * a + 1]) > std::fabs(cs[2 * a])) op->need_T = true;
     }
+    const int rc = bundle_map(*op, cs);
+    if (rc != RADON_OK) {
+        delete op;
+        return rc;
+    }
+    op->n_fb = n_fb_of(*op);
     *res = op;
     return RADON_OK;
 }
@@ -989,6 +1038,8 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     return RADON_OK;
 }
 
+static_assert(sizeof(radon_geom) == 32 && sizeof(radon_info) == 88, "C ABI struct sizes");
+
 extern "C" void radon_op_destroy(radon_op *p) { op_free(as_op(p)); }
 
 extern "C" int radon_op_info(const radon_op *p, radon_info *out)
@@ -1010,6 +1061,7 @@ extern "C" int radon_op_info(const radon_op *p, radon_info *out)
     out->n_bins = op->n_bins;
     out->needs_transpose = op->need_T ? 1 : 0;
     out->fwd_bundle = op->bw;
+    out->fwd_angles = op->bang;
     return RADON_OK;
 }
 

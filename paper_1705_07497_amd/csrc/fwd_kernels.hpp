@@ -115,9 +115,8 @@ inline void fwd_band_wbc(const Op &op, const BandSet &bs, const TV *x, const TV 
         op.fb, bs.order, bs.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
         static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, bs.n_bands,
         bs.lines, batch, tickets);
-    const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
     k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(batch)), 256, 0, s>>>(
-        op.fb, part, y, op.rows, op.n_bins, nbpa, op.bw, bs.n_bands, bs.lines);
+        op.fb, part, y, op.rows, op.n_bins, op.bmap, bs.n_bands, bs.lines);
 }
 
 template <class TM, class TV, int BC, int BW>
@@ -154,9 +153,8 @@ inline void fwd_pm_launch(const Op &op, const BandSet *bs, const TV *xp, const T
         k_fwd_pm_band<TM, TV, W, C, BW><<<unsigned(g), 64 * W, 0, s>>>(
             op.fb, bs->order, bs->n_order, op.f_idx, v0, v1, xp, xpT, part, op.n, op.rows, bs->n_bands,
             bs->lines, nb, tickets);
-        const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
         k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(nb)), 256, 0, s>>>(
-            op.fb, part, y, op.rows, op.n_bins, nbpa, op.bw, bs->n_bands, bs->lines);
+            op.fb, part, y, op.rows, op.n_bins, op.bmap, bs->n_bands, bs->lines);
     } else {
         const int64_t g = op.n_order < kPersistentBlocks ? op.n_order : kPersistentBlocks;
         k_fwd_pm<TM, TV, W, C, BW><<<unsigned(g), 64 * W, 0, s>>>(op.fb, op.fb_order, op.n_order, op.f_idx,

@@ -216,13 +216,14 @@ __device__ __forceinline__ void pm_bundle(const FwdBundle &d, const uint16_t *__
         }
         __syncthreads();   // red is reused by the next bundle
     }
-    if (wave == 0 && q == 0 && r < d.nrays) {
+    const int64_t ray = bundle_ray(d, r);
+    if (wave == 0 && q == 0 && ray >= 0) {
 #pragma unroll
         for (int iq = 0; iq < S::IQ; ++iq)
 #pragma unroll
             for (int v = 0; v < S::VW; ++v) {
                 const int c = (iq * S::GL + gl) * S::VW + v;
-                if (c < nbc) y[int64_t(c) * ystride + d.ray0 + r] = acc[iq][v];
+                if (c < nbc) y[int64_t(c) * ystride + ray] = acc[iq][v];
             }
     }
 }

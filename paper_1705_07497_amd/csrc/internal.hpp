@@ -12,17 +12,23 @@
 
 namespace sct {
 
-// Forward product layout: one bundle = up to BW adjacent bins of one measured
-// angle (BW, the bundle width, is 16, 32 or 64, chosen when the operator is
-// built).  Slot (t, r) covers ray r of the bundle on image line m0 + t along
-// the rays' major axis (rows for rays closer to vertical, columns for rays
-// closer to horizontal).  Slots are grouped in quads of 4 consecutive lines of
-// one ray so that a lane reads 4 slots with one 16-byte load:
+// Forward product layout: one bundle = up to R adjacent bins of each of up to
+// A consecutive measured angles of one gather class (A, the angles per
+// bundle, is 1, 2 or 4; BW = A*R, the bundle width, is 16, 32 or 64; both are
+// chosen when the operator is built).  Lane r of a bundle is angle r / R, bin
+// r % R.  Slot (t, r) covers lane r's ray on image line m0 + t along the
+// rays' major axis (rows for rays closer to vertical, columns for rays closer
+// to horizontal).  Slots are grouped in quads of 4 consecutive lines of one
+// ray so that a lane reads 4 slots with one 16-byte load:
 //   slot(t, r) = off + ((t/4)*BW + r)*4 + t%4.
 // A wave's 64 lanes cover BW rays and 64/BW consecutive quads, so one gather
-// instruction reads BW adjacent rays on each of 64/BW image lines.
+// instruction reads the BW rays on each of 64/BW image lines.  The rays of
+// neighbouring angles and the same bins cross an image line a few pixels
+// apart, so with A > 1 the lanes of one gather share most of their cache
+// lines.
 constexpr int kFwdLanes = 16;   // default bundle width
 inline bool valid_bundle_width(int bw) { return bw == 16 || bw == 32 || bw == 64; }
+inline bool valid_bundle_angles(int a, int bw) { return (a == 1 || a == 2 || a == 4) && bw / a >= 16; }
 // Adjoint layout: one group = an 8x8 pixel tile (tile (ty, tx) is group
 // g = ty*tiles + tx, tiles = ceil(n/8); lane l = (iy%8)*8 + ix%8), chosen
 // because an 8x8 tile projects onto at most 14 adjacent bins at any angle, so
@@ -70,15 +76,56 @@ __host__ __device__ inline int64_t adj_slot(int iy, int ix, int a, int nq, int t
 }
 
 struct FwdBundle {
-    int64_t off;    // first slot
-    int32_t m0;     // first major line
-    int32_t nrows;  // major lines covered (multiple of 4, may be 0)
-    int32_t ray0;   // first measured ray of the bundle
-    int32_t nrays;  // rays in the bundle (<= the bundle width)
-    int32_t horiz;  // 1: major axis is x (gather from the transposed image)
-    int32_t pad;
+    int64_t off;      // first slot
+    int32_t m0;       // first major line
+    int32_t nrows;    // major lines covered (multiple of 4, may be 0)
+    int32_t ray0;     // measured ray of lane 0 (first angle, first bin)
+    int32_t astride;  // measured rays from one angle of the bundle to the next (n_bins)
+    int16_t nrays;    // bins per angle in the bundle (<= R)
+    int16_t nang;     // angles in the bundle (<= A)
+    int16_t rshift;   // log2 R: lane r is angle r >> rshift, bin r & (R - 1)
+    int16_t horiz;    // 1: major axis is x (gather from the transposed image)
 };
 static_assert(sizeof(FwdBundle) == 32, "FwdBundle layout");
+
+// Measured ray of lane r of bundle d, or -1 for a lane without a ray.
+__host__ __device__ inline int64_t bundle_ray(const FwdBundle &d, int r)
+{
+    const int j = r >> d.rshift, k = r & ((1 << d.rshift) - 1);
+    if (j >= d.nang || k >= d.nrays) return -1;
+    return int64_t(d.ray0) + int64_t(j) * d.astride + k;
+}
+
+// Angles -> bundles.  The measured angles (in index order) fall into runs of
+// one gather class (at most three: up to pi/4, to 3pi/4, to pi); each run is
+// cut into groups of A consecutive angles, group g holding bundles
+// g*nbpr .. g*nbpr + nbpr - 1 of R bins each (nbpr = ceil(n_bins / R)).
+constexpr int kMaxAngleRuns = 4;
+struct BundleMap {
+    int32_t angles = 1, rpa = kFwdLanes, nbpr = 0, runs = 1;
+    int32_t start[kMaxAngleRuns + 1] = {};   // first measured angle of each run; start[runs] = n_meas
+    int32_t gbase[kMaxAngleRuns + 1] = {};   // first group of each run; gbase[runs] = groups
+
+    __host__ __device__ int64_t bundles() const { return int64_t(gbase[runs]) * nbpr; }
+    // bundle of (measured angle a, bin) and the ray's lane in it
+    __host__ __device__ int64_t bundle_of(int a, int bin, int *lane) const
+    {
+        int k = 0;
+        while (k + 1 < runs && a >= start[k + 1]) ++k;
+        const int rel = a - start[k];
+        *lane = (rel % angles) * rpa + bin % rpa;
+        return int64_t(gbase[k] + rel / angles) * nbpr + bin / rpa;
+    }
+    // first measured angle and angle count of group g
+    __host__ __device__ void group(int64_t g, int *a0, int *na) const
+    {
+        int k = 0;
+        while (k + 1 < runs && g >= gbase[k + 1]) ++k;
+        *a0 = start[k] + int(g - gbase[k]) * angles;
+        const int left = start[k + 1] - *a0;
+        *na = left < angles ? left : angles;
+    }
+};
 
 struct Op {
     int32_t n = 0, n_angles = 0, n_bins = 0, dtype = 0;
@@ -90,7 +137,9 @@ struct Op {
     std::vector<int32_t> meas;       // measured angle indices (host)
     int32_t msize = 4;               // bytes per stored matrix value
     int32_t vsize = 4;               // bytes per vector element
-    int32_t bw = kFwdLanes;          // rays per forward bundle (16, 32 or 64)
+    int32_t bw = kFwdLanes;          // lanes (rays) per forward bundle (16, 32 or 64)
+    int32_t bang = 1;                // measured angles per forward bundle (1, 2 or 4)
+    BundleMap bmap;                  // angles -> forward bundles
 
     // CSR of MR (device)
     int64_t *rp = nullptr;

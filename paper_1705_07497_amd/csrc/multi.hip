@@ -489,10 +489,9 @@ static int multi_launch_fwd(const Multi &m, const TV *x, const TV *xT, TV *y, TV
     for (int i = 0; i < m.count; ++i) {
         const Op &op = *m.ops[size_t(i)];
         if (m.part_off[size_t(i)] < 0) continue;
-        const int nbpa = (op.n_bins + op.bw - 1) / op.bw;
         k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), 1u), 256, 0, s>>>(
-            op.fb, fpart + m.part_off[size_t(i)], y + m.sino_off[size_t(i)], op.rows, op.n_bins, nbpa,
-            op.bw, op.n_bands, kBandLines);
+            op.fb, fpart + m.part_off[size_t(i)], y + m.sino_off[size_t(i)], op.rows, op.n_bins, op.bmap,
+            op.n_bands, kBandLines);
         SCT_TRY(check_launch("k_fwd_band_sum"));
     }
     return RADON_OK;

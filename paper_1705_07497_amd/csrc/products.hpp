@@ -159,10 +159,11 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
         }
         __syncthreads();   // red is reused by the next bundle
     }
-    if (wave == 0 && q == 0 && r < d.nrays) {
+    const int64_t ray = bundle_ray(d, r);
+    if (wave == 0 && q == 0 && ray >= 0) {
 #pragma unroll
         for (int c = 0; c < BC; ++c)
-            if (c < nbc) y[int64_t(c) * rows + d.ray0 + r] = acc[c];
+            if (c < nbc) y[int64_t(c) * rows + ray] = acc[c];
     }
 }
 
@@ -171,14 +172,15 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
 template <class TV>
 __global__ __launch_bounds__(256) void k_fwd_band_sum(const FwdBundle *__restrict__ fb,
                                                       const TV *__restrict__ part, TV *__restrict__ y,
-                                                      int64_t rows, int nb, int nbpa, int bw,
+                                                      int64_t rows, int nb, BundleMap bm,
                                                       int n_bands, int lines)
 {
     const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ray >= rows) return;
     const int b = blockIdx.y;
     const int a = int(ray / nb), bin = int(ray % nb);
-    const FwdBundle d = fb[int64_t(a) * nbpa + bin / bw];
+    int lane = 0;
+    const FwdBundle d = fb[bm.bundle_of(a, bin, &lane)];
     TV acc = TV(0);
     if (d.nrows > 0) {
         const int lo = d.m0 / lines, hi = (d.m0 + d.nrows - 4) / lines;

@@ -42,7 +42,7 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct.CgInfo) == 24
     assert ctypes.sizeof(sct.SbParams) == 40
     assert ctypes.sizeof(sct.SbInfo) == 32
-    assert ctypes.sizeof(sct._Info) == 80
+    assert ctypes.sizeof(sct._Info) == 88
     assert ctypes.sizeof(sct.PdParams) == 40
     assert int(consts["RADON_WS_PD"]) == sct.WS_PD
     assert int(consts["RADON_WS_TUNE"]) == sct.WS_TUNE
@@ -57,13 +57,13 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct.Tuning) == 32
 
 
-def _build(n, na, nb, dtype=0, measured=None):
+def _build(n, na, nb, dtype=0, measured=None, bundle=0, angles=0):
     L = sct.lib()
     m = None
     if measured is not None:
         arr = (ctypes.c_uint8 * len(measured))(*measured)
         m = ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint8))
-    g = sct._Geom(n, na, nb, dtype, m)
+    g = sct._Geom(n, na, nb, dtype, m, bundle, angles)
     h = ctypes.c_void_p()
     rc = L.build_radon_csr(ctypes.byref(g), None, ctypes.byref(h))
     return rc, L.radon_last_error().decode()
@@ -80,6 +80,18 @@ def _build(n, na, nb, dtype=0, measured=None):
 def test_build_rejects_bad_geometry(args, code, frag):
     rc, msg = _build(*args)
     assert rc == code and frag in msg
+
+
+@pytest.mark.parametrize("bundle,angles,frag", [
+    (48, 0, "fwd_bundle"),
+    (16, 2, "fwd_angles"),     # 8 bins per angle
+    (32, 4, "fwd_angles"),
+    (64, 3, "fwd_angles"),
+    (64, -1, "fwd_angles"),
+])
+def test_build_rejects_bad_bundle_layout(bundle, angles, frag):
+    rc, msg = _build(8, 4, 13, 0, None, bundle, angles)
+    assert rc == -1 and frag in msg
 
 
 def test_build_rejects_no_measured_angle():
