@@ -89,6 +89,10 @@ typedef struct {
                                    1, 2 or 4 (0 = 1), with fwd_bundle / fwd_angles
                                    >= 16 adjacent bins of each; a layout choice
                                    only, like fwd_bundle */
+    int32_t fwd_compact;        /* 1: the forward layout stores one length per
+                                   slot and derives the second (see below); 0:
+                                   both stored */
+    int32_t reserved;           /* must be 0 */
 } radon_geom;
 
 typedef struct {
@@ -106,6 +110,7 @@ typedef struct {
                                    from the transposed image too */
     int32_t fwd_bundle;         /* rays per forward bundle (16, 32 or 64) */
     int32_t fwd_angles;         /* measured angles per forward bundle (1, 2 or 4) */
+    int32_t fwd_compact;        /* 1: compact forward layout */
 } radon_info;
 
 /*
@@ -124,12 +129,20 @@ typedef struct {
  *     one gather class, one slot per (ray, image line along the ray's major
  *     axis) holding the first pixel's offset along that line (uint16) and
  *     the lengths in that pixel and the next one (a ray meets at most two
- *     adjacent pixels of any line along its major axis);
+ *     adjacent pixels of any line along its major axis).  With
+ *     g->fwd_compact the second length is not stored: it is the ray's chord
+ *     minus the first on every line the ray crosses from side to side (the
+ *     two lengths add up to the same chord there), and is kept per ray for
+ *     its first and last lines, the only ones it can cross in part;
  *   - a pixel-group layout of (MR)^T for the adjoint: groups of 64 pixels,
  *     one slot per (pixel, measured angle) holding the first bin crossing
  *     the pixel (uint16) and the lengths for that bin and the next one (a
  *     pixel meets at most two adjacent bins of any angle).
- * Both layouts hold exactly the CSR's values.
+ * Both layouts hold exactly the CSR's values, except that a compact
+ * ray-bundle layout's derived second lengths differ from the CSR's by about
+ * one rounding of the matrix type relative to the chord (the build checks
+ * every line against the chord to 1e-9); the CSR and the adjoint keep the
+ * stored values.
  *
  *   g       geometry (host struct); `measured` is read during the call only.
  *   stream  stream for the build kernels; the call synchronises it.
@@ -137,7 +150,8 @@ typedef struct {
  * Errors: RADON_EINVAL (geometry out of range), RADON_EOVERFLOW (nnz or a
  * layout needs >= 2^31 entries per index type it uses), RADON_EUNSUPPORTED
  * (fwd_angles > 1 and the measured angles fall into more than four runs of
- * one gather class; angles in index order make at most three), RADON_EHIP.
+ * one gather class, which angles in index order never do; or a layout
+ * assumption above failed for some ray), RADON_EHIP.
  */
 int build_radon_csr(const radon_geom *g, void *stream, radon_op **out);
 

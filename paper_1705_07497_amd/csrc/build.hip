@@ -199,10 +199,12 @@ __device__ void trace_ray(int n, double c, double s, double sb, Emit &&emit)
 
 __device__ inline bool is_horiz(double c, double s) { return fabs(s) > fabs(c); }
 
-// Pass 1: entries per measured ray and the range of major lines it covers.
+// Pass 1: entries per measured ray, the range of major lines it covers and
+// its chord: the summed length on its second line when a third follows (that
+// line is crossed from side to side), else 0.
 __global__ void k_ray_count(const double2 *__restrict__ cs, int n, int nb, int64_t rows,
                             int64_t *__restrict__ cnt, int32_t *__restrict__ mlo,
-                            int32_t *__restrict__ mhi)
+                            int32_t *__restrict__ mhi, double *__restrict__ chord)
 {
     const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ray >= rows) return;
@@ -212,15 +214,26 @@ __global__ void k_ray_count(const double2 *__restrict__ cs, int n, int nb, int64
     const bool hz = is_horiz(c, s);
     int64_t count = 0;
     int lo = INT_MAX, hi = -1;
-    trace_ray(n, c, s, sb, [&](int j, double) {
+    int cur = -1, lines = 0;
+    double lsum = 0.0, ch = 0.0;
+    trace_ray(n, c, s, sb, [&](int j, double len) {
         ++count;
         const int m = hz ? j % n : j / n;
         lo = m < lo ? m : lo;
         hi = m > hi ? m : hi;
+        if (m != cur) {
+            if (lines == 2) ch = lsum;   // the second line is complete and not the last
+            ++lines;
+            cur = m;
+            lsum = len;
+        } else {
+            lsum += len;
+        }
     });
     cnt[ray] = count;
     mlo[ray] = lo;
     mhi[ray] = hi;
+    chord[ray] = ch;
 }
 
 // Bundle extents: union of the major ranges of the bundle's rays (up to R
@@ -268,15 +281,25 @@ __global__ void k_bundle_off(FwdBundle *__restrict__ fb, const int64_t *__restri
     fb[B].off = incl[B] - int64_t(fb[B].nrows) * bw;
 }
 
-// Pass 2: write the CSR row and the ray's forward slots, and mark the first
-// bin of every (pixel, angle) pair the ray touches.
+// Relative tolerance of the chord check: lengths on one line add up to the
+// chord to within the rounding of the FP64 ray parameters (about 1e-13 of the
+// image side) and the dropped slivers (below kSliver).
+constexpr double kChordTol = 1e-9;
+
+// Pass 2: write the CSR row, the ray's forward slots (first pixel, its
+// length and, unless the operator is compact (f_v1 == nullptr), the second
+// length) and its RayEdge, and mark the first bin of every (pixel, angle)
+// pair the ray touches.  Every line between the ray's first and last must
+// hold the chord (bad flag 32 otherwise: a compact forward derives the
+// second length from it).
 template <class T>
 __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, BundleMap bm, int bw, int64_t rows,
                            int n_aq, int tiles, const int64_t *__restrict__ rp, int32_t *__restrict__ col,
                            T *__restrict__ val, const FwdBundle *__restrict__ fb,
-                           uint16_t *__restrict__ f_idx, T *__restrict__ f_v0,
-                           T *__restrict__ f_v1, int32_t *__restrict__ bin_tmp,
-                           int32_t *__restrict__ bad)
+                           uint16_t *__restrict__ f_idx, T *__restrict__ f_v0, T *__restrict__ f_v1,
+                           const int32_t *__restrict__ mlo, const int32_t *__restrict__ mhi,
+                           const double *__restrict__ chord, RayEdge *__restrict__ f_edge,
+                           int32_t *__restrict__ bin_tmp, int32_t *__restrict__ bad)
 {
     const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ray >= rows) return;
@@ -286,9 +309,18 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
     const bool hz = is_horiz(c, s);
     int r = 0;
     const FwdBundle d = fb[bm.bundle_of(a, b, &r)];
+    const int mf = mlo[ray], ml = mhi[ray];
+    const double ch = chord[ray];
+    RayEdge e;
+    e.chord = ch;
+    e.w1f = 0.0;
+    e.w1l = 0.0;
+    e.mf = ml >= 0 ? mf : 1;   // no pixels: mf > ml
+    e.ml = ml >= 0 ? ml : 0;
     int64_t o = rp[ray];
     int cur = -1, nline = 0, q0 = 0, q1 = 0;
     T w0 = T(0), w1 = T(0);
+    double l0 = 0.0, l1 = 0.0;
     const int64_t oend = rp[ray + 1];
     auto flush = [&]() {
         if (cur < 0) return;
@@ -297,17 +329,21 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
             return;
         }
         const int64_t slot = fwd_slot(d.off, cur - d.m0, r, bw);
+        T v1 = T(0);
         if (nline == 1) {
             f_idx[slot] = uint16_t(q0);
             f_v0[slot] = w0;
-            f_v1[slot] = T(0);
         } else {
             if (q1 != q0 + 1 && q0 != q1 + 1) atomicOr(bad, 1);
             const bool first0 = q0 < q1;
             f_idx[slot] = uint16_t(first0 ? q0 : q1);
             f_v0[slot] = first0 ? w0 : w1;
-            f_v1[slot] = first0 ? w1 : w0;
+            v1 = first0 ? w1 : w0;
         }
+        if (f_v1) f_v1[slot] = v1;
+        if (cur == mf) e.w1f = double(v1);
+        if (cur == ml) e.w1l = double(v1);
+        if (cur != mf && cur != ml && !(fabs(l0 + l1 - ch) <= kChordTol * ch)) atomicOr(bad, 32);
     };
     trace_ray(n, c, s, sb, [&](int j, double len) {
         const T v = T(len);
@@ -326,16 +362,20 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
             nline = 1;
             q0 = q;
             w0 = v;
+            l0 = len;
+            l1 = 0.0;
         } else {
             if (nline >= 2) atomicOr(bad, 2);
             nline = 2;
             q1 = q;
             w1 = v;
+            l1 = len;
         }
         atomicMin(&bin_tmp[adj_slot(j / n, j % n, a, n_aq, tiles)], b);
     });
     flush();
     if (o != oend) atomicOr(bad, 4);
+    f_edge[ray] = e;
 }
 
 // Pass 3: place each entry in its (pixel, angle) slot as the first or second bin.
@@ -460,6 +500,7 @@ static int build_ws_bytes(const Op &op, int64_t *out)
     b += up256(int64_t(sizeof(FwdBundle)) * n_fb);        // bundle table (sizes query)
     b += up256(16 * int64_t(op.n_meas));                  // (cos, sin)
     b += up256(8 * rows) + 2 * up256(4 * rows);           // counts, major-line ranges
+    b += up256(8 * rows);                                 // chords
     b += up256(4);                                        // error flags
     b += 2 * up256(8 * n_fb);                             // bundle slots and their scan
     b += up256(int64_t(sb));                              // scan temporaries
@@ -474,7 +515,8 @@ static int64_t layout_bytes(const Op &op, const Plan &pl)
     const int64_t es = op.msize;
     int64_t b = 0;
     b += up256(int64_t(sizeof(FwdBundle)) * n_fb_of(op));
-    b += up256(2 * pl.fslots) + 2 * up256(es * pl.fslots);
+    b += up256(2 * pl.fslots) + (op.compact ? 1 : 2) * up256(es * pl.fslots);
+    b += up256(int64_t(sizeof(RayEdge)) * op.rows);
     b += up256(op.a_slots) + up256(2 * op.n_ag * op.n_aq * 4) + 2 * up256(es * op.a_slots);
     b += up256(4 * int64_t(pl.order.size()));
     for (const auto &bo : pl.border) b += up256(8 * int64_t(bo.size()));
@@ -488,6 +530,7 @@ struct CountTmp {
     double2 *cs = nullptr;
     int64_t *cnt = nullptr, *bslots = nullptr, *bincl = nullptr;
     int32_t *mlo = nullptr, *mhi = nullptr, *bad = nullptr;
+    double *chord = nullptr;
     void *scan = nullptr;
     size_t scan_bytes = 0;
     int32_t *bin_tmp = nullptr;
@@ -509,6 +552,7 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
     SCT_TRY(ws.take(&t.cnt, 8 * rows));
     SCT_TRY(ws.take(&t.mlo, 4 * rows));
     SCT_TRY(ws.take(&t.mhi, 4 * rows));
+    SCT_TRY(ws.take(&t.chord, 8 * rows));
     SCT_TRY(ws.take(&t.bad, 4));
     SCT_TRY(ws.take(&t.bslots, 8 * op.n_fb));
     SCT_TRY(ws.take(&t.bincl, 8 * op.n_fb));
@@ -519,7 +563,7 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
     SCT_HIP(hipMemcpyAsync(t.cs, cs_host.data(), sizeof(double2) * op.n_meas, hipMemcpyHostToDevice, st));
     SCT_HIP(hipMemsetAsync(t.bad, 0, 4, st));
     SCT_TRY(grid_for(rows, blk, &g));
-    k_ray_count<<<g, blk, 0, st>>>(t.cs, n, nb, rows, t.cnt, t.mlo, t.mhi);
+    k_ray_count<<<g, blk, 0, st>>>(t.cs, n, nb, rows, t.cnt, t.mlo, t.mhi, t.chord);
     SCT_TRY(check_launch("k_ray_count"));
 
     SCT_HIP(hipMemsetAsync(rp, 0, 8, st));
@@ -656,7 +700,7 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     unsigned g;
     SCT_HIP(hipMemsetAsync(op.f_idx, 0, size_t(2 * op.f_slots), st));
     SCT_HIP(hipMemsetAsync(op.f_v0, 0, size_t(es * op.f_slots), st));
-    SCT_HIP(hipMemsetAsync(op.f_v1, 0, size_t(es * op.f_slots), st));
+    if (op.f_v1) SCT_HIP(hipMemsetAsync(op.f_v1, 0, size_t(es * op.f_slots), st));
     SCT_HIP(hipMemsetAsync(op.a_v0, 0, size_t(es * op.a_slots), st));
     SCT_HIP(hipMemsetAsync(op.a_v1, 0, size_t(es * op.a_slots), st));
     SCT_HIP(hipMemsetAsync(t.bin_tmp, 0x7f, size_t(4 * op.a_slots), st));   // 0x7f7f7f7f > any bin
@@ -664,8 +708,9 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     SCT_TRY(grid_for(rows, blk, &g));
     k_ray_fill<T><<<g, blk, 0, st>>>(t.cs, n, nb, op.bmap, op.bw, rows, op.n_aq, op.tiles, op.rp, op.col,
                                      static_cast<T *>(op.val), op.fb, op.f_idx,
-                                     static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), t.bin_tmp,
-                                     t.bad);
+                                     static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), t.mlo, t.mhi,
+                                     t.chord, op.f_edge,
+                                     t.bin_tmp, t.bad);
     SCT_TRY(check_launch("k_ray_fill"));
     k_adj_fill<T><<<g, blk, 0, st>>>(n, nb, rows, op.n_aq, op.tiles, op.rp, op.col,
                                      static_cast<const T *>(op.val), t.bin_tmp,
@@ -691,7 +736,8 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     if (bad_h)
         return set_error(RADON_EUNSUPPORTED,
                          "slotted layout assumption violated (code %d): a ray met more than two "
-                         "pixels of one line, or a pixel more than two bins of one angle", bad_h);
+                         "pixels of one line, a pixel more than two bins of one angle, or a line "
+                         "inside a ray's range held other than the ray's chord (32)", bad_h);
     return RADON_OK;
 }
 
@@ -703,7 +749,9 @@ static int carve_layouts(Op &op, const Plan &pl, Carve &lay, bool fb_taken)
     if (!fb_taken) SCT_TRY(lay.take(&op.fb, int64_t(sizeof(FwdBundle)) * op.n_fb));
     SCT_TRY(lay.take(&op.f_idx, 2 * pl.fslots));
     SCT_TRY(lay.take(&op.f_v0, es * pl.fslots));
-    SCT_TRY(lay.take(&op.f_v1, es * pl.fslots));
+    op.f_v1 = nullptr;
+    if (!op.compact) SCT_TRY(lay.take(&op.f_v1, es * pl.fslots));
+    SCT_TRY(lay.take(&op.f_edge, int64_t(sizeof(RayEdge)) * op.rows));
     SCT_TRY(lay.take(&op.a_rel, op.a_slots));
     SCT_TRY(lay.take(&op.a_base, 2 * op.n_ag * op.n_aq * 4));
     SCT_TRY(lay.take(&op.a_v0, es * op.a_slots));
@@ -808,6 +856,9 @@ static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
     if (g->fwd_bundle != 0 && !valid_bundle_width(g->fwd_bundle))
         return set_error(RADON_EINVAL, "fwd_bundle must be 0, 16, 32 or 64 (got %d)", g->fwd_bundle);
     const int bw = g->fwd_bundle ? g->fwd_bundle : kFwdLanes;
+    if (g->fwd_compact != 0 && g->fwd_compact != 1)
+        return set_error(RADON_EINVAL, "fwd_compact must be 0 or 1 (got %d)", g->fwd_compact);
+    if (g->reserved != 0) return set_error(RADON_EINVAL, "reserved must be 0 (got %d)", g->reserved);
     if (g->fwd_angles != 0 && !valid_bundle_angles(g->fwd_angles, bw))
         return set_error(RADON_EINVAL,
                          "fwd_angles must be 0, 1, 2 or 4 with at least 16 rays per angle "
@@ -837,6 +888,7 @@ static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
     op->vsize = g->dtype == SPARSECT_F32 ? 4 : 8;
     op->bw = bw;
     op->bang = g->fwd_angles ? g->fwd_angles : 1;
+    op->compact = g->fwd_compact != 0;
     op->tiles = (op->n + 7) / 8;
     op->n_ag = int64_t(op->tiles) * op->tiles;
     op->n_aq = (op->n_meas + 3) / 4;
@@ -1038,7 +1090,7 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     return RADON_OK;
 }
 
-static_assert(sizeof(radon_geom) == 32 && sizeof(radon_info) == 88, "C ABI struct sizes");
+static_assert(sizeof(radon_geom) == 40 && sizeof(radon_info) == 88, "C ABI struct sizes");
 
 extern "C" void radon_op_destroy(radon_op *p) { op_free(as_op(p)); }
 
@@ -1062,6 +1114,7 @@ extern "C" int radon_op_info(const radon_op *p, radon_info *out)
     out->needs_transpose = op->need_T ? 1 : 0;
     out->fwd_bundle = op->bw;
     out->fwd_angles = op->bang;
+    out->fwd_compact = op->compact ? 1 : 0;
     return RADON_OK;
 }
 

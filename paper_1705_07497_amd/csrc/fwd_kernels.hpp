@@ -15,6 +15,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb
                                                 const int32_t *__restrict__ order, int64_t n_order,
                                                 const uint16_t *__restrict__ idx,
                                                 const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                const RayEdge *__restrict__ edge,
                                                 const TV *__restrict__ x, const TV *__restrict__ xT,
                                                 TV *__restrict__ y, int n, int64_t nn, int64_t rows,
                                                 int batch)
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd(const FwdBundle *__restrict__ fb
         const int B = order[o];
         if (B < 0) continue;           // padding entry (uniform per block)
         const FwdBundle d = fb[B];
-        fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, (d.horiz ? xT : x) + int64_t(b0) * nn,
+        fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, edge, (d.horiz ? xT : x) + int64_t(b0) * nn,
                                       y + int64_t(b0) * rows, n, nn, rows, nbc);
     }
 }
@@ -47,6 +48,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict
                                                      const int2 *__restrict__ order, int64_t n_order,
                                                      const uint16_t *__restrict__ idx,
                                                      const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                const RayEdge *__restrict__ edge,
                                                      const TV *__restrict__ x, const TV *__restrict__ xT,
                                                      TV *__restrict__ part, int n, int64_t nn,
                                                      int64_t rows, int n_bands, int lines, int batch,
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_band(const FwdBundle *__restrict
         const int lo = it.y * lines - d.m0, hi = lo + lines;
         const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
         const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
-        fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, d.horiz ? xT : x, part + int64_t(it.y) * rows, n, nn,
+        fwd_bundle<TM, TV, W, BC, BW>(d, idx, v0, v1, edge, d.horiz ? xT : x, part + int64_t(it.y) * rows, n, nn,
                                       stride, nbc, tq0, tq1);
     }
 }
@@ -91,7 +93,7 @@ inline void fwd_wbc(const Op &op, const TV *x, const TV *xT, TV *y, int batch, h
     const unsigned chunks = unsigned((batch + BC - 1) / BC);
     k_fwd<TM, TV, W, BC, BW><<<dim3(unsigned(g), chunks), 64 * W, 0, s>>>(
         op.fb, op.fb_order, op.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
-        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, y, op.n, op.nn, op.rows, batch);
+        static_cast<const TM *>(op.f_v1), op.f_edge, x, xT ? xT : x, y, op.n, op.nn, op.rows, batch);
 }
 
 template <class TM, class TV, int BC, int BW>
@@ -113,7 +115,7 @@ inline void fwd_band_wbc(const Op &op, const BandSet &bs, const TV *x, const TV 
     k_ticket_reset<<<1, 64, 0, s>>>(tickets);
     k_fwd_band<TM, TV, W, BC, BW><<<dim3(unsigned(g), 1u), 64 * W, 0, s>>>(
         op.fb, bs.order, bs.n_order, op.f_idx, static_cast<const TM *>(op.f_v0),
-        static_cast<const TM *>(op.f_v1), x, xT ? xT : x, part, op.n, op.nn, op.rows, bs.n_bands,
+        static_cast<const TM *>(op.f_v1), op.f_edge, x, xT ? xT : x, part, op.n, op.nn, op.rows, bs.n_bands,
         bs.lines, batch, tickets);
     k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(batch)), 256, 0, s>>>(
         op.fb, part, y, op.rows, op.n_bins, op.bmap, bs.n_bands, bs.lines);
@@ -151,14 +153,14 @@ inline void fwd_pm_launch(const Op &op, const BandSet *bs, const TV *xp, const T
         const int64_t g = bs->n_order < kPersistentBlocks ? (bs->n_order + 7) / 8 * 8 : kPersistentBlocks;
         k_ticket_reset<<<1, 64, 0, s>>>(tickets);
         k_fwd_pm_band<TM, TV, W, C, BW><<<unsigned(g), 64 * W, 0, s>>>(
-            op.fb, bs->order, bs->n_order, op.f_idx, v0, v1, xp, xpT, part, op.n, op.rows, bs->n_bands,
+            op.fb, bs->order, bs->n_order, op.f_idx, v0, v1, op.f_edge, xp, xpT, part, op.n, op.rows, bs->n_bands,
             bs->lines, nb, tickets);
         k_fwd_band_sum<TV><<<dim3(unsigned((op.rows + 255) / 256), unsigned(nb)), 256, 0, s>>>(
             op.fb, part, y, op.rows, op.n_bins, op.bmap, bs->n_bands, bs->lines);
     } else {
         const int64_t g = op.n_order < kPersistentBlocks ? op.n_order : kPersistentBlocks;
         k_fwd_pm<TM, TV, W, C, BW><<<unsigned(g), 64 * W, 0, s>>>(op.fb, op.fb_order, op.n_order, op.f_idx,
-                                                                  v0, v1, xp, xpT, y, op.n, op.rows, nb);
+                                                                  v0, v1, op.f_edge, xp, xpT, y, op.n, op.rows, nb);
     }
 }
 

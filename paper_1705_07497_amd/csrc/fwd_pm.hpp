@@ -105,11 +105,13 @@ __device__ __forceinline__ V group_bcast(const V &v)
 // (PAIR as in fwd_quads).  The GL lanes of a (q, r) group load GL
 // consecutive quads of ray r with one set of stream loads and hand each
 // quad's slots to the whole group, so every matrix entry is loaded once; a
-// quad past s1 gets zero weights (in-bounds gathers, no branch).
-template <class TM, class TV, int C, bool PAIR, int BW>
+// quad past s1 gets zero lengths (in-bounds gathers, no branch).  The group's
+// lanes share ray r, so each derives the second lengths from its own ev.
+template <class TM, class TV, int C, bool PAIR, bool COMPACT, int BW>
 __device__ __forceinline__ void pm_quads(const FwdBundle &d, const u16x4 *__restrict__ I,
                                          const typename Quad<TM>::type *__restrict__ A,
                                          const typename Quad<TM>::type *__restrict__ Bv,
+                                         const EdgeV<TV> &ev,
                                          const typename Vec16<TV>::type *__restrict__ xp, int n,
                                          int s0, int s1, int q, int r, int gl,
                                          TV (&acc)[PmShape<TV, C, BW>::IQ][PmShape<TV, C, BW>::VW])
@@ -122,21 +124,30 @@ __device__ __forceinline__ void pm_quads(const FwdBundle &d, const u16x4 *__rest
         const int e = (live ? tq + gl : tq) * BW + r;
         const u16x4 i4 = stream_load(I + e);
         Qv a4 = stream_load(A + e);
-        Qv b4 = stream_load(Bv + e);
         a4 = live ? a4 : Qv(0);
-        b4 = live ? b4 : Qv(0);
+        Qv b4;
+        if constexpr (!COMPACT) {
+            b4 = stream_load(Bv + e);
+            b4 = live ? b4 : Qv(0);
+        }
         StaticFor<0, S::GL>::run([&](auto jc) {
             constexpr int J = decltype(jc)::value;
             const u16x4 ij = group_bcast<S::GL, J>(i4);
             const Qv aj = group_bcast<S::GL, J>(a4);
-            const Qv bj = group_bcast<S::GL, J>(b4);
+            Qv bj;
+            if constexpr (!COMPACT) bj = group_bcast<S::GL, J>(b4);
+            const bool live_j = tq + J < s1;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int m = min(d.m0 + 4 * (tq + J) + k, n - 1);
+                const int mu = d.m0 + 4 * (tq + J) + k;
+                const int m = min(mu, n - 1);
                 const int i0 = ij[k];
                 const int ic = PAIR ? (i0 < n - 1 ? i0 : n - 2) : 0;
                 const V *__restrict__ p = xp + (int64_t(m) * n + ic) * S::NG + gl;
-                const TV a = TV(aj[k]), b = TV(bj[k]);
+                const TV a = TV(aj[k]);
+                TV b;
+                if constexpr (COMPACT) b = PAIR && live_j && i0 == ic ? second_len(ev, mu, a) : TV(0);
+                else b = TV(bj[k]);
 #pragma unroll
                 for (int iq = 0; iq < S::IQ; ++iq) {
                     const V u = p[iq * S::GL];
@@ -165,6 +176,7 @@ __device__ __forceinline__ void pm_quads(const FwdBundle &d, const u16x4 *__rest
 template <class TM, class TV, int W, int C, int BW>
 __device__ __forceinline__ void pm_bundle(const FwdBundle &d, const uint16_t *__restrict__ idx,
                                           const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                          const RayEdge *__restrict__ edge,
                                           const TV *__restrict__ xp, TV *__restrict__ y, int n,
                                           int64_t ystride, int nbc, int tq0 = 0, int tq1 = -1)
 {
@@ -177,17 +189,27 @@ __device__ __forceinline__ void pm_bundle(const FwdBundle &d, const uint16_t *__
     const int s0 = tq0 + (nq * wave) / W, s1 = tq0 + (nq * (wave + 1)) / W;
     const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
     const Qv *__restrict__ A = reinterpret_cast<const Qv *>(v0 + d.off);
-    const Qv *__restrict__ Bv = reinterpret_cast<const Qv *>(v1 + d.off);
+    const int64_t ray = bundle_ray(d, r);
     const V *__restrict__ xv = reinterpret_cast<const V *>(xp);
     TV acc[S::IQ][S::VW];
 #pragma unroll
     for (int iq = 0; iq < S::IQ; ++iq)
 #pragma unroll
         for (int v = 0; v < S::VW; ++v) acc[iq][v] = TV(0);
-    if (n >= 2)
-        pm_quads<TM, TV, C, true, BW>(d, I, A, Bv, xv, n, s0, s1, q, r, gl, acc);
-    else
-        pm_quads<TM, TV, C, false, BW>(d, I, A, Bv, xv, n, s0, s1, q, r, gl, acc);
+    if (v1) {   // both lengths stored
+        const Qv *__restrict__ Bv = reinterpret_cast<const Qv *>(v1 + d.off);
+        const EdgeV<TV> ev{};
+        if (n >= 2)
+            pm_quads<TM, TV, C, true, false, BW>(d, I, A, Bv, ev, xv, n, s0, s1, q, r, gl, acc);
+        else
+            pm_quads<TM, TV, C, false, false, BW>(d, I, A, Bv, ev, xv, n, s0, s1, q, r, gl, acc);
+    } else {    // compact: second lengths from the ray's chord
+        const EdgeV<TV> ev = load_edge<TV>(edge, ray);
+        if (n >= 2)
+            pm_quads<TM, TV, C, true, true, BW>(d, I, A, nullptr, ev, xv, n, s0, s1, q, r, gl, acc);
+        else
+            pm_quads<TM, TV, C, false, true, BW>(d, I, A, nullptr, ev, xv, n, s0, s1, q, r, gl, acc);
+    }
 #pragma unroll
     for (int iq = 0; iq < S::IQ; ++iq)
 #pragma unroll
@@ -216,7 +238,6 @@ __device__ __forceinline__ void pm_bundle(const FwdBundle &d, const uint16_t *__
         }
         __syncthreads();   // red is reused by the next bundle
     }
-    const int64_t ray = bundle_ray(d, r);
     if (wave == 0 && q == 0 && ray >= 0) {
 #pragma unroll
         for (int iq = 0; iq < S::IQ; ++iq)
@@ -234,6 +255,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_pm(const FwdBundle *__restrict__
                                                    const int32_t *__restrict__ order, int64_t n_order,
                                                    const uint16_t *__restrict__ idx,
                                                    const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                   const RayEdge *__restrict__ edge,
                                                    const TV *__restrict__ xp, const TV *__restrict__ xpT,
                                                    TV *__restrict__ y, int n, int64_t rows, int nbc)
 {
@@ -241,7 +263,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_pm(const FwdBundle *__restrict__
         const int B = order[o];
         if (B < 0) continue;           // padding entry (uniform per block)
         const FwdBundle d = fb[B];
-        pm_bundle<TM, TV, W, C, BW>(d, idx, v0, v1, d.horiz ? xpT : xp, y, n, rows, nbc);
+        pm_bundle<TM, TV, W, C, BW>(d, idx, v0, v1, edge, d.horiz ? xpT : xp, y, n, rows, nbc);
     }
 }
 
@@ -256,6 +278,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_pm_band(const FwdBundle *__restr
                                                         const uint16_t *__restrict__ idx,
                                                         const TM *__restrict__ v0,
                                                         const TM *__restrict__ v1,
+                                                        const RayEdge *__restrict__ edge,
                                                         const TV *__restrict__ xp,
                                                         const TV *__restrict__ xpT, TV *__restrict__ part,
                                                         int n, int64_t rows, int n_bands, int lines,
@@ -278,7 +301,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd_pm_band(const FwdBundle *__restr
         const int lo = it.y * lines - d.m0, hi = lo + lines;
         const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
         const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
-        pm_bundle<TM, TV, W, C, BW>(d, idx, v0, v1, d.horiz ? xpT : xp, part + int64_t(it.y) * rows, n,
+        pm_bundle<TM, TV, W, C, BW>(d, idx, v0, v1, edge, d.horiz ? xpT : xp, part + int64_t(it.y) * rows, n,
                                     stride, nbc, tq0, tq1);
     }
 }

@@ -18,8 +18,18 @@ namespace sct {
 // chosen when the operator is built).  Lane r of a bundle is angle r / R, bin
 // r % R.  Slot (t, r) covers lane r's ray on image line m0 + t along the
 // rays' major axis (rows for rays closer to vertical, columns for rays closer
-// to horizontal).  Slots are grouped in quads of 4 consecutive lines of one
-// ray so that a lane reads 4 slots with one 16-byte load:
+// to horizontal): the first of the (at most two adjacent) pixels the ray
+// meets on that line, the ray's length in it and its length in the second.
+// A compact operator does not store the second length: on a line the ray
+// crosses from one side to the other the two lengths add up to the same
+// chord on every such line (1/|cos| or 1/|sin| of the angle), so the second
+// is that chord minus the first; only the ray's first and last lines can be
+// crossed in part (where it enters or leaves the image), and their second
+// lengths are kept per ray (RayEdge).  Its forward then uses, for the FP32
+// matrix, second lengths within about one FP32 rounding of the chord of the
+// stored (CSR) ones; the CSR and the adjoint keep the stored values.
+// Slots are grouped in quads of 4 consecutive lines of one ray so that a
+// lane reads 4 slots with one 16-byte load:
 //   slot(t, r) = off + ((t/4)*BW + r)*4 + t%4.
 // A wave's 64 lanes cover BW rays and 64/BW consecutive quads, so one gather
 // instruction reads the BW rays on each of 64/BW image lines.  The rays of
@@ -88,6 +98,16 @@ struct FwdBundle {
 };
 static_assert(sizeof(FwdBundle) == 32, "FwdBundle layout");
 
+// Per measured ray: its chord on a fully crossed major line (the sum of its
+// two lengths there, from the build's own lengths), its first and last major
+// lines and the second lengths on those two (rounded to the matrix type).  A
+// ray without pixels has mf > ml.
+struct RayEdge {
+    double chord, w1f, w1l;
+    int32_t mf, ml;
+};
+static_assert(sizeof(RayEdge) == 32, "RayEdge layout");
+
 // Measured ray of lane r of bundle d, or -1 for a lane without a ray.
 __host__ __device__ inline int64_t bundle_ray(const FwdBundle &d, int r)
 {
@@ -152,7 +172,10 @@ struct Op {
     int32_t *fb_order = nullptr;     // block -> bundle (-1: idle), XCD-aware
     int64_t n_order = 0;
     uint16_t *f_idx = nullptr;
-    void *f_v0 = nullptr, *f_v1 = nullptr;
+    bool compact = false;            // forward derives the second lengths (no f_v1)
+    void *f_v0 = nullptr;            // first lengths, per slot
+    void *f_v1 = nullptr;            // second lengths, per slot (nullptr when compact)
+    RayEdge *f_edge = nullptr;       // per measured ray
 
     // adjoint pixel-group layout (device)
     int64_t n_ag = 0, a_slots = 0;

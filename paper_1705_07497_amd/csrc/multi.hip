@@ -24,6 +24,7 @@ struct MultiInst {
     const FwdBundle *fb;
     const uint16_t *f_idx;
     const void *f_v0, *f_v1;
+    const RayEdge *f_edge;
     const uint8_t *a_rel;
     const uint16_t *a_base;
     const void *a_v0, *a_v1;
@@ -139,14 +140,14 @@ __global__ __launch_bounds__(64 * W) void k_multi_fwd(const int2 *__restrict__ w
                 const int tq0 = lo <= 0 ? 0 : min(nq, (lo + 3) >> 2);
                 const int tq1 = hi <= 0 ? 0 : min(nq, (hi + 3) >> 2);
                 fwd_bundle<TM, TV, W, 1, BW>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
-                                             static_cast<const TM *>(I.f_v1),
+                                             static_cast<const TM *>(I.f_v1), I.f_edge,
                                              (d.horiz ? xT : x) + I.img_off,
                                              part + I.part_off + int64_t(band) * I.rows, I.n, I.nn,
                                              I.rows, 1, tq0, tq1);
             } else {
                 const FwdBundle d = I.fb[w.y];
                 fwd_bundle<TM, TV, W, 1, BW>(d, I.f_idx, static_cast<const TM *>(I.f_v0),
-                                             static_cast<const TM *>(I.f_v1),
+                                             static_cast<const TM *>(I.f_v1), I.f_edge,
                                              (d.horiz ? xT : x) + I.img_off, y + I.sino_off, I.n,
                                              I.nn, I.rows, 1);
             }
@@ -681,6 +682,7 @@ static int plan_multi(Multi &m, const radon_op *const *ops, int count, const dou
         I.f_idx = op.f_idx;
         I.f_v0 = op.f_v0;
         I.f_v1 = op.f_v1;
+        I.f_edge = op.f_edge;
         I.a_rel = op.a_rel;
         I.a_base = op.a_base;
         I.a_v0 = op.a_v0;

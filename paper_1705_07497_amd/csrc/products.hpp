@@ -53,6 +53,44 @@ __device__ inline V stream_load(const V *p)
     return __builtin_nontemporal_load(p);
 }
 
+// A lane's ray, for the second lengths of its slots (RayEdge in the vector
+// type; a lane without a ray gets mf > ml, so every second length is 0).
+template <class TV>
+struct EdgeV {
+    TV chord, w1f, w1l;
+    int mf, ml;
+};
+
+template <class TV>
+__device__ __forceinline__ EdgeV<TV> load_edge(const RayEdge *__restrict__ edge, int64_t ray)
+{
+    EdgeV<TV> v;
+    v.chord = v.w1f = v.w1l = TV(0);
+    v.mf = 1;
+    v.ml = 0;
+    if (ray >= 0) {
+        const RayEdge e = edge[ray];
+        v.chord = TV(e.chord);
+        v.w1f = TV(e.w1f);
+        v.w1l = TV(e.w1l);
+        v.mf = e.mf;
+        v.ml = e.ml;
+    }
+    return v;
+}
+
+// Length in the second pixel of the slot on major line mu (unclamped) whose
+// first length is w0: the chord minus w0 on the lines the ray crosses from
+// side to side, the stored value on its first and last lines, 0 outside.
+template <class TV>
+__device__ __forceinline__ TV second_len(const EdgeV<TV> &e, int mu, TV w0)
+{
+    TV w = e.chord - w0;
+    w = mu == e.mf ? e.w1f : w;
+    w = mu == e.ml ? e.w1l : w;
+    return (mu < e.mf || mu > e.ml) ? TV(0) : w;
+}
+
 // One workgroup of W waves per ray bundle (block -> bundle through `order`,
 // which places bundles of rays closer to vertical and closer to horizontal on
 // different XCDs, so each XCD's L2 caches only x or only its transpose).
@@ -66,15 +104,16 @@ __device__ inline V stream_load(const V *p)
 // share every matrix load (the fused multi-RHS product), one accumulator each.
 // The quads of wave shares [s0, s1) of one bundle for up to BC images.
 // PAIR (n >= 2): one 16-byte load fetches both pixels of a slot; a slot at
-// the last column has no second pixel (weight 0), so its pair starts at n-2.
+// the last column has no second pixel (its second length is 0), so its pair
+// starts at n-2.
 // The test is a template parameter so that the loop body has no branch: a
 // branch around each gather makes every gather wait for all loads in flight.
-template <class TM, class TV, int BC, bool PAIR, int BW>
+template <class TM, class TV, int BC, bool PAIR, bool COMPACT, int BW>
 __device__ __forceinline__ void fwd_quads(const FwdBundle &d, const u16x4 *__restrict__ I,
                                           const typename Quad<TM>::type *__restrict__ A,
                                           const typename Quad<TM>::type *__restrict__ Bv,
-                                          const TV *__restrict__ img, int n, int64_t nn, int nbc,
-                                          int s0, int s1, int q, int r, TV *acc)
+                                          const EdgeV<TV> &ev, const TV *__restrict__ img, int n,
+                                          int64_t nn, int nbc, int s0, int s1, int q, int r, TV *acc)
 {
     using Q = typename Quad<TM>::type;
     using P = typename PairU<TV>::type;
@@ -84,23 +123,29 @@ __device__ __forceinline__ void fwd_quads(const FwdBundle &d, const u16x4 *__res
         const int e = tq * BW + r;
         const u16x4 i4 = stream_load(I + e);
         const Q a4 = stream_load(A + e);
-        const Q b4 = stream_load(Bv + e);
+        Q b4;
+        if constexpr (!COMPACT) b4 = stream_load(Bv + e);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int m = min(d.m0 + 4 * tq + k, n - 1);
+            const int mu = d.m0 + 4 * tq + k;
+            const int m = min(mu, n - 1);
             const int i0 = i4[k];
             const int ic = PAIR ? (i0 < n - 1 ? i0 : n - 2) : 0;
             const int64_t at = int64_t(m) * n + ic;
+            const TV a = TV(a4[k]);
+            TV b;
+            if constexpr (COMPACT) b = PAIR && i0 == ic ? second_len(ev, mu, a) : TV(0);
+            else b = TV(b4[k]);
 #pragma unroll
             for (int c = 0; c < BC; ++c) {
                 if (BC == 1 || c < nbc) {
                     const TV *__restrict__ line = img + int64_t(c) * nn;
                     if constexpr (PAIR) {
                         const P pr = *reinterpret_cast<const P *>(line + at);
-                        acc[c] = fma(TV(a4[k]), i0 == ic ? pr.x : pr.y, acc[c]);
-                        acc[c] = fma(TV(b4[k]), pr.y, acc[c]);
+                        acc[c] = fma(a, i0 == ic ? pr.x : pr.y, acc[c]);
+                        acc[c] = fma(b, pr.y, acc[c]);
                     } else {
-                        acc[c] = fma(TV(a4[k]), line[0], acc[c]);
+                        acc[c] = fma(a, line[0], acc[c]);
                     }
                 }
             }
@@ -116,6 +161,7 @@ __device__ __forceinline__ void fwd_quads(const FwdBundle &d, const u16x4 *__res
 template <class TM, class TV, int W, int BC, int BW>
 __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *__restrict__ idx,
                                            const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                           const RayEdge *__restrict__ edge,
                                            const TV *__restrict__ img, TV *__restrict__ y, int n,
                                            int64_t nn, int64_t rows, int nbc, int tq0 = 0,
                                            int tq1 = -1)
@@ -129,14 +175,24 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
     const int s0 = tq0 + (nq * wave) / W, s1 = tq0 + (nq * (wave + 1)) / W;
     const u16x4 *__restrict__ I = reinterpret_cast<const u16x4 *>(idx + d.off);
     const Q *__restrict__ A = reinterpret_cast<const Q *>(v0 + d.off);
-    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
+    const int64_t ray = bundle_ray(d, r);
     TV acc[BC];
 #pragma unroll
     for (int c = 0; c < BC; ++c) acc[c] = TV(0);
-    if (n >= 2)
-        fwd_quads<TM, TV, BC, true, BW>(d, I, A, Bv, img, n, nn, nbc, s0, s1, q, r, acc);
-    else
-        fwd_quads<TM, TV, BC, false, BW>(d, I, A, Bv, img, n, nn, nbc, s0, s1, q, r, acc);
+    if (v1) {   // both lengths stored
+        const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1 + d.off);
+        const EdgeV<TV> ev{};
+        if (n >= 2)
+            fwd_quads<TM, TV, BC, true, false, BW>(d, I, A, Bv, ev, img, n, nn, nbc, s0, s1, q, r, acc);
+        else
+            fwd_quads<TM, TV, BC, false, false, BW>(d, I, A, Bv, ev, img, n, nn, nbc, s0, s1, q, r, acc);
+    } else {    // compact: second lengths from the ray's chord
+        const EdgeV<TV> ev = load_edge<TV>(edge, ray);
+        if (n >= 2)
+            fwd_quads<TM, TV, BC, true, true, BW>(d, I, A, nullptr, ev, img, n, nn, nbc, s0, s1, q, r, acc);
+        else
+            fwd_quads<TM, TV, BC, false, true, BW>(d, I, A, nullptr, ev, img, n, nn, nbc, s0, s1, q, r, acc);
+    }
 #pragma unroll
     for (int c = 0; c < BC; ++c) {
 #pragma unroll
@@ -159,7 +215,6 @@ __device__ __forceinline__ void fwd_bundle(const FwdBundle &d, const uint16_t *_
         }
         __syncthreads();   // red is reused by the next bundle
     }
-    const int64_t ray = bundle_ray(d, r);
     if (wave == 0 && q == 0 && ray >= 0) {
 #pragma unroll
         for (int c = 0; c < BC; ++c)

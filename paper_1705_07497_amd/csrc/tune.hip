@@ -33,10 +33,10 @@ static int tune_key(const Op &op, int batch, std::string *key)
             h *= 1099511628211ull;
         }
     }
-    // the bundle layout: width, and angles per bundle when more than one
+    // the bundle layout: width, angles per bundle when more than one, c when compact
     char lay[32];
-    if (op.bang > 1) snprintf(lay, sizeof lay, "bw%da%d", op.bw, op.bang);
-    else snprintf(lay, sizeof lay, "bw%d", op.bw);
+    if (op.bang > 1) snprintf(lay, sizeof lay, "bw%da%d%s", op.bw, op.bang, op.compact ? "c" : "");
+    else snprintf(lay, sizeof lay, "bw%d%s", op.bw, op.compact ? "c" : "");
     char buf[256];
     snprintf(buf, sizeof buf, "%s|n%d|a%d|b%d|m%016llx|k%d|%s|B%d", arch.c_str(), op.n, op.n_angles,
              op.n_bins, (unsigned long long)h, op.dtype, lay, batch);

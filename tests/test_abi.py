@@ -51,19 +51,19 @@ def test_header_constants_match_binding():
     assert int(consts["RADON_LAYOUT_PIXEL"]) == sct.LAYOUT_PIXEL
     hexes = dict(re.findall(r"#define\s+(\w+)\s+0x([0-9a-fA-F]+)", text))
     assert int(hexes["RADON_WS_PIXEL_LAYOUT"], 16) == sct.WS_PIXEL_LAYOUT
-    assert ctypes.sizeof(sct._Geom) == 32
+    assert ctypes.sizeof(sct._Geom) == 40
     assert ctypes.sizeof(sct.RadonSizes) == 72
     assert ctypes.sizeof(sct.RadonBuffers) == 80
     assert ctypes.sizeof(sct.Tuning) == 32
 
 
-def _build(n, na, nb, dtype=0, measured=None, bundle=0, angles=0):
+def _build(n, na, nb, dtype=0, measured=None, bundle=0, angles=0, compact=0, reserved=0):
     L = sct.lib()
     m = None
     if measured is not None:
         arr = (ctypes.c_uint8 * len(measured))(*measured)
         m = ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint8))
-    g = sct._Geom(n, na, nb, dtype, m, bundle, angles)
+    g = sct._Geom(n, na, nb, dtype, m, bundle, angles, compact, reserved)
     h = ctypes.c_void_p()
     rc = L.build_radon_csr(ctypes.byref(g), None, ctypes.byref(h))
     return rc, L.radon_last_error().decode()
@@ -92,6 +92,13 @@ def test_build_rejects_bad_geometry(args, code, frag):
 def test_build_rejects_bad_bundle_layout(bundle, angles, frag):
     rc, msg = _build(8, 4, 13, 0, None, bundle, angles)
     assert rc == -1 and frag in msg
+
+
+def test_build_rejects_bad_compact_flag_and_reserved():
+    rc, msg = _build(8, 4, 13, 0, None, 0, 0, 2)
+    assert rc == -1 and "fwd_compact" in msg
+    rc, msg = _build(8, 4, 13, 0, None, 0, 0, 0, 5)
+    assert rc == -1 and "reserved" in msg
 
 
 def test_build_rejects_no_measured_angle():

@@ -11,7 +11,10 @@ def test_geometry_key_distinguishes_geometry_mask_kind_and_arch():
     keys = {autotune.geometry_key("gfx950", 64, 10, 91, m, k) for m in (m1, m2) for k in (0, 2)}
     keys.add(autotune.geometry_key("gfx950", 65, 10, 91, m1, 0))
     keys.add(autotune.geometry_key("gfx942", 64, 10, 91, m1, 0))
-    assert len(keys) == 6
+    keys.add(autotune.geometry_key("gfx950", 64, 10, 91, m1, 0, compact=True))
+    assert len(keys) == 7
+    assert autotune.geometry_key("gfx950", 64, 10, 91, m1, 0) == \
+        autotune.geometry_key("gfx950", 64, 10, 91, m1, 0, compact=False)
 
 
 def test_bundle_cache_roundtrip_last_line_wins_and_foreign_lines_ignored(tmp_path):

@@ -11,7 +11,11 @@
   images, line-banded forward with per-image band partials) over all 64
   slices, with three slices (first, middle, last chunk) compared element by
   element against the oracle's per-slice products; for the default chunking
-  (4 images per forward chunk, 8 per adjoint chunk) and for 16-image chunks.
+  (4 images per forward chunk, 8 per adjoint chunk), for 16-image chunks,
+  and for the compact forward layout of 32 rays over 2 angles gathering from
+  pixel-major chunk copies.
+* Both large workloads also run with the compact forward layout (one stored
+  length per ray and line, the second derived from the ray's chord).
 
 The oracle is the plain FP64 one (exact Siddon entries), so the tolerance
 1e-5 covers the single rounding of the GPU's FP32 matrix entries as well as
@@ -53,10 +57,20 @@ def test_large_2048_normal_and_split_bregman_30x10():
     err_n = rel_l2(got, want)
     say(f"large_2048: normal operator rel L2 = {err_n:.3e}")
     assert err_n <= 1e-5
+    # and with the compact forward layout, 64 rays over 2 angles
+    opc = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=F64,
+                      tuning="default", bundle=64, bundle_angles=2, compact=True)
+    got_c = host(opc.normal(to_dev(mu[None], F64), w.alpha, w.lam))[0]
+    err_nc = rel_l2(got_c, want)
+    say(f"large_2048: normal operator, compact layout, rel L2 = {err_nc:.3e}")
+    assert err_nc <= 1e-5
     say("large_2048: split Bregman 30x10 on the GPU")
     u, info = op.sb(to_dev(f[None], F64), w.alpha, w.lam, w.n_outer, w.n_cg)
     uh = host(u)[0]
     assert sct.decode_sb_info(info)[0]["outer"] == w.n_outer
+    uc, _ = opc.sb(to_dev(f[None], F64), w.alpha, w.lam, w.n_outer, w.n_cg)
+    uch = host(uc)[0]
+    del opc
     # the oracle runs the 30 outer iterations as three resumed runs of 10
     # (resuming is bitwise the same as one run), printing between them
     uo, st, done = None, None, 0
@@ -66,14 +80,17 @@ def test_large_2048_normal_and_split_bregman_30x10():
         uo, _, _, _, st = ref.sb(f, w.alpha, w.lam, k, w.n_cg, u0=uo, state=st)
         done += k
     err = rel_l2(uh, uo)
-    say(f"large_2048: split Bregman rel L2 = {err:.3e}")
+    err_c = rel_l2(uch, uo)
+    say(f"large_2048: split Bregman rel L2 = {err:.3e}, compact layout {err_c:.3e}")
     assert err <= 1e-5
+    assert err_c <= 1e-5
 
 
 @pytest.mark.parametrize("chunks,bundle,vec", [(None, 16, "f64"), ((16, 16), 16, "f64"),
-                                               ((16, 16), 64, "f32"), ((8, 8), 32, "f32")],
+                                               ((16, 16), 64, "f32"), ((8, 8), 32, "f32"),
+                                               ((16, 16), (32, 2, True), "f32")],
                          ids=["default_chunks", "chunks16", "f32_chunks16_bundle64",
-                              "f32_chunks8_bundle32"])
+                              "f32_chunks8_bundle32", "f32_chunks16_compact_32x2_pixel_major"])
 def test_volume_64x1024_fused_normal_slices(chunks, bundle, vec):
     """FP64 vectors (the mixed kind) and FP32 vectors (the pure FP32 kind the
     benchmark's volume leg times); the FP32 kind's inputs are the phantoms
@@ -83,10 +100,15 @@ def test_volume_64x1024_fused_normal_slices(chunks, bundle, vec):
     say(f"volume_64x1024 {chunks} {bundle} {vec}: oracle build (FP64 entries)")
     ref = _volume_oracle(w)
     say(f"volume_64x1024 {chunks} {bundle} {vec}: gpu build and {w.batch} phantoms")
-    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
-                     tuning="default", bundle=bundle)
-    if chunks is not None:
-        op.tuning = {"fwd_rhs": chunks[0], "adj_rhs": chunks[1]}
+    if isinstance(bundle, tuple):   # (rays, angles, compact), gathering from pixel-major chunks
+        op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                         tuning="default", bundle=bundle[0], bundle_angles=bundle[1], compact=bundle[2])
+        op.tuning = {"fwd_rhs": chunks[0], "adj_rhs": chunks[1], "fwd_layout": 1, "adj_layout": 1}
+    else:
+        op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                         tuning="default", bundle=bundle)
+        if chunks is not None:
+            op.tuning = {"fwd_rhs": chunks[0], "adj_rhs": chunks[1]}
     X = np.stack([W.phantom(w.n, w.n_ellipses, seed=0, index=i) for i in range(w.batch)])
     if vec == "f32":
         X = X.astype(np.float32).astype(np.float64)

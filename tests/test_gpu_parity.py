@@ -316,14 +316,23 @@ def test_main_workload_normal_and_split_bregman():
     want = ref.normal(x, w.alpha, w.lam)
     assert rel_l2(host(op.normal(to_dev(x, F64), w.alpha, w.lam)), want) <= 1e-5
     assert rel_l2(host(op32.normal(to_dev(x, F32), w.alpha, w.lam)), want) <= 1e-5
+    # the compact forward layout of 64 rays over 2 angles at 4 waves per
+    # bundle, as the benchmark's tuned operator
+    opc = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=F32, vec_dtype=F64, tuning="default",
+                      bundle=64, bundle_angles=2, compact=True)
+    opc.tuning = {"fwd_waves": 4}
+    assert rel_l2(host(opc.normal(to_dev(x, F64), w.alpha, w.lam)), want) <= 1e-5
     fr = rounded(f, F32)
     say("gpu_512_f32: split Bregman 50x20 on the GPU")
     u, info = op.sb(to_dev(fr, F64), w.alpha, w.lam, w.n_outer, w.n_cg)
+    uc, _ = opc.sb(to_dev(fr, F64), w.alpha, w.lam, w.n_outer, w.n_cg)
     say("gpu_512_f32: split Bregman 50x20 on the oracle")
     uo = ref.sb(fr, w.alpha, w.lam, w.n_outer, w.n_cg)[0]
     err = rel_l2(host(u), uo)
-    say(f"gpu_512_f32: split Bregman rel L2 = {err:.3e}")
+    err_c = rel_l2(host(uc), uo)
+    say(f"gpu_512_f32: split Bregman rel L2 = {err:.3e}, compact layout {err_c:.3e}")
     assert err <= 1e-5
+    assert err_c <= 1e-5
 
 
 def test_large_workload_sampled_and_invariants():
