@@ -92,7 +92,12 @@ typedef struct {
     int32_t fwd_compact;        /* 1: the forward layout stores one length per
                                    slot and derives the second (see below); 0:
                                    both stored */
-    int32_t reserved;           /* must be 0 */
+    int32_t fwd_symmetric;      /* 1: the forward layout stores only the measured
+                                   angles in [0, pi/4] and serves the rays of
+                                   pi - theta, pi/2 - theta and pi/2 + theta from
+                                   them (see below); needs n >= 2, an even
+                                   n_angles and a measured set closed under
+                                   those maps */
 } radon_geom;
 
 typedef struct {
@@ -111,6 +116,7 @@ typedef struct {
     int32_t fwd_bundle;         /* rays per forward bundle (16, 32 or 64) */
     int32_t fwd_angles;         /* measured angles per forward bundle (1, 2 or 4) */
     int32_t fwd_compact;        /* 1: compact forward layout */
+    int32_t fwd_symmetric;      /* 1: forward layout stored by symmetry */
 } radon_info;
 
 /*
@@ -133,7 +139,11 @@ typedef struct {
  *     g->fwd_compact the second length is not stored: it is the ray's chord
  *     minus the first on every line the ray crosses from side to side (the
  *     two lengths add up to the same chord there), and is kept per ray for
- *     its first and last lines, the only ones it can cross in part;
+ *     its first and last lines, the only ones it can cross in part.  With
+ *     g->fwd_symmetric only the rays of the measured angles in [0, pi/4]
+ *     have slots: the rays of pi - theta, pi/2 - theta and pi/2 + theta with
+ *     the same bin are their images under x -> -x, the transpose and both,
+ *     and the forward reads their lengths from the stored ray's slots;
  *   - a pixel-group layout of (MR)^T for the adjoint: groups of 64 pixels,
  *     one slot per (pixel, measured angle) holding the first bin crossing
  *     the pixel (uint16) and the lengths for that bin and the next one (a
@@ -150,8 +160,9 @@ typedef struct {
  * Errors: RADON_EINVAL (geometry out of range), RADON_EOVERFLOW (nnz or a
  * layout needs >= 2^31 entries per index type it uses), RADON_EUNSUPPORTED
  * (fwd_angles > 1 and the measured angles fall into more than four runs of
- * one gather class, which angles in index order never do; or a layout
- * assumption above failed for some ray), RADON_EHIP.
+ * one gather class, which angles in index order never do; fwd_symmetric and
+ * the measured set is not closed under the maps above, or n_angles is odd;
+ * or a layout assumption above failed for some ray), RADON_EHIP.
  */
 int build_radon_csr(const radon_geom *g, void *stream, radon_op **out);
 

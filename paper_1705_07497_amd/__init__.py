@@ -40,7 +40,7 @@ class _Geom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("measured", ctypes.POINTER(ctypes.c_uint8)),
                 ("fwd_bundle", ctypes.c_int32), ("fwd_angles", ctypes.c_int32),
-                ("fwd_compact", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fwd_compact", ctypes.c_int32), ("fwd_symmetric", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -50,7 +50,8 @@ class _Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("dtype", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
                 ("needs_transpose", ctypes.c_int32), ("fwd_bundle", ctypes.c_int32),
-                ("fwd_angles", ctypes.c_int32), ("fwd_compact", ctypes.c_int32)]
+                ("fwd_angles", ctypes.c_int32), ("fwd_compact", ctypes.c_int32),
+                ("fwd_symmetric", ctypes.c_int32)]
 
 
 class RadonSizes(ctypes.Structure):
@@ -255,14 +256,18 @@ class RadonOp:
     compact=True builds the compact forward layout: one stored length per
     (ray, line), the second derived from the ray's chord (within about one
     rounding of the matrix type of the stored value; the CSR and the adjoint
-    keep the stored values).
+    keep the stored values).  symmetric=True stores only the measured angles
+    in [0, pi/4] in the forward layout and serves their mirror and transpose
+    partners from them (the measured set must be closed under theta ->
+    pi - theta and theta -> pi/2 - theta).
     tuning: "cache" applies cached launch settings for tune_batch images,
     "tune" chooses the bundle layout and times the launch settings now (and
     caches both), "default" leaves the library defaults."""
 
     def __init__(self, n: int, n_angles: int, n_bins: int, measured=None, dtype=None, device=None,
                  vec_dtype=None, tuning: str = "cache", storage: str = "library", bundle: int = 0,
-                 tune_batch: int = 1, bundle_angles: int = 0, compact: bool = False):
+                 tune_batch: int = 1, bundle_angles: int = 0, compact: bool = False,
+                 symmetric: bool = False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise SparsectError("no GPU visible: libsparsect runs on AMD Instinct GPUs only")
@@ -293,15 +298,16 @@ class RadonOp:
             if tuning == "tune":
                 ch = autotune.choose_bundle(self.n, self.n_angles, self.n_bins, self.measured,
                                             dtype, vec_dtype, self.device, batch=tune_batch,
-                                            compact=compact)
+                                            compact=compact, symmetric=symmetric)
                 bundle, bundle_angles = ch["bundle"], ch["angles"]
             else:
                 bundle, bundle_angles = autotune.cached_bundle(self.n, self.n_angles, self.n_bins,
                                                                self.measured, self.kind,
-                                                               self.device, compact=compact) or (0, 0)
+                                                               self.device, compact=compact,
+                                                               symmetric=symmetric) or (0, 0)
         g = _Geom(self.n, self.n_angles, self.n_bins, self.kind,
                   self.measured.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(bundle),
-                  int(bundle_angles), 1 if compact else 0, 0)
+                  int(bundle_angles), 1 if compact else 0, 1 if symmetric else 0)
         h = _vp()
         self._storage = None
         with torch.cuda.device(self.device):
@@ -322,6 +328,7 @@ class RadonOp:
         self.bundle = int(inf.fwd_bundle)
         self.bundle_angles = int(inf.fwd_angles)
         self.compact = bool(inf.fwd_compact)
+        self.symmetric = bool(inf.fwd_symmetric)
         self._ws = {}
         if tuning == "cache":
             from . import autotune

@@ -43,11 +43,12 @@ def cache_path() -> str:
 
 
 def geometry_key(arch: str, n: int, n_angles: int, n_bins: int, measured, kind: int,
-                 compact: bool = False) -> str:
-    """Key of a geometry, operator kind and forward storage (compact or not;
-    no bundle layout, no batch)."""
+                 compact: bool = False, symmetric: bool = False) -> str:
+    """Key of a geometry, operator kind and forward storage (compact, stored by
+    symmetry; no bundle layout, no batch)."""
     mh = hashlib.sha1(bytes(bytearray(int(v) != 0 for v in measured))).hexdigest()[:12]
-    return f"{arch}|n{n}|a{n_angles}|b{n_bins}|m{mh}|k{kind}" + ("|c" if compact else "")
+    return (f"{arch}|n{n}|a{n_angles}|b{n_bins}|m{mh}|k{kind}" + ("|c" if compact else "")
+            + ("|s" if symmetric else ""))
 
 
 def load_bundles(path: str | None = None) -> dict:
@@ -81,9 +82,10 @@ def device_arch(device) -> str:
     return name.split(":")[0]
 
 
-def cached_bundle(n, n_angles, n_bins, measured, kind, device, path=None, compact=False) -> tuple | None:
+def cached_bundle(n, n_angles, n_bins, measured, kind, device, path=None, compact=False,
+                  symmetric=False) -> tuple | None:
     """(rays, angles) per bundle cached for this geometry, or None."""
-    key = geometry_key(device_arch(device), n, n_angles, n_bins, measured, kind, compact)
+    key = geometry_key(device_arch(device), n, n_angles, n_bins, measured, kind, compact, symmetric)
     return load_bundles(path).get(key)
 
 
@@ -125,8 +127,9 @@ def autotune(op, batch: int = 16, path: str | None = None, save: bool = True) ->
 
 def choose_bundle(n, n_angles, n_bins, measured=None, dtype=None, vec_dtype=None, device=None,
                   batch: int = 1, reps: int = 50, rounds: int = 3, path: str | None = None,
-                  save: bool = True, layouts=LAYOUTS, compact: bool = False) -> dict:
-    """Build the operator (compact forward storage or not) with each bundle
+                  save: bool = True, layouts=LAYOUTS, compact: bool = False, symmetric: bool = False) -> dict:
+    """Build the operator (forward storage compact and/or by symmetry, as
+    asked) with each bundle
     layout (rays, angles), tune its launch settings, time its normal operator
     at `batch` (the best of `rounds` runs of `reps` calls, so that a layout is
     not ranked on one noisy run) and return the fastest {"bundle": rays,
@@ -139,7 +142,7 @@ def choose_bundle(n, n_angles, n_bins, measured=None, dtype=None, vec_dtype=None
     kind = None
     for bw, ang in layouts:
         op = RadonOp(n, n_angles, n_bins, measured, dtype=dtype, device=device, vec_dtype=vec_dtype,
-                     tuning="default", bundle=bw, bundle_angles=ang, compact=compact)
+                     tuning="default", bundle=bw, bundle_angles=ang, compact=compact, symmetric=symmetric)
         kind, dev = op.kind, op.device
         autotune(op, batch=batch, save=False)
         x = torch.randn((batch, op.nn), dtype=op.dtype, device=op.device)
@@ -161,7 +164,7 @@ def choose_bundle(n, n_angles, n_bins, measured=None, dtype=None, vec_dtype=None
     best = min(times, key=times.get)
     if save:
         m = np.ones(n_angles, np.uint8) if measured is None else measured
-        store_bundle(geometry_key(device_arch(dev), n, n_angles, n_bins, m, kind, compact), best[0], best[1],
-                     path)
+        store_bundle(geometry_key(device_arch(dev), n, n_angles, n_bins, m, kind, compact, symmetric), best[0],
+                     best[1], path)
     return {"bundle": best[0], "angles": best[1],
             "normal_s": {f"{bw}x{ang}": t for (bw, ang), t in times.items()}}

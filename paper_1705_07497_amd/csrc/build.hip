@@ -299,7 +299,7 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
                            uint16_t *__restrict__ f_idx, T *__restrict__ f_v0, T *__restrict__ f_v1,
                            const int32_t *__restrict__ mlo, const int32_t *__restrict__ mhi,
                            const double *__restrict__ chord, RayEdge *__restrict__ f_edge,
-                           int32_t *__restrict__ bin_tmp, int32_t *__restrict__ bad)
+                           int n_stored, int32_t *__restrict__ bin_tmp, int32_t *__restrict__ bad)
 {
     const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ray >= rows) return;
@@ -307,8 +307,12 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
     const double c = cs[a].x, s = cs[a].y;
     const double sb = double(b) - 0.5 * double(nb - 1);
     const bool hz = is_horiz(c, s);
+    // rays of angles without bundles of their own (a symmetric operator's
+    // partners) get no slots
+    const bool slotted = a < n_stored;
     int r = 0;
-    const FwdBundle d = fb[bm.bundle_of(a, b, &r)];
+    FwdBundle d{};
+    if (slotted) d = fb[bm.bundle_of(a, b, &r)];
     const int mf = mlo[ray], ml = mhi[ray];
     const double ch = chord[ray];
     RayEdge e;
@@ -324,23 +328,26 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
     const int64_t oend = rp[ray + 1];
     auto flush = [&]() {
         if (cur < 0) return;
-        if (cur < d.m0 || cur >= d.m0 + d.nrows) {
+        if (slotted && (cur < d.m0 || cur >= d.m0 + d.nrows)) {
             atomicOr(bad, 16);
             return;
         }
-        const int64_t slot = fwd_slot(d.off, cur - d.m0, r, bw);
         T v1 = T(0);
-        if (nline == 1) {
-            f_idx[slot] = uint16_t(q0);
-            f_v0[slot] = w0;
-        } else {
+        int first = q0;
+        T v0 = w0;
+        if (nline != 1) {
             if (q1 != q0 + 1 && q0 != q1 + 1) atomicOr(bad, 1);
             const bool first0 = q0 < q1;
-            f_idx[slot] = uint16_t(first0 ? q0 : q1);
-            f_v0[slot] = first0 ? w0 : w1;
+            first = first0 ? q0 : q1;
+            v0 = first0 ? w0 : w1;
             v1 = first0 ? w1 : w0;
         }
-        if (f_v1) f_v1[slot] = v1;
+        if (slotted) {
+            const int64_t slot = fwd_slot(d.off, cur - d.m0, r, bw);
+            f_idx[slot] = uint16_t(first);
+            f_v0[slot] = v0;
+            if (f_v1) f_v1[slot] = v1;
+        }
         if (cur == mf) e.w1f = double(v1);
         if (cur == ml) e.w1l = double(v1);
         if (cur != mf && cur != ml && !(fabs(l0 + l1 - ch) <= kChordTol * ch)) atomicOr(bad, 32);
@@ -517,6 +524,7 @@ static int64_t layout_bytes(const Op &op, const Plan &pl)
     b += up256(int64_t(sizeof(FwdBundle)) * n_fb_of(op));
     b += up256(2 * pl.fslots) + (op.compact ? 1 : 2) * up256(es * pl.fslots);
     b += up256(int64_t(sizeof(RayEdge)) * op.rows);
+    if (op.sym) b += up256(16 * int64_t(op.n_rep));
     b += up256(op.a_slots) + up256(2 * op.n_ag * op.n_aq * 4) + 2 * up256(es * op.a_slots);
     b += up256(4 * int64_t(pl.order.size()));
     for (const auto &bo : pl.border) b += up256(8 * int64_t(bo.size()));
@@ -709,7 +717,7 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     k_ray_fill<T><<<g, blk, 0, st>>>(t.cs, n, nb, op.bmap, op.bw, rows, op.n_aq, op.tiles, op.rp, op.col,
                                      static_cast<T *>(op.val), op.fb, op.f_idx,
                                      static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), t.mlo, t.mhi,
-                                     t.chord, op.f_edge,
+                                     t.chord, op.f_edge, op.sym ? op.n_rep : op.n_meas,
                                      t.bin_tmp, t.bad);
     SCT_TRY(check_launch("k_ray_fill"));
     k_adj_fill<T><<<g, blk, 0, st>>>(n, nb, rows, op.n_aq, op.tiles, op.rp, op.col,
@@ -724,6 +732,9 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     SCT_TRY(check_launch("k_adj_finish"));
 
     SCT_HIP(hipMemcpyAsync(op.fb_order, pl.order.data(), 4 * pl.order.size(), hipMemcpyHostToDevice, st));
+    if (op.sym)
+        SCT_HIP(hipMemcpyAsync(op.f_partner, op.partner_host.data(), 16 * op.partner_host.size(),
+                               hipMemcpyHostToDevice, st));
     for (int h = 0; h < 4; ++h)
         if (op.bands[h].n_bands > 0)
             SCT_HIP(hipMemcpyAsync(op.bands[h].order, pl.border[h].data(), 8 * pl.border[h].size(),
@@ -752,6 +763,8 @@ static int carve_layouts(Op &op, const Plan &pl, Carve &lay, bool fb_taken)
     op.f_v1 = nullptr;
     if (!op.compact) SCT_TRY(lay.take(&op.f_v1, es * pl.fslots));
     SCT_TRY(lay.take(&op.f_edge, int64_t(sizeof(RayEdge)) * op.rows));
+    op.f_partner = nullptr;
+    if (op.sym) SCT_TRY(lay.take(&op.f_partner, 16 * int64_t(op.n_rep)));
     SCT_TRY(lay.take(&op.a_rel, op.a_slots));
     SCT_TRY(lay.take(&op.a_base, 2 * op.n_ag * op.n_aq * 4));
     SCT_TRY(lay.take(&op.a_v0, es * op.a_slots));
@@ -819,11 +832,12 @@ static int bundle_map(Op &op, const std::vector<double> &cs)
     m.nbpr = (op.n_bins + m.rpa - 1) / m.rpa;
     m.runs = 0;
     int groups = 0;
-    for (int a = 0; a < op.n_meas;) {
+    const int n_stored = op.sym ? op.n_rep : op.n_meas;   // angles with bundles of their own
+    for (int a = 0; a < n_stored;) {
         const bool hz = std::fabs(cs[2 * size_t(a) + 1]) > std::fabs(cs[2 * size_t(a)]);
         int e = a + 1;
         // with one angle per bundle the classes need no runs of their own
-        while (e < op.n_meas &&
+        while (e < n_stored &&
                (op.bang == 1 || (std::fabs(cs[2 * size_t(e) + 1]) > std::fabs(cs[2 * size_t(e)])) == hz))
             ++e;
         if (m.runs == kMaxAngleRuns)
@@ -835,8 +849,58 @@ static int bundle_map(Op &op, const std::vector<double> &cs)
         ++m.runs;
         a = e;
     }
-    m.start[m.runs] = op.n_meas;
+    m.start[m.runs] = n_stored;
     m.gbase[m.runs] = groups;
+    return RADON_OK;
+}
+
+// Storage by the symmetries of the square: the measured angles k (theta =
+// pi k / n_angles) with 4k <= n_angles are stored (a prefix of the measured
+// list, all closer to vertical); each stands for the measured angles of
+// pi - theta, pi/2 - theta and pi/2 + theta that are not itself or an
+// earlier partner.  Every measured angle must be stored or such a partner,
+// exactly once.
+static int symmetry_map(Op &op, const std::vector<double> &cs)
+{
+    const int na = op.n_angles;
+    std::vector<int32_t> pos(size_t(na), -1);   // angle index -> measured position
+    for (int a = 0; a < op.n_meas; ++a) pos[size_t(op.meas[size_t(a)])] = a;
+    std::vector<int> covered(size_t(op.n_meas), 0);
+    op.n_rep = 0;
+    op.partner_host.clear();
+    for (int a = 0; a < op.n_meas; ++a) {
+        const int k = op.meas[size_t(a)];
+        if (4 * int64_t(k) > na) break;
+        if (std::fabs(cs[2 * size_t(a) + 1]) > std::fabs(cs[2 * size_t(a)]))
+            return set_error(RADON_EUNSUPPORTED, "symmetric storage: angle %d of [0, pi/4] is closer to horizontal",
+                             k);
+        ++op.n_rep;
+        ++covered[size_t(a)];
+        // partner angle indices in [0, na): pi - theta (none for theta = 0:
+        // that is theta itself, with the bins mirrored), pi/2 - theta and
+        // pi/2 + theta, which need an even number of angles
+        int cand[3] = {k > 0 ? na - k : -1, (na % 2 == 0) ? na / 2 - k : -1, (na % 2 == 0) ? na / 2 + k : -1};
+        int got[3] = {-1, -1, -1};
+        for (int j = 0; j < 3; ++j) {
+            const int c = cand[j];
+            if (c < 0 || c >= na || c == k) continue;
+            bool dup = false;
+            for (int i = 0; i < j; ++i) dup = dup || cand[i] == c;
+            if (dup) continue;
+            const int pa = pos[size_t(c)];
+            if (pa < 0) continue;   // not measured: its rays are not in the operator
+            got[j] = pa;
+            ++covered[size_t(pa)];
+        }
+        op.partner_host.push_back(make_int4(got[0], got[1], got[2], -1));
+    }
+    if (na % 2 != 0) return set_error(RADON_EUNSUPPORTED, "symmetric storage needs an even number of angles");
+    for (int a = 0; a < op.n_meas; ++a)
+        if (covered[size_t(a)] != 1)
+            return set_error(RADON_EUNSUPPORTED,
+                             "symmetric storage: measured angle %d is %s (the measured angles must be closed "
+                             "under theta -> pi - theta and theta -> pi/2 - theta)",
+                             op.meas[size_t(a)], covered[size_t(a)] ? "covered twice" : "not covered");
     return RADON_OK;
 }
 
@@ -858,7 +922,9 @@ static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
     const int bw = g->fwd_bundle ? g->fwd_bundle : kFwdLanes;
     if (g->fwd_compact != 0 && g->fwd_compact != 1)
         return set_error(RADON_EINVAL, "fwd_compact must be 0 or 1 (got %d)", g->fwd_compact);
-    if (g->reserved != 0) return set_error(RADON_EINVAL, "reserved must be 0 (got %d)", g->reserved);
+    if (g->fwd_symmetric != 0 && g->fwd_symmetric != 1)
+        return set_error(RADON_EINVAL, "fwd_symmetric must be 0 or 1 (got %d)", g->fwd_symmetric);
+    if (g->fwd_symmetric && g->n < 2) return set_error(RADON_EINVAL, "fwd_symmetric needs n >= 2");
     if (g->fwd_angles != 0 && !valid_bundle_angles(g->fwd_angles, bw))
         return set_error(RADON_EINVAL,
                          "fwd_angles must be 0, 1, 2 or 4 with at least 16 rays per angle "
@@ -889,6 +955,7 @@ static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
     op->bw = bw;
     op->bang = g->fwd_angles ? g->fwd_angles : 1;
     op->compact = g->fwd_compact != 0;
+    op->sym = g->fwd_symmetric != 0;
     op->tiles = (op->n + 7) / 8;
     op->n_ag = int64_t(op->tiles) * op->tiles;
     op->n_aq = (op->n_meas + 3) / 4;
@@ -898,7 +965,8 @@ static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
         angle_cos_sin(meas[a], g->n_angles, &cs[2 * a], &cs[2 * a + 1]);
         if (std::fabs(cs[2 * a + 1]) > std::fabs(cs[2 * a])) op->need_T = true;
     }
-    const int rc = bundle_map(*op, cs);
+    int rc = op->sym ? symmetry_map(*op, cs) : RADON_OK;
+    if (rc == RADON_OK) rc = bundle_map(*op, cs);
     if (rc != RADON_OK) {
         delete op;
         return rc;
@@ -1090,7 +1158,7 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     return RADON_OK;
 }
 
-static_assert(sizeof(radon_geom) == 40 && sizeof(radon_info) == 88, "C ABI struct sizes");
+static_assert(sizeof(radon_geom) == 40 && sizeof(radon_info) == 96, "C ABI struct sizes");
 
 extern "C" void radon_op_destroy(radon_op *p) { op_free(as_op(p)); }
 
@@ -1115,6 +1183,7 @@ extern "C" int radon_op_info(const radon_op *p, radon_info *out)
     out->fwd_bundle = op->bw;
     out->fwd_angles = op->bang;
     out->fwd_compact = op->compact ? 1 : 0;
+    out->fwd_symmetric = op->sym ? 1 : 0;
     return RADON_OK;
 }
 

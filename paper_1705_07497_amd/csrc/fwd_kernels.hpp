@@ -5,6 +5,7 @@
 #pragma once
 
 #include "fwd_pm.hpp"
+#include "fwd_sym.hpp"
 
 namespace sct {
 
@@ -192,6 +193,7 @@ inline void fwd_pm_chunks(const Op &op, const BandSet *bs, const TV *x, TV *y, T
 template <class TM, class TV, int BW>
 int launch_fwd_bw(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStream_t s, TV *part)
 {
+    if (op.sym) return launch_fwd_sym<TM, TV, BW>(op, x, xT, y, batch, s);
     const int bc = fwd_rhs_chunk(batch, op.tune.fwd_rhs);
     const BandSet *bs = part ? band_set_for(op, bc) : nullptr;
     if (part && fwd_pixel_major(op.tune.fwd_layout, bc)) {

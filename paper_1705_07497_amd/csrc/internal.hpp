@@ -173,6 +173,13 @@ struct Op {
     int64_t n_order = 0;
     uint16_t *f_idx = nullptr;
     bool compact = false;            // forward derives the second lengths (no f_v1)
+    // stored by the symmetries of the square: bundles only for the first
+    // n_rep measured angles (theta in [0, pi/4]), each ray also standing for
+    // the rays of f_partner[a] (see fwd_sym.hpp)
+    bool sym = false;
+    int32_t n_rep = 0;
+    std::vector<int4> partner_host;
+    int4 *f_partner = nullptr;
     void *f_v0 = nullptr;            // first lengths, per slot
     void *f_v1 = nullptr;            // second lengths, per slot (nullptr when compact)
     RayEdge *f_edge = nullptr;       // per measured ray

@@ -766,6 +766,8 @@ static int check_group_ops(const radon_op *const *ops, int32_t count)
             return set_error(RADON_EINVAL, "operator %d has another dtype than operator 0", i);
         if (as_op(ops[i])->bw != as_op(ops[0])->bw)
             return set_error(RADON_EINVAL, "operator %d has another forward bundle width than operator 0", i);
+        if (as_op(ops[i])->sym)
+            return set_error(RADON_EUNSUPPORTED, "operator %d is stored by symmetry, which a group does not take", i);
     }
     return RADON_OK;
 }

@@ -33,10 +33,12 @@ static int tune_key(const Op &op, int batch, std::string *key)
             h *= 1099511628211ull;
         }
     }
-    // the bundle layout: width, angles per bundle when more than one, c when compact
+    // the bundle layout: width, angles per bundle when more than one, c when
+    // compact, s when stored by symmetry
     char lay[32];
-    if (op.bang > 1) snprintf(lay, sizeof lay, "bw%da%d%s", op.bw, op.bang, op.compact ? "c" : "");
-    else snprintf(lay, sizeof lay, "bw%d%s", op.bw, op.compact ? "c" : "");
+    const char *st = op.compact ? (op.sym ? "cs" : "c") : (op.sym ? "s" : "");
+    if (op.bang > 1) snprintf(lay, sizeof lay, "bw%da%d%s", op.bw, op.bang, st);
+    else snprintf(lay, sizeof lay, "bw%d%s", op.bw, st);
     char buf[256];
     snprintf(buf, sizeof buf, "%s|n%d|a%d|b%d|m%016llx|k%d|%s|B%d", arch.c_str(), op.n, op.n_angles,
              op.n_bins, (unsigned long long)h, op.dtype, lay, batch);

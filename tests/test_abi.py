@@ -42,7 +42,7 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct.CgInfo) == 24
     assert ctypes.sizeof(sct.SbParams) == 40
     assert ctypes.sizeof(sct.SbInfo) == 32
-    assert ctypes.sizeof(sct._Info) == 88
+    assert ctypes.sizeof(sct._Info) == 96
     assert ctypes.sizeof(sct.PdParams) == 40
     assert int(consts["RADON_WS_PD"]) == sct.WS_PD
     assert int(consts["RADON_WS_TUNE"]) == sct.WS_TUNE
@@ -57,13 +57,13 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct.Tuning) == 32
 
 
-def _build(n, na, nb, dtype=0, measured=None, bundle=0, angles=0, compact=0, reserved=0):
+def _build(n, na, nb, dtype=0, measured=None, bundle=0, angles=0, compact=0, symmetric=0):
     L = sct.lib()
     m = None
     if measured is not None:
         arr = (ctypes.c_uint8 * len(measured))(*measured)
         m = ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint8))
-    g = sct._Geom(n, na, nb, dtype, m, bundle, angles, compact, reserved)
+    g = sct._Geom(n, na, nb, dtype, m, bundle, angles, compact, symmetric)
     h = ctypes.c_void_p()
     rc = L.build_radon_csr(ctypes.byref(g), None, ctypes.byref(h))
     return rc, L.radon_last_error().decode()
@@ -94,11 +94,23 @@ def test_build_rejects_bad_bundle_layout(bundle, angles, frag):
     assert rc == -1 and frag in msg
 
 
-def test_build_rejects_bad_compact_flag_and_reserved():
+def test_build_rejects_bad_compact_and_symmetric_flags():
     rc, msg = _build(8, 4, 13, 0, None, 0, 0, 2)
     assert rc == -1 and "fwd_compact" in msg
     rc, msg = _build(8, 4, 13, 0, None, 0, 0, 0, 5)
-    assert rc == -1 and "reserved" in msg
+    assert rc == -1 and "fwd_symmetric" in msg
+    rc, msg = _build(1, 4, 13, 0, None, 0, 0, 0, 1)
+    assert rc == -1 and "n >= 2" in msg
+
+
+@pytest.mark.parametrize("na,measured,frag", [
+    (7, None, "even number"),               # pi/2 - theta is not an angle
+    (8, [1, 0, 1, 1, 1, 1, 1, 1], "not covered"),   # pi/8 unmeasured: 3, 5 and 7 pi/8 have no stored image
+])
+def test_build_rejects_asymmetric_angle_sets(na, measured, frag):
+    """The symmetry map is host logic, checked before any device work."""
+    rc, msg = _build(16, na, 25, 0, measured, 0, 0, 0, 1)
+    assert rc == -6 and frag in msg, msg
 
 
 def test_build_rejects_no_measured_angle():

@@ -64,6 +64,14 @@ def test_large_2048_normal_and_split_bregman_30x10():
     err_nc = rel_l2(got_c, want)
     say(f"large_2048: normal operator, compact layout, rel L2 = {err_nc:.3e}")
     assert err_nc <= 1e-5
+    # stored by symmetry too (the 90 measured angles are closed under the maps)
+    ops = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=F64,
+                      tuning="default", bundle=64, bundle_angles=2, compact=True, symmetric=True)
+    err_ns = rel_l2(host(ops.normal(to_dev(mu[None], F64), w.alpha, w.lam))[0], want)
+    say(f"large_2048: normal operator, compact and symmetric, rel L2 = {err_ns:.3e}")
+    assert err_ns <= 1e-5
+    us = host(ops.sb(to_dev(f[None], F64), w.alpha, w.lam, w.n_outer, w.n_cg)[0])[0]
+    del ops
     say("large_2048: split Bregman 30x10 on the GPU")
     u, info = op.sb(to_dev(f[None], F64), w.alpha, w.lam, w.n_outer, w.n_cg)
     uh = host(u)[0]
@@ -81,9 +89,12 @@ def test_large_2048_normal_and_split_bregman_30x10():
         done += k
     err = rel_l2(uh, uo)
     err_c = rel_l2(uch, uo)
-    say(f"large_2048: split Bregman rel L2 = {err:.3e}, compact layout {err_c:.3e}")
+    err_s = rel_l2(us, uo)
+    say(f"large_2048: split Bregman rel L2 = {err:.3e}, compact layout {err_c:.3e}, "
+        f"compact and symmetric {err_s:.3e}")
     assert err <= 1e-5
     assert err_c <= 1e-5
+    assert err_s <= 1e-5
 
 
 @pytest.mark.parametrize("chunks,bundle,vec", [(None, 16, "f64"), ((16, 16), 16, "f64"),

@@ -1,0 +1,77 @@
+"""The forward layout stored by the symmetries of the square (fwd_symmetric):
+bundles only for the measured angles in [0, pi/4], each ray also serving the
+rays of pi - theta, pi/2 - theta and pi/2 + theta with the same bin (their
+images under x -> -x, the transpose and both).
+
+Those rays meet the mirrored pixels with the same lengths in exact
+arithmetic, so the forward matches the FP64 oracle (which traces every ray
+itself) at the bar of its kind and the stored layout to rounding, for angle
+sets that are closed under the maps (every angle, every second angle, the
+axis-aligned and 45-degree angles whose images coincide), with both lengths
+stored or compact, one or two angles per bundle, and several images per
+call.  The adjoint is the stored layout's, bitwise.  Angle sets that are not
+closed are refused by the build (host checks in test_abi.py); a group does
+not take such an operator.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_common import host, need_gpu, rel_l2, rounded, say, to_dev, torch
+
+import paper_1705_07497_amd as sct
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = torch.float32, torch.float64
+MODES = {"f64": (F64, F64), "f32": (F32, F32), "mixed": (F32, F64)}
+
+
+@pytest.mark.parametrize("mode", ["mixed", "f32", "f64"])
+@pytest.mark.parametrize("geom", [(70, 36, 2), (61, 44, 1), (33, 8, 1), (8, 4, 1)])
+def test_symmetric_matches_oracle_and_stored_layout(mode, geom):
+    need_gpu()
+    n, na, ev = geom
+    nb = W.n_bins_for(n)
+    mask = W.angle_mask(na, ev)
+    say(f"symmetric {mode} n={n} angles={na} every {ev}")
+    ref = oracle.OracleOp(n, na, nb, mask)
+    mat, vec = MODES[mode]
+    tol = 1e-12 if mode == "f64" else 1e-5
+    rng = np.random.default_rng(n + 7 * na)
+    x = rounded(rng.standard_normal((3, n * n)), vec)
+    y = rounded(rng.standard_normal((3, ref.rows)), vec)
+    X, Y = to_dev(x, vec), to_dev(y, vec)
+    for bw, ang, compact in ((16, 1, False), (64, 2, False), (64, 2, True), (32, 2, True)):
+        full = sct.RadonOp(n, na, nb, mask, dtype=mat, vec_dtype=vec, tuning="default", bundle=bw,
+                           bundle_angles=ang)
+        op = sct.RadonOp(n, na, nb, mask, dtype=mat, vec_dtype=vec, tuning="default", bundle=bw,
+                         bundle_angles=ang, compact=compact, symmetric=True)
+        assert op.symmetric and op.compact == compact
+        assert op.info.fwd_slots < full.info.fwd_slots
+        assert torch.equal(op.adj(Y), full.adj(Y))
+        for waves in (2, 4):
+            op.tuning = {"fwd_waves": waves}
+            yy = host(op.fwd(X))
+            bound = 1e-13 if mode == "f64" else 5e-7
+            assert rel_l2(yy, host(full.fwd(X))) <= bound, (bw, ang, compact, waves)
+            a = host(op.normal(X, 0.7, 0.3, 0.05))
+            for b in range(3):
+                assert rel_l2(yy[b], ref.fwd(x[b])) <= tol, (bw, ang, compact, waves, b)
+                assert rel_l2(a[b], ref.normal(x[b], 0.7, 0.3, 0.05)) <= tol, (bw, ang, compact, waves, b)
+
+
+def test_symmetric_cg_and_group_refusal():
+    need_gpu()
+    na = 44
+    nb = W.n_bins_for(64)
+    ref = oracle.OracleOp(64, na, nb)
+    op = sct.RadonOp(64, na, nb, None, dtype=F64, tuning="default", bundle=64, bundle_angles=2,
+                     compact=True, symmetric=True)
+    rhs = np.random.default_rng(9).standard_normal((2, op.nn))
+    xs, _ = op.cg(to_dev(rhs, F64), 0.5, 1.0, 0.1, n_iter=6)
+    xo = ref.cg(0.5, 1.0, 0.1, rhs=rhs[1], n_iter=6)[0]
+    assert rel_l2(host(xs)[1], xo) <= 1e-7
+    with pytest.raises(sct.SparsectError, match="symmetry"):
+        sct.RadonMulti([op])
