@@ -72,16 +72,17 @@ def parse():
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_fwd_k_adj1_512x512_180angles.md")
-# forward bundle layouts (rays, angles per bundle, compact storage) of the
-# --profile sequence, in launch order
-PROFILE_LAYOUTS = ((16, 1, 0), (32, 1, 0), (64, 1, 0), (32, 2, 0), (64, 2, 0), (64, 4, 0),
-                   (16, 1, 1), (32, 2, 1), (64, 2, 1), (64, 4, 1))
+# forward bundle layouts (rays, angles per bundle, compact storage, stored by
+# symmetry) of the --profile sequence, in launch order
+PROFILE_LAYOUTS = ((16, 1, 0, 0), (32, 1, 0, 0), (64, 1, 0, 0), (32, 2, 0, 0), (64, 2, 0, 0), (64, 4, 0, 0),
+                   (16, 1, 1, 0), (32, 2, 1, 0), (64, 2, 1, 0), (64, 4, 1, 0),
+                   (32, 2, 1, 1), (64, 2, 1, 1), (64, 4, 1, 1), (32, 2, 0, 1))
 
 
-def traffic_from_profile(kernel, bundle=None, angles=1, waves=None, compact=False):
+def traffic_from_profile(kernel, bundle=None, angles=1, waves=None, compact=False, symmetric=False):
     """HBM bytes per launch of `kernel` (the forward: of the given bundle
-    layout, rays and angles per bundle, compact storage or not, and waves per
-    bundle) from the committed counter record (FETCH_SIZE and WRITE_SIZE
+    layout, rays and angles per bundle, compact storage or not, stored by
+    symmetry or not, and waves per bundle) from the committed counter record (FETCH_SIZE and WRITE_SIZE
     scaled by the copy-kernel calibration), or None when the record is
     missing or the kernel's sources changed since."""
     import hashlib
@@ -98,6 +99,8 @@ def traffic_from_profile(kernel, bundle=None, angles=1, waves=None, compact=Fals
         if waves is not None and kv.get("waves", str(waves)) != str(waves):
             continue
         if bundle is not None and kv.get("compact", "0") != ("1" if compact else "0"):
+            continue
+        if bundle is not None and kv.get("symmetric", "0") != ("1" if symmetric else "0"):
             continue
         h = hashlib.sha256()
         for f in kv["sources"].split(","):
@@ -505,9 +508,11 @@ def main():
     print(f"# built operator: nnz={op_def.info.nnz} rows={op_def.rows} in {build_s:.2f} s",
           file=sys.stderr, flush=True)
     # the autotuned operator the timed steps run: the compact forward layout
-    # (one stored length per ray and line, the second from the ray's chord),
-    # its bundle layout (rays and angles per bundle) chosen by the normal
-    # operator's time, then the launch settings timed
+    # (one stored length per ray and line, the second from the ray's chord)
+    # stored by the symmetries of the square (the measured angles in [0, pi/4]
+    # serve their mirror and transpose partners), its bundle layout (rays and
+    # angles per bundle) chosen by the normal operator's time, then the launch
+    # settings timed
     from paper_1705_07497_amd import autotune
     if args.profile or args.profile_fourier or args.profile_multi:
         op = op_def
@@ -515,16 +520,18 @@ def main():
     else:
         t0 = time.perf_counter()
         ch = autotune.choose_bundle(w.n, w.n_angles, w.n_bins, w.mask, torch.float32, vdt, dev, batch=1,
-                                    save=False, compact=True)
+                                    save=False, compact=True, symmetric=True)
         op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
                          device=dev, tuning="default", bundle=ch["bundle"], bundle_angles=ch["angles"],
-                         compact=True)
+                         compact=True, symmetric=True)
         autotune.autotune(op, batch=1, save=False)
         tuning_info = {"bundle": op.bundle, "bundle_angles": op.bundle_angles, "fwd_compact": op.compact,
+                       "fwd_symmetric": op.symmetric,
                        **op.tuning,
                        "tune_s": round(time.perf_counter() - t0, 2),
                        "normal_us_by_bundle": {str(k): round(v * 1e6, 1) for k, v in ch["normal_s"].items()}}
-        print(f"# autotuned: bundle {op.bundle}x{op.bundle_angles}{' compact' if op.compact else ''}, "
+        print(f"# autotuned: bundle {op.bundle}x{op.bundle_angles}{' compact' if op.compact else ''}"
+              f"{' symmetric' if op.symmetric else ''}, "
               f"{op.tuning}", file=sys.stderr, flush=True)
 
     mu_np, eps_np = W.phantom_and_noise(w.n, w.n_ellipses, op.rows, seed=0)
@@ -567,10 +574,11 @@ def main():
         # one width and wave count share a kernel name and are told apart by
         # that order), then the adjoint, the normal operator and CG of the
         # default operator
-        for bw, ang, cmp in PROFILE_LAYOUTS:
-            op_b = op if (bw, ang, cmp) == (op.bundle, op.bundle_angles, int(op.compact)) else sct.RadonOp(
+        for bw, ang, cmp, sym in PROFILE_LAYOUTS:
+            same = (bw, ang, cmp, sym) == (op.bundle, op.bundle_angles, int(op.compact), int(op.symmetric))
+            op_b = op if same else sct.RadonOp(
                 w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt, device=dev,
-                tuning="default", bundle=bw, bundle_angles=ang, compact=bool(cmp))
+                tuning="default", bundle=bw, bundle_angles=ang, compact=bool(cmp), symmetric=bool(sym))
             for waves in (2, 4):
                 op_b.tuning = {"fwd_waves": waves}
                 for _ in range(100):
@@ -660,7 +668,8 @@ def main():
     achieved = kbytes / kavg / 1e9
     normal_bytes = bytes_fwd + bytes_adj
     if kname == "k_fwd":
-        traffic = traffic_from_profile(kname, op.bundle, op.bundle_angles, op.tuning["fwd_waves"], op.compact)
+        traffic = traffic_from_profile(kname, op.bundle, op.bundle_angles, op.tuning["fwd_waves"], op.compact,
+                                       op.symmetric)
     else:
         traffic = traffic_from_profile(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -696,7 +705,8 @@ def main():
     # throughput figure only (the timed operator's bundle layout, launch
     # settings tuned for this kind)
     op32 = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, device=dev, tuning="default",
-                       bundle=op.bundle, bundle_angles=op.bundle_angles, compact=op.compact)
+                       bundle=op.bundle, bundle_angles=op.bundle_angles, compact=op.compact,
+                       symmetric=op.symmetric)
     if tuning_info is not None:
         autotune.autotune(op32, batch=1, save=False)
     x32 = x.float()
@@ -709,7 +719,7 @@ def main():
                                        "gbs": round(bytes32 / t32 / 1e9, 1),
                                        "frac": round(bytes32 / t32 / 1e9 / HBM_PEAK_GBS, 4),
                                        "bundle": op32.bundle, "bundle_angles": op32.bundle_angles,
-                                       "fwd_compact": op32.compact,
+                                       "fwd_compact": op32.compact, "fwd_symmetric": op32.symmetric,
                                        "tuning": op32.tuning}
     print(f"# normal operator, FP32 kind: {t32 * 1e6:.1f} us, {bytes32 / t32 / 1e9:.0f} GB/s",
           file=sys.stderr, flush=True)
