@@ -507,29 +507,34 @@ def main():
     build_s = time.perf_counter() - t0
     print(f"# built operator: nnz={op_def.info.nnz} rows={op_def.rows} in {build_s:.2f} s",
           file=sys.stderr, flush=True)
-    # the autotuned operator the timed steps run: the compact forward layout
-    # (one stored length per ray and line, the second from the ray's chord)
-    # stored by the symmetries of the square (the measured angles in [0, pi/4]
-    # serve their mirror and transpose partners), its bundle layout (rays and
-    # angles per bundle) chosen by the normal operator's time, then the launch
-    # settings timed
+    # the autotuned operator the timed steps run: the forward layout stored by
+    # the symmetries of the square (the measured angles in [0, pi/4] serve
+    # their mirror and transpose partners), with both lengths per ray and line
+    # or compact (the second from the ray's chord), and its bundle layout
+    # (rays and angles per bundle) chosen by the normal operator's time, then
+    # the launch settings timed
     from paper_1705_07497_amd import autotune
     if args.profile or args.profile_fourier or args.profile_multi:
         op = op_def
         tuning_info = None
     else:
         t0 = time.perf_counter()
-        ch = autotune.choose_bundle(w.n, w.n_angles, w.n_bins, w.mask, torch.float32, vdt, dev, batch=1,
-                                    save=False, compact=True, symmetric=True)
+        # both storages of the second length: with a quarter of the slots
+        # streamed, deriving it can cost more than loading it
+        chs = {cmp: autotune.choose_bundle(w.n, w.n_angles, w.n_bins, w.mask, torch.float32, vdt, dev, batch=1,
+                                           save=False, compact=cmp, symmetric=True) for cmp in (False, True)}
+        cmp = min(chs, key=lambda c: min(chs[c]["normal_s"].values()))
+        ch = chs[cmp]
         op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
                          device=dev, tuning="default", bundle=ch["bundle"], bundle_angles=ch["angles"],
-                         compact=True, symmetric=True)
+                         compact=cmp, symmetric=True)
         autotune.autotune(op, batch=1, save=False)
         tuning_info = {"bundle": op.bundle, "bundle_angles": op.bundle_angles, "fwd_compact": op.compact,
                        "fwd_symmetric": op.symmetric,
                        **op.tuning,
                        "tune_s": round(time.perf_counter() - t0, 2),
-                       "normal_us_by_bundle": {str(k): round(v * 1e6, 1) for k, v in ch["normal_s"].items()}}
+                       "normal_us_by_bundle": {("compact " if c else "") + str(k): round(v * 1e6, 1)
+                                               for c in chs for k, v in chs[c]["normal_s"].items()}}
         print(f"# autotuned: bundle {op.bundle}x{op.bundle_angles}{' compact' if op.compact else ''}"
               f"{' symmetric' if op.symmetric else ''}, "
               f"{op.tuning}", file=sys.stderr, flush=True)
