@@ -577,8 +577,9 @@ def main():
         # layout choose_bundle picks) at 2 and 4 waves per bundle, 100
         # launches each, layouts in the order of PROFILE_LAYOUTS (layouts of
         # one width and wave count share a kernel name and are told apart by
-        # that order), then the adjoint, the normal operator and CG of the
-        # default operator
+        # that order; the full pixel-group layout's adjoint, 100 launches,
+        # after the 64x2 compact layout's forwards), then the adjoint, the
+        # normal operator and CG of the timed operator
         for bw, ang, cmp, sym in PROFILE_LAYOUTS:
             same = (bw, ang, cmp, sym) == (op.bundle, op.bundle_angles, int(op.compact), int(op.symmetric))
             op_b = op if same else sct.RadonOp(
@@ -588,9 +589,14 @@ def main():
                 op_b.tuning = {"fwd_waves": waves}
                 for _ in range(100):
                     op_b.fwd_xt(x, xT, out=ysb)
+            if (bw, ang, cmp, sym) == (64, 2, 1, 0):
+                # the adjoint of the full pixel-group layout (k_adj1)
+                for _ in range(100):
+                    op_b.adj(ysb, out=out)
             op_b.tuning = {"fwd_waves": 2}
             torch.cuda.synchronize()
             del op_b
+        # the timed operator's adjoint (k_adj1_sym when stored by symmetry)
         for _ in range(100):
             op.adj(ysb, out=out)
         for _ in range(20):
@@ -667,7 +673,7 @@ def main():
     bytes_adj = 8 * nnz + 4 * (nn + 1) + vb * rows + vb * nn
     avg_fwd, avg_adj = t_fwd / args.applies, t_adj / args.applies
     if avg_adj >= avg_fwd:
-        kname, kbytes, kavg = "k_adj", bytes_adj, avg_adj
+        kname, kbytes, kavg = ("k_adj_sym" if op.adj_symmetric else "k_adj"), bytes_adj, avg_adj
     else:
         kname, kbytes, kavg = "k_fwd", bytes_fwd, avg_fwd
     achieved = kbytes / kavg / 1e9

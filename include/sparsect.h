@@ -95,9 +95,10 @@ typedef struct {
     int32_t fwd_symmetric;      /* 1: the forward layout stores only the measured
                                    angles in [0, pi/4] and serves the rays of
                                    pi - theta, pi/2 - theta and pi/2 + theta from
-                                   them (see below); needs n >= 2, an even
-                                   n_angles and a measured set closed under
-                                   those maps */
+                                   them (see below), and so does the adjoint
+                                   layout when n is a multiple of 8; needs
+                                   n >= 2, an even n_angles and a measured set
+                                   closed under those maps */
 } radon_geom;
 
 typedef struct {
@@ -117,6 +118,8 @@ typedef struct {
     int32_t fwd_angles;         /* measured angles per forward bundle (1, 2 or 4) */
     int32_t fwd_compact;        /* 1: compact forward layout */
     int32_t fwd_symmetric;      /* 1: forward layout stored by symmetry */
+    int32_t adj_symmetric;      /* 1: adjoint layout stored by symmetry too */
+    int32_t reserved;
 } radon_info;
 
 /*
@@ -147,7 +150,11 @@ typedef struct {
  *   - a pixel-group layout of (MR)^T for the adjoint: groups of 64 pixels,
  *     one slot per (pixel, measured angle) holding the first bin crossing
  *     the pixel (uint16) and the lengths for that bin and the next one (a
- *     pixel meets at most two adjacent bins of any angle).
+ *     pixel meets at most two adjacent bins of any angle).  With
+ *     g->fwd_symmetric and n a multiple of 8 only the angles in [0, pi/4]
+ *     have slots: pixel (px, py) meets the rays of pi - theta, pi/2 - theta
+ *     and pi/2 + theta as pixel (n-1-px, py), (py, px) and (py, n-1-px)
+ *     meets those of theta, bin for bin.
  * Both layouts hold exactly the CSR's values, except that a compact
  * ray-bundle layout's derived second lengths differ from the CSR's by about
  * one rounding of the matrix type relative to the chord (the build checks

@@ -51,7 +51,8 @@ class _Info(ctypes.Structure):
                 ("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
                 ("needs_transpose", ctypes.c_int32), ("fwd_bundle", ctypes.c_int32),
                 ("fwd_angles", ctypes.c_int32), ("fwd_compact", ctypes.c_int32),
-                ("fwd_symmetric", ctypes.c_int32)]
+                ("fwd_symmetric", ctypes.c_int32), ("adj_symmetric", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class RadonSizes(ctypes.Structure):
@@ -259,7 +260,8 @@ class RadonOp:
     keep the stored values).  symmetric=True stores only the measured angles
     in [0, pi/4] in the forward layout and serves their mirror and transpose
     partners from them (the measured set must be closed under theta ->
-    pi - theta and theta -> pi/2 - theta).
+    pi - theta and theta -> pi/2 - theta); with n a multiple of 8 the adjoint
+    layout is stored the same way (.adj_symmetric).
     tuning: "cache" applies cached launch settings for tune_batch images,
     "tune" chooses the bundle layout and times the launch settings now (and
     caches both), "default" leaves the library defaults."""
@@ -329,6 +331,7 @@ class RadonOp:
         self.bundle_angles = int(inf.fwd_angles)
         self.compact = bool(inf.fwd_compact)
         self.symmetric = bool(inf.fwd_symmetric)
+        self.adj_symmetric = bool(inf.adj_symmetric)
         self._ws = {}
         if tuning == "cache":
             from . import autotune

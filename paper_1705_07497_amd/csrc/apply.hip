@@ -58,6 +58,116 @@ __global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel
     }
 }
 
+// Adjoint of an operator whose adjoint is stored by symmetry (Op::sym_adj):
+// pixel-group slots for the stored angles theta in [0, pi/4] only.  Pixel
+// P = (px, py) meets the rays of a partner angle of theta with the lengths,
+// bin for bin, with which its image Q meets the rays of theta:
+//   pi - theta    (x -> -x):       Q = (n-1-px, py);
+//   pi/2 - theta  (the transpose): Q = (py, px);
+//   pi/2 + theta  (both):          Q = (py, n-1-px)
+// (the maps of the forward's partner rays, inverted).  With n a multiple of
+// 8 each map carries 8x8 tiles onto tiles, lanes onto lanes, so tile g sums,
+// per map, the stored quads of its source tile at the mapped lanes against
+// the sinogram band of the partner angles (absent partners: zero band).  A
+// wave takes its share of the 4 * n_aq (map, quad) items; bases and partner
+// angles are staged per chunk of quads in LDS as in adj_tile1.  The tiles of
+// one orbit read the same slots and the tile order keeps them on one XCD at
+// once, so three in four slot reads hit L2.
+template <class TM, class T, int W>
+__global__ __launch_bounds__(64 * W) void k_adj1_sym(const uint8_t *__restrict__ rel,
+                                                    const uint16_t *__restrict__ base,
+                                                    const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                    const int4 *__restrict__ partner, int n_rep, int n_aq,
+                                                    int nb, const T *__restrict__ y, const T *__restrict__ x,
+                                                    T *__restrict__ out, T alpha, T lambda, T sigma,
+                                                    double *__restrict__ part, int n, int tiles, int64_t nn,
+                                                    int64_t rows, const int32_t *__restrict__ order,
+                                                    int64_t n_order)
+{
+    using Q = typename Quad<TM>::type;
+    __shared__ T band[W][4 * kAdjBand];
+    __shared__ uint16_t bases[W][kAdjLanes];
+    __shared__ int32_t rowat[W][kAdjLanes];   // partner angle * nb, or -1
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t bat = blockIdx.y;
+    const T *__restrict__ yb = y + bat * rows;
+    const T *__restrict__ xb = x ? x + bat * nn : nullptr;
+    const uint32_t *__restrict__ Rl = reinterpret_cast<const uint32_t *>(rel);
+    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0);
+    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1);
+    const int items = 4 * n_aq;
+    const int q0 = (items * wave) / W, q1 = (items * (wave + 1)) / W;
+    const int kk = lane >> 4, ee = lane & 15;   // this lane's band element
+    const int lx = lane & 7, ly = lane >> 3;
+    T *__restrict__ my = band[wave];
+    double dsum = 0.0;
+    for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
+        const int g = order[o];
+        if (g < 0) continue;   // padding entry (uniform per block)
+        const int tx = g % tiles, ty = g / tiles;
+        T acc = T(0);
+        for (int c0 = q0; c0 < q1;) {
+            const int mu = c0 / n_aq, aq0 = c0 % n_aq;   // wave-uniform
+            const int nc = min(min(kBaseChunk, q1 - c0), n_aq - aq0);
+            int S, sl;
+            if (mu == 0) S = g, sl = lane;
+            else if (mu == 1) S = ty * tiles + (tiles - 1 - tx), sl = ly * 8 + (7 - lx);
+            else if (mu == 2) S = tx * tiles + ty, sl = lx * 8 + ly;
+            else S = (tiles - 1 - tx) * tiles + ty, sl = (7 - lx) * 8 + ly;
+            if (lane < 4 * nc) {
+                const int a = 4 * aq0 + lane;
+                int pa = -1;
+                if (a < n_rep) {
+                    const int4 p = partner[a];
+                    pa = mu == 0 ? a : (mu == 1 ? p.x : (mu == 2 ? p.y : p.z));
+                }
+                bases[wave][lane] = base[(int64_t(S) * n_aq + aq0) * 4 + lane];
+                rowat[wave][lane] = pa < 0 ? -1 : pa * nb;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+            for (int j = 0; j < nc; ++j) {
+                const int64_t gq = int64_t(S) * n_aq + aq0 + j;
+                const int ra = rowat[wave][4 * j + kk];
+                const int b_band = min(int(bases[wave][4 * j + kk]) + ee, nb - 1);
+                const T yv = ra >= 0 ? yb[int64_t(ra) + b_band] : T(0);
+                const int64_t e = gq * kAdjLanes + sl;
+                // plain loads: three more tiles of the orbit read these slots
+                // shortly after, from L2
+                const uint32_t r4 = Rl[e];
+                const Q a4 = A[e];
+                const Q c4 = Bv[e];
+                my[lane] = yv;
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int rb = int((r4 >> (8 * k)) & 0xffu);
+                    acc = fma(T(a4[k]), my[k * kAdjBand + rb], acc);
+                    acc = fma(T(c4[k]), my[k * kAdjBand + rb + 1], acc);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            c0 += nc;
+        }
+        if constexpr (W > 1) {
+            __shared__ T red[W][64];
+            red[wave][lane] = acc;
+            __syncthreads();
+            if (wave == 0) {
+                acc = red[0][lane];
+#pragma unroll
+                for (int w = 1; w < W; ++w) acc += red[w][lane];
+            }
+            __syncthreads();   // red is reused by the next tile
+        }
+        if (wave == 0) dsum += adj_epilogue(g, lane, acc, xb, out + bat * nn, alpha, lambda, sigma, n, tiles);
+    }
+    if (part && wave == 0) {
+        dsum = wave_sum(dsum);
+        if (lane == 0) part[bat * gridDim.x + blockIdx.x] = dsum;
+    }
+}
+
 // Adjoint: one workgroup of W waves per 8x8 pixel tile (persistent loop over
 // the tiles in `order`, the XCD-compact order: the tiles a workgroup on XCD x
 // visits lie in one compact region of the image, so the sinogram bands the
@@ -449,6 +559,26 @@ static void adj_wbc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV l
     }
 }
 
+// Adjoint stored by symmetry: one image per blockIdx.y.
+template <class TM, class TV>
+static void adj_sym(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV la, TV si, double *part,
+                    int batch, hipStream_t s)
+{
+    const dim3 grid(unsigned(adj_blocks(op)), unsigned(batch));
+    const TM *a0 = static_cast<const TM *>(op.a_v0), *a1 = static_cast<const TM *>(op.a_v1);
+#define SCT_SYM(W)                                                                                    \
+    k_adj1_sym<TM, TV, W><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.f_partner, op.n_rep, \
+                                                  op.n_aq, op.n_bins, y, x, out, al, la, si, part, op.n, \
+                                                  op.tiles, op.nn, op.rows, op.a_order, op.n_a_order)
+    const int w = op.tune.adj_waves == 1 || op.tune.adj_waves == 2 || op.tune.adj_waves == 4
+                      ? op.tune.adj_waves
+                      : adj_waves_for(4 * op.n_adj_ang);
+    if (w == 4) SCT_SYM(4);
+    else if (w == 2) SCT_SYM(2);
+    else SCT_SYM(1);
+#undef SCT_SYM
+}
+
 template <class TM, class TV, int BC>
 static void adj_bc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV la, TV si,
                    double *part, int batch, hipStream_t s, TV *scratch)
@@ -463,7 +593,7 @@ static void adj_bc(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV la
 int64_t adj_scratch_elems(const Op &op, int batch)
 {
     const int bc = rhs_chunk(batch, op.tune.adj_rhs);
-    if (op.tune.adj_layout != 1 || bc < 4) return 0;
+    if (op.sym_adj || op.tune.adj_layout != 1 || bc < 4) return 0;
     return kPixelMajorSlack + int64_t(bc) * op.rows;
 }
 
@@ -479,6 +609,10 @@ int launch_adj(const Op &op, const TV *y, const TV *x, TV *out, double alpha, do
 {
     SCT_TRY(check_grid_y(batch));
     const TV al = TV(alpha), la = TV(lambda), si = TV(sigma);
+    if (op.sym_adj) {
+        adj_sym<TM, TV>(op, y, x, out, al, la, si, part, batch, s);
+        return check_launch("k_adj1_sym");
+    }
     switch (rhs_chunk(batch, op.tune.adj_rhs)) {
     case 16: adj_bc<TM, TV, 16>(op, y, x, out, al, la, si, part, batch, s, scratch); break;
     case 8: adj_bc<TM, TV, 8>(op, y, x, out, al, la, si, part, batch, s, scratch); break;

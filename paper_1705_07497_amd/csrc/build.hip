@@ -299,7 +299,8 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
                            uint16_t *__restrict__ f_idx, T *__restrict__ f_v0, T *__restrict__ f_v1,
                            const int32_t *__restrict__ mlo, const int32_t *__restrict__ mhi,
                            const double *__restrict__ chord, RayEdge *__restrict__ f_edge,
-                           int n_stored, int32_t *__restrict__ bin_tmp, int32_t *__restrict__ bad)
+                           int n_stored, int n_adj_ang, int32_t *__restrict__ bin_tmp,
+                           int32_t *__restrict__ bad)
 {
     const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ray >= rows) return;
@@ -378,7 +379,7 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
             w1 = v;
             l1 = len;
         }
-        atomicMin(&bin_tmp[adj_slot(j / n, j % n, a, n_aq, tiles)], b);
+        if (a < n_adj_ang) atomicMin(&bin_tmp[adj_slot(j / n, j % n, a, n_aq, tiles)], b);
     });
     flush();
     if (o != oend) atomicOr(bad, 4);
@@ -387,14 +388,15 @@ __global__ void k_ray_fill(const double2 *__restrict__ cs, int n, int nb, Bundle
 
 // Pass 3: place each entry in its (pixel, angle) slot as the first or second bin.
 template <class T>
-__global__ void k_adj_fill(int n, int nb, int64_t rows, int n_aq, int tiles, const int64_t *__restrict__ rp,
-                           const int32_t *__restrict__ col, const T *__restrict__ val,
-                           const int32_t *__restrict__ bin_tmp, T *__restrict__ a_v0,
+__global__ void k_adj_fill(int n, int nb, int64_t rows, int n_aq, int tiles, int n_adj_ang,
+                           const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const T *__restrict__ val, const int32_t *__restrict__ bin_tmp, T *__restrict__ a_v0,
                            T *__restrict__ a_v1, int32_t *__restrict__ bad)
 {
     const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ray >= rows) return;
     const int a = int(ray / nb), b = int(ray % nb);
+    if (a >= n_adj_ang) return;   // a partner angle of an adjoint stored by symmetry
     for (int64_t e = rp[ray]; e < rp[ray + 1]; ++e) {
         const int j = col[e];
         const int64_t as = adj_slot(j / n, j % n, a, n_aq, tiles);
@@ -684,13 +686,56 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
                 mt.emplace_back(code, ty * T + tx);
             }
         std::sort(mt.begin(), mt.end());
-        const int64_t per = (op.n_ag + nx - 1) / nx;
-        pl.aorder.assign(size_t(per * nx), -1);
-        for (int64_t r = 0; r < nx; ++r)
-            for (int64_t j = 0; j < per; ++j) {
-                const int64_t k = r * per + j;
-                if (k < op.n_ag) pl.aorder[size_t(j * nx + r)] = mt[size_t(k)].second;
+        if (op.sym_adj) {
+            // An adjoint stored by symmetry: tile g reads the slots of its
+            // images under x -> -x, the transpose and both, so the tiles of
+            // one orbit under those maps (8, or 4 or 1 on the diagonals and
+            // the middle lines) read the same slots.  Orbits fill groups of 8
+            // entries (whole orbits of 8 first, in the Morton order of their
+            // first tile, then the smaller ones by decreasing size, which
+            // packs them without gaps); group i goes to XCD i % 8 with its
+            // entries at r*64 + i%8 + 8k (r = i / 8): the workgroups of one
+            // XCD take an orbit's tiles at once, so all but the first reader
+            // of a slot find it in L2.
+            std::vector<char> seen(size_t(op.n_ag), 0);
+            std::vector<std::vector<int32_t>> small;
+            std::vector<int32_t> flat;   // orbit tiles, groups of 8 (-1: unused)
+            for (const auto &m : mt) {
+                if (seen[size_t(m.second)]) continue;
+                std::vector<int32_t> orb(1, m.second);
+                seen[size_t(m.second)] = 1;
+                for (size_t h = 0; h < orb.size(); ++h) {
+                    const int tx = orb[h] % T, ty = orb[h] / T;
+                    const int32_t img[2] = {ty * T + (T - 1 - tx), tx * T + ty};
+                    for (int32_t u : img)
+                        if (!seen[size_t(u)]) {
+                            seen[size_t(u)] = 1;
+                            orb.push_back(u);
+                        }
+                }
+                if (orb.size() == 8) flat.insert(flat.end(), orb.begin(), orb.end());
+                else small.push_back(std::move(orb));
             }
+            std::stable_sort(small.begin(), small.end(),
+                             [](const std::vector<int32_t> &a, const std::vector<int32_t> &b) {
+                                 return a.size() > b.size();
+                             });
+            for (const auto &orb : small) flat.insert(flat.end(), orb.begin(), orb.end());
+            flat.resize((flat.size() + 7) / 8 * 8, -1);
+            const int64_t groups = int64_t(flat.size()) / 8;
+            pl.aorder.assign(size_t((groups + nx - 1) / nx * 64), -1);
+            for (int64_t i = 0; i < groups; ++i)
+                for (int k = 0; k < 8; ++k)
+                    pl.aorder[size_t((i / nx) * 64 + i % nx + 8 * k)] = flat[size_t(i * 8 + k)];
+        } else {
+            const int64_t per = (op.n_ag + nx - 1) / nx;
+            pl.aorder.assign(size_t(per * nx), -1);
+            for (int64_t r = 0; r < nx; ++r)
+                for (int64_t j = 0; j < per; ++j) {
+                    const int64_t k = r * per + j;
+                    if (k < op.n_ag) pl.aorder[size_t(j * nx + r)] = mt[size_t(k)].second;
+                }
+        }
     }
     return RADON_OK;
 }
@@ -717,10 +762,10 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
     k_ray_fill<T><<<g, blk, 0, st>>>(t.cs, n, nb, op.bmap, op.bw, rows, op.n_aq, op.tiles, op.rp, op.col,
                                      static_cast<T *>(op.val), op.fb, op.f_idx,
                                      static_cast<T *>(op.f_v0), static_cast<T *>(op.f_v1), t.mlo, t.mhi,
-                                     t.chord, op.f_edge, op.sym ? op.n_rep : op.n_meas,
+                                     t.chord, op.f_edge, op.sym ? op.n_rep : op.n_meas, op.n_adj_ang,
                                      t.bin_tmp, t.bad);
     SCT_TRY(check_launch("k_ray_fill"));
-    k_adj_fill<T><<<g, blk, 0, st>>>(n, nb, rows, op.n_aq, op.tiles, op.rp, op.col,
+    k_adj_fill<T><<<g, blk, 0, st>>>(n, nb, rows, op.n_aq, op.tiles, op.n_adj_ang, op.rp, op.col,
                                      static_cast<const T *>(op.val), t.bin_tmp,
                                      static_cast<T *>(op.a_v0), static_cast<T *>(op.a_v1), t.bad);
     SCT_TRY(check_launch("k_adj_fill"));
@@ -971,6 +1016,12 @@ static int new_op(const radon_geom *g, Op **res, std::vector<double> &cs)
         delete op;
         return rc;
     }
+    // an operator stored by symmetry keeps adjoint slots for its stored
+    // angles only when the maps carry whole 8x8 tiles onto tiles
+    op->sym_adj = op->sym && op->n % 8 == 0;
+    op->n_adj_ang = op->sym_adj ? op->n_rep : op->n_meas;
+    op->n_aq = (op->n_adj_ang + 3) / 4;
+    op->a_slots = op->n_ag * 64 * 4 * int64_t(op->n_aq);
     op->n_fb = n_fb_of(*op);
     *res = op;
     return RADON_OK;
@@ -1158,7 +1209,7 @@ extern "C" int build_radon_csr(const radon_geom *g, void *stream, radon_op **out
     return RADON_OK;
 }
 
-static_assert(sizeof(radon_geom) == 40 && sizeof(radon_info) == 96, "C ABI struct sizes");
+static_assert(sizeof(radon_geom) == 40 && sizeof(radon_info) == 104, "C ABI struct sizes");
 
 extern "C" void radon_op_destroy(radon_op *p) { op_free(as_op(p)); }
 
@@ -1184,6 +1235,8 @@ extern "C" int radon_op_info(const radon_op *p, radon_info *out)
     out->fwd_angles = op->bang;
     out->fwd_compact = op->compact ? 1 : 0;
     out->fwd_symmetric = op->sym ? 1 : 0;
+    out->adj_symmetric = op->sym_adj ? 1 : 0;
+    out->reserved = 0;
     return RADON_OK;
 }
 
@@ -1224,9 +1277,25 @@ static int export_adj_typed(const Op &op, int32_t *bin, double *v0, double *v1)
     SCT_HIP(hipMemcpy(base.data(), op.a_base, 2 * base.size(), hipMemcpyDeviceToHost));
     SCT_HIP(hipMemcpy(a0.data(), op.a_v0, sizeof(T) * ns, hipMemcpyDeviceToHost));
     SCT_HIP(hipMemcpy(a1.data(), op.a_v1, sizeof(T) * ns, hipMemcpyDeviceToHost));
+    // measured angle -> (angle with slots, map): an adjoint stored by
+    // symmetry holds the records of a partner angle at the stored angle, for
+    // the pixel's image under the inverse map (see k_adj1_sym)
+    std::vector<int2> src(size_t(op.n_meas));
+    for (int a = 0; a < op.n_meas; ++a) src[size_t(a)] = make_int2(a, 0);
+    if (op.sym_adj)
+        for (int a = 0; a < op.n_rep; ++a) {
+            const int4 p = op.partner_host[size_t(a)];
+            const int pm[3] = {p.x, p.y, p.z};
+            for (int mu = 1; mu <= 3; ++mu)
+                if (pm[mu - 1] >= 0) src[size_t(pm[mu - 1])] = make_int2(a, mu);
+        }
+    const int n = op.n;
     for (int64_t j = 0; j < op.nn; ++j)
         for (int a = 0; a < op.n_meas; ++a) {
-            const size_t s = size_t(adj_slot(int(j / op.n), int(j % op.n), a, op.n_aq, op.tiles));
+            const int px = int(j % n), py = int(j / n), mu = src[size_t(a)].y;
+            const int qx = mu == 0 ? px : (mu == 1 ? n - 1 - px : py);
+            const int qy = mu == 0 ? py : (mu == 1 ? py : (mu == 2 ? px : n - 1 - px));
+            const size_t s = size_t(adj_slot(qy, qx, src[size_t(a)].x, op.n_aq, op.tiles));
             const size_t bi = ((s >> 2) / kAdjLanes) * 4 + (s & 3);
             const size_t o = size_t(j * op.n_meas + a);
             const bool empty = a0[s] == T(0) && a1[s] == T(0);

@@ -178,6 +178,11 @@ struct Op {
     // the rays of f_partner[a] (see fwd_sym.hpp)
     bool sym = false;
     int32_t n_rep = 0;
+    // the adjoint stored by symmetry too (n a multiple of 8, so the maps
+    // carry 8x8 tiles onto tiles): pixel-group slots for the first n_rep
+    // angles only; n_adj_ang is the number of angles with adjoint slots
+    bool sym_adj = false;
+    int32_t n_adj_ang = 0;
     std::vector<int4> partner_host;
     int4 *f_partner = nullptr;
     void *f_v0 = nullptr;            // first lengths, per slot

@@ -42,7 +42,7 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(sct.CgInfo) == 24
     assert ctypes.sizeof(sct.SbParams) == 40
     assert ctypes.sizeof(sct.SbInfo) == 32
-    assert ctypes.sizeof(sct._Info) == 96
+    assert ctypes.sizeof(sct._Info) == 104
     assert ctypes.sizeof(sct.PdParams) == 40
     assert int(consts["RADON_WS_PD"]) == sct.WS_PD
     assert int(consts["RADON_WS_TUNE"]) == sct.WS_TUNE

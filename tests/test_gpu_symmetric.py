@@ -9,9 +9,16 @@ itself) at the bar of its kind and the stored layout to rounding, for angle
 sets that are closed under the maps (every angle, every second angle, the
 axis-aligned and 45-degree angles whose images coincide), with both lengths
 stored or compact, one or two angles per bundle, and several images per
-call.  The adjoint is the stored layout's, bitwise.  Angle sets that are not
-closed are refused by the build (host checks in test_abi.py); a group does
-not take such an operator.
+call.  Angle sets that are not closed are refused by the build (host checks
+in test_abi.py); a group does not take such an operator.
+
+With n a multiple of 8 the adjoint layout is stored the same way (pixel
+(px, py) meets the rays of the three partner angles as (n-1-px, py),
+(py, px) and (py, n-1-px) meet those of the stored angle, and 8x8 tiles map
+onto tiles): the adjoint matches the oracle at the bar of its kind and the
+full layout to rounding, and the exported per-(pixel, angle) records, read
+through the maps, hold the full layout's bins exactly and its lengths to
+rounding.  Otherwise the adjoint is the full layout's, bitwise.
 """
 import numpy as np
 import pytest
@@ -29,7 +36,8 @@ MODES = {"f64": (F64, F64), "f32": (F32, F32), "mixed": (F32, F64)}
 
 
 @pytest.mark.parametrize("mode", ["mixed", "f32", "f64"])
-@pytest.mark.parametrize("geom", [(70, 36, 2), (61, 44, 1), (33, 8, 1), (8, 4, 1)])
+@pytest.mark.parametrize("geom", [(70, 36, 2), (61, 44, 1), (33, 8, 1), (8, 4, 1), (64, 36, 2), (40, 20, 1),
+                                  (24, 180, 2)])
 def test_symmetric_matches_oracle_and_stored_layout(mode, geom):
     need_gpu()
     n, na, ev = geom
@@ -50,7 +58,17 @@ def test_symmetric_matches_oracle_and_stored_layout(mode, geom):
                          bundle_angles=ang, compact=compact, symmetric=True)
         assert op.symmetric and op.compact == compact
         assert op.info.fwd_slots < full.info.fwd_slots
-        assert torch.equal(op.adj(Y), full.adj(Y))
+        assert op.adj_symmetric == (n % 8 == 0)
+        if op.adj_symmetric:
+            assert op.info.adj_slots <= full.info.adj_slots   # equal when both fit one quad
+            for aw in (1, 2, 4):
+                op.tuning = {"adj_waves": aw}
+                xa = host(op.adj(Y))
+                assert rel_l2(xa, host(full.adj(Y))) <= (1e-13 if mode == "f64" else 5e-7), (bw, ang, aw)
+                for b in range(3):
+                    assert rel_l2(xa[b], ref.adj(y[b])) <= tol, (bw, ang, aw, b)
+        else:
+            assert torch.equal(op.adj(Y), full.adj(Y))
         for waves in (2, 4):
             op.tuning = {"fwd_waves": waves}
             yy = host(op.fwd(X))
@@ -75,3 +93,50 @@ def test_symmetric_cg_and_group_refusal():
     assert rel_l2(host(xs)[1], xo) <= 1e-7
     with pytest.raises(sct.SparsectError, match="symmetry"):
         sct.RadonMulti([op])
+
+
+@pytest.mark.parametrize("mode", ["mixed", "f64"])
+def test_symmetric_adjoint_records(mode):
+    """The adjoint records exported through the maps: bins equal the full
+    layout's, lengths equal them to the rounding of the matrix type."""
+    need_gpu()
+    n, na = 48, 40
+    nb = W.n_bins_for(n)
+    mat, vec = MODES[mode]
+    say(f"symmetric adjoint records {mode}")
+    full = sct.RadonOp(n, na, nb, None, dtype=mat, vec_dtype=vec, tuning="default", bundle=32)
+    op = sct.RadonOp(n, na, nb, None, dtype=mat, vec_dtype=vec, tuning="default", bundle=32, symmetric=True)
+    assert op.adj_symmetric
+    bf, v0f, v1f = full.export_adj()
+    bs, v0s, v1s = op.export_adj()
+    np.testing.assert_array_equal(bs, bf)
+    bound = 1e-14 if mode == "f64" else 1e-6
+    assert np.max(np.abs(v0s - v0f)) <= bound * max(1.0, np.max(np.abs(v0f)))
+    assert np.max(np.abs(v1s - v1f)) <= bound * max(1.0, np.max(np.abs(v1f)))
+
+
+def test_symmetric_adjoint_batched_normal_and_partials():
+    """Several images per call through every entry that runs the adjoint:
+    radon_normal with its FP64 <x, Ax> partials (CG's dot), and image
+    batches of each size the multi-image paths chunk by."""
+    need_gpu()
+    n, na = 96, 60
+    nb = W.n_bins_for(n)
+    say("symmetric adjoint batched")
+    ref = oracle.OracleOp(n, na, nb)
+    op = sct.RadonOp(n, na, nb, None, dtype=F32, vec_dtype=F64, tuning="default", bundle=64, bundle_angles=2,
+                     compact=True, symmetric=True)
+    assert op.adj_symmetric
+    rng = np.random.default_rng(5)
+    for batch in (1, 5, 16):
+        x = rng.standard_normal((batch, n * n))
+        y = rng.standard_normal((batch, ref.rows))
+        for rhs in (1, 4, 16):
+            op.tuning = {"adj_rhs": rhs, "fwd_rhs": rhs}
+            xa = host(op.adj(to_dev(y, F64)))
+            a = host(op.normal(to_dev(x, F64), 0.5, 1.0, 0.1))
+            for b in range(batch):
+                assert rel_l2(xa[b], ref.adj(y[b])) <= 1e-5, (batch, rhs, b)
+                assert rel_l2(a[b], ref.normal(x[b], 0.5, 1.0, 0.1)) <= 1e-5, (batch, rhs, b)
+    xs, _ = op.cg(to_dev(rng.standard_normal((3, n * n)), F64), 0.5, 1.0, 0.1, n_iter=4)
+    assert np.all(np.isfinite(host(xs)))
