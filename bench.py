@@ -577,9 +577,9 @@ def main():
         # layout choose_bundle picks) at 2 and 4 waves per bundle, 100
         # launches each, layouts in the order of PROFILE_LAYOUTS (layouts of
         # one width and wave count share a kernel name and are told apart by
-        # that order; the full pixel-group layout's adjoint, 100 launches,
-        # after the 64x2 compact layout's forwards), then the adjoint, the
-        # normal operator and CG of the timed operator
+        # that order; the adjoint stored by symmetry, 100 launches, after the
+        # forwards of the symmetric layout with both lengths), then the
+        # adjoint, the normal operator and CG of the default operator
         for bw, ang, cmp, sym in PROFILE_LAYOUTS:
             same = (bw, ang, cmp, sym) == (op.bundle, op.bundle_angles, int(op.compact), int(op.symmetric))
             op_b = op if same else sct.RadonOp(
@@ -589,14 +589,14 @@ def main():
                 op_b.tuning = {"fwd_waves": waves}
                 for _ in range(100):
                     op_b.fwd_xt(x, xT, out=ysb)
-            if (bw, ang, cmp, sym) == (64, 2, 1, 0):
-                # the adjoint of the full pixel-group layout (k_adj1)
+            if sym and not cmp:
+                # the adjoint stored by symmetry (k_adj1_sym; the same
+                # pixel-group layout for every forward layout)
                 for _ in range(100):
                     op_b.adj(ysb, out=out)
             op_b.tuning = {"fwd_waves": 2}
             torch.cuda.synchronize()
             del op_b
-        # the timed operator's adjoint (k_adj1_sym when stored by symmetry)
         for _ in range(100):
             op.adj(ysb, out=out)
         for _ in range(20):

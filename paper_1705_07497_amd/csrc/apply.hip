@@ -66,13 +66,16 @@ __global__ __launch_bounds__(64 * W) void k_adj1(const uint8_t *__restrict__ rel
 //   pi/2 - theta  (the transpose): Q = (py, px);
 //   pi/2 + theta  (both):          Q = (py, n-1-px)
 // (the maps of the forward's partner rays, inverted).  With n a multiple of
-// 8 each map carries 8x8 tiles onto tiles, lanes onto lanes, so tile g sums,
-// per map, the stored quads of its source tile at the mapped lanes against
-// the sinogram band of the partner angles (absent partners: zero band).  A
-// wave takes its share of the 4 * n_aq (map, quad) items; bases and partner
-// angles are staged per chunk of quads in LDS as in adj_tile1.  The tiles of
-// one orbit read the same slots and the tile order keeps them on one XCD at
-// once, so three in four slot reads hit L2.
+// 8 each map carries 8x8 tiles onto tiles and lanes onto lanes, so output
+// tile g sums, per map, the stored quads of its source tile against the
+// sinogram band of the partner angles (absent partners: zero band).  Lane l
+// reads slot l of the source tile (whole 64-lane runs, as in adj_tile1) and
+// keeps one sum per map for source pixel l; at the end of the tile the sums
+// go through LDS to the output lanes they belong to.  A wave takes its share
+// of the 4 * n_aq (map, quad) items; bases and partner angles are staged per
+// chunk of quads in LDS.  The tiles of one orbit read the same slots and the
+// tile order keeps them on one XCD at once, so the slots are read with plain
+// loads and the later readers find them in L2.
 template <class TM, class T, int W>
 __global__ __launch_bounds__(64 * W) void k_adj1_sym(const uint8_t *__restrict__ rel,
                                                     const uint16_t *__restrict__ base,
@@ -88,6 +91,7 @@ __global__ __launch_bounds__(64 * W) void k_adj1_sym(const uint8_t *__restrict__
     __shared__ T band[W][4 * kAdjBand];
     __shared__ uint16_t bases[W][kAdjLanes];
     __shared__ int32_t rowat[W][kAdjLanes];   // partner angle * nb, or -1
+    __shared__ T red[W][4][64];               // per-map sums at their output lanes
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t bat = blockIdx.y;
     const T *__restrict__ yb = y + bat * rows;
@@ -98,22 +102,23 @@ __global__ __launch_bounds__(64 * W) void k_adj1_sym(const uint8_t *__restrict__
     const int items = 4 * n_aq;
     const int q0 = (items * wave) / W, q1 = (items * (wave + 1)) / W;
     const int kk = lane >> 4, ee = lane & 15;   // this lane's band element
-    const int lx = lane & 7, ly = lane >> 3;
+    // output lane of source lane (qy, qx) = (lane >> 3, lane & 7) per map
+    const int sx = lane & 7, sy = lane >> 3;
+    const int dest[4] = {lane, sy * 8 + (7 - sx), sx * 8 + sy, sx * 8 + (7 - sy)};
     T *__restrict__ my = band[wave];
     double dsum = 0.0;
     for (int64_t o = blockIdx.x; o < n_order; o += gridDim.x) {
         const int g = order[o];
         if (g < 0) continue;   // padding entry (uniform per block)
         const int tx = g % tiles, ty = g / tiles;
-        T acc = T(0);
+        T acc[4] = {T(0), T(0), T(0), T(0)};
         for (int c0 = q0; c0 < q1;) {
             const int mu = c0 / n_aq, aq0 = c0 % n_aq;   // wave-uniform
             const int nc = min(min(kBaseChunk, q1 - c0), n_aq - aq0);
-            int S, sl;
-            if (mu == 0) S = g, sl = lane;
-            else if (mu == 1) S = ty * tiles + (tiles - 1 - tx), sl = ly * 8 + (7 - lx);
-            else if (mu == 2) S = tx * tiles + ty, sl = lx * 8 + ly;
-            else S = (tiles - 1 - tx) * tiles + ty, sl = (7 - lx) * 8 + ly;
+            const int S = mu == 0 ? g
+                        : mu == 1 ? ty * tiles + (tiles - 1 - tx)
+                        : mu == 2 ? tx * tiles + ty
+                                  : (tiles - 1 - tx) * tiles + ty;
             if (lane < 4 * nc) {
                 const int a = 4 * aq0 + lane;
                 int pa = -1;
@@ -125,15 +130,14 @@ __global__ __launch_bounds__(64 * W) void k_adj1_sym(const uint8_t *__restrict__
                 rowat[wave][lane] = pa < 0 ? -1 : pa * nb;
             }
             __builtin_amdgcn_wave_barrier();
+            T sum = T(0);
 #pragma unroll 2
             for (int j = 0; j < nc; ++j) {
                 const int64_t gq = int64_t(S) * n_aq + aq0 + j;
                 const int ra = rowat[wave][4 * j + kk];
                 const int b_band = min(int(bases[wave][4 * j + kk]) + ee, nb - 1);
                 const T yv = ra >= 0 ? yb[int64_t(ra) + b_band] : T(0);
-                const int64_t e = gq * kAdjLanes + sl;
-                // plain loads: three more tiles of the orbit read these slots
-                // shortly after, from L2
+                const int64_t e = gq * kAdjLanes + lane;
                 const uint32_t r4 = Rl[e];
                 const Q a4 = A[e];
                 const Q c4 = Bv[e];
@@ -142,25 +146,30 @@ __global__ __launch_bounds__(64 * W) void k_adj1_sym(const uint8_t *__restrict__
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int rb = int((r4 >> (8 * k)) & 0xffu);
-                    acc = fma(T(a4[k]), my[k * kAdjBand + rb], acc);
-                    acc = fma(T(c4[k]), my[k * kAdjBand + rb + 1], acc);
+                    sum = fma(T(a4[k]), my[k * kAdjBand + rb], sum);
+                    sum = fma(T(c4[k]), my[k * kAdjBand + rb + 1], sum);
                 }
                 __builtin_amdgcn_wave_barrier();
             }
+            if (mu == 0) acc[0] += sum;
+            else if (mu == 1) acc[1] += sum;
+            else if (mu == 2) acc[2] += sum;
+            else acc[3] += sum;
             c0 += nc;
         }
-        if constexpr (W > 1) {
-            __shared__ T red[W][64];
-            red[wave][lane] = acc;
-            __syncthreads();
-            if (wave == 0) {
-                acc = red[0][lane];
 #pragma unroll
-                for (int w = 1; w < W; ++w) acc += red[w][lane];
+        for (int m = 0; m < 4; ++m) red[wave][m][dest[m]] = acc[m];
+        __syncthreads();
+        T tot = T(0);
+        if (wave == 0) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) tot += red[w][m][lane];
             }
-            __syncthreads();   // red is reused by the next tile
         }
-        if (wave == 0) dsum += adj_epilogue(g, lane, acc, xb, out + bat * nn, alpha, lambda, sigma, n, tiles);
+        __syncthreads();   // red is reused by the next tile
+        if (wave == 0) dsum += adj_epilogue(g, lane, tot, xb, out + bat * nn, alpha, lambda, sigma, n, tiles);
     }
     if (part && wave == 0) {
         dsum = wave_sum(dsum);
@@ -570,9 +579,11 @@ static void adj_sym(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV l
     k_adj1_sym<TM, TV, W><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.f_partner, op.n_rep, \
                                                   op.n_aq, op.n_bins, y, x, out, al, la, si, part, op.n, \
                                                   op.tiles, op.nn, op.rows, op.a_order, op.n_a_order)
+    // default: about 12 or more (map, quad) items per wave
+    const int items = 4 * op.n_aq;
     const int w = op.tune.adj_waves == 1 || op.tune.adj_waves == 2 || op.tune.adj_waves == 4
                       ? op.tune.adj_waves
-                      : adj_waves_for(4 * op.n_adj_ang);
+                      : (items >= 48 ? 4 : (items >= 24 ? 2 : 1));
     if (w == 4) SCT_SYM(4);
     else if (w == 2) SCT_SYM(2);
     else SCT_SYM(1);
