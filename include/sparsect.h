@@ -844,7 +844,8 @@ int radon_export_csr(const radon_op *op, int64_t *row_ptr, int32_t *col, double 
  * per-(pixel, measured angle) records: bin int32[n*n*n_meas_angles] (first
  * bin, or -1 if no ray of that angle crosses the pixel), v0 and v1
  * double[n*n*n_meas_angles] (lengths for that bin and the next one).  Record
- * (j, a) is at j*n_meas_angles + a.  Synchronous.
+ * (j, a) is at j*n_meas_angles + a.  A layout stored by symmetry is read
+ * through its maps, so every measured angle has its records.  Synchronous.
  */
 int radon_export_adj(const radon_op *op, int32_t *bin, double *v0, double *v1);
 
