@@ -379,8 +379,28 @@ def bench_large(sct, W, torch, dev, vdt, t, verify=True):
     (4.8e8 nonzeros), split Bregman 30 outer x 10 CG on a random-ellipse
     phantom; the normal operator alone and whole reconstructions."""
     w = W.WORKLOADS["large_2048_f32"]
-    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
-                     device=dev)
+    from paper_1705_07497_amd import autotune
+    # the layout: the library default (line-banded forward, 16 rays of one
+    # angle) or a layout stored by the symmetries of the square (the 90
+    # angles are closed under the maps, 2048 is a multiple of 8), each with
+    # its launch settings tuned, whichever applies the normal operator faster
+    x0 = torch.randn((1, w.n * w.n), dtype=vdt, device=dev)
+    o0 = torch.empty_like(x0)
+    op, t_best, by_layout = None, None, {}
+    for bw, ang, cmp, sym in ((16, 1, False, False), (64, 2, True, True), (32, 2, True, True),
+                              (32, 2, False, True)):
+        cand = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=vdt,
+                           device=dev, tuning="default", bundle=bw, bundle_angles=ang, compact=cmp,
+                           symmetric=sym)
+        autotune.autotune(cand, batch=1, save=False)
+        tc = t(lambda: cand.normal(x0, w.alpha, w.lam, out=o0), 10)
+        by_layout[f"{bw}x{ang}{'c' if cmp else ''}{'s' if sym else ''}"] = round(tc * 1e3, 3)
+        if t_best is None or tc < t_best:
+            op, t_best = cand, tc
+        else:
+            del cand
+        torch.cuda.empty_cache()
+    del x0, o0
     mu_np, eps_np = W.phantom_and_noise(w.n, w.n_ellipses, op.rows, seed=0)
     mu = torch.as_tensor(mu_np, dtype=vdt, device=dev).reshape(1, -1)
     y = op.fwd(mu)
@@ -394,9 +414,14 @@ def bench_large(sct, W, torch, dev, vdt, t, verify=True):
                 / torch.linalg.vector_norm(mu))
     nnz = op.info.nnz
     bytes_normal = 2 * 8 * nnz + 4 * (op.rows + 1) + 4 * (op.nn + 1) + 8 * (3 * op.nn + 2 * op.rows)
-    print(f"# large 2048x2048/90 angles: normal {t_normal * 1e3:.3f} ms, split Bregman "
+    print(f"# large 2048x2048/90 angles: layout {op.bundle}x{op.bundle_angles}"
+          f"{' compact' if op.compact else ''}{' symmetric' if op.symmetric else ''} "
+          f"(normal ms by layout {by_layout}): normal {t_normal * 1e3:.3f} ms, split Bregman "
           f"{t_sb * 1e3:.1f} ms", file=sys.stderr, flush=True)
     out_d = {"n": w.n, "angles": w.n_angles, "bins": w.n_bins, "nnz": nnz, "bundle": op.bundle,
+             "bundle_angles": op.bundle_angles, "fwd_compact": op.compact, "fwd_symmetric": op.symmetric,
+             "adj_symmetric": op.adj_symmetric, "tuning": dict(op.tuning),
+             "normal_ms_by_layout": by_layout,
              "normal_apply_ms": round(t_normal * 1e3, 3),
              "normal_apply_gbs": round(bytes_normal / t_normal / 1e9, 1),
              "sb_ms": round(t_sb * 1e3, 1), "sb_applies": w.n_outer * w.n_cg,
