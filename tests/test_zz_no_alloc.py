@@ -2,8 +2,9 @@
 
 Its output must equal normal_apply's (same kernels, same summation order:
 bitwise) on consecutive calls that share the library's fixed per-GPU scratch
-array, the later call with a smaller input than the earlier one, and match
-the FP64 oracle; a size beyond the fixed array is refused before anything is
+array, the later call with a smaller input than the earlier one, for the
+default layout and for both products stored by symmetry, and match the FP64
+oracle; a size beyond the fixed array is refused before anything is
 enqueued.
 """
 import ctypes
@@ -71,6 +72,26 @@ def test_noalloc_equals_normal_apply_on_consecutive_calls():
         want = ref.normal(xs[b], 1.5, 0.5, 0.1)
         assert rel_l2(got[b], want) <= 1e-12
         assert abs(float(host(d_na)[b]) - float(np.dot(xs[b], want))) <= 1e-10 * abs(np.dot(xs[b], want))
+    # call 4: the benchmark's layout (32-ray bundles over 2 angles, both
+    # products stored by symmetry) on the 512^2 operator, then on a 64^2
+    # FP64 one against the oracle
+    say("noalloc: 512^2 stored by symmetry, batch 2")
+    sym = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=F32, vec_dtype=F64, tuning="default",
+                      bundle=32, bundle_angles=2, symmetric=True)
+    assert sym.adj_symmetric
+    o_ws, o_na, d_ws, d_na = _abi_pair(sym, x1[:2].contiguous(), w.alpha, w.lam, 0.0)
+    assert torch.equal(o_ws, o_na) and torch.equal(d_ws, d_na)
+    say("noalloc: 64^2 / 44 angles FP64 stored by symmetry, batch 2")
+    n, na = 64, 44
+    nb = W.n_bins_for(n)
+    sym = sct.RadonOp(n, na, nb, None, dtype=F64, tuning="default", bundle=32, bundle_angles=2, symmetric=True)
+    xs = rng.standard_normal((2, n * n))
+    o_ws, o_na, d_ws, d_na = _abi_pair(sym, to_dev(xs, F64), 1.5, 0.5, 0.1)
+    assert torch.equal(o_ws, o_na) and torch.equal(d_ws, d_na)
+    ref = oracle.OracleOp(n, na, nb)
+    got = host(o_na)
+    for b in range(2):
+        assert rel_l2(got[b], ref.normal(xs[b], 1.5, 0.5, 0.1)) <= 1e-12
 
 
 def test_noalloc_refuses_sizes_beyond_its_scratch():
