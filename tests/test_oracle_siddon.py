@@ -198,6 +198,28 @@ def test_mirror_symmetries_exact(n, n_angles):
             np.testing.assert_array_equal(row[my], R[ky * nb + by])
 
 
+@pytest.mark.parametrize("n,n_angles", [(16, 8), (24, 12), (15, 20)])
+def test_transpose_symmetries(n, n_angles):
+    """The maps behind the layouts stored by symmetry: the transpose of the
+    pixel grid carries the ray (theta, s) onto (pi/2 - theta, s), and the
+    transpose after x -> -x onto (pi/2 + theta, s), so the ray with bin b at
+    pi/2 - theta meets pixel (iy, ix), and the one at pi/2 + theta pixel
+    (n-1-iy, ix), with the lengths the ray at theta meets (ix, iy) with."""
+    nb = W.n_bins_for(n)
+    R = dense_R(n, n_angles, nb)
+    j = np.arange(n * n)
+    iy, ix = j // n, j % n
+    tr = ix * n + iy                  # pixel (iy, ix)
+    both = ix * n + (n - 1 - iy)      # pixel (n-1-iy, ix)
+    h = n_angles // 2
+    for k in range(h + 1):
+        for b in range(nb):
+            row = R[k * nb + b]
+            np.testing.assert_allclose(R[(h - k) * nb + b][tr], row, rtol=0, atol=1e-12)
+            if h + k < n_angles:
+                np.testing.assert_allclose(R[(h + k) * nb + b][both], row, rtol=0, atol=1e-12)
+
+
 def test_adjoint_identity_and_transpose():
     w = W.WORKLOADS["small_64_f64"]
     op = oracle.OracleOp(w.n, w.n_angles, w.n_bins, w.mask)
