@@ -520,6 +520,29 @@ def test_bundle_width_in_banded_volume_and_group():
                                             tuning="default", bundle=16)])
 
 
+@pytest.mark.parametrize("compact", [False, True])
+def test_caller_buffer_build_symmetric(compact):
+    """The caller-buffer build of operators stored by symmetry (forward and,
+    with n a multiple of 8, adjoint): the same sizes, records and products,
+    bitwise, as the library build."""
+    n, na = 120, 48
+    nb = W.n_bins_for(n)
+    mask = W.angle_mask(na, 2)
+    kw = dict(dtype=F32, vec_dtype=F64, tuning="default", bundle=32, bundle_angles=2, compact=compact,
+              symmetric=True)
+    a = sct.RadonOp(n, na, nb, mask, **kw)
+    b = sct.RadonOp(n, na, nb, mask, storage="torch", **kw)
+    assert a.adj_symmetric and b.adj_symmetric
+    assert b.sizes["fwd_slots"] == a.info.fwd_slots and b.sizes["adj_slots"] == a.info.adj_slots
+    for u, v in zip(a.export_adj(), b.export_adj()):
+        np.testing.assert_array_equal(u, v)
+    x = to_dev(np.random.default_rng(3).standard_normal((2, n * n)), F64)
+    y = to_dev(np.random.default_rng(4).standard_normal((2, a.rows)), F64)
+    assert torch.equal(a.fwd(x), b.fwd(x))
+    assert torch.equal(a.adj(y), b.adj(y))
+    assert torch.equal(a.normal(x, 1.0, 0.5), b.normal(x, 1.0, 0.5))
+
+
 @pytest.mark.parametrize("mode", ["mixed", "f64"])
 def test_caller_buffer_build_equals_library_build(mode):
     """radon_csr_sizes + build_radon_csr_into (every array a torch tensor)
