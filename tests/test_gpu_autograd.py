@@ -7,8 +7,9 @@
   eq:PD_resolve (Section 2) against the oracle's hand-written reverse sweep,
   against directional finite differences, with and without checkpoints
   (bitwise equal), batched against one image at a time (bitwise equal),
-  through iterations that stop early (closed form), and at the full gradient
-  workload size on sampled images.
+  through iterations that stop early (closed form), on an operator with both
+  products stored by symmetry, and at the full gradient workload size on
+  sampled images.
 """
 import numpy as np
 import pytest
@@ -94,6 +95,27 @@ def test_unrolled_loss_matches_oracle(small, mode, nit):
     L, gm, gf = _ad(op, mu, f, mode, ta, nit, 5)
     dt = MODES[mode][1]
     want = oracle_for(w, mode, ref).loss2(rounded(mu, dt), rounded(f, dt), ta, nit)
+    _check_loss(float(host(L)[0]), host(gm), host(gf), want, UNROLLED_TOL[(64, nit)])
+
+
+@pytest.mark.parametrize("nit", [4, 10])
+def test_unrolled_loss_symmetric_operator(nit):
+    """The same loss and gradients on an operator with both products stored
+    by symmetry (64 x 64, 44 angles: a set closed under the maps), FP64,
+    against the oracle at the tolerances above."""
+    need_gpu()
+    n, na = 64, 44
+    nb = W.n_bins_for(n)
+    ref = oracle.OracleOp(n, na, nb)
+    mu, eps = W.phantom_and_noise(n, 5, ref.rows, seed=3)
+    y = ref.fwd(mu)
+    f = y + 0.02 * np.sqrt(np.mean(y ** 2)) * eps
+    op = sct.RadonOp(n, na, nb, None, dtype=torch.float64, tuning="default", bundle=32, bundle_angles=2,
+                     symmetric=True)
+    assert op.adj_symmetric
+    say(f"unrolled loss parity, stored by symmetry, iters={nit}")
+    L, gm, gf = _ad(op, mu, f, "f64", 1.0, nit, 5)
+    want = ref.loss2(mu, f, 1.0, nit)
     _check_loss(float(host(L)[0]), host(gm), host(gf), want, UNROLLED_TOL[(64, nit)])
 
 
