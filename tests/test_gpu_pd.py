@@ -51,6 +51,15 @@ def test_pd_benchmark_workload():
     u = op.pd(to_dev(f[None], torch.float64), w.alpha, 50, 10)
     uo = ref.pd(f, w.alpha, STEP, STEP, 50, 10)
     assert rel_l2(host(u), uo) <= 1e-6
+    # the benchmark's layout: 32-ray bundles over 2 angles, both products
+    # stored by symmetry (a partner ray's FP32 length is the stored ray's,
+    # which can differ from the partner's own rounded-once value by one
+    # rounding, so the bar of the kind, 1e-5)
+    say("Chambolle-Pock 512x512, 50 x 10, stored by symmetry")
+    sym = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=torch.float32, vec_dtype=torch.float64,
+                      tuning="default", bundle=32, bundle_angles=2, symmetric=True)
+    us = sym.pd(to_dev(f[None], torch.float64), w.alpha, 50, 10)
+    assert rel_l2(host(us), uo) <= 1e-5
 
 
 def test_pd_argument_errors():
