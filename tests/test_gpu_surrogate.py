@@ -36,6 +36,20 @@ def ref_for(n, na, nb, mask, mode):
     return oracle.OracleOp(n, na, nb, mask, values="f64" if mode == "f64" else "f32")
 
 
+@pytest.mark.parametrize("r", [1, 3])
+def test_weights_from_symmetric_operator(r):
+    """Weights built through an operator with both products stored by
+    symmetry (64 x 64, 44 angles, FP64) against the oracle's."""
+    need_gpu()
+    n, na = 64, 44
+    nb = W.n_bins_for(n)
+    op = sct.RadonOp(n, na, nb, None, dtype=torch.float64, tuning="default", bundle=32, bundle_angles=2,
+                     symmetric=True)
+    assert op.adj_symmetric
+    sur = sct.RadonSurrogate(op, r)
+    assert rel_l2(sur.weights, oracle.OracleOp(n, na, nb).surrogate_weights(r)) <= 1e-12
+
+
 @pytest.mark.parametrize("mode", ["f64", "mixed", "f32"])
 @pytest.mark.parametrize("geom,r", [((64, 45, 91, 1), 1), ((64, 45, 91, 1), 3), ((33, 10, 47, 2), 2),
                                     ((100, 30, 143, 3), 4)])
