@@ -744,9 +744,12 @@ def main():
                                        op.symmetric)
     else:
         traffic = traffic_from_profile(kname)
+    # the kernel's own name (the traffic records are keyed by product and layout)
+    kernel_name = {"k_fwd": "k_fwd_sym" if op.symmetric else "k_fwd",
+                   "k_adj": "k_adj1", "k_adj_sym": "k_adj1_sym"}[kname]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kname, "avg_us": round(kavg * 1e6, 2), "algorithmic_bytes": kbytes,
+                "kernel": kernel_name, "avg_us": round(kavg * 1e6, 2), "algorithmic_bytes": kbytes,
                 "ceiling_gbs": ceiling["read_gbs"],
                 "frac_of_ceiling": round(achieved / ceiling["read_gbs"], 4), "ceiling": ceiling}
 
