@@ -20,7 +20,7 @@
 The oracle is the plain FP64 one (exact Siddon entries), so the tolerance
 1e-5 covers the single rounding of the GPU's FP32 matrix entries as well as
 the summation order.  Each test builds an oracle of ~4.9e8 nonzeros (about
-12 GB of host memory and a minute of host time) and runs on the GPU machine only.
+12 GB of host memory and a minute of host time) and needs a GPU.
 """
 import numpy as np
 import pytest
