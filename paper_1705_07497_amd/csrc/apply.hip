@@ -177,6 +177,126 @@ __global__ __launch_bounds__(64 * W) void k_adj1_sym(const uint8_t *__restrict__
     }
 }
 
+// The same adjoint with one workgroup per tile orbit (k_adj1_sym's tiles of
+// one orbit read the same slots, four times over).  Wave w takes the orbit's
+// source tiles w, w + W, ... whole: it reads each of their stored slots once
+// and applies the four maps to it, staging per quad the sinogram band of
+// each map's partner angles (4 x 64 values) and forming four sums, one per
+// map, for source pixel `lane`.  The sum of source s under map m is stored
+// at [s][m][dest_m(lane)] in LDS (each written once); output tile t then adds
+// its four sums, from sources src[t][0..3], in map order, and wave t % W
+// applies the epilogue.
+template <class TM, class T, int W>
+__global__ __launch_bounds__(64 * W) void k_adj1_orb(const uint8_t *__restrict__ rel,
+                                                    const uint16_t *__restrict__ base,
+                                                    const TM *__restrict__ v0, const TM *__restrict__ v1,
+                                                    const int4 *__restrict__ partner, int n_rep, int n_aq,
+                                                    int nb, const T *__restrict__ y, const T *__restrict__ x,
+                                                    T *__restrict__ out, T alpha, T lambda, T sigma,
+                                                    double *__restrict__ part, int n, int tiles, int64_t nn,
+                                                    int64_t rows, const AdjOrbit *__restrict__ orbs,
+                                                    int64_t n_orb)
+{
+    using Q = typename Quad<TM>::type;
+    __shared__ T band[W][4][4 * kAdjBand];
+    __shared__ uint16_t bases[W][kAdjLanes];
+    __shared__ int32_t rowat[W][4][kAdjLanes];   // partner angle * nb per map, or -1
+    __shared__ T sums[8][4][64];                 // per source tile and map, at the output lanes
+    __shared__ double dred[W];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t bat = blockIdx.y;
+    const T *__restrict__ yb = y + bat * rows;
+    const T *__restrict__ xb = x ? x + bat * nn : nullptr;
+    const uint32_t *__restrict__ Rl = reinterpret_cast<const uint32_t *>(rel);
+    const Q *__restrict__ A = reinterpret_cast<const Q *>(v0);
+    const Q *__restrict__ Bv = reinterpret_cast<const Q *>(v1);
+    const int kk = lane >> 4, ee = lane & 15;   // this lane's band element
+    const int sx = lane & 7, sy = lane >> 3;
+    const int d1 = sy * 8 + (7 - sx), d2 = sx * 8 + sy, d3 = sx * 8 + (7 - sy);
+    double dsum = 0.0;
+    for (int64_t o = blockIdx.x; o < n_orb; o += gridDim.x) {
+        const AdjOrbit &ob = orbs[o];
+        int k = 0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) k += ob.tile[t] >= 0 ? 1 : 0;
+        for (int si = wave; si < k; si += W) {
+            const int S = ob.tile[si];
+            T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+            for (int aq0 = 0; aq0 < n_aq; aq0 += kBaseChunk) {
+                const int nc = min(kBaseChunk, n_aq - aq0);
+                if (lane < 4 * nc) {
+                    const int a = 4 * aq0 + lane;
+                    int4 p = make_int4(-1, -1, -1, -1);
+                    if (a < n_rep) p = partner[a];
+                    bases[wave][lane] = base[(int64_t(S) * n_aq + aq0) * 4 + lane];
+                    rowat[wave][0][lane] = a < n_rep ? a * nb : -1;
+                    rowat[wave][1][lane] = p.x < 0 ? -1 : p.x * nb;
+                    rowat[wave][2][lane] = p.y < 0 ? -1 : p.y * nb;
+                    rowat[wave][3][lane] = p.z < 0 ? -1 : p.z * nb;
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+                for (int j = 0; j < nc; ++j) {
+                    const int64_t gq = int64_t(S) * n_aq + aq0 + j;
+                    const int bi = 4 * j + kk;
+                    const int b_band = min(int(bases[wave][bi]) + ee, nb - 1);
+                    T yv[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int ra = rowat[wave][m][bi];
+                        yv[m] = ra >= 0 ? yb[int64_t(ra) + b_band] : T(0);
+                    }
+                    const int64_t e = gq * kAdjLanes + lane;
+                    const uint32_t r4 = stream_load(Rl + e);
+                    const Q a4 = stream_load(A + e);
+                    const Q c4 = stream_load(Bv + e);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) band[wave][m][lane] = yv[m];
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int rb = q * kAdjBand + int((r4 >> (8 * q)) & 0xffu);
+                        const T av = T(a4[q]), cv = T(c4[q]);
+                        s0 = fma(av, band[wave][0][rb], s0);
+                        s0 = fma(cv, band[wave][0][rb + 1], s0);
+                        s1 = fma(av, band[wave][1][rb], s1);
+                        s1 = fma(cv, band[wave][1][rb + 1], s1);
+                        s2 = fma(av, band[wave][2][rb], s2);
+                        s2 = fma(cv, band[wave][2][rb + 1], s2);
+                        s3 = fma(av, band[wave][3][rb], s3);
+                        s3 = fma(cv, band[wave][3][rb + 1], s3);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            sums[si][0][lane] = s0;
+            sums[si][1][d1] = s1;
+            sums[si][2][d2] = s2;
+            sums[si][3][d3] = s3;
+        }
+        __syncthreads();
+        for (int t = wave; t < k; t += W) {
+            T tot = sums[ob.src[t][0]][0][lane];
+            tot += sums[ob.src[t][1]][1][lane];
+            tot += sums[ob.src[t][2]][2][lane];
+            tot += sums[ob.src[t][3]][3][lane];
+            dsum += adj_epilogue(ob.tile[t], lane, tot, xb, out + bat * nn, alpha, lambda, sigma, n, tiles);
+        }
+        __syncthreads();   // sums are rewritten by the next orbit
+    }
+    if (part) {
+        dsum = wave_sum(dsum);
+        if (lane == 0) dred[wave] = dsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) v += dred[w];
+            part[bat * gridDim.x + blockIdx.x] = v;
+        }
+    }
+}
+
 // Adjoint: one workgroup of W waves per 8x8 pixel tile (persistent loop over
 // the tiles in `order`, the XCD-compact order: the tiles a workgroup on XCD x
 // visits lie in one compact region of the image, so the sinogram bands the
@@ -516,7 +636,14 @@ int launch_fwd(const Op &op, const TV *x, const TV *xT, TV *y, int batch, hipStr
     }
 }
 
-int adj_blocks(const Op &op) { return int(op.n_ag < kPersistentBlocks ? op.n_ag : kPersistentBlocks); }
+// The adjoint stored by symmetry with one workgroup per tile orbit.
+static bool adj_by_orbit(const Op &op) { return op.sym_adj && op.a_orb && op.tune.adj_layout == 1; }
+
+int adj_blocks(const Op &op)
+{
+    const int64_t items = adj_by_orbit(op) ? op.n_orb : op.n_ag;
+    return int(items < kPersistentBlocks ? items : kPersistentBlocks);
+}
 
 static int adj_waves(const Op &op)
 {
@@ -575,6 +702,18 @@ static void adj_sym(const Op &op, const TV *y, const TV *x, TV *out, TV al, TV l
 {
     const dim3 grid(unsigned(adj_blocks(op)), unsigned(batch));
     const TM *a0 = static_cast<const TM *>(op.a_v0), *a1 = static_cast<const TM *>(op.a_v1);
+    if (adj_by_orbit(op)) {
+        // 2 x adj_waves waves per orbit (default 8: one per source tile)
+#define SCT_ORB(W)                                                                                     \
+    k_adj1_orb<TM, TV, W><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.f_partner, op.n_rep, \
+                                                  op.n_aq, op.n_bins, y, x, out, al, la, si, part, op.n, \
+                                                  op.tiles, op.nn, op.rows, op.a_orb, op.n_orb)
+        if (op.tune.adj_waves == 1) SCT_ORB(2);
+        else if (op.tune.adj_waves == 2) SCT_ORB(4);
+        else SCT_ORB(8);
+#undef SCT_ORB
+        return;
+    }
 #define SCT_SYM(W)                                                                                    \
     k_adj1_sym<TM, TV, W><<<grid, 64 * W, 0, s>>>(op.a_rel, op.a_base, a0, a1, op.f_partner, op.n_rep, \
                                                   op.n_aq, op.n_bins, y, x, out, al, la, si, part, op.n, \

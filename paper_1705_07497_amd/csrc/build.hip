@@ -479,6 +479,7 @@ struct Plan {
     std::vector<int32_t> order;   // block -> bundle of the forward product
     std::vector<int2> border[4];  // (bundle, band) items of the line-banded forward, per height
     std::vector<int32_t> aorder;  // adjoint tile order of the fused products
+    std::vector<AdjOrbit> orbs;   // tile orbits of an adjoint stored by symmetry
 };
 
 static int64_t up256(int64_t b) { return (b + 255) & ~int64_t(255); }
@@ -531,6 +532,7 @@ static int64_t layout_bytes(const Op &op, const Plan &pl)
     b += up256(4 * int64_t(pl.order.size()));
     for (const auto &bo : pl.border) b += up256(8 * int64_t(bo.size()));
     b += up256(4 * int64_t(pl.aorder.size()));
+    b += up256(int64_t(sizeof(AdjOrbit)) * int64_t(pl.orbs.size()));
     return b;
 }
 
@@ -699,6 +701,7 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
             // of a slot find it in L2.
             std::vector<char> seen(size_t(op.n_ag), 0);
             std::vector<std::vector<int32_t>> small;
+            pl.orbs.clear();
             std::vector<int32_t> flat;   // orbit tiles, groups of 8 (-1: unused)
             for (const auto &m : mt) {
                 if (seen[size_t(m.second)]) continue;
@@ -713,6 +716,22 @@ static int count_phase(Op &op, const std::vector<double> &cs_host, hipStream_t s
                             orb.push_back(u);
                         }
                 }
+                // the orbit table: for output tile t and each map, the
+                // source tile k_adj1_sym reads (for k_adj1_orb)
+                AdjOrbit ob;
+                for (int k = 0; k < 8; ++k) ob.tile[k] = k < int(orb.size()) ? orb[size_t(k)] : -1;
+                for (size_t ti = 0; ti < 8; ++ti)
+                    for (int m = 0; m < 4; ++m) ob.src[ti][m] = 0;
+                for (size_t ti = 0; ti < orb.size(); ++ti) {
+                    const int tx = orb[ti] % T, ty = orb[ti] / T;
+                    const int32_t src[4] = {orb[ti], ty * T + (T - 1 - tx), tx * T + ty, (T - 1 - tx) * T + ty};
+                    for (int m = 0; m < 4; ++m) {
+                        size_t at = 0;
+                        while (orb[at] != src[m]) ++at;   // the orbit is closed under the maps
+                        ob.src[ti][m] = uint8_t(at);
+                    }
+                }
+                pl.orbs.push_back(ob);
                 if (orb.size() == 8) flat.insert(flat.end(), orb.begin(), orb.end());
                 else small.push_back(std::move(orb));
             }
@@ -785,6 +804,9 @@ static int fill_phase(Op &op, const Plan &pl, hipStream_t st, const CountTmp &t)
             SCT_HIP(hipMemcpyAsync(op.bands[h].order, pl.border[h].data(), 8 * pl.border[h].size(),
                                    hipMemcpyHostToDevice, st));
     SCT_HIP(hipMemcpyAsync(op.a_order, pl.aorder.data(), 4 * pl.aorder.size(), hipMemcpyHostToDevice, st));
+    if (op.n_orb)
+        SCT_HIP(hipMemcpyAsync(op.a_orb, pl.orbs.data(), sizeof(AdjOrbit) * pl.orbs.size(), hipMemcpyHostToDevice,
+                               st));
 
     int32_t bad_h = 0;
     SCT_HIP(hipMemcpyAsync(&bad_h, t.bad, 4, hipMemcpyDeviceToHost, st));
@@ -831,6 +853,9 @@ static int carve_layouts(Op &op, const Plan &pl, Carve &lay, bool fb_taken)
     op.fb_band_order = single ? op.bands[0].order : nullptr;
     op.n_a_order = int64_t(pl.aorder.size());
     SCT_TRY(lay.take(&op.a_order, 4 * op.n_a_order));
+    op.n_orb = int64_t(pl.orbs.size());
+    op.a_orb = nullptr;
+    if (op.n_orb) SCT_TRY(lay.take(&op.a_orb, int64_t(sizeof(AdjOrbit)) * op.n_orb));
     return RADON_OK;
 }
 

@@ -108,6 +108,16 @@ struct RayEdge {
 };
 static_assert(sizeof(RayEdge) == 32, "RayEdge layout");
 
+// One orbit of 8x8 tiles under x -> -x and the transpose, for an adjoint
+// stored by symmetry: its tiles (-1 past the orbit's 1, 4 or 8), and for
+// output tile t and map m (identity, x -> -x, transpose, both) the place in
+// `tile` of the source tile whose slots feed it under that map.
+struct AdjOrbit {
+    int32_t tile[8];
+    uint8_t src[8][4];
+};
+static_assert(sizeof(AdjOrbit) == 64, "AdjOrbit layout");
+
 // Measured ray of lane r of bundle d, or -1 for a lane without a ray.
 __host__ __device__ inline int64_t bundle_ray(const FwdBundle &d, int r)
 {
@@ -217,6 +227,8 @@ struct Op {
     // bands stay in its L2; entries -1 pad each run
     int32_t *a_order = nullptr;
     int64_t n_a_order = 0;
+    AdjOrbit *a_orb = nullptr;   // sym_adj: the tile orbits (k_adj1_orb)
+    int64_t n_orb = 0;
 
     radon_tuning tune{2, 0, 4, 8, 0, 0, 0, 0};   // launch tuning (see radon_set_tuning)
 };

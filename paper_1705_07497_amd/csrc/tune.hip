@@ -211,6 +211,24 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
         }
     }
     cur.adj_waves = best->adj_waves;
+    // an adjoint stored by symmetry: one workgroup per tile orbit
+    // (adj_layout 1) at each wave count, against the best per-tile launch
+    if (op.sym_adj) {
+        for (int w : {1, 2, 4}) {
+            op.tune = cur;
+            op.tune.adj_waves = w;
+            op.tune.adj_layout = 1;
+            float t = 0.f;
+            SCT_TRY(time_calls(s, tm, reps1, adj(1), &t));
+            if (t < bt) {
+                bt = t;
+                best->adj_waves = w;
+                best->adj_layout = 1;
+            }
+        }
+        cur.adj_waves = best->adj_waves;
+        cur.adj_layout = best->adj_layout;
+    }
     // several images: how many share each matrix load, in both products
     // together (the chunkings interact through the caches), timed on the
     // normal operator's two products; then, at the best adjoint chunk, the

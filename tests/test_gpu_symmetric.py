@@ -15,8 +15,9 @@ in test_abi.py); a group does not take such an operator.
 With n a multiple of 8 the adjoint layout is stored the same way (pixel
 (px, py) meets the rays of the three partner angles as (n-1-px, py),
 (py, px) and (py, n-1-px) meet those of the stored angle, and 8x8 tiles map
-onto tiles): the adjoint matches the oracle at the bar of its kind and the
-full layout to rounding, and the exported per-(pixel, angle) records, read
+onto tiles): the adjoint, with one workgroup per tile or per tile orbit
+(adj_layout 0 or 1) at each wave count, matches the oracle at the bar of
+its kind and the full layout to rounding, and the exported per-(pixel, angle) records, read
 through the maps, hold the full layout's bins exactly and its lengths to
 rounding.  Otherwise the adjoint is the full layout's, bitwise.
 """
@@ -62,11 +63,16 @@ def test_symmetric_matches_oracle_and_stored_layout(mode, geom):
         if op.adj_symmetric:
             assert op.info.adj_slots <= full.info.adj_slots   # equal when both fit one quad
             for aw in (1, 2, 4):
-                op.tuning = {"adj_waves": aw}
-                xa = host(op.adj(Y))
-                assert rel_l2(xa, host(full.adj(Y))) <= (1e-13 if mode == "f64" else 5e-7), (bw, ang, aw)
-                for b in range(3):
-                    assert rel_l2(xa[b], ref.adj(y[b])) <= tol, (bw, ang, aw, b)
+                for al in (0, 1):   # one workgroup per tile, or per tile orbit
+                    op.tuning = {"adj_waves": aw, "adj_layout": al}
+                    xa = host(op.adj(Y))
+                    assert rel_l2(xa, host(full.adj(Y))) <= (1e-13 if mode == "f64" else 5e-7), (bw, ang, aw, al)
+                    for b in range(3):
+                        assert rel_l2(xa[b], ref.adj(y[b])) <= tol, (bw, ang, aw, al, b)
+                    a = host(op.normal(X, 0.7, 0.3, 0.05))
+                    for b in range(3):
+                        assert rel_l2(a[b], ref.normal(x[b], 0.7, 0.3, 0.05)) <= tol, (bw, ang, aw, al, b)
+            op.tuning = {"adj_waves": 0, "adj_layout": 0}
         else:
             assert torch.equal(op.adj(Y), full.adj(Y))
         for waves in (2, 4):
@@ -131,12 +137,35 @@ def test_symmetric_adjoint_batched_normal_and_partials():
     for batch in (1, 5, 16):
         x = rng.standard_normal((batch, n * n))
         y = rng.standard_normal((batch, ref.rows))
-        for rhs in (1, 4, 16):
-            op.tuning = {"adj_rhs": rhs, "fwd_rhs": rhs}
+        for rhs, al in ((1, 0), (4, 1), (16, 0), (16, 1)):
+            op.tuning = {"adj_rhs": rhs, "fwd_rhs": rhs, "adj_layout": al}
             xa = host(op.adj(to_dev(y, F64)))
             a = host(op.normal(to_dev(x, F64), 0.5, 1.0, 0.1))
             for b in range(batch):
                 assert rel_l2(xa[b], ref.adj(y[b])) <= 1e-5, (batch, rhs, b)
                 assert rel_l2(a[b], ref.normal(x[b], 0.5, 1.0, 0.1)) <= 1e-5, (batch, rhs, b)
-    xs, _ = op.cg(to_dev(rng.standard_normal((3, n * n)), F64), 0.5, 1.0, 0.1, n_iter=4)
-    assert np.all(np.isfinite(host(xs)))
+    # CG through the <x, Ax> partials of both adjoint kernels
+    rhs = rng.standard_normal((3, n * n))
+    xo = ref.cg(0.5, 1.0, 0.1, rhs=rhs[2], n_iter=4)[0]
+    for al in (0, 1):
+        op.tuning = {"adj_layout": al}
+        xs, _ = op.cg(to_dev(rhs, F64), 0.5, 1.0, 0.1, n_iter=4)
+        assert rel_l2(host(xs)[2], xo) <= 1e-5, al
+
+
+def test_symmetric_adjoint_kernels_agree_and_autotune():
+    """At 512^2 each map's quads fit one staging chunk, so the per-tile and
+    the per-orbit kernels form the same sums in the same order: bitwise
+    equal.  The autotuner may pick either; its choice stays at the bar."""
+    need_gpu()
+    w = W.WORKLOADS["gpu_512_f32"]
+    op = sct.RadonOp(w.n, w.n_angles, w.n_bins, w.mask, dtype=F32, vec_dtype=F64, tuning="default", bundle=32,
+                     bundle_angles=2, symmetric=True)
+    y = to_dev(np.random.default_rng(8).standard_normal((2, op.rows)), F64)
+    op.tuning = {"adj_layout": 0}
+    a0 = op.adj(y)
+    op.tuning = {"adj_layout": 1}
+    assert torch.equal(op.adj(y), a0)
+    from paper_1705_07497_amd import autotune
+    autotune.autotune(op, batch=1, save=False)
+    assert rel_l2(host(op.adj(y)), host(a0)) <= 1e-13
