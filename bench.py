@@ -638,8 +638,9 @@ def main():
         # layout choose_bundle picks) at 2 and 4 waves per bundle, 100
         # launches each, layouts in the order of PROFILE_LAYOUTS (layouts of
         # one width and wave count share a kernel name and are told apart by
-        # that order; the adjoint stored by symmetry, 100 launches, after the
-        # forwards of the symmetric layout with both lengths), then the
+        # that order; the adjoint stored by symmetry, 100 launches per tile and
+        # 100 per tile orbit, after the forwards of the symmetric layout with
+        # both lengths), then the
         # adjoint, the normal operator and CG of the default operator
         for bw, ang, cmp, sym in PROFILE_LAYOUTS:
             same = (bw, ang, cmp, sym) == (op.bundle, op.bundle_angles, int(op.compact), int(op.symmetric))
@@ -651,10 +652,14 @@ def main():
                 for _ in range(100):
                     op_b.fwd_xt(x, xT, out=ysb)
             if sym and not cmp:
-                # the adjoint stored by symmetry (k_adj1_sym; the same
-                # pixel-group layout for every forward layout)
-                for _ in range(100):
-                    op_b.adj(ysb, out=out)
+                # the adjoint stored by symmetry (the same pixel-group layout
+                # for every forward layout): one workgroup per tile
+                # (k_adj1_sym), then per tile orbit (k_adj1_orb)
+                for al in (0, 1):
+                    op_b.tuning = {"adj_layout": al}
+                    for _ in range(100):
+                        op_b.adj(ysb, out=out)
+                op_b.tuning = {"adj_layout": 0}
             op_b.tuning = {"fwd_waves": 2}
             torch.cuda.synchronize()
             del op_b
@@ -734,7 +739,8 @@ def main():
     bytes_adj = 8 * nnz + 4 * (nn + 1) + vb * rows + vb * nn
     avg_fwd, avg_adj = t_fwd / args.applies, t_adj / args.applies
     if avg_adj >= avg_fwd:
-        kname, kbytes, kavg = ("k_adj_sym" if op.adj_symmetric else "k_adj"), bytes_adj, avg_adj
+        kname = ("k_adj_orb" if op.tuning["adj_layout"] == 1 else "k_adj_sym") if op.adj_symmetric else "k_adj"
+        kbytes, kavg = bytes_adj, avg_adj
     else:
         kname, kbytes, kavg = "k_fwd", bytes_fwd, avg_fwd
     achieved = kbytes / kavg / 1e9
@@ -746,7 +752,7 @@ def main():
         traffic = traffic_from_profile(kname)
     # the kernel's own name (the traffic records are keyed by product and layout)
     kernel_name = {"k_fwd": "k_fwd_sym" if op.symmetric else "k_fwd",
-                   "k_adj": "k_adj1", "k_adj_sym": "k_adj1_sym"}[kname]
+                   "k_adj": "k_adj1", "k_adj_sym": "k_adj1_sym", "k_adj_orb": "k_adj1_orb"}[kname]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel_name, "avg_us": round(kavg * 1e6, 2), "algorithmic_bytes": kbytes,
