@@ -769,7 +769,8 @@ int split_bregman_tv_fourier(const radon_fourier *f, int32_t path, const radon_s
  *              symmetry (radon_info.adj_symmetric), whatever the image count:
  *              0 = one workgroup per 8x8 tile (adj_waves waves), 1 = one
  *              workgroup per orbit of tiles under the maps, reading each
- *              stored slot once (2 x adj_waves waves, 8 for 0);
+ *              stored slot once (2 x adj_waves waves, 8 for 0; radon_autotune
+ *              tries it from 1024 orbits on);
  *   fwd_lines  height of the line bands of a forward that has a workspace:
  *              0 = chosen from the chunk's image bytes (the largest of 128,
  *              64, 32, 16 lines whose band of the chunk's images fits 2 MB;

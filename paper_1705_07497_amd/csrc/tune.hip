@@ -212,8 +212,11 @@ static int tune_typed(Op &op, int batch, void *ws, hipStream_t s, radon_tuning *
     }
     cur.adj_waves = best->adj_waves;
     // an adjoint stored by symmetry: one workgroup per tile orbit
-    // (adj_layout 1) at each wave count, against the best per-tile launch
-    if (op.sym_adj) {
+    // (adj_layout 1) at each wave count, against the best per-tile launch,
+    // when there are at least 4 orbits per CU of the 256 (with fewer, the
+    // last round of orbits leaves most CUs idle: at 512 x 512, 528 orbits,
+    // the orbit kernel is faster alone but not inside the solves)
+    if (op.sym_adj && op.n_orb >= 4 * 256) {
         for (int w : {1, 2, 4}) {
             op.tune = cur;
             op.tune.adj_waves = w;
