@@ -38,7 +38,7 @@ MODES = {"f64": (F64, F64), "f32": (F32, F32), "mixed": (F32, F64)}
 
 @pytest.mark.parametrize("mode", ["mixed", "f32", "f64"])
 @pytest.mark.parametrize("geom", [(70, 36, 2), (61, 44, 1), (33, 8, 1), (8, 4, 1), (64, 36, 2), (40, 20, 1),
-                                  (24, 180, 2)])
+                                  (24, 180, 2), (32, 256, 1)])   # the last: 17 quads of stored angles
 def test_symmetric_matches_oracle_and_stored_layout(mode, geom):
     need_gpu()
     n, na, ev = geom
