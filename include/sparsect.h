@@ -752,7 +752,8 @@ int split_bregman_tv_fourier(const radon_fourier *f, int32_t path, const radon_s
  * rounding level).
  *   fwd_waves  waves per ray bundle in the forward product: 2 or 4;
  *   adj_waves  waves per 8x8 tile in the adjoint: 1, 2 or 4 (0: chosen from
- *              the number of measured angles);
+ *              the number of measured angles, or of stored angles for an
+ *              adjoint stored by symmetry);
  *   fwd_rhs, adj_rhs  largest number of images (right-hand sides) that share
  *              each matrix load in a fused multi-image product: 1, 4, 8, 16;
  *   fwd_layout how a fused forward chunk of 4 or more images gathers its
